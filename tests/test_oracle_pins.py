@@ -1,0 +1,254 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Nothing here touches the HIP path.  Each test pins one part of the oracle to
+something other than itself: closed forms (circle eigenvalues, Mie series),
+identities (Calderon), an independent method (multipole), invariants (energy,
+optical theorem, reciprocity), high-precision arithmetic (mpmath), brute force
+(fast vs dense) and the paper's printed degree-of-freedom table.
+"""
+import os
+
+import mpmath
+import numpy as np
+import pytest
+from scipy import special as sp
+
+from oracle import analytic, dense, fast, layer
+from paper_2603_09381_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_scipy_hankel_matches_mpmath():
+    """The oracle's library primitive (scipy Hankel functions) against 30-digit mpmath."""
+    mpmath.mp.dps = 30
+    for z in [1e-6, 0.01, 0.3, 1.0, 2.5, 7.9, 12.3, 19.0, 33.3, 150.0, 999.0]:
+        for nu in (0, 1):
+            ref = complex(mpmath.hankel1(nu, z))
+            got = sp.hankel1(nu, z)
+            assert abs(got - ref) <= 2e-15 * max(1.0, abs(ref)), (nu, z, got, ref)
+
+
+@pytest.mark.parametrize("n", [16, 64])
+def test_kress_weights_exact_on_trig_polynomials(n):
+    """int_0^2pi ln(4 sin^2((t-tau)/2)) e^{i m tau} dtau = -2pi/|m| e^{i m t} (0 for m = 0),
+    reproduced exactly for |m| < n/2."""
+    h = n // 2
+    R = layer.kress_log_weights(n)
+    t = 2 * np.pi * np.arange(n) / n
+    a = np.arange(n)
+    Rm = R[(a[:, None] - a[None, :]) % n]
+    for m in range(-h + 1, h):
+        got = Rm @ np.exp(1j * m * t)
+        ref = np.zeros(n, complex) if m == 0 else -2 * np.pi / abs(m) * np.exp(1j * m * t)
+        assert np.max(np.abs(got - ref)) < 1e-12
+
+
+def test_trig_diff_matrix_exact():
+    n = 32
+    t = 2 * np.pi * np.arange(n) / n
+    Dt = layer.trig_diff_matrix(n)
+    for m in range(-n // 2 + 1, n // 2):
+        assert np.max(np.abs(Dt @ np.exp(1j * m * t) - 1j * m * np.exp(1j * m * t))) < 1e-11
+
+
+def _circle(n, R=0.4):
+    w = W.single_disk(n=n, radius=R)
+    return w
+
+
+@pytest.mark.parametrize("k", [2 * np.pi, 4 * np.pi])
+def test_circle_eigenvalues(k):
+    """Kress S, D, D* and Maue N on a circle against the Graf closed forms:
+    S -> (i pi R/2) J H, D = D* -> (i pi k R/4)(J'H + JH'), N -> (i pi k^2 R/2) J'H'."""
+    n, R = 64, 0.4
+    w = _circle(n, R)
+    S, D, Ds, N = layer.self_blocks(w.x, w.y, w.dx, w.dy, w.ddx, w.ddy, k)
+    t = 2 * np.pi * np.arange(n) / n
+    z = k * R
+    for l in range(-n // 4 + 1, n // 4):
+        e = np.exp(1j * l * t)
+        J, H, Jp, Hp = sp.jv(l, z), sp.hankel1(l, z), sp.jvp(l, z), sp.h1vp(l, z)
+        lamS = 1j * np.pi * R / 2 * J * H
+        lamD = 1j * np.pi * k * R / 4 * (Jp * H + J * Hp)
+        lamN = 1j * np.pi * k * k * R / 2 * Jp * Hp
+        for M, lam, tol in ((S, lamS, 1e-12), (D, lamD, 1e-12), (Ds, lamD, 1e-12), (N, lamN, 1e-10)):
+            err = np.max(np.abs(M @ e - lam * e))
+            assert err <= tol * max(1.0, abs(lam)), (l, err, lam)
+
+
+def _point_source(x, y, nx, ny, z, k):
+    d1, d2 = x - z[0], y - z[1]
+    r = np.hypot(d1, d2)
+    v = 0.25j * sp.hankel1(0, k * r)
+    dv = -0.25j * k * sp.hankel1(1, k * r) * (nx * d1 + ny * d2) / r
+    return v, dv
+
+
+@pytest.mark.parametrize("k", [10.0, 15.0])
+def test_calderon_identities_on_star(k):
+    """(D - 1/2) v - S dv = 0 and -(D* + 1/2) dv + N v = 0 for v radiating from a point
+    inside; (D + 1/2) w - S dw = 0 and -(D* - 1/2) dw + N w = 0 for a source outside."""
+    w = W.star_grid(1, n=128, k_ext=k, k_int=k)
+    S, D, Ds, N = layer.self_blocks(w.x, w.y, w.dx, w.dy, w.ddx, w.ddy, k)
+    speed, nx, ny, _, _ = layer.boundary_quantities(w.dx, w.dy, w.ddx, w.ddy, w.node_off)
+    I = np.eye(128)
+    v, dv = _point_source(w.x, w.y, nx, ny, (0.05, -0.03), k)
+    r1 = (D - I / 2) @ v - S @ dv
+    r2 = -(Ds + I / 2) @ dv + N @ v
+    assert np.max(np.abs(r1)) < 1e-11 * np.max(np.abs(v))
+    assert np.max(np.abs(r2)) < 1e-9 * np.max(np.abs(dv))
+    v, dv = _point_source(w.x, w.y, nx, ny, (0.9, 0.7), k)
+    r1 = (D + I / 2) @ v - S @ dv
+    r2 = -(Ds - I / 2) @ dv + N @ v
+    assert np.max(np.abs(r1)) < 1e-11 * np.max(np.abs(v))
+    assert np.max(np.abs(r2)) < 1e-9 * np.max(np.abs(dv))
+
+
+def test_single_disk_against_mie():
+    w = W.single_disk(n=64, angles=[0.0, 0.7])
+    g = dense.Geometry(w)
+    phi = dense.solve(w)
+    q, u = dense.split_density(g, phi)
+    th = 2 * np.pi * np.arange(64) / 64
+    ep, em = dense.materials(w)
+    for c, a in enumerate(w.angles):
+        qm, um = analytic.mie_boundary(th, w.k_ext, w.k_int[0], 0.4, ep, em[0], angle=a)
+        ref = np.concatenate([qm, um])
+        assert np.linalg.norm(np.concatenate([q[:, c], u[:, c]]) - ref) / np.linalg.norm(ref) < 1e-13
+        ff = dense.far_field(g, phi[:, c:c + 1], th)[:, 0]
+        ffm = analytic.mie_far_field(th, w.k_ext, w.k_int[0], 0.4, ep, em[0], angle=a)
+        assert np.max(np.abs(ff - ffm)) < 1e-13 * np.max(np.abs(ffm))
+
+
+def test_graf_translation_formula():
+    """The multipole translation used by the multi-disk reference, against direct evaluation."""
+    k = 2 * np.pi
+    cj, cl = np.array([1.0, 0.0]), np.array([0.0, 1.0])
+    x = cj + np.array([0.21, -0.13])
+    dvec = cj - cl
+    b, phi = np.hypot(*dvec), np.arctan2(dvec[1], dvec[0])
+    rj, tj = np.hypot(*(x - cj)), np.arctan2(*(x - cj)[::-1])
+    rl, tl = np.hypot(*(x - cl)), np.arctan2(*(x - cl)[::-1])
+    for m in (-3, 0, 2, 5):
+        lhs = sp.hankel1(m, k * rl) * np.exp(1j * m * tl)
+        ns = np.arange(-60, 61)
+        rhs = np.sum(sp.hankel1(m - ns, k * b) * np.exp(1j * (m - ns) * phi) * sp.jv(ns, k * rj)
+                     * np.exp(1j * ns * tj))
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("n,tol", [(64, 5e-9), (128, 1e-11)])
+def test_two_by_two_disks_against_multipole(n, tol):
+    """Dense Nystrom solve of the 2x2 disk grid against the multipole solution."""
+    w = W.disk_grid(2, n=n)
+    g = dense.Geometry(w)
+    phi = dense.solve(w)
+    ep, em = dense.materials(w)
+    bnd, _, _ = analytic.multi_disk(w.centers, 0.4, w.k_ext, w.k_int[0], ep, em[0])
+    th = 2 * np.pi * np.arange(n) / n
+    ref = np.concatenate([np.concatenate(bnd(j, th)) for j in range(4)])
+    assert dense.rel_error(phi[:, 0], ref) < tol
+    assert np.max(np.abs(dense.energy_defect(g, phi))) < 1e-11
+
+
+def test_optical_theorem_and_reciprocity():
+    """int |u_inf|^2 = -sqrt(8 pi/k) Re(e^{i pi/4} u_inf(a)); u_inf(t; a) = u_inf(a+pi; t+pi)."""
+    w = W.star_grid(2, n=128, k_ext=10.0, k_int=15.0, seed=2,
+                    angles=2 * np.pi * np.arange(4) / 4)
+    g = dense.Geometry(w)
+    phi = dense.solve(w)
+    nd = 720
+    th = 2 * np.pi * np.arange(nd) / nd
+    ff = dense.far_field(g, phi, th)
+    k = w.k_ext
+    for c, a in enumerate(w.angles):
+        lhs = np.sum(np.abs(ff[:, c]) ** 2) * 2 * np.pi / nd
+        f0 = dense.far_field(g, phi[:, c:c + 1], np.array([a]))[0, 0]
+        rhs = -np.sqrt(8 * np.pi / k) * np.real(np.exp(1j * np.pi / 4) * f0)
+        assert abs(lhs - rhs) < 1e-9 * lhs
+    A = dense.far_field(g, phi, w.angles)        # A[i, j] = u_inf(angle_i; incidence angle_j)
+    for i in range(4):
+        for j in range(4):
+            assert abs(A[i, j] - A[(j + 2) % 4, (i + 2) % 4]) < 1e-9 * np.max(np.abs(A))
+    assert np.max(np.abs(dense.energy_defect(g, phi))) < 1e-10
+
+
+def test_paper_dof_table():
+    """N = 2 n m unknowns (Sec. 4, Table tb:dof), for the star grids at n = 200."""
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "table_dof.txt"))
+            if l.strip() and not l.startswith("#")]
+    for m, dof in rows:
+        g = int(round(np.sqrt(int(m))))
+        w = W.star_grid(1, n=200)
+        assert g * g * w.n_unknowns == int(dof)
+
+
+def test_fast_method_against_dense_2x2_disks():
+    """Every leaf ID is full rank at this geometry: the fast method reproduces LU."""
+    w = W.config1()
+    ref = dense.solve(w)
+    fs = fast.FastSolver(w)
+    assert dense.rel_error(fs.solve(), ref) < 1e-12
+    assert fs.root_size() == 512
+
+
+@pytest.mark.parametrize("tol,bound", [(1e-10, 5e-9), (1e-6, 5e-5)])
+def test_fast_method_tracks_tolerance(tol, bound):
+    w = W.sub_grid(W.config2(), 4)
+    w.id_tol = tol
+    ref = dense.solve(w)
+    fs = fast.FastSolver(w)
+    err = dense.rel_error(fs.solve(), ref)
+    assert err < bound
+    assert err > 1e-3 * tol        # it does compress: not an exact solve
+    assert fs.root_size() < w.n_unknowns // 4
+
+
+def test_id_residual_and_rank_on_proxy_matrices():
+    """ID of a leaf's proxy/near matrix: residual ~ tol, rank >= SVD tol-rank."""
+    w = W.sub_grid(W.config2(), 4)
+    fs = fast.FastSolver.__new__(fast.FastSolver)
+    fs.w, fs.g, fs.tol = w, dense.Geometry(w), w.id_tol
+    fs.levels = fast.plan(w)
+    cells = fs.levels[0]
+    acts = [fs._leaf_active(c) for c in cells]
+    mats = fs._id_matrices(cells[5], acts[5], acts, cells)
+    for key, M in mats.items():
+        R, piv, k = fast.cpqr_id(M, w.id_tol)
+        Z = fast.interp_matrix(R, piv, k, M.shape[1])
+        res = np.linalg.norm(M - M[:, piv[:k]] @ Z, 2) / np.linalg.norm(M, 2)
+        s = np.linalg.svd(M, compute_uv=False)
+        svd_rank = int(np.sum(s > w.id_tol * s[0]))
+        assert res < 50 * w.id_tol, key
+        assert k >= svd_rank - 2, key
+
+
+def test_planted_sign_error_is_caught():
+    """A plausible mistake in the oracle (the sign of D*) breaks the Calderon pin."""
+    w = W.star_grid(1, n=128, k_ext=10.0, k_int=10.0)
+    S, D, Ds, N = layer.self_blocks(w.x, w.y, w.dx, w.dy, w.ddx, w.ddy, 10.0)
+    _, nx, ny, _, _ = layer.boundary_quantities(w.dx, w.dy, w.ddx, w.ddy, w.node_off)
+    v, dv = _point_source(w.x, w.y, nx, ny, (0.05, -0.03), 10.0)
+    I = np.eye(128)
+    good = np.max(np.abs(-(Ds + I / 2) @ dv + N @ v))
+    bad = np.max(np.abs(-(-Ds + I / 2) @ dv + N @ v))
+    assert good < 1e-9 * np.max(np.abs(dv)) < bad
+
+
+def test_planted_missing_interior_term_is_caught():
+    """Dropping the interior wavenumber from the diagonal block breaks the Mie pin."""
+    w = W.single_disk(n=64)
+    g = dense.Geometry(w)
+    A = dense.diagonal_block(g, 0)
+    s = (w.x, w.y, w.dx, w.dy, w.ddx, w.ddy)
+    Sm, Dm, Dsm, Nm = layer.self_blocks(*s, w.k_int[0])
+    em = g.eps_m[0]
+    A_bad = A - np.block([[-em * Sm, Dm], [-Dsm, Nm / em]])
+    f = dense.rhs(g, [0.0])[:, 0]
+    th = 2 * np.pi * np.arange(64) / 64
+    qm, um = analytic.mie_boundary(th, w.k_ext, w.k_int[0], 0.4, g.eps_p, em)
+    ref = np.concatenate([qm, um])
+    good = np.linalg.norm(np.linalg.solve(A, f) - ref) / np.linalg.norm(ref)
+    bad = np.linalg.norm(np.linalg.solve(A_bad, f) - ref) / np.linalg.norm(ref)
+    assert good < 1e-13 and bad > 1e-2
