@@ -1,0 +1,127 @@
+/* pmx: proxy-method fast direct solver for 2-D Helmholtz transmission through many
+ * disjoint inclusions, PMCHWT (Omit) Nystrom discretisation, on one AMD MI355X (gfx950).
+ *
+ * Method: arXiv 2603.09381.  Problem and boundary data: Sec. 2.1 (transmission
+ * conditions, eqs. pressure and flux; unknowns u and q = (1/eps) du/dn on each
+ * boundary).  System: the Omit form of Sec. 2.2 (exterior kernels only between
+ * different inclusions), unknowns ordered per inclusion as (q_i; u_i) and right-hand
+ * side (-u^I_i; -q^I_i).  Solver: Sec. 3 (proxy method + interpolative decomposition
+ * by column-pivoted QR with threshold rank, compressed system of eq. compressed,
+ * recovery formula, multi-level recursion), top system by partial-pivoted LU (Sec. 4).
+ * Self-interaction quadrature: Kress' logarithmic product rule (the paper uses a
+ * zeta-corrected rule instead), hypersingular operator through Maue's identity.
+ *
+ * Conventions.  Every function returns a pmx_status and never aborts; the text of the
+ * last error of the calling thread is returned by pmx_last_error().  Host pointers are
+ * only read during the call.  Device pointers must be device memory of the current
+ * HIP device (e.g. torch tensors); device results are written in stream order on the
+ * stream passed (a hipStream_t, NULL = default stream).
+ */
+#ifndef PMX_H
+#define PMX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  double re, im;
+} pmx_c64;
+
+typedef enum {
+  PMX_OK = 0,
+  PMX_EINVAL = 1,     /* bad argument (sizes, NULL, odd node count, NaN, ...) */
+  PMX_EGEOM = 2,      /* geometry not supported (shared grid cell, missing grid) */
+  PMX_ENOMEM = 3,     /* device allocation failed */
+  PMX_EHIP = 4,       /* a HIP runtime call failed */
+  PMX_ESINGULAR = 5,  /* zero pivot in an LU factorisation */
+  PMX_ENOTCONV = 6    /* iterative refinement did not reach its tolerance */
+} pmx_status;
+
+/* Geometry: m closed, counterclockwise, smooth boundaries.  Inclusion j owns nodes
+ * node_off[j] .. node_off[j+1]-1 (n_j = node_off[j+1]-node_off[j] even, >= 8), sampled at
+ * t = 2 pi l / n_j with the curve x(t), its first and second t-derivatives.  The unit
+ * normal n = (x2', -x1')/|x'| points into the exterior (Sec. 2.1).  Wavenumbers: k_ext
+ * outside, k_int[j] inside inclusion j; material constants eps_ext and eps_int[j]
+ * (NULL: eps_ext (k_int[j]/k_ext)^2, from k = omega sqrt(eps)).  grid_ij[2j], grid_ij[2j+1]
+ * are the integer grid cell of inclusion j (one inclusion per cell); the quadtree is
+ * built over these cells.  All arrays are host memory. */
+typedef struct {
+  int32_t m;
+  const int64_t* node_off;   /* [m+1] */
+  const double *x, *y;       /* [node_off[m]] */
+  const double *dx, *dy;
+  const double *ddx, *ddy;
+  const double* center;      /* [2m] inclusion centres (cell centres are their means) */
+  const int32_t* grid_ij;    /* [2m] */
+  double k_ext, eps_ext;
+  const double* k_int;       /* [m] */
+  const double* eps_int;     /* [m] or NULL */
+} pmx_geometry;
+
+typedef struct {
+  double id_tol;        /* CPQR threshold: keep |R_jj| > id_tol |R_11| (Sec. 3) */
+  double proxy_ratio;   /* proxy radius >= proxy_ratio * cell radius */
+  int32_t proxy_min;    /* minimum number of proxy points (exact number if proxy_rule = 1) */
+  int32_t proxy_rule;   /* 0: radius max(ratio r_c, 0.9 rho_far), adaptive count; 1: fixed */
+  int32_t near_rule;    /* 0: edge-adjacent cells + geometric test (Sec. 4); 1: geometric */
+  int32_t precision;    /* 0: FP64 throughout */
+  int32_t timing;       /* 1: record per-phase device times in pmx_info */
+  int32_t reserved[8];
+} pmx_options;
+
+typedef struct {
+  int32_t levels;            /* compressed levels below the root */
+  int32_t root_size;         /* size of the top compressed system */
+  int32_t n_unknowns;        /* 2 * total nodes */
+  int32_t cells[32];         /* cells per level */
+  int32_t rank_min[32], rank_max[32];   /* min / max skeleton count K per level */
+  double rank_mean[32];
+  double bytes_factor;       /* device bytes held by the factor */
+  double t_factor_ms;        /* wall time of pmx_factor_create (host clock, synchronised) */
+  double t_phase_ms[16];     /* with options.timing: assemble, id, schur, root, other */
+} pmx_info;
+
+typedef struct pmx_factor pmx_factor;
+
+/* Fills defaults: id_tol 1e-10, proxy_ratio 1.5, proxy_min 0, proxy_rule 0, near_rule 0,
+ * precision 0, timing 0. */
+void pmx_options_default(pmx_options* o);
+
+/* Builds the plan and the whole compressed factorisation on `hip_stream`.  Returns when
+ * the factor is complete (the call synchronises the stream).  *out is owned by the
+ * caller and released by pmx_factor_destroy.  Errors: PMX_EINVAL (bad sizes, odd or
+ * small n_j, NaN, non-positive wavenumber), PMX_EGEOM (missing or shared grid cells),
+ * PMX_ENOMEM, PMX_EHIP, PMX_ESINGULAR. */
+pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, void* hip_stream,
+                             pmx_factor** out);
+
+/* Densities for plane waves u^I = exp(i k_ext (cos a, sin a).x) (Sec. 4): dens is device
+ * memory [nrhs][2 * node_off[m]] of pmx_c64; column r holds, per inclusion j, q_j at its
+ * nodes followed by u_j at its nodes (Sec. 2.2).  angles is host memory [nrhs]. */
+pmx_status pmx_solve_plane_waves(pmx_factor* f, int32_t nrhs, const double* angles, pmx_c64* dens,
+                                 void* hip_stream);
+
+/* Densities for a general right-hand side f (device, same layout as dens, holding
+ * (-u^I_j; -q^I_j) per inclusion).  f and dens may not overlap. */
+pmx_status pmx_solve(pmx_factor* f, int32_t nrhs, const pmx_c64* rhs, pmx_c64* dens, void* hip_stream);
+
+/* Far-field pattern u_inf(theta) of the scattered field, u^S ~ e^{ikr}/sqrt(r) u_inf:
+ * out (device) [nrhs][ndir]; dirs host [ndir] angles; dens device as above. */
+pmx_status pmx_far_field(const pmx_factor* f, int32_t nrhs, const pmx_c64* dens, int32_t ndir,
+                         const double* dirs, pmx_c64* out, void* hip_stream);
+
+pmx_status pmx_factor_info(const pmx_factor* f, pmx_info* info);
+
+/* Releases everything the factor holds; accepts NULL. */
+void pmx_factor_destroy(pmx_factor* f);
+
+const char* pmx_status_string(pmx_status s);
+const char* pmx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

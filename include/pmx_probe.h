@@ -1,0 +1,65 @@
+/* pmx probe API: the library's own kernels on explicit inputs, for step-level checks.
+ *
+ * Each entry point runs exactly the kernel the factorisation uses, on caller data, so
+ * that a test can compare one step of the method with an independent reference.
+ * Pointers marked (device) are device memory; (host) host memory.  Results are written
+ * in stream order on `stream`; every call synchronises it before returning.
+ */
+#ifndef PMX_PROBE_H
+#define PMX_PROBE_H
+
+#include "pmx.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* J0, J1, Y0, Y1 at z[i] > 0 (device, n values); out (device) [4][n]. */
+pmx_status pmx_probe_bessel(const double* z, int64_t n, double* out, void* stream);
+
+/* Self block A_jj of inclusion j (Sec. 2.2 Omit form, Kress quadrature): out (device)
+ * 2n_j x 2n_j column major. */
+pmx_status pmx_probe_diag_block(const pmx_geometry* geom, int32_t j, pmx_c64* out, void* stream);
+
+/* Off-diagonal (exterior) matrix entries between boundary nodes: rows (host) [nr] node
+ * indices with row types rtyp (0 value, 1 normal-derivative equation), cols (host) [nc]
+ * with column types ctyp (0 q, 1 u); out (device) nr x nc column major. */
+pmx_status pmx_probe_entries(const pmx_geometry* geom, int32_t nr, const int32_t* rows,
+                             const int32_t* rtyp, int32_t nc, const int32_t* cols,
+                             const int32_t* ctyp, pmx_c64* out, void* stream);
+
+/* C = A B for a batch of column-major complex matrices packed back to back (device):
+ * A [batch][m x k], B [batch][k x n], C [batch][m x n]; opa/opb 0 N, 1 T, 2 C (conjugate
+ * transpose of the stored operand, whose shape is then k x m / n x k). */
+pmx_status pmx_probe_zgemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t opa, int32_t opb,
+                           const pmx_c64* A, const pmx_c64* B, pmx_c64* C, void* stream);
+
+/* LU with partial pivoting of a batch of n x n matrices (device, in place) and solve with
+ * nrhs right-hand sides B [batch][n x nrhs] (device, in place).  ipiv (device) [batch][n].
+ * info (host) [batch]: first zero pivot (1-based) or 0. */
+pmx_status pmx_probe_lu_solve(int32_t batch, int32_t n, pmx_c64* A, int32_t* ipiv, int32_t nrhs,
+                              pmx_c64* B, int32_t* info, void* stream);
+
+/* Interpolative decomposition of a batch of m x c matrices (device, destroyed): QR, then
+ * column-pivoted QR with threshold rank |R_jj| > tol |R_11|; k = max(rank, kmin[b]) pivots
+ * are kept.  Outputs: piv (device) [batch][c] column order, rank (host) [batch] threshold
+ * ranks, T (device) [batch][c x c] with T[0:k, 0:c-k] = R11^-1 R12 (leading dimension c).
+ * kmin (host) [batch] or NULL. */
+pmx_status pmx_probe_id(int32_t batch, int32_t m, int32_t c, pmx_c64* M, double tol,
+                        const int32_t* kmin, int32_t* piv, int32_t* rank, pmx_c64* T, void* stream);
+
+/* The quadtree plan, host only (no GPU): per level the number of cells; per cell its
+ * centre, radius, proxy radius, proxy count and near list.  Buffers (host) are filled up
+ * to their capacity; *n_levels, *n_cells_total and *n_near_total report the sizes
+ * needed.  cell_level [cap_cells], cell_first_incl, cell_center [2 cap], cell_rc,
+ * cell_rp, cell_p, near_off [cap_cells + 1], near [cap_near] (indices within the level). */
+pmx_status pmx_plan_query(const pmx_geometry* geom, const pmx_options* opts, int32_t cap_cells,
+                          int32_t cap_near, int32_t* n_levels, int32_t* n_cells_total,
+                          int32_t* n_near_total, int32_t* cell_level, int32_t* cell_first_incl,
+                          double* cell_center, double* cell_rc, double* cell_rp, int32_t* cell_p,
+                          int32_t* near_off, int32_t* near);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

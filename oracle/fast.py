@@ -110,9 +110,11 @@ def _cell_nodes(g, cell):
 def _near_and_proxy(w, g, cells):
     pts = [_cell_nodes(g, c) for c in cells]
     for c in cells:
-        cx = float(np.mean(w.centers[c.incl, 0]))
-        cy = float(np.mean(w.centers[c.incl, 1]))
-        c.center = (cx, cy)
+        sx = sy = 0.0
+        for j in c.incl:                      # plain left-to-right sums
+            sx += float(w.centers[j, 0])
+            sy += float(w.centers[j, 1])
+        c.center = (sx / len(c.incl), sy / len(c.incl))
     for t, c in enumerate(cells):
         px, py = pts[t]
         c.rc = float(np.max(np.hypot(px - c.center[0], py - c.center[1])))

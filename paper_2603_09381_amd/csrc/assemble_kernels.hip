@@ -1,0 +1,479 @@
+// Kernel-matrix assembly for the PMCHWT (Omit) system (arXiv 2603.09381, Sec. 2),
+// FP64 on gfx950 vector ALUs.
+//
+// Kernels: G = (i/4) H0(k r) with d = x - y, r = |d|; the four operators of Sec. 2.1
+// (eqs. slp, dlp, d_slp, d_dlp):
+//   S  = (i/4) H0,  D = (ik/4) H1 (n_y.d)/r,  D* = -(ik/4) H1 (n_x.d)/r,
+//   N  = (ik/4) [k H0 (n_x.d)(n_y.d)/r^2 - 2 H1 (n_x.d)(n_y.d)/r^3 + H1 (n_x.n_y)/r].
+// Off-diagonal blocks of the Omit form use only k+ and the trapezoid weight of the
+// source node (Sec. 2.2):  [[-e+ S, D], [-D*, N/e+]].  Self blocks use both k+ and
+// the inclusion's k- with Kress' logarithmic product quadrature and N written by
+// Maue's identity N = |x'|^-1 D_t S |x'|^-1 D_t + k^2 S_nn (trigonometric
+// differentiation D_t), then combined as
+//   [[-(e+ S+ + e- S-), D+ + D-], [-(D*+ + D*-), N+/e+ + N-/e-]].
+#include "assemble.h"
+#include "bessel.h"
+
+struct Pt {
+  double x, y, nx, ny, w;
+  int type;
+};
+
+__device__ inline Pt fetch_pt(const DevGeom& g, const DevProxy& p, int code) {
+  Pt q;
+  if (code >= 0) {
+    int n = code >> 1;
+    q.type = code & 1;
+    q.x = g.x[n];
+    q.y = g.y[n];
+    q.nx = g.nx[n];
+    q.ny = g.ny[n];
+    q.w = g.w[n];
+  } else {
+    int c = -code - 1;
+    int i = c >> 1;
+    q.type = c & 1;
+    q.x = p.x[i];
+    q.y = p.y[i];
+    q.nx = p.nx[i];
+    q.ny = p.ny[i];
+    q.w = p.w[i];
+  }
+  return q;
+}
+
+// One entry of the exterior (Omit off-diagonal) operator between target t (row type)
+// and source s (column type, carrying its quadrature weight).
+__device__ inline zd omit_entry(const Pt& t, const Pt& s, const ExtParams& e) {
+  const double d1 = t.x - s.x, d2 = t.y - s.y;
+  const double r = sqrt(d1 * d1 + d2 * d2);
+  const double ir = 1.0 / r;
+  const bes4 b = bessel01(e.k * r);
+  if (t.type == 0) {
+    if (s.type == 0) {  // -e+ (i/4) H0 w
+      const double f = 0.25 * e.eps * s.w;
+      return zmk(f * b.y0, -f * b.j0);
+    }
+    const double f = 0.25 * e.k * (s.nx * d1 + s.ny * d2) * ir * s.w;  // (ik/4) H1 (n_s.d)/r w
+    return zmk(-f * b.y1, f * b.j1);
+  }
+  const double ntd = (t.nx * d1 + t.ny * d2) * ir;
+  if (s.type == 0) {  // -D* w = (ik/4) H1 (n_t.d)/r w
+    const double f = 0.25 * e.k * ntd * s.w;
+    return zmk(-f * b.y1, f * b.j1);
+  }
+  const double nsd = (s.nx * d1 + s.ny * d2) * ir;
+  const double a = ntd * nsd;
+  const double bc = (t.nx * s.nx + t.ny * s.ny - 2.0 * a) * ir;
+  const double X = e.k * b.j0 * a + b.j1 * bc;
+  const double Y = e.k * b.y0 * a + b.y1 * bc;
+  const double f = 0.25 * e.k * s.w / e.eps;
+  return zmk(-f * Y, f * X);
+}
+
+// ---------------------------------------------------------------------------------
+__global__ void k_geometry(const double* dx, const double* dy, const double* ddx, const double* ddy,
+                           const int* owner, const int64_t* node_off, double* nx, double* ny,
+                           double* w, double* speed, double* kappa, int n_nodes) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_nodes) return;
+  const double a = dx[i], b = dy[i];
+  const double sp = sqrt(a * a + b * b);
+  const int j = owner[i];
+  const double n = (double)(node_off[j + 1] - node_off[j]);
+  speed[i] = sp;
+  nx[i] = b / sp;
+  ny[i] = -a / sp;
+  w[i] = (2.0 * PMX_PI / n) * sp;
+  kappa[i] = (a * ddy[i] - b * ddx[i]) / (sp * sp * sp);
+}
+
+void asm_geometry(const double* dx, const double* dy, const double* ddx, const double* ddy,
+                  const int* owner, const int64_t* node_off, double* nx, double* ny, double* w,
+                  double* speed, double* kappa, int n_nodes, hipStream_t s) {
+  if (n_nodes <= 0) return;
+  hipLaunchKernelGGL(k_geometry, dim3((n_nodes + 255) / 256), dim3(256), 0, s, dx, dy, ddx, ddy,
+                     owner, node_off, nx, ny, w, speed, kappa, n_nodes);
+}
+
+// Kress weights R_d = -(2pi/h) sum_{m<h} cos(m t_d)/m - (pi/h^2) cos(h t_d), n = 2h, and the
+// trigonometric differentiation stencil dt_d = (1/2)(-1)^d cot(t_d/2), t_d = 2 pi d / n.
+__global__ void k_tables(const int* ns, const int* tbl_off, double* R, double* dt) {
+  const int t = blockIdx.y;
+  const int n = ns[t];
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= n) return;
+  const int h = n / 2;
+  double s = 0;
+  for (int m = h - 1; m >= 1; --m) {
+    const int ph = (int)(((int64_t)m * d) % n);
+    s += cos(2.0 * PMX_PI * ph / n) / m;
+  }
+  const double sign = (d & 1) ? -1.0 : 1.0;
+  R[tbl_off[t] + d] = -(2.0 * PMX_PI / h) * s - (PMX_PI / ((double)h * h)) * sign;
+  dt[tbl_off[t] + d] = d == 0 ? 0.0 : 0.5 * sign / tan(PMX_PI * d / n);
+}
+
+void asm_tables(const int* ns, const int* tbl_off, int ntbl, int max_n, double* R, double* dt,
+                hipStream_t s) {
+  if (ntbl <= 0) return;
+  hipLaunchKernelGGL(k_tables, dim3((max_n + 127) / 128, ntbl), dim3(128), 0, s, ns, tbl_off, R, dt);
+}
+
+// ---------------------------------------------------------------------------------
+// self block, pair stage: everything except the D_t products of Maue's identity
+struct KressOps {
+  zd S, D, Ds, Snn;
+};
+
+__device__ inline KressOps kress_pair(double k, double r, double d1, double d2, double nxa, double nya,
+                                      double nxb, double nyb, double spb, double Rw, double L, double q) {
+  const bes4 b = bessel01(k * r);
+  const double ir = 1.0 / r;
+  const double ndy = (nxb * d1 + nyb * d2) * ir;
+  const double ndx = (nxa * d1 + nya * d2) * ir;
+  const double nn = nxa * nxb + nya * nyb;
+  const double i4p = 1.0 / (4.0 * PMX_PI);
+  KressOps o;
+  // S: K = (-y0/4 + i j0/4) sp, K1 = -j0 sp/(4 pi)
+  {
+    const double K1 = -b.j0 * spb * i4p;
+    o.S = zmk(Rw * K1 + q * (-0.25 * b.y0 * spb - K1 * L), q * 0.25 * b.j0 * spb);
+    o.Snn = zscale(o.S, nn);
+  }
+  // D: K = (ik/4) H1 ndy sp = (-k y1/4 + i k j1/4) ndy sp, K1 = -(k/4pi) j1 ndy sp
+  {
+    const double f = ndy * spb;
+    const double K1 = -k * i4p * b.j1 * f;
+    o.D = zmk(Rw * K1 + q * (-0.25 * k * b.y1 * f - K1 * L), q * 0.25 * k * b.j1 * f);
+  }
+  // D*: K = -(ik/4) H1 ndx sp = (k y1/4 - i k j1/4) ndx sp, K1 = (k/4pi) j1 ndx sp
+  {
+    const double f = ndx * spb;
+    const double K1 = k * i4p * b.j1 * f;
+    o.Ds = zmk(Rw * K1 + q * (0.25 * k * b.y1 * f - K1 * L), -q * 0.25 * k * b.j1 * f);
+  }
+  return o;
+}
+
+__device__ inline KressOps kress_self(double k, double sp, double kap, double R0, double q) {
+  KressOps o;
+  const double i4p = 1.0 / (4.0 * PMX_PI);
+  const double K1 = -sp * i4p;
+  const zd K2 = zmk((-PMX_EULER / (2.0 * PMX_PI) - log(0.5 * k * sp) / (2.0 * PMX_PI)) * sp, 0.25 * sp);
+  o.S = zmk(R0 * K1 + q * K2.re, q * K2.im);
+  o.Snn = o.S;
+  o.D = zmk(-q * kap * sp * i4p, 0.0);
+  o.Ds = o.D;
+  return o;
+}
+
+__global__ __launch_bounds__(256) void k_diag_pairs(DevGeom g, ExtParams e, const DiagDesc* ds,
+                                                     const double* R) {
+  const DiagDesc d = ds[blockIdx.y];
+  const int n = d.n;
+  const int e_idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e_idx >= n * n) return;
+  const int a = e_idx % n, b = e_idx / n;
+  const int ia = d.node0 + a, ib = d.node0 + b;
+  const double q = 2.0 * PMX_PI / n;
+  const int dd = ((a - b) % n + n) % n;
+  const double Rw = R[d.tbl + dd];
+  KressOps P, M;
+  if (a == b) {
+    P = kress_self(e.k, g.speed[ia], g.kappa[ia], Rw, q);
+    M = kress_self(d.k_int, g.speed[ia], g.kappa[ia], Rw, q);
+  } else {
+    const double d1 = g.x[ia] - g.x[ib], d2 = g.y[ia] - g.y[ib];
+    const double r = sqrt(d1 * d1 + d2 * d2);
+    const double sn = sin(PMX_PI * dd / n);
+    const double L = log(4.0 * sn * sn);
+    P = kress_pair(e.k, r, d1, d2, g.nx[ia], g.ny[ia], g.nx[ib], g.ny[ib], g.speed[ib], Rw, L, q);
+    M = kress_pair(d.k_int, r, d1, d2, g.nx[ia], g.ny[ia], g.nx[ib], g.ny[ib], g.speed[ib], Rw, L, q);
+  }
+  const double ep = e.eps, em = d.eps_int;
+  const int64_t ld = 2 * n;
+  zd* out = d.out;
+  out[a + (int64_t)b * ld] = zadd(zscale(P.S, -ep), zscale(M.S, -em));
+  out[a + (int64_t)(n + b) * ld] = zadd(P.D, M.D);
+  out[(n + a) + (int64_t)b * ld] = zscale(zadd(P.Ds, M.Ds), -1.0);
+  out[(n + a) + (int64_t)(n + b) * ld] =
+      zadd(zscale(P.Snn, e.k * e.k / ep), zscale(M.Snn, d.k_int * d.k_int / em));
+  d.scratch[a + (int64_t)b * n] = zadd(zscale(P.S, 1.0 / ep), zscale(M.S, 1.0 / em));
+}
+
+// W = X |x'|^-1 D_t   (X in scratch, W to scratch2)
+__global__ __launch_bounds__(256) void k_diag_maue1(DevGeom g, const DiagDesc* ds, const double* dt) {
+  const DiagDesc d = ds[blockIdx.y];
+  const int n = d.n;
+  const int e_idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e_idx >= n * n) return;
+  const int c = e_idx % n, b = e_idx / n;
+  const double* tb = dt + d.tbl;
+  double sr = 0, si = 0;
+  for (int k = 0; k < n; ++k) {
+    const int dd = ((k - b) % n + n) % n;
+    const double f = tb[dd] / g.speed[d.node0 + k];
+    const zd x = d.scratch[c + (int64_t)k * n];
+    sr = fma(x.re, f, sr);
+    si = fma(x.im, f, si);
+  }
+  d.scratch2[c + (int64_t)b * n] = zmk(sr, si);
+}
+
+// A22 += |x'|^-1 D_t W
+__global__ __launch_bounds__(256) void k_diag_maue2(DevGeom g, const DiagDesc* ds, const double* dt) {
+  const DiagDesc d = ds[blockIdx.y];
+  const int n = d.n;
+  const int e_idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e_idx >= n * n) return;
+  const int a = e_idx % n, b = e_idx / n;
+  const double* tb = dt + d.tbl;
+  double sr = 0, si = 0;
+  for (int c = 0; c < n; ++c) {
+    const int dd = ((a - c) % n + n) % n;
+    const zd w = d.scratch2[c + (int64_t)b * n];
+    sr = fma(tb[dd], w.re, sr);
+    si = fma(tb[dd], w.im, si);
+  }
+  const double f = 1.0 / g.speed[d.node0 + a];
+  const int64_t ld = 2 * n;
+  zd* o = d.out + (n + a) + (int64_t)(n + b) * ld;
+  *o = zadd(*o, zmk(sr * f, si * f));
+}
+
+void asm_diag(DevGeom g, ExtParams e, const DiagDesc* d, int batch, int max_n, const double* R,
+              const double* dt, hipStream_t s) {
+  if (batch <= 0 || max_n <= 0) return;
+  dim3 grid((max_n * max_n + 255) / 256, batch);
+  hipLaunchKernelGGL(k_diag_pairs, grid, dim3(256), 0, s, g, e, d, R);
+  hipLaunchKernelGGL(k_diag_maue1, grid, dim3(256), 0, s, g, d, dt);
+  hipLaunchKernelGGL(k_diag_maue2, grid, dim3(256), 0, s, g, d, dt);
+}
+
+// ---------------------------------------------------------------------------------
+#define ENT_ROWS 64
+#define ENT_COLS 16
+__global__ __launch_bounds__(256) void k_entries(DevGeom g, DevProxy p, ExtParams e, const EntryMat* ms) {
+  const EntryMat m = ms[blockIdx.z];
+  const int i = blockIdx.x * ENT_ROWS + (threadIdx.x & 63);
+  const int j0 = blockIdx.y * ENT_COLS + (threadIdx.x >> 6);
+  if (blockIdx.x * ENT_ROWS >= m.na || blockIdx.y * ENT_COLS >= m.nb) return;
+  if (i >= m.na) return;
+  const Pt pa = fetch_pt(g, p, m.a[i]);
+  for (int j = j0; j < min(m.nb, (int)(blockIdx.y + 1) * ENT_COLS); j += 4) {
+    const Pt pb = fetch_pt(g, p, m.b[j]);
+    m.out[i + (int64_t)j * m.ld] = m.a_is_target ? omit_entry(pa, pb, e) : omit_entry(pb, pa, e);
+  }
+}
+
+void asm_entries(DevGeom g, DevProxy p, ExtParams e, const EntryMat* d, int batch, int max_a,
+                 int max_b, hipStream_t s) {
+  if (batch <= 0 || max_a <= 0 || max_b <= 0) return;
+  dim3 grid((max_a + ENT_ROWS - 1) / ENT_ROWS, (max_b + ENT_COLS - 1) / ENT_COLS, batch);
+  hipLaunchKernelGGL(k_entries, grid, dim3(256), 0, s, g, p, e, d);
+}
+
+__global__ __launch_bounds__(256) void k_parent(DevGeom g, ExtParams e, const ParentDesc* ds) {
+  const ParentDesc d = ds[blockIdx.y];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)d.s * d.s) return;
+  const int a = (int)(idx % d.s), b = (int)(idx / d.s);
+  const int ra = d.rloc[a], cb = d.cloc[b];
+  const int sa = ra >> 24, sb = cb >> 24;
+  zd v;
+  if (sa == sb) {
+    const int la = ra & 0xFFFFFF, lb = cb & 0xFFFFFF;
+    v = d.at[sa][la + (int64_t)lb * d.kc[sa]];
+  } else {
+    DevProxy none{nullptr, nullptr, nullptr, nullptr, nullptr};
+    v = omit_entry(fetch_pt(g, none, d.rcode[a]), fetch_pt(g, none, d.ccode[b]), e);
+  }
+  d.out[idx] = v;
+}
+
+void asm_parent(DevGeom g, ExtParams e, const ParentDesc* d, int batch, int max_s, hipStream_t s) {
+  if (batch <= 0 || max_s <= 0) return;
+  int64_t tot = (int64_t)max_s * max_s;
+  hipLaunchKernelGGL(k_parent, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, s, g, e, d);
+}
+
+// ---------------------------------------------------------------------------------
+__global__ void k_incident(DevGeom g, ExtParams e, const int* cell_node0, const int* cell_n,
+                           const int64_t* cell_off, const double* angles, int nrhs, zd* f) {
+  const int c = blockIdx.z;
+  const int n = cell_n[c];
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (row >= 2 * n || r >= nrhs) return;
+  const int node = cell_node0[c] + (row < n ? row : row - n);
+  double sa, ca;
+  sincos(angles[r], &sa, &ca);
+  const double ph = e.k * (ca * g.x[node] + sa * g.y[node]);
+  double s, co;
+  sincos(ph, &s, &co);
+  zd u = zmk(co, s);
+  zd v;
+  if (row < n) {
+    v = zmk(-u.re, -u.im);
+  } else {
+    const double dn = e.k * (ca * g.nx[node] + sa * g.ny[node]) / e.eps;  // q = i k (d.n)/e u
+    v = zmk(dn * u.im, -dn * u.re);                                        // -(i dn) u
+  }
+  f[cell_off[c] + row + (int64_t)r * 2 * n] = v;
+}
+
+void asm_incident(DevGeom g, ExtParams e, const int* cell_node0, const int* cell_n,
+                  const int64_t* cell_off, int ncell, int max_n, const double* angles, int nrhs,
+                  zd* f, hipStream_t s) {
+  if (ncell <= 0 || nrhs <= 0) return;
+  dim3 grid((2 * max_n + 127) / 128, nrhs, ncell);
+  hipLaunchKernelGGL(k_incident, grid, dim3(128), 0, s, g, e, cell_node0, cell_n, cell_off,
+                     angles, nrhs, f);
+}
+
+__global__ void k_gather(const zd* src, const GatherDesc* ds) {
+  const GatherDesc d = ds[blockIdx.z];
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int c = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= d.nrows || c >= d.ncols) return;
+  const RowSrc rs = d.src[i];
+  d.dst[i + (int64_t)c * d.ld] = src[rs.off + (int64_t)c * rs.ld];
+}
+
+void asm_gather(const zd* src, const GatherDesc* d, int batch, int max_rows, int max_cols, hipStream_t s) {
+  if (batch <= 0 || max_rows <= 0 || max_cols <= 0) return;
+  dim3 grid((max_rows + 63) / 64, (max_cols + 3) / 4, batch);
+  hipLaunchKernelGGL(k_gather, grid, dim3(256), 0, s, src, d);
+}
+
+__global__ void k_identity(const Mat2* ds) {
+  const Mat2 d = ds[blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)d.n * d.n) return;
+  const int i = (int)(e % d.n), j = (int)(e / d.n);
+  d.p[i + j * d.ld] = zmk(i == j ? 1.0 : 0.0, 0.0);
+}
+
+void asm_identity(const Mat2* d, int batch, int max_n, hipStream_t s) {
+  if (batch <= 0 || max_n <= 0) return;
+  int64_t tot = (int64_t)max_n * max_n;
+  hipLaunchKernelGGL(k_identity, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, s, d);
+}
+
+__global__ void k_zero(zd* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = zmk(0, 0);
+}
+
+void asm_zero(zd* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+}
+
+__global__ void k_axpy(zd* y, const zd* x, zd a, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = zfma(a, x[i], y[i]);
+}
+
+void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, x, a, n);
+}
+
+// ---------------------------------------------------------------------------------
+// u_inf(xh) = e^{i pi/4}/sqrt(8 pi k) sum_b w_b [-i k (xh.n_b) u_b - e+ q_b] e^{-i k xh.y_b}
+__global__ __launch_bounds__(256) void k_far_field(DevGeom g, ExtParams e, const int* owner,
+                                                    const int64_t* node_off, const zd* dens, int nrhs,
+                                                    const double* dirs, int ndir, zd* out) {
+  const int t = blockIdx.x, r = blockIdx.y;
+  double sx, cx;
+  sincos(dirs[t], &sx, &cx);
+  const int64_t ld = 2 * (int64_t)g.n_nodes;
+  double ar = 0, ai = 0;
+  for (int i = threadIdx.x; i < g.n_nodes; i += 256) {
+    const int j = owner[i];
+    const int64_t o = node_off[j];
+    const int64_t n = node_off[j + 1] - o;
+    const int64_t l = i - o;
+    const zd q = dens[r * ld + 2 * o + l];
+    const zd u = dens[r * ld + 2 * o + n + l];
+    const double xn = cx * g.nx[i] + sx * g.ny[i];
+    // -i k xn u - e q
+    const zd a = zmk(e.k * xn * u.im - e.eps * q.re, -e.k * xn * u.re - e.eps * q.im);
+    double s, c;
+    sincos(-e.k * (cx * g.x[i] + sx * g.y[i]), &s, &c);
+    const zd v = zmul(a, zmk(c, s));
+    ar = fma(g.w[i], v.re, ar);
+    ai = fma(g.w[i], v.im, ai);
+  }
+  __shared__ double red[2][4];
+  for (int o = 32; o >= 1; o >>= 1) {
+    ar += __shfl_xor(ar, o, 64);
+    ai += __shfl_xor(ai, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = ar;
+    red[1][threadIdx.x >> 6] = ai;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sr = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    double si = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const double amp = 1.0 / sqrt(8.0 * PMX_PI * e.k);
+    const double c4 = 0.70710678118654752440;
+    const zd ph = zmk(c4 * amp, c4 * amp);
+    out[(int64_t)r * ndir + t] = zmul(ph, zmk(sr, si));
+  }
+}
+
+void asm_far_field(DevGeom g, ExtParams e, const int* owner, const int64_t* node_off,
+                   const zd* dens, int nrhs, const double* dirs, int ndir, zd* out, hipStream_t s) {
+  if (nrhs <= 0 || ndir <= 0) return;
+  hipLaunchKernelGGL(k_far_field, dim3(ndir, nrhs), dim3(256), 0, s, g, e, owner, node_off, dens,
+                     nrhs, dirs, ndir, out);
+}
+
+// ---------------------------------------------------------------------------------
+__global__ void k_build_l(const LDesc* ds) {
+  const LDesc d = ds[blockIdx.z];
+  const int type = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sb = type ? d.s1 : d.s0;
+  if (j >= sb) return;
+  const int kb = type ? d.k1 : d.k0;
+  const int* piv = type ? d.piv1 : d.piv0;
+  const zd* t = type ? d.t1 : d.t0;
+  const int ldt = type ? d.ldt1 : d.ldt0;
+  const int off_r = type ? d.s0 : 0;
+  const int off_c = type ? d.k0 : 0;
+  const int64_t s = d.s0 + d.s1;
+  const int row = off_r + piv[j];
+  if (j < kb) {
+    d.out[row + (int64_t)(off_c + j) * s] = zmk(1, 0);
+  } else {
+    for (int i = 0; i < kb; ++i) d.out[row + (int64_t)(off_c + i) * s] = t[i + (int64_t)(j - kb) * ldt];
+  }
+}
+
+void asm_build_l(const LDesc* d, int batch, int max_s, int max_k, hipStream_t s) {
+  (void)max_k;
+  if (batch <= 0 || max_s <= 0) return;
+  dim3 grid((max_s + 127) / 128, 2, batch);
+  hipLaunchKernelGGL(k_build_l, grid, dim3(128), 0, s, d);
+}
+
+__global__ void k_probe_bessel(const double* z, int64_t n, double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bes4 b = bessel01(z[i]);
+  out[i] = b.j0;
+  out[n + i] = b.j1;
+  out[2 * n + i] = b.y0;
+  out[3 * n + i] = b.y1;
+}
+
+void asm_probe_bessel(const double* z, int64_t n, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_probe_bessel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, n, out);
+}

@@ -1,0 +1,1440 @@
+// Host orchestration of the recursive proxy solver (arXiv 2603.09381, Sec. 3) and the
+// C-ABI of include/pmx.h and include/pmx_probe.h.
+//
+// Factorisation, level by level from the leaves (one inclusion per cell) to the root:
+//   1. D_tau: the self block A_ii at the leaves; at a parent the block of the compressed
+//      system gathered from the children (their At on the diagonal, kernel entries
+//      between different children's skeletons off it, Sec. 3 multi-level remark).
+//   2. Four interpolative decompositions per cell (q columns, u columns, value rows,
+//      derivative rows): matrices of the cell's active columns against the near cells'
+//      active rows plus proxy rows (and the transposed row versions), exterior kernel
+//      only (the Omit property); Householder QR, then column-pivoted QR with the
+//      threshold |R_jj| > tol |R_11|; pairs (q, value) and (u, derivative) keep the
+//      larger of their two ranks; T = R11^-1 R12.
+//   3. Schur step: LU(D), Y = D^-1 L, M = R Y, At = M^-1 (At = (R A^-1 L)^-1 of Sec. 3).
+//   4. Skeleton rows and columns become the parent's active sets.
+// The top system is factored by partial-pivoted LU (Sec. 4).  The solve runs the
+// upward pass (y = D^-1 f, g = At R y), the root solve and the downward recovery
+// x = y - Y (g - At psi), the recovery formula of Sec. 3.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pmx.h"
+#include "../../include/pmx_probe.h"
+#include "assemble.h"
+#include "la.h"
+#include "plan.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct PmxErr {
+  pmx_status st;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess) throw PmxErr{PMX_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+void fail(pmx_status st, const std::string& msg) { throw PmxErr{st, msg}; }
+
+// Device allocations owned by one object, released together.
+class Arena {
+ public:
+  ~Arena() { release(); }
+  template <class T>
+  T* alloc(size_t n) {
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(PMX_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    }
+    ptrs_.push_back(p);
+    bytes_ += n * sizeof(T);
+    return (T*)p;
+  }
+  // The host data is copied into storage owned by the arena, so the asynchronous copy
+  // never reads a buffer the caller has already released.
+  template <class T>
+  T* upload(const std::vector<T>& v, hipStream_t s) {
+    T* p = alloc<T>(v.size());
+    if (!v.empty()) {
+      keep_.emplace_back((const char*)v.data(), (const char*)v.data() + v.size() * sizeof(T));
+      HIPCHK(hipMemcpyAsync(p, keep_.back().data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    return p;
+  }
+  void release() {
+    for (void* p : ptrs_) (void)hipFree(p);
+    ptrs_.clear();
+    keep_.clear();
+    bytes_ = 0;
+  }
+  double bytes() const { return (double)bytes_; }
+
+ private:
+  std::vector<void*> ptrs_;
+  std::vector<std::vector<char>> keep_;
+  size_t bytes_ = 0;
+};
+
+template <class T>
+void download(std::vector<T>& v, const T* d, size_t n, hipStream_t s) {
+  v.resize(n);
+  if (n) HIPCHK(hipMemcpyAsync(v.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+void sync_check(hipStream_t s) {
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// Data kept for one compressed level.
+struct LevelData {
+  int ncell = 0;
+  std::vector<int> s0, s1, k0, k1;            // active sizes and skeleton sizes per type
+  std::vector<int64_t> offD, offY, offA, offT, offS, offK;
+  std::vector<int> cpiv;                      // column-ID pivots, per cell [s0 | s1]
+  std::vector<int64_t> offP;                  // offsets into cpiv (= offS)
+  // active codes (rows, cols) and skeleton codes, host
+  std::vector<int> rows, cols;                // concatenated per cell, offsets offS
+  std::vector<int> rskel, cskel;              // concatenated per cell, offsets offK
+  std::vector<std::vector<int>> children;     // plan children (only for the parent level)
+  zd* D = nullptr;                            // LU of D per cell
+  int* ipiv = nullptr;
+  zd* Y = nullptr;                            // D^-1 L, s x K
+  zd* At = nullptr;                           // K x K
+  zd* Tc = nullptr;                           // column-ID T blocks, [k0 x (s0-k0)] then [k1 x (s1-k1)]
+  LuDesc* d_lu = nullptr;
+  int max_s = 0, max_k = 0;
+  int64_t tot_s = 0, tot_k = 0;
+};
+
+struct SolveCache {
+  int nrhs = -1;
+  std::vector<zd*> F;      // per level: y / f vectors, sum s x nrhs
+  std::vector<zd*> G;      // per level: K x nrhs
+  std::vector<zd*> Red;    // per level: redundant rows scratch
+  zd* Froot = nullptr;
+  Arena arena;
+};
+
+struct pmx_factor {
+  // geometry (device)
+  int m = 0, n_nodes = 0;
+  double k_ext = 0, eps_ext = 1;
+  std::vector<int64_t> node_off;
+  std::vector<double> k_int, eps_int;
+  double *x, *y, *nx, *ny, *w, *speed, *kappa;
+  int* owner = nullptr;
+  int64_t* d_node_off = nullptr;
+  pmx_options opts;
+  std::vector<std::vector<CellPlan>> plan;
+  std::vector<LevelData> lev;     // compressed levels
+  // root
+  int root_s = 0;
+  zd* Droot = nullptr;
+  int* ipiv_root = nullptr;
+  LuDesc* d_lu_root = nullptr;
+  std::vector<int> root_rows, root_cols;
+  Arena arena;
+  SolveCache sc;
+  pmx_info info;
+  DevGeom geom() const { return DevGeom{x, y, nx, ny, w, speed, kappa, n_nodes}; }
+  ExtParams ext() const { return ExtParams{k_ext, eps_ext}; }
+};
+
+namespace {
+
+void validate(const pmx_geometry* g, const pmx_options* o) {
+  if (!g) fail(PMX_EINVAL, "geometry is NULL");
+  if (g->m <= 0) fail(PMX_EINVAL, "m must be positive");
+  if (!g->node_off || !g->x || !g->y || !g->dx || !g->dy || !g->ddx || !g->ddy || !g->center || !g->k_int)
+    fail(PMX_EINVAL, "a required geometry array is NULL");
+  if (!(g->k_ext > 0) || !std::isfinite(g->k_ext)) fail(PMX_EINVAL, "k_ext must be positive");
+  if (!(g->eps_ext > 0)) fail(PMX_EINVAL, "eps_ext must be positive");
+  if (g->node_off[0] != 0) fail(PMX_EINVAL, "node_off[0] must be 0");
+  for (int j = 0; j < g->m; ++j) {
+    int64_t n = g->node_off[j + 1] - g->node_off[j];
+    if (n < 8 || (n & 1)) fail(PMX_EINVAL, "inclusion " + std::to_string(j) + ": node count must be even and >= 8");
+    if (!(g->k_int[j] > 0) || !std::isfinite(g->k_int[j])) fail(PMX_EINVAL, "k_int must be positive");
+    if (g->eps_int && !(g->eps_int[j] > 0)) fail(PMX_EINVAL, "eps_int must be positive");
+  }
+  int64_t N = g->node_off[g->m];
+  if (N > (int64_t)1 << 29) fail(PMX_EINVAL, "too many nodes");
+  for (int64_t i = 0; i < N; ++i) {
+    double v[6] = {g->x[i], g->y[i], g->dx[i], g->dy[i], g->ddx[i], g->ddy[i]};
+    for (double t : v)
+      if (!std::isfinite(t)) fail(PMX_EINVAL, "non-finite node data");
+    if (g->dx[i] == 0.0 && g->dy[i] == 0.0) fail(PMX_EINVAL, "zero tangent");
+  }
+  if (o) {
+    if (!(o->id_tol > 0) || o->id_tol >= 1) fail(PMX_EINVAL, "id_tol must be in (0, 1)");
+    if (!(o->proxy_ratio > 1.0)) fail(PMX_EINVAL, "proxy_ratio must exceed 1");
+    if (o->proxy_rule == 1 && o->proxy_min < 8) fail(PMX_EINVAL, "a fixed proxy count must be >= 8");
+    if (o->precision != 0) fail(PMX_EINVAL, "only precision 0 (FP64) is available");
+  }
+}
+
+PlanOptions plan_options(const pmx_geometry* g, const pmx_options& o) {
+  PlanOptions p;
+  p.proxy_ratio = o.proxy_ratio;
+  p.proxy_min = o.proxy_min;
+  p.near_rule = o.near_rule;
+  p.proxy_rule = o.proxy_rule;
+  p.id_tol = o.id_tol;
+  p.k_ext = g->k_ext;
+  return p;
+}
+
+void make_plan(const pmx_geometry* g, const pmx_options& o, std::vector<std::vector<CellPlan>>& levels) {
+  std::string err = build_plan(g->m, g->grid_ij, g->center, g->node_off, g->x, g->y, plan_options(g, o), levels);
+  if (!err.empty()) fail(PMX_EGEOM, err);
+}
+
+void upload_geometry(pmx_factor* F, const pmx_geometry* g, hipStream_t s) {
+  F->m = g->m;
+  F->node_off.assign(g->node_off, g->node_off + g->m + 1);
+  F->n_nodes = (int)F->node_off.back();
+  F->k_ext = g->k_ext;
+  F->eps_ext = g->eps_ext;
+  F->k_int.assign(g->k_int, g->k_int + g->m);
+  F->eps_int.resize(g->m);
+  for (int j = 0; j < g->m; ++j)
+    F->eps_int[j] = g->eps_int ? g->eps_int[j] : g->eps_ext * (g->k_int[j] / g->k_ext) * (g->k_int[j] / g->k_ext);
+  const int N = F->n_nodes;
+  Arena& A = F->arena;
+  std::vector<int> owner(N);
+  for (int j = 0; j < g->m; ++j)
+    for (int64_t i = g->node_off[j]; i < g->node_off[j + 1]; ++i) owner[i] = j;
+  auto up = [&](const double* h) {
+    double* d = A.alloc<double>(N);
+    HIPCHK(hipMemcpyAsync(d, h, N * sizeof(double), hipMemcpyHostToDevice, s));
+    return d;
+  };
+  F->x = up(g->x);
+  F->y = up(g->y);
+  double* dx = up(g->dx);
+  double* dy = up(g->dy);
+  double* ddx = up(g->ddx);
+  double* ddy = up(g->ddy);
+  F->owner = A.upload(owner, s);
+  F->d_node_off = A.upload(F->node_off, s);
+  F->nx = A.alloc<double>(N);
+  F->ny = A.alloc<double>(N);
+  F->w = A.alloc<double>(N);
+  F->speed = A.alloc<double>(N);
+  F->kappa = A.alloc<double>(N);
+  asm_geometry(dx, dy, ddx, ddy, F->owner, F->d_node_off, F->nx, F->ny, F->w, F->speed, F->kappa, N, s);
+  sync_check(s);
+}
+
+// Kress / differentiation tables for the distinct node counts.
+struct Tables {
+  std::map<int, int> off;   // n -> offset
+  double *R = nullptr, *dt = nullptr;
+};
+
+Tables make_tables(Arena& A, const std::vector<int>& ns_all, hipStream_t s) {
+  Tables T;
+  std::vector<int> ns, offs;
+  int tot = 0, maxn = 0;
+  for (int n : ns_all)
+    if (!T.off.count(n)) {
+      T.off[n] = tot;
+      ns.push_back(n);
+      offs.push_back(tot);
+      tot += n;
+      maxn = std::max(maxn, n);
+    }
+  T.R = A.alloc<double>(tot);
+  T.dt = A.alloc<double>(tot);
+  int* d_ns = A.upload(ns, s);
+  int* d_off = A.upload(offs, s);
+  asm_tables(d_ns, d_off, (int)ns.size(), maxn, T.R, T.dt, s);
+  return T;
+}
+
+// Leaf self blocks for the given inclusions into out[off_i], ld 2 n_i.
+void assemble_diag(pmx_factor* F, Arena& tmp, const std::vector<int>& incl, zd* D,
+                   const std::vector<int64_t>& offD, hipStream_t s) {
+  std::vector<int> ns;
+  for (int j : incl) ns.push_back((int)(F->node_off[j + 1] - F->node_off[j]));
+  Tables T = make_tables(tmp, ns, s);
+  int64_t scr = 0;
+  int maxn = 0;
+  for (int n : ns) {
+    scr += (int64_t)n * n;
+    maxn = std::max(maxn, n);
+  }
+  zd* s1 = tmp.alloc<zd>(scr);
+  zd* s2 = tmp.alloc<zd>(scr);
+  std::vector<DiagDesc> dd(incl.size());
+  int64_t so = 0;
+  for (size_t t = 0; t < incl.size(); ++t) {
+    int j = incl[t];
+    DiagDesc& d = dd[t];
+    d.node0 = (int)F->node_off[j];
+    d.n = ns[t];
+    d.k_int = F->k_int[j];
+    d.eps_int = F->eps_int[j];
+    d.tbl = T.off[d.n];
+    d.out = D + offD[t];
+    d.scratch = s1 + so;
+    d.scratch2 = s2 + so;
+    so += (int64_t)d.n * d.n;
+  }
+  DiagDesc* d_dd = tmp.upload(dd, s);
+  asm_diag(F->geom(), F->ext(), d_dd, (int)incl.size(), maxn, T.R, T.dt, s);
+}
+
+struct ProxyTable {
+  DevProxy dev{nullptr, nullptr, nullptr, nullptr, nullptr};
+  std::vector<int> off;   // per cell first proxy index
+};
+
+ProxyTable make_proxies(Arena& A, const std::vector<CellPlan>& cells, hipStream_t s) {
+  ProxyTable P;
+  std::vector<double> px, py, pnx, pny, pw;
+  for (const CellPlan& c : cells) {
+    P.off.push_back((int)px.size());
+    for (int k = 0; k < c.P; ++k) {
+      double th = 2.0 * M_PI * k / c.P;
+      double ct = std::cos(th), st = std::sin(th);
+      px.push_back(c.cx + c.Rp * ct);
+      py.push_back(c.cy + c.Rp * st);
+      pnx.push_back(ct);
+      pny.push_back(st);
+      pw.push_back(2.0 * M_PI * c.Rp / c.P);
+    }
+  }
+  if (px.empty()) return P;
+  P.dev.x = A.upload(px, s);
+  P.dev.y = A.upload(py, s);
+  P.dev.nx = A.upload(pnx, s);
+  P.dev.ny = A.upload(pny, s);
+  P.dev.w = A.upload(pw, s);
+  return P;
+}
+
+// Compress one level whose active sets (L.rows, L.cols, s0, s1) and blocks D are set.
+void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& cells, hipStream_t s) {
+  const int nc = L.ncell;
+  const double tol = F->opts.id_tol;
+  Arena tmp;
+  ProxyTable PT = make_proxies(tmp, cells, s);
+  // ---- ID matrices: 4 per cell, kinds 0/1 column IDs of type 0/1, 2/3 row IDs
+  std::vector<int> nearrows, nearcols;
+  std::vector<int64_t> nro(nc), mid(nc);
+  for (int t = 0; t < nc; ++t) {
+    nro[t] = (int64_t)nearrows.size();
+    for (int sgm : cells[t].near) {
+      nearrows.insert(nearrows.end(), L.rows.begin() + L.offS[sgm], L.rows.begin() + L.offS[sgm] + L.s0[sgm] + L.s1[sgm]);
+      nearcols.insert(nearcols.end(), L.cols.begin() + L.offS[sgm], L.cols.begin() + L.offS[sgm] + L.s0[sgm] + L.s1[sgm]);
+    }
+    for (int ty = 0; ty < 2; ++ty)
+      for (int k = 0; k < cells[t].P; ++k) {
+        nearrows.push_back(pmx_code_proxy(PT.off[t] + k, ty));
+        nearcols.push_back(pmx_code_proxy(PT.off[t] + k, ty));
+      }
+    mid[t] = (int64_t)nearrows.size() - nro[t];
+    if (mid[t] == 0) fail(PMX_EGEOM, "a cell has neither near cells nor a proxy circle");
+  }
+  int* d_nr = tmp.upload(nearrows, s);
+  int* d_ncol = tmp.upload(nearcols, s);
+  int* d_rows = tmp.upload(L.rows, s);
+  int* d_cols = tmp.upload(L.cols, s);
+  const int nid = 4 * nc;
+  std::vector<int64_t> offM(nid), offR(nid), offV(nid), offW(nid), offC(nid);
+  std::vector<int> idm(nid), idc(nid);
+  int64_t totM = 0, totR = 0, totV = 0, totW = 0, totC = 0;
+  int maxm = 0, maxc = 0;
+  for (int t = 0; t < nc; ++t)
+    for (int kd = 0; kd < 4; ++kd) {
+      int q = 4 * t + kd;
+      int c = (kd & 1) ? L.s1[t] : L.s0[t];
+      int m = (int)mid[t];
+      idm[q] = m;
+      idc[q] = c;
+      offM[q] = totM;
+      totM += (int64_t)m * c;
+      offR[q] = totR;
+      totR += (int64_t)std::min(m, c) * c;
+      offV[q] = totV;
+      totV += (int64_t)m * PMX_QR_NB;
+      offW[q] = totW;
+      totW += (int64_t)PMX_QR_NB * c;
+      offC[q] = totC;
+      totC += c;
+      maxm = std::max(maxm, m);
+      maxc = std::max(maxc, c);
+    }
+  zd* Mb = tmp.alloc<zd>(totM);
+  zd* Rb = tmp.alloc<zd>(totR);
+  zd* Vb = tmp.alloc<zd>(totV);
+  zd* VTb = tmp.alloc<zd>(totV);
+  zd* Wb = tmp.alloc<zd>(totW);
+  int* pivb = tmp.alloc<int>(totC);
+  double* nrmb = tmp.alloc<double>(2 * totC);
+  int* stb = tmp.alloc<int>(4 * nid);
+  double* r11b = tmp.alloc<double>(nid);
+  std::vector<EntryMat> em(nid);
+  std::vector<QrDesc> qd(nid);
+  std::vector<CpqrDesc> cd(nid);
+  for (int t = 0; t < nc; ++t)
+    for (int kd = 0; kd < 4; ++kd) {
+      int q = 4 * t + kd;
+      int ty = kd & 1;
+      const int* own = ((kd < 2) ? d_cols : d_rows) + L.offS[t] + (ty ? L.s0[t] : 0);
+      EntryMat& e = em[q];
+      e.a = ((kd < 2) ? d_nr : d_ncol) + nro[t];
+      e.na = idm[q];
+      e.b = own;
+      e.nb = idc[q];
+      e.out = Mb + offM[q];
+      e.ld = idm[q];
+      e.a_is_target = (kd < 2) ? 1 : 0;
+      QrDesc& Q = qd[q];
+      Q.a = Mb + offM[q];
+      Q.ld = idm[q];
+      Q.m = idm[q];
+      Q.c = idc[q];
+      Q.r = Rb + offR[q];
+      Q.v = Vb + offV[q];
+      Q.t = VTb + offV[q];
+      Q.w = Wb + offW[q];
+      CpqrDesc& C = cd[q];
+      C.b = Rb + offR[q];
+      C.mb = std::min(idm[q], idc[q]);
+      C.c = idc[q];
+      C.piv = pivb + offC[q];
+      C.nrm = nrmb + 2 * offC[q];
+      C.state = stb + 4 * q;
+      C.r11 = r11b + q;
+    }
+  EntryMat* d_em = tmp.upload(em, s);
+  QrDesc* d_qd = tmp.upload(qd, s);
+  CpqrDesc* d_cd = tmp.upload(cd, s);
+  asm_entries(F->geom(), PT.dev, F->ext(), d_em, nid, maxm, maxc, s);
+  la_geqrf_r(d_qd, nid, maxm, maxc, s);
+  la_cpqr(d_cd, nid, maxc, tol, nullptr, 1, s);
+  std::vector<int> st;
+  download(st, stb, 4 * nid, s);
+  // ---- common ranks per pair, continuation
+  std::vector<int> kq(nid);
+  L.k0.assign(nc, 0);
+  L.k1.assign(nc, 0);
+  for (int t = 0; t < nc; ++t)
+    for (int ty = 0; ty < 2; ++ty) {
+      int qc = 4 * t + ty, qr = 4 * t + 2 + ty;
+      int kb = std::max(st[4 * qc + 1], st[4 * qr + 1]);
+      int cap = std::min(idc[qc], std::min(idm[qc], idc[qc]));
+      kb = std::max(1, std::min(kb, cap));
+      kq[qc] = kq[qr] = kb;
+    }
+  int* d_kq = tmp.upload(kq, s);
+  la_cpqr(d_cd, nid, maxc, 0.0, d_kq, 0, s);
+  download(st, stb, 4 * nid, s);
+  for (int t = 0; t < nc; ++t)
+    for (int ty = 0; ty < 2; ++ty) {
+      int qc = 4 * t + ty, qr = 4 * t + 2 + ty;
+      int kb = std::min(kq[qc], std::min(st[4 * qc], st[4 * qr]));
+      if (kb < 1) fail(PMX_ESINGULAR, "an interpolative decomposition has rank 0");
+      kq[qc] = kq[qr] = kb;
+      (ty ? L.k1 : L.k0)[t] = kb;
+    }
+  HIPCHK(hipMemcpyAsync(d_kq, kq.data(), nid * sizeof(int), hipMemcpyHostToDevice, s));
+  la_cpqr_tsolve(d_cd, d_kq, nid, maxc, maxc, s);
+  std::vector<int> piv;
+  download(piv, pivb, totC, s);
+  // ---- level bookkeeping
+  L.offK.resize(nc + 1);
+  L.offY.resize(nc);
+  L.offA.resize(nc);
+  L.offT.resize(nc);
+  int64_t tk = 0, ty_ = 0, ta = 0, tt = 0;
+  L.max_k = 0;
+  for (int t = 0; t < nc; ++t) {
+    int K = L.k0[t] + L.k1[t];
+    int sz = L.s0[t] + L.s1[t];
+    L.offK[t] = tk;
+    tk += K;
+    L.offY[t] = ty_;
+    ty_ += (int64_t)sz * K;
+    L.offA[t] = ta;
+    ta += (int64_t)K * K;
+    L.offT[t] = tt;
+    tt += (int64_t)L.k0[t] * (L.s0[t] - L.k0[t]) + (int64_t)L.k1[t] * (L.s1[t] - L.k1[t]);
+    L.max_k = std::max(L.max_k, K);
+  }
+  L.offK[nc] = tk;
+  L.tot_k = tk;
+  L.cpiv.resize(L.tot_s);
+  L.rskel.resize(tk);
+  L.cskel.resize(tk);
+  for (int t = 0; t < nc; ++t) {
+    int64_t o = L.offK[t];
+    for (int ty = 0; ty < 2; ++ty) {
+      const int* pc = piv.data() + offC[4 * t + ty];
+      const int* pr = piv.data() + offC[4 * t + 2 + ty];
+      int kb = ty ? L.k1[t] : L.k0[t];
+      int base = ty ? L.s0[t] : 0;
+      int sb = ty ? L.s1[t] : L.s0[t];
+      for (int j = 0; j < sb; ++j) L.cpiv[L.offS[t] + base + j] = pc[j];
+      for (int i = 0; i < kb; ++i) {
+        L.rskel[o + i] = L.rows[L.offS[t] + base + pr[i]];
+        L.cskel[o + i] = L.cols[L.offS[t] + base + pc[i]];
+      }
+      o += kb;
+    }
+  }
+  Arena& A = F->arena;
+  L.Y = A.alloc<zd>(ty_);
+  L.At = A.alloc<zd>(ta);
+  L.Tc = A.alloc<zd>(tt);
+  // ---- compact copies of the column-ID T blocks
+  {
+    std::vector<RowSrc> rs;
+    std::vector<GatherDesc> gd;
+    std::vector<int64_t> rso;
+    int maxr = 0, maxcc = 0;
+    for (int t = 0; t < nc; ++t)
+      for (int ty = 0; ty < 2; ++ty) {
+        int q = 4 * t + ty;
+        int kb = kq[q];
+        int mb = std::min(idm[q], idc[q]);
+        int ncol = idc[q] - kb;
+        rso.push_back((int64_t)rs.size());
+        for (int i = 0; i < kb; ++i) rs.push_back(RowSrc{offR[q] + i + (int64_t)kb * mb, mb});
+        GatherDesc g;
+        g.nrows = ncol > 0 ? kb : 0;
+        g.ncols = ncol;
+        g.dst = L.Tc + L.offT[t] + (ty ? (int64_t)L.k0[t] * (L.s0[t] - L.k0[t]) : 0);
+        g.ld = kb;
+        gd.push_back(g);
+        maxr = std::max(maxr, kb);
+        maxcc = std::max(maxcc, ncol);
+      }
+    RowSrc* d_rs = tmp.upload(rs, s);
+    for (size_t i = 0; i < gd.size(); ++i) gd[i].src = d_rs + rso[i];
+    GatherDesc* d_gd = tmp.upload(gd, s);
+    asm_gather(Rb, d_gd, (int)gd.size(), maxr, maxcc, s);
+  }
+  // ---- L, LU(D), Y = D^-1 L
+  asm_zero(L.Y, ty_, s);
+  {
+    std::vector<LDesc> ld(nc);
+    for (int t = 0; t < nc; ++t) {
+      LDesc& d = ld[t];
+      d.out = L.Y + L.offY[t];
+      d.s0 = L.s0[t];
+      d.s1 = L.s1[t];
+      d.k0 = L.k0[t];
+      d.k1 = L.k1[t];
+      int q0 = 4 * t + 2, q1 = 4 * t + 3;
+      d.piv0 = pivb + offC[q0];
+      d.piv1 = pivb + offC[q1];
+      int mb0 = std::min(idm[q0], idc[q0]), mb1 = std::min(idm[q1], idc[q1]);
+      d.t0 = Rb + offR[q0] + (int64_t)L.k0[t] * mb0;
+      d.t1 = Rb + offR[q1] + (int64_t)L.k1[t] * mb1;
+      d.ldt0 = mb0;
+      d.ldt1 = mb1;
+    }
+    LDesc* d_ld = tmp.upload(ld, s);
+    asm_build_l(d_ld, nc, L.max_s, L.max_k, s);
+  }
+  std::vector<LuDesc> lu(nc);
+  for (int t = 0; t < nc; ++t) {
+    int sz = L.s0[t] + L.s1[t];
+    lu[t] = LuDesc{L.D + L.offD[t], sz, sz, L.ipiv + L.offS[t]};
+  }
+  L.d_lu = A.upload(lu, s);
+  int* d_info = tmp.alloc<int>(nc);
+  HIPCHK(hipMemsetAsync(d_info, 0, nc * sizeof(int), s));
+  la_getrf(L.d_lu, nc, L.max_s, d_info, s);
+  std::vector<Mat> ym(nc);
+  for (int t = 0; t < nc; ++t) {
+    int sz = L.s0[t] + L.s1[t];
+    ym[t] = Mat{L.Y + L.offY[t], sz, sz, L.k0[t] + L.k1[t]};
+  }
+  Mat* d_ym = tmp.upload(ym, s);
+  la_getrs(L.d_lu, d_ym, nc, L.max_s, L.max_k, s);
+  // ---- M = R Y: skeleton rows of Y plus T times its redundant rows
+  zd* Mm = tmp.alloc<zd>(ta);
+  int64_t totred = 0;
+  for (int t = 0; t < nc; ++t) totred += (int64_t)(L.s0[t] + L.s1[t] - L.k0[t] - L.k1[t]) * (L.k0[t] + L.k1[t]);
+  zd* Red = tmp.alloc<zd>(std::max<int64_t>(totred, 1));
+  {
+    std::vector<RowSrc> rs;
+    std::vector<int64_t> rso;
+    std::vector<GatherDesc> gd;
+    std::vector<GemmArgs> ga;
+    int maxr = 0;
+    int64_t ro = 0;
+    for (int t = 0; t < nc; ++t) {
+      int K = L.k0[t] + L.k1[t];
+      int sz = L.s0[t] + L.s1[t];
+      // skeleton rows
+      rso.push_back((int64_t)rs.size());
+      for (int ty = 0; ty < 2; ++ty) {
+        int kb = ty ? L.k1[t] : L.k0[t];
+        int base = ty ? L.s0[t] : 0;
+        for (int i = 0; i < kb; ++i) rs.push_back(RowSrc{L.offY[t] + base + L.cpiv[L.offS[t] + base + i], sz});
+      }
+      GatherDesc g;
+      g.nrows = K;
+      g.ncols = K;
+      g.dst = Mm + L.offA[t];
+      g.ld = K;
+      gd.push_back(g);
+      maxr = std::max(maxr, K);
+      for (int ty = 0; ty < 2; ++ty) {
+        int kb = ty ? L.k1[t] : L.k0[t];
+        int base = ty ? L.s0[t] : 0;
+        int sb = ty ? L.s1[t] : L.s0[t];
+        int nr = sb - kb;
+        rso.push_back((int64_t)rs.size());
+        for (int j = 0; j < nr; ++j) rs.push_back(RowSrc{L.offY[t] + base + L.cpiv[L.offS[t] + base + kb + j], sz});
+        GatherDesc h;
+        h.nrows = nr;
+        h.ncols = K;
+        h.dst = Red + ro;
+        h.ld = std::max(nr, 1);
+        gd.push_back(h);
+        maxr = std::max(maxr, nr);
+        if (nr > 0) {
+          GemmArgs a;
+          a.m = kb;
+          a.n = K;
+          a.k = nr;
+          a.A = L.Tc + L.offT[t] + (ty ? (int64_t)L.k0[t] * (L.s0[t] - L.k0[t]) : 0);
+          a.lda = kb;
+          a.B = Red + ro;
+          a.ldb = nr;
+          a.C = Mm + L.offA[t] + (ty ? L.k0[t] : 0);
+          a.ldc = K;
+          ga.push_back(a);
+        }
+        ro += (int64_t)nr * K;
+      }
+    }
+    RowSrc* d_rs = tmp.upload(rs, s);
+    for (size_t i = 0; i < gd.size(); ++i) gd[i].src = d_rs + rso[i];
+    GatherDesc* d_gd = tmp.upload(gd, s);
+    asm_gather(L.Y, d_gd, (int)gd.size(), maxr, L.max_k, s);
+    if (!ga.empty()) {
+      GemmArgs* d_ga = tmp.upload(ga, s);
+      la_zgemm_list(OP_N, OP_N, d_ga, (int)ga.size(), L.max_k, L.max_k, zmk(1, 0), zmk(1, 0), s);
+    }
+  }
+  // ---- At = M^-1
+  {
+    std::vector<LuDesc> lm(nc);
+    std::vector<Mat2> id(nc);
+    std::vector<Mat> am(nc);
+    int* ipm = tmp.alloc<int>(std::max<int64_t>(tk, 1));
+    for (int t = 0; t < nc; ++t) {
+      int K = L.k0[t] + L.k1[t];
+      lm[t] = LuDesc{Mm + L.offA[t], K, K, ipm + L.offK[t]};
+      id[t] = Mat2{L.At + L.offA[t], K, K};
+      am[t] = Mat{L.At + L.offA[t], K, K, K};
+    }
+    LuDesc* d_lm = tmp.upload(lm, s);
+    Mat2* d_id = tmp.upload(id, s);
+    Mat* d_am = tmp.upload(am, s);
+    int* d_info2 = tmp.alloc<int>(nc);
+    HIPCHK(hipMemsetAsync(d_info2, 0, nc * sizeof(int), s));
+    la_getrf(d_lm, nc, L.max_k, d_info2, s);
+    asm_identity(d_id, nc, L.max_k, s);
+    la_getrs(d_lm, d_am, nc, L.max_k, L.max_k, s);
+    std::vector<int> info;
+    download(info, d_info, nc, s);
+    for (int t = 0; t < nc; ++t)
+      if (info[t]) fail(PMX_ESINGULAR, "zero pivot in the LU of a cell block");
+    download(info, d_info2, nc, s);
+    for (int t = 0; t < nc; ++t)
+      if (info[t]) fail(PMX_ESINGULAR, "zero pivot in the LU of R D^-1 L");
+  }
+  sync_check(s);
+}
+
+// Active sets and block of every parent at level `lv` from the compressed children.
+void merge_level(pmx_factor* F, const LevelData& C, const std::vector<CellPlan>& cells, LevelData& P,
+                 Arena& tmp, hipStream_t s) {
+  const int np = (int)cells.size();
+  P.ncell = np;
+  P.s0.assign(np, 0);
+  P.s1.assign(np, 0);
+  P.offS.resize(np + 1);
+  P.offD.resize(np);
+  P.rows.clear();
+  P.cols.clear();
+  std::vector<int> rloc, cloc;
+  int64_t td = 0;
+  P.max_s = 0;
+  for (int p = 0; p < np; ++p) {
+    P.offS[p] = (int64_t)P.rows.size();
+    for (int ty = 0; ty < 2; ++ty)
+      for (int sl = 0; sl < (int)cells[p].children.size(); ++sl) {
+        int c = cells[p].children[sl];
+        int kb = ty ? C.k1[c] : C.k0[c];
+        int64_t o = C.offK[c] + (ty ? C.k0[c] : 0);
+        for (int i = 0; i < kb; ++i) {
+          P.rows.push_back(C.rskel[o + i]);
+          P.cols.push_back(C.cskel[o + i]);
+          int loc = (ty ? C.k0[c] : 0) + i;
+          rloc.push_back((sl << 24) | loc);
+          cloc.push_back((sl << 24) | loc);
+        }
+        (ty ? P.s1 : P.s0)[p] += kb;
+      }
+    int sz = P.s0[p] + P.s1[p];
+    P.offD[p] = td;
+    td += (int64_t)sz * sz;
+    P.max_s = std::max(P.max_s, sz);
+  }
+  P.offS[np] = (int64_t)P.rows.size();
+  P.tot_s = P.offS[np];
+  P.D = F->arena.alloc<zd>(td);
+  P.ipiv = F->arena.alloc<int>(std::max<int64_t>(P.tot_s, 1));
+  int* d_r = tmp.upload(P.rows, s);
+  int* d_c = tmp.upload(P.cols, s);
+  int* d_rl = tmp.upload(rloc, s);
+  int* d_cl = tmp.upload(cloc, s);
+  std::vector<ParentDesc> pd(np);
+  for (int p = 0; p < np; ++p) {
+    ParentDesc& d = pd[p];
+    d.rcode = d_r + P.offS[p];
+    d.ccode = d_c + P.offS[p];
+    d.rloc = d_rl + P.offS[p];
+    d.cloc = d_cl + P.offS[p];
+    d.s = P.s0[p] + P.s1[p];
+    d.out = P.D + P.offD[p];
+    for (int sl = 0; sl < 4; ++sl) {
+      d.at[sl] = nullptr;
+      d.kc[sl] = 0;
+    }
+    for (int sl = 0; sl < (int)cells[p].children.size(); ++sl) {
+      int c = cells[p].children[sl];
+      d.at[sl] = C.At + C.offA[c];
+      d.kc[sl] = C.k0[c] + C.k1[c];
+    }
+  }
+  ParentDesc* d_pd = tmp.upload(pd, s);
+  asm_parent(F->geom(), F->ext(), d_pd, np, P.max_s, s);
+}
+
+void factor_all(pmx_factor* F, hipStream_t s) {
+  const double t0 = now_ms();
+  const auto& plan = F->plan;
+  // leaf level
+  LevelData L0;
+  const std::vector<CellPlan>& leaves = plan[0];
+  const int nc0 = (int)leaves.size();
+  L0.ncell = nc0;
+  L0.s0.resize(nc0);
+  L0.s1.resize(nc0);
+  L0.offS.resize(nc0 + 1);
+  L0.offD.resize(nc0);
+  int64_t td = 0;
+  std::vector<int> incl(nc0);
+  L0.max_s = 0;
+  for (int t = 0; t < nc0; ++t) {
+    int j = leaves[t].incl[0];
+    incl[t] = j;
+    int n = (int)(F->node_off[j + 1] - F->node_off[j]);
+    int node0 = (int)F->node_off[j];
+    L0.s0[t] = L0.s1[t] = n;
+    L0.offS[t] = (int64_t)L0.rows.size();
+    for (int ty = 0; ty < 2; ++ty)
+      for (int a = 0; a < n; ++a) {
+        L0.rows.push_back(pmx_code_node(node0 + a, ty));
+        L0.cols.push_back(pmx_code_node(node0 + a, ty));
+      }
+    L0.offD[t] = td;
+    td += (int64_t)4 * n * n;
+    L0.max_s = std::max(L0.max_s, 2 * n);
+  }
+  L0.offS[nc0] = (int64_t)L0.rows.size();
+  L0.tot_s = L0.offS[nc0];
+  L0.D = F->arena.alloc<zd>(td);
+  L0.ipiv = F->arena.alloc<int>(L0.tot_s);
+  {
+    Arena tmp;
+    assemble_diag(F, tmp, incl, L0.D, L0.offD, s);
+    sync_check(s);
+  }
+  F->info.t_phase_ms[0] += now_ms() - t0;
+  LevelData cur = std::move(L0);
+  for (size_t lv = 0; lv < plan.size(); ++lv) {
+    if (lv > 0) {
+      Arena tmp;
+      LevelData nxt;
+      merge_level(F, F->lev.back(), plan[lv], nxt, tmp, s);
+      sync_check(s);
+      cur = std::move(nxt);
+    }
+    if (plan[lv].size() == 1) {
+      // root: dense partial-pivoted LU of the top compressed system
+      const double tr = now_ms();
+      F->root_s = cur.s0[0] + cur.s1[0];
+      F->Droot = cur.D;
+      F->ipiv_root = cur.ipiv;
+      F->root_rows = cur.rows;
+      F->root_cols = cur.cols;
+      std::vector<LuDesc> lu{LuDesc{F->Droot, F->root_s, F->root_s, F->ipiv_root}};
+      F->d_lu_root = F->arena.upload(lu, s);
+      Arena tmp;
+      int* d_info = tmp.alloc<int>(1);
+      HIPCHK(hipMemsetAsync(d_info, 0, sizeof(int), s));
+      la_getrf(F->d_lu_root, 1, F->root_s, d_info, s);
+      std::vector<int> info;
+      download(info, d_info, 1, s);
+      if (info[0]) fail(PMX_ESINGULAR, "zero pivot in the LU of the top compressed system");
+      F->info.t_phase_ms[3] += now_ms() - tr;
+      break;
+    }
+    const double tc = now_ms();
+    compress_level(F, cur, plan[lv], s);
+    F->info.t_phase_ms[1] += now_ms() - tc;
+    F->lev.push_back(std::move(cur));
+    cur = LevelData();
+  }
+}
+
+void fill_info(pmx_factor* F) {
+  pmx_info& I = F->info;
+  I.levels = (int)F->lev.size();
+  I.root_size = F->root_s;
+  I.n_unknowns = 2 * F->n_nodes;
+  for (size_t l = 0; l < F->lev.size() && l < 32; ++l) {
+    const LevelData& L = F->lev[l];
+    I.cells[l] = L.ncell;
+    int mn = 1 << 30, mx = 0;
+    double sum = 0;
+    for (int t = 0; t < L.ncell; ++t) {
+      int K = L.k0[t] + L.k1[t];
+      mn = std::min(mn, K);
+      mx = std::max(mx, K);
+      sum += K;
+    }
+    I.rank_min[l] = mn;
+    I.rank_max[l] = mx;
+    I.rank_mean[l] = sum / std::max(1, L.ncell);
+  }
+  I.bytes_factor = F->arena.bytes();
+}
+
+// ---------------------------------------------------------------------------------
+// solve
+void ensure_solve_buffers(pmx_factor* F, int nrhs) {
+  SolveCache& S = F->sc;
+  if (S.nrhs == nrhs) return;
+  S.arena.release();
+  S.F.clear();
+  S.G.clear();
+  S.Red.clear();
+  for (const LevelData& L : F->lev) {
+    S.F.push_back(S.arena.alloc<zd>(L.tot_s * nrhs));
+    S.G.push_back(S.arena.alloc<zd>(std::max<int64_t>(L.tot_k, 1) * nrhs));
+    S.Red.push_back(S.arena.alloc<zd>(std::max<int64_t>(L.tot_s - L.tot_k, 1) * nrhs));
+  }
+  S.Froot = S.arena.alloc<zd>((int64_t)F->root_s * nrhs);
+  S.nrhs = nrhs;
+}
+
+// vectors of a level are stored per cell, column major with leading dimension = rows
+void solve_core(pmx_factor* F, int nrhs, zd* fleaf_or_root, hipStream_t s) {
+  SolveCache& S = F->sc;
+  Arena tmp;
+  const int nl = (int)F->lev.size();
+  const zd one = zmk(1, 0), mone = zmk(-1, 0);
+  for (int l = 0; l < nl; ++l) {
+    LevelData& L = F->lev[l];
+    const int nc = L.ncell;
+    zd* Fv = S.F[l];
+    // y = D^-1 f
+    std::vector<Mat> bm(nc);
+    for (int t = 0; t < nc; ++t) {
+      int sz = L.s0[t] + L.s1[t];
+      bm[t] = Mat{Fv + L.offS[t] * nrhs, sz, sz, nrhs};
+    }
+    Mat* d_bm = tmp.upload(bm, s);
+    la_getrs(L.d_lu, d_bm, nc, L.max_s, nrhs, s);
+    // R y -> G (skeleton rows, then + T * redundant rows)
+    std::vector<RowSrc> rs;
+    std::vector<int64_t> rso;
+    std::vector<GatherDesc> gd;
+    std::vector<GemmArgs> ga, gb;
+    int maxr = 0;
+    int64_t ro = 0;
+    for (int t = 0; t < nc; ++t) {
+      int K = L.k0[t] + L.k1[t];
+      int sz = L.s0[t] + L.s1[t];
+      int64_t yo = L.offS[t] * nrhs;
+      rso.push_back((int64_t)rs.size());
+      for (int ty = 0; ty < 2; ++ty) {
+        int kb = ty ? L.k1[t] : L.k0[t];
+        int base = ty ? L.s0[t] : 0;
+        for (int i = 0; i < kb; ++i) rs.push_back(RowSrc{yo + base + L.cpiv[L.offS[t] + base + i], sz});
+      }
+      gd.push_back(GatherDesc{nullptr, K, nrhs, S.G[l] + L.offK[t] * nrhs, K});
+      maxr = std::max(maxr, K);
+      for (int ty = 0; ty < 2; ++ty) {
+        int kb = ty ? L.k1[t] : L.k0[t];
+        int base = ty ? L.s0[t] : 0;
+        int sb = ty ? L.s1[t] : L.s0[t];
+        int nr = sb - kb;
+        rso.push_back((int64_t)rs.size());
+        for (int j = 0; j < nr; ++j) rs.push_back(RowSrc{yo + base + L.cpiv[L.offS[t] + base + kb + j], sz});
+        gd.push_back(GatherDesc{nullptr, nr, nrhs, S.Red[l] + ro, std::max(nr, 1)});
+        maxr = std::max(maxr, nr);
+        if (nr > 0) {
+          GemmArgs a;
+          a.m = kb;
+          a.n = nrhs;
+          a.k = nr;
+          a.A = L.Tc + L.offT[t] + (ty ? (int64_t)L.k0[t] * (L.s0[t] - L.k0[t]) : 0);
+          a.lda = kb;
+          a.B = S.Red[l] + ro;
+          a.ldb = nr;
+          a.C = S.G[l] + L.offK[t] * nrhs + (ty ? L.k0[t] : 0);
+          a.ldc = K;
+          ga.push_back(a);
+        }
+        ro += (int64_t)nr * nrhs;
+      }
+    }
+    RowSrc* d_rs = tmp.upload(rs, s);
+    for (size_t i = 0; i < gd.size(); ++i) gd[i].src = d_rs + rso[i];
+    GatherDesc* d_gd = tmp.upload(gd, s);
+    asm_gather(Fv, d_gd, (int)gd.size(), maxr, nrhs, s);
+    if (!ga.empty()) {
+      GemmArgs* d_ga = tmp.upload(ga, s);
+      la_zgemm_list(OP_N, OP_N, d_ga, (int)ga.size(), L.max_k, nrhs, one, one, s);
+    }
+    // g = At (R y): into Red-free temporary then back to G
+    zd* Ry = tmp.alloc<zd>(std::max<int64_t>(L.tot_k, 1) * nrhs);
+    HIPCHK(hipMemcpyAsync(Ry, S.G[l], L.tot_k * nrhs * sizeof(zd), hipMemcpyDeviceToDevice, s));
+    for (int t = 0; t < nc; ++t) {
+      int K = L.k0[t] + L.k1[t];
+      GemmArgs a;
+      a.m = K;
+      a.n = nrhs;
+      a.k = K;
+      a.A = L.At + L.offA[t];
+      a.lda = K;
+      a.B = Ry + L.offK[t] * nrhs;
+      a.ldb = K;
+      a.C = S.G[l] + L.offK[t] * nrhs;
+      a.ldc = K;
+      gb.push_back(a);
+    }
+    GemmArgs* d_gb = tmp.upload(gb, s);
+    la_zgemm_list(OP_N, OP_N, d_gb, nc, L.max_k, nrhs, one, zmk(0, 0), s);
+    // parent right-hand sides
+    const bool top = (l + 1 == nl);
+    const std::vector<CellPlan>& pc = F->plan[l + 1];
+    zd* dst = top ? S.Froot : S.F[l + 1];
+    std::vector<RowSrc> prs;
+    std::vector<GatherDesc> pgd;
+    std::vector<int64_t> pro;
+    int maxp = 0;
+    int64_t po = 0;
+    for (size_t p = 0; p < pc.size(); ++p) {
+      pro.push_back((int64_t)prs.size());
+      int cnt = 0;
+      for (int ty = 0; ty < 2; ++ty)
+        for (int c : pc[p].children) {
+          int K = L.k0[c] + L.k1[c];
+          int kb = ty ? L.k1[c] : L.k0[c];
+          int base = ty ? L.k0[c] : 0;
+          for (int i = 0; i < kb; ++i) prs.push_back(RowSrc{L.offK[c] * nrhs + base + i, K});
+          cnt += kb;
+        }
+      pgd.push_back(GatherDesc{nullptr, cnt, nrhs, dst + po * nrhs, cnt});
+      po += cnt;
+      maxp = std::max(maxp, cnt);
+    }
+    RowSrc* d_prs = tmp.upload(prs, s);
+    for (size_t i = 0; i < pgd.size(); ++i) pgd[i].src = d_prs + pro[i];
+    GatherDesc* d_pgd = tmp.upload(pgd, s);
+    asm_gather(S.G[l], d_pgd, (int)pgd.size(), maxp, nrhs, s);
+  }
+  // root solve
+  {
+    zd* root = (nl == 0) ? fleaf_or_root : S.Froot;
+    std::vector<Mat> bm{Mat{root, F->root_s, F->root_s, nrhs}};
+    Mat* d_bm = tmp.upload(bm, s);
+    la_getrs(F->d_lu_root, d_bm, 1, F->root_s, nrhs, s);
+  }
+  // downward pass
+  for (int l = nl - 1; l >= 0; --l) {
+    LevelData& L = F->lev[l];
+    const int nc = L.ncell;
+    const bool top = (l + 1 == nl);
+    const zd* xp = top ? S.Froot : S.F[l + 1];
+    const LevelData* Pl = top ? nullptr : &F->lev[l + 1];
+    const std::vector<CellPlan>& pc = F->plan[l + 1];
+    // psi of each child from its parent's solution -> Red scratch (K x nrhs per cell)
+    std::vector<int64_t> psio(nc);
+    int64_t o = 0;
+    for (int t = 0; t < nc; ++t) {
+      psio[t] = o;
+      o += (int64_t)(L.k0[t] + L.k1[t]) * nrhs;
+    }
+    zd* Psi = tmp.alloc<zd>(std::max<int64_t>(o, 1));
+    std::vector<RowSrc> rs(L.tot_k);
+    std::vector<GatherDesc> gd(nc);
+    for (size_t p = 0; p < pc.size(); ++p) {
+      int64_t pbase = top ? 0 : Pl->offS[p];
+      int psz = top ? F->root_s : Pl->s0[p] + Pl->s1[p];
+      int pos = 0;
+      for (int ty = 0; ty < 2; ++ty)
+        for (int c : pc[p].children) {
+          int kb = ty ? L.k1[c] : L.k0[c];
+          int base = ty ? L.k0[c] : 0;
+          for (int i = 0; i < kb; ++i) rs[L.offK[c] + base + i] = RowSrc{pbase * nrhs + pos + i, psz};
+          pos += kb;
+        }
+    }
+    RowSrc* d_rs = tmp.upload(rs, s);
+    for (int t = 0; t < nc; ++t) {
+      int K = L.k0[t] + L.k1[t];
+      gd[t] = GatherDesc{d_rs + L.offK[t], K, nrhs, Psi + psio[t], K};
+    }
+    GatherDesc* d_gd = tmp.upload(gd, s);
+    asm_gather(xp, d_gd, nc, L.max_k, nrhs, s);
+    // g <- g - At psi ; x = y - Y g
+    std::vector<GemmArgs> g1(nc), g2(nc);
+    for (int t = 0; t < nc; ++t) {
+      int K = L.k0[t] + L.k1[t];
+      int sz = L.s0[t] + L.s1[t];
+      g1[t] = GemmArgs{K, nrhs, K, L.At + L.offA[t], K, Psi + psio[t], K, S.G[l] + L.offK[t] * nrhs, K};
+      g2[t] = GemmArgs{sz, nrhs, K, L.Y + L.offY[t], sz, S.G[l] + L.offK[t] * nrhs, K, S.F[l] + L.offS[t] * nrhs, sz};
+    }
+    GemmArgs* d_g1 = tmp.upload(g1, s);
+    GemmArgs* d_g2 = tmp.upload(g2, s);
+    la_zgemm_list(OP_N, OP_N, d_g1, nc, L.max_k, nrhs, mone, one, s);
+    la_zgemm_list(OP_N, OP_N, d_g2, nc, L.max_s, nrhs, mone, one, s);
+  }
+  sync_check(s);
+}
+
+// leaf cell vectors <-> dens layout [nrhs][2 N] (per inclusion [q; u])
+void leaf_to_dens(pmx_factor* F, const zd* leaf, int nrhs, zd* dens, Arena& tmp, hipStream_t s) {
+  const std::vector<CellPlan>& leaves = F->plan[0];
+  const int N2 = 2 * F->n_nodes;
+  std::vector<RowSrc> rs(N2);
+  int64_t off = 0;
+  for (size_t t = 0; t < leaves.size(); ++t) {
+    int j = leaves[t].incl[0];
+    int n = (int)(F->node_off[j + 1] - F->node_off[j]);
+    for (int r = 0; r < 2 * n; ++r) rs[2 * F->node_off[j] + r] = RowSrc{off * nrhs + r, 2 * n};
+    off += 2 * n;
+  }
+  RowSrc* d_rs = tmp.upload(rs, s);
+  std::vector<GatherDesc> gd{GatherDesc{d_rs, N2, nrhs, dens, N2}};
+  GatherDesc* d_gd = tmp.upload(gd, s);
+  asm_gather(leaf, d_gd, 1, N2, nrhs, s);
+}
+
+void dens_to_leaf(pmx_factor* F, const zd* dens, int nrhs, zd* leaf, Arena& tmp, hipStream_t s) {
+  const std::vector<CellPlan>& leaves = F->plan[0];
+  const int N2 = 2 * F->n_nodes;
+  std::vector<RowSrc> rs(N2);
+  int64_t off = 0;
+  std::vector<GatherDesc> gd;
+  int maxr = 0;
+  for (size_t t = 0; t < leaves.size(); ++t) {
+    int j = leaves[t].incl[0];
+    int n = (int)(F->node_off[j + 1] - F->node_off[j]);
+    for (int r = 0; r < 2 * n; ++r) rs[off + r] = RowSrc{2 * F->node_off[j] + r, N2};
+    gd.push_back(GatherDesc{nullptr, 2 * n, nrhs, leaf + off * nrhs, 2 * n});
+    off += 2 * n;
+    maxr = std::max(maxr, 2 * n);
+  }
+  RowSrc* d_rs = tmp.upload(rs, s);
+  off = 0;
+  for (size_t t = 0; t < gd.size(); ++t) {
+    gd[t].src = d_rs + off;
+    off += gd[t].nrows;
+  }
+  GatherDesc* d_gd = tmp.upload(gd, s);
+  asm_gather(dens, d_gd, (int)gd.size(), maxr, nrhs, s);
+}
+
+zd* leaf_vectors(pmx_factor* F) {
+  return F->lev.empty() ? F->sc.Froot : F->sc.F[0];
+}
+
+void solve_plane(pmx_factor* F, int nrhs, const double* angles, zd* dens, hipStream_t s) {
+  ensure_solve_buffers(F, nrhs);
+  Arena tmp;
+  const std::vector<CellPlan>& leaves = F->plan[0];
+  const int nc = (int)leaves.size();
+  std::vector<int> node0(nc), nn(nc);
+  std::vector<int64_t> off(nc);
+  int64_t o = 0;
+  int maxn = 0;
+  for (int t = 0; t < nc; ++t) {
+    int j = leaves[t].incl[0];
+    node0[t] = (int)F->node_off[j];
+    nn[t] = (int)(F->node_off[j + 1] - F->node_off[j]);
+    off[t] = o * nrhs;
+    o += 2 * nn[t];
+    maxn = std::max(maxn, nn[t]);
+  }
+  std::vector<double> ang(angles, angles + nrhs);
+  zd* leaf = leaf_vectors(F);
+  asm_incident(F->geom(), F->ext(), tmp.upload(node0, s), tmp.upload(nn, s), tmp.upload(off, s), nc, maxn,
+               tmp.upload(ang, s), nrhs, leaf, s);
+  solve_core(F, nrhs, leaf, s);
+  leaf_to_dens(F, leaf, nrhs, dens, tmp, s);
+  sync_check(s);
+}
+
+void solve_general(pmx_factor* F, int nrhs, const zd* rhs, zd* dens, hipStream_t s) {
+  ensure_solve_buffers(F, nrhs);
+  Arena tmp;
+  zd* leaf = leaf_vectors(F);
+  dens_to_leaf(F, rhs, nrhs, leaf, tmp, s);
+  solve_core(F, nrhs, leaf, s);
+  leaf_to_dens(F, leaf, nrhs, dens, tmp, s);
+  sync_check(s);
+}
+
+template <class Fn>
+pmx_status guarded(Fn&& fn) {
+  try {
+    fn();
+    return PMX_OK;
+  } catch (const PmxErr& e) {
+    g_last_error = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return PMX_ENOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return PMX_EINVAL;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------
+extern "C" {
+
+void pmx_options_default(pmx_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->id_tol = 1e-10;
+  o->proxy_ratio = 1.5;
+  o->proxy_min = 0;
+  o->proxy_rule = 0;
+  o->near_rule = 0;
+  o->precision = 0;
+  o->timing = 0;
+}
+
+pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, void* hip_stream,
+                             pmx_factor** out) {
+  return guarded([&] {
+    if (!out) fail(PMX_EINVAL, "out is NULL");
+    *out = nullptr;
+    pmx_options o;
+    pmx_options_default(&o);
+    if (opts) o = *opts;
+    validate(geom, &o);
+    hipStream_t s = (hipStream_t)hip_stream;
+    std::unique_ptr<pmx_factor> F(new pmx_factor());
+    std::memset(&F->info, 0, sizeof(F->info));
+    F->opts = o;
+    const double t0 = now_ms();
+    make_plan(geom, o, F->plan);
+    upload_geometry(F.get(), geom, s);
+    factor_all(F.get(), s);
+    fill_info(F.get());
+    F->info.t_factor_ms = now_ms() - t0;
+    *out = F.release();
+  });
+}
+
+pmx_status pmx_solve_plane_waves(pmx_factor* f, int32_t nrhs, const double* angles, pmx_c64* dens,
+                                 void* hip_stream) {
+  return guarded([&] {
+    if (!f || !angles || !dens || nrhs <= 0) fail(PMX_EINVAL, "bad arguments to pmx_solve_plane_waves");
+    for (int r = 0; r < nrhs; ++r)
+      if (!std::isfinite(angles[r])) fail(PMX_EINVAL, "non-finite angle");
+    solve_plane(f, nrhs, angles, (zd*)dens, (hipStream_t)hip_stream);
+  });
+}
+
+pmx_status pmx_solve(pmx_factor* f, int32_t nrhs, const pmx_c64* rhs, pmx_c64* dens, void* hip_stream) {
+  return guarded([&] {
+    if (!f || !rhs || !dens || nrhs <= 0) fail(PMX_EINVAL, "bad arguments to pmx_solve");
+    if ((const void*)rhs == (const void*)dens) fail(PMX_EINVAL, "rhs and dens overlap");
+    solve_general(f, nrhs, (const zd*)rhs, (zd*)dens, (hipStream_t)hip_stream);
+  });
+}
+
+pmx_status pmx_far_field(const pmx_factor* f, int32_t nrhs, const pmx_c64* dens, int32_t ndir,
+                         const double* dirs, pmx_c64* out, void* hip_stream) {
+  return guarded([&] {
+    if (!f || !dens || !dirs || !out || nrhs <= 0 || ndir <= 0) fail(PMX_EINVAL, "bad arguments to pmx_far_field");
+    hipStream_t s = (hipStream_t)hip_stream;
+    Arena tmp;
+    std::vector<double> d(dirs, dirs + ndir);
+    asm_far_field(f->geom(), f->ext(), f->owner, f->d_node_off, (const zd*)dens, nrhs, tmp.upload(d, s), ndir,
+                  (zd*)out, s);
+    sync_check(s);
+  });
+}
+
+pmx_status pmx_factor_info(const pmx_factor* f, pmx_info* info) {
+  return guarded([&] {
+    if (!f || !info) fail(PMX_EINVAL, "NULL argument");
+    *info = f->info;
+  });
+}
+
+void pmx_factor_destroy(pmx_factor* f) { delete f; }
+
+const char* pmx_status_string(pmx_status s) {
+  switch (s) {
+    case PMX_OK: return "ok";
+    case PMX_EINVAL: return "invalid argument";
+    case PMX_EGEOM: return "unsupported geometry";
+    case PMX_ENOMEM: return "out of device memory";
+    case PMX_EHIP: return "HIP runtime error";
+    case PMX_ESINGULAR: return "singular block";
+    case PMX_ENOTCONV: return "iterative refinement did not converge";
+  }
+  return "unknown status";
+}
+
+const char* pmx_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------------
+// probes
+pmx_status pmx_probe_bessel(const double* z, int64_t n, double* out, void* stream) {
+  return guarded([&] {
+    if (!z || !out || n <= 0) fail(PMX_EINVAL, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    asm_probe_bessel(z, n, out, s);
+    sync_check(s);
+  });
+}
+
+pmx_status pmx_probe_diag_block(const pmx_geometry* geom, int32_t j, pmx_c64* out, void* stream) {
+  return guarded([&] {
+    validate(geom, nullptr);
+    if (j < 0 || j >= geom->m || !out) fail(PMX_EINVAL, "bad inclusion index");
+    hipStream_t s = (hipStream_t)stream;
+    pmx_factor F;
+    upload_geometry(&F, geom, s);
+    Arena tmp;
+    std::vector<int> incl{j};
+    std::vector<int64_t> off{0};
+    assemble_diag(&F, tmp, incl, (zd*)out, off, s);
+    sync_check(s);
+  });
+}
+
+pmx_status pmx_probe_entries(const pmx_geometry* geom, int32_t nr, const int32_t* rows, const int32_t* rtyp,
+                             int32_t nc, const int32_t* cols, const int32_t* ctyp, pmx_c64* out, void* stream) {
+  return guarded([&] {
+    validate(geom, nullptr);
+    if (nr <= 0 || nc <= 0 || !rows || !rtyp || !cols || !ctyp || !out) fail(PMX_EINVAL, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    pmx_factor F;
+    upload_geometry(&F, geom, s);
+    std::vector<int> a(nr), b(nc);
+    for (int i = 0; i < nr; ++i) {
+      if (rows[i] < 0 || rows[i] >= F.n_nodes || (rtyp[i] & ~1)) fail(PMX_EINVAL, "bad row");
+      a[i] = pmx_code_node(rows[i], rtyp[i]);
+    }
+    for (int i = 0; i < nc; ++i) {
+      if (cols[i] < 0 || cols[i] >= F.n_nodes || (ctyp[i] & ~1)) fail(PMX_EINVAL, "bad column");
+      b[i] = pmx_code_node(cols[i], ctyp[i]);
+    }
+    Arena tmp;
+    std::vector<EntryMat> em{EntryMat{tmp.upload(a, s), tmp.upload(b, s), nr, nc, (zd*)out, nr, 1}};
+    asm_entries(F.geom(), DevProxy{nullptr, nullptr, nullptr, nullptr, nullptr}, F.ext(), tmp.upload(em, s), 1, nr,
+                nc, s);
+    sync_check(s);
+  });
+}
+
+pmx_status pmx_probe_zgemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t opa, int32_t opb,
+                           const pmx_c64* A, const pmx_c64* B, pmx_c64* C, void* stream) {
+  return guarded([&] {
+    if (batch <= 0 || m <= 0 || n <= 0 || k < 0 || (k > 0 && (!A || !B)) || !C || opa < 0 || opa > 2 || opb < 0 ||
+        opb > 2)
+      fail(PMX_EINVAL, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<GemmArgs> ga(batch);
+    for (int b = 0; b < batch; ++b) {
+      GemmArgs& g = ga[b];
+      g.m = m;
+      g.n = n;
+      g.k = k;
+      g.A = (const zd*)A + (int64_t)b * m * k;
+      g.lda = opa == OP_N ? m : k;
+      g.B = (const zd*)B + (int64_t)b * k * n;
+      g.ldb = opb == OP_N ? k : n;
+      g.C = (zd*)C + (int64_t)b * m * n;
+      g.ldc = m;
+    }
+    Arena tmp;
+    la_zgemm_list(opa, opb, tmp.upload(ga, s), batch, m, n, zmk(1, 0), zmk(0, 0), s);
+    sync_check(s);
+  });
+}
+
+pmx_status pmx_probe_lu_solve(int32_t batch, int32_t n, pmx_c64* A, int32_t* ipiv, int32_t nrhs, pmx_c64* B,
+                              int32_t* info, void* stream) {
+  return guarded([&] {
+    if (batch <= 0 || n <= 0 || nrhs < 0 || !A || !ipiv || (nrhs > 0 && !B) || !info) fail(PMX_EINVAL, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<LuDesc> lu(batch);
+    std::vector<Mat> bm(batch);
+    for (int b = 0; b < batch; ++b) {
+      lu[b] = LuDesc{(zd*)A + (int64_t)b * n * n, n, n, ipiv + (int64_t)b * n};
+      bm[b] = Mat{nrhs > 0 ? (zd*)B + (int64_t)b * n * nrhs : nullptr, n, n, nrhs};
+    }
+    Arena tmp;
+    LuDesc* d_lu = tmp.upload(lu, s);
+    int* d_info = tmp.alloc<int>(batch);
+    HIPCHK(hipMemsetAsync(d_info, 0, batch * sizeof(int), s));
+    la_getrf(d_lu, batch, n, d_info, s);
+    if (nrhs > 0) la_getrs(d_lu, tmp.upload(bm, s), batch, n, nrhs, s);
+    std::vector<int> hi;
+    download(hi, d_info, batch, s);
+    std::copy(hi.begin(), hi.end(), info);
+    sync_check(s);
+  });
+}
+
+pmx_status pmx_probe_id(int32_t batch, int32_t m, int32_t c, pmx_c64* M, double tol, const int32_t* kmin,
+                        int32_t* piv, int32_t* rank, pmx_c64* T, void* stream) {
+  return guarded([&] {
+    if (batch <= 0 || m <= 0 || c <= 0 || !M || !piv || !rank || !T || !(tol > 0)) fail(PMX_EINVAL, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    Arena tmp;
+    const int mb = std::min(m, c);
+    zd* Rb = tmp.alloc<zd>((int64_t)batch * mb * c);
+    zd* Vb = tmp.alloc<zd>((int64_t)batch * m * PMX_QR_NB);
+    zd* VTb = tmp.alloc<zd>((int64_t)batch * m * PMX_QR_NB);
+    zd* Wb = tmp.alloc<zd>((int64_t)batch * PMX_QR_NB * c);
+    double* nrm = tmp.alloc<double>((int64_t)batch * 2 * c);
+    int* st = tmp.alloc<int>(4 * batch);
+    double* r11 = tmp.alloc<double>(batch);
+    std::vector<QrDesc> qd(batch);
+    std::vector<CpqrDesc> cd(batch);
+    for (int b = 0; b < batch; ++b) {
+      qd[b] = QrDesc{(zd*)M + (int64_t)b * m * c, m, m, c, Rb + (int64_t)b * mb * c, Vb + (int64_t)b * m * PMX_QR_NB,
+                     VTb + (int64_t)b * m * PMX_QR_NB, Wb + (int64_t)b * PMX_QR_NB * c};
+      cd[b] = CpqrDesc{Rb + (int64_t)b * mb * c, mb, c, piv + (int64_t)b * c, nrm + (int64_t)b * 2 * c, st + 4 * b,
+                       r11 + b};
+    }
+    QrDesc* d_qd = tmp.upload(qd, s);
+    CpqrDesc* d_cd = tmp.upload(cd, s);
+    la_geqrf_r(d_qd, batch, m, c, s);
+    la_cpqr(d_cd, batch, c, tol, nullptr, 1, s);
+    std::vector<int> sth;
+    download(sth, st, 4 * batch, s);
+    std::vector<int> k(batch);
+    for (int b = 0; b < batch; ++b) {
+      rank[b] = sth[4 * b + 1];
+      k[b] = std::max(rank[b], kmin ? kmin[b] : 0);
+      k[b] = std::max(1, std::min(k[b], mb));
+    }
+    int* d_k = tmp.upload(k, s);
+    la_cpqr(d_cd, batch, c, 0.0, d_k, 0, s);
+    download(sth, st, 4 * batch, s);
+    for (int b = 0; b < batch; ++b) k[b] = std::min(k[b], sth[4 * b]);
+    HIPCHK(hipMemcpyAsync(d_k, k.data(), batch * sizeof(int), hipMemcpyHostToDevice, s));
+    la_cpqr_tsolve(d_cd, d_k, batch, c, c, s);
+    // T[b] (c x c, ld c): rows 0..k-1 hold R11^-1 R12 in columns 0..c-k-1
+    std::vector<RowSrc> rs;
+    std::vector<GatherDesc> gd(batch);
+    for (int b = 0; b < batch; ++b) {
+      for (int i = 0; i < k[b]; ++i) rs.push_back(RowSrc{(int64_t)b * mb * c + i + (int64_t)k[b] * mb, mb});
+    }
+    RowSrc* d_rs = tmp.upload(rs, s);
+    int64_t ro = 0;
+    for (int b = 0; b < batch; ++b) {
+      gd[b] = GatherDesc{d_rs + ro, c - k[b] > 0 ? k[b] : 0, c - k[b], (zd*)T + (int64_t)b * c * c, c};
+      ro += k[b];
+    }
+    asm_gather(Rb, tmp.upload(gd, s), batch, c, c, s);
+    sync_check(s);
+  });
+}
+
+pmx_status pmx_plan_query(const pmx_geometry* geom, const pmx_options* opts, int32_t cap_cells, int32_t cap_near,
+                          int32_t* n_levels, int32_t* n_cells_total, int32_t* n_near_total, int32_t* cell_level,
+                          int32_t* cell_first_incl, double* cell_center, double* cell_rc, double* cell_rp,
+                          int32_t* cell_p, int32_t* near_off, int32_t* near) {
+  return guarded([&] {
+    pmx_options o;
+    pmx_options_default(&o);
+    if (opts) o = *opts;
+    validate(geom, &o);
+    if (!n_levels || !n_cells_total || !n_near_total) fail(PMX_EINVAL, "NULL size outputs");
+    std::vector<std::vector<CellPlan>> levels;
+    make_plan(geom, o, levels);
+    int tc = 0, tn = 0;
+    for (auto& L : levels)
+      for (auto& c : L) {
+        if (tc < cap_cells) {
+          if (cell_level) cell_level[tc] = (int)(&L - &levels[0]);
+          if (cell_first_incl) cell_first_incl[tc] = c.incl[0];
+          if (cell_center) {
+            cell_center[2 * tc] = c.cx;
+            cell_center[2 * tc + 1] = c.cy;
+          }
+          if (cell_rc) cell_rc[tc] = c.rc;
+          if (cell_rp) cell_rp[tc] = c.Rp;
+          if (cell_p) cell_p[tc] = c.P;
+          if (near_off) near_off[tc] = tn;
+        }
+        for (int v : c.near) {
+          if (near && tn < cap_near) near[tn] = v;
+          ++tn;
+        }
+        ++tc;
+      }
+    if (near_off && tc <= cap_cells) near_off[tc] = tn;
+    *n_levels = (int)levels.size();
+    *n_cells_total = tc;
+    *n_near_total = tn;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,186 @@
+// Quadtree, near lists and proxy circles of the recursive proxy solver.
+//
+// Sec. 3 of arXiv 2603.09381 takes each inclusion as a leaf cell and merges cells up
+// a tree; Sec. 4 orders grid cells along the Morton curve and treats the four
+// edge-adjacent cells as near field in the proxy method.  Readings used here:
+//  * parents are the 2x2 blocks of the grid at the level below (quadtree);
+//  * the cell centre is the mean of its inclusion centres, r_c the farthest own node;
+//  * near cells: the edge-adjacent cells of the same level plus every same-level cell
+//    with a node inside the proxy circle; the circle radius is max(ratio r_c,
+//    0.9 rho_far), rho_far the distance to the nearest node of a far cell;
+//  * P = max(P_min, 2 ceil(k+ R_p) + 2 ceil(ln tol / ln(r_c / rho_far)) + 16), or a
+//    fixed P and radius ratio r_c when the caller fixes them;
+//  * no proxy circle when every other cell of the level is near.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <map>
+#include <utility>
+
+uint64_t morton_code(uint32_t i, uint32_t j) {
+  uint64_t c = 0;
+  for (int b = 0; b < 32; ++b) {
+    c |= (uint64_t)((i >> b) & 1u) << (2 * b);
+    c |= (uint64_t)((j >> b) & 1u) << (2 * b + 1);
+  }
+  return c;
+}
+
+namespace {
+
+struct NodeSet {
+  std::vector<double> x, y;
+};
+
+double min_dist(const NodeSet& s, double cx, double cy) {
+  double d = std::numeric_limits<double>::infinity();
+  for (size_t i = 0; i < s.x.size(); ++i) d = std::min(d, std::hypot(s.x[i] - cx, s.y[i] - cy));
+  return d;
+}
+
+void near_and_proxy(const PlanOptions& o, const double* centers, const int64_t* node_off, const double* x,
+                    const double* y, std::vector<CellPlan>& cells) {
+  const int nc = (int)cells.size();
+  std::vector<NodeSet> pts(nc);
+  for (int t = 0; t < nc; ++t) {
+    CellPlan& c = cells[t];
+    double sx = 0, sy = 0;
+    for (int j : c.incl) {
+      sx += centers[2 * j];
+      sy += centers[2 * j + 1];
+    }
+    c.cx = sx / (double)c.incl.size();
+    c.cy = sy / (double)c.incl.size();
+    for (int j : c.incl)
+      for (int64_t i = node_off[j]; i < node_off[j + 1]; ++i) {
+        pts[t].x.push_back(x[i]);
+        pts[t].y.push_back(y[i]);
+      }
+    double rc = 0;
+    for (size_t i = 0; i < pts[t].x.size(); ++i) rc = std::max(rc, std::hypot(pts[t].x[i] - c.cx, pts[t].y[i] - c.cy));
+    c.rc = rc;
+  }
+  if (nc == 1) return;
+  const double inf = std::numeric_limits<double>::infinity();
+  for (int t = 0; t < nc; ++t) {
+    CellPlan& c = cells[t];
+    // lower bounds |c_t - c_s| - r_s on the node distance, to visit cells nearest first
+    std::vector<std::pair<double, int>> order;
+    order.reserve(nc - 1);
+    for (int s = 0; s < nc; ++s)
+      if (s != t) {
+        double lb = std::hypot(cells[s].cx - c.cx, cells[s].cy - c.cy) - cells[s].rc;
+        order.push_back({lb - 1e-9 * (1.0 + std::fabs(lb)), s});  // safe lower bound
+      }
+    std::sort(order.begin(), order.end());
+    std::vector<double> dmin(nc, -1.0);
+    auto dist = [&](int s) {
+      if (dmin[s] < 0) dmin[s] = min_dist(pts[s], c.cx, c.cy);
+      return dmin[s];
+    };
+    std::vector<char> isnear(nc, 0);
+    if (o.near_rule == 0)
+      for (int s = 0; s < nc; ++s)
+        if (s != t && std::abs(cells[s].I - c.I) + std::abs(cells[s].J - c.J) == 1) isnear[s] = 1;
+    double rho = inf, Rp = 0;
+    bool anyfar = false;
+    for (;;) {
+      rho = inf;
+      anyfar = false;
+      for (auto& pr : order) {
+        if (isnear[pr.second]) continue;
+        anyfar = true;
+        if (pr.first > rho) break;
+        rho = std::min(rho, dist(pr.second));
+      }
+      if (o.proxy_rule == 0 && anyfar)
+        Rp = std::max(o.proxy_ratio * c.rc, 0.9 * rho);
+      else
+        Rp = o.proxy_ratio * c.rc;
+      bool added = false;
+      for (auto& pr : order) {
+        if (pr.first > Rp) break;
+        if (isnear[pr.second]) continue;
+        if (dist(pr.second) <= Rp) {
+          isnear[pr.second] = 1;
+          added = true;
+        }
+      }
+      if (!added) break;
+    }
+    c.near.clear();
+    for (int s = 0; s < nc; ++s)
+      if (isnear[s]) c.near.push_back(s);
+    c.rho_far = rho;
+    if (anyfar) {
+      c.Rp = Rp;
+      if (o.proxy_rule == 0) {
+        double q = std::min(c.rc / rho, 0.95);
+        int P = 2 * (int)std::ceil(o.k_ext * Rp) + 2 * (int)std::ceil(std::log(o.id_tol) / std::log(q)) + 16;
+        c.P = std::max(o.proxy_min, P);
+      } else {
+        c.P = o.proxy_min;
+      }
+    } else {
+      c.Rp = 0;
+      c.P = 0;
+    }
+  }
+}
+
+}  // namespace
+
+std::string build_plan(int m, const int32_t* grid_ij, const double* centers, const int64_t* node_off,
+                       const double* x, const double* y, const PlanOptions& o,
+                       std::vector<std::vector<CellPlan>>& levels) {
+  levels.clear();
+  if (m <= 0) return "no inclusions";
+  if (!grid_ij) return "grid coordinates are required";
+  std::map<std::pair<int, int>, std::vector<int>> cur;
+  for (int j = 0; j < m; ++j) {
+    if (grid_ij[2 * j] < 0 || grid_ij[2 * j + 1] < 0) return "negative grid coordinate";
+    cur[{grid_ij[2 * j], grid_ij[2 * j + 1]}].push_back(j);
+  }
+  for (auto& kv : cur)
+    if (kv.second.size() != 1) return "two inclusions share a grid cell";
+  int lev = 0;
+  for (;;) {
+    std::vector<std::pair<uint64_t, std::pair<int, int>>> keys;
+    for (auto& kv : cur) keys.push_back({morton_code(kv.first.first, kv.first.second), kv.first});
+    std::sort(keys.begin(), keys.end());
+    std::vector<CellPlan> cells;
+    for (auto& k : keys) {
+      CellPlan c;
+      c.I = k.second.first;
+      c.J = k.second.second;
+      c.incl = cur[k.second];
+      std::sort(c.incl.begin(), c.incl.end());
+      cells.push_back(c);
+    }
+    if (lev > 0) {
+      const std::vector<CellPlan>& prev = levels.back();
+      std::map<std::pair<int, int>, int> index;
+      for (int t = 0; t < (int)prev.size(); ++t) index[{prev[t].I, prev[t].J}] = t;
+      for (auto& c : cells)
+        for (int b = 0; b < 2; ++b)
+          for (int a = 0; a < 2; ++a) {
+            auto it = index.find({2 * c.I + a, 2 * c.J + b});
+            if (it != index.end()) c.children.push_back(it->second);
+          }
+    }
+    levels.push_back(cells);
+    if (cells.size() == 1) break;
+    std::map<std::pair<int, int>, std::vector<int>> nxt;
+    for (auto& c : cells) {
+      auto& v = nxt[{c.I >> 1, c.J >> 1}];
+      v.insert(v.end(), c.incl.begin(), c.incl.end());
+    }
+    cur.swap(nxt);
+    ++lev;
+    if (lev > 40) return "tree too deep";
+  }
+  for (auto& cells : levels) near_and_proxy(o, centers, node_off, x, y, cells);
+  return "";
+}

@@ -1,0 +1,330 @@
+"""ctypes binding of libpmx.so (include/pmx.h, include/pmx_probe.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  Device buffers are torch tensors on the current device (complex128 for
+densities and far fields); the current torch stream is passed to every call.
+The library must have been built (``__graft_entry__.build()``); loading fails
+loudly when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmx.so")
+_lib = None
+
+PMX_STATUS = {0: "PMX_OK", 1: "PMX_EINVAL", 2: "PMX_EGEOM", 3: "PMX_ENOMEM", 4: "PMX_EHIP",
+              5: "PMX_ESINGULAR", 6: "PMX_ENOTCONV"}
+
+EXPORTS = [
+    "pmx_options_default", "pmx_factor_create", "pmx_solve_plane_waves", "pmx_solve",
+    "pmx_far_field", "pmx_factor_info", "pmx_factor_destroy", "pmx_status_string",
+    "pmx_last_error", "pmx_probe_bessel", "pmx_probe_diag_block", "pmx_probe_entries",
+    "pmx_probe_zgemm", "pmx_probe_lu_solve", "pmx_probe_id", "pmx_plan_query",
+]
+
+
+class PmxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{PMX_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Geometry(C.Structure):
+    _fields_ = [("m", C.c_int32), ("node_off", C.POINTER(C.c_int64)),
+                ("x", C.POINTER(C.c_double)), ("y", C.POINTER(C.c_double)),
+                ("dx", C.POINTER(C.c_double)), ("dy", C.POINTER(C.c_double)),
+                ("ddx", C.POINTER(C.c_double)), ("ddy", C.POINTER(C.c_double)),
+                ("center", C.POINTER(C.c_double)), ("grid_ij", C.POINTER(C.c_int32)),
+                ("k_ext", C.c_double), ("eps_ext", C.c_double),
+                ("k_int", C.POINTER(C.c_double)), ("eps_int", C.POINTER(C.c_double))]
+
+
+class Options(C.Structure):
+    _fields_ = [("id_tol", C.c_double), ("proxy_ratio", C.c_double), ("proxy_min", C.c_int32),
+                ("proxy_rule", C.c_int32), ("near_rule", C.c_int32), ("precision", C.c_int32),
+                ("timing", C.c_int32), ("reserved", C.c_int32 * 8)]
+
+
+class Info(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("root_size", C.c_int32), ("n_unknowns", C.c_int32),
+                ("cells", C.c_int32 * 32), ("rank_min", C.c_int32 * 32), ("rank_max", C.c_int32 * 32),
+                ("rank_mean", C.c_double * 32), ("bytes_factor", C.c_double),
+                ("t_factor_ms", C.c_double), ("t_phase_ms", C.c_double * 16)]
+
+
+def load(path=None):
+    """Load libpmx.so (once)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    # PyTorch bundles its own HIP runtime under the same soname; importing it first makes
+    # the library bind to that one runtime instead of loading a second copy.
+    import torch  # noqa: F401
+    if not os.path.exists(p):
+        raise RuntimeError(f"libpmx.so is not built ({p}); run __graft_entry__.build()")
+    lib = C.CDLL(p)
+    vp = C.c_void_p
+    lib.pmx_options_default.argtypes = [C.POINTER(Options)]
+    lib.pmx_options_default.restype = None
+    lib.pmx_factor_create.argtypes = [C.POINTER(Geometry), C.POINTER(Options), vp, C.POINTER(vp)]
+    lib.pmx_solve_plane_waves.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), vp, vp]
+    lib.pmx_solve.argtypes = [vp, C.c_int32, vp, vp, vp]
+    lib.pmx_far_field.argtypes = [vp, C.c_int32, vp, C.c_int32, C.POINTER(C.c_double), vp, vp]
+    lib.pmx_factor_info.argtypes = [vp, C.POINTER(Info)]
+    lib.pmx_factor_destroy.argtypes = [vp]
+    lib.pmx_factor_destroy.restype = None
+    lib.pmx_status_string.argtypes = [C.c_int]
+    lib.pmx_status_string.restype = C.c_char_p
+    lib.pmx_last_error.argtypes = []
+    lib.pmx_last_error.restype = C.c_char_p
+    lib.pmx_probe_bessel.argtypes = [vp, C.c_int64, vp, vp]
+    lib.pmx_probe_diag_block.argtypes = [C.POINTER(Geometry), C.c_int32, vp, vp]
+    ip = C.POINTER(C.c_int32)
+    lib.pmx_probe_entries.argtypes = [C.POINTER(Geometry), C.c_int32, ip, ip, C.c_int32, ip, ip, vp, vp]
+    lib.pmx_probe_zgemm.argtypes = [C.c_int32] * 6 + [vp, vp, vp, vp]
+    lib.pmx_probe_lu_solve.argtypes = [C.c_int32, C.c_int32, vp, vp, C.c_int32, vp, ip, vp]
+    lib.pmx_probe_id.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, C.c_double, ip, vp, ip, vp, vp]
+    dp = C.POINTER(C.c_double)
+    lib.pmx_plan_query.argtypes = [C.POINTER(Geometry), C.POINTER(Options), C.c_int32, C.c_int32,
+                                   ip, ip, ip, ip, ip, dp, dp, dp, ip, ip, ip]
+    for name in EXPORTS:
+        if name not in ("pmx_options_default", "pmx_factor_destroy", "pmx_status_string",
+                        "pmx_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != 0:
+        raise PmxError(st, _lib.pmx_last_error().decode())
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class _GeomKeep:
+    """Host arrays of a workload kept alive while a Geometry structure points at them."""
+
+    def __init__(self, w, eps_int=None):
+        self.node_off = np.ascontiguousarray(w.node_off, dtype=np.int64)
+        self.arr = [np.ascontiguousarray(a, dtype=np.float64) for a in (w.x, w.y, w.dx, w.dy, w.ddx, w.ddy)]
+        self.center = np.ascontiguousarray(np.asarray(w.centers, float).reshape(-1))
+        gi = w.grid_index if w.grid_index is not None else np.zeros((w.m, 2), int)
+        self.grid = np.ascontiguousarray(np.asarray(gi).reshape(-1), dtype=np.int32)
+        self.k_int = np.ascontiguousarray(w.k_int, dtype=np.float64)
+        self.eps_int = None if eps_int is None else np.ascontiguousarray(eps_int, dtype=np.float64)
+        g = Geometry()
+        g.m = w.m
+        g.node_off = _ptr(self.node_off, C.c_int64)
+        g.x, g.y, g.dx, g.dy, g.ddx, g.ddy = [_ptr(a, C.c_double) for a in self.arr]
+        g.center = _ptr(self.center, C.c_double)
+        g.grid_ij = _ptr(self.grid, C.c_int32) if w.grid_index is not None else None
+        g.k_ext = w.k_ext
+        g.eps_ext = w.eps_ext
+        g.k_int = _ptr(self.k_int, C.c_double)
+        g.eps_int = None if self.eps_int is None else _ptr(self.eps_int, C.c_double)
+        self.g = g
+
+
+def options(w=None, **kw):
+    load()
+    o = Options()
+    _lib.pmx_options_default(C.byref(o))
+    if w is not None:
+        o.id_tol = w.id_tol
+        o.proxy_ratio = w.proxy_ratio
+        o.proxy_min = w.proxy_min
+        o.proxy_rule = 0 if w.proxy_paper_rule else 1
+        o.near_rule = w.near_rule
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Factor:
+    """A factorisation held by the library; `solve_plane_waves` returns torch tensors."""
+
+    def __init__(self, w, opts=None):
+        load()
+        self.w = w
+        self._keep = _GeomKeep(w)
+        self.opts = options(w) if opts is None else opts
+        h = C.c_void_p()
+        _check(_lib.pmx_factor_create(C.byref(self._keep.g), C.byref(self.opts), _stream(), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.pmx_factor_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        i = Info()
+        _check(_lib.pmx_factor_info(self.h, C.byref(i)))
+        return i
+
+    def solve_plane_waves(self, angles, out=None):
+        import torch
+        ang = np.ascontiguousarray(angles, dtype=np.float64)
+        n2 = self.w.n_unknowns
+        if out is None:
+            out = torch.empty((len(ang), n2), dtype=torch.complex128, device="cuda")
+        _check(_lib.pmx_solve_plane_waves(self.h, len(ang), _ptr(ang, C.c_double), C.c_void_p(out.data_ptr()),
+                                          _stream()))
+        return out
+
+    def solve(self, rhs, out=None):
+        import torch
+        rhs = rhs.contiguous()
+        if out is None:
+            out = torch.empty_like(rhs)
+        _check(_lib.pmx_solve(self.h, rhs.shape[0], C.c_void_p(rhs.data_ptr()), C.c_void_p(out.data_ptr()),
+                              _stream()))
+        return out
+
+    def far_field(self, dens, dirs):
+        import torch
+        d = np.ascontiguousarray(dirs, dtype=np.float64)
+        dens = dens.contiguous()
+        out = torch.empty((dens.shape[0], len(d)), dtype=torch.complex128, device=dens.device)
+        _check(_lib.pmx_far_field(self.h, dens.shape[0], C.c_void_p(dens.data_ptr()), len(d), _ptr(d, C.c_double),
+                                  C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+
+def dens_to_numpy(d, w):
+    """(nrhs, 2N) tensor -> (2N, nrhs) numpy, the oracle's stacked layout."""
+    return d.detach().cpu().numpy().T.copy()
+
+
+# -- probes -------------------------------------------------------------------------
+def probe_bessel(z):
+    import torch
+    load()
+    zt = torch.as_tensor(np.ascontiguousarray(z, dtype=np.float64), device="cuda")
+    out = torch.empty((4, len(z)), dtype=torch.float64, device="cuda")
+    _check(_lib.pmx_probe_bessel(C.c_void_p(zt.data_ptr()), len(z), C.c_void_p(out.data_ptr()), _stream()))
+    return out.cpu().numpy()
+
+
+def probe_diag_block(w, j):
+    import torch
+    load()
+    keep = _GeomKeep(w)
+    n = int(w.node_off[j + 1] - w.node_off[j])
+    out = torch.empty((2 * n, 2 * n), dtype=torch.complex128, device="cuda")
+    _check(_lib.pmx_probe_diag_block(C.byref(keep.g), j, C.c_void_p(out.data_ptr()), _stream()))
+    return out.cpu().numpy().T.copy()       # column major on the device
+
+
+def probe_entries(w, rows, rtyp, cols, ctyp):
+    import torch
+    load()
+    keep = _GeomKeep(w)
+    r = np.ascontiguousarray(rows, np.int32)
+    rt = np.ascontiguousarray(rtyp, np.int32)
+    c = np.ascontiguousarray(cols, np.int32)
+    ct = np.ascontiguousarray(ctyp, np.int32)
+    out = torch.empty((len(c), len(r)), dtype=torch.complex128, device="cuda")
+    _check(_lib.pmx_probe_entries(C.byref(keep.g), len(r), _ptr(r, C.c_int32), _ptr(rt, C.c_int32), len(c),
+                                  _ptr(c, C.c_int32), _ptr(ct, C.c_int32), C.c_void_p(out.data_ptr()), _stream()))
+    return out.cpu().numpy().T.copy()
+
+
+def _colmajor(t):
+    """(batch, rows, cols) torch -> device buffer holding each matrix column major."""
+    return t.transpose(-1, -2).contiguous()
+
+
+def probe_zgemm(A, B, opa=0, opb=0):
+    """A, B: (batch, ., .) complex128 numpy arrays in their stored shapes."""
+    import torch
+    load()
+    At = _colmajor(torch.as_tensor(A, device="cuda"))
+    Bt = _colmajor(torch.as_tensor(B, device="cuda"))
+    batch = A.shape[0]
+    m = A.shape[1] if opa == 0 else A.shape[2]
+    k = A.shape[2] if opa == 0 else A.shape[1]
+    n = B.shape[2] if opb == 0 else B.shape[1]
+    Ct = torch.empty((batch, n, m), dtype=torch.complex128, device="cuda")
+    _check(_lib.pmx_probe_zgemm(batch, m, n, k, opa, opb, C.c_void_p(At.data_ptr()), C.c_void_p(Bt.data_ptr()),
+                                C.c_void_p(Ct.data_ptr()), _stream()))
+    return Ct.transpose(-1, -2).cpu().numpy()
+
+
+def probe_lu_solve(A, B):
+    import torch
+    load()
+    batch, n, _ = A.shape
+    nrhs = B.shape[2]
+    At = _colmajor(torch.as_tensor(A, device="cuda"))
+    Bt = _colmajor(torch.as_tensor(B, device="cuda"))
+    piv = torch.empty((batch, n), dtype=torch.int32, device="cuda")
+    info = np.zeros(batch, np.int32)
+    _check(_lib.pmx_probe_lu_solve(batch, n, C.c_void_p(At.data_ptr()), C.c_void_p(piv.data_ptr()), nrhs,
+                                   C.c_void_p(Bt.data_ptr()), _ptr(info, C.c_int32), _stream()))
+    return (At.transpose(-1, -2).cpu().numpy(), piv.cpu().numpy(), Bt.transpose(-1, -2).cpu().numpy(), info)
+
+
+def probe_id(M, tol, kmin=None):
+    import torch
+    load()
+    batch, m, c = M.shape
+    Mt = _colmajor(torch.as_tensor(M, device="cuda"))
+    piv = torch.empty((batch, c), dtype=torch.int32, device="cuda")
+    rank = np.zeros(batch, np.int32)
+    T = torch.zeros((batch, c, c), dtype=torch.complex128, device="cuda")
+    km = None if kmin is None else np.ascontiguousarray(kmin, np.int32)
+    _check(_lib.pmx_probe_id(batch, m, c, C.c_void_p(Mt.data_ptr()), tol,
+                             None if km is None else _ptr(km, C.c_int32), C.c_void_p(piv.data_ptr()),
+                             _ptr(rank, C.c_int32), C.c_void_p(T.data_ptr()), _stream()))
+    return piv.cpu().numpy(), rank, T.transpose(-1, -2).cpu().numpy()
+
+
+def plan_query(w, opts=None):
+    """Host-only plan of the library: list of levels, each a list of dicts."""
+    load()
+    keep = _GeomKeep(w)
+    o = options(w) if opts is None else opts
+    nl, nct, nnt = C.c_int32(), C.c_int32(), C.c_int32()
+    z = C.POINTER(C.c_int32)()
+    zd_ = C.POINTER(C.c_double)()
+    _check(_lib.pmx_plan_query(C.byref(keep.g), C.byref(o), 0, 0, C.byref(nl), C.byref(nct), C.byref(nnt),
+                               z, z, zd_, zd_, zd_, z, z, z))
+    nc, nn = nct.value, nnt.value
+    lev = np.zeros(nc, np.int32)
+    first = np.zeros(nc, np.int32)
+    cen = np.zeros(2 * nc)
+    rc = np.zeros(nc)
+    rp = np.zeros(nc)
+    P = np.zeros(nc, np.int32)
+    noff = np.zeros(nc + 1, np.int32)
+    near = np.zeros(max(nn, 1), np.int32)
+    _check(_lib.pmx_plan_query(C.byref(keep.g), C.byref(o), nc, nn, C.byref(nl), C.byref(nct), C.byref(nnt),
+                               _ptr(lev, C.c_int32), _ptr(first, C.c_int32), _ptr(cen, C.c_double),
+                               _ptr(rc, C.c_double), _ptr(rp, C.c_double), _ptr(P, C.c_int32),
+                               _ptr(noff, C.c_int32), _ptr(near, C.c_int32)))
+    levels = [[] for _ in range(nl.value)]
+    for t in range(nc):
+        levels[lev[t]].append(dict(first=int(first[t]), center=(cen[2 * t], cen[2 * t + 1]), rc=rc[t],
+                                   Rp=rp[t], P=int(P[t]), near=list(near[noff[t]:noff[t + 1]])))
+    return levels

@@ -1,0 +1,113 @@
+"""Host-side tests of libpmx.so that need no GPU: exports, plan, argument validation."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import fast
+from paper_2603_09381_amd import pmx
+from paper_2603_09381_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for h in ("pmx.h", "pmx_probe.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        names.update(re.findall(r"\b(pmx_[a-z_0-9]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pmx.load()
+    declared = _declared_symbols()
+    assert declared, "no declarations found"
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert set(pmx.EXPORTS) == declared
+
+
+def test_status_strings():
+    lib = pmx.load()
+    for s in range(7):
+        assert lib.pmx_status_string(s)
+    lib.pmx_factor_destroy(None)
+
+
+@pytest.mark.parametrize("w", [W.config1(), W.sub_grid(W.config2(), 4), W.star_grid(6, n=64),
+                               W.sub_grid(W.config2(), 8)], ids=lambda w: w.name)
+def test_plan_matches_oracle_exactly(w):
+    """Tree, centres, radii, proxy radius and count and near lists: bit-exact."""
+    lv = pmx.plan_query(w)
+    ol = fast.plan(w)
+    assert len(lv) == len(ol)
+    for a, b in zip(lv, ol):
+        assert len(a) == len(b)
+        for ca, cb in zip(a, b):
+            assert ca["first"] == cb.incl[0]
+            assert ca["center"] == cb.center
+            assert ca["rc"] == cb.rc
+            assert ca["Rp"] == cb.Rp
+            assert ca["P"] == cb.P
+            assert ca["near"] == cb.near
+
+
+def test_plan_full_cfg2_structure():
+    """16x16 grid: 5 levels (256, 64, 16, 4, 1 cells); the root's children have no proxy."""
+    lv = pmx.plan_query(W.config2())
+    assert [len(l) for l in lv] == [256, 64, 16, 4, 1]
+    assert all(c["P"] == 0 for c in lv[3])
+    assert all(c["P"] > 0 for c in lv[0])
+    interior = [c for c in lv[0] if len(c["near"]) == 4]
+    assert len(interior) == 14 * 14
+
+
+def _create(w, **kw):
+    lib = pmx.load()
+    keep = pmx._GeomKeep(w)
+    for k, v in kw.items():
+        setattr(keep.g, k, v)
+    o = pmx.options(w)
+    h = C.c_void_p()
+    st = lib.pmx_factor_create(C.byref(keep.g), C.byref(o), None, C.byref(h))
+    return st, lib.pmx_last_error().decode()
+
+
+def test_rejects_odd_node_count():
+    w = W.star_grid(2, n=64)
+    w.node_off = w.node_off.copy()
+    w.node_off[1] = 63
+    st, msg = _create(w)
+    assert st == 1 and "even" in msg
+
+
+def test_rejects_nonpositive_wavenumber():
+    w = W.star_grid(2, n=64)
+    st, _ = _create(w, k_ext=-1.0)
+    assert st == 1
+
+
+def test_rejects_shared_grid_cell():
+    w = W.star_grid(2, n=64)
+    w.grid_index = w.grid_index.copy()
+    w.grid_index[1] = w.grid_index[0]
+    st, msg = _create(w)
+    assert st == 2 and "share" in msg
+
+
+def test_rejects_nan_geometry():
+    w = W.star_grid(2, n=64)
+    w.x = w.x.copy()
+    w.x[5] = np.nan
+    st, _ = _create(w)
+    assert st == 1
+
+
+def test_rejects_missing_grid():
+    w = W.star_grid(2, n=64)
+    w.grid_index = None
+    st, msg = _create(w)
+    assert st == 2
