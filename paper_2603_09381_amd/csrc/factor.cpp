@@ -384,7 +384,7 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
       offR[q] = totR;
       totR += (int64_t)std::min(m, c) * c;
       offV[q] = totV;
-      totV += (int64_t)m * PMX_QR_NB;
+      totV += la_geqrf_workspace(m);
       offW[q] = totW;
       totW += (int64_t)PMX_QR_NB * c;
       offC[q] = totC;
@@ -396,7 +396,9 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
   zd* Rb = tmp.alloc<zd>(totR);
   zd* Vb = tmp.alloc<zd>(totV);
   zd* VTb = tmp.alloc<zd>(totV);
-  zd* Wb = tmp.alloc<zd>(totW);
+  zd* CVb = tmp.alloc<zd>(totC);
+  double* taub = tmp.alloc<double>(nid);
+  int* d_work = tmp.alloc<int>(1);
   int* pivb = tmp.alloc<int>(totC);
   double* nrmb = tmp.alloc<double>(2 * totC);
   int* stb = tmp.alloc<int>(4 * nid);
@@ -425,7 +427,7 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
       Q.r = Rb + offR[q];
       Q.v = Vb + offV[q];
       Q.t = VTb + offV[q];
-      Q.w = Wb + offW[q];
+
       CpqrDesc& C = cd[q];
       C.b = Rb + offR[q];
       C.mb = std::min(idm[q], idc[q]);
@@ -434,13 +436,15 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
       C.nrm = nrmb + 2 * offC[q];
       C.state = stb + 4 * q;
       C.r11 = r11b + q;
+      C.v = CVb + offC[q];
+      C.tau = taub + q;
     }
   EntryMat* d_em = tmp.upload(em, s);
   QrDesc* d_qd = tmp.upload(qd, s);
   CpqrDesc* d_cd = tmp.upload(cd, s);
   asm_entries(F->geom(), PT.dev, F->ext(), d_em, nid, maxm, maxc, s);
   la_geqrf_r(d_qd, nid, maxm, maxc, s);
-  la_cpqr(d_cd, nid, maxc, tol, nullptr, 1, s);
+  la_cpqr(d_cd, nid, maxc, tol, nullptr, 1, d_work, s);
   std::vector<int> st;
   download(st, stb, 4 * nid, s);
   // ---- common ranks per pair, continuation
@@ -456,7 +460,7 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
       kq[qc] = kq[qr] = kb;
     }
   int* d_kq = tmp.upload(kq, s);
-  la_cpqr(d_cd, nid, maxc, 0.0, d_kq, 0, s);
+  la_cpqr(d_cd, nid, maxc, 0.0, d_kq, 0, d_work, s);
   download(st, stb, 4 * nid, s);
   for (int t = 0; t < nc; ++t)
     for (int ty = 0; ty < 2; ++ty) {
@@ -1348,24 +1352,27 @@ pmx_status pmx_probe_id(int32_t batch, int32_t m, int32_t c, pmx_c64* M, double 
     Arena tmp;
     const int mb = std::min(m, c);
     zd* Rb = tmp.alloc<zd>((int64_t)batch * mb * c);
-    zd* Vb = tmp.alloc<zd>((int64_t)batch * m * PMX_QR_NB);
-    zd* VTb = tmp.alloc<zd>((int64_t)batch * m * PMX_QR_NB);
-    zd* Wb = tmp.alloc<zd>((int64_t)batch * PMX_QR_NB * c);
+    const int64_t wsz = la_geqrf_workspace(m);
+    zd* Vb = tmp.alloc<zd>((int64_t)batch * wsz);
+    zd* VTb = tmp.alloc<zd>((int64_t)batch * wsz);
+    zd* CVb = tmp.alloc<zd>((int64_t)batch * c);
+    double* taub = tmp.alloc<double>(batch);
+    int* d_work = tmp.alloc<int>(1);
     double* nrm = tmp.alloc<double>((int64_t)batch * 2 * c);
     int* st = tmp.alloc<int>(4 * batch);
     double* r11 = tmp.alloc<double>(batch);
     std::vector<QrDesc> qd(batch);
     std::vector<CpqrDesc> cd(batch);
     for (int b = 0; b < batch; ++b) {
-      qd[b] = QrDesc{(zd*)M + (int64_t)b * m * c, m, m, c, Rb + (int64_t)b * mb * c, Vb + (int64_t)b * m * PMX_QR_NB,
-                     VTb + (int64_t)b * m * PMX_QR_NB, Wb + (int64_t)b * PMX_QR_NB * c};
+      qd[b] = QrDesc{(zd*)M + (int64_t)b * m * c, m, m, c, Rb + (int64_t)b * mb * c, Vb + (int64_t)b * wsz,
+                     VTb + (int64_t)b * wsz};
       cd[b] = CpqrDesc{Rb + (int64_t)b * mb * c, mb, c, piv + (int64_t)b * c, nrm + (int64_t)b * 2 * c, st + 4 * b,
-                       r11 + b};
+                       r11 + b, CVb + (int64_t)b * c, taub + b};
     }
     QrDesc* d_qd = tmp.upload(qd, s);
     CpqrDesc* d_cd = tmp.upload(cd, s);
     la_geqrf_r(d_qd, batch, m, c, s);
-    la_cpqr(d_cd, batch, c, tol, nullptr, 1, s);
+    la_cpqr(d_cd, batch, c, tol, nullptr, 1, d_work, s);
     std::vector<int> sth;
     download(sth, st, 4 * batch, s);
     std::vector<int> k(batch);
@@ -1375,7 +1382,7 @@ pmx_status pmx_probe_id(int32_t batch, int32_t m, int32_t c, pmx_c64* M, double 
       k[b] = std::max(1, std::min(k[b], mb));
     }
     int* d_k = tmp.upload(k, s);
-    la_cpqr(d_cd, batch, c, 0.0, d_k, 0, s);
+    la_cpqr(d_cd, batch, c, 0.0, d_k, 0, d_work, s);
     download(sth, st, 4 * batch, s);
     for (int b = 0; b < batch; ++b) k[b] = std::min(k[b], sth[4 * b]);
     HIPCHK(hipMemcpyAsync(d_k, k.data(), batch * sizeof(int), hipMemcpyHostToDevice, s));

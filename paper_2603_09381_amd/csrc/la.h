@@ -27,14 +27,13 @@ struct GemmArgs {
   int64_t ldc;
 };
 
-struct QrDesc {      // tall matrix M (m x c), factored by Householder, R written to r (c x c)
+struct QrDesc {      // tall matrix M (m x c), factored by Householder, R written to r
   zd* a;
   int64_t ld;
   int m, c;
   zd* r;             // [min(m,c) x c], leading dimension min(m,c)
-  zd* v;             // workspace: m x PMX_QR_NB explicit reflectors
-  zd* t;             // workspace: m x PMX_QR_NB, the reflectors times T^H (compact WY)
-  zd* w;             // workspace: PMX_QR_NB x c
+  zd* v;             // workspace: la_geqrf_workspace(m) reflector entries
+  zd* t;             // workspace: as v, the reflectors times T^H (compact WY)
 };
 
 struct CpqrDesc {    // column pivoted QR of b (mb x c, ld mb) in place
@@ -42,12 +41,15 @@ struct CpqrDesc {    // column pivoted QR of b (mb x c, ld mb) in place
   int mb, c;
   int* piv;          // [c] column permutation
   double* nrm;       // [2c] running squared norms and the reference squared norms
-  int* state;        // [4]: next step, threshold rank (-1 while running), status, pad
+  int* state;        // [4]: next step, threshold rank (-1 while running), done flag, current step
   double* r11;       // |R_11|
+  zd* v;             // [mb] current reflector (multi-workgroup variant)
+  double* tau;       // current reflector coefficient (multi-workgroup variant)
 };
 
 #define PMX_LU_NB 32
-#define PMX_QR_NB 16
+#define PMX_QR_NB 32
+#define PMX_TS_MAXLEV 4
 
 enum { OP_N = 0, OP_T = 1, OP_C = 2 };
 
@@ -58,13 +60,14 @@ void la_zgemm_list(int opa, int opb, const GemmArgs* d_list, int batch, int max_
 void la_getrf(const LuDesc* d_lu, int batch, int max_n, int* d_info, hipStream_t s);
 // Solve A X = B in place in B (n x nrhs per entry) using the LU of getrf.
 void la_getrs(const LuDesc* d_lu, const Mat* d_b, int batch, int max_n, int max_nrhs, hipStream_t s);
-// Householder QR of each M; writes R (upper, zero below) to QrDesc::r.
+// Householder QR of each M (destroyed); writes R (upper, zero below) to QrDesc::r.
+int64_t la_geqrf_workspace(int m);
 void la_geqrf_r(const QrDesc* d_qr, int batch, int max_m, int max_c, hipStream_t s);
-// Column pivoted QR with threshold rank on each CpqrDesc (in place).
-// Runs steps until |R_jj| <= tol |R_11| (phase 1, tol > 0) or until the step count
-// reaches kmin[b] (continuation, tol <= 0; kmin may be NULL).  A zero column stops both.
+// Matrices with max_c >= PMX_CPQR_MULTI_MIN columns use the multi-workgroup variant, which
+// needs d_work (one device int) and synchronises the stream every 16 steps.
+#define PMX_CPQR_MULTI_MIN 256
 void la_cpqr(const CpqrDesc* d_cp, int batch, int max_c, double tol, const int* d_kmin,
-             int init, hipStream_t s);
+             int init, int* d_work, hipStream_t s);
 // T = R11^-1 R12 in place: R11 = b[0:k,0:k] upper, R12 = b[0:k,k:c]; k from d_k.
 void la_cpqr_tsolve(const CpqrDesc* d_cp, const int* d_k, int batch, int max_k, int max_c,
                     hipStream_t s);

@@ -14,16 +14,35 @@
 // norm of the trailing part of the pivot column, which is what the threshold tests.
 #include "la.h"
 
+#include <algorithm>
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 #define PMX_CHECK_LAUNCH() (void)hipGetLastError()
 
 // ---------------------------------------------------------------------------------
 // wave / block reductions
+// DPP moves of a double (two 32-bit halves); lanes outside row_mask receive 0.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane: quad permutations, half-row and
+// row mirrors give each row of 16 its sum, row broadcasts 15 and 31 carry the row sums up
+// to lane 63, which is read back as a scalar.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_move<0xB1>(v);         // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);         // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);        // row_half_mirror
+  v += dpp_move<0x140>(v);        // row_mirror
+  v += dpp_move<0x142, 0xA>(v);   // row_bcast15 into rows 1 and 3
+  v += dpp_move<0x143, 0xC>(v);   // row_bcast31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 template <int NT>
@@ -102,16 +121,10 @@ __global__ __launch_bounds__(256) void k_zgemm(F f, zd alpha, zd beta) {
         i = (tid >> 3) + 32 * pass;
       }
       const int gi = tm + i, gk = k0 + kk;
-      zd v = zmk(0, 0);
-      if (gi < g.m && gk < g.k) {
-        if (OPA == OP_N) {
-          v = g.A[gi + (int64_t)gk * g.lda];
-        } else {
-          v = g.A[gk + (int64_t)gi * g.lda];
-          if (OPA == OP_C) v.im = -v.im;
-        }
-      }
-      As[kk][i] = v;
+      const int ci = min(gi, g.m - 1), ck = min(gk, g.k - 1);
+      zd v = (OPA == OP_N) ? g.A[ci + (int64_t)ck * g.lda] : g.A[ck + (int64_t)ci * g.lda];
+      if (OPA == OP_C) v.im = -v.im;
+      As[kk][i] = (gi < g.m && gk < g.k) ? v : zmk(0, 0);
     }
 #pragma unroll
     for (int pass = 0; pass < 2; ++pass) {
@@ -124,16 +137,10 @@ __global__ __launch_bounds__(256) void k_zgemm(F f, zd alpha, zd beta) {
         kk = (tid >> 6) + 4 * pass;
       }
       const int gj = tn + j, gk = k0 + kk;
-      zd v = zmk(0, 0);
-      if (gj < g.n && gk < g.k) {
-        if (OPB == OP_N) {
-          v = g.B[gk + (int64_t)gj * g.ldb];
-        } else {
-          v = g.B[gj + (int64_t)gk * g.ldb];
-          if (OPB == OP_C) v.im = -v.im;
-        }
-      }
-      Bs[kk][j] = v;
+      const int cj = min(gj, g.n - 1), ck = min(gk, g.k - 1);
+      zd v = (OPB == OP_N) ? g.B[ck + (int64_t)cj * g.ldb] : g.B[cj + (int64_t)ck * g.ldb];
+      if (OPB == OP_C) v.im = -v.im;
+      Bs[kk][j] = (gj < g.n && gk < g.k) ? v : zmk(0, 0);
     }
     __syncthreads();
 #pragma unroll
@@ -227,8 +234,10 @@ __global__ __launch_bounds__(64) void k_trsm_small(F f) {
     Ts[r][c] = a.T[r + (int64_t)c * a.ldt];
   }
   const bool active = col < a.nrhs;
-  if (active)
+  if (active) {
+#pragma unroll 8
     for (int i = 0; i < a.nb; ++i) xs[i][tid] = a.B[i + (int64_t)col * a.ldb];
+  }
   __syncthreads();
   if (active) {
     if (!UPPER) {
@@ -479,182 +488,353 @@ void la_getrs(const LuDesc* d_lu, const Mat* d_b, int batch, int max_n, int max_
 
 // ---------------------------------------------------------------------------------
 // Householder QR (only R is kept)
-#define QR_NT 256
-__global__ __launch_bounds__(QR_NT) void k_geqrf_panel(const QrDesc* qrs, int j0) {
-  const QrDesc Q = qrs[blockIdx.x];
+// Householder QR as a tree of in-LDS block factorisations (TSQR panels).
+//
+// Panel [j0, j0+jb) of rows [j0, m): the rows are cut into blocks of PMX_TS_BR rows; each
+// block is factored in LDS by one workgroup (16 Householder steps), leaving its R in the
+// block's first jb rows.  The stacked R factors form the rows of the next tree level
+// (block b, row r < jb of level L-1 becomes row b*jb + r of level L), factored the same
+// way until a single block remains, whose R is the panel's R in rows j0 .. j0+jb-1.
+// After each tree level the trailing columns of the same rows receive the block
+// reflectors Q_b^H = I - V_b T_b^H V_b^H (one fused kernel: W = V^H A, A -= (V T^H) W).
+// Only R is kept, so the order of the untouched remaining rows is free.
+#define PMX_TS_BR 256
+
+struct TsGeom {
+  int mr0, mr1, mr2, mr3;        // rows of tree levels 0..3
+  int nb0, nb1, nb2, nb3;        // blocks of tree levels 0..3
+  int64_t wo0, wo1, wo2, wo3;    // workspace offsets of the levels' V / VT blocks
+  int nlev;
+};
+
+__device__ inline int ts_sel(int L, int a0, int a1, int a2, int a3) {
+  return L == 0 ? a0 : (L == 1 ? a1 : (L == 2 ? a2 : a3));
+}
+__device__ inline int64_t ts_sel64(int L, int64_t a0, int64_t a1, int64_t a2, int64_t a3) {
+  return L == 0 ? a0 : (L == 1 ? a1 : (L == 2 ? a2 : a3));
+}
+
+__device__ inline void ts_geom(int m, int j0, int jb, TsGeom& g) {
+  const int64_t blk = (int64_t)PMX_TS_BR * PMX_QR_NB;
+  g.mr0 = m - j0;
+  g.nb0 = (g.mr0 + PMX_TS_BR - 1) / PMX_TS_BR;
+  g.wo0 = 0;
+  g.mr1 = g.nb0 * jb;
+  g.nb1 = g.nb0 > 1 ? (g.mr1 + PMX_TS_BR - 1) / PMX_TS_BR : 0;
+  g.wo1 = g.wo0 + g.nb0 * blk;
+  g.mr2 = g.nb1 * jb;
+  g.nb2 = g.nb1 > 1 ? (g.mr2 + PMX_TS_BR - 1) / PMX_TS_BR : 0;
+  g.wo2 = g.wo1 + g.nb1 * blk;
+  g.mr3 = g.nb2 * jb;
+  g.nb3 = g.nb2 > 1 ? (g.mr3 + PMX_TS_BR - 1) / PMX_TS_BR : 0;
+  g.wo3 = g.wo2 + g.nb2 * blk;
+  g.nlev = g.nb0 <= 1 ? 1 : (g.nb1 <= 1 ? 2 : (g.nb2 <= 1 ? 3 : 4));
+}
+
+// physical row of local row lr at tree level L, or -1 if the row does not exist
+__device__ inline int ts_phys(int lr, int L, int jb, int j0, const TsGeom& g) {
+  if (lr >= ts_sel(L, g.mr0, g.mr1, g.mr2, g.mr3)) return -1;
+#pragma unroll
+  for (int l = 3; l >= 1; --l) {
+    if (l <= L) {
+      const int b = lr / jb, r = lr - b * jb;
+      lr = b * PMX_TS_BR + r;
+      if (lr >= ts_sel(l - 1, g.mr0, g.mr1, g.mr2, g.mr3)) return -1;
+    }
+  }
+  return j0 + lr;
+}
+
+__device__ inline double ts_block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0;
+#pragma unroll
+  for (int w = 0; w < PMX_TS_BR / 64; ++w) s += red[w];
+  return s;
+}
+
+// One block of one tree level: Householder QR of its rows of the panel, entirely in LDS.
+// Columns are owned cyclically by the four waves (column q by wave q % 4), each lane
+// holding rows lane + 64k; a column's dot products are reduced inside its owner wave, so a
+// step costs two barriers: the owner of column i forms the reflector, then every wave
+// applies it to its own columns and forms its share of the compact-WY inner products.
+__global__ __launch_bounds__(PMX_TS_BR) void k_ts_leaf(const QrDesc* qrs, int j0, int L) {
+  const QrDesc Q = qrs[blockIdx.y];
   const int kmax = min(Q.m, Q.c);
   const int jb = min(PMX_QR_NB, kmax - j0);
   if (jb <= 0) return;
-  __shared__ double red[QR_NT / 64][2 * PMX_QR_NB];
-  __shared__ zd Ts[PMX_QR_NB][PMX_QR_NB];
-  __shared__ zd sh_beta_scale[2];
+  TsGeom g;
+  ts_geom(Q.m, j0, jb, g);
+  if (L >= g.nlev) return;
+  const int b = blockIdx.x;
+  if (b >= ts_sel(L, g.nb0, g.nb1, g.nb2, g.nb3)) return;
+  const int nrb = min(PMX_TS_BR, ts_sel(L, g.mr0, g.mr1, g.mr2, g.mr3) - b * PMX_TS_BR);
+  constexpr int NW = PMX_TS_BR / 64;           // waves
+  constexpr int RPL = PMX_TS_BR / 64;          // rows per lane
+  __shared__ zd Ps[PMX_QR_NB][PMX_TS_BR];      // panel block, column major; R above, V below
+  __shared__ zd vs[PMX_TS_BR];                 // current reflector
+  __shared__ zd Ts[PMX_QR_NB][PMX_QR_NB + 1];
+  __shared__ zd zs[PMX_QR_NB];
   __shared__ double sh_tau;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int phys = (t < nrb) ? ts_phys(b * PMX_TS_BR + t, L, jb, j0, g) : -1;
   zd* A = Q.a;
   const int64_t ld = Q.ld;
-  const int64_t ldv = Q.m;
-  for (int i = 0; i < jb; ++i) {
-    const int col = j0 + i;
-    double p = 0;
-    for (int r = col + tid; r < Q.m; r += QR_NT) p += zabs2(A[r + col * ld]);
-    p = wave_sum(p);
-    __syncthreads();
-    if (lane == 0) red[wave][0] = p;
-    __syncthreads();
-    if (tid == 0) {
-      double s2 = 0;
-      for (int w = 0; w < QR_NT / 64; ++w) s2 += red[w][0];
-      double xn = sqrt(s2);
-      zd alpha = A[col + col * ld];
-      double aa = sqrt(zabs2(alpha));
+  {
+    const int pr = phys >= 0 ? phys : j0;
+    zd tmpv[PMX_QR_NB];
+#pragma unroll
+    for (int i = 0; i < PMX_QR_NB; ++i) tmpv[i] = A[pr + (int64_t)min(j0 + i, Q.c - 1) * ld];
+#pragma unroll
+    for (int i = 0; i < PMX_QR_NB; ++i) Ps[i][t] = (phys >= 0 && i < jb) ? tmpv[i] : zmk(0, 0);
+  }
+  __syncthreads();
+  const int nref = min(jb, nrb);
+  for (int i = 0; i < nref; ++i) {
+    if (wave == (i % NW)) {
+      // owner wave: norm, Householder parameters (every lane computes them), reflector
+      zd x[RPL];
+      double p = 0;
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) {
+        const int r = lane + 64 * k;
+        x[k] = Ps[i][r];
+        if (r >= i) p += zabs2(x[k]);
+      }
+      const double xn = sqrt(wave_sum(p));
+      const zd alpha = Ps[i][i];
+      const double aa = sqrt(zabs2(alpha));
+      double tau;
+      zd beta, scale;
       if (xn == 0.0) {
-        sh_tau = 0.0;
-        sh_beta_scale[0] = zmk(0, 0);
-        sh_beta_scale[1] = zmk(0, 0);
+        tau = 0.0;
+        beta = zmk(0, 0);
+        scale = zmk(0, 0);
+      } else if (aa == 0.0) {
+        tau = 1.0;
+        beta = zmk(-xn, 0);
+        scale = zmk(1.0 / xn, 0);
       } else {
-        zd sg = aa > 0 ? zscale(alpha, 1.0 / aa) : zmk(1, 0);
-        zd beta = zscale(sg, -xn);
-        sh_tau = 1.0 + aa / xn;
-        sh_beta_scale[0] = beta;
-        sh_beta_scale[1] = zdiv(zmk(1, 0), zsub(alpha, beta));
+        // beta = -alpha |x|/|alpha|, tau = 1 + |alpha|/|x|, scale = conj(alpha)/(|alpha|(|alpha|+|x|))
+        const double ip = 1.0 / (aa * xn * (aa + xn));
+        tau = (aa + xn) * aa * (aa + xn) * ip;
+        beta = zscale(alpha, -xn * xn * (aa + xn) * ip);
+        scale = zscale(zconj(alpha), xn * ip);
+      }
+#pragma unroll
+      for (int k = 0; k < RPL; ++k) {
+        const int r = lane + 64 * k;
+        const zd v = (r == i) ? zmk(1, 0) : ((r > i) ? zmul(x[k], scale) : zmk(0, 0));
+        vs[r] = v;
+        if (r > i) Ps[i][r] = v;
+        if (r == i) Ps[i][i] = beta;
+      }
+      if (lane == 0) {
+        sh_tau = tau;
+        Ts[i][i] = zmk(tau, 0);
       }
     }
     __syncthreads();
     const double tau = sh_tau;
-    const zd beta = sh_beta_scale[0], scale = sh_beta_scale[1];
-    // reflector into the column and the explicit V buffer (rows j0..m-1)
-    for (int r = j0 + tid; r < Q.m; r += QR_NT) {
-      zd v;
-      if (r < col) {
-        v = zmk(0, 0);
-      } else if (r == col) {
-        v = zmk(1, 0);
-      } else {
-        v = zmul(A[r + col * ld], scale);
-        A[r + col * ld] = v;
-      }
-      Q.v[(r - j0) + i * ldv] = v;
-    }
-    __syncthreads();
-    if (tid == 0) A[col + col * ld] = beta;
-    // dot products: w_cc = v^H A[:, cc] for the remaining panel columns, z_j = V_j^H v
-    const int nrem = jb - 1 - i;
-    double acc[2 * PMX_QR_NB];
+    zd vr[RPL];
 #pragma unroll
-    for (int t = 0; t < 2 * PMX_QR_NB; ++t) acc[t] = 0;
-    for (int r = col + tid; r < Q.m; r += QR_NT) {
-      zd v = Q.v[(r - j0) + i * ldv];
+    for (int k = 0; k < RPL; ++k) vr[k] = vs[lane + 64 * k];
+    for (int q = wave; q < jb; q += NW) {
+      if (q > i) {
+        // w = v^H P[:, q]; P[:, q] -= tau v w
+        zd pq[RPL];
+        double wr = 0, wi = 0;
 #pragma unroll
-      for (int t = 0; t < PMX_QR_NB; ++t) {
-        if (t < nrem) {
-          zd a = (r == col) ? A[col + (col + 1 + t) * ld] : A[r + (col + 1 + t) * ld];
-          zd w = zcmul(v, a);
-          acc[2 * t] += w.re;
-          acc[2 * t + 1] += w.im;
-        } else if (t - nrem < i) {
-          int j = t - nrem;
-          zd vj = Q.v[(r - j0) + j * ldv];
-          zd z = zcmul(vj, v);
-          acc[2 * t] += z.re;
-          acc[2 * t + 1] += z.im;
+        for (int k = 0; k < RPL; ++k) {
+          pq[k] = Ps[q][lane + 64 * k];
+          const zd pr = zcmul(vr[k], pq[k]);
+          wr += pr.re;
+          wi += pr.im;
         }
-      }
-    }
-    const int nred = nrem + i;
+        const zd w = zscale(zmk(wave_sum(wr), wave_sum(wi)), tau);
 #pragma unroll
-    for (int t = 0; t < 2 * PMX_QR_NB; ++t)
-      if (t < 2 * nred) acc[t] = wave_sum(acc[t]);
-    __syncthreads();
-    if (lane == 0)
-      for (int t = 0; t < 2 * nred; ++t) red[wave][t] = acc[t];
-    __syncthreads();
-    if (tid < 2 * nred) {
-      double s = 0;
-      for (int w = 0; w < QR_NT / 64; ++w) s += red[w][tid];
-      red[0][tid] = s;
-    }
-    __syncthreads();
-    // A[:, cc] -= tau v w_cc ; the pivot row of the panel uses the value before beta was
-    // written, but row col of column col is excluded from the update (cc > col).
-    for (int r = col + tid; r < Q.m; r += QR_NT) {
-      zd v = Q.v[(r - j0) + i * ldv];
-      for (int t = 0; t < nrem; ++t) {
-        zd w = zmk(red[0][2 * t], red[0][2 * t + 1]);
-        int cc = col + 1 + t;
-        A[r + cc * ld] = zsub(A[r + cc * ld], zscale(zmul(v, w), tau));
+        for (int k = 0; k < RPL; ++k) {
+          const int r = lane + 64 * k;
+          if (r >= i) Ps[q][r] = zsub(pq[k], zmul(vr[k], w));
+        }
+      } else if (q < i) {
+        // z_q = V_q^H v for the compact-WY factor
+        double zr = 0, zi = 0;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+          const int r = lane + 64 * k;
+          const zd vq = (r == q) ? zmk(1, 0) : ((r > q) ? Ps[q][r] : zmk(0, 0));
+          const zd pr = zcmul(vq, vr[k]);
+          zr += pr.re;
+          zi += pr.im;
+        }
+        zr = wave_sum(zr);
+        zi = wave_sum(zi);
+        if (lane == 0) zs[q] = zmk(zr, zi);
       }
     }
-    // T column i: T[i,i] = tau, T[0:i, i] = -tau T[0:i,0:i] z
-    if (tid == 0) {
-      Ts[i][i] = zmk(tau, 0);
-      for (int r = 0; r < i; ++r) {
-        zd s = zmk(0, 0);
-        for (int j = r; j < i; ++j) s = zadd(s, zmul(Ts[r][j], zmk(red[0][2 * (nrem + j)], red[0][2 * (nrem + j) + 1])));
-        Ts[r][i] = zscale(s, -tau);
-      }
-      for (int r = i + 1; r < PMX_QR_NB; ++r) Ts[r][i] = zmk(0, 0);
-    }
     __syncthreads();
+    if (t < i) {  // T[0:i, i] = -tau T[0:i, 0:i] z, one row per thread
+      zd s2 = zmk(0, 0);
+#pragma unroll 8
+      for (int jj = t; jj < i; ++jj) s2 = zadd(s2, zmul(Ts[t][jj], zs[jj]));
+      Ts[t][i] = zscale(s2, -tau);
+    }
   }
-  // VT = V T^H for the trailing update, stored in the T workspace area after V
-  // (Q.t holds m x NB entries): VT[r, j] = sum_{i >= j} V[r, i] conj(T[j, i])
-  for (int r = j0 + tid; r < Q.m; r += QR_NT) {
-    zd vr[PMX_QR_NB];
+  __syncthreads();
+  // write back: R in the block's first rows, the reflectors V and V T^H to the workspace
+  if (phys >= 0 && t < jb) {
+    for (int i = 0; i < jb; ++i) A[phys + (int64_t)(j0 + i) * ld] = (i >= t) ? Ps[i][t] : zmk(0, 0);
+  }
+  const int64_t wo = ts_sel64(L, g.wo0, g.wo1, g.wo2, g.wo3) + (int64_t)b * PMX_TS_BR * PMX_QR_NB;
+  zd* V = Q.v + wo;
+  zd* VT = Q.t + wo;
+  zd vrow[PMX_QR_NB];
 #pragma unroll
-    for (int i = 0; i < PMX_QR_NB; ++i) vr[i] = (i < jb) ? Q.v[(r - j0) + i * ldv] : zmk(0, 0);
+  for (int i = 0; i < PMX_QR_NB; ++i) {
+    zd v = zmk(0, 0);
+    if (i < nref && t < nrb) v = (t == i) ? zmk(1, 0) : ((t > i) ? Ps[i][t] : zmk(0, 0));
+    vrow[i] = v;
+    V[t + (int64_t)i * PMX_TS_BR] = v;
+  }
 #pragma unroll
-    for (int j = 0; j < PMX_QR_NB; ++j) {
-      if (j >= jb) break;
-      zd s = zmk(0, 0);
+  for (int j = 0; j < PMX_QR_NB; ++j) {
+    zd s2 = zmk(0, 0);
 #pragma unroll
-      for (int i = 0; i < PMX_QR_NB; ++i)
-        if (i >= j && i < jb) s = zadd(s, zmul(vr[i], zconj(Ts[j][i])));
-      Q.t[(r - j0) + j * ldv] = s;
-    }
+    for (int i = j; i < PMX_QR_NB; ++i)
+      if (i < nref) s2 = zadd(s2, zmul(vrow[i], zconj(Ts[j][i])));
+    VT[t + (int64_t)j * PMX_TS_BR] = (j < nref) ? s2 : zmk(0, 0);
   }
 }
 
-struct FQrW {  // W = V^H A[j0:m, j0+jb:c]
-  const QrDesc* d;
-  int j0;
-  __device__ bool operator()(int b, GemmArgs& g) const {
-    QrDesc Q = d[b];
-    int jb = min(PMX_QR_NB, min(Q.m, Q.c) - j0);
-    int nc = Q.c - j0 - jb;
-    if (jb <= 0 || nc <= 0) return false;
-    g.m = jb;
-    g.n = nc;
-    g.k = Q.m - j0;
-    g.A = Q.v;
-    g.lda = Q.m;
-    g.B = Q.a + j0 + (j0 + jb) * Q.ld;
-    g.ldb = Q.ld;
-    g.C = Q.w;
-    g.ldc = PMX_QR_NB;
-    return true;
+// trailing update of one block of one tree level: A_b -= (V T^H) (V^H A_b), 64 columns per
+// workgroup, rows streamed through LDS in slices of 32, both products on 16x16x4 MFMA
+#define TSU_ROWS 32
+__global__ __launch_bounds__(256) void k_ts_update(const QrDesc* qrs, int j0, int L) {
+  const QrDesc Q = qrs[blockIdx.z];
+  const int kmax = min(Q.m, Q.c);
+  const int jb = min(PMX_QR_NB, kmax - j0);
+  const int nc = Q.c - j0 - jb;
+  if (jb <= 0 || nc <= 0) return;
+  const int c0 = blockIdx.x * 64;
+  if (c0 >= nc) return;
+  TsGeom g;
+  ts_geom(Q.m, j0, jb, g);
+  if (L >= g.nlev) return;
+  const int b = blockIdx.y;
+  if (b >= ts_sel(L, g.nb0, g.nb1, g.nb2, g.nb3)) return;
+  const int nrb = min(PMX_TS_BR, ts_sel(L, g.mr0, g.mr1, g.mr2, g.mr3) - b * PMX_TS_BR);
+  const int64_t wo = ts_sel64(L, g.wo0, g.wo1, g.wo2, g.wo3) + (int64_t)b * PMX_TS_BR * PMX_QR_NB;
+  const zd* V = Q.v + wo;
+  const zd* VT = Q.t + wo;
+  __shared__ zd Vs[TSU_ROWS][PMX_QR_NB + 1];
+  __shared__ zd As[TSU_ROWS][64 + 1];
+  __shared__ zd Ws[PMX_QR_NB][64 + 1];
+  __shared__ int rows[TSU_ROWS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  zd* A = Q.a;
+  const int64_t ld = Q.ld;
+  const int ccol0 = j0 + jb + c0;
+  // W = V^H A_b: output PMX_QR_NB x 64 as (NB/16) x 4 blocks of 16x16, NB/16 per wave
+  constexpr int RB = PMX_QR_NB / 16;
+  d4 accR[RB], accI[RB];
+#pragma unroll
+  for (int q = 0; q < RB; ++q) {
+    accR[q] = (d4){0, 0, 0, 0};
+    accI[q] = (d4){0, 0, 0, 0};
   }
-};
-
-struct FQrUpd {  // A[j0:m, j0+jb:c] -= VT W
-  const QrDesc* d;
-  int j0;
-  __device__ bool operator()(int b, GemmArgs& g) const {
-    QrDesc Q = d[b];
-    int jb = min(PMX_QR_NB, min(Q.m, Q.c) - j0);
-    int nc = Q.c - j0 - jb;
-    if (jb <= 0 || nc <= 0) return false;
-    g.m = Q.m - j0;
-    g.n = nc;
-    g.k = jb;
-    g.A = Q.t;
-    g.lda = Q.m;
-    g.B = Q.w;
-    g.ldb = PMX_QR_NB;
-    g.C = Q.a + j0 + (j0 + jb) * Q.ld;
-    g.ldc = Q.ld;
-    return true;
+  for (int rb = 0; rb < nrb; rb += TSU_ROWS) {
+    if (tid < TSU_ROWS) rows[tid] = (rb + tid < nrb) ? ts_phys(b * PMX_TS_BR + rb + tid, L, jb, j0, g) : -1;
+    __syncthreads();
+    {
+      const int rr = tid & (TSU_ROWS - 1);
+      const int cc = tid >> 5;
+      const int pr = rows[rr];
+      // the workspace rows exist up to PMX_TS_BR; matrix addresses are clamped
+      zd tv[PMX_QR_NB / 8], ta[8];
+#pragma unroll
+      for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
+        tv[pass] = V[rb + rr + (int64_t)(cc + 8 * pass) * PMX_TS_BR];
+      const int prc = pr >= 0 ? pr : j0;
+#pragma unroll
+      for (int pass = 0; pass < 8; ++pass)
+        ta[pass] = A[prc + (int64_t)(ccol0 + min(cc + 8 * pass, nc - 1 - c0)) * ld];
+#pragma unroll
+      for (int pass = 0; pass < PMX_QR_NB / 8; ++pass) Vs[rr][cc + 8 * pass] = (rb + rr < nrb) ? tv[pass] : zmk(0, 0);
+#pragma unroll
+      for (int pass = 0; pass < 8; ++pass)
+        As[rr][cc + 8 * pass] = (pr >= 0 && c0 + cc + 8 * pass < nc) ? ta[pass] : zmk(0, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TSU_ROWS; kk += 4) {
+      const zd bb = As[kk + (lane >> 4)][wave * 16 + (lane & 15)];
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        const zd a = Vs[kk + (lane >> 4)][q * 16 + (lane & 15)];
+        accR[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, bb.re, accR[q], 0, 0, 0);
+        accR[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, bb.im, accR[q], 0, 0, 0);
+        accI[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, bb.im, accI[q], 0, 0, 0);
+        accI[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, bb.re, accI[q], 0, 0, 0);
+      }
+    }
+    __syncthreads();
   }
-};
+#pragma unroll
+  for (int q = 0; q < RB; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      Ws[q * 16 + (lane >> 4) + 4 * r][wave * 16 + (lane & 15)] = zmk(accR[q][r], accI[q][r]);
+  __syncthreads();
+  // A_b -= VT W: a 32 x 64 slice is 2 x 4 blocks of 16x16, two per wave
+  const int rbk = wave & 1;
+  const int cbk0 = (wave >> 1) * 2;
+  for (int rb = 0; rb < nrb; rb += TSU_ROWS) {
+    if (tid < TSU_ROWS) rows[tid] = (rb + tid < nrb) ? ts_phys(b * PMX_TS_BR + rb + tid, L, jb, j0, g) : -1;
+    __syncthreads();
+    {
+      const int rr = tid & (TSU_ROWS - 1);
+      const int cc = tid >> 5;
+      zd tv[PMX_QR_NB / 8];
+#pragma unroll
+      for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
+        tv[pass] = VT[rb + rr + (int64_t)(cc + 8 * pass) * PMX_TS_BR];
+#pragma unroll
+      for (int pass = 0; pass < PMX_QR_NB / 8; ++pass) Vs[rr][cc + 8 * pass] = (rb + rr < nrb) ? tv[pass] : zmk(0, 0);
+    }
+    __syncthreads();
+    d4 dR[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, dI[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+#pragma unroll
+    for (int kk = 0; kk < PMX_QR_NB; kk += 4) {
+      const zd a = Vs[rbk * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const zd bb = Ws[kk + (lane >> 4)][(cbk0 + q) * 16 + (lane & 15)];
+        dR[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, bb.re, dR[q], 0, 0, 0);
+        dR[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, bb.im, dR[q], 0, 0, 0);
+        dI[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, bb.im, dI[q], 0, 0, 0);
+        dI[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, bb.re, dI[q], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rbk * 16 + (lane >> 4) + 4 * r;
+        const int col = (cbk0 + q) * 16 + (lane & 15);
+        const int pr = rows[row];
+        if (pr >= 0 && c0 + col < nc) {
+          zd* ap = A + pr + (int64_t)(ccol0 + col) * ld;
+          *ap = zsub(*ap, zmk(dR[q][r], dI[q][r]));
+        }
+      }
+    __syncthreads();
+  }
+}
 
 __global__ void k_copy_r(const QrDesc* qrs) {
   const QrDesc Q = qrs[blockIdx.y];
@@ -665,15 +845,35 @@ __global__ void k_copy_r(const QrDesc* qrs) {
   Q.r[e] = (r <= c) ? Q.a[r + c * Q.ld] : zmk(0, 0);
 }
 
+int64_t la_geqrf_workspace(int m) {
+  // V (and V T^H) blocks of every tree level for a matrix with m rows
+  int64_t tot = 0;
+  int mr = m;
+  for (int L = 0; L < PMX_TS_MAXLEV; ++L) {
+    int nb = (mr + PMX_TS_BR - 1) / PMX_TS_BR;
+    tot += (int64_t)std::max(nb, 1) * PMX_TS_BR * PMX_QR_NB;
+    if (nb <= 1) break;
+    mr = nb * PMX_QR_NB;
+  }
+  return tot;
+}
+
 void la_geqrf_r(const QrDesc* d_qr, int batch, int max_m, int max_c, hipStream_t s) {
   if (batch <= 0 || max_m <= 0 || max_c <= 0) return;
+  // four tree levels cover PMX_TS_BR * (PMX_TS_BR / PMX_QR_NB)^3 rows
+  const int64_t cap = (int64_t)PMX_TS_BR * (PMX_TS_BR / PMX_QR_NB) * (PMX_TS_BR / PMX_QR_NB) * (PMX_TS_BR / PMX_QR_NB);
+  if (max_m > cap) return;
   const int kmax = min(max_m, max_c);
   for (int j0 = 0; j0 < kmax; j0 += PMX_QR_NB) {
-    hipLaunchKernelGGL(k_geqrf_panel, dim3(batch), dim3(QR_NT), 0, s, d_qr, j0);
-    int nc = max_c - j0 - PMX_QR_NB;
-    if (nc > 0) {
-      launch_zgemm<OP_C, OP_N>(FQrW{d_qr, j0}, batch, PMX_QR_NB, nc, zmk(1, 0), zmk(0, 0), s);
-      launch_zgemm<OP_N, OP_N>(FQrUpd{d_qr, j0}, batch, max_m - j0, nc, zmk(-1, 0), zmk(1, 0), s);
+    int mr = max_m - j0;
+    const int nc = max_c - j0 - 1;
+    for (int L = 0; L < PMX_TS_MAXLEV; ++L) {
+      const int nb = (mr + PMX_TS_BR - 1) / PMX_TS_BR;
+      hipLaunchKernelGGL(k_ts_leaf, dim3(nb, batch), dim3(PMX_TS_BR), 0, s, d_qr, j0, L);
+      if (nc > 0)
+        hipLaunchKernelGGL(k_ts_update, dim3((nc + 63) / 64, nb, batch), dim3(256), 0, s, d_qr, j0, L);
+      if (nb <= 1) break;
+      mr = nb * PMX_QR_NB;
     }
   }
   int64_t tot = (int64_t)kmax * max_c;
@@ -817,12 +1017,193 @@ __global__ __launch_bounds__(CP_NT) void k_cpqr(const CpqrDesc* cps, double tol,
   }
 }
 
-void la_cpqr(const CpqrDesc* d_cp, int batch, int max_c, double tol, const int* d_kmin, int init,
+// Multi-workgroup variant for large matrices: per step one launch selects the pivot,
+// swaps it in and forms the reflector (one workgroup per matrix), a second applies the
+// reflector to the trailing columns (16 columns per workgroup, one wave per column) and
+// downdates their norms.  state[2] marks a finished matrix; finished matrices bump *ndone.
+__global__ __launch_bounds__(256) void k_cpqr_init(const CpqrDesc* cps, int init) {
+  const CpqrDesc C = cps[blockIdx.y];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l = blockIdx.x * 4 + wave;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && C.c > 0) {
+    if (init) {
+      C.state[0] = 0;
+      C.state[1] = -1;
+      *C.r11 = 0.0;
+    }
+    C.state[2] = 0;
+  }
+  if (!init || l >= C.c) return;
+  double p = 0;
+  for (int r = lane; r < C.mb; r += 64) p += zabs2(C.b[r + (int64_t)l * C.mb]);
+  p = wave_sum(p);
+  if (lane == 0) {
+    C.nrm[l] = p;
+    C.nrm[C.c + l] = p;
+    C.piv[l] = l;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cpqr_pivot(const CpqrDesc* cps, double tol, const int* kmin, int* ndone) {
+  const CpqrDesc C = cps[blockIdx.x];
+  if (C.c <= 0 || C.state[2]) return;
+  __shared__ double redv[4];
+  __shared__ int redi[4];
+  __shared__ int sh_stop;
+  __shared__ zd sh_scale;
+  const int tid = threadIdx.x;
+  zd* B = C.b;
+  const int mb = C.mb, c = C.c;
+  const int64_t ld = mb;
+  const int kmax = min(mb, c);
+  const int target = (tol > 0.0) ? kmax : min(kmax, kmin ? kmin[blockIdx.x] : kmax);
+  const int j = C.state[0];
+  if (j >= target) {
+    if (tid == 0) {
+      C.state[2] = 1;
+      if (tol > 0.0) C.state[1] = j;
+      atomicAdd(ndone, 1);
+    }
+    return;
+  }
+  double* nrm = C.nrm;
+  double best = -1.0;
+  int bi = -1;
+  for (int l = j + tid; l < c; l += 256) argmax_pair(best, bi, nrm[l], l);
+  const int p = block_argmax<256>(best, bi, redv, redi, nullptr);
+  if (p != j) {
+    for (int r = tid; r < mb; r += 256) {
+      zd t = B[r + j * ld];
+      B[r + j * ld] = B[r + p * ld];
+      B[r + p * ld] = t;
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && p != j) {
+    int ti = C.piv[j];
+    C.piv[j] = C.piv[p];
+    C.piv[p] = ti;
+    double t0 = nrm[j];
+    nrm[j] = nrm[p];
+    nrm[p] = t0;
+    t0 = nrm[c + j];
+    nrm[c + j] = nrm[c + p];
+    nrm[c + p] = t0;
+  }
+  double part = 0;
+  for (int r = j + tid; r < mb; r += 256) part += zabs2(B[r + j * ld]);
+  const double xn = sqrt(block_sum<256>(part, redv));
+  if (tid == 0) {
+    double r11 = (j == 0) ? xn : *C.r11;
+    if (j == 0) *C.r11 = xn;
+    int stop = 0;
+    if (xn == 0.0) stop = 1;
+    else if (tol > 0.0 && xn <= tol * r11) stop = 1;
+    sh_stop = stop;
+    if (stop) {
+      C.state[2] = 1;
+      if (tol > 0.0) C.state[1] = j;
+      atomicAdd(ndone, 1);
+    } else {
+      const zd alpha = B[j + j * ld];
+      const double aa = sqrt(zabs2(alpha));
+      const zd sg = aa > 0 ? zscale(alpha, 1.0 / aa) : zmk(1, 0);
+      const zd beta = zscale(sg, -xn);
+      *C.tau = 1.0 + aa / xn;
+      sh_scale = zdiv(zmk(1, 0), zsub(alpha, beta));
+      B[j + j * ld] = beta;
+    }
+  }
+  __syncthreads();
+  if (sh_stop) return;
+  const zd scale = sh_scale;
+  for (int r = j + tid; r < mb; r += 256) {
+    if (r == j) {
+      C.v[0] = zmk(1, 0);
+    } else {
+      C.v[r - j] = zmul(B[r + j * ld], scale);
+      B[r + j * ld] = zmk(0, 0);
+    }
+  }
+  if (tid == 0) {
+    C.state[3] = j;
+    C.state[0] = j + 1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_cpqr_update(const CpqrDesc* cps) {
+  const CpqrDesc C = cps[blockIdx.y];
+  if (C.c <= 0 || C.state[2]) return;
+  const int j = C.state[3];
+  const int l0 = blockIdx.x * 16;
+  if (l0 + 16 <= j + 1 || l0 >= C.c) return;
+  extern __shared__ zd vs[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int mb = C.mb, c = C.c;
+  const int64_t ld = mb;
+  for (int r = j + tid; r < mb; r += 256) vs[r - j] = C.v[r - j];
+  __syncthreads();
+  const double tau = *C.tau;
+  double* nrm = C.nrm;
+  for (int l = l0 + wave; l < min(l0 + 16, c); l += 4) {
+    if (l <= j) continue;
+    zd* col = C.b + (int64_t)l * ld;
+    double wr = 0, wi = 0;
+    for (int r = j + lane; r < mb; r += 64) {
+      const zd t = zcmul(vs[r - j], col[r]);
+      wr += t.re;
+      wi += t.im;
+    }
+    wr = wave_sum(wr);
+    wi = wave_sum(wi);
+    const zd w = zscale(zmk(wr, wi), tau);
+    double tail = 0;
+    zd first = zmk(0, 0);
+    for (int r = j + lane; r < mb; r += 64) {
+      const zd nv = zsub(col[r], zmul(vs[r - j], w));
+      col[r] = nv;
+      if (r > j) tail += zabs2(nv);
+      else first = nv;
+    }
+    const zd rjl = zmk(__shfl(first.re, 0, 64), __shfl(first.im, 0, 64));
+    const double nw2 = nrm[l] - zabs2(rjl);
+    if (nw2 <= 1e-8 * nrm[c + l]) {
+      tail = wave_sum(tail);
+      if (lane == 0) {
+        nrm[l] = tail;
+        nrm[c + l] = tail;
+      }
+    } else if (lane == 0) {
+      nrm[l] = nw2;
+    }
+  }
+}
+
+void la_cpqr(const CpqrDesc* d_cp, int batch, int max_c, double tol, const int* d_kmin, int init, int* d_work,
              hipStream_t s) {
   if (batch <= 0 || max_c <= 0) return;
   size_t shm = (size_t)max_c * sizeof(zd) + 16;
-  if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void*)k_cpqr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL(k_cpqr, dim3(batch), dim3(CP_NT), shm, s, d_cp, tol, d_kmin, init);
+  if (shm > 64 * 1024) {
+    (void)hipFuncSetAttribute((const void*)k_cpqr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    (void)hipFuncSetAttribute((const void*)k_cpqr_update, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  }
+  if (max_c < PMX_CPQR_MULTI_MIN) {
+    hipLaunchKernelGGL(k_cpqr, dim3(batch), dim3(CP_NT), shm, s, d_cp, tol, d_kmin, init);
+    return;
+  }
+  (void)hipMemsetAsync(d_work, 0, sizeof(int), s);
+  hipLaunchKernelGGL(k_cpqr_init, dim3((max_c + 3) / 4, batch), dim3(256), 0, s, d_cp, init);
+  const int ucols = (max_c + 15) / 16;
+  for (int it = 0; it <= max_c; ++it) {
+    hipLaunchKernelGGL(k_cpqr_pivot, dim3(batch), dim3(256), 0, s, d_cp, tol, d_kmin, d_work);
+    hipLaunchKernelGGL(k_cpqr_update, dim3(ucols, batch), dim3(256), shm, s, d_cp);
+    if ((it & 15) == 15) {
+      int nd = 0;
+      (void)hipMemcpyAsync(&nd, d_work, sizeof(int), hipMemcpyDeviceToHost, s);
+      (void)hipStreamSynchronize(s);
+      if (nd >= batch) break;
+    }
+  }
 }
 
 // T = R11^-1 R12 in place
