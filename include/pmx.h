@@ -81,7 +81,17 @@ typedef struct {
   double rank_mean[32];
   double bytes_factor;       /* device bytes held by the factor */
   double t_factor_ms;        /* wall time of pmx_factor_create (host clock, synchronised) */
-  double t_phase_ms[16];     /* with options.timing: assemble, id, schur, root, other */
+  double t_phase_ms[16];     /* host wall time of phases: 0 self blocks, 1 level compression,
+                                3 top LU */
+  /* with options.timing = 1: per-kernel device time from HIP events around every launch of
+   * the factorisation (index: 0 QR leaf blocks, 1 QR trailing update, 2 LU panel, 3 CPQR
+   * update, 4 CPQR single-workgroup, 5 complex GEMM, 6 small triangular solves, 7 entry
+   * assembly, 8 self blocks), launch counts, and the algorithmic bytes and flops of the
+   * kernels whose work the library counts (0, 1). */
+  double t_kernel_ms[16];
+  int32_t n_kernel_launch[16];
+  double kernel_bytes[16];
+  double kernel_flops[16];
 } pmx_info;
 
 typedef struct pmx_factor pmx_factor;

@@ -13,6 +13,7 @@
 //   [[-(e+ S+ + e- S-), D+ + D-], [-(D*+ + D*-), N+/e+ + N-/e-]].
 #include "assemble.h"
 #include "bessel.h"
+#include "ktimer.h"
 
 struct Pt {
   double x, y, nx, ny, w;
@@ -246,6 +247,7 @@ void asm_diag(DevGeom g, ExtParams e, const DiagDesc* d, int batch, int max_n, c
               const double* dt, hipStream_t s) {
   if (batch <= 0 || max_n <= 0) return;
   dim3 grid((max_n * max_n + 255) / 256, batch);
+  KScope ks(PK_DIAG, s);
   hipLaunchKernelGGL(k_diag_pairs, grid, dim3(256), 0, s, g, e, d, R);
   hipLaunchKernelGGL(k_diag_maue1, grid, dim3(256), 0, s, g, d, dt);
   hipLaunchKernelGGL(k_diag_maue2, grid, dim3(256), 0, s, g, d, dt);
@@ -271,6 +273,7 @@ void asm_entries(DevGeom g, DevProxy p, ExtParams e, const EntryMat* d, int batc
                  int max_b, hipStream_t s) {
   if (batch <= 0 || max_a <= 0 || max_b <= 0) return;
   dim3 grid((max_a + ENT_ROWS - 1) / ENT_ROWS, (max_b + ENT_COLS - 1) / ENT_COLS, batch);
+  KScope ks(PK_ENTRIES, s);
   hipLaunchKernelGGL(k_entries, grid, dim3(256), 0, s, g, p, e, d);
 }
 

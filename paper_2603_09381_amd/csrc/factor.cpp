@@ -33,6 +33,9 @@
 #include "assemble.h"
 #include "la.h"
 #include "plan.h"
+#include "ktimer.h"
+
+thread_local KernelTimer* g_ktimer = nullptr;
 
 namespace {
 
@@ -444,6 +447,9 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
   CpqrDesc* d_cd = tmp.upload(cd, s);
   asm_entries(F->geom(), PT.dev, F->ext(), d_em, nid, maxm, maxc, s);
   la_geqrf_r(d_qd, nid, maxm, maxc, s);
+  for (int q = 0; q < nid; ++q)
+    la_geqrf_work(idm[q], idc[q], &F->info.kernel_bytes[PK_TS_UPDATE], &F->info.kernel_flops[PK_TS_UPDATE],
+                  &F->info.kernel_bytes[PK_TS_LEAF], &F->info.kernel_flops[PK_TS_LEAF]);
   la_cpqr(d_cd, nid, maxc, tol, nullptr, 1, d_work, s);
   std::vector<int> st;
   download(st, stb, 4 * nid, s);
@@ -579,6 +585,8 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
   int* d_info = tmp.alloc<int>(nc);
   HIPCHK(hipMemsetAsync(d_info, 0, nc * sizeof(int), s));
   la_getrf(L.d_lu, nc, L.max_s, d_info, s);
+  for (int t = 0; t < nc; ++t)
+    la_getrf_work(L.s0[t] + L.s1[t], &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
   std::vector<Mat> ym(nc);
   for (int t = 0; t < nc; ++t) {
     int sz = L.s0[t] + L.s1[t];
@@ -672,6 +680,8 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
     int* d_info2 = tmp.alloc<int>(nc);
     HIPCHK(hipMemsetAsync(d_info2, 0, nc * sizeof(int), s));
     la_getrf(d_lm, nc, L.max_k, d_info2, s);
+    for (int t = 0; t < nc; ++t)
+      la_getrf_work(L.k0[t] + L.k1[t], &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
     asm_identity(d_id, nc, L.max_k, s);
     la_getrs(d_lm, d_am, nc, L.max_k, L.max_k, s);
     std::vector<int> info;
@@ -815,6 +825,7 @@ void factor_all(pmx_factor* F, hipStream_t s) {
       int* d_info = tmp.alloc<int>(1);
       HIPCHK(hipMemsetAsync(d_info, 0, sizeof(int), s));
       la_getrf(F->d_lu_root, 1, F->root_s, d_info, s);
+      la_getrf_work(F->root_s, &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
       std::vector<int> info;
       download(info, d_info, 1, s);
       if (info[0]) fail(PMX_ESINGULAR, "zero pivot in the LU of the top compressed system");
@@ -1179,11 +1190,23 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
     std::memset(&F->info, 0, sizeof(F->info));
     F->opts = o;
     const double t0 = now_ms();
+    std::unique_ptr<KernelTimer> kt;
+    if (o.timing) {
+      kt.reset(new KernelTimer());
+      g_ktimer = kt.get();
+    }
+    struct Reset {
+      ~Reset() { g_ktimer = nullptr; }
+    } reset_timer;
     make_plan(geom, o, F->plan);
     upload_geometry(F.get(), geom, s);
     factor_all(F.get(), s);
     fill_info(F.get());
     F->info.t_factor_ms = now_ms() - t0;
+    if (kt) {
+      HIPCHK(hipStreamSynchronize(s));
+      kt->collect(F->info.t_kernel_ms, F->info.n_kernel_launch);
+    }
     *out = F.release();
   });
 }

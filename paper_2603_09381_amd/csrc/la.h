@@ -56,12 +56,16 @@ enum { OP_N = 0, OP_T = 1, OP_C = 2 };
 // C = alpha op(A) op(B) + beta C for a device list of GemmArgs.
 void la_zgemm_list(int opa, int opb, const GemmArgs* d_list, int batch, int max_m, int max_n,
                    zd alpha, zd beta, hipStream_t s);
+// algorithmic bytes and flops of the LU panels of one n x n factorisation
+void la_getrf_work(int n, double* bytes, double* flops);
 // In-place LU with partial pivoting. info[b] = first zero pivot (1-based) or 0.
 void la_getrf(const LuDesc* d_lu, int batch, int max_n, int* d_info, hipStream_t s);
 // Solve A X = B in place in B (n x nrhs per entry) using the LU of getrf.
 void la_getrs(const LuDesc* d_lu, const Mat* d_b, int batch, int max_n, int max_nrhs, hipStream_t s);
 // Householder QR of each M (destroyed); writes R (upper, zero below) to QrDesc::r.
 int64_t la_geqrf_workspace(int m);
+// algorithmic bytes and flops of the trailing updates and the leaf factorisations
+void la_geqrf_work(int m, int c, double* upd_bytes, double* upd_flops, double* leaf_bytes, double* leaf_flops);
 void la_geqrf_r(const QrDesc* d_qr, int batch, int max_m, int max_c, hipStream_t s);
 // Matrices with max_c >= PMX_CPQR_MULTI_MIN columns use the multi-workgroup variant, which
 // needs d_work (one device int) and synchronises the stream every 16 steps.

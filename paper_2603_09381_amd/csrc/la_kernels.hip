@@ -13,6 +13,7 @@
 // Reflectors are Hermitian: H = I - tau v v^H with real tau, so |R_jj| equals the
 // norm of the trailing part of the pivot column, which is what the threshold tests.
 #include "la.h"
+#include "ktimer.h"
 
 #include <algorithm>
 
@@ -185,6 +186,7 @@ template <int OPA, int OPB, class F>
 static void launch_zgemm(F f, int batch, int max_m, int max_n, zd alpha, zd beta, hipStream_t s) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
   dim3 grid((max_m + 63) / 64, (max_n + 63) / 64, batch);
+  KScope ks(PK_ZGEMM, s);
   hipLaunchKernelGGL((k_zgemm<OPA, OPB, F>), grid, dim3(256), 0, s, f, alpha, beta);
 }
 
@@ -267,6 +269,7 @@ template <bool UPPER, bool UNIT, class F>
 static void launch_trsm_small(F f, int batch, int max_nrhs, hipStream_t s) {
   if (batch <= 0 || max_nrhs <= 0) return;
   dim3 grid((max_nrhs + 63) / 64, batch);
+  KScope ks(PK_TRSM, s);
   hipLaunchKernelGGL((k_trsm_small<UPPER, UNIT, F>), grid, dim3(64), 0, s, f);
 }
 
@@ -377,7 +380,10 @@ struct FLuUpd {
 void la_getrf(const LuDesc* d_lu, int batch, int max_n, int* d_info, hipStream_t s) {
   if (batch <= 0 || max_n <= 0) return;
   for (int j0 = 0; j0 < max_n; j0 += PMX_LU_NB) {
-    hipLaunchKernelGGL(k_getrf_panel, dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+    {
+      KScope ks(PK_GETRF_PANEL, s);
+      hipLaunchKernelGGL(k_getrf_panel, dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+    }
     hipLaunchKernelGGL(k_laswp_panel, dim3((max_n + 255) / 256, batch), dim3(256), 0, s, d_lu, j0);
     int rem = max_n - j0 - PMX_LU_NB;
     if (rem > 0) {
@@ -869,9 +875,14 @@ void la_geqrf_r(const QrDesc* d_qr, int batch, int max_m, int max_c, hipStream_t
     const int nc = max_c - j0 - 1;
     for (int L = 0; L < PMX_TS_MAXLEV; ++L) {
       const int nb = (mr + PMX_TS_BR - 1) / PMX_TS_BR;
-      hipLaunchKernelGGL(k_ts_leaf, dim3(nb, batch), dim3(PMX_TS_BR), 0, s, d_qr, j0, L);
-      if (nc > 0)
+      {
+        KScope ks(PK_TS_LEAF, s);
+        hipLaunchKernelGGL(k_ts_leaf, dim3(nb, batch), dim3(PMX_TS_BR), 0, s, d_qr, j0, L);
+      }
+      if (nc > 0) {
+        KScope ks(PK_TS_UPDATE, s);
         hipLaunchKernelGGL(k_ts_update, dim3((nc + 63) / 64, nb, batch), dim3(256), 0, s, d_qr, j0, L);
+      }
       if (nb <= 1) break;
       mr = nb * PMX_QR_NB;
     }
@@ -1188,6 +1199,7 @@ void la_cpqr(const CpqrDesc* d_cp, int batch, int max_c, double tol, const int* 
     (void)hipFuncSetAttribute((const void*)k_cpqr_update, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   }
   if (max_c < PMX_CPQR_MULTI_MIN) {
+    KScope ks(PK_CPQR, s);
     hipLaunchKernelGGL(k_cpqr, dim3(batch), dim3(CP_NT), shm, s, d_cp, tol, d_kmin, init);
     return;
   }
@@ -1196,7 +1208,10 @@ void la_cpqr(const CpqrDesc* d_cp, int batch, int max_c, double tol, const int* 
   const int ucols = (max_c + 15) / 16;
   for (int it = 0; it <= max_c; ++it) {
     hipLaunchKernelGGL(k_cpqr_pivot, dim3(batch), dim3(256), 0, s, d_cp, tol, d_kmin, d_work);
-    hipLaunchKernelGGL(k_cpqr_update, dim3(ucols, batch), dim3(256), shm, s, d_cp);
+    {
+      KScope ks(PK_CPQR_UPDATE, s);
+      hipLaunchKernelGGL(k_cpqr_update, dim3(ucols, batch), dim3(256), shm, s, d_cp);
+    }
     if ((it & 15) == 15) {
       int nd = 0;
       (void)hipMemcpyAsync(&nd, d_work, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -1256,5 +1271,44 @@ void la_cpqr_tsolve(const CpqrDesc* d_cp, const int* d_k, int batch, int max_k, 
     int j0 = bk * PMX_LU_NB;
     launch_trsm_small<true, false>(FTTrsm{d_cp, d_k, j0}, batch, max_c, s);
     if (j0 > 0) launch_zgemm<OP_N, OP_N>(FTUpd{d_cp, d_k, j0}, batch, j0, max_c, zmk(-1, 0), zmk(1, 0), s);
+  }
+}
+
+// Algorithmic work of the QR kernels for one m x c matrix, mirroring the launch sequence.
+// Trailing update of an nrb x nc block by jb reflectors: bytes 16 (2 nrb nc + 2 nrb jb)
+// (the block read and written once, V and V T^H read once), flops 16 nrb nc jb (two
+// complex products).  Leaf factorisation of an nrb x jb block: bytes 16 (2 nrb jb + 2 nrb
+// PMX_QR_NB) (panel read and written, V and V T^H written), flops 8 nrb jb^2.
+void la_geqrf_work(int m, int c, double* upd_bytes, double* upd_flops, double* leaf_bytes, double* leaf_flops) {
+  const int kmax = std::min(m, c);
+  for (int j0 = 0; j0 < kmax; j0 += PMX_QR_NB) {
+    const int jb = std::min(PMX_QR_NB, kmax - j0);
+    const int nc = c - j0 - jb;
+    int mr = m - j0;
+    for (int L = 0; L < PMX_TS_MAXLEV; ++L) {
+      const int nb = (mr + PMX_TS_BR - 1) / PMX_TS_BR;
+      for (int b = 0; b < nb; ++b) {
+        const double nrb = std::min(PMX_TS_BR, mr - b * PMX_TS_BR);
+        *leaf_bytes += 16.0 * (2 * nrb * jb + 2 * nrb * PMX_QR_NB);
+        *leaf_flops += 8.0 * nrb * jb * jb;
+        if (nc > 0) {
+          *upd_bytes += 16.0 * (2 * nrb * nc + 2 * nrb * jb);
+          *upd_flops += 16.0 * nrb * nc * jb;
+        }
+      }
+      if (nb <= 1) break;
+      mr = nb * jb;
+    }
+  }
+}
+
+// Algorithmic work of the LU panels of one n x n factorisation: each panel of jb columns
+// is read and written once (bytes 32 (n - j0) jb) and its column steps cost 8 (n - c - 1)
+// (j0 + jb - c - 1) flops for the rank-one updates.
+void la_getrf_work(int n, double* bytes, double* flops) {
+  for (int j0 = 0; j0 < n; j0 += PMX_LU_NB) {
+    const int jb = std::min(PMX_LU_NB, n - j0);
+    *bytes += 32.0 * (double)(n - j0) * jb;
+    for (int c = j0; c < j0 + jb; ++c) *flops += 8.0 * (double)(n - c - 1) * (j0 + jb - c - 1);
   }
 }

@@ -54,7 +54,12 @@ class Info(C.Structure):
     _fields_ = [("levels", C.c_int32), ("root_size", C.c_int32), ("n_unknowns", C.c_int32),
                 ("cells", C.c_int32 * 32), ("rank_min", C.c_int32 * 32), ("rank_max", C.c_int32 * 32),
                 ("rank_mean", C.c_double * 32), ("bytes_factor", C.c_double),
-                ("t_factor_ms", C.c_double), ("t_phase_ms", C.c_double * 16)]
+                ("t_factor_ms", C.c_double), ("t_phase_ms", C.c_double * 16),
+                ("t_kernel_ms", C.c_double * 16), ("n_kernel_launch", C.c_int32 * 16),
+                ("kernel_bytes", C.c_double * 16), ("kernel_flops", C.c_double * 16)]
+
+KERNEL_NAMES = ["k_ts_leaf", "k_ts_update", "k_getrf_panel", "k_cpqr_update", "k_cpqr", "k_zgemm",
+                "k_trsm_small", "k_entries", "k_diag_pairs/maue"]
 
 
 def load(path=None):
