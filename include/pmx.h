@@ -67,8 +67,17 @@ typedef struct {
   int32_t proxy_min;    /* minimum number of proxy points (exact number if proxy_rule = 1) */
   int32_t proxy_rule;   /* 0: radius max(ratio r_c, 0.9 rho_far), adaptive count; 1: fixed */
   int32_t near_rule;    /* 0: edge-adjacent cells + geometric test (Sec. 4); 1: geometric */
-  int32_t precision;    /* 0: FP64 throughout */
+  int32_t precision;    /* 0: FP64 throughout.  1: mixed: the factor (assembly storage,
+                           QR, CPQR data, LU, Schur products) in complex FP32 with FP64 column
+                           norms and pivot decisions, used as the inner solver of iterative
+                           refinement against the FP64 operator (self blocks by the FP64
+                           Kress rule, the rest evaluated on the fly); id_tol >= 1e-6.
+                           2: the FP64 factor
+                           (typically at a looser id_tol) refined the same way */
   int32_t timing;       /* 1: record per-phase device times in pmx_info */
+  int32_t ir_max_iter;  /* precision 1, 2: at most this many refinement steps (1..100) */
+  double ir_tol;        /* precision 1, 2: stop when max over right-hand sides of
+                           |f - A x| / |f| <= ir_tol (2-norms) */
   int32_t reserved[8];
 } pmx_options;
 
@@ -86,18 +95,25 @@ typedef struct {
   /* with options.timing = 1: per-kernel device time from HIP events around every launch of
    * the factorisation (index: 0 QR leaf blocks, 1 QR trailing update, 2 LU panel, 3 CPQR
    * update, 4 CPQR single-workgroup, 5 complex GEMM, 6 small triangular solves, 7 entry
-   * assembly, 8 self blocks), launch counts, and the algorithmic bytes and flops of the
-   * kernels whose work the library counts (0, 1). */
+   * assembly, 8 self blocks, 9 dense operator apply of refinement residuals, recorded by
+   * solves), launch counts, and the algorithmic bytes and flops of the kernels whose work
+   * the library counts (0, 1, 2). */
   double t_kernel_ms[16];
   int32_t n_kernel_launch[16];
   double kernel_bytes[16];
   double kernel_flops[16];
+  /* last solve: host wall time (synchronised), refinement steps and the final relative
+   * residual max_r |f - A x| / |f| (precision 1, 2; 0 for precision 0) */
+  double t_solve_ms;
+  int32_t ir_iterations;
+  double ir_residual;
+  double ir_history[16];     /* relative residual after each of the first 16 steps */
 } pmx_info;
 
 typedef struct pmx_factor pmx_factor;
 
 /* Fills defaults: id_tol 1e-10, proxy_ratio 1.5, proxy_min 0, proxy_rule 0, near_rule 0,
- * precision 0, timing 0. */
+ * precision 0, timing 0, ir_max_iter 10, ir_tol 1e-10. */
 void pmx_options_default(pmx_options* o);
 
 /* Builds the plan and the whole compressed factorisation on `hip_stream`.  Returns when
@@ -115,7 +131,9 @@ pmx_status pmx_solve_plane_waves(pmx_factor* f, int32_t nrhs, const double* angl
                                  void* hip_stream);
 
 /* Densities for a general right-hand side f (device, same layout as dens, holding
- * (-u^I_j; -q^I_j) per inclusion).  f and dens may not overlap. */
+ * (-u^I_j; -q^I_j) per inclusion).  f and dens may not overlap.
+ * Both solves: with precision 1 or 2, PMX_ENOTCONV when refinement stops above ir_tol (dens
+ * then holds the last iterate). */
 pmx_status pmx_solve(pmx_factor* f, int32_t nrhs, const pmx_c64* rhs, pmx_c64* dens, void* hip_stream);
 
 /* Far-field pattern u_inf(theta) of the scattered field, u^S ~ e^{ikr}/sqrt(r) u_inf:

@@ -14,6 +14,10 @@
 extern "C" {
 #endif
 
+typedef struct {
+  float re, im;
+} pmx_c32;
+
 /* J0, J1, Y0, Y1 at z[i] > 0 (device, n values); out (device) [4][n]. */
 pmx_status pmx_probe_bessel(const double* z, int64_t n, double* out, void* stream);
 
@@ -34,11 +38,19 @@ pmx_status pmx_probe_entries(const pmx_geometry* geom, int32_t nr, const int32_t
 pmx_status pmx_probe_zgemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t opa, int32_t opb,
                            const pmx_c64* A, const pmx_c64* B, pmx_c64* C, void* stream);
 
+/* As pmx_probe_zgemm in complex FP32 (the FP32 MFMA kernel of the mixed-precision factor). */
+pmx_status pmx_probe_cgemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t opa, int32_t opb,
+                           const pmx_c32* A, const pmx_c32* B, pmx_c32* C, void* stream);
+
 /* LU with partial pivoting of a batch of n x n matrices (device, in place) and solve with
  * nrhs right-hand sides B [batch][n x nrhs] (device, in place).  ipiv (device) [batch][n].
  * info (host) [batch]: first zero pivot (1-based) or 0. */
 pmx_status pmx_probe_lu_solve(int32_t batch, int32_t n, pmx_c64* A, int32_t* ipiv, int32_t nrhs,
                               pmx_c64* B, int32_t* info, void* stream);
+
+/* As pmx_probe_lu_solve in complex FP32. */
+pmx_status pmx_probe_lu_solve_c32(int32_t batch, int32_t n, pmx_c32* A, int32_t* ipiv, int32_t nrhs,
+                                  pmx_c32* B, int32_t* info, void* stream);
 
 /* Interpolative decomposition of a batch of m x c matrices (device, destroyed): QR, then
  * column-pivoted QR with threshold rank |R_jj| > tol |R_11|; k = max(rank, kmin[b]) pivots
@@ -47,6 +59,17 @@ pmx_status pmx_probe_lu_solve(int32_t batch, int32_t n, pmx_c64* A, int32_t* ipi
  * kmin (host) [batch] or NULL. */
 pmx_status pmx_probe_id(int32_t batch, int32_t m, int32_t c, pmx_c64* M, double tol,
                         const int32_t* kmin, int32_t* piv, int32_t* rank, pmx_c64* T, void* stream);
+
+/* As pmx_probe_id in complex FP32 (column norms, |R_11| and pivot decisions stay FP64). */
+pmx_status pmx_probe_id_c32(int32_t batch, int32_t m, int32_t c, pmx_c32* M, double tol,
+                            const int32_t* kmin, int32_t* piv, int32_t* rank, pmx_c32* T, void* stream);
+
+/* y = A x for the whole FP64 PMCHWT (Omit) matrix of Sec. 2.2 (self blocks by the Kress
+ * rule, the exterior blocks between inclusions evaluated on the fly), the operator of the
+ * refinement residual: x, y (device) [nrhs][2 node_off[m]] in the density layout of
+ * pmx_solve; x and y may not overlap. */
+pmx_status pmx_probe_apply(const pmx_geometry* geom, int32_t nrhs, const pmx_c64* x, pmx_c64* y,
+                           void* stream);
 
 /* The quadtree plan, host only (no GPU): per level the number of cells; per cell its
  * centre, radius, proxy radius, proxy count and near list.  Buffers (host) are filled up

@@ -1,4 +1,5 @@
-// Kernel-matrix assembly, right-hand sides, gathers and the far field (FP64, gfx950).
+// Kernel-matrix assembly, right-hand sides, gathers and the far field (gfx950).  Matrix
+// entries are always evaluated in FP64; the templated launchers store them as cx<R>.
 #pragma once
 #include "pmx_common.h"
 
@@ -27,14 +28,16 @@ struct ExtParams {
 __host__ __device__ inline int pmx_code_node(int node, int type) { return 2 * node + type; }
 __host__ __device__ inline int pmx_code_proxy(int p, int type) { return -(2 * p + type) - 1; }
 
-struct EntryMat {   // out[i + j ld] = entry(list a[i], list b[j])
+template <class R>
+struct EntryMatT {  // out[i + j ld] = entry(list a[i], list b[j]), computed in FP64, stored as R
   const int* a;
   const int* b;
   int na, nb;
-  zd* out;
+  cx<R>* out;
   int64_t ld;
   int a_is_target;  // 1: a = targets (rows of A), b = sources; 0: swapped (transposed block)
 };
+typedef EntryMatT<double> EntryMat;
 
 struct DiagDesc {   // one inclusion's self block
   int node0, n;
@@ -45,19 +48,21 @@ struct DiagDesc {   // one inclusion's self block
   zd* scratch2;     // n x n
 };
 
-struct ParentDesc { // gathered parent block of the compressed system
+template <class R>
+struct ParentDescT { // gathered parent block of the compressed system
   const int* rcode;
   const int* ccode;
   const int* rloc;  // child slot << 24 | local index (rows)
   const int* cloc;
   int s;
-  zd* out;          // s x s
-  const zd* at[4];  // children's compressed blocks
-  int kc[4];        // their sizes
+  cx<R>* out;          // s x s
+  const cx<R>* at[4];  // children's compressed blocks
+  int kc[4];           // their sizes
 };
 
-struct Mat2 {       // plain matrix view (n x n, leading dimension ld)
-  zd* p;
+template <class R>
+struct Mat2T {      // plain matrix view (n x n, leading dimension ld)
+  cx<R>* p;
   int64_t ld;
   int n;
 };
@@ -67,12 +72,14 @@ struct RowSrc {     // source of one gathered row
   int64_t ld;       // distance between consecutive columns
 };
 
-struct GatherDesc {
+template <class R>
+struct GatherDescT {
   const RowSrc* src;
   int nrows, ncols;
-  zd* dst;
+  cx<R>* dst;
   int64_t ld;
 };
+typedef GatherDescT<double> GatherDesc;
 
 void asm_geometry(const double* dx, const double* dy, const double* ddx, const double* ddy,
                   const int* owner, const int64_t* node_off, double* nx, double* ny, double* w,
@@ -81,34 +88,67 @@ void asm_tables(const int* ns, const int* tbl_off, int ntbl, int max_n, double* 
                 hipStream_t s);
 void asm_diag(DevGeom g, ExtParams e, const DiagDesc* d, int batch, int max_n, const double* R,
               const double* dt, hipStream_t s);
-void asm_entries(DevGeom g, DevProxy p, ExtParams e, const EntryMat* d, int batch, int max_a,
-                 int max_b, hipStream_t s);
-void asm_parent(DevGeom g, ExtParams e, const ParentDesc* d, int batch, int max_s, hipStream_t s);
+template <class R>
+void asm_entries(DevGeom g, DevProxy p, ExtParams e, const EntryMatT<R>* d, int batch, int max_a, int max_b,
+                 hipStream_t s);
+template <class R>
+void asm_parent(DevGeom g, ExtParams e, const ParentDescT<R>* d, int batch, int max_s, hipStream_t s);
 // leaf right-hand sides: rows [0,n) = -u^I, [n,2n) = -q^I per cell, column per angle
 void asm_incident(DevGeom g, ExtParams e, const int* cell_node0, const int* cell_n,
                   const int64_t* cell_off, int ncell, int max_n, const double* angles, int nrhs,
                   zd* f, hipStream_t s);
-// dst[i + c ld] = src[row_i.off + c row_i.ld] for i < nrows, c < ncols of each entry
-void asm_gather(const zd* src, const GatherDesc* d, int batch, int max_rows, int max_cols,
-                hipStream_t s);
+// dst[i + c ld] = src[row_i.off + c row_i.ld] for i < nrows, c < ncols of each entry;
+// the source may be of another real type (converted), and with acc = 1 the value is added
+// to dst instead of stored
+template <class RS, class RD>
+void asm_gather(const cx<RS>* src, const GatherDescT<RD>* d, int batch, int max_rows, int max_cols, hipStream_t s,
+                int acc = 0);
 // batched identity: a[i + j ld] = (i == j) for an n x n matrix per entry
-void asm_identity(const Mat2* d, int batch, int max_n, hipStream_t s);
-void asm_zero(zd* p, int64_t n, hipStream_t s);
+template <class R>
+void asm_identity(const Mat2T<R>* d, int batch, int max_n, hipStream_t s);
+template <class R>
+void asm_zero(cx<R>* p, int64_t n, hipStream_t s);
+// dst[i] = src[i] converted to the destination's real type
+template <class RS, class RD>
+void asm_convert(const cx<RS>* src, cx<RD>* dst, int64_t n, hipStream_t s);
 // far field: out[r * ndir + t] for densities dens (ld = 2 * n_nodes, per inclusion [q; u])
 void asm_far_field(DevGeom g, ExtParams e, const int* owner, const int64_t* node_off,
                    const zd* dens, int nrhs, const double* dirs, int ndir, zd* out, hipStream_t s);
 // build the explicit L = blockdiag(Z_0^T, Z_1^T) (s x K) of a batch of cells
-struct LDesc {
-  zd* out;          // s x K, ld s
+template <class R>
+struct LDescT {
+  cx<R>* out;          // s x K, ld s
   int s0, s1, k0, k1;
-  const int* piv0;  // row-ID pivots, type 0 and 1
+  const int* piv0;     // row-ID pivots, type 0 and 1
   const int* piv1;
-  const zd* t0;     // T blocks: t[i + j ldt]
-  const zd* t1;
+  const cx<R>* t0;     // T blocks: t[i + j ldt]
+  const cx<R>* t1;
   int ldt0, ldt1;
 };
-void asm_build_l(const LDesc* d, int batch, int max_s, int max_k, hipStream_t s);
-// y[i] += x[i] for complex arrays (used for the residual of iterative refinement)
+template <class R>
+void asm_build_l(const LDescT<R>* d, int batch, int max_s, int max_k, hipStream_t s);
+// y[i] += a x[i] for complex FP64 arrays
 void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s);
+// Dense FP64 operator apply between different inclusions (on the fly, exterior kernels),
+// for a block of right-hand sides in the density layout (ld = 2 n_nodes, per inclusion
+// [q; u]); partial sums of nsplit source ranges go to part [nsplit][nrhs][ld].
+struct ApplyArgs {
+  const double *x, *y, *nx, *ny, *w;
+  const int* owner;
+  const int64_t* node_off;
+  int n_nodes;
+  double k, eps;
+  const zd* xin;
+  int nrhs;
+  int64_t ld;
+  zd* part;
+};
+int apply_splits(int n_nodes, int nrhs);
+void asm_apply_off(const ApplyArgs& a, int nsplit, hipStream_t s);
+// out = sf f + sa (ydiag + sum_p part[p]) elementwise over total entries (f may be NULL)
+void asm_apply_finish(const zd* f, const zd* ydiag, const zd* part, int nsplit, int64_t total, double sf, double sa,
+                      zd* out, hipStream_t s);
+// squared column norms: part[c nblk + b], summed over b by the caller
+void asm_colnorm2(const zd* a, int64_t n, int ncol, int64_t ld, int nblk, double* part, hipStream_t s);
 // J0, J1, Y0, Y1 at z[i]: out[f * n + i]
 void asm_probe_bessel(const double* z, int64_t n, double* out, hipStream_t s);

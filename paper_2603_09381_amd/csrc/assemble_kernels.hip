@@ -256,8 +256,9 @@ void asm_diag(DevGeom g, ExtParams e, const DiagDesc* d, int batch, int max_n, c
 // ---------------------------------------------------------------------------------
 #define ENT_ROWS 64
 #define ENT_COLS 16
-__global__ __launch_bounds__(256) void k_entries(DevGeom g, DevProxy p, ExtParams e, const EntryMat* ms) {
-  const EntryMat m = ms[blockIdx.z];
+template <class R>
+__global__ __launch_bounds__(256) void k_entries(DevGeom g, DevProxy p, ExtParams e, const EntryMatT<R>* ms) {
+  const EntryMatT<R> m = ms[blockIdx.z];
   const int i = blockIdx.x * ENT_ROWS + (threadIdx.x & 63);
   const int j0 = blockIdx.y * ENT_COLS + (threadIdx.x >> 6);
   if (blockIdx.x * ENT_ROWS >= m.na || blockIdx.y * ENT_COLS >= m.nb) return;
@@ -265,40 +266,45 @@ __global__ __launch_bounds__(256) void k_entries(DevGeom g, DevProxy p, ExtParam
   const Pt pa = fetch_pt(g, p, m.a[i]);
   for (int j = j0; j < min(m.nb, (int)(blockIdx.y + 1) * ENT_COLS); j += 4) {
     const Pt pb = fetch_pt(g, p, m.b[j]);
-    m.out[i + (int64_t)j * m.ld] = m.a_is_target ? omit_entry(pa, pb, e) : omit_entry(pb, pa, e);
+    const zd v = m.a_is_target ? omit_entry(pa, pb, e) : omit_entry(pb, pa, e);
+    m.out[i + (int64_t)j * m.ld] = cmk<R>(v.re, v.im);
   }
 }
 
-void asm_entries(DevGeom g, DevProxy p, ExtParams e, const EntryMat* d, int batch, int max_a,
-                 int max_b, hipStream_t s) {
+template <class R>
+void asm_entries(DevGeom g, DevProxy p, ExtParams e, const EntryMatT<R>* d, int batch, int max_a, int max_b,
+                 hipStream_t s) {
   if (batch <= 0 || max_a <= 0 || max_b <= 0) return;
   dim3 grid((max_a + ENT_ROWS - 1) / ENT_ROWS, (max_b + ENT_COLS - 1) / ENT_COLS, batch);
   KScope ks(PK_ENTRIES, s);
-  hipLaunchKernelGGL(k_entries, grid, dim3(256), 0, s, g, p, e, d);
+  hipLaunchKernelGGL(k_entries<R>, grid, dim3(256), 0, s, g, p, e, d);
 }
 
-__global__ __launch_bounds__(256) void k_parent(DevGeom g, ExtParams e, const ParentDesc* ds) {
-  const ParentDesc d = ds[blockIdx.y];
+template <class R>
+__global__ __launch_bounds__(256) void k_parent(DevGeom g, ExtParams e, const ParentDescT<R>* ds) {
+  const ParentDescT<R> d = ds[blockIdx.y];
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)d.s * d.s) return;
   const int a = (int)(idx % d.s), b = (int)(idx / d.s);
   const int ra = d.rloc[a], cb = d.cloc[b];
   const int sa = ra >> 24, sb = cb >> 24;
-  zd v;
+  cx<R> v;
   if (sa == sb) {
     const int la = ra & 0xFFFFFF, lb = cb & 0xFFFFFF;
     v = d.at[sa][la + (int64_t)lb * d.kc[sa]];
   } else {
     DevProxy none{nullptr, nullptr, nullptr, nullptr, nullptr};
-    v = omit_entry(fetch_pt(g, none, d.rcode[a]), fetch_pt(g, none, d.ccode[b]), e);
+    const zd w = omit_entry(fetch_pt(g, none, d.rcode[a]), fetch_pt(g, none, d.ccode[b]), e);
+    v = cmk<R>(w.re, w.im);
   }
   d.out[idx] = v;
 }
 
-void asm_parent(DevGeom g, ExtParams e, const ParentDesc* d, int batch, int max_s, hipStream_t s) {
+template <class R>
+void asm_parent(DevGeom g, ExtParams e, const ParentDescT<R>* d, int batch, int max_s, hipStream_t s) {
   if (batch <= 0 || max_s <= 0) return;
   int64_t tot = (int64_t)max_s * max_s;
-  hipLaunchKernelGGL(k_parent, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, s, g, e, d);
+  hipLaunchKernelGGL(k_parent<R>, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, s, g, e, d);
 }
 
 // ---------------------------------------------------------------------------------
@@ -335,43 +341,70 @@ void asm_incident(DevGeom g, ExtParams e, const int* cell_node0, const int* cell
                      angles, nrhs, f);
 }
 
-__global__ void k_gather(const zd* src, const GatherDesc* ds) {
-  const GatherDesc d = ds[blockIdx.z];
+template <class RS, class RD, bool ACC>
+__global__ void k_gather(const cx<RS>* src, const GatherDescT<RD>* ds) {
+  const GatherDescT<RD> d = ds[blockIdx.z];
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
   const int c = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (i >= d.nrows || c >= d.ncols) return;
   const RowSrc rs = d.src[i];
-  d.dst[i + (int64_t)c * d.ld] = src[rs.off + (int64_t)c * rs.ld];
+  const cx<RS> v = src[rs.off + (int64_t)c * rs.ld];
+  cx<RD>* o = d.dst + i + (int64_t)c * d.ld;
+  if (ACC)
+    *o = cmk<RD>(o->re + (RD)v.re, o->im + (RD)v.im);
+  else
+    *o = cmk<RD>((RD)v.re, (RD)v.im);
 }
 
-void asm_gather(const zd* src, const GatherDesc* d, int batch, int max_rows, int max_cols, hipStream_t s) {
+template <class RS, class RD>
+void asm_gather(const cx<RS>* src, const GatherDescT<RD>* d, int batch, int max_rows, int max_cols, hipStream_t s,
+                int acc) {
   if (batch <= 0 || max_rows <= 0 || max_cols <= 0) return;
   dim3 grid((max_rows + 63) / 64, (max_cols + 3) / 4, batch);
-  hipLaunchKernelGGL(k_gather, grid, dim3(256), 0, s, src, d);
+  if (acc)
+    hipLaunchKernelGGL((k_gather<RS, RD, true>), grid, dim3(256), 0, s, src, d);
+  else
+    hipLaunchKernelGGL((k_gather<RS, RD, false>), grid, dim3(256), 0, s, src, d);
 }
 
-__global__ void k_identity(const Mat2* ds) {
-  const Mat2 d = ds[blockIdx.y];
+template <class R>
+__global__ void k_identity(const Mat2T<R>* ds) {
+  const Mat2T<R> d = ds[blockIdx.y];
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)d.n * d.n) return;
   const int i = (int)(e % d.n), j = (int)(e / d.n);
-  d.p[i + j * d.ld] = zmk(i == j ? 1.0 : 0.0, 0.0);
+  d.p[i + j * d.ld] = cmk<R>(i == j ? 1 : 0, 0);
 }
 
-void asm_identity(const Mat2* d, int batch, int max_n, hipStream_t s) {
+template <class R>
+void asm_identity(const Mat2T<R>* d, int batch, int max_n, hipStream_t s) {
   if (batch <= 0 || max_n <= 0) return;
   int64_t tot = (int64_t)max_n * max_n;
-  hipLaunchKernelGGL(k_identity, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_identity<R>, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, s, d);
 }
 
-__global__ void k_zero(zd* p, int64_t n) {
+template <class R>
+__global__ void k_zero(cx<R>* p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = zmk(0, 0);
+  if (i < n) p[i] = cmk<R>(0, 0);
 }
 
-void asm_zero(zd* p, int64_t n, hipStream_t s) {
+template <class R>
+void asm_zero(cx<R>* p, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  hipLaunchKernelGGL(k_zero<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+}
+
+template <class RS, class RD>
+__global__ void k_convert(const cx<RS>* src, cx<RD>* dst, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = cmk<RD>((RD)src[i].re, (RD)src[i].im);
+}
+
+template <class RS, class RD>
+void asm_convert(const cx<RS>* src, cx<RD>* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_convert<RS, RD>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
 }
 
 __global__ void k_axpy(zd* y, const zd* x, zd a, int64_t n) {
@@ -438,32 +471,34 @@ void asm_far_field(DevGeom g, ExtParams e, const int* owner, const int64_t* node
 }
 
 // ---------------------------------------------------------------------------------
-__global__ void k_build_l(const LDesc* ds) {
-  const LDesc d = ds[blockIdx.z];
+template <class R>
+__global__ void k_build_l(const LDescT<R>* ds) {
+  const LDescT<R> d = ds[blockIdx.z];
   const int type = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int sb = type ? d.s1 : d.s0;
   if (j >= sb) return;
   const int kb = type ? d.k1 : d.k0;
   const int* piv = type ? d.piv1 : d.piv0;
-  const zd* t = type ? d.t1 : d.t0;
+  const cx<R>* t = type ? d.t1 : d.t0;
   const int ldt = type ? d.ldt1 : d.ldt0;
   const int off_r = type ? d.s0 : 0;
   const int off_c = type ? d.k0 : 0;
   const int64_t s = d.s0 + d.s1;
   const int row = off_r + piv[j];
   if (j < kb) {
-    d.out[row + (int64_t)(off_c + j) * s] = zmk(1, 0);
+    d.out[row + (int64_t)(off_c + j) * s] = cmk<R>(1, 0);
   } else {
     for (int i = 0; i < kb; ++i) d.out[row + (int64_t)(off_c + i) * s] = t[i + (int64_t)(j - kb) * ldt];
   }
 }
 
-void asm_build_l(const LDesc* d, int batch, int max_s, int max_k, hipStream_t s) {
+template <class R>
+void asm_build_l(const LDescT<R>* d, int batch, int max_s, int max_k, hipStream_t s) {
   (void)max_k;
   if (batch <= 0 || max_s <= 0) return;
   dim3 grid((max_s + 127) / 128, 2, batch);
-  hipLaunchKernelGGL(k_build_l, grid, dim3(128), 0, s, d);
+  hipLaunchKernelGGL(k_build_l<R>, grid, dim3(128), 0, s, d);
 }
 
 __global__ void k_probe_bessel(const double* z, int64_t n, double* out) {
@@ -480,3 +515,21 @@ void asm_probe_bessel(const double* z, int64_t n, double* out, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_probe_bessel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, n, out);
 }
+
+// explicit instantiations: storage in complex FP64 and complex FP32
+#define PMX_ASM_INST(R)                                                                                    \
+  template void asm_entries<R>(DevGeom, DevProxy, ExtParams, const EntryMatT<R>*, int, int, int, hipStream_t); \
+  template void asm_parent<R>(DevGeom, ExtParams, const ParentDescT<R>*, int, int, hipStream_t);          \
+  template void asm_identity<R>(const Mat2T<R>*, int, int, hipStream_t);                                  \
+  template void asm_zero<R>(cx<R>*, int64_t, hipStream_t);                                                \
+  template void asm_build_l<R>(const LDescT<R>*, int, int, int, hipStream_t);
+PMX_ASM_INST(double)
+PMX_ASM_INST(float)
+#undef PMX_ASM_INST
+template void asm_gather<double, double>(const zd*, const GatherDescT<double>*, int, int, int, hipStream_t, int);
+template void asm_gather<float, float>(const zf*, const GatherDescT<float>*, int, int, int, hipStream_t, int);
+template void asm_gather<double, float>(const zd*, const GatherDescT<float>*, int, int, int, hipStream_t, int);
+template void asm_gather<float, double>(const zf*, const GatherDescT<double>*, int, int, int, hipStream_t, int);
+template void asm_convert<double, float>(const zd*, zf*, int64_t, hipStream_t);
+template void asm_convert<float, double>(const zf*, zd*, int64_t, hipStream_t);
+template void asm_convert<double, double>(const zd*, zd*, int64_t, hipStream_t);

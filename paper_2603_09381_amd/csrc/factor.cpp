@@ -115,7 +115,8 @@ double now_ms() {
 
 }  // namespace
 
-// Data kept for one compressed level.
+// Data kept for one compressed level, in the factor's real type R.
+template <class R>
 struct LevelData {
   int ncell = 0;
   std::vector<int> s0, s1, k0, k1;            // active sizes and skeleton sizes per type
@@ -126,23 +127,36 @@ struct LevelData {
   std::vector<int> rows, cols;                // concatenated per cell, offsets offS
   std::vector<int> rskel, cskel;              // concatenated per cell, offsets offK
   std::vector<std::vector<int>> children;     // plan children (only for the parent level)
-  zd* D = nullptr;                            // LU of D per cell
+  cx<R>* D = nullptr;                         // LU of D per cell
   int* ipiv = nullptr;
-  zd* Y = nullptr;                            // D^-1 L, s x K
-  zd* At = nullptr;                           // K x K
-  zd* Tc = nullptr;                           // column-ID T blocks, [k0 x (s0-k0)] then [k1 x (s1-k1)]
-  LuDesc* d_lu = nullptr;
+  cx<R>* Y = nullptr;                         // D^-1 L, s x K
+  cx<R>* At = nullptr;                        // K x K
+  cx<R>* Tc = nullptr;                        // column-ID T blocks, [k0 x (s0-k0)] then [k1 x (s1-k1)]
+  LuDescT<R>* d_lu = nullptr;
   int max_s = 0, max_k = 0;
   int64_t tot_s = 0, tot_k = 0;
 };
 
+template <class R>
 struct SolveCache {
   int nrhs = -1;
-  std::vector<zd*> F;      // per level: y / f vectors, sum s x nrhs
-  std::vector<zd*> G;      // per level: K x nrhs
-  std::vector<zd*> Red;    // per level: redundant rows scratch
-  zd* Froot = nullptr;
+  std::vector<cx<R>*> F;   // per level: y / f vectors, sum s x nrhs
+  std::vector<cx<R>*> G;   // per level: K x nrhs
+  std::vector<cx<R>*> Red; // per level: redundant rows scratch
+  cx<R>* Froot = nullptr;
   Arena arena;
+};
+
+// The compressed factorisation in one real type: levels, top system and solve buffers.
+template <class R>
+struct Tier {
+  std::vector<LevelData<R>> lev;
+  int root_s = 0;
+  cx<R>* Droot = nullptr;
+  int* ipiv_root = nullptr;
+  LuDescT<R>* d_lu_root = nullptr;
+  std::vector<int> root_rows, root_cols;
+  SolveCache<R> sc;
 };
 
 struct pmx_factor {
@@ -156,19 +170,29 @@ struct pmx_factor {
   int64_t* d_node_off = nullptr;
   pmx_options opts;
   std::vector<std::vector<CellPlan>> plan;
-  std::vector<LevelData> lev;     // compressed levels
-  // root
-  int root_s = 0;
-  zd* Droot = nullptr;
-  int* ipiv_root = nullptr;
-  LuDesc* d_lu_root = nullptr;
-  std::vector<int> root_rows, root_cols;
+  Tier<double> t64;   // precision 0
+  Tier<float> t32;    // precision 1
+  // precision 1: the FP64 self blocks of the leaves (leaf order, offsets selfOff) for the
+  // refinement residual
+  zd* Dself = nullptr;
+  std::vector<int> selfIncl;
+  std::vector<int64_t> selfOff;
   Arena arena;
-  SolveCache sc;
   pmx_info info;
   DevGeom geom() const { return DevGeom{x, y, nx, ny, w, speed, kappa, n_nodes}; }
   ExtParams ext() const { return ExtParams{k_ext, eps_ext}; }
 };
+
+template <class R>
+Tier<R>& tier(pmx_factor* F);
+template <>
+Tier<double>& tier<double>(pmx_factor* F) {
+  return F->t64;
+}
+template <>
+Tier<float>& tier<float>(pmx_factor* F) {
+  return F->t32;
+}
 
 namespace {
 
@@ -198,7 +222,13 @@ void validate(const pmx_geometry* g, const pmx_options* o) {
     if (!(o->id_tol > 0) || o->id_tol >= 1) fail(PMX_EINVAL, "id_tol must be in (0, 1)");
     if (!(o->proxy_ratio > 1.0)) fail(PMX_EINVAL, "proxy_ratio must exceed 1");
     if (o->proxy_rule == 1 && o->proxy_min < 8) fail(PMX_EINVAL, "a fixed proxy count must be >= 8");
-    if (o->precision != 0) fail(PMX_EINVAL, "only precision 0 (FP64) is available");
+    if (o->precision < 0 || o->precision > 2) fail(PMX_EINVAL, "precision must be 0, 1 or 2");
+    if (o->precision == 1 && o->id_tol < 1e-6)
+      fail(PMX_EINVAL, "precision 1 needs id_tol >= 1e-6: FP32 column norms cannot resolve smaller ratios");
+    if (o->precision != 0) {
+      if (o->ir_max_iter < 1 || o->ir_max_iter > 100) fail(PMX_EINVAL, "ir_max_iter must be in [1, 100]");
+      if (!(o->ir_tol > 0) || o->ir_tol >= 1) fail(PMX_EINVAL, "ir_tol must be in (0, 1)");
+    }
   }
 }
 
@@ -344,7 +374,8 @@ ProxyTable make_proxies(Arena& A, const std::vector<CellPlan>& cells, hipStream_
 }
 
 // Compress one level whose active sets (L.rows, L.cols, s0, s1) and blocks D are set.
-void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& cells, hipStream_t s) {
+template <class R>
+void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>& cells, hipStream_t s) {
   const int nc = L.ncell;
   const double tol = F->opts.id_tol;
   Arena tmp;
@@ -395,26 +426,26 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
       maxm = std::max(maxm, m);
       maxc = std::max(maxc, c);
     }
-  zd* Mb = tmp.alloc<zd>(totM);
-  zd* Rb = tmp.alloc<zd>(totR);
-  zd* Vb = tmp.alloc<zd>(totV);
-  zd* VTb = tmp.alloc<zd>(totV);
-  zd* CVb = tmp.alloc<zd>(totC);
+  cx<R>* Mb = tmp.alloc<cx<R>>(totM);
+  cx<R>* Rb = tmp.alloc<cx<R>>(totR);
+  cx<R>* Vb = tmp.alloc<cx<R>>(totV);
+  cx<R>* VTb = tmp.alloc<cx<R>>(totV);
+  cx<R>* CVb = tmp.alloc<cx<R>>(totC);
   double* taub = tmp.alloc<double>(nid);
   int* d_work = tmp.alloc<int>(1);
   int* pivb = tmp.alloc<int>(totC);
   double* nrmb = tmp.alloc<double>(2 * totC);
   int* stb = tmp.alloc<int>(4 * nid);
   double* r11b = tmp.alloc<double>(nid);
-  std::vector<EntryMat> em(nid);
-  std::vector<QrDesc> qd(nid);
-  std::vector<CpqrDesc> cd(nid);
+  std::vector<EntryMatT<R>> em(nid);
+  std::vector<QrDescT<R>> qd(nid);
+  std::vector<CpqrDescT<R>> cd(nid);
   for (int t = 0; t < nc; ++t)
     for (int kd = 0; kd < 4; ++kd) {
       int q = 4 * t + kd;
       int ty = kd & 1;
       const int* own = ((kd < 2) ? d_cols : d_rows) + L.offS[t] + (ty ? L.s0[t] : 0);
-      EntryMat& e = em[q];
+      EntryMatT<R>& e = em[q];
       e.a = ((kd < 2) ? d_nr : d_ncol) + nro[t];
       e.na = idm[q];
       e.b = own;
@@ -422,7 +453,7 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
       e.out = Mb + offM[q];
       e.ld = idm[q];
       e.a_is_target = (kd < 2) ? 1 : 0;
-      QrDesc& Q = qd[q];
+      QrDescT<R>& Q = qd[q];
       Q.a = Mb + offM[q];
       Q.ld = idm[q];
       Q.m = idm[q];
@@ -431,7 +462,7 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
       Q.v = Vb + offV[q];
       Q.t = VTb + offV[q];
 
-      CpqrDesc& C = cd[q];
+      CpqrDescT<R>& C = cd[q];
       C.b = Rb + offR[q];
       C.mb = std::min(idm[q], idc[q]);
       C.c = idc[q];
@@ -442,13 +473,13 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
       C.v = CVb + offC[q];
       C.tau = taub + q;
     }
-  EntryMat* d_em = tmp.upload(em, s);
-  QrDesc* d_qd = tmp.upload(qd, s);
-  CpqrDesc* d_cd = tmp.upload(cd, s);
+  EntryMatT<R>* d_em = tmp.upload(em, s);
+  QrDescT<R>* d_qd = tmp.upload(qd, s);
+  CpqrDescT<R>* d_cd = tmp.upload(cd, s);
   asm_entries(F->geom(), PT.dev, F->ext(), d_em, nid, maxm, maxc, s);
   la_geqrf_r(d_qd, nid, maxm, maxc, s);
   for (int q = 0; q < nid; ++q)
-    la_geqrf_work(idm[q], idc[q], &F->info.kernel_bytes[PK_TS_UPDATE], &F->info.kernel_flops[PK_TS_UPDATE],
+    la_geqrf_work(idm[q], idc[q], (int)sizeof(R), &F->info.kernel_bytes[PK_TS_UPDATE], &F->info.kernel_flops[PK_TS_UPDATE],
                   &F->info.kernel_bytes[PK_TS_LEAF], &F->info.kernel_flops[PK_TS_LEAF]);
   la_cpqr(d_cd, nid, maxc, tol, nullptr, 1, d_work, s);
   std::vector<int> st;
@@ -522,13 +553,13 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
     }
   }
   Arena& A = F->arena;
-  L.Y = A.alloc<zd>(ty_);
-  L.At = A.alloc<zd>(ta);
-  L.Tc = A.alloc<zd>(tt);
+  L.Y = A.alloc<cx<R>>(ty_);
+  L.At = A.alloc<cx<R>>(ta);
+  L.Tc = A.alloc<cx<R>>(tt);
   // ---- compact copies of the column-ID T blocks
   {
     std::vector<RowSrc> rs;
-    std::vector<GatherDesc> gd;
+    std::vector<GatherDescT<R>> gd;
     std::vector<int64_t> rso;
     int maxr = 0, maxcc = 0;
     for (int t = 0; t < nc; ++t)
@@ -539,7 +570,7 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
         int ncol = idc[q] - kb;
         rso.push_back((int64_t)rs.size());
         for (int i = 0; i < kb; ++i) rs.push_back(RowSrc{offR[q] + i + (int64_t)kb * mb, mb});
-        GatherDesc g;
+        GatherDescT<R> g;
         g.nrows = ncol > 0 ? kb : 0;
         g.ncols = ncol;
         g.dst = L.Tc + L.offT[t] + (ty ? (int64_t)L.k0[t] * (L.s0[t] - L.k0[t]) : 0);
@@ -550,15 +581,15 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
       }
     RowSrc* d_rs = tmp.upload(rs, s);
     for (size_t i = 0; i < gd.size(); ++i) gd[i].src = d_rs + rso[i];
-    GatherDesc* d_gd = tmp.upload(gd, s);
+    GatherDescT<R>* d_gd = tmp.upload(gd, s);
     asm_gather(Rb, d_gd, (int)gd.size(), maxr, maxcc, s);
   }
   // ---- L, LU(D), Y = D^-1 L
   asm_zero(L.Y, ty_, s);
   {
-    std::vector<LDesc> ld(nc);
+    std::vector<LDescT<R>> ld(nc);
     for (int t = 0; t < nc; ++t) {
-      LDesc& d = ld[t];
+      LDescT<R>& d = ld[t];
       d.out = L.Y + L.offY[t];
       d.s0 = L.s0[t];
       d.s1 = L.s1[t];
@@ -573,37 +604,37 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
       d.ldt0 = mb0;
       d.ldt1 = mb1;
     }
-    LDesc* d_ld = tmp.upload(ld, s);
+    LDescT<R>* d_ld = tmp.upload(ld, s);
     asm_build_l(d_ld, nc, L.max_s, L.max_k, s);
   }
-  std::vector<LuDesc> lu(nc);
+  std::vector<LuDescT<R>> lu(nc);
   for (int t = 0; t < nc; ++t) {
     int sz = L.s0[t] + L.s1[t];
-    lu[t] = LuDesc{L.D + L.offD[t], sz, sz, L.ipiv + L.offS[t]};
+    lu[t] = LuDescT<R>{L.D + L.offD[t], sz, sz, L.ipiv + L.offS[t]};
   }
   L.d_lu = A.upload(lu, s);
   int* d_info = tmp.alloc<int>(nc);
   HIPCHK(hipMemsetAsync(d_info, 0, nc * sizeof(int), s));
   la_getrf(L.d_lu, nc, L.max_s, d_info, s);
   for (int t = 0; t < nc; ++t)
-    la_getrf_work(L.s0[t] + L.s1[t], &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
-  std::vector<Mat> ym(nc);
+    la_getrf_work(L.s0[t] + L.s1[t], (int)sizeof(R), &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
+  std::vector<MatT<R>> ym(nc);
   for (int t = 0; t < nc; ++t) {
     int sz = L.s0[t] + L.s1[t];
-    ym[t] = Mat{L.Y + L.offY[t], sz, sz, L.k0[t] + L.k1[t]};
+    ym[t] = MatT<R>{L.Y + L.offY[t], sz, sz, L.k0[t] + L.k1[t]};
   }
-  Mat* d_ym = tmp.upload(ym, s);
+  MatT<R>* d_ym = tmp.upload(ym, s);
   la_getrs(L.d_lu, d_ym, nc, L.max_s, L.max_k, s);
   // ---- M = R Y: skeleton rows of Y plus T times its redundant rows
-  zd* Mm = tmp.alloc<zd>(ta);
+  cx<R>* Mm = tmp.alloc<cx<R>>(ta);
   int64_t totred = 0;
   for (int t = 0; t < nc; ++t) totred += (int64_t)(L.s0[t] + L.s1[t] - L.k0[t] - L.k1[t]) * (L.k0[t] + L.k1[t]);
-  zd* Red = tmp.alloc<zd>(std::max<int64_t>(totred, 1));
+  cx<R>* Red = tmp.alloc<cx<R>>(std::max<int64_t>(totred, 1));
   {
     std::vector<RowSrc> rs;
     std::vector<int64_t> rso;
-    std::vector<GatherDesc> gd;
-    std::vector<GemmArgs> ga;
+    std::vector<GatherDescT<R>> gd;
+    std::vector<GemmArgsT<R>> ga;
     int maxr = 0;
     int64_t ro = 0;
     for (int t = 0; t < nc; ++t) {
@@ -616,7 +647,7 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
         int base = ty ? L.s0[t] : 0;
         for (int i = 0; i < kb; ++i) rs.push_back(RowSrc{L.offY[t] + base + L.cpiv[L.offS[t] + base + i], sz});
       }
-      GatherDesc g;
+      GatherDescT<R> g;
       g.nrows = K;
       g.ncols = K;
       g.dst = Mm + L.offA[t];
@@ -630,7 +661,7 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
         int nr = sb - kb;
         rso.push_back((int64_t)rs.size());
         for (int j = 0; j < nr; ++j) rs.push_back(RowSrc{L.offY[t] + base + L.cpiv[L.offS[t] + base + kb + j], sz});
-        GatherDesc h;
+        GatherDescT<R> h;
         h.nrows = nr;
         h.ncols = K;
         h.dst = Red + ro;
@@ -638,7 +669,7 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
         gd.push_back(h);
         maxr = std::max(maxr, nr);
         if (nr > 0) {
-          GemmArgs a;
+          GemmArgsT<R> a;
           a.m = kb;
           a.n = K;
           a.k = nr;
@@ -655,33 +686,33 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
     }
     RowSrc* d_rs = tmp.upload(rs, s);
     for (size_t i = 0; i < gd.size(); ++i) gd[i].src = d_rs + rso[i];
-    GatherDesc* d_gd = tmp.upload(gd, s);
+    GatherDescT<R>* d_gd = tmp.upload(gd, s);
     asm_gather(L.Y, d_gd, (int)gd.size(), maxr, L.max_k, s);
     if (!ga.empty()) {
-      GemmArgs* d_ga = tmp.upload(ga, s);
-      la_zgemm_list(OP_N, OP_N, d_ga, (int)ga.size(), L.max_k, L.max_k, zmk(1, 0), zmk(1, 0), s);
+      GemmArgsT<R>* d_ga = tmp.upload(ga, s);
+      la_zgemm_list(OP_N, OP_N, d_ga, (int)ga.size(), L.max_k, L.max_k, cmk<R>(1, 0), cmk<R>(1, 0), s);
     }
   }
   // ---- At = M^-1
   {
-    std::vector<LuDesc> lm(nc);
-    std::vector<Mat2> id(nc);
-    std::vector<Mat> am(nc);
+    std::vector<LuDescT<R>> lm(nc);
+    std::vector<Mat2T<R>> id(nc);
+    std::vector<MatT<R>> am(nc);
     int* ipm = tmp.alloc<int>(std::max<int64_t>(tk, 1));
     for (int t = 0; t < nc; ++t) {
       int K = L.k0[t] + L.k1[t];
-      lm[t] = LuDesc{Mm + L.offA[t], K, K, ipm + L.offK[t]};
-      id[t] = Mat2{L.At + L.offA[t], K, K};
-      am[t] = Mat{L.At + L.offA[t], K, K, K};
+      lm[t] = LuDescT<R>{Mm + L.offA[t], K, K, ipm + L.offK[t]};
+      id[t] = Mat2T<R>{L.At + L.offA[t], K, K};
+      am[t] = MatT<R>{L.At + L.offA[t], K, K, K};
     }
-    LuDesc* d_lm = tmp.upload(lm, s);
-    Mat2* d_id = tmp.upload(id, s);
-    Mat* d_am = tmp.upload(am, s);
+    LuDescT<R>* d_lm = tmp.upload(lm, s);
+    Mat2T<R>* d_id = tmp.upload(id, s);
+    MatT<R>* d_am = tmp.upload(am, s);
     int* d_info2 = tmp.alloc<int>(nc);
     HIPCHK(hipMemsetAsync(d_info2, 0, nc * sizeof(int), s));
     la_getrf(d_lm, nc, L.max_k, d_info2, s);
     for (int t = 0; t < nc; ++t)
-      la_getrf_work(L.k0[t] + L.k1[t], &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
+      la_getrf_work(L.k0[t] + L.k1[t], (int)sizeof(R), &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
     asm_identity(d_id, nc, L.max_k, s);
     la_getrs(d_lm, d_am, nc, L.max_k, L.max_k, s);
     std::vector<int> info;
@@ -696,7 +727,8 @@ void compress_level(pmx_factor* F, LevelData& L, const std::vector<CellPlan>& ce
 }
 
 // Active sets and block of every parent at level `lv` from the compressed children.
-void merge_level(pmx_factor* F, const LevelData& C, const std::vector<CellPlan>& cells, LevelData& P,
+template <class R>
+void merge_level(pmx_factor* F, const LevelData<R>& C, const std::vector<CellPlan>& cells, LevelData<R>& P,
                  Arena& tmp, hipStream_t s) {
   const int np = (int)cells.size();
   P.ncell = np;
@@ -732,15 +764,15 @@ void merge_level(pmx_factor* F, const LevelData& C, const std::vector<CellPlan>&
   }
   P.offS[np] = (int64_t)P.rows.size();
   P.tot_s = P.offS[np];
-  P.D = F->arena.alloc<zd>(td);
+  P.D = F->arena.alloc<cx<R>>(td);
   P.ipiv = F->arena.alloc<int>(std::max<int64_t>(P.tot_s, 1));
   int* d_r = tmp.upload(P.rows, s);
   int* d_c = tmp.upload(P.cols, s);
   int* d_rl = tmp.upload(rloc, s);
   int* d_cl = tmp.upload(cloc, s);
-  std::vector<ParentDesc> pd(np);
+  std::vector<ParentDescT<R>> pd(np);
   for (int p = 0; p < np; ++p) {
-    ParentDesc& d = pd[p];
+    ParentDescT<R>& d = pd[p];
     d.rcode = d_r + P.offS[p];
     d.ccode = d_c + P.offS[p];
     d.rloc = d_rl + P.offS[p];
@@ -757,15 +789,17 @@ void merge_level(pmx_factor* F, const LevelData& C, const std::vector<CellPlan>&
       d.kc[sl] = C.k0[c] + C.k1[c];
     }
   }
-  ParentDesc* d_pd = tmp.upload(pd, s);
+  ParentDescT<R>* d_pd = tmp.upload(pd, s);
   asm_parent(F->geom(), F->ext(), d_pd, np, P.max_s, s);
 }
 
+template <class R>
 void factor_all(pmx_factor* F, hipStream_t s) {
+  Tier<R>& T = tier<R>(F);
   const double t0 = now_ms();
   const auto& plan = F->plan;
   // leaf level
-  LevelData L0;
+  LevelData<R> L0;
   const std::vector<CellPlan>& leaves = plan[0];
   const int nc0 = (int)leaves.size();
   L0.ncell = nc0;
@@ -794,38 +828,47 @@ void factor_all(pmx_factor* F, hipStream_t s) {
   }
   L0.offS[nc0] = (int64_t)L0.rows.size();
   L0.tot_s = L0.offS[nc0];
-  L0.D = F->arena.alloc<zd>(td);
+  L0.D = F->arena.alloc<cx<R>>(td);
   L0.ipiv = F->arena.alloc<int>(L0.tot_s);
   {
     Arena tmp;
-    assemble_diag(F, tmp, incl, L0.D, L0.offD, s);
+    if (F->opts.precision == 0) {
+      assemble_diag(F, tmp, incl, (zd*)L0.D, L0.offD, s);
+    } else {
+      // FP64 self blocks kept for the refinement residual; copies (rounded for FP32) factored
+      F->Dself = F->arena.alloc<zd>(td);
+      F->selfOff = L0.offD;
+      F->selfIncl = incl;
+      assemble_diag(F, tmp, incl, F->Dself, L0.offD, s);
+      asm_convert(F->Dself, L0.D, td, s);
+    }
     sync_check(s);
   }
   F->info.t_phase_ms[0] += now_ms() - t0;
-  LevelData cur = std::move(L0);
+  LevelData<R> cur = std::move(L0);
   for (size_t lv = 0; lv < plan.size(); ++lv) {
     if (lv > 0) {
       Arena tmp;
-      LevelData nxt;
-      merge_level(F, F->lev.back(), plan[lv], nxt, tmp, s);
+      LevelData<R> nxt;
+      merge_level(F, T.lev.back(), plan[lv], nxt, tmp, s);
       sync_check(s);
       cur = std::move(nxt);
     }
     if (plan[lv].size() == 1) {
       // root: dense partial-pivoted LU of the top compressed system
       const double tr = now_ms();
-      F->root_s = cur.s0[0] + cur.s1[0];
-      F->Droot = cur.D;
-      F->ipiv_root = cur.ipiv;
-      F->root_rows = cur.rows;
-      F->root_cols = cur.cols;
-      std::vector<LuDesc> lu{LuDesc{F->Droot, F->root_s, F->root_s, F->ipiv_root}};
-      F->d_lu_root = F->arena.upload(lu, s);
+      T.root_s = cur.s0[0] + cur.s1[0];
+      T.Droot = cur.D;
+      T.ipiv_root = cur.ipiv;
+      T.root_rows = cur.rows;
+      T.root_cols = cur.cols;
+      std::vector<LuDescT<R>> lu{LuDescT<R>{T.Droot, T.root_s, T.root_s, T.ipiv_root}};
+      T.d_lu_root = F->arena.upload(lu, s);
       Arena tmp;
       int* d_info = tmp.alloc<int>(1);
       HIPCHK(hipMemsetAsync(d_info, 0, sizeof(int), s));
-      la_getrf(F->d_lu_root, 1, F->root_s, d_info, s);
-      la_getrf_work(F->root_s, &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
+      la_getrf(T.d_lu_root, 1, T.root_s, d_info, s);
+      la_getrf_work(T.root_s, (int)sizeof(R), &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
       std::vector<int> info;
       download(info, d_info, 1, s);
       if (info[0]) fail(PMX_ESINGULAR, "zero pivot in the LU of the top compressed system");
@@ -835,18 +878,20 @@ void factor_all(pmx_factor* F, hipStream_t s) {
     const double tc = now_ms();
     compress_level(F, cur, plan[lv], s);
     F->info.t_phase_ms[1] += now_ms() - tc;
-    F->lev.push_back(std::move(cur));
-    cur = LevelData();
+    T.lev.push_back(std::move(cur));
+    cur = LevelData<R>();
   }
 }
 
+template <class R>
 void fill_info(pmx_factor* F) {
+  Tier<R>& T = tier<R>(F);
   pmx_info& I = F->info;
-  I.levels = (int)F->lev.size();
-  I.root_size = F->root_s;
+  I.levels = (int)T.lev.size();
+  I.root_size = T.root_s;
   I.n_unknowns = 2 * F->n_nodes;
-  for (size_t l = 0; l < F->lev.size() && l < 32; ++l) {
-    const LevelData& L = F->lev[l];
+  for (size_t l = 0; l < T.lev.size() && l < 32; ++l) {
+    const LevelData<R>& L = T.lev[l];
     I.cells[l] = L.ncell;
     int mn = 1 << 30, mx = 0;
     double sum = 0;
@@ -865,45 +910,49 @@ void fill_info(pmx_factor* F) {
 
 // ---------------------------------------------------------------------------------
 // solve
+template <class R>
 void ensure_solve_buffers(pmx_factor* F, int nrhs) {
-  SolveCache& S = F->sc;
+  Tier<R>& T = tier<R>(F);
+  SolveCache<R>& S = T.sc;
   if (S.nrhs == nrhs) return;
   S.arena.release();
   S.F.clear();
   S.G.clear();
   S.Red.clear();
-  for (const LevelData& L : F->lev) {
-    S.F.push_back(S.arena.alloc<zd>(L.tot_s * nrhs));
-    S.G.push_back(S.arena.alloc<zd>(std::max<int64_t>(L.tot_k, 1) * nrhs));
-    S.Red.push_back(S.arena.alloc<zd>(std::max<int64_t>(L.tot_s - L.tot_k, 1) * nrhs));
+  for (const LevelData<R>& L : T.lev) {
+    S.F.push_back(S.arena.template alloc<cx<R>>(L.tot_s * nrhs));
+    S.G.push_back(S.arena.template alloc<cx<R>>(std::max<int64_t>(L.tot_k, 1) * nrhs));
+    S.Red.push_back(S.arena.template alloc<cx<R>>(std::max<int64_t>(L.tot_s - L.tot_k, 1) * nrhs));
   }
-  S.Froot = S.arena.alloc<zd>((int64_t)F->root_s * nrhs);
+  S.Froot = S.arena.template alloc<cx<R>>((int64_t)T.root_s * nrhs);
   S.nrhs = nrhs;
 }
 
 // vectors of a level are stored per cell, column major with leading dimension = rows
-void solve_core(pmx_factor* F, int nrhs, zd* fleaf_or_root, hipStream_t s) {
-  SolveCache& S = F->sc;
+template <class R>
+void solve_core(pmx_factor* F, int nrhs, cx<R>* fleaf_or_root, hipStream_t s) {
+  Tier<R>& T = tier<R>(F);
+  SolveCache<R>& S = T.sc;
   Arena tmp;
-  const int nl = (int)F->lev.size();
-  const zd one = zmk(1, 0), mone = zmk(-1, 0);
+  const int nl = (int)T.lev.size();
+  const cx<R> one = cmk<R>(1, 0), mone = cmk<R>(-1, 0);
   for (int l = 0; l < nl; ++l) {
-    LevelData& L = F->lev[l];
+    LevelData<R>& L = T.lev[l];
     const int nc = L.ncell;
-    zd* Fv = S.F[l];
+    cx<R>* Fv = S.F[l];
     // y = D^-1 f
-    std::vector<Mat> bm(nc);
+    std::vector<MatT<R>> bm(nc);
     for (int t = 0; t < nc; ++t) {
       int sz = L.s0[t] + L.s1[t];
-      bm[t] = Mat{Fv + L.offS[t] * nrhs, sz, sz, nrhs};
+      bm[t] = MatT<R>{Fv + L.offS[t] * nrhs, sz, sz, nrhs};
     }
-    Mat* d_bm = tmp.upload(bm, s);
+    MatT<R>* d_bm = tmp.upload(bm, s);
     la_getrs(L.d_lu, d_bm, nc, L.max_s, nrhs, s);
     // R y -> G (skeleton rows, then + T * redundant rows)
     std::vector<RowSrc> rs;
     std::vector<int64_t> rso;
-    std::vector<GatherDesc> gd;
-    std::vector<GemmArgs> ga, gb;
+    std::vector<GatherDescT<R>> gd;
+    std::vector<GemmArgsT<R>> ga, gb;
     int maxr = 0;
     int64_t ro = 0;
     for (int t = 0; t < nc; ++t) {
@@ -916,7 +965,7 @@ void solve_core(pmx_factor* F, int nrhs, zd* fleaf_or_root, hipStream_t s) {
         int base = ty ? L.s0[t] : 0;
         for (int i = 0; i < kb; ++i) rs.push_back(RowSrc{yo + base + L.cpiv[L.offS[t] + base + i], sz});
       }
-      gd.push_back(GatherDesc{nullptr, K, nrhs, S.G[l] + L.offK[t] * nrhs, K});
+      gd.push_back(GatherDescT<R>{nullptr, K, nrhs, S.G[l] + L.offK[t] * nrhs, K});
       maxr = std::max(maxr, K);
       for (int ty = 0; ty < 2; ++ty) {
         int kb = ty ? L.k1[t] : L.k0[t];
@@ -925,10 +974,10 @@ void solve_core(pmx_factor* F, int nrhs, zd* fleaf_or_root, hipStream_t s) {
         int nr = sb - kb;
         rso.push_back((int64_t)rs.size());
         for (int j = 0; j < nr; ++j) rs.push_back(RowSrc{yo + base + L.cpiv[L.offS[t] + base + kb + j], sz});
-        gd.push_back(GatherDesc{nullptr, nr, nrhs, S.Red[l] + ro, std::max(nr, 1)});
+        gd.push_back(GatherDescT<R>{nullptr, nr, nrhs, S.Red[l] + ro, std::max(nr, 1)});
         maxr = std::max(maxr, nr);
         if (nr > 0) {
-          GemmArgs a;
+          GemmArgsT<R> a;
           a.m = kb;
           a.n = nrhs;
           a.k = nr;
@@ -945,18 +994,18 @@ void solve_core(pmx_factor* F, int nrhs, zd* fleaf_or_root, hipStream_t s) {
     }
     RowSrc* d_rs = tmp.upload(rs, s);
     for (size_t i = 0; i < gd.size(); ++i) gd[i].src = d_rs + rso[i];
-    GatherDesc* d_gd = tmp.upload(gd, s);
+    GatherDescT<R>* d_gd = tmp.upload(gd, s);
     asm_gather(Fv, d_gd, (int)gd.size(), maxr, nrhs, s);
     if (!ga.empty()) {
-      GemmArgs* d_ga = tmp.upload(ga, s);
+      GemmArgsT<R>* d_ga = tmp.upload(ga, s);
       la_zgemm_list(OP_N, OP_N, d_ga, (int)ga.size(), L.max_k, nrhs, one, one, s);
     }
     // g = At (R y): into Red-free temporary then back to G
-    zd* Ry = tmp.alloc<zd>(std::max<int64_t>(L.tot_k, 1) * nrhs);
-    HIPCHK(hipMemcpyAsync(Ry, S.G[l], L.tot_k * nrhs * sizeof(zd), hipMemcpyDeviceToDevice, s));
+    cx<R>* Ry = tmp.alloc<cx<R>>(std::max<int64_t>(L.tot_k, 1) * nrhs);
+    HIPCHK(hipMemcpyAsync(Ry, S.G[l], L.tot_k * nrhs * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
     for (int t = 0; t < nc; ++t) {
       int K = L.k0[t] + L.k1[t];
-      GemmArgs a;
+      GemmArgsT<R> a;
       a.m = K;
       a.n = nrhs;
       a.k = K;
@@ -968,14 +1017,14 @@ void solve_core(pmx_factor* F, int nrhs, zd* fleaf_or_root, hipStream_t s) {
       a.ldc = K;
       gb.push_back(a);
     }
-    GemmArgs* d_gb = tmp.upload(gb, s);
-    la_zgemm_list(OP_N, OP_N, d_gb, nc, L.max_k, nrhs, one, zmk(0, 0), s);
+    GemmArgsT<R>* d_gb = tmp.upload(gb, s);
+    la_zgemm_list(OP_N, OP_N, d_gb, nc, L.max_k, nrhs, one, cmk<R>(0, 0), s);
     // parent right-hand sides
     const bool top = (l + 1 == nl);
     const std::vector<CellPlan>& pc = F->plan[l + 1];
-    zd* dst = top ? S.Froot : S.F[l + 1];
+    cx<R>* dst = top ? S.Froot : S.F[l + 1];
     std::vector<RowSrc> prs;
-    std::vector<GatherDesc> pgd;
+    std::vector<GatherDescT<R>> pgd;
     std::vector<int64_t> pro;
     int maxp = 0;
     int64_t po = 0;
@@ -990,29 +1039,29 @@ void solve_core(pmx_factor* F, int nrhs, zd* fleaf_or_root, hipStream_t s) {
           for (int i = 0; i < kb; ++i) prs.push_back(RowSrc{L.offK[c] * nrhs + base + i, K});
           cnt += kb;
         }
-      pgd.push_back(GatherDesc{nullptr, cnt, nrhs, dst + po * nrhs, cnt});
+      pgd.push_back(GatherDescT<R>{nullptr, cnt, nrhs, dst + po * nrhs, cnt});
       po += cnt;
       maxp = std::max(maxp, cnt);
     }
     RowSrc* d_prs = tmp.upload(prs, s);
     for (size_t i = 0; i < pgd.size(); ++i) pgd[i].src = d_prs + pro[i];
-    GatherDesc* d_pgd = tmp.upload(pgd, s);
+    GatherDescT<R>* d_pgd = tmp.upload(pgd, s);
     asm_gather(S.G[l], d_pgd, (int)pgd.size(), maxp, nrhs, s);
   }
   // root solve
   {
-    zd* root = (nl == 0) ? fleaf_or_root : S.Froot;
-    std::vector<Mat> bm{Mat{root, F->root_s, F->root_s, nrhs}};
-    Mat* d_bm = tmp.upload(bm, s);
-    la_getrs(F->d_lu_root, d_bm, 1, F->root_s, nrhs, s);
+    cx<R>* root = (nl == 0) ? fleaf_or_root : S.Froot;
+    std::vector<MatT<R>> bm{MatT<R>{root, T.root_s, T.root_s, nrhs}};
+    MatT<R>* d_bm = tmp.upload(bm, s);
+    la_getrs(T.d_lu_root, d_bm, 1, T.root_s, nrhs, s);
   }
   // downward pass
   for (int l = nl - 1; l >= 0; --l) {
-    LevelData& L = F->lev[l];
+    LevelData<R>& L = T.lev[l];
     const int nc = L.ncell;
     const bool top = (l + 1 == nl);
-    const zd* xp = top ? S.Froot : S.F[l + 1];
-    const LevelData* Pl = top ? nullptr : &F->lev[l + 1];
+    const cx<R>* xp = top ? S.Froot : S.F[l + 1];
+    const LevelData<R>* Pl = top ? nullptr : &T.lev[l + 1];
     const std::vector<CellPlan>& pc = F->plan[l + 1];
     // psi of each child from its parent's solution -> Red scratch (K x nrhs per cell)
     std::vector<int64_t> psio(nc);
@@ -1021,12 +1070,12 @@ void solve_core(pmx_factor* F, int nrhs, zd* fleaf_or_root, hipStream_t s) {
       psio[t] = o;
       o += (int64_t)(L.k0[t] + L.k1[t]) * nrhs;
     }
-    zd* Psi = tmp.alloc<zd>(std::max<int64_t>(o, 1));
+    cx<R>* Psi = tmp.alloc<cx<R>>(std::max<int64_t>(o, 1));
     std::vector<RowSrc> rs(L.tot_k);
-    std::vector<GatherDesc> gd(nc);
+    std::vector<GatherDescT<R>> gd(nc);
     for (size_t p = 0; p < pc.size(); ++p) {
       int64_t pbase = top ? 0 : Pl->offS[p];
-      int psz = top ? F->root_s : Pl->s0[p] + Pl->s1[p];
+      int psz = top ? T.root_s : Pl->s0[p] + Pl->s1[p];
       int pos = 0;
       for (int ty = 0; ty < 2; ++ty)
         for (int c : pc[p].children) {
@@ -1039,76 +1088,92 @@ void solve_core(pmx_factor* F, int nrhs, zd* fleaf_or_root, hipStream_t s) {
     RowSrc* d_rs = tmp.upload(rs, s);
     for (int t = 0; t < nc; ++t) {
       int K = L.k0[t] + L.k1[t];
-      gd[t] = GatherDesc{d_rs + L.offK[t], K, nrhs, Psi + psio[t], K};
+      gd[t] = GatherDescT<R>{d_rs + L.offK[t], K, nrhs, Psi + psio[t], K};
     }
-    GatherDesc* d_gd = tmp.upload(gd, s);
+    GatherDescT<R>* d_gd = tmp.upload(gd, s);
     asm_gather(xp, d_gd, nc, L.max_k, nrhs, s);
     // g <- g - At psi ; x = y - Y g
-    std::vector<GemmArgs> g1(nc), g2(nc);
+    std::vector<GemmArgsT<R>> g1(nc), g2(nc);
     for (int t = 0; t < nc; ++t) {
       int K = L.k0[t] + L.k1[t];
       int sz = L.s0[t] + L.s1[t];
-      g1[t] = GemmArgs{K, nrhs, K, L.At + L.offA[t], K, Psi + psio[t], K, S.G[l] + L.offK[t] * nrhs, K};
-      g2[t] = GemmArgs{sz, nrhs, K, L.Y + L.offY[t], sz, S.G[l] + L.offK[t] * nrhs, K, S.F[l] + L.offS[t] * nrhs, sz};
+      g1[t] = GemmArgsT<R>{K, nrhs, K, L.At + L.offA[t], K, Psi + psio[t], K, S.G[l] + L.offK[t] * nrhs, K};
+      g2[t] = GemmArgsT<R>{sz, nrhs, K, L.Y + L.offY[t], sz, S.G[l] + L.offK[t] * nrhs, K, S.F[l] + L.offS[t] * nrhs, sz};
     }
-    GemmArgs* d_g1 = tmp.upload(g1, s);
-    GemmArgs* d_g2 = tmp.upload(g2, s);
+    GemmArgsT<R>* d_g1 = tmp.upload(g1, s);
+    GemmArgsT<R>* d_g2 = tmp.upload(g2, s);
     la_zgemm_list(OP_N, OP_N, d_g1, nc, L.max_k, nrhs, mone, one, s);
     la_zgemm_list(OP_N, OP_N, d_g2, nc, L.max_s, nrhs, mone, one, s);
   }
   sync_check(s);
 }
 
-// leaf cell vectors <-> dens layout [nrhs][2 N] (per inclusion [q; u])
-void leaf_to_dens(pmx_factor* F, const zd* leaf, int nrhs, zd* dens, Arena& tmp, hipStream_t s) {
+// Row maps between the leaf cell vectors (per cell [2 n x nrhs], cells in leaf order) and
+// the density layout [nrhs][2 N] (per inclusion [q; u]); built once per right-hand-side
+// count and reused by every gather of a solve.
+struct LeafMap {
+  int nrhs = -1;
+  int n2 = 0, max_cell = 0, ncell = 0;
+  std::vector<RowSrc> to_dens, to_leaf;
+  std::vector<int64_t> leaf_off;    // per cell: first leaf entry / nrhs
+  std::vector<int> cell_rows;
+  RowSrc *d_to_dens = nullptr, *d_to_leaf = nullptr;
+  Arena arena;
+};
+
+void build_leaf_map(pmx_factor* F, int nrhs, LeafMap& M, hipStream_t s) {
+  M.arena.release();
   const std::vector<CellPlan>& leaves = F->plan[0];
-  const int N2 = 2 * F->n_nodes;
-  std::vector<RowSrc> rs(N2);
+  M.n2 = 2 * F->n_nodes;
+  M.ncell = (int)leaves.size();
+  M.to_dens.assign(M.n2, RowSrc{0, 0});
+  M.to_leaf.assign(M.n2, RowSrc{0, 0});
+  M.leaf_off.assign(M.ncell, 0);
+  M.cell_rows.assign(M.ncell, 0);
+  M.max_cell = 0;
   int64_t off = 0;
-  for (size_t t = 0; t < leaves.size(); ++t) {
+  for (int t = 0; t < M.ncell; ++t) {
     int j = leaves[t].incl[0];
     int n = (int)(F->node_off[j + 1] - F->node_off[j]);
-    for (int r = 0; r < 2 * n; ++r) rs[2 * F->node_off[j] + r] = RowSrc{off * nrhs + r, 2 * n};
+    for (int r = 0; r < 2 * n; ++r) {
+      M.to_dens[2 * F->node_off[j] + r] = RowSrc{off * nrhs + r, 2 * n};
+      M.to_leaf[off + r] = RowSrc{2 * F->node_off[j] + r, M.n2};
+    }
+    M.leaf_off[t] = off;
+    M.cell_rows[t] = 2 * n;
+    M.max_cell = std::max(M.max_cell, 2 * n);
     off += 2 * n;
   }
-  RowSrc* d_rs = tmp.upload(rs, s);
-  std::vector<GatherDesc> gd{GatherDesc{d_rs, N2, nrhs, dens, N2}};
-  GatherDesc* d_gd = tmp.upload(gd, s);
-  asm_gather(leaf, d_gd, 1, N2, nrhs, s);
+  M.d_to_dens = M.arena.upload(M.to_dens, s);
+  M.d_to_leaf = M.arena.upload(M.to_leaf, s);
+  M.nrhs = nrhs;
 }
 
-void dens_to_leaf(pmx_factor* F, const zd* dens, int nrhs, zd* leaf, Arena& tmp, hipStream_t s) {
-  const std::vector<CellPlan>& leaves = F->plan[0];
-  const int N2 = 2 * F->n_nodes;
-  std::vector<RowSrc> rs(N2);
-  int64_t off = 0;
-  std::vector<GatherDesc> gd;
-  int maxr = 0;
-  for (size_t t = 0; t < leaves.size(); ++t) {
-    int j = leaves[t].incl[0];
-    int n = (int)(F->node_off[j + 1] - F->node_off[j]);
-    for (int r = 0; r < 2 * n; ++r) rs[off + r] = RowSrc{2 * F->node_off[j] + r, N2};
-    gd.push_back(GatherDesc{nullptr, 2 * n, nrhs, leaf + off * nrhs, 2 * n});
-    off += 2 * n;
-    maxr = std::max(maxr, 2 * n);
-  }
-  RowSrc* d_rs = tmp.upload(rs, s);
-  off = 0;
-  for (size_t t = 0; t < gd.size(); ++t) {
-    gd[t].src = d_rs + off;
-    off += gd[t].nrows;
-  }
-  GatherDesc* d_gd = tmp.upload(gd, s);
-  asm_gather(dens, d_gd, (int)gd.size(), maxr, nrhs, s);
+// dens (type RD) [+]= leaf (type RS)
+template <class RS, class RD>
+void leaf_to_dens(const LeafMap& M, const cx<RS>* leaf, int nrhs, cx<RD>* dens, int acc, Arena& tmp,
+                  hipStream_t s) {
+  std::vector<GatherDescT<RD>> gd{GatherDescT<RD>{M.d_to_dens, M.n2, nrhs, dens, M.n2}};
+  asm_gather(leaf, tmp.upload(gd, s), 1, M.n2, nrhs, s, acc);
 }
 
-zd* leaf_vectors(pmx_factor* F) {
-  return F->lev.empty() ? F->sc.Froot : F->sc.F[0];
+template <class RS, class RD>
+void dens_to_leaf(const LeafMap& M, const cx<RS>* dens, int nrhs, cx<RD>* leaf, Arena& tmp, hipStream_t s) {
+  std::vector<GatherDescT<RD>> gd(M.ncell);
+  for (int t = 0; t < M.ncell; ++t)
+    gd[t] = GatherDescT<RD>{M.d_to_leaf + M.leaf_off[t], M.cell_rows[t], nrhs, leaf + M.leaf_off[t] * nrhs,
+                            M.cell_rows[t]};
+  asm_gather(dens, tmp.upload(gd, s), M.ncell, M.max_cell, nrhs, s, 0);
 }
 
-void solve_plane(pmx_factor* F, int nrhs, const double* angles, zd* dens, hipStream_t s) {
-  ensure_solve_buffers(F, nrhs);
-  Arena tmp;
+template <class R>
+cx<R>* leaf_vectors(pmx_factor* F) {
+  Tier<R>& T = tier<R>(F);
+  return T.lev.empty() ? T.sc.Froot : T.sc.F[0];
+}
+
+// leaf right-hand sides of plane waves (FP64, leaf layout)
+void plane_wave_leaf(pmx_factor* F, int nrhs, const double* angles, zd* leaf, Arena& tmp, hipStream_t s) {
   const std::vector<CellPlan>& leaves = F->plan[0];
   const int nc = (int)leaves.size();
   std::vector<int> node0(nc), nn(nc);
@@ -1124,21 +1189,258 @@ void solve_plane(pmx_factor* F, int nrhs, const double* angles, zd* dens, hipStr
     maxn = std::max(maxn, nn[t]);
   }
   std::vector<double> ang(angles, angles + nrhs);
-  zd* leaf = leaf_vectors(F);
   asm_incident(F->geom(), F->ext(), tmp.upload(node0, s), tmp.upload(nn, s), tmp.upload(off, s), nc, maxn,
                tmp.upload(ang, s), nrhs, leaf, s);
-  solve_core(F, nrhs, leaf, s);
-  leaf_to_dens(F, leaf, nrhs, dens, tmp, s);
+}
+
+// Dense FP64 operator apply y = A x, or the residual out = f - A x: the self blocks from
+// FP64 storage (leaf order, offsets doff) by batched MFMA products, the blocks between
+// inclusions evaluated on the fly.  Buffers are sized once per right-hand-side count.
+struct DenseApply {
+  int nrhs = -1, nsplit = 1, nblk = 1;
+  int64_t total = 0;
+  zd *ydiag = nullptr, *part = nullptr;
+  double* d_norm = nullptr;
+  Arena arena;
+};
+
+void build_dense_apply(pmx_factor* F, int nrhs, DenseApply& D) {
+  D.arena.release();
+  const int64_t N2 = 2 * (int64_t)F->n_nodes;
+  D.total = N2 * nrhs;
+  D.nsplit = apply_splits(F->n_nodes, nrhs);
+  D.ydiag = D.arena.alloc<zd>(D.total);
+  D.part = D.arena.alloc<zd>(D.total * D.nsplit);
+  D.nblk = (int)std::min<int64_t>(64, (N2 + 4095) / 4096);
+  D.d_norm = D.arena.alloc<double>((int64_t)D.nblk * nrhs);
+  D.nrhs = nrhs;
+}
+
+// dself holds the self block of inclusion incl[t] at offset doff[t] (2 n x 2 n, ld 2 n)
+void run_dense_apply(pmx_factor* F, DenseApply& D, const zd* dself, const std::vector<int>& incl,
+                     const std::vector<int64_t>& doff, const zd* x, const zd* f, zd* out, Arena& tmp, hipStream_t s) {
+  const int64_t N2 = 2 * (int64_t)F->n_nodes;
+  std::vector<GemmArgs> ga(incl.size());
+  int max_s = 0;
+  for (size_t t = 0; t < incl.size(); ++t) {
+    int j = incl[t];
+    int n2 = (int)(2 * (F->node_off[j + 1] - F->node_off[j]));
+    ga[t] = GemmArgs{n2, D.nrhs, n2, dself + doff[t], n2, x + 2 * F->node_off[j], N2, D.ydiag + 2 * F->node_off[j], N2};
+    max_s = std::max(max_s, n2);
+  }
+  la_zgemm_list(OP_N, OP_N, tmp.upload(ga, s), (int)ga.size(), max_s, D.nrhs, zmk(1, 0), zmk(0, 0), s);
+  ApplyArgs aa;
+  aa.x = F->x;
+  aa.y = F->y;
+  aa.nx = F->nx;
+  aa.ny = F->ny;
+  aa.w = F->w;
+  aa.owner = F->owner;
+  aa.node_off = F->d_node_off;
+  aa.n_nodes = F->n_nodes;
+  aa.k = F->k_ext;
+  aa.eps = F->eps_ext;
+  aa.xin = x;
+  aa.nrhs = D.nrhs;
+  aa.ld = N2;
+  aa.part = D.part;
+  asm_apply_off(aa, D.nsplit, s);
+  if (f)
+    asm_apply_finish(f, D.ydiag, D.part, D.nsplit, D.total, 1.0, -1.0, out, s);
+  else
+    asm_apply_finish(nullptr, D.ydiag, D.part, D.nsplit, D.total, 0.0, 1.0, out, s);
+}
+
+// squared column norms of v (density layout, nrhs columns)
+std::vector<double> dens_norms2(pmx_factor* F, DenseApply& D, const zd* v, hipStream_t s) {
+  const int64_t N2 = 2 * (int64_t)F->n_nodes;
+  asm_colnorm2(v, N2, D.nrhs, N2, D.nblk, D.d_norm, s);
+  std::vector<double> part;
+  download(part, D.d_norm, (size_t)D.nblk * D.nrhs, s);
+  std::vector<double> out(D.nrhs, 0.0);
+  for (int c = 0; c < D.nrhs; ++c)
+    for (int b = 0; b < D.nblk; ++b) out[c] += part[(size_t)c * D.nblk + b];
+  return out;
+}
+
+// FP64 factor: leaf right-hand sides, one pass of the solver, densities.
+void solve_fp64(pmx_factor* F, int nrhs, const double* angles, const zd* rhs, zd* dens, hipStream_t s) {
+  ensure_solve_buffers<double>(F, nrhs);
+  Arena tmp;
+  LeafMap M;
+  build_leaf_map(F, nrhs, M, s);
+  zd* leaf = leaf_vectors<double>(F);
+  if (angles)
+    plane_wave_leaf(F, nrhs, angles, leaf, tmp, s);
+  else
+    dens_to_leaf(M, rhs, nrhs, leaf, tmp, s);
+  solve_core<double>(F, nrhs, leaf, s);
+  leaf_to_dens(M, leaf, nrhs, dens, 0, tmp, s);
   sync_check(s);
 }
 
-void solve_general(pmx_factor* F, int nrhs, const zd* rhs, zd* dens, hipStream_t s) {
-  ensure_solve_buffers(F, nrhs);
+// Refinement: the factor of type R as the inner solver of iterative refinement with the
+// FP64 operator, x_0 = 0, r_i = f - A x_i, x_{i+1} = x_i + solve(r_i), until
+// max_r |r_i| / |f| <= ir_tol.
+template <class R>
+void solve_refined(pmx_factor* F, int nrhs, const double* angles, const zd* rhs, zd* dens, hipStream_t s) {
+  ensure_solve_buffers<R>(F, nrhs);
   Arena tmp;
-  zd* leaf = leaf_vectors(F);
-  dens_to_leaf(F, rhs, nrhs, leaf, tmp, s);
-  solve_core(F, nrhs, leaf, s);
-  leaf_to_dens(F, leaf, nrhs, dens, tmp, s);
+  LeafMap M;
+  build_leaf_map(F, nrhs, M, s);
+  DenseApply D;
+  build_dense_apply(F, nrhs, D);
+  const int64_t total = D.total;
+  zd* f = tmp.alloc<zd>(total);
+  if (angles) {
+    zd* leaf64 = tmp.alloc<zd>(total);
+    plane_wave_leaf(F, nrhs, angles, leaf64, tmp, s);
+    leaf_to_dens(M, leaf64, nrhs, f, 0, tmp, s);
+  } else {
+    HIPCHK(hipMemcpyAsync(f, rhs, total * sizeof(zd), hipMemcpyDeviceToDevice, s));
+  }
+  zd* r = tmp.alloc<zd>(total);
+  HIPCHK(hipMemcpyAsync(r, f, total * sizeof(zd), hipMemcpyDeviceToDevice, s));
+  asm_zero(dens, total, s);
+  const std::vector<double> fn = dens_norms2(F, D, f, s);
+  cx<R>* leaf = leaf_vectors<R>(F);
+  const int maxit = std::max(1, F->opts.ir_max_iter);
+  double rel = 0;
+  int it = 0;
+  for (int h = 0; h < 16; ++h) F->info.ir_history[h] = 0;
+  for (it = 1; it <= maxit; ++it) {
+    dens_to_leaf(M, r, nrhs, leaf, tmp, s);
+    solve_core<R>(F, nrhs, leaf, s);
+    leaf_to_dens(M, leaf, nrhs, dens, 1, tmp, s);
+    run_dense_apply(F, D, F->Dself, F->selfIncl, F->selfOff, dens, f, r, tmp, s);
+    const std::vector<double> rn = dens_norms2(F, D, r, s);
+    rel = 0;
+    for (int c = 0; c < nrhs; ++c) rel = std::max(rel, fn[c] > 0 ? std::sqrt(rn[c] / fn[c]) : std::sqrt(rn[c]));
+    if (it <= 16) F->info.ir_history[it - 1] = rel;
+    if (rel <= F->opts.ir_tol) break;
+  }
+  F->info.ir_iterations = std::min(it, maxit);
+  F->info.ir_residual = rel;
+  sync_check(s);
+  if (rel > F->opts.ir_tol) {
+    char buf[160];
+    snprintf(buf, sizeof(buf), "iterative refinement stopped at relative residual %.3e after %d steps", rel, maxit);
+    fail(PMX_ENOTCONV, buf);
+  }
+}
+
+void solve_any(pmx_factor* F, int nrhs, const double* angles, const zd* rhs, zd* dens, hipStream_t s) {
+  const double t0 = now_ms();
+  if (F->opts.precision == 1)
+    solve_refined<float>(F, nrhs, angles, rhs, dens, s);
+  else if (F->opts.precision == 2)
+    solve_refined<double>(F, nrhs, angles, rhs, dens, s);
+  else
+    solve_fp64(F, nrhs, angles, rhs, dens, s);
+  F->info.t_solve_ms = now_ms() - t0;
+}
+
+// ---------------------------------------------------------------------------------
+// probe bodies, shared by the complex FP64 and FP32 entry points
+template <class R>
+void probe_gemm(int batch, int m, int n, int k, int opa, int opb, const cx<R>* A, const cx<R>* B, cx<R>* Cm,
+                hipStream_t s) {
+  if (batch <= 0 || m <= 0 || n <= 0 || k < 0 || (k > 0 && (!A || !B)) || !Cm || opa < 0 || opa > 2 || opb < 0 ||
+      opb > 2)
+    fail(PMX_EINVAL, "bad arguments");
+  std::vector<GemmArgsT<R>> ga(batch);
+  for (int b = 0; b < batch; ++b) {
+    GemmArgsT<R>& g = ga[b];
+    g.m = m;
+    g.n = n;
+    g.k = k;
+    g.A = A + (int64_t)b * m * k;
+    g.lda = opa == OP_N ? m : k;
+    g.B = B + (int64_t)b * k * n;
+    g.ldb = opb == OP_N ? k : n;
+    g.C = Cm + (int64_t)b * m * n;
+    g.ldc = m;
+  }
+  Arena tmp;
+  la_zgemm_list<R>(opa, opb, tmp.upload(ga, s), batch, m, n, cmk<R>(1, 0), cmk<R>(0, 0), s);
+  sync_check(s);
+}
+
+template <class R>
+void probe_lu(int batch, int n, cx<R>* A, int* ipiv, int nrhs, cx<R>* B, int* info, hipStream_t s) {
+  if (batch <= 0 || n <= 0 || nrhs < 0 || !A || !ipiv || (nrhs > 0 && !B) || !info) fail(PMX_EINVAL, "bad arguments");
+  std::vector<LuDescT<R>> lu(batch);
+  std::vector<MatT<R>> bm(batch);
+  for (int b = 0; b < batch; ++b) {
+    lu[b] = LuDescT<R>{A + (int64_t)b * n * n, n, n, ipiv + (int64_t)b * n};
+    bm[b] = MatT<R>{nrhs > 0 ? B + (int64_t)b * n * nrhs : nullptr, n, n, nrhs};
+  }
+  Arena tmp;
+  LuDescT<R>* d_lu = tmp.upload(lu, s);
+  int* d_info = tmp.alloc<int>(batch);
+  HIPCHK(hipMemsetAsync(d_info, 0, batch * sizeof(int), s));
+  la_getrf<R>(d_lu, batch, n, d_info, s);
+  if (nrhs > 0) la_getrs<R>(d_lu, tmp.upload(bm, s), batch, n, nrhs, s);
+  std::vector<int> hi;
+  download(hi, d_info, batch, s);
+  std::copy(hi.begin(), hi.end(), info);
+  sync_check(s);
+}
+
+template <class R>
+void probe_id(int batch, int m, int c, cx<R>* M, double tol, const int* kmin, int* piv, int* rank, cx<R>* T,
+              hipStream_t s) {
+  if (batch <= 0 || m <= 0 || c <= 0 || !M || !piv || !rank || !T || !(tol > 0)) fail(PMX_EINVAL, "bad arguments");
+  Arena tmp;
+  const int mb = std::min(m, c);
+  cx<R>* Rb = tmp.alloc<cx<R>>((int64_t)batch * mb * c);
+  const int64_t wsz = la_geqrf_workspace(m);
+  cx<R>* Vb = tmp.alloc<cx<R>>((int64_t)batch * wsz);
+  cx<R>* VTb = tmp.alloc<cx<R>>((int64_t)batch * wsz);
+  cx<R>* CVb = tmp.alloc<cx<R>>((int64_t)batch * c);
+  double* taub = tmp.alloc<double>(batch);
+  int* d_work = tmp.alloc<int>(1);
+  double* nrm = tmp.alloc<double>((int64_t)batch * 2 * c);
+  int* st = tmp.alloc<int>(4 * batch);
+  double* r11 = tmp.alloc<double>(batch);
+  std::vector<QrDescT<R>> qd(batch);
+  std::vector<CpqrDescT<R>> cd(batch);
+  for (int b = 0; b < batch; ++b) {
+    qd[b] = QrDescT<R>{M + (int64_t)b * m * c, m, m, c, Rb + (int64_t)b * mb * c, Vb + (int64_t)b * wsz,
+                       VTb + (int64_t)b * wsz};
+    cd[b] = CpqrDescT<R>{Rb + (int64_t)b * mb * c, mb, c, piv + (int64_t)b * c, nrm + (int64_t)b * 2 * c, st + 4 * b,
+                         r11 + b, CVb + (int64_t)b * c, taub + b};
+  }
+  QrDescT<R>* d_qd = tmp.upload(qd, s);
+  CpqrDescT<R>* d_cd = tmp.upload(cd, s);
+  la_geqrf_r<R>(d_qd, batch, m, c, s);
+  la_cpqr<R>(d_cd, batch, c, tol, nullptr, 1, d_work, s);
+  std::vector<int> sth;
+  download(sth, st, 4 * batch, s);
+  std::vector<int> k(batch);
+  for (int b = 0; b < batch; ++b) {
+    rank[b] = sth[4 * b + 1];
+    k[b] = std::max(rank[b], kmin ? kmin[b] : 0);
+    k[b] = std::max(1, std::min(k[b], mb));
+  }
+  int* d_k = tmp.upload(k, s);
+  la_cpqr<R>(d_cd, batch, c, 0.0, d_k, 0, d_work, s);
+  download(sth, st, 4 * batch, s);
+  for (int b = 0; b < batch; ++b) k[b] = std::min(k[b], sth[4 * b]);
+  HIPCHK(hipMemcpyAsync(d_k, k.data(), batch * sizeof(int), hipMemcpyHostToDevice, s));
+  la_cpqr_tsolve<R>(d_cd, d_k, batch, c, c, s);
+  // T[b] (c x c, ld c): rows 0..k-1 hold R11^-1 R12 in columns 0..c-k-1
+  std::vector<RowSrc> rs;
+  std::vector<GatherDescT<R>> gd(batch);
+  for (int b = 0; b < batch; ++b)
+    for (int i = 0; i < k[b]; ++i) rs.push_back(RowSrc{(int64_t)b * mb * c + i + (int64_t)k[b] * mb, mb});
+  RowSrc* d_rs = tmp.upload(rs, s);
+  int64_t ro = 0;
+  for (int b = 0; b < batch; ++b) {
+    gd[b] = GatherDescT<R>{d_rs + ro, c - k[b] > 0 ? k[b] : 0, c - k[b], T + (int64_t)b * c * c, c};
+    ro += k[b];
+  }
+  asm_gather(Rb, tmp.upload(gd, s), batch, c, c, s);
   sync_check(s);
 }
 
@@ -1174,6 +1476,8 @@ void pmx_options_default(pmx_options* o) {
   o->near_rule = 0;
   o->precision = 0;
   o->timing = 0;
+  o->ir_max_iter = 10;
+  o->ir_tol = 1e-10;
 }
 
 pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, void* hip_stream,
@@ -1200,8 +1504,13 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
     } reset_timer;
     make_plan(geom, o, F->plan);
     upload_geometry(F.get(), geom, s);
-    factor_all(F.get(), s);
-    fill_info(F.get());
+    if (o.precision == 1) {
+      factor_all<float>(F.get(), s);
+      fill_info<float>(F.get());
+    } else {
+      factor_all<double>(F.get(), s);
+      fill_info<double>(F.get());
+    }
     F->info.t_factor_ms = now_ms() - t0;
     if (kt) {
       HIPCHK(hipStreamSynchronize(s));
@@ -1217,7 +1526,7 @@ pmx_status pmx_solve_plane_waves(pmx_factor* f, int32_t nrhs, const double* angl
     if (!f || !angles || !dens || nrhs <= 0) fail(PMX_EINVAL, "bad arguments to pmx_solve_plane_waves");
     for (int r = 0; r < nrhs; ++r)
       if (!std::isfinite(angles[r])) fail(PMX_EINVAL, "non-finite angle");
-    solve_plane(f, nrhs, angles, (zd*)dens, (hipStream_t)hip_stream);
+    solve_any(f, nrhs, angles, nullptr, (zd*)dens, (hipStream_t)hip_stream);
   });
 }
 
@@ -1225,7 +1534,7 @@ pmx_status pmx_solve(pmx_factor* f, int32_t nrhs, const pmx_c64* rhs, pmx_c64* d
   return guarded([&] {
     if (!f || !rhs || !dens || nrhs <= 0) fail(PMX_EINVAL, "bad arguments to pmx_solve");
     if ((const void*)rhs == (const void*)dens) fail(PMX_EINVAL, "rhs and dens overlap");
-    solve_general(f, nrhs, (const zd*)rhs, (zd*)dens, (hipStream_t)hip_stream);
+    solve_any(f, nrhs, nullptr, (const zd*)rhs, (zd*)dens, (hipStream_t)hip_stream);
   });
 }
 
@@ -1319,110 +1628,58 @@ pmx_status pmx_probe_entries(const pmx_geometry* geom, int32_t nr, const int32_t
 
 pmx_status pmx_probe_zgemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t opa, int32_t opb,
                            const pmx_c64* A, const pmx_c64* B, pmx_c64* C, void* stream) {
-  return guarded([&] {
-    if (batch <= 0 || m <= 0 || n <= 0 || k < 0 || (k > 0 && (!A || !B)) || !C || opa < 0 || opa > 2 || opb < 0 ||
-        opb > 2)
-      fail(PMX_EINVAL, "bad arguments");
-    hipStream_t s = (hipStream_t)stream;
-    std::vector<GemmArgs> ga(batch);
-    for (int b = 0; b < batch; ++b) {
-      GemmArgs& g = ga[b];
-      g.m = m;
-      g.n = n;
-      g.k = k;
-      g.A = (const zd*)A + (int64_t)b * m * k;
-      g.lda = opa == OP_N ? m : k;
-      g.B = (const zd*)B + (int64_t)b * k * n;
-      g.ldb = opb == OP_N ? k : n;
-      g.C = (zd*)C + (int64_t)b * m * n;
-      g.ldc = m;
-    }
-    Arena tmp;
-    la_zgemm_list(opa, opb, tmp.upload(ga, s), batch, m, n, zmk(1, 0), zmk(0, 0), s);
-    sync_check(s);
-  });
+  return guarded([&] { probe_gemm<double>(batch, m, n, k, opa, opb, (const zd*)A, (const zd*)B, (zd*)C,
+                                          (hipStream_t)stream); });
+}
+
+pmx_status pmx_probe_cgemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32_t opa, int32_t opb,
+                           const pmx_c32* A, const pmx_c32* B, pmx_c32* C, void* stream) {
+  return guarded([&] { probe_gemm<float>(batch, m, n, k, opa, opb, (const zf*)A, (const zf*)B, (zf*)C,
+                                         (hipStream_t)stream); });
 }
 
 pmx_status pmx_probe_lu_solve(int32_t batch, int32_t n, pmx_c64* A, int32_t* ipiv, int32_t nrhs, pmx_c64* B,
                               int32_t* info, void* stream) {
-  return guarded([&] {
-    if (batch <= 0 || n <= 0 || nrhs < 0 || !A || !ipiv || (nrhs > 0 && !B) || !info) fail(PMX_EINVAL, "bad arguments");
-    hipStream_t s = (hipStream_t)stream;
-    std::vector<LuDesc> lu(batch);
-    std::vector<Mat> bm(batch);
-    for (int b = 0; b < batch; ++b) {
-      lu[b] = LuDesc{(zd*)A + (int64_t)b * n * n, n, n, ipiv + (int64_t)b * n};
-      bm[b] = Mat{nrhs > 0 ? (zd*)B + (int64_t)b * n * nrhs : nullptr, n, n, nrhs};
-    }
-    Arena tmp;
-    LuDesc* d_lu = tmp.upload(lu, s);
-    int* d_info = tmp.alloc<int>(batch);
-    HIPCHK(hipMemsetAsync(d_info, 0, batch * sizeof(int), s));
-    la_getrf(d_lu, batch, n, d_info, s);
-    if (nrhs > 0) la_getrs(d_lu, tmp.upload(bm, s), batch, n, nrhs, s);
-    std::vector<int> hi;
-    download(hi, d_info, batch, s);
-    std::copy(hi.begin(), hi.end(), info);
-    sync_check(s);
-  });
+  return guarded([&] { probe_lu<double>(batch, n, (zd*)A, ipiv, nrhs, (zd*)B, info, (hipStream_t)stream); });
+}
+
+pmx_status pmx_probe_lu_solve_c32(int32_t batch, int32_t n, pmx_c32* A, int32_t* ipiv, int32_t nrhs, pmx_c32* B,
+                                  int32_t* info, void* stream) {
+  return guarded([&] { probe_lu<float>(batch, n, (zf*)A, ipiv, nrhs, (zf*)B, info, (hipStream_t)stream); });
 }
 
 pmx_status pmx_probe_id(int32_t batch, int32_t m, int32_t c, pmx_c64* M, double tol, const int32_t* kmin,
                         int32_t* piv, int32_t* rank, pmx_c64* T, void* stream) {
+  return guarded([&] { probe_id<double>(batch, m, c, (zd*)M, tol, kmin, piv, rank, (zd*)T, (hipStream_t)stream); });
+}
+
+pmx_status pmx_probe_id_c32(int32_t batch, int32_t m, int32_t c, pmx_c32* M, double tol, const int32_t* kmin,
+                            int32_t* piv, int32_t* rank, pmx_c32* T, void* stream) {
+  return guarded([&] { probe_id<float>(batch, m, c, (zf*)M, tol, kmin, piv, rank, (zf*)T, (hipStream_t)stream); });
+}
+
+pmx_status pmx_probe_apply(const pmx_geometry* geom, int32_t nrhs, const pmx_c64* x, pmx_c64* y, void* stream) {
   return guarded([&] {
-    if (batch <= 0 || m <= 0 || c <= 0 || !M || !piv || !rank || !T || !(tol > 0)) fail(PMX_EINVAL, "bad arguments");
+    validate(geom, nullptr);
+    if (nrhs <= 0 || !x || !y || (const void*)x == (const void*)y) fail(PMX_EINVAL, "bad arguments");
     hipStream_t s = (hipStream_t)stream;
+    pmx_factor F;
+    upload_geometry(&F, geom, s);
     Arena tmp;
-    const int mb = std::min(m, c);
-    zd* Rb = tmp.alloc<zd>((int64_t)batch * mb * c);
-    const int64_t wsz = la_geqrf_workspace(m);
-    zd* Vb = tmp.alloc<zd>((int64_t)batch * wsz);
-    zd* VTb = tmp.alloc<zd>((int64_t)batch * wsz);
-    zd* CVb = tmp.alloc<zd>((int64_t)batch * c);
-    double* taub = tmp.alloc<double>(batch);
-    int* d_work = tmp.alloc<int>(1);
-    double* nrm = tmp.alloc<double>((int64_t)batch * 2 * c);
-    int* st = tmp.alloc<int>(4 * batch);
-    double* r11 = tmp.alloc<double>(batch);
-    std::vector<QrDesc> qd(batch);
-    std::vector<CpqrDesc> cd(batch);
-    for (int b = 0; b < batch; ++b) {
-      qd[b] = QrDesc{(zd*)M + (int64_t)b * m * c, m, m, c, Rb + (int64_t)b * mb * c, Vb + (int64_t)b * wsz,
-                     VTb + (int64_t)b * wsz};
-      cd[b] = CpqrDesc{Rb + (int64_t)b * mb * c, mb, c, piv + (int64_t)b * c, nrm + (int64_t)b * 2 * c, st + 4 * b,
-                       r11 + b, CVb + (int64_t)b * c, taub + b};
+    std::vector<int> incl(geom->m);
+    std::vector<int64_t> off(geom->m);
+    int64_t o = 0;
+    for (int j = 0; j < geom->m; ++j) {
+      incl[j] = j;
+      off[j] = o;
+      const int64_t n = geom->node_off[j + 1] - geom->node_off[j];
+      o += 4 * n * n;
     }
-    QrDesc* d_qd = tmp.upload(qd, s);
-    CpqrDesc* d_cd = tmp.upload(cd, s);
-    la_geqrf_r(d_qd, batch, m, c, s);
-    la_cpqr(d_cd, batch, c, tol, nullptr, 1, d_work, s);
-    std::vector<int> sth;
-    download(sth, st, 4 * batch, s);
-    std::vector<int> k(batch);
-    for (int b = 0; b < batch; ++b) {
-      rank[b] = sth[4 * b + 1];
-      k[b] = std::max(rank[b], kmin ? kmin[b] : 0);
-      k[b] = std::max(1, std::min(k[b], mb));
-    }
-    int* d_k = tmp.upload(k, s);
-    la_cpqr(d_cd, batch, c, 0.0, d_k, 0, d_work, s);
-    download(sth, st, 4 * batch, s);
-    for (int b = 0; b < batch; ++b) k[b] = std::min(k[b], sth[4 * b]);
-    HIPCHK(hipMemcpyAsync(d_k, k.data(), batch * sizeof(int), hipMemcpyHostToDevice, s));
-    la_cpqr_tsolve(d_cd, d_k, batch, c, c, s);
-    // T[b] (c x c, ld c): rows 0..k-1 hold R11^-1 R12 in columns 0..c-k-1
-    std::vector<RowSrc> rs;
-    std::vector<GatherDesc> gd(batch);
-    for (int b = 0; b < batch; ++b) {
-      for (int i = 0; i < k[b]; ++i) rs.push_back(RowSrc{(int64_t)b * mb * c + i + (int64_t)k[b] * mb, mb});
-    }
-    RowSrc* d_rs = tmp.upload(rs, s);
-    int64_t ro = 0;
-    for (int b = 0; b < batch; ++b) {
-      gd[b] = GatherDesc{d_rs + ro, c - k[b] > 0 ? k[b] : 0, c - k[b], (zd*)T + (int64_t)b * c * c, c};
-      ro += k[b];
-    }
-    asm_gather(Rb, tmp.upload(gd, s), batch, c, c, s);
+    zd* dself = tmp.alloc<zd>(o);
+    assemble_diag(&F, tmp, incl, dself, off, s);
+    DenseApply D;
+    build_dense_apply(&F, nrhs, D);
+    run_dense_apply(&F, D, dself, incl, off, (const zd*)x, nullptr, (zd*)y, tmp, s);
     sync_check(s);
   });
 }

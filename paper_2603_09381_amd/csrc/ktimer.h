@@ -16,7 +16,8 @@ enum PmxKernelId {
   PK_TRSM = 6,         // k_trsm_small: triangular solves on diagonal blocks
   PK_ENTRIES = 7,      // k_entries: interaction and proxy matrices
   PK_DIAG = 8,         // k_diag_*: self blocks (Kress quadrature, Maue products)
-  PK_COUNT = 9
+  PK_APPLY = 9,        // k_apply_off: dense FP64 operator apply for refinement residuals
+  PK_COUNT = 10
 };
 
 struct KernelTimer {

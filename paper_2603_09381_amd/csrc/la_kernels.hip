@@ -1,15 +1,17 @@
-// Batched complex FP64 dense linear algebra kernels for gfx950.
+// Batched complex dense linear algebra kernels for gfx950, templated on the real type R
+// (double: FP64 MFMA 16x16x4; float: FP32 MFMA 16x16x4).
 //
 //  * zgemm: 64x64 tiles per 256-thread workgroup, each wave a 32x32 sub-tile built
-//    from 16x16x4 FP64 MFMA blocks; a complex product is four real MFMAs.
+//    from 16x16x4 MFMA blocks; a complex product is four real MFMAs.
 //  * getrf: right-looking blocked LU with partial pivoting (panel of 32 columns in
 //    one workgroup per matrix, row swaps, unit-lower triangular solve, MFMA update).
 //  * getrs: blocked forward and backward substitution (small triangular solves on
 //    32x32 diagonal blocks in LDS, MFMA updates of the rest).
-//  * geqrf: blocked Householder QR (16-column panels, compact WY form I - V T V^H,
-//    trailing update as two MFMA products); only R is kept.
-//  * cpqr: column pivoted Householder QR with norm downdating, one workgroup per
-//    matrix, one wave per trailing column, stopping at a relative threshold.
+//  * geqrf: Householder QR as a tree of in-LDS block factorisations (TSQR panels of 32
+//    columns), trailing update in compact WY form on MFMA; only R is kept.
+//  * cpqr: column pivoted Householder QR with norm downdating, stopping at a relative
+//    threshold; one workgroup per matrix, or a pivot and an update launch per step for
+//    large matrices.  Norms and pivot decisions are FP64 for both real types.
 // Reflectors are Hermitian: H = I - tau v v^H with real tau, so |R_jj| equals the
 // norm of the trailing part of the pivot column, which is what the threshold tests.
 #include "la.h"
@@ -18,32 +20,79 @@
 #include <algorithm>
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
-#define PMX_CHECK_LAUNCH() (void)hipGetLastError()
+template <class R>
+struct AccT;
+template <>
+struct AccT<double> {
+  typedef d4 type;
+};
+template <>
+struct AccT<float> {
+  typedef f4 type;
+};
+
+// D += A B on a 16x16x4 block.  Operand lanes: A[i][k] in lane i + 16 k, B[k][j] in lane
+// j + 16 k.  The accumulator layouts differ: FP64 keeps element (i, j) in register i / 4 of
+// lane j + 16 (i % 4), FP32 in register i % 4 of lane j + 16 (i / 4).
+__device__ inline d4 mfma16(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma16(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <class R>
+__device__ inline int mfma_row(int lane, int r);
+template <>
+__device__ inline int mfma_row<double>(int lane, int r) {
+  return (lane >> 4) + 4 * r;
+}
+template <>
+__device__ inline int mfma_row<float>(int lane, int r) {
+  return 4 * (lane >> 4) + r;
+}
 
 // ---------------------------------------------------------------------------------
 // wave / block reductions
-// DPP moves of a double (two 32-bit halves); lanes outside row_mask receive 0.
+// DPP moves of a 32-bit value; lanes outside row_mask receive 0.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ inline int dpp_move_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWMASK, 0xf, false);
+}
 template <int CTRL, int ROWMASK = 0xf>
 __device__ inline double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, false);
+  const int lo = dpp_move_i<CTRL, ROWMASK>(__double2loint(v));
+  const int hi = dpp_move_i<CTRL, ROWMASK>(__double2hiint(v));
   return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWMASK = 0xf>
+__device__ inline float dpp_move(float v) {
+  return __int_as_float(dpp_move_i<CTRL, ROWMASK>(__float_as_int(v)));
 }
 
 // Sum over the 64 lanes of a wave, returned to every lane: quad permutations, half-row and
 // row mirrors give each row of 16 its sum, row broadcasts 15 and 31 carry the row sums up
 // to lane 63, which is read back as a scalar.
-__device__ inline double wave_sum(double v) {
+template <class T>
+__device__ inline T wave_sum_dpp(T v) {
   v += dpp_move<0xB1>(v);         // quad_perm [1,0,3,2]
   v += dpp_move<0x4E>(v);         // quad_perm [2,3,0,1]
   v += dpp_move<0x141>(v);        // row_half_mirror
   v += dpp_move<0x140>(v);        // row_mirror
   v += dpp_move<0x142, 0xA>(v);   // row_bcast15 into rows 1 and 3
   v += dpp_move<0x143, 0xC>(v);   // row_bcast31 into rows 2 and 3
+  return v;
+}
+__device__ inline double wave_sum(double v) {
+  v = wave_sum_dpp(v);
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
   return __hiloint2double(hi, lo);
+}
+__device__ inline float wave_sum(float v) {
+  v = wave_sum_dpp(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 template <int NT>
@@ -92,23 +141,25 @@ __device__ inline int block_argmax(double v, int i, double* redv, int* redi, dou
 
 // ---------------------------------------------------------------------------------
 // ZGEMM
-template <int OPA, int OPB, class F>
-__global__ __launch_bounds__(256) void k_zgemm(F f, zd alpha, zd beta) {
-  GemmArgs g;
+template <class R, int OPA, int OPB, class F>
+__global__ __launch_bounds__(256) void k_zgemm(F f, cx<R> alpha, cx<R> beta) {
+  typedef cx<R> C;
+  typedef typename AccT<R>::type V4;
+  GemmArgsT<R> g;
   if (!f(blockIdx.z, g)) return;
   const int tm = blockIdx.x * 64, tn = blockIdx.y * 64;
   if (tm >= g.m || tn >= g.n) return;
-  __shared__ zd As[8][64 + 1];
-  __shared__ zd Bs[8][64 + 1];
+  __shared__ C As[8][64 + 1];
+  __shared__ C Bs[8][64 + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  d4 accR[2][2], accI[2][2];
+  V4 accR[2][2], accI[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      accR[a][b] = (d4){0, 0, 0, 0};
-      accI[a][b] = (d4){0, 0, 0, 0};
+      accR[a][b] = V4{0, 0, 0, 0};
+      accI[a][b] = V4{0, 0, 0, 0};
     }
   for (int k0 = 0; k0 < g.k; k0 += 8) {
 #pragma unroll
@@ -123,9 +174,9 @@ __global__ __launch_bounds__(256) void k_zgemm(F f, zd alpha, zd beta) {
       }
       const int gi = tm + i, gk = k0 + kk;
       const int ci = min(gi, g.m - 1), ck = min(gk, g.k - 1);
-      zd v = (OPA == OP_N) ? g.A[ci + (int64_t)ck * g.lda] : g.A[ck + (int64_t)ci * g.lda];
+      C v = (OPA == OP_N) ? g.A[ci + (int64_t)ck * g.lda] : g.A[ck + (int64_t)ci * g.lda];
       if (OPA == OP_C) v.im = -v.im;
-      As[kk][i] = (gi < g.m && gk < g.k) ? v : zmk(0, 0);
+      As[kk][i] = (gi < g.m && gk < g.k) ? v : cmk<R>(0, 0);
     }
 #pragma unroll
     for (int pass = 0; pass < 2; ++pass) {
@@ -139,14 +190,14 @@ __global__ __launch_bounds__(256) void k_zgemm(F f, zd alpha, zd beta) {
       }
       const int gj = tn + j, gk = k0 + kk;
       const int cj = min(gj, g.n - 1), ck = min(gk, g.k - 1);
-      zd v = (OPB == OP_N) ? g.B[ck + (int64_t)cj * g.ldb] : g.B[cj + (int64_t)ck * g.ldb];
+      C v = (OPB == OP_N) ? g.B[ck + (int64_t)cj * g.ldb] : g.B[cj + (int64_t)ck * g.ldb];
       if (OPB == OP_C) v.im = -v.im;
-      Bs[kk][j] = (gj < g.n && gk < g.k) ? v : zmk(0, 0);
+      Bs[kk][j] = (gj < g.n && gk < g.k) ? v : cmk<R>(0, 0);
     }
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < 8; ks += 4) {
-      zd a[2], b[2];
+      C a[2], b[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         a[t] = As[ks + (lane >> 4)][wm + t * 16 + (lane & 15)];
@@ -156,55 +207,57 @@ __global__ __launch_bounds__(256) void k_zgemm(F f, zd alpha, zd beta) {
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
-          accR[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].re, b[bj].re, accR[bi][bj], 0, 0, 0);
-          accR[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[bi].im, b[bj].im, accR[bi][bj], 0, 0, 0);
-          accI[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].re, b[bj].im, accI[bi][bj], 0, 0, 0);
-          accI[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].im, b[bj].re, accI[bi][bj], 0, 0, 0);
+          accR[bi][bj] = mfma16(a[bi].re, b[bj].re, accR[bi][bj]);
+          accR[bi][bj] = mfma16(-a[bi].im, b[bj].im, accR[bi][bj]);
+          accI[bi][bj] = mfma16(a[bi].re, b[bj].im, accI[bi][bj]);
+          accI[bi][bj] = mfma16(a[bi].im, b[bj].re, accI[bi][bj]);
         }
     }
     __syncthreads();
   }
-  const bool use_beta = (beta.re != 0.0 || beta.im != 0.0);
+  const bool use_beta = (beta.re != R(0) || beta.im != R(0));
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = tm + wm + bi * 16 + (lane >> 4) + 4 * r;  // accumulator r of lane: row lane/16 + 4r
+        const int row = tm + wm + bi * 16 + mfma_row<R>(lane, r);
         const int col = tn + wn + bj * 16 + (lane & 15);
         if (row < g.m && col < g.n) {
-          zd v = zmul(alpha, zmk(accR[bi][bj][r], accI[bi][bj][r]));
-          zd* cp = g.C + row + (int64_t)col * g.ldc;
+          C v = zmul(alpha, cmk<R>(accR[bi][bj][r], accI[bi][bj][r]));
+          C* cp = g.C + row + (int64_t)col * g.ldc;
           if (use_beta) v = zfma(beta, *cp, v);
           *cp = v;
         }
       }
 }
 
-template <int OPA, int OPB, class F>
-static void launch_zgemm(F f, int batch, int max_m, int max_n, zd alpha, zd beta, hipStream_t s) {
+template <class R, int OPA, int OPB, class F>
+static void launch_zgemm(F f, int batch, int max_m, int max_n, cx<R> alpha, cx<R> beta, hipStream_t s) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
   dim3 grid((max_m + 63) / 64, (max_n + 63) / 64, batch);
   KScope ks(PK_ZGEMM, s);
-  hipLaunchKernelGGL((k_zgemm<OPA, OPB, F>), grid, dim3(256), 0, s, f, alpha, beta);
+  hipLaunchKernelGGL((k_zgemm<R, OPA, OPB, F>), grid, dim3(256), 0, s, f, alpha, beta);
 }
 
+template <class R>
 struct FList {
-  const GemmArgs* l;
-  __device__ bool operator()(int b, GemmArgs& g) const {
+  const GemmArgsT<R>* l;
+  __device__ bool operator()(int b, GemmArgsT<R>& g) const {
     g = l[b];
     return g.m > 0 && g.n > 0;
   }
 };
 
-void la_zgemm_list(int opa, int opb, const GemmArgs* d_list, int batch, int max_m, int max_n,
-                   zd alpha, zd beta, hipStream_t s) {
-  FList f{d_list};
-#define PMX_G(A, B)                                                   \
-  if (opa == A && opb == B) {                                         \
-    launch_zgemm<A, B>(f, batch, max_m, max_n, alpha, beta, s);       \
-    return;                                                           \
+template <class R>
+void la_zgemm_list(int opa, int opb, const GemmArgsT<R>* d_list, int batch, int max_m, int max_n, cx<R> alpha,
+                   cx<R> beta, hipStream_t s) {
+  FList<R> f{d_list};
+#define PMX_G(A, B)                                                \
+  if (opa == A && opb == B) {                                      \
+    launch_zgemm<R, A, B>(f, batch, max_m, max_n, alpha, beta, s); \
+    return;                                                        \
   }
   PMX_G(OP_N, OP_N) PMX_G(OP_N, OP_T) PMX_G(OP_N, OP_C)
   PMX_G(OP_T, OP_N) PMX_G(OP_T, OP_T) PMX_G(OP_T, OP_C)
@@ -214,20 +267,22 @@ void la_zgemm_list(int opa, int opb, const GemmArgs* d_list, int batch, int max_
 
 // ---------------------------------------------------------------------------------
 // small triangular solve on a <=32 x <=32 diagonal block, one thread per right-hand side
+template <class R>
 struct TrsmArgs {
-  const zd* T;
+  const cx<R>* T;
   int64_t ldt;
-  zd* B;
+  cx<R>* B;
   int64_t ldb;
   int nb, nrhs;
 };
 
-template <bool UPPER, bool UNIT, class F>
+template <class R, bool UPPER, bool UNIT, class F>
 __global__ __launch_bounds__(64) void k_trsm_small(F f) {
-  TrsmArgs a;
+  typedef cx<R> C;
+  TrsmArgs<R> a;
   if (!f(blockIdx.y, a)) return;
-  __shared__ zd Ts[32][33];
-  __shared__ zd xs[32][64];
+  __shared__ C Ts[32][33];
+  __shared__ C xs[32][64];
   const int tid = threadIdx.x;
   const int col = blockIdx.x * 64 + tid;
   if (blockIdx.x * 64 >= a.nrhs) return;
@@ -244,7 +299,7 @@ __global__ __launch_bounds__(64) void k_trsm_small(F f) {
   if (active) {
     if (!UPPER) {
       for (int i = 0; i < a.nb; ++i) {
-        zd xi = xs[i][tid];
+        C xi = xs[i][tid];
         if (!UNIT) {
           xi = zdiv(xi, Ts[i][i]);
           xs[i][tid] = xi;
@@ -253,7 +308,7 @@ __global__ __launch_bounds__(64) void k_trsm_small(F f) {
       }
     } else {
       for (int i = a.nb - 1; i >= 0; --i) {
-        zd xi = xs[i][tid];
+        C xi = xs[i][tid];
         if (!UNIT) {
           xi = zdiv(xi, Ts[i][i]);
           xs[i][tid] = xi;
@@ -265,31 +320,33 @@ __global__ __launch_bounds__(64) void k_trsm_small(F f) {
   }
 }
 
-template <bool UPPER, bool UNIT, class F>
+template <class R, bool UPPER, bool UNIT, class F>
 static void launch_trsm_small(F f, int batch, int max_nrhs, hipStream_t s) {
   if (batch <= 0 || max_nrhs <= 0) return;
   dim3 grid((max_nrhs + 63) / 64, batch);
   KScope ks(PK_TRSM, s);
-  hipLaunchKernelGGL((k_trsm_small<UPPER, UNIT, F>), grid, dim3(64), 0, s, f);
+  hipLaunchKernelGGL((k_trsm_small<R, UPPER, UNIT, F>), grid, dim3(64), 0, s, f);
 }
 
 // ---------------------------------------------------------------------------------
 // LU
-__global__ __launch_bounds__(256) void k_getrf_panel(const LuDesc* lus, int j0, int* info) {
-  const LuDesc L = lus[blockIdx.x];
+template <class R>
+__global__ __launch_bounds__(256) void k_getrf_panel(const LuDescT<R>* lus, int j0, int* info) {
+  typedef cx<R> C;
+  const LuDescT<R> L = lus[blockIdx.x];
   const int jb = min(PMX_LU_NB, L.n - j0);
   if (jb <= 0) return;
   __shared__ double redv[4];
   __shared__ int redi[4];
   const int tid = threadIdx.x;
-  zd* A = L.a;
+  C* A = L.a;
   const int64_t ld = L.ld;
   for (int c = j0; c < j0 + jb; ++c) {
     double best = -1.0;
     int bi = -1;
     for (int r = c + tid; r < L.n; r += 256) {
-      zd v = A[r + c * ld];
-      double av = fabs(v.re) + fabs(v.im);
+      C v = A[r + c * ld];
+      double av = fabs((double)v.re) + fabs((double)v.im);
       argmax_pair(best, bi, av, r);
     }
     double bestv;
@@ -300,17 +357,17 @@ __global__ __launch_bounds__(256) void k_getrf_panel(const LuDesc* lus, int j0, 
     }
     if (p != c) {
       for (int cc = j0 + tid; cc < j0 + jb; cc += 256) {
-        zd t = A[c + cc * ld];
+        C t = A[c + cc * ld];
         A[c + cc * ld] = A[p + cc * ld];
         A[p + cc * ld] = t;
       }
     }
     __syncthreads();
-    zd piv = A[c + c * ld];
-    if (piv.re != 0.0 || piv.im != 0.0) {
-      zd inv = zdiv(zmk(1, 0), piv);
+    C piv = A[c + c * ld];
+    if (piv.re != R(0) || piv.im != R(0)) {
+      C inv = zdiv(cmk<R>(1, 0), piv);
       for (int r = c + 1 + tid; r < L.n; r += 256) {
-        zd l = zmul(A[r + c * ld], inv);
+        C l = zmul(A[r + c * ld], inv);
         A[r + c * ld] = l;
         for (int cc = c + 1; cc < j0 + jb; ++cc)
           A[r + cc * ld] = zsub(A[r + cc * ld], zmul(l, A[c + cc * ld]));
@@ -321,29 +378,31 @@ __global__ __launch_bounds__(256) void k_getrf_panel(const LuDesc* lus, int j0, 
 }
 
 // apply the swaps of panel [j0, j0+jb) to the columns outside the panel
-__global__ void k_laswp_panel(const LuDesc* lus, int j0) {
-  const LuDesc L = lus[blockIdx.y];
+template <class R>
+__global__ void k_laswp_panel(const LuDescT<R>* lus, int j0) {
+  const LuDescT<R> L = lus[blockIdx.y];
   const int jb = min(PMX_LU_NB, L.n - j0);
   if (jb <= 0) return;
   int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= L.n - jb) return;
   if (col >= j0) col += jb;
-  zd* A = L.a + col * L.ld;
+  cx<R>* A = L.a + col * L.ld;
   for (int c = j0; c < j0 + jb; ++c) {
     int p = L.ipiv[c];
     if (p != c) {
-      zd t = A[c];
+      cx<R> t = A[c];
       A[c] = A[p];
       A[p] = t;
     }
   }
 }
 
+template <class R>
 struct FLuTrsm {
-  const LuDesc* d;
+  const LuDescT<R>* d;
   int j0;
-  __device__ bool operator()(int b, TrsmArgs& a) const {
-    LuDesc L = d[b];
+  __device__ bool operator()(int b, TrsmArgs<R>& a) const {
+    LuDescT<R> L = d[b];
     int jb = min(PMX_LU_NB, L.n - j0);
     if (jb <= 0 || L.n - j0 - jb <= 0) return false;
     a.T = L.a + j0 + j0 * L.ld;
@@ -356,11 +415,12 @@ struct FLuTrsm {
   }
 };
 
+template <class R>
 struct FLuUpd {
-  const LuDesc* d;
+  const LuDescT<R>* d;
   int j0;
-  __device__ bool operator()(int b, GemmArgs& g) const {
-    LuDesc L = d[b];
+  __device__ bool operator()(int b, GemmArgsT<R>& g) const {
+    LuDescT<R> L = d[b];
     int jb = min(PMX_LU_NB, L.n - j0);
     int r = L.n - j0 - jb;
     if (jb <= 0 || r <= 0) return false;
@@ -377,47 +437,50 @@ struct FLuUpd {
   }
 };
 
-void la_getrf(const LuDesc* d_lu, int batch, int max_n, int* d_info, hipStream_t s) {
+template <class R>
+void la_getrf(const LuDescT<R>* d_lu, int batch, int max_n, int* d_info, hipStream_t s) {
   if (batch <= 0 || max_n <= 0) return;
   for (int j0 = 0; j0 < max_n; j0 += PMX_LU_NB) {
     {
       KScope ks(PK_GETRF_PANEL, s);
-      hipLaunchKernelGGL(k_getrf_panel, dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      hipLaunchKernelGGL(k_getrf_panel<R>, dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
     }
-    hipLaunchKernelGGL(k_laswp_panel, dim3((max_n + 255) / 256, batch), dim3(256), 0, s, d_lu, j0);
+    hipLaunchKernelGGL(k_laswp_panel<R>, dim3((max_n + 255) / 256, batch), dim3(256), 0, s, d_lu, j0);
     int rem = max_n - j0 - PMX_LU_NB;
     if (rem > 0) {
-      launch_trsm_small<false, true>(FLuTrsm{d_lu, j0}, batch, rem, s);
-      launch_zgemm<OP_N, OP_N>(FLuUpd{d_lu, j0}, batch, rem, rem, zmk(-1, 0), zmk(1, 0), s);
+      launch_trsm_small<R, false, true>(FLuTrsm<R>{d_lu, j0}, batch, rem, s);
+      launch_zgemm<R, OP_N, OP_N>(FLuUpd<R>{d_lu, j0}, batch, rem, rem, cmk<R>(-1, 0), cmk<R>(1, 0), s);
     }
   }
 }
 
 // ---------------------------------------------------------------------------------
 // getrs
-__global__ void k_laswp_rhs(const LuDesc* lus, const Mat* bs) {
-  const LuDesc L = lus[blockIdx.y];
-  const Mat B = bs[blockIdx.y];
+template <class R>
+__global__ void k_laswp_rhs(const LuDescT<R>* lus, const MatT<R>* bs) {
+  const LuDescT<R> L = lus[blockIdx.y];
+  const MatT<R> B = bs[blockIdx.y];
   int col = blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= B.n) return;
-  zd* x = B.p + col * B.ld;
+  cx<R>* x = B.p + col * B.ld;
   for (int c = 0; c < L.n; ++c) {
     int p = L.ipiv[c];
     if (p != c) {
-      zd t = x[c];
+      cx<R> t = x[c];
       x[c] = x[p];
       x[p] = t;
     }
   }
 }
 
+template <class R>
 struct FRsTrsm {
-  const LuDesc* d;
-  const Mat* b;
+  const LuDescT<R>* d;
+  const MatT<R>* b;
   int j0;
-  __device__ bool operator()(int i, TrsmArgs& a) const {
-    LuDesc L = d[i];
-    Mat B = b[i];
+  __device__ bool operator()(int i, TrsmArgs<R>& a) const {
+    LuDescT<R> L = d[i];
+    MatT<R> B = b[i];
     int jb = min(PMX_LU_NB, L.n - j0);
     if (jb <= 0 || B.n <= 0) return false;
     a.T = L.a + j0 + j0 * L.ld;
@@ -430,13 +493,14 @@ struct FRsTrsm {
   }
 };
 
+template <class R>
 struct FRsFwd {
-  const LuDesc* d;
-  const Mat* b;
+  const LuDescT<R>* d;
+  const MatT<R>* b;
   int j0;
-  __device__ bool operator()(int i, GemmArgs& g) const {
-    LuDesc L = d[i];
-    Mat B = b[i];
+  __device__ bool operator()(int i, GemmArgsT<R>& g) const {
+    LuDescT<R> L = d[i];
+    MatT<R> B = b[i];
     int jb = min(PMX_LU_NB, L.n - j0);
     int r = L.n - j0 - jb;
     if (jb <= 0 || r <= 0 || B.n <= 0) return false;
@@ -453,13 +517,14 @@ struct FRsFwd {
   }
 };
 
+template <class R>
 struct FRsBwd {
-  const LuDesc* d;
-  const Mat* b;
+  const LuDescT<R>* d;
+  const MatT<R>* b;
   int j0;
-  __device__ bool operator()(int i, GemmArgs& g) const {
-    LuDesc L = d[i];
-    Mat B = b[i];
+  __device__ bool operator()(int i, GemmArgsT<R>& g) const {
+    LuDescT<R> L = d[i];
+    MatT<R> B = b[i];
     int jb = min(PMX_LU_NB, L.n - j0);
     if (jb <= 0 || j0 <= 0 || B.n <= 0) return false;
     g.m = j0;
@@ -475,35 +540,36 @@ struct FRsBwd {
   }
 };
 
-void la_getrs(const LuDesc* d_lu, const Mat* d_b, int batch, int max_n, int max_nrhs, hipStream_t s) {
+template <class R>
+void la_getrs(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max_n, int max_nrhs, hipStream_t s) {
   if (batch <= 0 || max_n <= 0 || max_nrhs <= 0) return;
-  hipLaunchKernelGGL(k_laswp_rhs, dim3((max_nrhs + 63) / 64, batch), dim3(64), 0, s, d_lu, d_b);
+  const cx<R> one = cmk<R>(1, 0), mone = cmk<R>(-1, 0);
+  hipLaunchKernelGGL(k_laswp_rhs<R>, dim3((max_nrhs + 63) / 64, batch), dim3(64), 0, s, d_lu, d_b);
   const int nblk = (max_n + PMX_LU_NB - 1) / PMX_LU_NB;
   for (int bk = 0; bk < nblk; ++bk) {
     int j0 = bk * PMX_LU_NB;
-    launch_trsm_small<false, true>(FRsTrsm{d_lu, d_b, j0}, batch, max_nrhs, s);
+    launch_trsm_small<R, false, true>(FRsTrsm<R>{d_lu, d_b, j0}, batch, max_nrhs, s);
     int rem = max_n - j0 - PMX_LU_NB;
-    if (rem > 0) launch_zgemm<OP_N, OP_N>(FRsFwd{d_lu, d_b, j0}, batch, rem, max_nrhs, zmk(-1, 0), zmk(1, 0), s);
+    if (rem > 0) launch_zgemm<R, OP_N, OP_N>(FRsFwd<R>{d_lu, d_b, j0}, batch, rem, max_nrhs, mone, one, s);
   }
   for (int bk = nblk - 1; bk >= 0; --bk) {
     int j0 = bk * PMX_LU_NB;
-    launch_trsm_small<true, false>(FRsTrsm{d_lu, d_b, j0}, batch, max_nrhs, s);
-    if (j0 > 0) launch_zgemm<OP_N, OP_N>(FRsBwd{d_lu, d_b, j0}, batch, j0, max_nrhs, zmk(-1, 0), zmk(1, 0), s);
+    launch_trsm_small<R, true, false>(FRsTrsm<R>{d_lu, d_b, j0}, batch, max_nrhs, s);
+    if (j0 > 0) launch_zgemm<R, OP_N, OP_N>(FRsBwd<R>{d_lu, d_b, j0}, batch, j0, max_nrhs, mone, one, s);
   }
 }
 
 // ---------------------------------------------------------------------------------
-// Householder QR (only R is kept)
-// Householder QR as a tree of in-LDS block factorisations (TSQR panels).
+// Householder QR as a tree of in-LDS block factorisations (TSQR panels); only R is kept.
 //
 // Panel [j0, j0+jb) of rows [j0, m): the rows are cut into blocks of PMX_TS_BR rows; each
-// block is factored in LDS by one workgroup (16 Householder steps), leaving its R in the
-// block's first jb rows.  The stacked R factors form the rows of the next tree level
-// (block b, row r < jb of level L-1 becomes row b*jb + r of level L), factored the same
-// way until a single block remains, whose R is the panel's R in rows j0 .. j0+jb-1.
-// After each tree level the trailing columns of the same rows receive the block
-// reflectors Q_b^H = I - V_b T_b^H V_b^H (one fused kernel: W = V^H A, A -= (V T^H) W).
-// Only R is kept, so the order of the untouched remaining rows is free.
+// block is factored in LDS by one workgroup, leaving its R in the block's first jb rows.
+// The stacked R factors form the rows of the next tree level (block b, row r < jb of
+// level L-1 becomes row b*jb + r of level L), factored the same way until a single block
+// remains, whose R is the panel's R in rows j0 .. j0+jb-1.  After each tree level the
+// trailing columns of the same rows receive the block reflectors
+// Q_b^H = I - V_b T_b^H V_b^H (one fused kernel: W = V^H A, A -= (V T^H) W).  Only R is
+// kept, so the order of the untouched remaining rows is free.
 #define PMX_TS_BR 256
 
 struct TsGeom {
@@ -551,25 +617,16 @@ __device__ inline int ts_phys(int lr, int L, int jb, int j0, const TsGeom& g) {
   return j0 + lr;
 }
 
-__device__ inline double ts_block_sum(double v, double* red) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0;
-#pragma unroll
-  for (int w = 0; w < PMX_TS_BR / 64; ++w) s += red[w];
-  return s;
-}
-
 // One block of one tree level: Householder QR of its rows of the panel, entirely in LDS.
 // Columns are owned cyclically by the four waves (column q by wave q % 4), each lane
 // holding rows lane + 64k; a column's dot products are reduced inside its owner wave, so a
 // step costs two barriers: the owner of column i forms the reflector, then every wave
 // applies it to its own columns and forms its share of the compact-WY inner products.
-__global__ __launch_bounds__(PMX_TS_BR) void k_ts_leaf(const QrDesc* qrs, int j0, int L) {
-  const QrDesc Q = qrs[blockIdx.y];
+// The Householder norm is accumulated in FP64 for both real types.
+template <class R>
+__global__ __launch_bounds__(PMX_TS_BR) void k_ts_leaf(const QrDescT<R>* qrs, int j0, int L) {
+  typedef cx<R> C;
+  const QrDescT<R> Q = qrs[blockIdx.y];
   const int kmax = min(Q.m, Q.c);
   const int jb = min(PMX_QR_NB, kmax - j0);
   if (jb <= 0) return;
@@ -581,49 +638,49 @@ __global__ __launch_bounds__(PMX_TS_BR) void k_ts_leaf(const QrDesc* qrs, int j0
   const int nrb = min(PMX_TS_BR, ts_sel(L, g.mr0, g.mr1, g.mr2, g.mr3) - b * PMX_TS_BR);
   constexpr int NW = PMX_TS_BR / 64;           // waves
   constexpr int RPL = PMX_TS_BR / 64;          // rows per lane
-  __shared__ zd Ps[PMX_QR_NB][PMX_TS_BR];      // panel block, column major; R above, V below
-  __shared__ zd vs[PMX_TS_BR];                 // current reflector
-  __shared__ zd Ts[PMX_QR_NB][PMX_QR_NB + 1];
-  __shared__ zd zs[PMX_QR_NB];
+  __shared__ C Ps[PMX_QR_NB][PMX_TS_BR];       // panel block, column major; R above, V below
+  __shared__ C vs[PMX_TS_BR];                  // current reflector
+  __shared__ C Ts[PMX_QR_NB][PMX_QR_NB + 1];
+  __shared__ C zs[PMX_QR_NB];
   __shared__ double sh_tau;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int phys = (t < nrb) ? ts_phys(b * PMX_TS_BR + t, L, jb, j0, g) : -1;
-  zd* A = Q.a;
+  C* A = Q.a;
   const int64_t ld = Q.ld;
   {
     const int pr = phys >= 0 ? phys : j0;
-    zd tmpv[PMX_QR_NB];
+    C tmpv[PMX_QR_NB];
 #pragma unroll
     for (int i = 0; i < PMX_QR_NB; ++i) tmpv[i] = A[pr + (int64_t)min(j0 + i, Q.c - 1) * ld];
 #pragma unroll
-    for (int i = 0; i < PMX_QR_NB; ++i) Ps[i][t] = (phys >= 0 && i < jb) ? tmpv[i] : zmk(0, 0);
+    for (int i = 0; i < PMX_QR_NB; ++i) Ps[i][t] = (phys >= 0 && i < jb) ? tmpv[i] : cmk<R>(0, 0);
   }
   __syncthreads();
   const int nref = min(jb, nrb);
   for (int i = 0; i < nref; ++i) {
     if (wave == (i % NW)) {
       // owner wave: norm, Householder parameters (every lane computes them), reflector
-      zd x[RPL];
+      C x[RPL];
       double p = 0;
 #pragma unroll
       for (int k = 0; k < RPL; ++k) {
         const int r = lane + 64 * k;
         x[k] = Ps[i][r];
-        if (r >= i) p += zabs2(x[k]);
+        if (r >= i) p += (double)x[k].re * x[k].re + (double)x[k].im * x[k].im;
       }
       const double xn = sqrt(wave_sum(p));
-      const zd alpha = Ps[i][i];
-      const double aa = sqrt(zabs2(alpha));
+      const C alpha = Ps[i][i];
+      const double aa = sqrt((double)alpha.re * alpha.re + (double)alpha.im * alpha.im);
       double tau;
-      zd beta, scale;
+      C beta, scale;
       if (xn == 0.0) {
         tau = 0.0;
-        beta = zmk(0, 0);
-        scale = zmk(0, 0);
+        beta = cmk<R>(0, 0);
+        scale = cmk<R>(0, 0);
       } else if (aa == 0.0) {
         tau = 1.0;
-        beta = zmk(-xn, 0);
-        scale = zmk(1.0 / xn, 0);
+        beta = cmk<R>(-xn, 0);
+        scale = cmk<R>(1.0 / xn, 0);
       } else {
         // beta = -alpha |x|/|alpha|, tau = 1 + |alpha|/|x|, scale = conj(alpha)/(|alpha|(|alpha|+|x|))
         const double ip = 1.0 / (aa * xn * (aa + xn));
@@ -634,34 +691,34 @@ __global__ __launch_bounds__(PMX_TS_BR) void k_ts_leaf(const QrDesc* qrs, int j0
 #pragma unroll
       for (int k = 0; k < RPL; ++k) {
         const int r = lane + 64 * k;
-        const zd v = (r == i) ? zmk(1, 0) : ((r > i) ? zmul(x[k], scale) : zmk(0, 0));
+        const C v = (r == i) ? cmk<R>(1, 0) : ((r > i) ? zmul(x[k], scale) : cmk<R>(0, 0));
         vs[r] = v;
         if (r > i) Ps[i][r] = v;
         if (r == i) Ps[i][i] = beta;
       }
       if (lane == 0) {
         sh_tau = tau;
-        Ts[i][i] = zmk(tau, 0);
+        Ts[i][i] = cmk<R>(tau, 0);
       }
     }
     __syncthreads();
-    const double tau = sh_tau;
-    zd vr[RPL];
+    const R tau = (R)sh_tau;
+    C vr[RPL];
 #pragma unroll
     for (int k = 0; k < RPL; ++k) vr[k] = vs[lane + 64 * k];
     for (int q = wave; q < jb; q += NW) {
       if (q > i) {
         // w = v^H P[:, q]; P[:, q] -= tau v w
-        zd pq[RPL];
-        double wr = 0, wi = 0;
+        C pq[RPL];
+        R wr = 0, wi = 0;
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
           pq[k] = Ps[q][lane + 64 * k];
-          const zd pr = zcmul(vr[k], pq[k]);
+          const C pr = zcmul(vr[k], pq[k]);
           wr += pr.re;
           wi += pr.im;
         }
-        const zd w = zscale(zmk(wave_sum(wr), wave_sum(wi)), tau);
+        const C w = zscale(cmk<R>(wave_sum(wr), wave_sum(wi)), tau);
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
           const int r = lane + 64 * k;
@@ -669,23 +726,23 @@ __global__ __launch_bounds__(PMX_TS_BR) void k_ts_leaf(const QrDesc* qrs, int j0
         }
       } else if (q < i) {
         // z_q = V_q^H v for the compact-WY factor
-        double zr = 0, zi = 0;
+        R zr = 0, zi = 0;
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
           const int r = lane + 64 * k;
-          const zd vq = (r == q) ? zmk(1, 0) : ((r > q) ? Ps[q][r] : zmk(0, 0));
-          const zd pr = zcmul(vq, vr[k]);
+          const C vq = (r == q) ? cmk<R>(1, 0) : ((r > q) ? Ps[q][r] : cmk<R>(0, 0));
+          const C pr = zcmul(vq, vr[k]);
           zr += pr.re;
           zi += pr.im;
         }
         zr = wave_sum(zr);
         zi = wave_sum(zi);
-        if (lane == 0) zs[q] = zmk(zr, zi);
+        if (lane == 0) zs[q] = cmk<R>(zr, zi);
       }
     }
     __syncthreads();
     if (t < i) {  // T[0:i, i] = -tau T[0:i, 0:i] z, one row per thread
-      zd s2 = zmk(0, 0);
+      C s2 = cmk<R>(0, 0);
 #pragma unroll 8
       for (int jj = t; jj < i; ++jj) s2 = zadd(s2, zmul(Ts[t][jj], zs[jj]));
       Ts[t][i] = zscale(s2, -tau);
@@ -694,34 +751,37 @@ __global__ __launch_bounds__(PMX_TS_BR) void k_ts_leaf(const QrDesc* qrs, int j0
   __syncthreads();
   // write back: R in the block's first rows, the reflectors V and V T^H to the workspace
   if (phys >= 0 && t < jb) {
-    for (int i = 0; i < jb; ++i) A[phys + (int64_t)(j0 + i) * ld] = (i >= t) ? Ps[i][t] : zmk(0, 0);
+    for (int i = 0; i < jb; ++i) A[phys + (int64_t)(j0 + i) * ld] = (i >= t) ? Ps[i][t] : cmk<R>(0, 0);
   }
   const int64_t wo = ts_sel64(L, g.wo0, g.wo1, g.wo2, g.wo3) + (int64_t)b * PMX_TS_BR * PMX_QR_NB;
-  zd* V = Q.v + wo;
-  zd* VT = Q.t + wo;
-  zd vrow[PMX_QR_NB];
+  C* V = Q.v + wo;
+  C* VT = Q.t + wo;
+  C vrow[PMX_QR_NB];
 #pragma unroll
   for (int i = 0; i < PMX_QR_NB; ++i) {
-    zd v = zmk(0, 0);
-    if (i < nref && t < nrb) v = (t == i) ? zmk(1, 0) : ((t > i) ? Ps[i][t] : zmk(0, 0));
+    C v = cmk<R>(0, 0);
+    if (i < nref && t < nrb) v = (t == i) ? cmk<R>(1, 0) : ((t > i) ? Ps[i][t] : cmk<R>(0, 0));
     vrow[i] = v;
     V[t + (int64_t)i * PMX_TS_BR] = v;
   }
 #pragma unroll
   for (int j = 0; j < PMX_QR_NB; ++j) {
-    zd s2 = zmk(0, 0);
+    C s2 = cmk<R>(0, 0);
 #pragma unroll
     for (int i = j; i < PMX_QR_NB; ++i)
       if (i < nref) s2 = zadd(s2, zmul(vrow[i], zconj(Ts[j][i])));
-    VT[t + (int64_t)j * PMX_TS_BR] = (j < nref) ? s2 : zmk(0, 0);
+    VT[t + (int64_t)j * PMX_TS_BR] = (j < nref) ? s2 : cmk<R>(0, 0);
   }
 }
 
 // trailing update of one block of one tree level: A_b -= (V T^H) (V^H A_b), 64 columns per
 // workgroup, rows streamed through LDS in slices of 32, both products on 16x16x4 MFMA
 #define TSU_ROWS 32
-__global__ __launch_bounds__(256) void k_ts_update(const QrDesc* qrs, int j0, int L) {
-  const QrDesc Q = qrs[blockIdx.z];
+template <class R>
+__global__ __launch_bounds__(256) void k_ts_update(const QrDescT<R>* qrs, int j0, int L) {
+  typedef cx<R> C;
+  typedef typename AccT<R>::type V4;
+  const QrDescT<R> Q = qrs[blockIdx.z];
   const int kmax = min(Q.m, Q.c);
   const int jb = min(PMX_QR_NB, kmax - j0);
   const int nc = Q.c - j0 - jb;
@@ -735,23 +795,23 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDesc* qrs, int j0, in
   if (b >= ts_sel(L, g.nb0, g.nb1, g.nb2, g.nb3)) return;
   const int nrb = min(PMX_TS_BR, ts_sel(L, g.mr0, g.mr1, g.mr2, g.mr3) - b * PMX_TS_BR);
   const int64_t wo = ts_sel64(L, g.wo0, g.wo1, g.wo2, g.wo3) + (int64_t)b * PMX_TS_BR * PMX_QR_NB;
-  const zd* V = Q.v + wo;
-  const zd* VT = Q.t + wo;
-  __shared__ zd Vs[TSU_ROWS][PMX_QR_NB + 1];
-  __shared__ zd As[TSU_ROWS][64 + 1];
-  __shared__ zd Ws[PMX_QR_NB][64 + 1];
+  const C* V = Q.v + wo;
+  const C* VT = Q.t + wo;
+  __shared__ C Vs[TSU_ROWS][PMX_QR_NB + 1];
+  __shared__ C As[TSU_ROWS][64 + 1];
+  __shared__ C Ws[PMX_QR_NB][64 + 1];
   __shared__ int rows[TSU_ROWS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  zd* A = Q.a;
+  C* A = Q.a;
   const int64_t ld = Q.ld;
   const int ccol0 = j0 + jb + c0;
   // W = V^H A_b: output PMX_QR_NB x 64 as (NB/16) x 4 blocks of 16x16, NB/16 per wave
   constexpr int RB = PMX_QR_NB / 16;
-  d4 accR[RB], accI[RB];
+  V4 accR[RB], accI[RB];
 #pragma unroll
   for (int q = 0; q < RB; ++q) {
-    accR[q] = (d4){0, 0, 0, 0};
-    accI[q] = (d4){0, 0, 0, 0};
+    accR[q] = V4{0, 0, 0, 0};
+    accI[q] = V4{0, 0, 0, 0};
   }
   for (int rb = 0; rb < nrb; rb += TSU_ROWS) {
     if (tid < TSU_ROWS) rows[tid] = (rb + tid < nrb) ? ts_phys(b * PMX_TS_BR + rb + tid, L, jb, j0, g) : -1;
@@ -761,7 +821,7 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDesc* qrs, int j0, in
       const int cc = tid >> 5;
       const int pr = rows[rr];
       // the workspace rows exist up to PMX_TS_BR; matrix addresses are clamped
-      zd tv[PMX_QR_NB / 8], ta[8];
+      C tv[PMX_QR_NB / 8], ta[8];
 #pragma unroll
       for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
         tv[pass] = V[rb + rr + (int64_t)(cc + 8 * pass) * PMX_TS_BR];
@@ -770,22 +830,23 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDesc* qrs, int j0, in
       for (int pass = 0; pass < 8; ++pass)
         ta[pass] = A[prc + (int64_t)(ccol0 + min(cc + 8 * pass, nc - 1 - c0)) * ld];
 #pragma unroll
-      for (int pass = 0; pass < PMX_QR_NB / 8; ++pass) Vs[rr][cc + 8 * pass] = (rb + rr < nrb) ? tv[pass] : zmk(0, 0);
+      for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
+        Vs[rr][cc + 8 * pass] = (rb + rr < nrb) ? tv[pass] : cmk<R>(0, 0);
 #pragma unroll
       for (int pass = 0; pass < 8; ++pass)
-        As[rr][cc + 8 * pass] = (pr >= 0 && c0 + cc + 8 * pass < nc) ? ta[pass] : zmk(0, 0);
+        As[rr][cc + 8 * pass] = (pr >= 0 && c0 + cc + 8 * pass < nc) ? ta[pass] : cmk<R>(0, 0);
     }
     __syncthreads();
 #pragma unroll
     for (int kk = 0; kk < TSU_ROWS; kk += 4) {
-      const zd bb = As[kk + (lane >> 4)][wave * 16 + (lane & 15)];
+      const C bb = As[kk + (lane >> 4)][wave * 16 + (lane & 15)];
 #pragma unroll
       for (int q = 0; q < RB; ++q) {
-        const zd a = Vs[kk + (lane >> 4)][q * 16 + (lane & 15)];
-        accR[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, bb.re, accR[q], 0, 0, 0);
-        accR[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, bb.im, accR[q], 0, 0, 0);
-        accI[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, bb.im, accI[q], 0, 0, 0);
-        accI[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, bb.re, accI[q], 0, 0, 0);
+        const C a = Vs[kk + (lane >> 4)][q * 16 + (lane & 15)];
+        accR[q] = mfma16(a.re, bb.re, accR[q]);
+        accR[q] = mfma16(a.im, bb.im, accR[q]);
+        accI[q] = mfma16(a.re, bb.im, accI[q]);
+        accI[q] = mfma16(-a.im, bb.re, accI[q]);
       }
     }
     __syncthreads();
@@ -794,7 +855,7 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDesc* qrs, int j0, in
   for (int q = 0; q < RB; ++q)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      Ws[q * 16 + (lane >> 4) + 4 * r][wave * 16 + (lane & 15)] = zmk(accR[q][r], accI[q][r]);
+      Ws[q * 16 + mfma_row<R>(lane, r)][wave * 16 + (lane & 15)] = cmk<R>(accR[q][r], accI[q][r]);
   __syncthreads();
   // A_b -= VT W: a 32 x 64 slice is 2 x 4 blocks of 16x16, two per wave
   const int rbk = wave & 1;
@@ -805,50 +866,52 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDesc* qrs, int j0, in
     {
       const int rr = tid & (TSU_ROWS - 1);
       const int cc = tid >> 5;
-      zd tv[PMX_QR_NB / 8];
+      C tv[PMX_QR_NB / 8];
 #pragma unroll
       for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
         tv[pass] = VT[rb + rr + (int64_t)(cc + 8 * pass) * PMX_TS_BR];
 #pragma unroll
-      for (int pass = 0; pass < PMX_QR_NB / 8; ++pass) Vs[rr][cc + 8 * pass] = (rb + rr < nrb) ? tv[pass] : zmk(0, 0);
+      for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
+        Vs[rr][cc + 8 * pass] = (rb + rr < nrb) ? tv[pass] : cmk<R>(0, 0);
     }
     __syncthreads();
-    d4 dR[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, dI[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    V4 dR[2] = {V4{0, 0, 0, 0}, V4{0, 0, 0, 0}}, dI[2] = {V4{0, 0, 0, 0}, V4{0, 0, 0, 0}};
 #pragma unroll
     for (int kk = 0; kk < PMX_QR_NB; kk += 4) {
-      const zd a = Vs[rbk * 16 + (lane & 15)][kk + (lane >> 4)];
+      const C a = Vs[rbk * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        const zd bb = Ws[kk + (lane >> 4)][(cbk0 + q) * 16 + (lane & 15)];
-        dR[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, bb.re, dR[q], 0, 0, 0);
-        dR[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.im, bb.im, dR[q], 0, 0, 0);
-        dI[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.re, bb.im, dI[q], 0, 0, 0);
-        dI[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.im, bb.re, dI[q], 0, 0, 0);
+        const C bb = Ws[kk + (lane >> 4)][(cbk0 + q) * 16 + (lane & 15)];
+        dR[q] = mfma16(a.re, bb.re, dR[q]);
+        dR[q] = mfma16(-a.im, bb.im, dR[q]);
+        dI[q] = mfma16(a.re, bb.im, dI[q]);
+        dI[q] = mfma16(a.im, bb.re, dI[q]);
       }
     }
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = rbk * 16 + (lane >> 4) + 4 * r;
+        const int row = rbk * 16 + mfma_row<R>(lane, r);
         const int col = (cbk0 + q) * 16 + (lane & 15);
         const int pr = rows[row];
         if (pr >= 0 && c0 + col < nc) {
-          zd* ap = A + pr + (int64_t)(ccol0 + col) * ld;
-          *ap = zsub(*ap, zmk(dR[q][r], dI[q][r]));
+          C* ap = A + pr + (int64_t)(ccol0 + col) * ld;
+          *ap = zsub(*ap, cmk<R>(dR[q][r], dI[q][r]));
         }
       }
     __syncthreads();
   }
 }
 
-__global__ void k_copy_r(const QrDesc* qrs) {
-  const QrDesc Q = qrs[blockIdx.y];
+template <class R>
+__global__ void k_copy_r(const QrDescT<R>* qrs) {
+  const QrDescT<R> Q = qrs[blockIdx.y];
   const int mb = min(Q.m, Q.c);
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)mb * Q.c) return;
   const int r = (int)(e % mb), c = (int)(e / mb);
-  Q.r[e] = (r <= c) ? Q.a[r + c * Q.ld] : zmk(0, 0);
+  Q.r[e] = (r <= c) ? Q.a[r + c * Q.ld] : cmk<R>(0, 0);
 }
 
 int64_t la_geqrf_workspace(int m) {
@@ -864,7 +927,8 @@ int64_t la_geqrf_workspace(int m) {
   return tot;
 }
 
-void la_geqrf_r(const QrDesc* d_qr, int batch, int max_m, int max_c, hipStream_t s) {
+template <class R>
+void la_geqrf_r(const QrDescT<R>* d_qr, int batch, int max_m, int max_c, hipStream_t s) {
   if (batch <= 0 || max_m <= 0 || max_c <= 0) return;
   // four tree levels cover PMX_TS_BR * (PMX_TS_BR / PMX_QR_NB)^3 rows
   const int64_t cap = (int64_t)PMX_TS_BR * (PMX_TS_BR / PMX_QR_NB) * (PMX_TS_BR / PMX_QR_NB) * (PMX_TS_BR / PMX_QR_NB);
@@ -877,61 +941,133 @@ void la_geqrf_r(const QrDesc* d_qr, int batch, int max_m, int max_c, hipStream_t
       const int nb = (mr + PMX_TS_BR - 1) / PMX_TS_BR;
       {
         KScope ks(PK_TS_LEAF, s);
-        hipLaunchKernelGGL(k_ts_leaf, dim3(nb, batch), dim3(PMX_TS_BR), 0, s, d_qr, j0, L);
+        hipLaunchKernelGGL(k_ts_leaf<R>, dim3(nb, batch), dim3(PMX_TS_BR), 0, s, d_qr, j0, L);
       }
       if (nc > 0) {
         KScope ks(PK_TS_UPDATE, s);
-        hipLaunchKernelGGL(k_ts_update, dim3((nc + 63) / 64, nb, batch), dim3(256), 0, s, d_qr, j0, L);
+        hipLaunchKernelGGL(k_ts_update<R>, dim3((nc + 63) / 64, nb, batch), dim3(256), 0, s, d_qr, j0, L);
       }
       if (nb <= 1) break;
       mr = nb * PMX_QR_NB;
     }
   }
   int64_t tot = (int64_t)kmax * max_c;
-  hipLaunchKernelGGL(k_copy_r, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, s, d_qr);
+  hipLaunchKernelGGL(k_copy_r<R>, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, s, d_qr);
 }
 
 // ---------------------------------------------------------------------------------
 // column pivoted QR with threshold rank
 #define CP_NT 512
-__global__ __launch_bounds__(CP_NT) void k_cpqr(const CpqrDesc* cps, double tol, const int* kmin, int init) {
-  const CpqrDesc C = cps[blockIdx.x];
-  if (C.c <= 0) return;
-  extern __shared__ zd vs[];  // [mb]
+// the reflector in dynamic LDS (declared once as double for every real type)
+extern __shared__ double cp_lds[];
+
+// Householder vector of the pivot column: beta = -sign(alpha) |x|, tau = 1 + |alpha|/|x|,
+// entries below the diagonal scaled by 1/(alpha - beta).
+template <class R>
+__device__ inline void cp_reflector(cx<R> alpha, double xn, cx<R>& beta, double& tau, cx<R>& scale) {
+  const double aa = sqrt((double)alpha.re * alpha.re + (double)alpha.im * alpha.im);
+  const cx<R> sg = aa > 0 ? zscale(alpha, 1.0 / aa) : cmk<R>(1, 0);
+  beta = zscale(sg, -xn);
+  tau = 1.0 + aa / xn;
+  // 1/(alpha - beta) = conj(sg) / (aa + xn)
+  scale = zscale(zconj(sg), 1.0 / (aa + xn));
+}
+
+// Relative squared norm below which a downdated column norm is recomputed: the downdate
+// loses the digits of the ratio, so at a squared ratio under the square root of the unit
+// roundoff of the data it no longer carries any (the criterion of LAPACK's xGEQP3).
+template <class R>
+__device__ constexpr double cp_recompute_ratio();
+template <>
+__device__ constexpr double cp_recompute_ratio<double>() {
+  return 1.5e-8;
+}
+template <>
+__device__ constexpr double cp_recompute_ratio<float>() {
+  return 2.5e-4;
+}
+
+// apply the current reflector (vs, rows j..mb-1) to column l and downdate its norm;
+// one wave per column, lane 0 ends with row j
+template <class R>
+__device__ inline void cp_apply_column(cx<R>* col, const cx<R>* vs, int j, int mb, double tau, double* nrm,
+                                       int c, int l, int lane) {
+  typedef cx<R> C;
+  R wr = 0, wi = 0;
+  for (int r = j + lane; r < mb; r += 64) {
+    const C t = zcmul(vs[r - j], col[r]);
+    wr += t.re;
+    wi += t.im;
+  }
+  wr = wave_sum(wr);
+  wi = wave_sum(wi);
+  const C w = zscale(cmk<R>(wr, wi), tau);
+  double tail = 0;
+  C first = cmk<R>(0, 0);
+  for (int r = j + lane; r < mb; r += 64) {
+    const C nv = zsub(col[r], zmul(vs[r - j], w));
+    col[r] = nv;
+    if (r > j) tail += (double)nv.re * nv.re + (double)nv.im * nv.im;
+    else first = nv;
+  }
+  // norm downdating with recomputation on cancellation
+  const double fr = __shfl((double)first.re, 0, 64), fi = __shfl((double)first.im, 0, 64);
+  const double nw2 = nrm[l] - (fr * fr + fi * fi);
+  if (nw2 <= cp_recompute_ratio<R>() * nrm[c + l]) {
+    tail = wave_sum(tail);
+    if (lane == 0) {
+      nrm[l] = tail;
+      nrm[c + l] = tail;
+    }
+  } else if (lane == 0) {
+    nrm[l] = nw2;
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(CP_NT) void k_cpqr(const CpqrDescT<R>* cps, double tol, const int* kmin, int init) {
+  typedef cx<R> C;
+  const CpqrDescT<R> Cd = cps[blockIdx.x];
+  if (Cd.c <= 0) return;
+  C* vs = reinterpret_cast<C*>(cp_lds);  // [mb]
   __shared__ double redv[CP_NT / 64];
   __shared__ int redi[CP_NT / 64];
   __shared__ double sh_tau;
   __shared__ int sh_stop;
+  __shared__ C sh_scale;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = CP_NT / 64;
-  zd* B = C.b;
-  const int mb = C.mb, c = C.c;
+  C* B = Cd.b;
+  const int mb = Cd.mb, c = Cd.c;
   const int64_t ld = mb;
   const int kmax = min(mb, c);
-  double* nrm = C.nrm;
+  double* nrm = Cd.nrm;
   if (init) {
     for (int l = wave; l < c; l += nw) {
       double p = 0;
-      for (int r = lane; r < mb; r += 64) p += zabs2(B[r + l * ld]);
+      for (int r = lane; r < mb; r += 64) {
+        const C x = B[r + l * ld];
+        p += (double)x.re * x.re + (double)x.im * x.im;
+      }
       p = wave_sum(p);
       if (lane == 0) {
         nrm[l] = p;
         nrm[c + l] = p;
-        C.piv[l] = l;
+        Cd.piv[l] = l;
       }
     }
     if (tid == 0) {
-      C.state[0] = 0;
-      C.state[1] = -1;
-      C.state[2] = 0;
-      *C.r11 = 0.0;
+      Cd.state[0] = 0;
+      Cd.state[1] = -1;
+      Cd.state[2] = 0;
+      *Cd.r11 = 0.0;
     }
     __syncthreads();
     __threadfence_block();
   }
-  int j = C.state[0];
+  int j = Cd.state[0];
   const int target = (tol > 0.0) ? kmax : min(kmax, kmin ? kmin[blockIdx.x] : kmax);
-  double r11 = *C.r11;
+  double r11 = *Cd.r11;
   while (j < target) {
     double best = -1.0;
     int bi = -1;
@@ -939,16 +1075,16 @@ __global__ __launch_bounds__(CP_NT) void k_cpqr(const CpqrDesc* cps, double tol,
     const int p = block_argmax<CP_NT>(best, bi, redv, redi, nullptr);
     if (p != j) {
       for (int r = tid; r < mb; r += CP_NT) {
-        zd t = B[r + j * ld];
+        C t = B[r + j * ld];
         B[r + j * ld] = B[r + p * ld];
         B[r + p * ld] = t;
       }
     }
     __syncthreads();
     if (tid == 0 && p != j) {
-      int ti = C.piv[j];
-      C.piv[j] = C.piv[p];
-      C.piv[p] = ti;
+      int ti = Cd.piv[j];
+      Cd.piv[j] = Cd.piv[p];
+      Cd.piv[p] = ti;
       double t0 = nrm[j];
       nrm[j] = nrm[p];
       nrm[p] = t0;
@@ -957,7 +1093,10 @@ __global__ __launch_bounds__(CP_NT) void k_cpqr(const CpqrDesc* cps, double tol,
       nrm[c + p] = t0;
     }
     double part = 0;
-    for (int r = j + tid; r < mb; r += CP_NT) part += zabs2(B[r + j * ld]);
+    for (int r = j + tid; r < mb; r += CP_NT) {
+      const C x = B[r + j * ld];
+      part += (double)x.re * x.re + (double)x.im * x.im;
+    }
     const double xn = sqrt(block_sum<CP_NT>(part, redv));
     if (tid == 0) {
       if (j == 0) r11 = xn;
@@ -965,66 +1104,33 @@ __global__ __launch_bounds__(CP_NT) void k_cpqr(const CpqrDesc* cps, double tol,
       if (xn == 0.0) stop = 1;
       else if (tol > 0.0 && xn <= tol * r11) stop = 1;
       sh_stop = stop;
-      zd alpha = B[j + j * ld];
-      double aa = sqrt(zabs2(alpha));
       if (!stop) {
-        zd sg = aa > 0 ? zscale(alpha, 1.0 / aa) : zmk(1, 0);
-        zd beta = zscale(sg, -xn);
-        sh_tau = 1.0 + aa / xn;
-        vs[0] = zdiv(zmk(1, 0), zsub(alpha, beta));   // scale, replaced by 1 below
+        C beta, scale;
+        double tau;
+        cp_reflector<R>(B[j + j * ld], xn, beta, tau, scale);
+        sh_tau = tau;
+        sh_scale = scale;
         B[j + j * ld] = beta;
       }
     }
     __syncthreads();
     if (sh_stop) break;
-    const zd scale = vs[0];
-    __syncthreads();
+    const C scale = sh_scale;
     for (int r = j + tid; r < mb; r += CP_NT) {
-      zd v = (r == j) ? zmk(1, 0) : zmul(B[r + j * ld], scale);
+      C v = (r == j) ? cmk<R>(1, 0) : zmul(B[r + j * ld], scale);
       vs[r - j] = v;
-      if (r > j) B[r + j * ld] = zmk(0, 0);
+      if (r > j) B[r + j * ld] = cmk<R>(0, 0);
     }
     __syncthreads();
     const double tau = sh_tau;
-    for (int l = j + 1 + wave; l < c; l += nw) {
-      zd* col = B + l * ld;
-      double wr = 0, wi = 0;
-      for (int r = j + lane; r < mb; r += 64) {
-        zd t = zcmul(vs[r - j], col[r]);
-        wr += t.re;
-        wi += t.im;
-      }
-      wr = wave_sum(wr);
-      wi = wave_sum(wi);
-      const zd w = zscale(zmk(wr, wi), tau);
-      double tail = 0;
-      zd first = zmk(0, 0);
-      for (int r = j + lane; r < mb; r += 64) {
-        zd nv = zsub(col[r], zmul(vs[r - j], w));
-        col[r] = nv;
-        if (r > j) tail += zabs2(nv);
-        else first = nv;
-      }
-      // norm downdating with recomputation on cancellation; lane 0 holds row j
-      zd rjl = zmk(__shfl(first.re, 0, 64), __shfl(first.im, 0, 64));
-      double nw2 = nrm[l] - zabs2(rjl);
-      if (nw2 <= 1e-8 * nrm[c + l]) {
-        tail = wave_sum(tail);
-        if (lane == 0) {
-          nrm[l] = tail;
-          nrm[c + l] = tail;
-        }
-      } else if (lane == 0) {
-        nrm[l] = nw2;
-      }
-    }
+    for (int l = j + 1 + wave; l < c; l += nw) cp_apply_column<R>(B + l * ld, vs, j, mb, tau, nrm, c, l, lane);
     __syncthreads();
     ++j;
   }
   if (tid == 0) {
-    C.state[0] = j;
-    if (tol > 0.0) C.state[1] = j;
-    *C.r11 = r11;
+    Cd.state[0] = j;
+    if (tol > 0.0) Cd.state[1] = j;
+    *Cd.r11 = r11;
   }
 }
 
@@ -1032,68 +1138,75 @@ __global__ __launch_bounds__(CP_NT) void k_cpqr(const CpqrDesc* cps, double tol,
 // swaps it in and forms the reflector (one workgroup per matrix), a second applies the
 // reflector to the trailing columns (16 columns per workgroup, one wave per column) and
 // downdates their norms.  state[2] marks a finished matrix; finished matrices bump *ndone.
-__global__ __launch_bounds__(256) void k_cpqr_init(const CpqrDesc* cps, int init) {
-  const CpqrDesc C = cps[blockIdx.y];
+template <class R>
+__global__ __launch_bounds__(256) void k_cpqr_init(const CpqrDescT<R>* cps, int init) {
+  const CpqrDescT<R> Cd = cps[blockIdx.y];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int l = blockIdx.x * 4 + wave;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && C.c > 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && Cd.c > 0) {
     if (init) {
-      C.state[0] = 0;
-      C.state[1] = -1;
-      *C.r11 = 0.0;
+      Cd.state[0] = 0;
+      Cd.state[1] = -1;
+      *Cd.r11 = 0.0;
     }
-    C.state[2] = 0;
+    Cd.state[2] = 0;
   }
-  if (!init || l >= C.c) return;
+  if (!init || l >= Cd.c) return;
   double p = 0;
-  for (int r = lane; r < C.mb; r += 64) p += zabs2(C.b[r + (int64_t)l * C.mb]);
+  for (int r = lane; r < Cd.mb; r += 64) {
+    const cx<R> x = Cd.b[r + (int64_t)l * Cd.mb];
+    p += (double)x.re * x.re + (double)x.im * x.im;
+  }
   p = wave_sum(p);
   if (lane == 0) {
-    C.nrm[l] = p;
-    C.nrm[C.c + l] = p;
-    C.piv[l] = l;
+    Cd.nrm[l] = p;
+    Cd.nrm[Cd.c + l] = p;
+    Cd.piv[l] = l;
   }
 }
 
-__global__ __launch_bounds__(256) void k_cpqr_pivot(const CpqrDesc* cps, double tol, const int* kmin, int* ndone) {
-  const CpqrDesc C = cps[blockIdx.x];
-  if (C.c <= 0 || C.state[2]) return;
+template <class R>
+__global__ __launch_bounds__(256) void k_cpqr_pivot(const CpqrDescT<R>* cps, double tol, const int* kmin,
+                                                    int* ndone) {
+  typedef cx<R> C;
+  const CpqrDescT<R> Cd = cps[blockIdx.x];
+  if (Cd.c <= 0 || Cd.state[2]) return;
   __shared__ double redv[4];
   __shared__ int redi[4];
   __shared__ int sh_stop;
-  __shared__ zd sh_scale;
+  __shared__ C sh_scale;
   const int tid = threadIdx.x;
-  zd* B = C.b;
-  const int mb = C.mb, c = C.c;
+  C* B = Cd.b;
+  const int mb = Cd.mb, c = Cd.c;
   const int64_t ld = mb;
   const int kmax = min(mb, c);
   const int target = (tol > 0.0) ? kmax : min(kmax, kmin ? kmin[blockIdx.x] : kmax);
-  const int j = C.state[0];
+  const int j = Cd.state[0];
   if (j >= target) {
     if (tid == 0) {
-      C.state[2] = 1;
-      if (tol > 0.0) C.state[1] = j;
+      Cd.state[2] = 1;
+      if (tol > 0.0) Cd.state[1] = j;
       atomicAdd(ndone, 1);
     }
     return;
   }
-  double* nrm = C.nrm;
+  double* nrm = Cd.nrm;
   double best = -1.0;
   int bi = -1;
   for (int l = j + tid; l < c; l += 256) argmax_pair(best, bi, nrm[l], l);
   const int p = block_argmax<256>(best, bi, redv, redi, nullptr);
   if (p != j) {
     for (int r = tid; r < mb; r += 256) {
-      zd t = B[r + j * ld];
+      C t = B[r + j * ld];
       B[r + j * ld] = B[r + p * ld];
       B[r + p * ld] = t;
     }
   }
   __syncthreads();
   if (tid == 0 && p != j) {
-    int ti = C.piv[j];
-    C.piv[j] = C.piv[p];
-    C.piv[p] = ti;
+    int ti = Cd.piv[j];
+    Cd.piv[j] = Cd.piv[p];
+    Cd.piv[p] = ti;
     double t0 = nrm[j];
     nrm[j] = nrm[p];
     nrm[p] = t0;
@@ -1102,115 +1215,91 @@ __global__ __launch_bounds__(256) void k_cpqr_pivot(const CpqrDesc* cps, double 
     nrm[c + p] = t0;
   }
   double part = 0;
-  for (int r = j + tid; r < mb; r += 256) part += zabs2(B[r + j * ld]);
+  for (int r = j + tid; r < mb; r += 256) {
+    const C x = B[r + j * ld];
+    part += (double)x.re * x.re + (double)x.im * x.im;
+  }
   const double xn = sqrt(block_sum<256>(part, redv));
   if (tid == 0) {
-    double r11 = (j == 0) ? xn : *C.r11;
-    if (j == 0) *C.r11 = xn;
+    double r11 = (j == 0) ? xn : *Cd.r11;
+    if (j == 0) *Cd.r11 = xn;
     int stop = 0;
     if (xn == 0.0) stop = 1;
     else if (tol > 0.0 && xn <= tol * r11) stop = 1;
     sh_stop = stop;
     if (stop) {
-      C.state[2] = 1;
-      if (tol > 0.0) C.state[1] = j;
+      Cd.state[2] = 1;
+      if (tol > 0.0) Cd.state[1] = j;
       atomicAdd(ndone, 1);
     } else {
-      const zd alpha = B[j + j * ld];
-      const double aa = sqrt(zabs2(alpha));
-      const zd sg = aa > 0 ? zscale(alpha, 1.0 / aa) : zmk(1, 0);
-      const zd beta = zscale(sg, -xn);
-      *C.tau = 1.0 + aa / xn;
-      sh_scale = zdiv(zmk(1, 0), zsub(alpha, beta));
+      C beta, scale;
+      double tau;
+      cp_reflector<R>(B[j + j * ld], xn, beta, tau, scale);
+      *Cd.tau = tau;
+      sh_scale = scale;
       B[j + j * ld] = beta;
     }
   }
   __syncthreads();
   if (sh_stop) return;
-  const zd scale = sh_scale;
+  const C scale = sh_scale;
   for (int r = j + tid; r < mb; r += 256) {
     if (r == j) {
-      C.v[0] = zmk(1, 0);
+      Cd.v[0] = cmk<R>(1, 0);
     } else {
-      C.v[r - j] = zmul(B[r + j * ld], scale);
-      B[r + j * ld] = zmk(0, 0);
+      Cd.v[r - j] = zmul(B[r + j * ld], scale);
+      B[r + j * ld] = cmk<R>(0, 0);
     }
   }
   if (tid == 0) {
-    C.state[3] = j;
-    C.state[0] = j + 1;
+    Cd.state[3] = j;
+    Cd.state[0] = j + 1;
   }
 }
 
-__global__ __launch_bounds__(256) void k_cpqr_update(const CpqrDesc* cps) {
-  const CpqrDesc C = cps[blockIdx.y];
-  if (C.c <= 0 || C.state[2]) return;
-  const int j = C.state[3];
+template <class R>
+__global__ __launch_bounds__(256) void k_cpqr_update(const CpqrDescT<R>* cps) {
+  typedef cx<R> C;
+  const CpqrDescT<R> Cd = cps[blockIdx.y];
+  if (Cd.c <= 0 || Cd.state[2]) return;
+  const int j = Cd.state[3];
   const int l0 = blockIdx.x * 16;
-  if (l0 + 16 <= j + 1 || l0 >= C.c) return;
-  extern __shared__ zd vs[];
+  if (l0 + 16 <= j + 1 || l0 >= Cd.c) return;
+  C* vs = reinterpret_cast<C*>(cp_lds);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int mb = C.mb, c = C.c;
+  const int mb = Cd.mb, c = Cd.c;
   const int64_t ld = mb;
-  for (int r = j + tid; r < mb; r += 256) vs[r - j] = C.v[r - j];
+  for (int r = j + tid; r < mb; r += 256) vs[r - j] = Cd.v[r - j];
   __syncthreads();
-  const double tau = *C.tau;
-  double* nrm = C.nrm;
+  const double tau = *Cd.tau;
   for (int l = l0 + wave; l < min(l0 + 16, c); l += 4) {
     if (l <= j) continue;
-    zd* col = C.b + (int64_t)l * ld;
-    double wr = 0, wi = 0;
-    for (int r = j + lane; r < mb; r += 64) {
-      const zd t = zcmul(vs[r - j], col[r]);
-      wr += t.re;
-      wi += t.im;
-    }
-    wr = wave_sum(wr);
-    wi = wave_sum(wi);
-    const zd w = zscale(zmk(wr, wi), tau);
-    double tail = 0;
-    zd first = zmk(0, 0);
-    for (int r = j + lane; r < mb; r += 64) {
-      const zd nv = zsub(col[r], zmul(vs[r - j], w));
-      col[r] = nv;
-      if (r > j) tail += zabs2(nv);
-      else first = nv;
-    }
-    const zd rjl = zmk(__shfl(first.re, 0, 64), __shfl(first.im, 0, 64));
-    const double nw2 = nrm[l] - zabs2(rjl);
-    if (nw2 <= 1e-8 * nrm[c + l]) {
-      tail = wave_sum(tail);
-      if (lane == 0) {
-        nrm[l] = tail;
-        nrm[c + l] = tail;
-      }
-    } else if (lane == 0) {
-      nrm[l] = nw2;
-    }
+    cp_apply_column<R>(Cd.b + (int64_t)l * ld, vs, j, mb, tau, Cd.nrm, c, l, lane);
   }
 }
 
-void la_cpqr(const CpqrDesc* d_cp, int batch, int max_c, double tol, const int* d_kmin, int init, int* d_work,
+template <class R>
+void la_cpqr(const CpqrDescT<R>* d_cp, int batch, int max_c, double tol, const int* d_kmin, int init, int* d_work,
              hipStream_t s) {
   if (batch <= 0 || max_c <= 0) return;
-  size_t shm = (size_t)max_c * sizeof(zd) + 16;
+  size_t shm = (size_t)max_c * sizeof(cx<R>) + 16;
   if (shm > 64 * 1024) {
-    (void)hipFuncSetAttribute((const void*)k_cpqr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    (void)hipFuncSetAttribute((const void*)k_cpqr_update, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    (void)hipFuncSetAttribute((const void*)k_cpqr<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    (void)hipFuncSetAttribute((const void*)k_cpqr_update<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   }
   if (max_c < PMX_CPQR_MULTI_MIN) {
     KScope ks(PK_CPQR, s);
-    hipLaunchKernelGGL(k_cpqr, dim3(batch), dim3(CP_NT), shm, s, d_cp, tol, d_kmin, init);
+    hipLaunchKernelGGL(k_cpqr<R>, dim3(batch), dim3(CP_NT), shm, s, d_cp, tol, d_kmin, init);
     return;
   }
   (void)hipMemsetAsync(d_work, 0, sizeof(int), s);
-  hipLaunchKernelGGL(k_cpqr_init, dim3((max_c + 3) / 4, batch), dim3(256), 0, s, d_cp, init);
+  hipLaunchKernelGGL(k_cpqr_init<R>, dim3((max_c + 3) / 4, batch), dim3(256), 0, s, d_cp, init);
   const int ucols = (max_c + 15) / 16;
   for (int it = 0; it <= max_c; ++it) {
-    hipLaunchKernelGGL(k_cpqr_pivot, dim3(batch), dim3(256), 0, s, d_cp, tol, d_kmin, d_work);
+    hipLaunchKernelGGL(k_cpqr_pivot<R>, dim3(batch), dim3(256), 0, s, d_cp, tol, d_kmin, d_work);
     {
       KScope ks(PK_CPQR_UPDATE, s);
-      hipLaunchKernelGGL(k_cpqr_update, dim3(ucols, batch), dim3(256), shm, s, d_cp);
+      hipLaunchKernelGGL(k_cpqr_update<R>, dim3(ucols, batch), dim3(256), shm, s, d_cp);
     }
     if ((it & 15) == 15) {
       int nd = 0;
@@ -1222,12 +1311,13 @@ void la_cpqr(const CpqrDesc* d_cp, int batch, int max_c, double tol, const int* 
 }
 
 // T = R11^-1 R12 in place
+template <class R>
 struct FTTrsm {
-  const CpqrDesc* d;
+  const CpqrDescT<R>* d;
   const int* ks;
   int j0;
-  __device__ bool operator()(int b, TrsmArgs& a) const {
-    CpqrDesc C = d[b];
+  __device__ bool operator()(int b, TrsmArgs<R>& a) const {
+    CpqrDescT<R> C = d[b];
     int k = ks[b];
     int jb = min(PMX_LU_NB, k - j0);
     if (jb <= 0 || C.c - k <= 0) return false;
@@ -1241,12 +1331,13 @@ struct FTTrsm {
   }
 };
 
+template <class R>
 struct FTUpd {
-  const CpqrDesc* d;
+  const CpqrDescT<R>* d;
   const int* ks;
   int j0;
-  __device__ bool operator()(int b, GemmArgs& g) const {
-    CpqrDesc C = d[b];
+  __device__ bool operator()(int b, GemmArgsT<R>& g) const {
+    CpqrDescT<R> C = d[b];
     int k = ks[b];
     int jb = min(PMX_LU_NB, k - j0);
     if (jb <= 0 || j0 <= 0 || C.c - k <= 0) return false;
@@ -1263,23 +1354,27 @@ struct FTUpd {
   }
 };
 
-void la_cpqr_tsolve(const CpqrDesc* d_cp, const int* d_k, int batch, int max_k, int max_c,
-                    hipStream_t s) {
+template <class R>
+void la_cpqr_tsolve(const CpqrDescT<R>* d_cp, const int* d_k, int batch, int max_k, int max_c, hipStream_t s) {
   if (batch <= 0 || max_k <= 0 || max_c <= 0) return;
   const int nblk = (max_k + PMX_LU_NB - 1) / PMX_LU_NB;
   for (int bk = nblk - 1; bk >= 0; --bk) {
     int j0 = bk * PMX_LU_NB;
-    launch_trsm_small<true, false>(FTTrsm{d_cp, d_k, j0}, batch, max_c, s);
-    if (j0 > 0) launch_zgemm<OP_N, OP_N>(FTUpd{d_cp, d_k, j0}, batch, j0, max_c, zmk(-1, 0), zmk(1, 0), s);
+    launch_trsm_small<R, true, false>(FTTrsm<R>{d_cp, d_k, j0}, batch, max_c, s);
+    if (j0 > 0)
+      launch_zgemm<R, OP_N, OP_N>(FTUpd<R>{d_cp, d_k, j0}, batch, j0, max_c, cmk<R>(-1, 0), cmk<R>(1, 0), s);
   }
 }
 
-// Algorithmic work of the QR kernels for one m x c matrix, mirroring the launch sequence.
-// Trailing update of an nrb x nc block by jb reflectors: bytes 16 (2 nrb nc + 2 nrb jb)
-// (the block read and written once, V and V T^H read once), flops 16 nrb nc jb (two
-// complex products).  Leaf factorisation of an nrb x jb block: bytes 16 (2 nrb jb + 2 nrb
-// PMX_QR_NB) (panel read and written, V and V T^H written), flops 8 nrb jb^2.
-void la_geqrf_work(int m, int c, double* upd_bytes, double* upd_flops, double* leaf_bytes, double* leaf_flops) {
+// Algorithmic work of the QR kernels for one m x c matrix, mirroring the launch sequence,
+// with z = 2 real_bytes bytes per complex entry.  Trailing update of an nrb x nc block by
+// jb reflectors: bytes z (2 nrb nc + 2 nrb jb) (the block read and written once, V and
+// V T^H read once), flops 16 nrb nc jb (two complex products).  Leaf factorisation of an
+// nrb x jb block: bytes z (2 nrb jb + 2 nrb PMX_QR_NB) (panel read and written, V and
+// V T^H written), flops 8 nrb jb^2.
+void la_geqrf_work(int m, int c, int real_bytes, double* upd_bytes, double* upd_flops, double* leaf_bytes,
+                   double* leaf_flops) {
+  const double z = 2.0 * real_bytes;
   const int kmax = std::min(m, c);
   for (int j0 = 0; j0 < kmax; j0 += PMX_QR_NB) {
     const int jb = std::min(PMX_QR_NB, kmax - j0);
@@ -1289,10 +1384,10 @@ void la_geqrf_work(int m, int c, double* upd_bytes, double* upd_flops, double* l
       const int nb = (mr + PMX_TS_BR - 1) / PMX_TS_BR;
       for (int b = 0; b < nb; ++b) {
         const double nrb = std::min(PMX_TS_BR, mr - b * PMX_TS_BR);
-        *leaf_bytes += 16.0 * (2 * nrb * jb + 2 * nrb * PMX_QR_NB);
+        *leaf_bytes += z * (2 * nrb * jb + 2 * nrb * PMX_QR_NB);
         *leaf_flops += 8.0 * nrb * jb * jb;
         if (nc > 0) {
-          *upd_bytes += 16.0 * (2 * nrb * nc + 2 * nrb * jb);
+          *upd_bytes += z * (2 * nrb * nc + 2 * nrb * jb);
           *upd_flops += 16.0 * nrb * nc * jb;
         }
       }
@@ -1303,12 +1398,25 @@ void la_geqrf_work(int m, int c, double* upd_bytes, double* upd_flops, double* l
 }
 
 // Algorithmic work of the LU panels of one n x n factorisation: each panel of jb columns
-// is read and written once (bytes 32 (n - j0) jb) and its column steps cost 8 (n - c - 1)
-// (j0 + jb - c - 1) flops for the rank-one updates.
-void la_getrf_work(int n, double* bytes, double* flops) {
+// is read and written once (bytes 2 z (n - j0) jb, z = 2 real_bytes) and its column steps
+// cost 8 (n - c - 1) (j0 + jb - c - 1) flops for the rank-one updates.
+void la_getrf_work(int n, int real_bytes, double* bytes, double* flops) {
+  const double z = 2.0 * real_bytes;
   for (int j0 = 0; j0 < n; j0 += PMX_LU_NB) {
     const int jb = std::min(PMX_LU_NB, n - j0);
-    *bytes += 32.0 * (double)(n - j0) * jb;
+    *bytes += 2.0 * z * (double)(n - j0) * jb;
     for (int c = j0; c < j0 + jb; ++c) *flops += 8.0 * (double)(n - c - 1) * (j0 + jb - c - 1);
   }
 }
+
+// explicit instantiations: complex FP64 and complex FP32
+#define PMX_LA_INST(R)                                                                                       \
+  template void la_zgemm_list<R>(int, int, const GemmArgsT<R>*, int, int, int, cx<R>, cx<R>, hipStream_t);  \
+  template void la_getrf<R>(const LuDescT<R>*, int, int, int*, hipStream_t);                                 \
+  template void la_getrs<R>(const LuDescT<R>*, const MatT<R>*, int, int, int, hipStream_t);                  \
+  template void la_geqrf_r<R>(const QrDescT<R>*, int, int, int, hipStream_t);                                \
+  template void la_cpqr<R>(const CpqrDescT<R>*, int, int, double, const int*, int, int*, hipStream_t);       \
+  template void la_cpqr_tsolve<R>(const CpqrDescT<R>*, const int*, int, int, int, hipStream_t);
+PMX_LA_INST(double)
+PMX_LA_INST(float)
+#undef PMX_LA_INST

@@ -1,41 +1,69 @@
-// Shared device/host helpers: complex double arithmetic, error plumbing.
+// Shared device/host helpers: complex arithmetic over double and float.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-struct zd {
-  double re, im;
+// complex number over a real type R (double or float)
+template <class R>
+struct cx {
+  R re, im;
 };
+typedef cx<double> zd;
+typedef cx<float> zf;
 
-__host__ __device__ inline zd zmk(double r, double i) { zd z; z.re = r; z.im = i; return z; }
-__host__ __device__ inline zd zadd(zd a, zd b) { return zmk(a.re + b.re, a.im + b.im); }
-__host__ __device__ inline zd zsub(zd a, zd b) { return zmk(a.re - b.re, a.im - b.im); }
-__host__ __device__ inline zd zmul(zd a, zd b) {
-  return zmk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+template <class R>
+__host__ __device__ inline cx<R> cmk(R r, R i) {
+  cx<R> z;
+  z.re = r;
+  z.im = i;
+  return z;
 }
-__host__ __device__ inline zd zconj(zd a) { return zmk(a.re, -a.im); }
-__host__ __device__ inline zd zscale(zd a, double s) { return zmk(a.re * s, a.im * s); }
-__host__ __device__ inline double zabs2(zd a) { return a.re * a.re + a.im * a.im; }
+__host__ __device__ inline zd zmk(double r, double i) { return cmk<double>(r, i); }
+template <class R>
+__host__ __device__ inline cx<R> zadd(cx<R> a, cx<R> b) { return cmk<R>(a.re + b.re, a.im + b.im); }
+template <class R>
+__host__ __device__ inline cx<R> zsub(cx<R> a, cx<R> b) { return cmk<R>(a.re - b.re, a.im - b.im); }
+template <class R>
+__host__ __device__ inline cx<R> zmul(cx<R> a, cx<R> b) {
+  return cmk<R>(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <class R>
+__host__ __device__ inline cx<R> zconj(cx<R> a) { return cmk<R>(a.re, -a.im); }
+// the scale factor does not take part in deducing R (it may be given in double)
+template <class T>
+struct nodeduce {
+  typedef T type;
+};
+template <class R>
+__host__ __device__ inline cx<R> zscale(cx<R> a, typename nodeduce<R>::type s) {
+  return cmk<R>(a.re * s, a.im * s);
+}
+template <class R>
+__host__ __device__ inline R zabs2(cx<R> a) { return a.re * a.re + a.im * a.im; }
 // a * conj(b)
-__host__ __device__ inline zd zmulc(zd a, zd b) {
-  return zmk(a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im);
+template <class R>
+__host__ __device__ inline cx<R> zmulc(cx<R> a, cx<R> b) {
+  return cmk<R>(a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im);
 }
 // conj(a) * b
-__host__ __device__ inline zd zcmul(zd a, zd b) {
-  return zmk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+template <class R>
+__host__ __device__ inline cx<R> zcmul(cx<R> a, cx<R> b) {
+  return cmk<R>(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
 }
-__host__ __device__ inline zd zdiv(zd a, zd b) {
+template <class R>
+__host__ __device__ inline cx<R> zdiv(cx<R> a, cx<R> b) {
   // Smith's algorithm
   if (fabs(b.re) >= fabs(b.im)) {
-    double r = b.im / b.re, d = b.re + b.im * r;
-    return zmk((a.re + a.im * r) / d, (a.im - a.re * r) / d);
+    R r = b.im / b.re, d = b.re + b.im * r;
+    return cmk<R>((a.re + a.im * r) / d, (a.im - a.re * r) / d);
   } else {
-    double r = b.re / b.im, d = b.re * r + b.im;
-    return zmk((a.re * r + a.im) / d, (a.im * r - a.re) / d);
+    R r = b.re / b.im, d = b.re * r + b.im;
+    return cmk<R>((a.re * r + a.im) / d, (a.im * r - a.re) / d);
   }
 }
-__host__ __device__ inline zd zfma(zd a, zd b, zd c) {  // a*b + c
-  return zmk(fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im)));
+template <class R>
+__host__ __device__ inline cx<R> zfma(cx<R> a, cx<R> b, cx<R> c) {  // a*b + c
+  return cmk<R>(fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im)));
 }
 
 #define PMX_PI 3.14159265358979323846264338327950288

@@ -25,6 +25,7 @@ EXPORTS = [
     "pmx_far_field", "pmx_factor_info", "pmx_factor_destroy", "pmx_status_string",
     "pmx_last_error", "pmx_probe_bessel", "pmx_probe_diag_block", "pmx_probe_entries",
     "pmx_probe_zgemm", "pmx_probe_lu_solve", "pmx_probe_id", "pmx_plan_query",
+    "pmx_probe_cgemm", "pmx_probe_lu_solve_c32", "pmx_probe_id_c32", "pmx_probe_apply",
 ]
 
 
@@ -47,7 +48,8 @@ class Geometry(C.Structure):
 class Options(C.Structure):
     _fields_ = [("id_tol", C.c_double), ("proxy_ratio", C.c_double), ("proxy_min", C.c_int32),
                 ("proxy_rule", C.c_int32), ("near_rule", C.c_int32), ("precision", C.c_int32),
-                ("timing", C.c_int32), ("reserved", C.c_int32 * 8)]
+                ("timing", C.c_int32), ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double),
+                ("reserved", C.c_int32 * 8)]
 
 
 class Info(C.Structure):
@@ -56,10 +58,12 @@ class Info(C.Structure):
                 ("rank_mean", C.c_double * 32), ("bytes_factor", C.c_double),
                 ("t_factor_ms", C.c_double), ("t_phase_ms", C.c_double * 16),
                 ("t_kernel_ms", C.c_double * 16), ("n_kernel_launch", C.c_int32 * 16),
-                ("kernel_bytes", C.c_double * 16), ("kernel_flops", C.c_double * 16)]
+                ("kernel_bytes", C.c_double * 16), ("kernel_flops", C.c_double * 16),
+                ("t_solve_ms", C.c_double), ("ir_iterations", C.c_int32), ("ir_residual", C.c_double),
+                ("ir_history", C.c_double * 16)]
 
 KERNEL_NAMES = ["k_ts_leaf", "k_ts_update", "k_getrf_panel", "k_cpqr_update", "k_cpqr", "k_zgemm",
-                "k_trsm_small", "k_entries", "k_diag_pairs/maue"]
+                "k_trsm_small", "k_entries", "k_diag_pairs/maue", "k_apply_off"]
 
 
 def load(path=None):
@@ -95,6 +99,10 @@ def load(path=None):
     lib.pmx_probe_zgemm.argtypes = [C.c_int32] * 6 + [vp, vp, vp, vp]
     lib.pmx_probe_lu_solve.argtypes = [C.c_int32, C.c_int32, vp, vp, C.c_int32, vp, ip, vp]
     lib.pmx_probe_id.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, C.c_double, ip, vp, ip, vp, vp]
+    lib.pmx_probe_cgemm.argtypes = [C.c_int32] * 6 + [vp, vp, vp, vp]
+    lib.pmx_probe_lu_solve_c32.argtypes = [C.c_int32, C.c_int32, vp, vp, C.c_int32, vp, ip, vp]
+    lib.pmx_probe_id_c32.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, C.c_double, ip, vp, ip, vp, vp]
+    lib.pmx_probe_apply.argtypes = [C.POINTER(Geometry), C.c_int32, vp, vp, vp]
     dp = C.POINTER(C.c_double)
     lib.pmx_plan_query.argtypes = [C.POINTER(Geometry), C.POINTER(Options), C.c_int32, C.c_int32,
                                    ip, ip, ip, ip, ip, dp, dp, dp, ip, ip, ip]
@@ -260,49 +268,73 @@ def _colmajor(t):
     return t.transpose(-1, -2).contiguous()
 
 
-def probe_zgemm(A, B, opa=0, opb=0):
-    """A, B: (batch, ., .) complex128 numpy arrays in their stored shapes."""
+def _ctype(fp32):
+    import torch
+    return torch.complex64 if fp32 else torch.complex128
+
+
+def probe_zgemm(A, B, opa=0, opb=0, fp32=False):
+    """A, B: (batch, ., .) complex numpy arrays in their stored shapes; fp32 runs the
+    complex FP32 kernel on the inputs rounded to complex64."""
     import torch
     load()
-    At = _colmajor(torch.as_tensor(A, device="cuda"))
-    Bt = _colmajor(torch.as_tensor(B, device="cuda"))
+    ct = _ctype(fp32)
+    At = _colmajor(torch.as_tensor(A, device="cuda").to(ct))
+    Bt = _colmajor(torch.as_tensor(B, device="cuda").to(ct))
     batch = A.shape[0]
     m = A.shape[1] if opa == 0 else A.shape[2]
     k = A.shape[2] if opa == 0 else A.shape[1]
     n = B.shape[2] if opb == 0 else B.shape[1]
-    Ct = torch.empty((batch, n, m), dtype=torch.complex128, device="cuda")
-    _check(_lib.pmx_probe_zgemm(batch, m, n, k, opa, opb, C.c_void_p(At.data_ptr()), C.c_void_p(Bt.data_ptr()),
-                                C.c_void_p(Ct.data_ptr()), _stream()))
+    Ct = torch.empty((batch, n, m), dtype=ct, device="cuda")
+    fn = _lib.pmx_probe_cgemm if fp32 else _lib.pmx_probe_zgemm
+    _check(fn(batch, m, n, k, opa, opb, C.c_void_p(At.data_ptr()), C.c_void_p(Bt.data_ptr()),
+              C.c_void_p(Ct.data_ptr()), _stream()))
     return Ct.transpose(-1, -2).cpu().numpy()
 
 
-def probe_lu_solve(A, B):
+def probe_lu_solve(A, B, fp32=False):
     import torch
     load()
+    ct = _ctype(fp32)
     batch, n, _ = A.shape
     nrhs = B.shape[2]
-    At = _colmajor(torch.as_tensor(A, device="cuda"))
-    Bt = _colmajor(torch.as_tensor(B, device="cuda"))
+    At = _colmajor(torch.as_tensor(A, device="cuda").to(ct))
+    Bt = _colmajor(torch.as_tensor(B, device="cuda").to(ct))
     piv = torch.empty((batch, n), dtype=torch.int32, device="cuda")
     info = np.zeros(batch, np.int32)
-    _check(_lib.pmx_probe_lu_solve(batch, n, C.c_void_p(At.data_ptr()), C.c_void_p(piv.data_ptr()), nrhs,
-                                   C.c_void_p(Bt.data_ptr()), _ptr(info, C.c_int32), _stream()))
+    fn = _lib.pmx_probe_lu_solve_c32 if fp32 else _lib.pmx_probe_lu_solve
+    _check(fn(batch, n, C.c_void_p(At.data_ptr()), C.c_void_p(piv.data_ptr()), nrhs,
+              C.c_void_p(Bt.data_ptr()), _ptr(info, C.c_int32), _stream()))
     return (At.transpose(-1, -2).cpu().numpy(), piv.cpu().numpy(), Bt.transpose(-1, -2).cpu().numpy(), info)
 
 
-def probe_id(M, tol, kmin=None):
+def probe_id(M, tol, kmin=None, fp32=False):
     import torch
     load()
+    ct = _ctype(fp32)
     batch, m, c = M.shape
-    Mt = _colmajor(torch.as_tensor(M, device="cuda"))
+    Mt = _colmajor(torch.as_tensor(M, device="cuda").to(ct))
     piv = torch.empty((batch, c), dtype=torch.int32, device="cuda")
     rank = np.zeros(batch, np.int32)
-    T = torch.zeros((batch, c, c), dtype=torch.complex128, device="cuda")
+    T = torch.zeros((batch, c, c), dtype=ct, device="cuda")
     km = None if kmin is None else np.ascontiguousarray(kmin, np.int32)
-    _check(_lib.pmx_probe_id(batch, m, c, C.c_void_p(Mt.data_ptr()), tol,
-                             None if km is None else _ptr(km, C.c_int32), C.c_void_p(piv.data_ptr()),
-                             _ptr(rank, C.c_int32), C.c_void_p(T.data_ptr()), _stream()))
+    fn = _lib.pmx_probe_id_c32 if fp32 else _lib.pmx_probe_id
+    _check(fn(batch, m, c, C.c_void_p(Mt.data_ptr()), tol, None if km is None else _ptr(km, C.c_int32),
+              C.c_void_p(piv.data_ptr()), _ptr(rank, C.c_int32), C.c_void_p(T.data_ptr()), _stream()))
     return piv.cpu().numpy(), rank, T.transpose(-1, -2).cpu().numpy()
+
+
+def probe_apply(w, x):
+    """y = A x with the library's dense FP64 operator; x numpy (2N, nrhs) in the oracle's
+    stacked layout, returned in the same layout."""
+    import torch
+    load()
+    keep = _GeomKeep(w)
+    xt = torch.as_tensor(np.ascontiguousarray(np.asarray(x).T), device="cuda").to(torch.complex128).contiguous()
+    y = torch.empty_like(xt)
+    _check(_lib.pmx_probe_apply(C.byref(keep.g), xt.shape[0], C.c_void_p(xt.data_ptr()), C.c_void_p(y.data_ptr()),
+                                _stream()))
+    return y.cpu().numpy().T.copy()
 
 
 def plan_query(w, opts=None):

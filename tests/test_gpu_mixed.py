@@ -1,0 +1,147 @@
+"""GPU parity of the mixed-precision form: complex FP32 primitives (MFMA GEMM, LU, ID), the
+dense FP64 operator apply of the refinement residual, and the refined solutions against
+the oracle's dense FP64 solve.
+
+Tolerances.  FP32 primitives are compared with FP64 results on the same (rounded) inputs:
+sums of k products carry a relative error of about k u32 (u32 = 6e-8), so the GEMM bound
+is 4e-7 sqrt(k) relative to the largest |A||B| entry.  The operator apply is FP64 (sums of
+N terms of rounding 1e-16): 1e-12 relative.  Refined solutions stop at a relative residual
+of 1e-10; with the condition numbers of these systems (~1e3) the error against the dense
+solve stays below 1e-8 (the accuracy target), and is typically 1e-10.
+"""
+import numpy as np
+import pytest
+
+from oracle import analytic, dense
+from paper_2603_09381_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RNG = np.random.default_rng(4321)
+
+
+def crandn(*shape):
+    return RNG.standard_normal(shape) + 1j * RNG.standard_normal(shape)
+
+
+def c64(a):
+    return a.astype(np.complex64).astype(np.complex128)
+
+
+@pytest.mark.parametrize("opa,opb", [(0, 0), (0, 1), (0, 2), (1, 0), (2, 0), (2, 2)])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (37, 5, 70), (130, 129, 17), (64, 64, 0), (16, 16, 4)])
+def test_cgemm_fp32(pmx, opa, opb, m, n, k):
+    batch = 3
+    A = c64(crandn(batch, m, k) if opa == 0 else crandn(batch, k, m))
+    B = c64(crandn(batch, k, n) if opb == 0 else crandn(batch, n, k))
+    op = {0: lambda X: X, 1: lambda X: np.swapaxes(X, 1, 2), 2: lambda X: np.conj(np.swapaxes(X, 1, 2))}
+    ref = op[opa](A) @ op[opb](B)
+    got = pmx.probe_zgemm(A, B, opa, opb, fp32=True)
+    assert got.dtype == np.complex64
+    scale = max(1.0, np.abs(op[opa](np.abs(A)) @ op[opb](np.abs(B))).max())
+    assert np.abs(got - ref).max() < 4e-7 * np.sqrt(max(k, 1)) * scale
+
+
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (31, 3), (100, 40), (257, 7)])
+def test_lu_solve_fp32(pmx, n, nrhs):
+    batch = 3
+    A = c64(crandn(batch, n, n) + 2 * np.sqrt(n) * np.eye(n))
+    B = c64(crandn(batch, n, nrhs))
+    _, _, X, info = pmx.probe_lu_solve(A, B, fp32=True)
+    assert (info == 0).all()
+    ref = np.linalg.solve(A, B)
+    # backward stable: residual of the FP32 solution ~ n u32 |A| |x|
+    res = np.abs(A @ X.astype(np.complex128) - B).max()
+    assert res < 1e-6 * n * np.abs(A).max() * np.abs(ref).max()
+
+
+def _lowrank(m, c, r, decay):
+    U = crandn(m, r)
+    V = crandn(r, c)
+    return (U * decay ** np.arange(r)) @ V
+
+
+@pytest.mark.parametrize("m,c", [(300, 60), (60, 60), (1000, 128), (700, 300)])
+def test_id_fp32(pmx, m, c):
+    batch = 2
+    tol = 1e-5
+    M = c64(np.stack([_lowrank(m, c, min(m, c), 0.6) for _ in range(batch)]))
+    piv, rank, T = pmx.probe_id(M.copy(), tol, fp32=True)
+    for b in range(batch):
+        k = int(rank[b])
+        p = piv[b]
+        assert sorted(p) == list(range(c))
+        Z = np.zeros((k, c), complex)
+        Z[:, p[:k]] = np.eye(k)
+        Z[:, p[k:]] = T[b][:k, :c - k]
+        res = np.linalg.norm(M[b] - M[b][:, p[:k]] @ Z, 2) / np.linalg.norm(M[b], 2)
+        assert res < 1e2 * tol, res
+        assert 0.6 ** k < 1e2 * tol and 0.6 ** max(k - 8, 0) > tol * 1e-2, k
+
+
+@pytest.mark.parametrize("g,n", [(2, 64), (3, 48)])
+def test_dense_apply_against_oracle(pmx, g, n):
+    w = W.star_grid(g, n=n, k_ext=10.0, k_int=15.0, seed=5)
+    A = dense.assemble(dense.Geometry(w))
+    x = crandn(w.n_unknowns, 3)
+    ref = A @ x
+    got = pmx.probe_apply(w, x)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("dense apply rel err", err)
+    assert err < 1e-12
+
+
+def _mixed(pmx, w, **kw):
+    import torch
+    o = pmx.options(w, precision=1, id_tol=kw.pop("id_tol", 1e-6), **kw)
+    fac = pmx.Factor(w, o)
+    dens = fac.solve_plane_waves(w.angles)
+    torch.cuda.synchronize()
+    return fac, pmx.dens_to_numpy(dens, w)
+
+
+def test_mixed_cfg1_against_dense_and_multipole(pmx):
+    w = W.config1()
+    fac, x = _mixed(pmx, w)
+    ref = dense.solve(w)
+    info = fac.info()
+    print("cfg1 mixed: iters", info.ir_iterations, "res", info.ir_residual, "err", dense.rel_error(x, ref))
+    assert info.ir_residual <= 1e-10
+    assert dense.rel_error(x, ref) < 1e-9
+    g = dense.Geometry(w)
+    bnd, _, _ = analytic.multi_disk(w.centers, 0.4, w.k_ext, w.k_int[0], g.eps_p, g.eps_m[0])
+    th = 2 * np.pi * np.arange(64) / 64
+    mref = np.concatenate([np.concatenate(bnd(j, th)) for j in range(4)])
+    assert dense.rel_error(x[:, 0], mref) < 5e-9
+
+
+@pytest.mark.parametrize("g", [2, 4])
+def test_mixed_star_grid_against_dense(pmx, g):
+    w = W.sub_grid(W.config2(), g)
+    fac, x = _mixed(pmx, w)
+    ref = dense.solve(w)
+    err = dense.rel_error(x, ref)
+    info = fac.info()
+    print(w.name, "mixed: iters", info.ir_iterations, "res", info.ir_residual, "err", err, "root", info.root_size)
+    assert info.ir_residual <= 1e-10 and info.ir_iterations >= 2
+    assert err < 1e-8
+    assert np.max(np.abs(dense.energy_defect(dense.Geometry(w), x))) < 1e-8
+
+
+def test_mixed_general_rhs(pmx):
+    import torch
+    w = W.sub_grid(W.config2(), 2)
+    fac, x = _mixed(pmx, w)
+    f = dense.rhs(dense.Geometry(w), w.angles)
+    y = fac.solve(torch.as_tensor(f.T.copy(), device="cuda")).cpu().numpy().T
+    assert dense.rel_error(y, dense.solve(w)) < 1e-8
+
+
+def test_mixed_reports_nonconvergence(pmx):
+    w = W.sub_grid(W.config2(), 2)
+    o = pmx.options(w, precision=1, id_tol=1e-4, ir_max_iter=1, ir_tol=1e-14)
+    fac = pmx.Factor(w, o)
+    with pytest.raises(pmx.PmxError) as e:
+        fac.solve_plane_waves(w.angles)
+    assert e.value.status == 6
+    assert fac.info().ir_iterations == 1 and fac.info().ir_residual > 1e-14
