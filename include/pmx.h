@@ -78,6 +78,8 @@ typedef struct {
   int32_t ir_max_iter;  /* precision 1, 2: at most this many refinement steps (1..100) */
   double ir_tol;        /* precision 1, 2: stop when max over right-hand sides of
                            |f - A x| / |f| <= ir_tol (2-norms) */
+  int32_t solve_graph;  /* 1: every solve's launch sequence (per right-hand-side count) is
+                           captured once as a HIP graph and replayed; 0: launched directly */
   int32_t reserved[8];
 } pmx_options;
 
@@ -95,9 +97,10 @@ typedef struct {
   /* with options.timing = 1: per-kernel device time from HIP events around every launch of
    * the factorisation (index: 0 QR leaf blocks, 1 QR trailing update, 2 LU panel, 3 CPQR
    * update, 4 CPQR single-workgroup, 5 complex GEMM, 6 small triangular solves, 7 entry
-   * assembly, 8 self blocks, 9 dense operator apply of refinement residuals, recorded by
-   * solves), launch counts, and the algorithmic bytes and flops of the kernels whose work
-   * the library counts (0, 1, 2). */
+   * assembly, 8 self blocks, 9 dense operator apply of refinement residuals, 10 fused
+   * substitutions of few right-hand sides; 9 and 10 run in solves, which are not timed),
+   * launch counts, and the algorithmic bytes and flops of the kernels whose work the
+   * library counts (0, 1, 2). */
   double t_kernel_ms[16];
   int32_t n_kernel_launch[16];
   double kernel_bytes[16];
@@ -113,7 +116,7 @@ typedef struct {
 typedef struct pmx_factor pmx_factor;
 
 /* Fills defaults: id_tol 1e-10, proxy_ratio 1.5, proxy_min 0, proxy_rule 0, near_rule 0,
- * precision 0, timing 0, ir_max_iter 10, ir_tol 1e-10. */
+ * precision 0, timing 0, ir_max_iter 10, ir_tol 1e-10, solve_graph 1. */
 void pmx_options_default(pmx_options* o);
 
 /* Builds the plan and the whole compressed factorisation on `hip_stream`.  Returns when

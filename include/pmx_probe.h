@@ -44,7 +44,8 @@ pmx_status pmx_probe_cgemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32
 
 /* LU with partial pivoting of a batch of n x n matrices (device, in place) and solve with
  * nrhs right-hand sides B [batch][n x nrhs] (device, in place).  ipiv (device) [batch][n].
- * info (host) [batch]: first zero pivot (1-based) or 0. */
+ * info (host) [batch]: first zero pivot (1-based) or 0.  Up to 64 right-hand sides take the
+ * fused substitution kernel of the solves, more the blocked one of the factorisation. */
 pmx_status pmx_probe_lu_solve(int32_t batch, int32_t n, pmx_c64* A, int32_t* ipiv, int32_t nrhs,
                               pmx_c64* B, int32_t* info, void* stream);
 

@@ -42,7 +42,9 @@ def build(verbose=False):
     if failed:
         raise RuntimeError("compilation failed: " + ", ".join(failed))
     tmp = OUT + ".tmp"
-    subprocess.run([HIPCC] + HIP_FLAGS + ["-shared", "-o", tmp] + objs, check=True)
+    # -z defs: an unresolved symbol of the library's own (a missing template instantiation)
+    # fails the link instead of the first load
+    subprocess.run([HIPCC] + HIP_FLAGS + ["-shared", "-Wl,-z,defs", "-o", tmp] + objs, check=True)
     os.replace(tmp, OUT)
     return OUT
 

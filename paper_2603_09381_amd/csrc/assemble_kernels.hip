@@ -533,3 +533,4 @@ template void asm_gather<float, double>(const zf*, const GatherDescT<double>*, i
 template void asm_convert<double, float>(const zd*, zf*, int64_t, hipStream_t);
 template void asm_convert<float, double>(const zf*, zd*, int64_t, hipStream_t);
 template void asm_convert<double, double>(const zd*, zd*, int64_t, hipStream_t);
+template void asm_convert<float, float>(const zf*, zf*, int64_t, hipStream_t);

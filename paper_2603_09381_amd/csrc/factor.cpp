@@ -129,6 +129,7 @@ struct LevelData {
   std::vector<std::vector<int>> children;     // plan children (only for the parent level)
   cx<R>* D = nullptr;                         // LU of D per cell
   int* ipiv = nullptr;
+  int* perm = nullptr;                        // row permutations of the LUs
   cx<R>* Y = nullptr;                         // D^-1 L, s x K
   cx<R>* At = nullptr;                        // K x K
   cx<R>* Tc = nullptr;                        // column-ID T blocks, [k0 x (s0-k0)] then [k1 x (s1-k1)]
@@ -137,13 +138,38 @@ struct LevelData {
   int64_t tot_s = 0, tot_k = 0;
 };
 
+// Buffers and device launch descriptors of one level of a solve pass.
 template <class R>
-struct SolveCache {
+struct SolveLevel {
+  cx<R>* F = nullptr;        // y / f vectors, sum s x nrhs
+  cx<R>* G = nullptr;        // K x nrhs
+  cx<R>* Red = nullptr;      // redundant rows
+  cx<R>* Ry = nullptr;       // copy of R y
+  cx<R>* W = nullptr;        // substitution workspace
+  cx<R>* Psi = nullptr;      // parent solution rows of each cell
+  MatT<R>* d_bm = nullptr;   // y = D^-1 f
+  MatT<R>* d_w = nullptr;    // its workspace
+  GatherDescT<R>* d_up = nullptr;    // R y: skeleton and redundant rows
+  int n_up = 0, max_up = 0;
+  GemmArgsT<R>* d_ga = nullptr;      // + T * redundant rows
+  int n_ga = 0;
+  GemmArgsT<R>* d_gb = nullptr;      // g = At (R y)
+  GatherDescT<R>* d_par = nullptr;   // parent right-hand sides
+  int n_par = 0, max_par = 0;
+  GatherDescT<R>* d_psi = nullptr;   // psi gathers
+  GemmArgsT<R>* d_g1 = nullptr;      // g -= At psi
+  GemmArgsT<R>* d_g2 = nullptr;      // x = y - Y g
+  int64_t tot_k = 0;
+};
+
+template <class R>
+struct SolveProgram {
   int nrhs = -1;
-  std::vector<cx<R>*> F;   // per level: y / f vectors, sum s x nrhs
-  std::vector<cx<R>*> G;   // per level: K x nrhs
-  std::vector<cx<R>*> Red; // per level: redundant rows scratch
+  std::vector<SolveLevel<R>> lv;
   cx<R>* Froot = nullptr;
+  cx<R>* leaf = nullptr;     // leaf vectors: input and output of a pass
+  MatT<R>* d_bm_root = nullptr;
+  MatT<R>* d_w_root = nullptr;
   Arena arena;
 };
 
@@ -154,10 +180,13 @@ struct Tier {
   int root_s = 0;
   cx<R>* Droot = nullptr;
   int* ipiv_root = nullptr;
+  int* perm_root = nullptr;
   LuDescT<R>* d_lu_root = nullptr;
   std::vector<int> root_rows, root_cols;
-  SolveCache<R> sc;
+  SolveProgram<R> prog;
 };
+
+struct SolveState;
 
 struct pmx_factor {
   // geometry (device)
@@ -179,6 +208,11 @@ struct pmx_factor {
   std::vector<int64_t> selfOff;
   Arena arena;
   pmx_info info;
+  // solves: own stream (captured graphs), ordering events, per right-hand-side-count state
+  hipStream_t gs = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::unique_ptr<SolveState> ss;
+  ~pmx_factor();
   DevGeom geom() const { return DevGeom{x, y, nx, ny, w, speed, kappa, n_nodes}; }
   ExtParams ext() const { return ExtParams{k_ext, eps_ext}; }
 };
@@ -610,7 +644,7 @@ void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>&
   std::vector<LuDescT<R>> lu(nc);
   for (int t = 0; t < nc; ++t) {
     int sz = L.s0[t] + L.s1[t];
-    lu[t] = LuDescT<R>{L.D + L.offD[t], sz, sz, L.ipiv + L.offS[t]};
+    lu[t] = LuDescT<R>{L.D + L.offD[t], sz, sz, L.ipiv + L.offS[t], L.perm + L.offS[t]};
   }
   L.d_lu = A.upload(lu, s);
   int* d_info = tmp.alloc<int>(nc);
@@ -766,6 +800,7 @@ void merge_level(pmx_factor* F, const LevelData<R>& C, const std::vector<CellPla
   P.tot_s = P.offS[np];
   P.D = F->arena.alloc<cx<R>>(td);
   P.ipiv = F->arena.alloc<int>(std::max<int64_t>(P.tot_s, 1));
+  P.perm = F->arena.alloc<int>(std::max<int64_t>(P.tot_s, 1));
   int* d_r = tmp.upload(P.rows, s);
   int* d_c = tmp.upload(P.cols, s);
   int* d_rl = tmp.upload(rloc, s);
@@ -830,6 +865,7 @@ void factor_all(pmx_factor* F, hipStream_t s) {
   L0.tot_s = L0.offS[nc0];
   L0.D = F->arena.alloc<cx<R>>(td);
   L0.ipiv = F->arena.alloc<int>(L0.tot_s);
+  L0.perm = F->arena.alloc<int>(L0.tot_s);
   {
     Arena tmp;
     if (F->opts.precision == 0) {
@@ -860,9 +896,10 @@ void factor_all(pmx_factor* F, hipStream_t s) {
       T.root_s = cur.s0[0] + cur.s1[0];
       T.Droot = cur.D;
       T.ipiv_root = cur.ipiv;
+      T.perm_root = cur.perm;
       T.root_rows = cur.rows;
       T.root_cols = cur.cols;
-      std::vector<LuDescT<R>> lu{LuDescT<R>{T.Droot, T.root_s, T.root_s, T.ipiv_root}};
+      std::vector<LuDescT<R>> lu{LuDescT<R>{T.Droot, T.root_s, T.root_s, T.ipiv_root, T.perm_root}};
       T.d_lu_root = F->arena.upload(lu, s);
       Arena tmp;
       int* d_info = tmp.alloc<int>(1);
@@ -910,44 +947,46 @@ void fill_info(pmx_factor* F) {
 
 // ---------------------------------------------------------------------------------
 // solve
+// ---------------------------------------------------------------------------------
+// solve programs
+//
+// A solve program holds, for one factor type and one right-hand-side count, every buffer
+// and launch descriptor of the upward pass (y = D^-1 f, g = At R y), the top solve and the
+// downward pass (x = y - Y (g - At psi)), so that running it only launches kernels.
+// Vectors of a level are stored per cell, column major with leading dimension = rows.
 template <class R>
-void ensure_solve_buffers(pmx_factor* F, int nrhs) {
+void build_program(pmx_factor* F, int nrhs, hipStream_t s) {
   Tier<R>& T = tier<R>(F);
-  SolveCache<R>& S = T.sc;
-  if (S.nrhs == nrhs) return;
-  S.arena.release();
-  S.F.clear();
-  S.G.clear();
-  S.Red.clear();
-  for (const LevelData<R>& L : T.lev) {
-    S.F.push_back(S.arena.template alloc<cx<R>>(L.tot_s * nrhs));
-    S.G.push_back(S.arena.template alloc<cx<R>>(std::max<int64_t>(L.tot_k, 1) * nrhs));
-    S.Red.push_back(S.arena.template alloc<cx<R>>(std::max<int64_t>(L.tot_s - L.tot_k, 1) * nrhs));
-  }
-  S.Froot = S.arena.template alloc<cx<R>>((int64_t)T.root_s * nrhs);
-  S.nrhs = nrhs;
-}
-
-// vectors of a level are stored per cell, column major with leading dimension = rows
-template <class R>
-void solve_core(pmx_factor* F, int nrhs, cx<R>* fleaf_or_root, hipStream_t s) {
-  Tier<R>& T = tier<R>(F);
-  SolveCache<R>& S = T.sc;
-  Arena tmp;
+  SolveProgram<R>& P = T.prog;
+  P.arena.release();
+  P.lv.clear();
+  P.nrhs = -1;
+  Arena& A = P.arena;
   const int nl = (int)T.lev.size();
-  const cx<R> one = cmk<R>(1, 0), mone = cmk<R>(-1, 0);
+  P.lv.resize(nl);
   for (int l = 0; l < nl; ++l) {
-    LevelData<R>& L = T.lev[l];
+    const LevelData<R>& L = T.lev[l];
+    SolveLevel<R>& S = P.lv[l];
+    S.F = A.alloc<cx<R>>(L.tot_s * nrhs);
+    S.G = A.alloc<cx<R>>(std::max<int64_t>(L.tot_k, 1) * nrhs);
+    S.Red = A.alloc<cx<R>>(std::max<int64_t>(L.tot_s - L.tot_k, 1) * nrhs);
+    S.Ry = A.alloc<cx<R>>(std::max<int64_t>(L.tot_k, 1) * nrhs);
+    S.W = A.alloc<cx<R>>(L.tot_s * nrhs);
+  }
+  P.Froot = A.alloc<cx<R>>((int64_t)T.root_s * nrhs);
+  for (int l = 0; l < nl; ++l) {
+    const LevelData<R>& L = T.lev[l];
+    SolveLevel<R>& S = P.lv[l];
     const int nc = L.ncell;
-    cx<R>* Fv = S.F[l];
     // y = D^-1 f
-    std::vector<MatT<R>> bm(nc);
+    std::vector<MatT<R>> bm(nc), wm(nc);
     for (int t = 0; t < nc; ++t) {
       int sz = L.s0[t] + L.s1[t];
-      bm[t] = MatT<R>{Fv + L.offS[t] * nrhs, sz, sz, nrhs};
+      bm[t] = MatT<R>{S.F + L.offS[t] * nrhs, sz, sz, nrhs};
+      wm[t] = MatT<R>{S.W + L.offS[t] * nrhs, sz, sz, nrhs};
     }
-    MatT<R>* d_bm = tmp.upload(bm, s);
-    la_getrs(L.d_lu, d_bm, nc, L.max_s, nrhs, s);
+    S.d_bm = A.upload(bm, s);
+    S.d_w = A.upload(wm, s);
     // R y -> G (skeleton rows, then + T * redundant rows)
     std::vector<RowSrc> rs;
     std::vector<int64_t> rso;
@@ -965,7 +1004,7 @@ void solve_core(pmx_factor* F, int nrhs, cx<R>* fleaf_or_root, hipStream_t s) {
         int base = ty ? L.s0[t] : 0;
         for (int i = 0; i < kb; ++i) rs.push_back(RowSrc{yo + base + L.cpiv[L.offS[t] + base + i], sz});
       }
-      gd.push_back(GatherDescT<R>{nullptr, K, nrhs, S.G[l] + L.offK[t] * nrhs, K});
+      gd.push_back(GatherDescT<R>{nullptr, K, nrhs, S.G + L.offK[t] * nrhs, K});
       maxr = std::max(maxr, K);
       for (int ty = 0; ty < 2; ++ty) {
         int kb = ty ? L.k1[t] : L.k0[t];
@@ -974,65 +1013,49 @@ void solve_core(pmx_factor* F, int nrhs, cx<R>* fleaf_or_root, hipStream_t s) {
         int nr = sb - kb;
         rso.push_back((int64_t)rs.size());
         for (int j = 0; j < nr; ++j) rs.push_back(RowSrc{yo + base + L.cpiv[L.offS[t] + base + kb + j], sz});
-        gd.push_back(GatherDescT<R>{nullptr, nr, nrhs, S.Red[l] + ro, std::max(nr, 1)});
+        gd.push_back(GatherDescT<R>{nullptr, nr, nrhs, S.Red + ro, std::max(nr, 1)});
         maxr = std::max(maxr, nr);
         if (nr > 0) {
-          GemmArgsT<R> a;
-          a.m = kb;
-          a.n = nrhs;
-          a.k = nr;
-          a.A = L.Tc + L.offT[t] + (ty ? (int64_t)L.k0[t] * (L.s0[t] - L.k0[t]) : 0);
-          a.lda = kb;
-          a.B = S.Red[l] + ro;
-          a.ldb = nr;
-          a.C = S.G[l] + L.offK[t] * nrhs + (ty ? L.k0[t] : 0);
-          a.ldc = K;
-          ga.push_back(a);
+          GemmArgsT<R> g;
+          g.m = kb;
+          g.n = nrhs;
+          g.k = nr;
+          g.A = L.Tc + L.offT[t] + (ty ? (int64_t)L.k0[t] * (L.s0[t] - L.k0[t]) : 0);
+          g.lda = kb;
+          g.B = S.Red + ro;
+          g.ldb = nr;
+          g.C = S.G + L.offK[t] * nrhs + (ty ? L.k0[t] : 0);
+          g.ldc = K;
+          ga.push_back(g);
         }
         ro += (int64_t)nr * nrhs;
       }
+      gb.push_back(GemmArgsT<R>{K, nrhs, K, L.At + L.offA[t], K, S.Ry + L.offK[t] * nrhs, K,
+                                S.G + L.offK[t] * nrhs, K});
     }
-    RowSrc* d_rs = tmp.upload(rs, s);
+    RowSrc* d_rs = A.upload(rs, s);
     for (size_t i = 0; i < gd.size(); ++i) gd[i].src = d_rs + rso[i];
-    GatherDescT<R>* d_gd = tmp.upload(gd, s);
-    asm_gather(Fv, d_gd, (int)gd.size(), maxr, nrhs, s);
-    if (!ga.empty()) {
-      GemmArgsT<R>* d_ga = tmp.upload(ga, s);
-      la_zgemm_list(OP_N, OP_N, d_ga, (int)ga.size(), L.max_k, nrhs, one, one, s);
-    }
-    // g = At (R y): into Red-free temporary then back to G
-    cx<R>* Ry = tmp.alloc<cx<R>>(std::max<int64_t>(L.tot_k, 1) * nrhs);
-    HIPCHK(hipMemcpyAsync(Ry, S.G[l], L.tot_k * nrhs * sizeof(cx<R>), hipMemcpyDeviceToDevice, s));
-    for (int t = 0; t < nc; ++t) {
-      int K = L.k0[t] + L.k1[t];
-      GemmArgsT<R> a;
-      a.m = K;
-      a.n = nrhs;
-      a.k = K;
-      a.A = L.At + L.offA[t];
-      a.lda = K;
-      a.B = Ry + L.offK[t] * nrhs;
-      a.ldb = K;
-      a.C = S.G[l] + L.offK[t] * nrhs;
-      a.ldc = K;
-      gb.push_back(a);
-    }
-    GemmArgsT<R>* d_gb = tmp.upload(gb, s);
-    la_zgemm_list(OP_N, OP_N, d_gb, nc, L.max_k, nrhs, one, cmk<R>(0, 0), s);
+    S.d_up = A.upload(gd, s);
+    S.n_up = (int)gd.size();
+    S.max_up = maxr;
+    S.n_ga = (int)ga.size();
+    if (!ga.empty()) S.d_ga = A.upload(ga, s);
+    S.d_gb = A.upload(gb, s);
+    S.tot_k = L.tot_k;
     // parent right-hand sides
     const bool top = (l + 1 == nl);
     const std::vector<CellPlan>& pc = F->plan[l + 1];
-    cx<R>* dst = top ? S.Froot : S.F[l + 1];
+    cx<R>* dst = top ? P.Froot : P.lv[l + 1].F;
     std::vector<RowSrc> prs;
     std::vector<GatherDescT<R>> pgd;
     std::vector<int64_t> pro;
     int maxp = 0;
     int64_t po = 0;
-    for (size_t p = 0; p < pc.size(); ++p) {
+    for (size_t q = 0; q < pc.size(); ++q) {
       pro.push_back((int64_t)prs.size());
       int cnt = 0;
       for (int ty = 0; ty < 2; ++ty)
-        for (int c : pc[p].children) {
+        for (int c : pc[q].children) {
           int K = L.k0[c] + L.k1[c];
           int kb = ty ? L.k1[c] : L.k0[c];
           int base = ty ? L.k0[c] : 0;
@@ -1043,91 +1066,106 @@ void solve_core(pmx_factor* F, int nrhs, cx<R>* fleaf_or_root, hipStream_t s) {
       po += cnt;
       maxp = std::max(maxp, cnt);
     }
-    RowSrc* d_prs = tmp.upload(prs, s);
+    RowSrc* d_prs = A.upload(prs, s);
     for (size_t i = 0; i < pgd.size(); ++i) pgd[i].src = d_prs + pro[i];
-    GatherDescT<R>* d_pgd = tmp.upload(pgd, s);
-    asm_gather(S.G[l], d_pgd, (int)pgd.size(), maxp, nrhs, s);
-  }
-  // root solve
-  {
-    cx<R>* root = (nl == 0) ? fleaf_or_root : S.Froot;
-    std::vector<MatT<R>> bm{MatT<R>{root, T.root_s, T.root_s, nrhs}};
-    MatT<R>* d_bm = tmp.upload(bm, s);
-    la_getrs(T.d_lu_root, d_bm, 1, T.root_s, nrhs, s);
-  }
-  // downward pass
-  for (int l = nl - 1; l >= 0; --l) {
-    LevelData<R>& L = T.lev[l];
-    const int nc = L.ncell;
-    const bool top = (l + 1 == nl);
-    const cx<R>* xp = top ? S.Froot : S.F[l + 1];
+    S.d_par = A.upload(pgd, s);
+    S.n_par = (int)pgd.size();
+    S.max_par = maxp;
+    // downward: psi of each cell from its parent's solution, then g -= At psi, x = y - Y g
     const LevelData<R>* Pl = top ? nullptr : &T.lev[l + 1];
-    const std::vector<CellPlan>& pc = F->plan[l + 1];
-    // psi of each child from its parent's solution -> Red scratch (K x nrhs per cell)
     std::vector<int64_t> psio(nc);
     int64_t o = 0;
     for (int t = 0; t < nc; ++t) {
       psio[t] = o;
       o += (int64_t)(L.k0[t] + L.k1[t]) * nrhs;
     }
-    cx<R>* Psi = tmp.alloc<cx<R>>(std::max<int64_t>(o, 1));
-    std::vector<RowSrc> rs(L.tot_k);
-    std::vector<GatherDescT<R>> gd(nc);
-    for (size_t p = 0; p < pc.size(); ++p) {
-      int64_t pbase = top ? 0 : Pl->offS[p];
-      int psz = top ? T.root_s : Pl->s0[p] + Pl->s1[p];
+    S.Psi = A.alloc<cx<R>>(std::max<int64_t>(o, 1));
+    std::vector<RowSrc> xrs(L.tot_k);
+    for (size_t q = 0; q < pc.size(); ++q) {
+      int64_t pbase = top ? 0 : Pl->offS[q];
+      int psz = top ? T.root_s : Pl->s0[q] + Pl->s1[q];
       int pos = 0;
       for (int ty = 0; ty < 2; ++ty)
-        for (int c : pc[p].children) {
+        for (int c : pc[q].children) {
           int kb = ty ? L.k1[c] : L.k0[c];
           int base = ty ? L.k0[c] : 0;
-          for (int i = 0; i < kb; ++i) rs[L.offK[c] + base + i] = RowSrc{pbase * nrhs + pos + i, psz};
+          for (int i = 0; i < kb; ++i) xrs[L.offK[c] + base + i] = RowSrc{pbase * nrhs + pos + i, psz};
           pos += kb;
         }
     }
-    RowSrc* d_rs = tmp.upload(rs, s);
-    for (int t = 0; t < nc; ++t) {
-      int K = L.k0[t] + L.k1[t];
-      gd[t] = GatherDescT<R>{d_rs + L.offK[t], K, nrhs, Psi + psio[t], K};
-    }
-    GatherDescT<R>* d_gd = tmp.upload(gd, s);
-    asm_gather(xp, d_gd, nc, L.max_k, nrhs, s);
-    // g <- g - At psi ; x = y - Y g
+    RowSrc* d_xrs = A.upload(xrs, s);
+    std::vector<GatherDescT<R>> xgd(nc);
     std::vector<GemmArgsT<R>> g1(nc), g2(nc);
     for (int t = 0; t < nc; ++t) {
       int K = L.k0[t] + L.k1[t];
       int sz = L.s0[t] + L.s1[t];
-      g1[t] = GemmArgsT<R>{K, nrhs, K, L.At + L.offA[t], K, Psi + psio[t], K, S.G[l] + L.offK[t] * nrhs, K};
-      g2[t] = GemmArgsT<R>{sz, nrhs, K, L.Y + L.offY[t], sz, S.G[l] + L.offK[t] * nrhs, K, S.F[l] + L.offS[t] * nrhs, sz};
+      xgd[t] = GatherDescT<R>{d_xrs + L.offK[t], K, nrhs, S.Psi + psio[t], K};
+      g1[t] = GemmArgsT<R>{K, nrhs, K, L.At + L.offA[t], K, S.Psi + psio[t], K, S.G + L.offK[t] * nrhs, K};
+      g2[t] = GemmArgsT<R>{sz, nrhs, K, L.Y + L.offY[t], sz, S.G + L.offK[t] * nrhs, K, S.F + L.offS[t] * nrhs, sz};
     }
-    GemmArgsT<R>* d_g1 = tmp.upload(g1, s);
-    GemmArgsT<R>* d_g2 = tmp.upload(g2, s);
-    la_zgemm_list(OP_N, OP_N, d_g1, nc, L.max_k, nrhs, mone, one, s);
-    la_zgemm_list(OP_N, OP_N, d_g2, nc, L.max_s, nrhs, mone, one, s);
+    S.d_psi = A.upload(xgd, s);
+    S.d_g1 = A.upload(g1, s);
+    S.d_g2 = A.upload(g2, s);
   }
-  sync_check(s);
+  std::vector<MatT<R>> rb{MatT<R>{P.Froot, T.root_s, T.root_s, nrhs}};
+  P.d_bm_root = A.upload(rb, s);
+  std::vector<MatT<R>> rw{MatT<R>{A.alloc<cx<R>>((int64_t)T.root_s * nrhs), T.root_s, T.root_s, nrhs}};
+  P.d_w_root = A.upload(rw, s);
+  P.leaf = nl ? P.lv[0].F : P.Froot;
+  P.nrhs = nrhs;
+}
+
+// the launches of one solve pass on the leaf vectors P.leaf (in place); no host work
+template <class R>
+void launch_program(pmx_factor* F, hipStream_t s) {
+  Tier<R>& T = tier<R>(F);
+  SolveProgram<R>& P = T.prog;
+  const int nrhs = P.nrhs;
+  const int nl = (int)T.lev.size();
+  const cx<R> one = cmk<R>(1, 0), mone = cmk<R>(-1, 0), zero = cmk<R>(0, 0);
+  for (int l = 0; l < nl; ++l) {
+    const LevelData<R>& L = T.lev[l];
+    SolveLevel<R>& S = P.lv[l];
+    if (nrhs <= PMX_GETRS_SMALL_MAX)
+      la_getrs_small(L.d_lu, S.d_bm, S.d_w, L.ncell, L.max_s, nrhs, s);
+    else
+      la_getrs(L.d_lu, S.d_bm, L.ncell, L.max_s, nrhs, s);
+    asm_gather(S.F, S.d_up, S.n_up, S.max_up, nrhs, s);
+    if (S.n_ga) la_zgemm_list(OP_N, OP_N, S.d_ga, S.n_ga, L.max_k, nrhs, one, one, s);
+    asm_convert(S.G, S.Ry, S.tot_k * nrhs, s);
+    la_zgemm_list(OP_N, OP_N, S.d_gb, L.ncell, L.max_k, nrhs, one, zero, s);
+    const bool top = (l + 1 == nl);
+    (void)top;
+    asm_gather(S.G, S.d_par, S.n_par, S.max_par, nrhs, s);
+  }
+  if (nrhs <= PMX_GETRS_SMALL_MAX)
+    la_getrs_small(T.d_lu_root, P.d_bm_root, P.d_w_root, 1, T.root_s, nrhs, s);
+  else
+    la_getrs(T.d_lu_root, P.d_bm_root, 1, T.root_s, nrhs, s);
+  for (int l = nl - 1; l >= 0; --l) {
+    const LevelData<R>& L = T.lev[l];
+    SolveLevel<R>& S = P.lv[l];
+    const cx<R>* xp = (l + 1 == nl) ? P.Froot : P.lv[l + 1].F;
+    asm_gather(xp, S.d_psi, L.ncell, L.max_k, nrhs, s);
+    la_zgemm_list(OP_N, OP_N, S.d_g1, L.ncell, L.max_k, nrhs, mone, one, s);
+    la_zgemm_list(OP_N, OP_N, S.d_g2, L.ncell, L.max_s, nrhs, mone, one, s);
+  }
 }
 
 // Row maps between the leaf cell vectors (per cell [2 n x nrhs], cells in leaf order) and
-// the density layout [nrhs][2 N] (per inclusion [q; u]); built once per right-hand-side
-// count and reused by every gather of a solve.
+// the density layout [nrhs][2 N] (per inclusion [q; u]).
 struct LeafMap {
-  int nrhs = -1;
   int n2 = 0, max_cell = 0, ncell = 0;
-  std::vector<RowSrc> to_dens, to_leaf;
   std::vector<int64_t> leaf_off;    // per cell: first leaf entry / nrhs
   std::vector<int> cell_rows;
   RowSrc *d_to_dens = nullptr, *d_to_leaf = nullptr;
-  Arena arena;
 };
 
-void build_leaf_map(pmx_factor* F, int nrhs, LeafMap& M, hipStream_t s) {
-  M.arena.release();
+void build_leaf_map(pmx_factor* F, int nrhs, LeafMap& M, Arena& A, hipStream_t s) {
   const std::vector<CellPlan>& leaves = F->plan[0];
   M.n2 = 2 * F->n_nodes;
   M.ncell = (int)leaves.size();
-  M.to_dens.assign(M.n2, RowSrc{0, 0});
-  M.to_leaf.assign(M.n2, RowSrc{0, 0});
+  std::vector<RowSrc> to_dens(M.n2, RowSrc{0, 0}), to_leaf(M.n2, RowSrc{0, 0});
   M.leaf_off.assign(M.ncell, 0);
   M.cell_rows.assign(M.ncell, 0);
   M.max_cell = 0;
@@ -1136,100 +1174,70 @@ void build_leaf_map(pmx_factor* F, int nrhs, LeafMap& M, hipStream_t s) {
     int j = leaves[t].incl[0];
     int n = (int)(F->node_off[j + 1] - F->node_off[j]);
     for (int r = 0; r < 2 * n; ++r) {
-      M.to_dens[2 * F->node_off[j] + r] = RowSrc{off * nrhs + r, 2 * n};
-      M.to_leaf[off + r] = RowSrc{2 * F->node_off[j] + r, M.n2};
+      to_dens[2 * F->node_off[j] + r] = RowSrc{off * nrhs + r, 2 * n};
+      to_leaf[off + r] = RowSrc{2 * F->node_off[j] + r, M.n2};
     }
     M.leaf_off[t] = off;
     M.cell_rows[t] = 2 * n;
     M.max_cell = std::max(M.max_cell, 2 * n);
     off += 2 * n;
   }
-  M.d_to_dens = M.arena.upload(M.to_dens, s);
-  M.d_to_leaf = M.arena.upload(M.to_leaf, s);
-  M.nrhs = nrhs;
+  M.d_to_dens = A.upload(to_dens, s);
+  M.d_to_leaf = A.upload(to_leaf, s);
 }
 
-// dens (type RD) [+]= leaf (type RS)
-template <class RS, class RD>
-void leaf_to_dens(const LeafMap& M, const cx<RS>* leaf, int nrhs, cx<RD>* dens, int acc, Arena& tmp,
-                  hipStream_t s) {
+// descriptors: leaf vectors -> one density-layout buffer, and back per cell
+template <class RD>
+GatherDescT<RD>* gather_to_dens(const LeafMap& M, cx<RD>* dens, int nrhs, Arena& A, hipStream_t s) {
   std::vector<GatherDescT<RD>> gd{GatherDescT<RD>{M.d_to_dens, M.n2, nrhs, dens, M.n2}};
-  asm_gather(leaf, tmp.upload(gd, s), 1, M.n2, nrhs, s, acc);
+  return A.upload(gd, s);
 }
 
-template <class RS, class RD>
-void dens_to_leaf(const LeafMap& M, const cx<RS>* dens, int nrhs, cx<RD>* leaf, Arena& tmp, hipStream_t s) {
+template <class RD>
+GatherDescT<RD>* gather_to_leaf(const LeafMap& M, cx<RD>* leaf, int nrhs, Arena& A, hipStream_t s) {
   std::vector<GatherDescT<RD>> gd(M.ncell);
   for (int t = 0; t < M.ncell; ++t)
     gd[t] = GatherDescT<RD>{M.d_to_leaf + M.leaf_off[t], M.cell_rows[t], nrhs, leaf + M.leaf_off[t] * nrhs,
                             M.cell_rows[t]};
-  asm_gather(dens, tmp.upload(gd, s), M.ncell, M.max_cell, nrhs, s, 0);
+  return A.upload(gd, s);
 }
 
-template <class R>
-cx<R>* leaf_vectors(pmx_factor* F) {
-  Tier<R>& T = tier<R>(F);
-  return T.lev.empty() ? T.sc.Froot : T.sc.F[0];
-}
-
-// leaf right-hand sides of plane waves (FP64, leaf layout)
-void plane_wave_leaf(pmx_factor* F, int nrhs, const double* angles, zd* leaf, Arena& tmp, hipStream_t s) {
-  const std::vector<CellPlan>& leaves = F->plan[0];
-  const int nc = (int)leaves.size();
-  std::vector<int> node0(nc), nn(nc);
-  std::vector<int64_t> off(nc);
-  int64_t o = 0;
-  int maxn = 0;
-  for (int t = 0; t < nc; ++t) {
-    int j = leaves[t].incl[0];
-    node0[t] = (int)F->node_off[j];
-    nn[t] = (int)(F->node_off[j + 1] - F->node_off[j]);
-    off[t] = o * nrhs;
-    o += 2 * nn[t];
-    maxn = std::max(maxn, nn[t]);
-  }
-  std::vector<double> ang(angles, angles + nrhs);
-  asm_incident(F->geom(), F->ext(), tmp.upload(node0, s), tmp.upload(nn, s), tmp.upload(off, s), nc, maxn,
-               tmp.upload(ang, s), nrhs, leaf, s);
-}
-
-// Dense FP64 operator apply y = A x, or the residual out = f - A x: the self blocks from
-// FP64 storage (leaf order, offsets doff) by batched MFMA products, the blocks between
-// inclusions evaluated on the fly.  Buffers are sized once per right-hand-side count.
+// Dense FP64 operator apply y = A x, or the residual out = f - A x, for fixed buffers: the
+// self blocks from FP64 storage (block of inclusion incl[t] at offset doff[t], 2 n x 2 n)
+// by batched MFMA products, the blocks between inclusions evaluated on the fly.
 struct DenseApply {
   int nrhs = -1, nsplit = 1, nblk = 1;
   int64_t total = 0;
   zd *ydiag = nullptr, *part = nullptr;
   double* d_norm = nullptr;
-  Arena arena;
+  GemmArgs* d_ga = nullptr;
+  int n_ga = 0, max_s = 0;
+  ApplyArgs aa;
+  const zd* f = nullptr;
+  zd* out = nullptr;
 };
 
-void build_dense_apply(pmx_factor* F, int nrhs, DenseApply& D) {
-  D.arena.release();
+void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vector<int>& incl,
+                       const std::vector<int64_t>& doff, const zd* x, const zd* f, zd* out, DenseApply& D, Arena& A,
+                       hipStream_t s) {
   const int64_t N2 = 2 * (int64_t)F->n_nodes;
   D.total = N2 * nrhs;
   D.nsplit = apply_splits(F->n_nodes, nrhs);
-  D.ydiag = D.arena.alloc<zd>(D.total);
-  D.part = D.arena.alloc<zd>(D.total * D.nsplit);
+  D.ydiag = A.alloc<zd>(D.total);
+  D.part = A.alloc<zd>(D.total * D.nsplit);
   D.nblk = (int)std::min<int64_t>(64, (N2 + 4095) / 4096);
-  D.d_norm = D.arena.alloc<double>((int64_t)D.nblk * nrhs);
-  D.nrhs = nrhs;
-}
-
-// dself holds the self block of inclusion incl[t] at offset doff[t] (2 n x 2 n, ld 2 n)
-void run_dense_apply(pmx_factor* F, DenseApply& D, const zd* dself, const std::vector<int>& incl,
-                     const std::vector<int64_t>& doff, const zd* x, const zd* f, zd* out, Arena& tmp, hipStream_t s) {
-  const int64_t N2 = 2 * (int64_t)F->n_nodes;
+  D.d_norm = A.alloc<double>((int64_t)D.nblk * nrhs);
   std::vector<GemmArgs> ga(incl.size());
-  int max_s = 0;
+  D.max_s = 0;
   for (size_t t = 0; t < incl.size(); ++t) {
     int j = incl[t];
     int n2 = (int)(2 * (F->node_off[j + 1] - F->node_off[j]));
-    ga[t] = GemmArgs{n2, D.nrhs, n2, dself + doff[t], n2, x + 2 * F->node_off[j], N2, D.ydiag + 2 * F->node_off[j], N2};
-    max_s = std::max(max_s, n2);
+    ga[t] = GemmArgs{n2, nrhs, n2, dself + doff[t], n2, x + 2 * F->node_off[j], N2, D.ydiag + 2 * F->node_off[j], N2};
+    D.max_s = std::max(D.max_s, n2);
   }
-  la_zgemm_list(OP_N, OP_N, tmp.upload(ga, s), (int)ga.size(), max_s, D.nrhs, zmk(1, 0), zmk(0, 0), s);
-  ApplyArgs aa;
+  D.d_ga = A.upload(ga, s);
+  D.n_ga = (int)ga.size();
+  ApplyArgs& aa = D.aa;
   aa.x = F->x;
   aa.y = F->y;
   aa.nx = F->nx;
@@ -1241,20 +1249,30 @@ void run_dense_apply(pmx_factor* F, DenseApply& D, const zd* dself, const std::v
   aa.k = F->k_ext;
   aa.eps = F->eps_ext;
   aa.xin = x;
-  aa.nrhs = D.nrhs;
+  aa.nrhs = nrhs;
   aa.ld = N2;
   aa.part = D.part;
-  asm_apply_off(aa, D.nsplit, s);
-  if (f)
-    asm_apply_finish(f, D.ydiag, D.part, D.nsplit, D.total, 1.0, -1.0, out, s);
-  else
-    asm_apply_finish(nullptr, D.ydiag, D.part, D.nsplit, D.total, 0.0, 1.0, out, s);
+  D.f = f;
+  D.out = out;
+  D.nrhs = nrhs;
 }
 
-// squared column norms of v (density layout, nrhs columns)
-std::vector<double> dens_norms2(pmx_factor* F, DenseApply& D, const zd* v, hipStream_t s) {
-  const int64_t N2 = 2 * (int64_t)F->n_nodes;
+void launch_dense_apply(const DenseApply& D, hipStream_t s) {
+  la_zgemm_list(OP_N, OP_N, D.d_ga, D.n_ga, D.max_s, D.nrhs, zmk(1, 0), zmk(0, 0), s);
+  asm_apply_off(D.aa, D.nsplit, s);
+  if (D.f)
+    asm_apply_finish(D.f, D.ydiag, D.part, D.nsplit, D.total, 1.0, -1.0, D.out, s);
+  else
+    asm_apply_finish(nullptr, D.ydiag, D.part, D.nsplit, D.total, 0.0, 1.0, D.out, s);
+}
+
+// squared column norms of v (density layout, nrhs columns), partial sums on the device
+void launch_norms(const DenseApply& D, const zd* v, hipStream_t s) {
+  const int64_t N2 = D.total / D.nrhs;
   asm_colnorm2(v, N2, D.nrhs, N2, D.nblk, D.d_norm, s);
+}
+
+std::vector<double> read_norms(const DenseApply& D, hipStream_t s) {
   std::vector<double> part;
   download(part, D.d_norm, (size_t)D.nblk * D.nrhs, s);
   std::vector<double> out(D.nrhs, 0.0);
@@ -1263,57 +1281,197 @@ std::vector<double> dens_norms2(pmx_factor* F, DenseApply& D, const zd* v, hipSt
   return out;
 }
 
-// FP64 factor: leaf right-hand sides, one pass of the solver, densities.
-void solve_fp64(pmx_factor* F, int nrhs, const double* angles, const zd* rhs, zd* dens, hipStream_t s) {
-  ensure_solve_buffers<double>(F, nrhs);
-  Arena tmp;
-  LeafMap M;
-  build_leaf_map(F, nrhs, M, s);
-  zd* leaf = leaf_vectors<double>(F);
-  if (angles)
-    plane_wave_leaf(F, nrhs, angles, leaf, tmp, s);
-  else
-    dens_to_leaf(M, rhs, nrhs, leaf, tmp, s);
-  solve_core<double>(F, nrhs, leaf, s);
-  leaf_to_dens(M, leaf, nrhs, dens, 0, tmp, s);
-  sync_check(s);
+}  // namespace
+
+// Everything a solve with a given right-hand-side count needs besides the factor: the
+// leaf maps, plane-wave tables, internal input / output vectors (density layout, FP64),
+// the refinement buffers and the captured graphs (one per launch sequence).
+struct SolveState {
+  int nrhs = -1;
+  LeafMap map;
+  int *d_node0 = nullptr, *d_nn = nullptr;
+  int64_t* d_off = nullptr;
+  double* d_angles = nullptr;
+  std::vector<double> h_angles;
+  int maxn = 0;
+  zd *fin = nullptr, *xout = nullptr;   // general right-hand side, solution
+  zd *f = nullptr, *r = nullptr, *leaf64 = nullptr;
+  GatherDescT<double>* d_fin_to_leaf = nullptr;    // precision 0: fin -> leaf vectors
+  GatherDescT<double>* d_leaf_to_x = nullptr;      // leaf (FP64) -> xout
+  GatherDescT<double>* d_leaf64_to_f = nullptr;    // refinement: plane-wave leaf -> f
+  void* d_r_to_leaf = nullptr;                     // refinement: r -> leaf vectors (factor type)
+  void* d_leafr_to_x = nullptr;                    // refinement: leaf (factor type) += -> xout
+  DenseApply apply;
+  hipGraphExec_t g_plane = nullptr, g_general = nullptr, g_iter = nullptr;
+  Arena arena;
+  void drop_graphs() {
+    for (hipGraphExec_t* g : {&g_plane, &g_general, &g_iter})
+      if (*g) {
+        (void)hipGraphExecDestroy(*g);
+        *g = nullptr;
+      }
+  }
+  void reset() {
+    drop_graphs();
+    arena.release();
+    nrhs = -1;
+  }
+  ~SolveState() { drop_graphs(); }
+};
+
+pmx_factor::~pmx_factor() {
+  if (gs) (void)hipStreamSynchronize(gs);
+  ss.reset();
+  if (ev_in) (void)hipEventDestroy(ev_in);
+  if (ev_out) (void)hipEventDestroy(ev_out);
+  if (gs) (void)hipStreamDestroy(gs);
+}
+
+namespace {
+
+template <class Fn>
+hipGraphExec_t capture_graph(hipStream_t gs, Fn&& fn) {
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+  fn();
+  const hipError_t e1 = hipStreamEndCapture(gs, &g);
+  if (e1 != hipSuccess || !g) {
+    (void)hipGetLastError();
+    fail(PMX_EHIP, std::string("graph capture failed: ") + hipGetErrorString(e1));
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) fail(PMX_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(e2));
+  return ex;
+}
+
+// run a launch sequence, through its captured graph when graphs are on
+template <class Fn>
+void run_seq(pmx_factor* F, hipGraphExec_t& g, Fn&& fn) {
+  if (!F->opts.solve_graph) {
+    fn();
+    return;
+  }
+  if (!g) g = capture_graph(F->gs, fn);
+  HIPCHK(hipGraphLaunch(g, F->gs));
+}
+
+template <class R>
+void ensure_state(pmx_factor* F, int nrhs) {
+  SolveState& S = *F->ss;
+  if (S.nrhs == nrhs) return;
+  S.reset();
+  hipStream_t s = F->gs;
+  Arena& A = S.arena;
+  build_program<R>(F, nrhs, s);
+  build_leaf_map(F, nrhs, S.map, A, s);
+  const std::vector<CellPlan>& leaves = F->plan[0];
+  const int nc = (int)leaves.size();
+  std::vector<int> node0(nc), nn(nc);
+  std::vector<int64_t> off(nc);
+  int64_t o = 0;
+  S.maxn = 0;
+  for (int t = 0; t < nc; ++t) {
+    int j = leaves[t].incl[0];
+    node0[t] = (int)F->node_off[j];
+    nn[t] = (int)(F->node_off[j + 1] - F->node_off[j]);
+    off[t] = o * nrhs;
+    o += 2 * nn[t];
+    S.maxn = std::max(S.maxn, nn[t]);
+  }
+  S.d_node0 = A.upload(node0, s);
+  S.d_nn = A.upload(nn, s);
+  S.d_off = A.upload(off, s);
+  S.d_angles = A.alloc<double>(nrhs);
+  S.h_angles.assign(nrhs, 0.0);
+  const int64_t total = 2 * (int64_t)F->n_nodes * nrhs;
+  S.fin = A.alloc<zd>(total);
+  S.xout = A.alloc<zd>(total);
+  cx<R>* leaf = tier<R>(F).prog.leaf;
+  if (F->opts.precision == 0) {
+    S.d_fin_to_leaf = gather_to_leaf(S.map, (zd*)leaf, nrhs, A, s);
+    S.d_leaf_to_x = gather_to_dens(S.map, S.xout, nrhs, A, s);
+  } else {
+    S.f = A.alloc<zd>(total);
+    S.r = A.alloc<zd>(total);
+    S.leaf64 = A.alloc<zd>(total);
+    S.d_leaf64_to_f = gather_to_dens(S.map, S.f, nrhs, A, s);
+    S.d_r_to_leaf = gather_to_leaf(S.map, leaf, nrhs, A, s);
+    S.d_leaf_to_x = gather_to_dens(S.map, S.xout, nrhs, A, s);
+    build_dense_apply(F, nrhs, F->Dself, F->selfIncl, F->selfOff, S.xout, S.f, S.r, S.apply, A, s);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  S.nrhs = nrhs;
+}
+
+void upload_angles(pmx_factor* F, const double* angles) {
+  SolveState& S = *F->ss;
+  std::copy(angles, angles + S.nrhs, S.h_angles.begin());
+  HIPCHK(hipMemcpyAsync(S.d_angles, S.h_angles.data(), S.nrhs * sizeof(double), hipMemcpyHostToDevice, F->gs));
+}
+
+// FP64 factor: right-hand side into the leaf vectors, one solve pass, solution to xout.
+void solve_fp64(pmx_factor* F, int nrhs, const double* angles, const zd* rhs) {
+  ensure_state<double>(F, nrhs);
+  SolveState& S = *F->ss;
+  hipStream_t gs = F->gs;
+  zd* leaf = F->t64.prog.leaf;
+  const LeafMap& M = S.map;
+  if (angles) {
+    upload_angles(F, angles);
+    run_seq(F, S.g_plane, [&] {
+      asm_incident(F->geom(), F->ext(), S.d_node0, S.d_nn, S.d_off, M.ncell, S.maxn, S.d_angles, nrhs, leaf, gs);
+      launch_program<double>(F, gs);
+      asm_gather(leaf, S.d_leaf_to_x, 1, M.n2, nrhs, gs, 0);
+    });
+  } else {
+    HIPCHK(hipMemcpyAsync(S.fin, rhs, 2 * (int64_t)F->n_nodes * nrhs * sizeof(zd), hipMemcpyDeviceToDevice, gs));
+    run_seq(F, S.g_general, [&] {
+      asm_gather(S.fin, S.d_fin_to_leaf, M.ncell, M.max_cell, nrhs, gs, 0);
+      launch_program<double>(F, gs);
+      asm_gather(leaf, S.d_leaf_to_x, 1, M.n2, nrhs, gs, 0);
+    });
+  }
 }
 
 // Refinement: the factor of type R as the inner solver of iterative refinement with the
 // FP64 operator, x_0 = 0, r_i = f - A x_i, x_{i+1} = x_i + solve(r_i), until
-// max_r |r_i| / |f| <= ir_tol.
+// max_r |r_i| / |f| <= ir_tol.  One step (gathers, solve pass, operator apply, residual
+// norms) is one captured graph.
 template <class R>
-void solve_refined(pmx_factor* F, int nrhs, const double* angles, const zd* rhs, zd* dens, hipStream_t s) {
-  ensure_solve_buffers<R>(F, nrhs);
-  Arena tmp;
-  LeafMap M;
-  build_leaf_map(F, nrhs, M, s);
-  DenseApply D;
-  build_dense_apply(F, nrhs, D);
-  const int64_t total = D.total;
-  zd* f = tmp.alloc<zd>(total);
+void solve_refined(pmx_factor* F, int nrhs, const double* angles, const zd* rhs) {
+  ensure_state<R>(F, nrhs);
+  SolveState& S = *F->ss;
+  hipStream_t gs = F->gs;
+  const LeafMap& M = S.map;
+  const int64_t total = S.apply.total;
   if (angles) {
-    zd* leaf64 = tmp.alloc<zd>(total);
-    plane_wave_leaf(F, nrhs, angles, leaf64, tmp, s);
-    leaf_to_dens(M, leaf64, nrhs, f, 0, tmp, s);
+    upload_angles(F, angles);
+    asm_incident(F->geom(), F->ext(), S.d_node0, S.d_nn, S.d_off, M.ncell, S.maxn, S.d_angles, nrhs, S.leaf64, gs);
+    asm_gather(S.leaf64, S.d_leaf64_to_f, 1, M.n2, nrhs, gs, 0);
   } else {
-    HIPCHK(hipMemcpyAsync(f, rhs, total * sizeof(zd), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(S.f, rhs, total * sizeof(zd), hipMemcpyDeviceToDevice, gs));
   }
-  zd* r = tmp.alloc<zd>(total);
-  HIPCHK(hipMemcpyAsync(r, f, total * sizeof(zd), hipMemcpyDeviceToDevice, s));
-  asm_zero(dens, total, s);
-  const std::vector<double> fn = dens_norms2(F, D, f, s);
-  cx<R>* leaf = leaf_vectors<R>(F);
+  asm_convert(S.f, S.r, total, gs);
+  asm_zero(S.xout, total, gs);
+  launch_norms(S.apply, S.f, gs);
+  const std::vector<double> fn = read_norms(S.apply, gs);
+  cx<R>* leaf = tier<R>(F).prog.leaf;
+  const GatherDescT<R>* r_to_leaf = (const GatherDescT<R>*)S.d_r_to_leaf;
   const int maxit = std::max(1, F->opts.ir_max_iter);
   double rel = 0;
   int it = 0;
   for (int h = 0; h < 16; ++h) F->info.ir_history[h] = 0;
   for (it = 1; it <= maxit; ++it) {
-    dens_to_leaf(M, r, nrhs, leaf, tmp, s);
-    solve_core<R>(F, nrhs, leaf, s);
-    leaf_to_dens(M, leaf, nrhs, dens, 1, tmp, s);
-    run_dense_apply(F, D, F->Dself, F->selfIncl, F->selfOff, dens, f, r, tmp, s);
-    const std::vector<double> rn = dens_norms2(F, D, r, s);
+    run_seq(F, S.g_iter, [&] {
+      asm_gather(S.r, r_to_leaf, M.ncell, M.max_cell, nrhs, gs, 0);
+      launch_program<R>(F, gs);
+      asm_gather(leaf, S.d_leaf_to_x, 1, M.n2, nrhs, gs, 1);
+      launch_dense_apply(S.apply, gs);
+      launch_norms(S.apply, S.r, gs);
+    });
+    const std::vector<double> rn = read_norms(S.apply, gs);
     rel = 0;
     for (int c = 0; c < nrhs; ++c) rel = std::max(rel, fn[c] > 0 ? std::sqrt(rn[c] / fn[c]) : std::sqrt(rn[c]));
     if (it <= 16) F->info.ir_history[it - 1] = rel;
@@ -1321,23 +1479,41 @@ void solve_refined(pmx_factor* F, int nrhs, const double* angles, const zd* rhs,
   }
   F->info.ir_iterations = std::min(it, maxit);
   F->info.ir_residual = rel;
-  sync_check(s);
   if (rel > F->opts.ir_tol) {
     char buf[160];
     snprintf(buf, sizeof(buf), "iterative refinement stopped at relative residual %.3e after %d steps", rel, maxit);
-    fail(PMX_ENOTCONV, buf);
+    throw PmxErr{PMX_ENOTCONV, buf};
   }
 }
 
+// Solves run on the factor's own stream (so that their launch sequences can be captured
+// as graphs), ordered after the caller's stream and before its later work.
 void solve_any(pmx_factor* F, int nrhs, const double* angles, const zd* rhs, zd* dens, hipStream_t s) {
   const double t0 = now_ms();
-  if (F->opts.precision == 1)
-    solve_refined<float>(F, nrhs, angles, rhs, dens, s);
-  else if (F->opts.precision == 2)
-    solve_refined<double>(F, nrhs, angles, rhs, dens, s);
-  else
-    solve_fp64(F, nrhs, angles, rhs, dens, s);
+  HIPCHK(hipEventRecord(F->ev_in, s));
+  HIPCHK(hipStreamWaitEvent(F->gs, F->ev_in, 0));
+  pmx_status late = PMX_OK;
+  std::string late_msg;
+  try {
+    if (F->opts.precision == 1)
+      solve_refined<float>(F, nrhs, angles, rhs);
+    else if (F->opts.precision == 2)
+      solve_refined<double>(F, nrhs, angles, rhs);
+    else
+      solve_fp64(F, nrhs, angles, rhs);
+  } catch (const PmxErr& e) {
+    if (e.st != PMX_ENOTCONV) throw;
+    late = e.st;
+    late_msg = e.msg;
+  }
+  // the last iterate is returned also when refinement did not converge
+  HIPCHK(hipMemcpyAsync(dens, F->ss->xout, 2 * (int64_t)F->n_nodes * nrhs * sizeof(zd), hipMemcpyDeviceToDevice,
+                        F->gs));
+  HIPCHK(hipEventRecord(F->ev_out, F->gs));
+  HIPCHK(hipStreamWaitEvent(s, F->ev_out, 0));
+  sync_check(F->gs);
   F->info.t_solve_ms = now_ms() - t0;
+  if (late != PMX_OK) throw PmxErr{late, late_msg};
 }
 
 // ---------------------------------------------------------------------------------
@@ -1369,18 +1545,27 @@ void probe_gemm(int batch, int m, int n, int k, int opa, int opb, const cx<R>* A
 template <class R>
 void probe_lu(int batch, int n, cx<R>* A, int* ipiv, int nrhs, cx<R>* B, int* info, hipStream_t s) {
   if (batch <= 0 || n <= 0 || nrhs < 0 || !A || !ipiv || (nrhs > 0 && !B) || !info) fail(PMX_EINVAL, "bad arguments");
-  std::vector<LuDescT<R>> lu(batch);
-  std::vector<MatT<R>> bm(batch);
-  for (int b = 0; b < batch; ++b) {
-    lu[b] = LuDescT<R>{A + (int64_t)b * n * n, n, n, ipiv + (int64_t)b * n};
-    bm[b] = MatT<R>{nrhs > 0 ? B + (int64_t)b * n * nrhs : nullptr, n, n, nrhs};
-  }
   Arena tmp;
+  const bool small = nrhs > 0 && nrhs <= PMX_GETRS_SMALL_MAX;
+  int* perm = small ? tmp.alloc<int>((int64_t)batch * n) : nullptr;
+  cx<R>* work = small ? tmp.alloc<cx<R>>((int64_t)batch * n * nrhs) : nullptr;
+  std::vector<LuDescT<R>> lu(batch);
+  std::vector<MatT<R>> bm(batch), wm(batch);
+  for (int b = 0; b < batch; ++b) {
+    lu[b] = LuDescT<R>{A + (int64_t)b * n * n, n, n, ipiv + (int64_t)b * n, small ? perm + (int64_t)b * n : nullptr};
+    bm[b] = MatT<R>{nrhs > 0 ? B + (int64_t)b * n * nrhs : nullptr, n, n, nrhs};
+    wm[b] = MatT<R>{small ? work + (int64_t)b * n * nrhs : nullptr, n, n, nrhs};
+  }
   LuDescT<R>* d_lu = tmp.upload(lu, s);
   int* d_info = tmp.alloc<int>(batch);
   HIPCHK(hipMemsetAsync(d_info, 0, batch * sizeof(int), s));
   la_getrf<R>(d_lu, batch, n, d_info, s);
-  if (nrhs > 0) la_getrs<R>(d_lu, tmp.upload(bm, s), batch, n, nrhs, s);
+  // few right-hand sides: the fused solve of the solve passes; more: the blocked solve of
+  // the factorisation
+  if (small)
+    la_getrs_small<R>(d_lu, tmp.upload(bm, s), tmp.upload(wm, s), batch, n, nrhs, s);
+  else if (nrhs > 0)
+    la_getrs<R>(d_lu, tmp.upload(bm, s), batch, n, nrhs, s);
   std::vector<int> hi;
   download(hi, d_info, batch, s);
   std::copy(hi.begin(), hi.end(), info);
@@ -1478,6 +1663,7 @@ void pmx_options_default(pmx_options* o) {
   o->timing = 0;
   o->ir_max_iter = 10;
   o->ir_tol = 1e-10;
+  o->solve_graph = 1;
 }
 
 pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, void* hip_stream,
@@ -1503,6 +1689,10 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
       ~Reset() { g_ktimer = nullptr; }
     } reset_timer;
     make_plan(geom, o, F->plan);
+    HIPCHK(hipStreamCreateWithFlags(&F->gs, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&F->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&F->ev_out, hipEventDisableTiming));
+    F->ss.reset(new SolveState());
     upload_geometry(F.get(), geom, s);
     if (o.precision == 1) {
       factor_all<float>(F.get(), s);
@@ -1678,8 +1868,8 @@ pmx_status pmx_probe_apply(const pmx_geometry* geom, int32_t nrhs, const pmx_c64
     zd* dself = tmp.alloc<zd>(o);
     assemble_diag(&F, tmp, incl, dself, off, s);
     DenseApply D;
-    build_dense_apply(&F, nrhs, D);
-    run_dense_apply(&F, D, dself, incl, off, (const zd*)x, nullptr, (zd*)y, tmp, s);
+    build_dense_apply(&F, nrhs, dself, incl, off, (const zd*)x, nullptr, (zd*)y, D, tmp, s);
+    launch_dense_apply(D, s);
     sync_check(s);
   });
 }

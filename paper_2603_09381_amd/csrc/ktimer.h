@@ -17,7 +17,8 @@ enum PmxKernelId {
   PK_ENTRIES = 7,      // k_entries: interaction and proxy matrices
   PK_DIAG = 8,         // k_diag_*: self blocks (Kress quadrature, Maue products)
   PK_APPLY = 9,        // k_apply_off: dense FP64 operator apply for refinement residuals
-  PK_COUNT = 10
+  PK_GETRS = 10,       // k_getrs_small: fused permutation and substitutions, few right-hand sides
+  PK_COUNT = 11
 };
 
 struct KernelTimer {

@@ -18,6 +18,7 @@ struct LuDescT {     // square matrix factored in place, P A = L U
   int64_t ld;
   int n;
   int* ipiv;         // [n], 0-based row swapped with row i at step i
+  int* perm;         // [n] or NULL: row i of P b is row perm[i] of b (filled by getrf)
 };
 
 template <class R>
@@ -80,6 +81,13 @@ void la_getrf(const LuDescT<R>* d_lu, int batch, int max_n, int* d_info, hipStre
 // Solve A X = B in place in B (n x nrhs per entry) using the LU of getrf.
 template <class R>
 void la_getrs(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max_n, int max_nrhs, hipStream_t s);
+// The same for few right-hand sides (max_nrhs <= PMX_GETRS_SMALL_MAX): one fused launch, a
+// workgroup per matrix and group of right-hand sides running the permutation and both
+// substitutions; needs LuDesc::perm and a workspace per entry (w[b].p, n x nrhs, ld >= n).
+#define PMX_GETRS_SMALL_MAX 64
+template <class R>
+void la_getrs_small(const LuDescT<R>* d_lu, const MatT<R>* d_b, const MatT<R>* d_w, int batch, int max_n,
+                    int max_nrhs, hipStream_t s);
 // Householder QR of each M (destroyed); writes R (upper, zero below) to QrDesc::r.
 int64_t la_geqrf_workspace(int m);
 // algorithmic bytes and flops of the trailing updates and the leaf factorisations

@@ -437,6 +437,25 @@ struct FLuUpd {
   }
 };
 
+// the row permutation P of the swaps ipiv: perm[i] = original row of row i of P b
+template <class R>
+__global__ __launch_bounds__(256) void k_lu_perm(const LuDescT<R>* lus) {
+  const LuDescT<R> L = lus[blockIdx.x];
+  if (!L.perm || L.n <= 0) return;
+  extern __shared__ int pl[];
+  for (int i = threadIdx.x; i < L.n; i += 256) pl[i] = i;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int i = 0; i < L.n; ++i) {
+      const int p = L.ipiv[i];
+      const int t = pl[i];
+      pl[i] = pl[p];
+      pl[p] = t;
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < L.n; i += 256) L.perm[i] = pl[i];
+}
+
 template <class R>
 void la_getrf(const LuDescT<R>* d_lu, int batch, int max_n, int* d_info, hipStream_t s) {
   if (batch <= 0 || max_n <= 0) return;
@@ -452,6 +471,10 @@ void la_getrf(const LuDescT<R>* d_lu, int batch, int max_n, int* d_info, hipStre
       launch_zgemm<R, OP_N, OP_N>(FLuUpd<R>{d_lu, j0}, batch, rem, rem, cmk<R>(-1, 0), cmk<R>(1, 0), s);
     }
   }
+  const size_t shm = (size_t)max_n * sizeof(int);
+  if (shm > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)k_lu_perm<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  hipLaunchKernelGGL(k_lu_perm<R>, dim3(batch), dim3(256), shm, s, d_lu);
 }
 
 // ---------------------------------------------------------------------------------
@@ -556,6 +579,131 @@ void la_getrs(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max_n, 
     int j0 = bk * PMX_LU_NB;
     launch_trsm_small<R, true, false>(FRsTrsm<R>{d_lu, d_b, j0}, batch, max_nrhs, s);
     if (j0 > 0) launch_zgemm<R, OP_N, OP_N>(FRsBwd<R>{d_lu, d_b, j0}, batch, j0, max_nrhs, mone, one, s);
+  }
+}
+
+// Fused solve for few right-hand sides.  Workgroup (entry b, group of NRC columns): the
+// permuted right-hand side goes to the workspace, then blocks of 32 rows are finished in
+// turn.  Inside a block each wave solves the 32x32 triangle for its columns with the block
+// of the factor held in registers (one row per lane, broadcasts by lane shuffles, no
+// barrier); then the whole workgroup subtracts the block's contribution from the rows
+// still to come, each thread issuing the 32 loads of a row of the factor at once (coalesced
+// across threads) so that the sweep is bound by bandwidth rather than load latency.  The
+// backward sweep writes each finished block to B.
+#define GS_NT 256
+
+// rows [i0, i1) of x (workspace columns c0..c0+nc-1) -= A[rows, j0:j0+jb] xb
+template <class R, int NRC>
+__device__ inline void getrs_update(const cx<R>* A, int64_t ld, cx<R>* W, int64_t ldw, int c0, int nc, int i0, int i1,
+                                    int j0, int jb, const cx<R> (*xb)[NRC]) {
+  typedef cx<R> C;
+  for (int i = i0 + (int)threadIdx.x; i < i1; i += GS_NT) {
+    C acc[NRC];
+#pragma unroll
+    for (int c = 0; c < NRC; ++c) acc[c] = (c < nc) ? W[i + (int64_t)(c0 + c) * ldw] : cmk<R>(0, 0);
+#pragma unroll
+    for (int h = 0; h < 32; h += 16) {
+      C l[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) l[k] = A[i + (int64_t)(j0 + min(h + k, jb - 1)) * ld];
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+        if (h + k < jb) {
+#pragma unroll
+          for (int c = 0; c < NRC; ++c) acc[c] = zsub(acc[c], zmul(l[k], xb[h + k][c]));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NRC; ++c)
+      if (c < nc) W[i + (int64_t)(c0 + c) * ldw] = acc[c];
+  }
+}
+
+template <class R, int NRC>
+__global__ __launch_bounds__(GS_NT) void k_getrs_small(const LuDescT<R>* lus, const MatT<R>* bs, const MatT<R>* ws) {
+  typedef cx<R> C;
+  const LuDescT<R> L = lus[blockIdx.x];
+  const MatT<R> B = bs[blockIdx.x];
+  const MatT<R> W = ws[blockIdx.x];
+  const int n = L.n;
+  const int c0 = blockIdx.y * NRC;
+  const int nc = min(NRC, B.n - c0);
+  if (n <= 0 || nc <= 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const C* A = L.a;
+  const int64_t ld = L.ld;
+  __shared__ C xb[32][NRC];
+  for (int e = tid; e < n * nc; e += GS_NT) {
+    const int i = e % n, c = e / n;
+    W.p[i + (int64_t)(c0 + c) * W.ld] = B.p[L.perm[i] + (int64_t)(c0 + c) * B.ld];
+  }
+  __syncthreads();
+  // forward: L unit lower
+  for (int j0 = 0; j0 < n; j0 += 32) {
+    const int jb = min(32, n - j0);
+    if (wave < nc) {
+      const int r = j0 + min(lane, jb - 1);
+      C lrow[32];
+#pragma unroll
+      for (int k = 0; k < 32; ++k) lrow[k] = A[r + (int64_t)(j0 + min(k, jb - 1)) * ld];
+      for (int c = wave; c < nc; c += GS_NT / 64) {
+        C x = (lane < jb) ? W.p[j0 + lane + (int64_t)(c0 + c) * W.ld] : cmk<R>(0, 0);
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+          const C xk = cmk<R>(__shfl(x.re, k, 64), __shfl(x.im, k, 64));
+          if (lane > k && k < jb) x = zsub(x, zmul(lrow[k], xk));
+        }
+        if (lane < jb) {
+          xb[lane][c] = x;
+          W.p[j0 + lane + (int64_t)(c0 + c) * W.ld] = x;
+        }
+      }
+    }
+    __syncthreads();
+    getrs_update<R, NRC>(A, ld, W.p, W.ld, c0, nc, j0 + jb, n, j0, jb, xb);
+    __syncthreads();
+  }
+  // backward: U upper with its diagonal
+  for (int j0 = ((n - 1) / 32) * 32; j0 >= 0; j0 -= 32) {
+    const int jb = min(32, n - j0);
+    if (wave < nc) {
+      const int r = j0 + min(lane, jb - 1);
+      C urow[32];
+#pragma unroll
+      for (int k = 0; k < 32; ++k) urow[k] = A[r + (int64_t)(j0 + min(k, jb - 1)) * ld];
+      for (int c = wave; c < nc; c += GS_NT / 64) {
+        C x = (lane < jb) ? W.p[j0 + lane + (int64_t)(c0 + c) * W.ld] : cmk<R>(0, 0);
+#pragma unroll
+        for (int k = 31; k >= 0; --k) {
+          if (k < jb) {
+            if (lane == k) x = zdiv(x, urow[k]);
+            const C xk = cmk<R>(__shfl(x.re, k, 64), __shfl(x.im, k, 64));
+            if (lane < k) x = zsub(x, zmul(urow[k], xk));
+          }
+        }
+        if (lane < jb) {
+          xb[lane][c] = x;
+          B.p[j0 + lane + (int64_t)(c0 + c) * B.ld] = x;
+        }
+      }
+    }
+    __syncthreads();
+    getrs_update<R, NRC>(A, ld, W.p, W.ld, c0, nc, 0, j0, j0, jb, xb);
+    __syncthreads();
+  }
+}
+
+template <class R>
+void la_getrs_small(const LuDescT<R>* d_lu, const MatT<R>* d_b, const MatT<R>* d_w, int batch, int max_n,
+                    int max_nrhs, hipStream_t s) {
+  if (batch <= 0 || max_n <= 0 || max_nrhs <= 0) return;
+  KScope ks(PK_GETRS, s);
+  if (max_nrhs <= 1) {
+    hipLaunchKernelGGL((k_getrs_small<R, 1>), dim3(batch, 1), dim3(GS_NT), 0, s, d_lu, d_b, d_w);
+  } else if (max_nrhs <= 2) {
+    hipLaunchKernelGGL((k_getrs_small<R, 2>), dim3(batch, 1), dim3(GS_NT), 0, s, d_lu, d_b, d_w);
+  } else {
+    hipLaunchKernelGGL((k_getrs_small<R, 4>), dim3(batch, (max_nrhs + 3) / 4), dim3(GS_NT), 0, s, d_lu, d_b, d_w);
   }
 }
 
@@ -1414,6 +1562,7 @@ void la_getrf_work(int n, int real_bytes, double* bytes, double* flops) {
   template void la_zgemm_list<R>(int, int, const GemmArgsT<R>*, int, int, int, cx<R>, cx<R>, hipStream_t);  \
   template void la_getrf<R>(const LuDescT<R>*, int, int, int*, hipStream_t);                                 \
   template void la_getrs<R>(const LuDescT<R>*, const MatT<R>*, int, int, int, hipStream_t);                  \
+  template void la_getrs_small<R>(const LuDescT<R>*, const MatT<R>*, const MatT<R>*, int, int, int, hipStream_t); \
   template void la_geqrf_r<R>(const QrDescT<R>*, int, int, int, hipStream_t);                                \
   template void la_cpqr<R>(const CpqrDescT<R>*, int, int, double, const int*, int, int*, hipStream_t);       \
   template void la_cpqr_tsolve<R>(const CpqrDescT<R>*, const int*, int, int, int, hipStream_t);

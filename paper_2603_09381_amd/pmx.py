@@ -49,7 +49,7 @@ class Options(C.Structure):
     _fields_ = [("id_tol", C.c_double), ("proxy_ratio", C.c_double), ("proxy_min", C.c_int32),
                 ("proxy_rule", C.c_int32), ("near_rule", C.c_int32), ("precision", C.c_int32),
                 ("timing", C.c_int32), ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double),
-                ("reserved", C.c_int32 * 8)]
+                ("solve_graph", C.c_int32), ("reserved", C.c_int32 * 8)]
 
 
 class Info(C.Structure):
@@ -63,7 +63,7 @@ class Info(C.Structure):
                 ("ir_history", C.c_double * 16)]
 
 KERNEL_NAMES = ["k_ts_leaf", "k_ts_update", "k_getrf_panel", "k_cpqr_update", "k_cpqr", "k_zgemm",
-                "k_trsm_small", "k_entries", "k_diag_pairs/maue", "k_apply_off"]
+                "k_trsm_small", "k_entries", "k_diag_pairs/maue", "k_apply_off", "k_getrs_small"]
 
 
 def load(path=None):

@@ -42,7 +42,7 @@ def test_cgemm_fp32(pmx, opa, opb, m, n, k):
     assert np.abs(got - ref).max() < 4e-7 * np.sqrt(max(k, 1)) * scale
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (31, 3), (100, 40), (257, 7)])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (31, 3), (100, 40), (257, 7), (120, 70)])
 def test_lu_solve_fp32(pmx, n, nrhs):
     batch = 3
     A = c64(crandn(batch, n, n) + 2 * np.sqrt(n) * np.eye(n))

@@ -46,7 +46,8 @@ def test_zgemm(pmx, opa, opb, m, n, k):
     assert np.abs(got - ref).max() < 1e-13 * scale * max(1, k)
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (31, 3), (64, 1), (100, 40), (257, 7)])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (31, 3), (64, 1), (100, 40), (257, 7), (33, 5), (100, 80),
+                                    (300, 65), (1100, 4)])
 def test_lu_solve(pmx, n, nrhs):
     batch = 4
     A = crandn(batch, n, n) + 2 * np.sqrt(n) * np.eye(n)
