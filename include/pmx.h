@@ -47,7 +47,10 @@ typedef enum {
  * outside, k_int[j] inside inclusion j; material constants eps_ext and eps_int[j]
  * (NULL: eps_ext (k_int[j]/k_ext)^2, from k = omega sqrt(eps)).  grid_ij[2j], grid_ij[2j+1]
  * are the integer grid cell of inclusion j (one inclusion per cell); the quadtree is
- * built over these cells.  All arrays are host memory. */
+ * built over these cells.  grid_ij NULL (scattered inclusions): the library places the
+ * centres on a uniform grid of spacing 0.99 d_min / sqrt(2) (d_min the smallest centre
+ * distance), one centre per cell, and prunes the empty cells of the quadtree.  All arrays
+ * are host memory. */
 typedef struct {
   int32_t m;
   const int64_t* node_off;   /* [m+1] */
@@ -55,7 +58,7 @@ typedef struct {
   const double *dx, *dy;
   const double *ddx, *ddy;
   const double* center;      /* [2m] inclusion centres (cell centres are their means) */
-  const int32_t* grid_ij;    /* [2m] */
+  const int32_t* grid_ij;    /* [2m] or NULL */
   double k_ext, eps_ext;
   const double* k_int;       /* [m] */
   const double* eps_int;     /* [m] or NULL */
@@ -122,7 +125,7 @@ void pmx_options_default(pmx_options* o);
 /* Builds the plan and the whole compressed factorisation on `hip_stream`.  Returns when
  * the factor is complete (the call synchronises the stream).  *out is owned by the
  * caller and released by pmx_factor_destroy.  Errors: PMX_EINVAL (bad sizes, odd or
- * small n_j, NaN, non-positive wavenumber), PMX_EGEOM (missing or shared grid cells),
+ * small n_j, NaN, non-positive wavenumber), PMX_EGEOM (shared grid cells, coincident centres),
  * PMX_ENOMEM, PMX_EHIP, PMX_ESINGULAR. */
 pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, void* hip_stream,
                              pmx_factor** out);

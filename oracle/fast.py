@@ -66,10 +66,37 @@ class Cell:
     P: int = 0
 
 
+def grid_assignment(centers):
+    """Integer cells for scattered inclusions (reading of Sec. 4's general arrangements as
+    an adaptive quadtree with at most one inclusion per leaf): a uniform grid of spacing
+    h = 0.99 d_min / sqrt(2), d_min the smallest distance between two centres, so that no
+    cell holds two centres (a cell's diagonal is shorter than d_min); the quadtree over
+    the occupied cells then prunes the empty ones."""
+    c = np.asarray(centers, dtype=float)
+    m = len(c)
+    if m == 1:
+        return np.zeros((1, 2), dtype=np.int64)
+    d2 = math.inf
+    for i in range(m):
+        for j in range(i + 1, m):
+            dx = float(c[i, 0]) - float(c[j, 0])
+            dy = float(c[i, 1]) - float(c[j, 1])
+            d2 = min(d2, dx * dx + dy * dy)
+    h = 0.99 * math.sqrt(d2 / 2.0)
+    x0 = float(np.min(c[:, 0]))
+    y0 = float(np.min(c[:, 1]))
+    out = np.zeros((m, 2), dtype=np.int64)
+    for i in range(m):
+        out[i, 0] = math.floor((float(c[i, 0]) - x0) / h)
+        out[i, 1] = math.floor((float(c[i, 1]) - y0) / h)
+    return out
+
+
 def plan(w):
-    """Tree, near lists and proxy circles for every level (grid workloads)."""
+    """Tree, near lists and proxy circles for every level (grid workloads; scattered ones
+    through grid_assignment)."""
     g = dense.Geometry(w)
-    gi = np.asarray(w.grid_index)
+    gi = np.asarray(w.grid_index) if w.grid_index is not None else grid_assignment(w.centers)
     levels = []
     cur = {}
     for j in range(w.m):

@@ -132,12 +132,47 @@ void near_and_proxy(const PlanOptions& o, const double* centers, const int64_t* 
 
 }  // namespace
 
+// Scattered inclusions: a uniform grid of spacing h = 0.99 d_min / sqrt(2) (d_min the
+// smallest centre distance) holds at most one centre per cell, as a cell's diagonal is
+// shorter than d_min; the quadtree over the occupied cells prunes the empty ones, which
+// makes it an adaptive tree with one inclusion per leaf.  Empty result: coincident centres.
+std::vector<int32_t> grid_assignment(int m, const double* centers) {
+  std::vector<int32_t> ij(2 * (size_t)m, 0);
+  if (m == 1) return ij;
+  double d2 = std::numeric_limits<double>::infinity();
+  for (int i = 0; i < m; ++i)
+    for (int j = i + 1; j < m; ++j) {
+      const double dx = centers[2 * i] - centers[2 * j];
+      const double dy = centers[2 * i + 1] - centers[2 * j + 1];
+      d2 = std::min(d2, dx * dx + dy * dy);
+    }
+  if (!(d2 > 0)) return {};
+  const double h = 0.99 * std::sqrt(d2 / 2.0);
+  double x0 = centers[0], y0 = centers[1];
+  for (int i = 1; i < m; ++i) {
+    x0 = std::min(x0, centers[2 * i]);
+    y0 = std::min(y0, centers[2 * i + 1]);
+  }
+  for (int i = 0; i < m; ++i) {
+    const double gx = std::floor((centers[2 * i] - x0) / h), gy = std::floor((centers[2 * i + 1] - y0) / h);
+    if (gx > 1e9 || gy > 1e9) return {};
+    ij[2 * i] = (int32_t)gx;
+    ij[2 * i + 1] = (int32_t)gy;
+  }
+  return ij;
+}
+
 std::string build_plan(int m, const int32_t* grid_ij, const double* centers, const int64_t* node_off,
                        const double* x, const double* y, const PlanOptions& o,
                        std::vector<std::vector<CellPlan>>& levels) {
   levels.clear();
   if (m <= 0) return "no inclusions";
-  if (!grid_ij) return "grid coordinates are required";
+  std::vector<int32_t> own_grid;
+  if (!grid_ij) {
+    own_grid = grid_assignment(m, centers);
+    if (own_grid.empty()) return "two inclusions share a centre";
+    grid_ij = own_grid.data();
+  }
   std::map<std::pair<int, int>, std::vector<int>> cur;
   for (int j = 0; j < m; ++j) {
     if (grid_ij[2 * j] < 0 || grid_ij[2 * j + 1] < 0) return "negative grid coordinate";

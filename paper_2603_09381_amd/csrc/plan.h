@@ -28,10 +28,15 @@ struct PlanOptions {
 };
 
 // Builds levels[0] (one cell per inclusion) up to the single root cell.
-// grid_ij: [2m] integer grid coordinates of the inclusions.
+// grid_ij: [2m] integer grid coordinates of the inclusions, or NULL for scattered
+// inclusions (grid_assignment below).
 // Returns an empty string on success, else an error message.
 std::string build_plan(int m, const int32_t* grid_ij, const double* centers, const int64_t* node_off,
                        const double* x, const double* y, const PlanOptions& o,
                        std::vector<std::vector<CellPlan>>& levels);
 
 uint64_t morton_code(uint32_t i, uint32_t j);
+
+// Cells of scattered inclusions: [2m] grid coordinates with at most one centre per cell
+// (empty when two centres coincide).
+std::vector<int32_t> grid_assignment(int m, const double* centers);

@@ -145,3 +145,12 @@ def test_mixed_reports_nonconvergence(pmx):
         fac.solve_plane_waves(w.angles)
     assert e.value.status == 6
     assert fac.info().ir_iterations == 1 and fac.info().ir_residual > 1e-14
+
+
+def test_mixed_scattered_uneven_against_dense(pmx):
+    w = W.config3(m=14, box=7.0, seed=3)
+    fac, x = _mixed(pmx, w)
+    info = fac.info()
+    err = dense.rel_error(x, dense.solve(w))
+    print(w.name, "mixed: iters", info.ir_iterations, "res", info.ir_residual, "err", err)
+    assert info.ir_residual <= 1e-10 and err < 1e-8

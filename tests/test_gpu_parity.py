@@ -212,3 +212,16 @@ def test_general_rhs_matches_plane_wave(pmx):
     # the two right-hand sides agree to rounding (numpy exp vs the device's sincos), and
     # the system's condition number (~1e4) amplifies that difference in the solutions
     assert dense.rel_error(y, x) < 1e-11
+
+
+def test_scattered_uneven_against_dense(pmx):
+    """Scattered inclusions of different shapes, sizes, node counts (uneven cells) and
+    contrasts, adaptive quadtree with single-child chains: against the dense solve."""
+    w = W.config3(m=14, box=7.0, seed=3)
+    assert len(set(np.diff(w.node_off))) > 3
+    fac, x = _solve(pmx, w)
+    ref = dense.solve(w)
+    err = dense.rel_error(x, ref)
+    print(w.name, "scattered vs dense", err, "levels", fac.info().levels)
+    assert err < 5e-9
+    assert np.max(np.abs(dense.energy_defect(dense.Geometry(w), x))) < 1e-8

@@ -106,8 +106,25 @@ def test_rejects_nan_geometry():
     assert st == 1
 
 
-def test_rejects_missing_grid():
-    w = W.star_grid(2, n=64)
-    w.grid_index = None
-    st, msg = _create(w)
-    assert st == 2
+def test_scattered_plan_matches_oracle():
+    """Scattered inclusions (no grid given): the library's grid assignment and adaptive
+    quadtree equal the oracle's, cell by cell."""
+    w = W.config3(m=14, box=7.0, seed=3)
+    assert w.grid_index is None
+    ref = fast.plan(w)
+    got = pmx.plan_query(w)
+    assert len(got) == len(ref)
+    for lg, lr in zip(got, ref):
+        assert len(lg) == len(lr)
+        for cg, cr in zip(lg, lr):
+            assert cg["first"] == cr.incl[0]
+            assert cg["near"] == list(cr.near)
+            assert cg["P"] == cr.P
+            assert cg["Rp"] == cr.Rp and cg["rc"] == cr.rc
+            assert cg["center"] == cr.center
+
+
+def test_grid_assignment_one_centre_per_cell():
+    w = W.config3(m=40, box=12.0, seed=5)
+    ij = fast.grid_assignment(w.centers)
+    assert len({tuple(r) for r in ij}) == w.m and ij.min() >= 0
