@@ -83,6 +83,12 @@ typedef struct {
                            |f - A x| / |f| <= ir_tol (2-norms) */
   int32_t solve_graph;  /* 1: every solve's launch sequence (per right-hand-side count) is
                            captured once as a HIP graph and replayed; 0: launched directly */
+  int32_t learned;      /* 1: the leaf IDs start from the network of model_path: per ID its
+                           proposed columns go first, QR stops after them, pivots are chosen
+                           among them, and the result stands when every other column is
+                           within id_tol |R_11| of their span (both IDs of both pairs of the
+                           cell); otherwise the cell's IDs take the full CPQR */
+  const char* model_path;  /* network file written by pmx_mlp_train (read at create) */
   int32_t reserved[8];
 } pmx_options;
 
@@ -114,12 +120,15 @@ typedef struct {
   int32_t ir_iterations;
   double ir_residual;
   double ir_history[16];     /* relative residual after each of the first 16 steps */
+  int32_t id_learned;        /* leaf cells whose IDs the learned proposals settled */
+  int32_t id_fallback;       /* leaf cells that fell back to the full CPQR */
 } pmx_info;
 
 typedef struct pmx_factor pmx_factor;
 
 /* Fills defaults: id_tol 1e-10, proxy_ratio 1.5, proxy_min 0, proxy_rule 0, near_rule 0,
- * precision 0, timing 0, ir_max_iter 10, ir_tol 1e-10, solve_graph 1. */
+ * precision 0, timing 0, ir_max_iter 10, ir_tol 1e-10, solve_graph 1, learned 0,
+ * model_path NULL. */
 void pmx_options_default(pmx_options* o);
 
 /* Builds the plan and the whole compressed factorisation on `hip_stream`.  Returns when
@@ -151,6 +160,41 @@ pmx_status pmx_factor_info(const pmx_factor* f, pmx_info* info);
 
 /* Releases everything the factor holds; accepts NULL. */
 void pmx_factor_destroy(pmx_factor* f);
+
+/* Learned skeleton proposals (the leaf IDs of Sec. 3 as training labels).
+ *
+ * Features per leaf node (20): the cell's k+ r_c, k+ R_p, contrast k-/k+, n / 256, near
+ * cells / 8, the relative Fourier magnitudes 2..6 of the node radii and mean radius / r_c;
+ * the node's direction from the centre, normal, radius / r_c, curvature r_c, speed / r_c,
+ * distance to the nearest near-cell node / r_c and to the proxy circle / r_c.
+ * Outputs per node (8): skeleton logits of the four IDs (column q, column u, row value,
+ * row derivative) and the four ranks as fractions k / n. */
+typedef struct {
+  int32_t epochs, batch;   /* passes over the training set; samples (nodes) per step */
+  int32_t hidden, layers;  /* hidden width and number of hidden layers (ReLU) */
+  float lr, wmse;          /* Adam step size; weight of the rank squared error */
+  uint64_t seed;           /* initial weights and sample order */
+} pmx_mlp_opts;
+
+/* epochs 30, batch 4096, hidden 256, layers 3, lr 1e-3, wmse 10, seed 1 */
+void pmx_mlp_opts_default(pmx_mlp_opts* o);
+
+/* Runs the full leaf IDs of a geometry (plain FP64 path) and writes (append = 0) or appends
+ * (append = 1) one training sample per leaf node to the file at path: features and labels
+ * (membership of the node in the skeleton of each of the four IDs, and k / n). */
+pmx_status pmx_id_dataset(const pmx_geometry* geom, const pmx_options* opts, const char* path, int32_t append,
+                          void* hip_stream);
+
+/* Trains the network on a training file with Adam (binary cross entropy on the logits,
+ * wmse times squared error on the rank fractions, inputs standardised by the file's mean
+ * and deviation) on the device and writes it to model_path; *final_loss (may be NULL) is
+ * the mean loss of the last epoch. */
+pmx_status pmx_mlp_train(const char* data_path, const pmx_mlp_opts* opts, const char* model_path, double* final_loss,
+                         void* hip_stream);
+
+/* The network's outputs for every boundary node of a geometry: out (host) [node][8]. */
+pmx_status pmx_mlp_predict(const char* model_path, const pmx_geometry* geom, const pmx_options* opts, float* out,
+                           void* hip_stream);
 
 const char* pmx_status_string(pmx_status s);
 const char* pmx_last_error(void);

@@ -72,6 +72,15 @@ pmx_status pmx_probe_id_c32(int32_t batch, int32_t m, int32_t c, pmx_c32* M, dou
 pmx_status pmx_probe_apply(const pmx_geometry* geom, int32_t nrhs, const pmx_c64* x, pmx_c64* y,
                            void* stream);
 
+/* One forward and backward pass of the network on a batch (all host memory): shape nin,
+ * nhidden x nlayer hidden ReLU layers, nout outputs; params packed per layer as W (out x
+ * in, column major) then b; X [B][nin], labels [B][nout] (first nout/2 binary, the rest
+ * regression targets weighted by wmse).  Outputs: out [B][nout] (the last layer before
+ * the loss), grad (as params) of the batch-mean loss, *loss the batch-mean loss. */
+pmx_status pmx_probe_mlp(int32_t nin, int32_t nhidden, int32_t nlayer, int32_t nout, const float* params,
+                         const float* X, const float* labels, int32_t B, float wmse, float* out, float* grad,
+                         double* loss, void* stream);
+
 /* The quadtree plan, host only (no GPU): per level the number of cells; per cell its
  * centre, radius, proxy radius, proxy count and near list.  Buffers (host) are filled up
  * to their capacity; *n_levels, *n_cells_total and *n_near_total report the sizes

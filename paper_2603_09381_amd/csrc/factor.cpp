@@ -32,6 +32,7 @@
 #include "../../include/pmx_probe.h"
 #include "assemble.h"
 #include "la.h"
+#include "learn.h"
 #include "plan.h"
 #include "ktimer.h"
 
@@ -212,6 +213,8 @@ struct pmx_factor {
   hipStream_t gs = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::unique_ptr<SolveState> ss;
+  // learned leaf IDs: the network's outputs per leaf node (PMX_NOUT x nodes, leaf order)
+  std::vector<float> leaf_pred;
   ~pmx_factor();
   DevGeom geom() const { return DevGeom{x, y, nx, ny, w, speed, kappa, n_nodes}; }
   ExtParams ext() const { return ExtParams{k_ext, eps_ext}; }
@@ -407,14 +410,40 @@ ProxyTable make_proxies(Arena& A, const std::vector<CellPlan>& cells, hipStream_
   return P;
 }
 
-// Compress one level whose active sets (L.rows, L.cols, s0, s1) and blocks D are set.
+// Candidate columns proposed for the leaf IDs: for ID q = 4 t + kind, the column order
+// (the first cand[q] are the candidates, best first) over the cell's active columns of the
+// ID's type.
+struct LearnedPlan {
+  std::vector<int> cand;
+  std::vector<std::vector<int>> order;
+};
+
+// Results of the ID stage of one level, per ID q = 4 t + kind (kinds 0/1: column IDs of
+// type 0/1, 2/3: row IDs).  R and the pivots live at fixed offsets; the leading dimension
+// of an ID's R is mbq[q] (rows of its CPQR matrix); pivots are original column indices.
 template <class R>
-void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>& cells, hipStream_t s) {
+struct IdOut {
+  std::vector<int> idm, idc, mbq, kq, piv;
+  std::vector<int64_t> offR, offC;
+  cx<R>* Rb = nullptr;
+  int* pivb = nullptr;
+  int learned = 0, fallback = 0;
+};
+
+// Interpolative decompositions of the four matrices of every cell (Sec. 3): column IDs of
+// [A(near rows, cell columns); proxy rows] per column type and row IDs of the transposed
+// [A(cell rows, near columns), proxy columns] per row type, exterior kernel only (Omit).
+// Full path: Householder QR, column-pivoted QR to the threshold |R_jj| <= tol |R_11|, the
+// pairs (q, value) and (u, derivative) take the larger rank, T = R11^-1 R12.  Learned path
+// (lp): the matrix is assembled with the proposed candidates first, QR stops after the
+// candidates, pivots are chosen among them only, and the result stands when every
+// remaining column (the part outside the candidates' span included) is at most
+// tol |R_11|, for both IDs of both pairs; other cells take the full path.
+template <class R>
+void id_stage(pmx_factor* F, const LevelData<R>& L, const std::vector<CellPlan>& cells, const ProxyTable& PT,
+              const LearnedPlan* lp, IdOut<R>& io, Arena& tmp, hipStream_t s) {
   const int nc = L.ncell;
   const double tol = F->opts.id_tol;
-  Arena tmp;
-  ProxyTable PT = make_proxies(tmp, cells, s);
-  // ---- ID matrices: 4 per cell, kinds 0/1 column IDs of type 0/1, 2/3 row IDs
   std::vector<int> nearrows, nearcols;
   std::vector<int64_t> nro(nc), mid(nc);
   for (int t = 0; t < nc; ++t) {
@@ -436,115 +465,204 @@ void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>&
   int* d_rows = tmp.upload(L.rows, s);
   int* d_cols = tmp.upload(L.cols, s);
   const int nid = 4 * nc;
-  std::vector<int64_t> offM(nid), offR(nid), offV(nid), offW(nid), offC(nid);
-  std::vector<int> idm(nid), idc(nid);
-  int64_t totM = 0, totR = 0, totV = 0, totW = 0, totC = 0;
-  int maxm = 0, maxc = 0;
+  io.idm.assign(nid, 0);
+  io.idc.assign(nid, 0);
+  io.mbq.assign(nid, 0);
+  io.kq.assign(nid, 0);
+  io.offR.assign(nid, 0);
+  io.offC.assign(nid, 0);
+  std::vector<int64_t> offM(nid), offV(nid);
+  int64_t totM = 0, totR = 0, totV = 0, totC = 0;
   for (int t = 0; t < nc; ++t)
     for (int kd = 0; kd < 4; ++kd) {
       int q = 4 * t + kd;
       int c = (kd & 1) ? L.s1[t] : L.s0[t];
       int m = (int)mid[t];
-      idm[q] = m;
-      idc[q] = c;
+      io.idm[q] = m;
+      io.idc[q] = c;
       offM[q] = totM;
       totM += (int64_t)m * c;
-      offR[q] = totR;
+      io.offR[q] = totR;
       totR += (int64_t)std::min(m, c) * c;
       offV[q] = totV;
       totV += la_geqrf_workspace(m);
-      offW[q] = totW;
-      totW += (int64_t)PMX_QR_NB * c;
-      offC[q] = totC;
+      io.offC[q] = totC;
       totC += c;
-      maxm = std::max(maxm, m);
-      maxc = std::max(maxc, c);
     }
   cx<R>* Mb = tmp.alloc<cx<R>>(totM);
-  cx<R>* Rb = tmp.alloc<cx<R>>(totR);
+  io.Rb = tmp.alloc<cx<R>>(totR);
   cx<R>* Vb = tmp.alloc<cx<R>>(totV);
   cx<R>* VTb = tmp.alloc<cx<R>>(totV);
   cx<R>* CVb = tmp.alloc<cx<R>>(totC);
   double* taub = tmp.alloc<double>(nid);
   int* d_work = tmp.alloc<int>(1);
-  int* pivb = tmp.alloc<int>(totC);
+  io.pivb = tmp.alloc<int>(totC);
   double* nrmb = tmp.alloc<double>(2 * totC);
+  double* extrab = tmp.alloc<double>(totC);
   int* stb = tmp.alloc<int>(4 * nid);
   double* r11b = tmp.alloc<double>(nid);
-  std::vector<EntryMatT<R>> em(nid);
-  std::vector<QrDescT<R>> qd(nid);
-  std::vector<CpqrDescT<R>> cd(nid);
-  for (int t = 0; t < nc; ++t)
-    for (int kd = 0; kd < 4; ++kd) {
-      int q = 4 * t + kd;
-      int ty = kd & 1;
-      const int* own = ((kd < 2) ? d_cols : d_rows) + L.offS[t] + (ty ? L.s0[t] : 0);
-      EntryMatT<R>& e = em[q];
+  io.piv.assign(totC, 0);
+  std::vector<char> done(nc, 0);
+
+  // one pass over the cells `sel`, full or learned; returns per cell whether it stands
+  auto pass = [&](const std::vector<int>& sel, bool learned) {
+    const int nb = 4 * (int)sel.size();
+    std::vector<EntryMatT<R>> em(nb);
+    std::vector<QrDescT<R>> qd(nb);
+    std::vector<CpqrDescT<R>> cd(nb);
+    std::vector<double*> tails(nb);
+    std::vector<int> ordcodes;
+    std::vector<int64_t> ordoff(nb, 0);
+    int maxm = 0, maxc = 0;
+    if (learned) {
+      for (int i = 0; i < nb; ++i) {
+        const int q = 4 * sel[i / 4] + (i % 4), t = q / 4, kd = q % 4, ty = kd & 1;
+        const std::vector<int>& src = (kd < 2) ? L.cols : L.rows;
+        const int64_t base = L.offS[t] + (ty ? L.s0[t] : 0);
+        ordoff[i] = (int64_t)ordcodes.size();
+        for (int j : lp->order[q]) ordcodes.push_back(src[base + j]);
+      }
+    }
+    const int* d_ord = learned ? tmp.upload(ordcodes, s) : nullptr;
+    for (int i = 0; i < nb; ++i) {
+      const int q = 4 * sel[i / 4] + (i % 4), t = q / 4, kd = q % 4, ty = kd & 1;
+      const int m = io.idm[q], c = io.idc[q];
+      const int kc = learned ? std::min(std::min(m, c), lp->cand[q]) : std::min(m, c);
+      EntryMatT<R>& e = em[i];
       e.a = ((kd < 2) ? d_nr : d_ncol) + nro[t];
-      e.na = idm[q];
-      e.b = own;
-      e.nb = idc[q];
+      e.na = m;
+      e.b = learned ? d_ord + ordoff[i] : ((kd < 2) ? d_cols : d_rows) + L.offS[t] + (ty ? L.s0[t] : 0);
+      e.nb = c;
       e.out = Mb + offM[q];
-      e.ld = idm[q];
+      e.ld = m;
       e.a_is_target = (kd < 2) ? 1 : 0;
-      QrDescT<R>& Q = qd[q];
+      QrDescT<R>& Q = qd[i];
       Q.a = Mb + offM[q];
-      Q.ld = idm[q];
-      Q.m = idm[q];
-      Q.c = idc[q];
-      Q.r = Rb + offR[q];
+      Q.ld = m;
+      Q.m = m;
+      Q.c = c;
+      Q.r = io.Rb + io.offR[q];
       Q.v = Vb + offV[q];
       Q.t = VTb + offV[q];
-
-      CpqrDescT<R>& C = cd[q];
-      C.b = Rb + offR[q];
-      C.mb = std::min(idm[q], idc[q]);
-      C.c = idc[q];
-      C.piv = pivb + offC[q];
-      C.nrm = nrmb + 2 * offC[q];
+      Q.kc = kc;
+      CpqrDescT<R>& C = cd[i];
+      C.b = io.Rb + io.offR[q];
+      C.mb = kc;
+      C.c = c;
+      C.piv = io.pivb + io.offC[q];
+      C.nrm = nrmb + 2 * io.offC[q];
       C.state = stb + 4 * q;
       C.r11 = r11b + q;
-      C.v = CVb + offC[q];
+      C.v = CVb + io.offC[q];
       C.tau = taub + q;
+      C.cpiv = learned ? kc : c;
+      C.extra = learned ? extrab + io.offC[q] : nullptr;
+      tails[i] = extrab + io.offC[q];
+      io.mbq[q] = kc;
+      maxm = std::max(maxm, m);
+      maxc = std::max(maxc, c);
+      la_geqrf_work(m, c, kc, (int)sizeof(R), &F->info.kernel_bytes[PK_TS_UPDATE], &F->info.kernel_flops[PK_TS_UPDATE],
+                    &F->info.kernel_bytes[PK_TS_LEAF], &F->info.kernel_flops[PK_TS_LEAF]);
     }
-  EntryMatT<R>* d_em = tmp.upload(em, s);
-  QrDescT<R>* d_qd = tmp.upload(qd, s);
-  CpqrDescT<R>* d_cd = tmp.upload(cd, s);
-  asm_entries(F->geom(), PT.dev, F->ext(), d_em, nid, maxm, maxc, s);
-  la_geqrf_r(d_qd, nid, maxm, maxc, s);
-  for (int q = 0; q < nid; ++q)
-    la_geqrf_work(idm[q], idc[q], (int)sizeof(R), &F->info.kernel_bytes[PK_TS_UPDATE], &F->info.kernel_flops[PK_TS_UPDATE],
-                  &F->info.kernel_bytes[PK_TS_LEAF], &F->info.kernel_flops[PK_TS_LEAF]);
-  la_cpqr(d_cd, nid, maxc, tol, nullptr, 1, d_work, s);
-  std::vector<int> st;
-  download(st, stb, 4 * nid, s);
-  // ---- common ranks per pair, continuation
-  std::vector<int> kq(nid);
+    EntryMatT<R>* d_em = tmp.upload(em, s);
+    QrDescT<R>* d_qd = tmp.upload(qd, s);
+    CpqrDescT<R>* d_cd = tmp.upload(cd, s);
+    asm_entries(F->geom(), PT.dev, F->ext(), d_em, nb, maxm, maxc, s);
+    la_geqrf_r(d_qd, nb, maxm, maxc, s);
+    if (learned) la_qr_tail_norms(d_qd, tmp.upload(tails, s), nb, maxc, s);
+    la_cpqr(d_cd, nb, maxc, tol, nullptr, 1, d_work, s);
+    std::vector<int> st;
+    download(st, stb, 4 * nid, s);
+    // common ranks per pair, continuation
+    std::vector<int> kb(nb);
+    for (int i = 0; i < nb; i += 4)
+      for (int ty = 0; ty < 2; ++ty) {
+        const int qc = 4 * sel[i / 4] + ty, qr = qc + 2;
+        int k = std::max(st[4 * qc + 1], st[4 * qr + 1]);
+        const int cap = std::min(io.idc[qc], std::min(io.idm[qc], io.idc[qc]));
+        k = std::max(1, std::min(k, cap));
+        kb[i + ty] = kb[i + 2 + ty] = k;
+      }
+    int* d_kb = tmp.upload(kb, s);
+    la_cpqr(d_cd, nb, maxc, 0.0, d_kb, 0, d_work, s);
+    download(st, stb, 4 * nid, s);
+    std::vector<char> ok(sel.size(), 1);
+    if (learned) {
+      int* d_acc = tmp.alloc<int>(nb);
+      la_cpqr_judge(d_cd, d_kb, tol, d_acc, nb, s);
+      std::vector<int> acc;
+      download(acc, d_acc, nb, s);
+      for (int i = 0; i < nb; ++i)
+        if (!acc[i]) ok[i / 4] = 0;
+    }
+    for (int i = 0; i < nb; i += 4)
+      for (int ty = 0; ty < 2; ++ty) {
+        const int qc = 4 * sel[i / 4] + ty, qr = qc + 2;
+        int k = std::min(kb[i + ty], std::min(st[4 * qc], st[4 * qr]));
+        if (learned && k < kb[i + ty]) ok[i / 4] = 0;
+        if (k < 1) fail(PMX_ESINGULAR, "an interpolative decomposition has rank 0");
+        kb[i + ty] = kb[i + 2 + ty] = k;
+        io.kq[qc] = io.kq[qr] = k;
+      }
+    HIPCHK(hipMemcpyAsync(d_kb, kb.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
+    la_cpqr_tsolve(d_cd, d_kb, nb, maxc, maxc, s);
+    // pivots as original column indices
+    std::vector<int> pv;
+    download(pv, io.pivb, totC, s);
+    for (int i = 0; i < nb; ++i) {
+      const int q = 4 * sel[i / 4] + (i % 4);
+      const int c = io.idc[q];
+      for (int j = 0; j < c; ++j) {
+        const int p = pv[io.offC[q] + j];
+        io.piv[io.offC[q] + j] = learned ? lp->order[q][p] : p;
+      }
+    }
+    return ok;
+  };
+
+  if (lp) {
+    std::vector<int> all(nc);
+    for (int t = 0; t < nc; ++t) all[t] = t;
+    std::vector<char> ok = pass(all, true);
+    for (int t = 0; t < nc; ++t) done[t] = ok[t];
+  }
+  std::vector<int> rest;
+  for (int t = 0; t < nc; ++t)
+    if (!done[t]) rest.push_back(t);
+  io.learned = nc - (int)rest.size();
+  io.fallback = lp ? (int)rest.size() : 0;
+  if (!rest.empty()) pass(rest, false);
+  if (lp) HIPCHK(hipMemcpyAsync(io.pivb, io.piv.data(), totC * sizeof(int), hipMemcpyHostToDevice, s));
+}
+
+// Compress one level whose active sets (L.rows, L.cols, s0, s1) and blocks D are set.
+template <class R>
+void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>& cells, const LearnedPlan* lp,
+                    hipStream_t s) {
+  const int nc = L.ncell;
+  const double tol = F->opts.id_tol;
+  Arena tmp;
+  ProxyTable PT = make_proxies(tmp, cells, s);
+  // ---- the four interpolative decompositions of every cell (learned proposals first at
+  // the leaves when a model is loaded, the full CPQR for every cell they do not settle)
+  IdOut<R> io;
+  id_stage<R>(F, L, cells, PT, lp, io, tmp, s);
+  F->info.id_learned += io.learned;
+  F->info.id_fallback += io.fallback;
+  const std::vector<int>& kq = io.kq;
+  const std::vector<int>& idc = io.idc;
+  const std::vector<int>& mbq = io.mbq;
+  const std::vector<int64_t>& offR = io.offR;
+  const std::vector<int64_t>& offC = io.offC;
+  const std::vector<int>& piv = io.piv;
+  cx<R>* Rb = io.Rb;
+  const int* pivb = io.pivb;
   L.k0.assign(nc, 0);
   L.k1.assign(nc, 0);
-  for (int t = 0; t < nc; ++t)
-    for (int ty = 0; ty < 2; ++ty) {
-      int qc = 4 * t + ty, qr = 4 * t + 2 + ty;
-      int kb = std::max(st[4 * qc + 1], st[4 * qr + 1]);
-      int cap = std::min(idc[qc], std::min(idm[qc], idc[qc]));
-      kb = std::max(1, std::min(kb, cap));
-      kq[qc] = kq[qr] = kb;
-    }
-  int* d_kq = tmp.upload(kq, s);
-  la_cpqr(d_cd, nid, maxc, 0.0, d_kq, 0, d_work, s);
-  download(st, stb, 4 * nid, s);
-  for (int t = 0; t < nc; ++t)
-    for (int ty = 0; ty < 2; ++ty) {
-      int qc = 4 * t + ty, qr = 4 * t + 2 + ty;
-      int kb = std::min(kq[qc], std::min(st[4 * qc], st[4 * qr]));
-      if (kb < 1) fail(PMX_ESINGULAR, "an interpolative decomposition has rank 0");
-      kq[qc] = kq[qr] = kb;
-      (ty ? L.k1 : L.k0)[t] = kb;
-    }
-  HIPCHK(hipMemcpyAsync(d_kq, kq.data(), nid * sizeof(int), hipMemcpyHostToDevice, s));
-  la_cpqr_tsolve(d_cd, d_kq, nid, maxc, maxc, s);
-  std::vector<int> piv;
-  download(piv, pivb, totC, s);
+  for (int t = 0; t < nc; ++t) {
+    L.k0[t] = kq[4 * t];
+    L.k1[t] = kq[4 * t + 1];
+  }
   // ---- level bookkeeping
   L.offK.resize(nc + 1);
   L.offY.resize(nc);
@@ -600,7 +718,7 @@ void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>&
       for (int ty = 0; ty < 2; ++ty) {
         int q = 4 * t + ty;
         int kb = kq[q];
-        int mb = std::min(idm[q], idc[q]);
+        int mb = mbq[q];
         int ncol = idc[q] - kb;
         rso.push_back((int64_t)rs.size());
         for (int i = 0; i < kb; ++i) rs.push_back(RowSrc{offR[q] + i + (int64_t)kb * mb, mb});
@@ -632,7 +750,7 @@ void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>&
       int q0 = 4 * t + 2, q1 = 4 * t + 3;
       d.piv0 = pivb + offC[q0];
       d.piv1 = pivb + offC[q1];
-      int mb0 = std::min(idm[q0], idc[q0]), mb1 = std::min(idm[q1], idc[q1]);
+      int mb0 = mbq[q0], mb1 = mbq[q1];
       d.t0 = Rb + offR[q0] + (int64_t)L.k0[t] * mb0;
       d.t1 = Rb + offR[q1] + (int64_t)L.k1[t] * mb1;
       d.ldt0 = mb0;
@@ -828,14 +946,11 @@ void merge_level(pmx_factor* F, const LevelData<R>& C, const std::vector<CellPla
   asm_parent(F->geom(), F->ext(), d_pd, np, P.max_s, s);
 }
 
+// Leaf level: one inclusion per cell, active rows and columns all its nodes (value /
+// q first, then derivative / u); returns the size of the self blocks.
 template <class R>
-void factor_all(pmx_factor* F, hipStream_t s) {
-  Tier<R>& T = tier<R>(F);
-  const double t0 = now_ms();
-  const auto& plan = F->plan;
-  // leaf level
-  LevelData<R> L0;
-  const std::vector<CellPlan>& leaves = plan[0];
+int64_t leaf_level(pmx_factor* F, LevelData<R>& L0, std::vector<int>& incl) {
+  const std::vector<CellPlan>& leaves = F->plan[0];
   const int nc0 = (int)leaves.size();
   L0.ncell = nc0;
   L0.s0.resize(nc0);
@@ -843,7 +958,7 @@ void factor_all(pmx_factor* F, hipStream_t s) {
   L0.offS.resize(nc0 + 1);
   L0.offD.resize(nc0);
   int64_t td = 0;
-  std::vector<int> incl(nc0);
+  incl.assign(nc0, 0);
   L0.max_s = 0;
   for (int t = 0; t < nc0; ++t) {
     int j = leaves[t].incl[0];
@@ -863,6 +978,83 @@ void factor_all(pmx_factor* F, hipStream_t s) {
   }
   L0.offS[nc0] = (int64_t)L0.rows.size();
   L0.tot_s = L0.offS[nc0];
+  return td;
+}
+
+// Candidate columns of the leaf IDs from the network's outputs.  Count: the pair (q,
+// value) and the pair (u, derivative) each take c = min(n, ceil(1.1 k) + 8) candidates, k
+// the larger of the two predicted ranks.  Choice: systematic sampling along the boundary
+// with density proportional to 1/4 + the predicted skeleton probability, so that the
+// candidates are spread over the whole boundary (a clustered subset interpolates the
+// others poorly) and denser where the network expects skeleton nodes; nodes whose density
+// would take more than one sample top the count up in the order of their scores.
+LearnedPlan learned_plan(const pmx_factor* F, const std::vector<int>& s0) {
+  const int nc = (int)s0.size();
+  LearnedPlan lp;
+  lp.cand.assign(4 * nc, 0);
+  lp.order.resize(4 * nc);
+  int64_t first = 0;
+  for (int t = 0; t < nc; ++t) {
+    const int n = s0[t];
+    const float* o = F->leaf_pred.data() + (size_t)PMX_NOUT * first;
+    for (int ty = 0; ty < 2; ++ty) {
+      double fc = 0, fr = 0;
+      for (int i = 0; i < n; ++i) {
+        fc += o[(size_t)PMX_NOUT * i + 4 + ty];
+        fr += o[(size_t)PMX_NOUT * i + 6 + ty];
+      }
+      const double khat = std::max(fc, fr);  // sums of the predicted k / n over the nodes
+      const int c = std::max(1, std::min(n, (int)std::ceil(1.1 * khat) + 8));
+      lp.cand[4 * t + ty] = lp.cand[4 * t + 2 + ty] = c;
+    }
+    for (int kd = 0; kd < 4; ++kd) {
+      const int c = lp.cand[4 * t + kd];
+      std::vector<double> dens(n);
+      double tot = 0;
+      for (int i = 0; i < n; ++i) {
+        const double z = o[(size_t)PMX_NOUT * i + kd];
+        dens[i] = 0.25 + 1.0 / (1.0 + std::exp(-z));
+        tot += dens[i];
+      }
+      std::vector<char> used(n, 0);
+      std::vector<int> ord;
+      double cum = 0;
+      for (int i = 0; i < n && (int)ord.size() < c; ++i) {
+        const double prev = cum;
+        cum += dens[i] * c / tot;
+        if (std::floor(cum + 0.5) > std::floor(prev + 0.5)) {
+          ord.push_back(i);
+          used[i] = 1;
+        }
+      }
+      std::vector<int> idx(n);
+      for (int i = 0; i < n; ++i) idx[i] = i;
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        return o[(size_t)PMX_NOUT * a + kd] > o[(size_t)PMX_NOUT * b + kd];
+      });
+      for (int i : idx)
+        if ((int)ord.size() < c && !used[i]) {
+          ord.push_back(i);
+          used[i] = 1;
+        }
+      for (int i = 0; i < n; ++i)
+        if (!used[i]) ord.push_back(i);
+      lp.order[4 * t + kd] = ord;
+    }
+    first += n;
+  }
+  return lp;
+}
+
+template <class R>
+void factor_all(pmx_factor* F, hipStream_t s) {
+  Tier<R>& T = tier<R>(F);
+  const double t0 = now_ms();
+  const auto& plan = F->plan;
+  // leaf level
+  LevelData<R> L0;
+  std::vector<int> incl;
+  const int64_t td = leaf_level(F, L0, incl);
   L0.D = F->arena.alloc<cx<R>>(td);
   L0.ipiv = F->arena.alloc<int>(L0.tot_s);
   L0.perm = F->arena.alloc<int>(L0.tot_s);
@@ -913,7 +1105,10 @@ void factor_all(pmx_factor* F, hipStream_t s) {
       break;
     }
     const double tc = now_ms();
-    compress_level(F, cur, plan[lv], s);
+    LearnedPlan lp;
+    const bool learned = (lv == 0 && !F->leaf_pred.empty());
+    if (learned) lp = learned_plan(F, cur.s0);
+    compress_level(F, cur, plan[lv], learned ? &lp : nullptr, s);
     F->info.t_phase_ms[1] += now_ms() - tc;
     T.lev.push_back(std::move(cur));
     cur = LevelData<R>();
@@ -1592,9 +1787,9 @@ void probe_id(int batch, int m, int c, cx<R>* M, double tol, const int* kmin, in
   std::vector<CpqrDescT<R>> cd(batch);
   for (int b = 0; b < batch; ++b) {
     qd[b] = QrDescT<R>{M + (int64_t)b * m * c, m, m, c, Rb + (int64_t)b * mb * c, Vb + (int64_t)b * wsz,
-                       VTb + (int64_t)b * wsz};
+                       VTb + (int64_t)b * wsz, mb};
     cd[b] = CpqrDescT<R>{Rb + (int64_t)b * mb * c, mb, c, piv + (int64_t)b * c, nrm + (int64_t)b * 2 * c, st + 4 * b,
-                         r11 + b, CVb + (int64_t)b * c, taub + b};
+                         r11 + b, CVb + (int64_t)b * c, taub + b, c, nullptr};
   }
   QrDescT<R>* d_qd = tmp.upload(qd, s);
   CpqrDescT<R>* d_cd = tmp.upload(cd, s);
@@ -1627,6 +1822,41 @@ void probe_id(int batch, int m, int c, cx<R>* M, double tol, const int* kmin, in
   }
   asm_gather(Rb, tmp.upload(gd, s), batch, c, c, s);
   sync_check(s);
+}
+
+HostGeom host_geom(const pmx_geometry* g) {
+  HostGeom h;
+  h.m = g->m;
+  h.node_off = g->node_off;
+  h.x = g->x;
+  h.y = g->y;
+  h.dx = g->dx;
+  h.dy = g->dy;
+  h.ddx = g->ddx;
+  h.ddy = g->ddy;
+  h.k_ext = g->k_ext;
+  h.k_int = g->k_int;
+  return h;
+}
+
+MlpModel load_model(const char* path) {
+  if (!path) fail(PMX_EINVAL, "learned IDs need a model path");
+  MlpModel m;
+  std::string err = mlp_load(path, m);
+  if (!err.empty()) fail(PMX_EINVAL, err);
+  if (m.sh.nin != PMX_NFEAT || m.sh.nout != PMX_NOUT) fail(PMX_EINVAL, "model shape does not match the features");
+  return m;
+}
+
+void leaf_predictions(pmx_factor* F, const pmx_geometry* g, const char* path, hipStream_t s) {
+  const MlpModel m = load_model(path);
+  std::vector<float> X;
+  leaf_features(host_geom(g), F->plan[0], X);
+  try {
+    mlp_predict(m, X, (int64_t)X.size() / PMX_NFEAT, F->leaf_pred, s);
+  } catch (const std::exception& e) {
+    fail(PMX_EHIP, e.what());
+  }
 }
 
 template <class Fn>
@@ -1664,6 +1894,8 @@ void pmx_options_default(pmx_options* o) {
   o->ir_max_iter = 10;
   o->ir_tol = 1e-10;
   o->solve_graph = 1;
+  o->learned = 0;
+  o->model_path = nullptr;
 }
 
 pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, void* hip_stream,
@@ -1693,6 +1925,7 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
     HIPCHK(hipEventCreateWithFlags(&F->ev_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&F->ev_out, hipEventDisableTiming));
     F->ss.reset(new SolveState());
+    if (o.learned) leaf_predictions(F.get(), geom, o.model_path, s);
     upload_geometry(F.get(), geom, s);
     if (o.precision == 1) {
       factor_all<float>(F.get(), s);
@@ -1870,6 +2103,173 @@ pmx_status pmx_probe_apply(const pmx_geometry* geom, int32_t nrhs, const pmx_c64
     DenseApply D;
     build_dense_apply(&F, nrhs, dself, incl, off, (const zd*)x, nullptr, (zd*)y, D, tmp, s);
     launch_dense_apply(D, s);
+    sync_check(s);
+  });
+}
+
+void pmx_mlp_opts_default(pmx_mlp_opts* o) {
+  if (!o) return;
+  TrainOpts d;
+  o->epochs = d.epochs;
+  o->batch = d.batch;
+  o->hidden = d.hidden;
+  o->layers = d.layers;
+  o->lr = d.lr;
+  o->wmse = d.wmse;
+  o->seed = d.seed;
+}
+
+pmx_status pmx_id_dataset(const pmx_geometry* geom, const pmx_options* opts, const char* path, int32_t append,
+                          void* stream) {
+  return guarded([&] {
+    pmx_options o;
+    pmx_options_default(&o);
+    if (opts) o = *opts;
+    o.precision = 0;
+    o.learned = 0;
+    validate(geom, &o);
+    if (!path) fail(PMX_EINVAL, "path is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    pmx_factor F;
+    F.opts = o;
+    make_plan(geom, o, F.plan);
+    if (F.plan.size() < 2) fail(PMX_EGEOM, "a single cell has no leaf IDs");
+    upload_geometry(&F, geom, s);
+    LevelData<double> L0;
+    std::vector<int> incl;
+    leaf_level(&F, L0, incl);
+    Arena tmp;
+    ProxyTable PT = make_proxies(tmp, F.plan[0], s);
+    IdOut<double> io;
+    id_stage<double>(&F, L0, F.plan[0], PT, nullptr, io, tmp, s);
+    // labels: skeleton membership of every node for the four IDs, and their ranks k / n
+    const int nc = L0.ncell;
+    std::vector<float> X, Y((size_t)PMX_NOUT * L0.tot_s / 2, 0.0f);
+    leaf_features(host_geom(geom), F.plan[0], X);
+    int64_t first = 0;
+    for (int t = 0; t < nc; ++t) {
+      const int n = L0.s0[t];
+      for (int kd = 0; kd < 4; ++kd) {
+        const int q = 4 * t + kd;
+        const int k = io.kq[q];
+        for (int i = 0; i < k; ++i) Y[(size_t)PMX_NOUT * (first + io.piv[io.offC[q] + i]) + kd] = 1.0f;
+        for (int i = 0; i < n; ++i) Y[(size_t)PMX_NOUT * (first + i) + 4 + kd] = (float)k / n;
+      }
+      first += n;
+    }
+    std::string err = dataset_append(path, append != 0, X, Y, first, PMX_NFEAT, PMX_NOUT);
+    if (!err.empty()) fail(PMX_EINVAL, err);
+  });
+}
+
+pmx_status pmx_mlp_train(const char* data_path, const pmx_mlp_opts* opts, const char* model_path, double* final_loss,
+                         void* stream) {
+  return guarded([&] {
+    if (!data_path || !model_path) fail(PMX_EINVAL, "NULL path");
+    pmx_mlp_opts mo;
+    pmx_mlp_opts_default(&mo);
+    if (opts) mo = *opts;
+    if (mo.epochs < 1 || mo.batch < 16 || mo.hidden < 8 || mo.hidden > 2048 || mo.layers < 1 || mo.layers > 16 ||
+        !(mo.lr > 0) || !(mo.wmse >= 0))
+      fail(PMX_EINVAL, "bad training options");
+    std::vector<float> X, Y;
+    int64_t n = 0;
+    int nin = 0, nout = 0;
+    std::string err = dataset_read(data_path, X, Y, n, nin, nout);
+    if (!err.empty()) fail(PMX_EINVAL, err);
+    if (nin != PMX_NFEAT || nout != PMX_NOUT) fail(PMX_EINVAL, "training file does not match the features");
+    TrainOpts to;
+    to.epochs = mo.epochs;
+    to.batch = mo.batch;
+    to.hidden = mo.hidden;
+    to.layers = mo.layers;
+    to.lr = mo.lr;
+    to.wmse = mo.wmse;
+    to.seed = mo.seed;
+    MlpModel m;
+    std::vector<double> hist;
+    try {
+      hist = mlp_train(X, Y, n, nin, nout, to, m, (hipStream_t)stream);
+    } catch (const std::exception& e) {
+      fail(PMX_EHIP, e.what());
+    }
+    err = mlp_save(model_path, m);
+    if (!err.empty()) fail(PMX_EINVAL, err);
+    if (final_loss) *final_loss = hist.empty() ? 0.0 : hist.back();
+  });
+}
+
+pmx_status pmx_mlp_predict(const char* model_path, const pmx_geometry* geom, const pmx_options* opts, float* out,
+                           void* stream) {
+  return guarded([&] {
+    pmx_options o;
+    pmx_options_default(&o);
+    if (opts) o = *opts;
+    validate(geom, &o);
+    if (!out) fail(PMX_EINVAL, "out is NULL");
+    pmx_factor F;
+    F.opts = o;
+    make_plan(geom, o, F.plan);
+    leaf_predictions(&F, geom, model_path, (hipStream_t)stream);
+    int64_t first = 0;
+    for (const CellPlan& c : F.plan[0]) {
+      const int j = c.incl[0];
+      const int64_t n = geom->node_off[j + 1] - geom->node_off[j];
+      std::memcpy(out + (size_t)PMX_NOUT * geom->node_off[j], F.leaf_pred.data() + (size_t)PMX_NOUT * first,
+                  (size_t)PMX_NOUT * n * sizeof(float));
+      first += n;
+    }
+  });
+}
+
+pmx_status pmx_probe_mlp(int32_t nin, int32_t nhidden, int32_t nlayer, int32_t nout, const float* params,
+                         const float* X, const float* labels, int32_t B, float wmse, float* out, float* grad,
+                         double* loss, void* stream) {
+  return guarded([&] {
+    if (nin <= 0 || nhidden <= 0 || nlayer < 0 || nout < 2 || (nout & 1) || B <= 0 || !params || !X || !labels ||
+        !out || !grad || !loss)
+      fail(PMX_EINVAL, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    MlpShape sh;
+    sh.nin = nin;
+    sh.nhidden = nhidden;
+    sh.nlayer = nlayer;
+    sh.nout = nout;
+    const std::vector<int64_t> off = mlp_param_offsets(sh);
+    Arena tmp;
+    float* P = tmp.alloc<float>(off.back());
+    float* G = tmp.alloc<float>(off.back());
+    float* Xd = tmp.alloc<float>((int64_t)nin * B);
+    float* Yd = tmp.alloc<float>((int64_t)nout * B);
+    float* lp = tmp.alloc<float>(B);
+    HIPCHK(hipMemcpyAsync(P, params, off.back() * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(Xd, X, (size_t)nin * B * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(Yd, labels, (size_t)nout * B * 4, hipMemcpyHostToDevice, s));
+    MlpBatch wk;
+    const int nl = sh.nlin();
+    wk.cap = B;
+    wk.Z.assign(nl + 1, nullptr);
+    wk.H.assign(nl + 1, nullptr);
+    wk.dZ.assign(nl + 1, nullptr);
+    wk.dH.assign(nl + 1, nullptr);
+    for (int l = 1; l <= nl; ++l) {
+      wk.Z[l] = tmp.alloc<float>((int64_t)sh.dims(l) * B);
+      wk.dZ[l] = tmp.alloc<float>((int64_t)sh.dims(l) * B);
+      if (l < nl) {
+        wk.H[l] = tmp.alloc<float>((int64_t)sh.dims(l) * B);
+        wk.dH[l] = tmp.alloc<float>((int64_t)sh.dims(l) * B);
+      }
+    }
+    mlp_forward(sh, P, off, Xd, B, wk, s);
+    mlp_loss_grad(wk.Z[nl], Yd, nout, nout / 2, wmse, B, wk.dZ[nl], lp, s);
+    mlp_backward(sh, P, off, B, wk, G, s);
+    std::vector<float> lh;
+    download(lh, lp, B, s);
+    double L = 0;
+    for (float v : lh) L += v;
+    *loss = L / B;
+    HIPCHK(hipMemcpyAsync(out, wk.Z[nl], (size_t)nout * B * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(grad, G, off.back() * 4, hipMemcpyDeviceToHost, s));
     sync_check(s);
   });
 }

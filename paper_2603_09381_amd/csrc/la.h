@@ -37,9 +37,12 @@ struct QrDescT {     // tall matrix M (m x c), factored by Householder, R writte
   cx<R>* a;
   int64_t ld;
   int m, c;
-  cx<R>* r;          // [min(m,c) x c], leading dimension min(m,c)
+  cx<R>* r;          // [kc x c], leading dimension kc
   cx<R>* v;          // workspace: la_geqrf_workspace(m) reflector entries
   cx<R>* t;          // workspace: as v, the reflectors times T^H (compact WY)
+  int kc;            // columns triangularised (min(m, c) for a full QR; fewer: the reflectors
+                     // of the first kc columns are applied to all others, rows kc.. of
+                     // the remaining columns keep their component orthogonal to the first kc)
 };
 
 // Column pivoted QR of b (mb x c, ld mb) in place.  Column norms, |R_11| and the pivot
@@ -54,6 +57,9 @@ struct CpqrDescT {
   double* r11;       // |R_11|
   cx<R>* v;          // [mb] current reflector (multi-workgroup variant)
   double* tau;       // current reflector coefficient (multi-workgroup variant)
+  int cpiv;          // pivots are chosen among the first cpiv columns only (c: all)
+  const double* extra;  // [c] or NULL: squared norm each column has outside b (added to its
+                        // norms; with cpiv < c, |R_11| is the largest initial column norm)
 };
 
 typedef MatT<double> Mat;
@@ -91,7 +97,7 @@ void la_getrs_small(const LuDescT<R>* d_lu, const MatT<R>* d_b, const MatT<R>* d
 // Householder QR of each M (destroyed); writes R (upper, zero below) to QrDesc::r.
 int64_t la_geqrf_workspace(int m);
 // algorithmic bytes and flops of the trailing updates and the leaf factorisations
-void la_geqrf_work(int m, int c, int real_bytes, double* upd_bytes, double* upd_flops, double* leaf_bytes,
+void la_geqrf_work(int m, int c, int kc, int real_bytes, double* upd_bytes, double* upd_flops, double* leaf_bytes,
                    double* leaf_flops);
 template <class R>
 void la_geqrf_r(const QrDescT<R>* d_qr, int batch, int max_m, int max_c, hipStream_t s);
@@ -107,3 +113,12 @@ void la_cpqr(const CpqrDescT<R>* d_cp, int batch, int max_c, double tol, const i
 // T = R11^-1 R12 in place: R11 = b[0:k,0:k] upper, R12 = b[0:k,k:c]; k from d_k.
 template <class R>
 void la_cpqr_tsolve(const CpqrDescT<R>* d_cp, const int* d_k, int batch, int max_k, int max_c, hipStream_t s);
+// Squared norms of rows kc..m-1 of every column of each (truncated) QR: out[b] [c]
+// (0 for the first kc columns).
+template <class R>
+void la_qr_tail_norms(const QrDescT<R>* d_qr, double* const* d_out, int batch, int max_c, hipStream_t s);
+// Interpolation check after a CPQR stopped at k[b] columns: accept[b] = 1 when every
+// remaining column (its downdated norm, outside b included) is at most tol |R_11|, and k[b]
+// steps were taken.
+template <class R>
+void la_cpqr_judge(const CpqrDescT<R>* d_cp, const int* d_k, double tol, int* d_accept, int batch, hipStream_t s);

@@ -775,7 +775,7 @@ template <class R>
 __global__ __launch_bounds__(PMX_TS_BR) void k_ts_leaf(const QrDescT<R>* qrs, int j0, int L) {
   typedef cx<R> C;
   const QrDescT<R> Q = qrs[blockIdx.y];
-  const int kmax = min(Q.m, Q.c);
+  const int kmax = Q.kc;
   const int jb = min(PMX_QR_NB, kmax - j0);
   if (jb <= 0) return;
   TsGeom g;
@@ -930,7 +930,7 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDescT<R>* qrs, int j0
   typedef cx<R> C;
   typedef typename AccT<R>::type V4;
   const QrDescT<R> Q = qrs[blockIdx.z];
-  const int kmax = min(Q.m, Q.c);
+  const int kmax = Q.kc;
   const int jb = min(PMX_QR_NB, kmax - j0);
   const int nc = Q.c - j0 - jb;
   if (jb <= 0 || nc <= 0) return;
@@ -1055,7 +1055,7 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDescT<R>* qrs, int j0
 template <class R>
 __global__ void k_copy_r(const QrDescT<R>* qrs) {
   const QrDescT<R> Q = qrs[blockIdx.y];
-  const int mb = min(Q.m, Q.c);
+  const int mb = Q.kc;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)mb * Q.c) return;
   const int r = (int)(e % mb), c = (int)(e / mb);
@@ -1139,7 +1139,7 @@ __device__ constexpr double cp_recompute_ratio<float>() {
 // one wave per column, lane 0 ends with row j
 template <class R>
 __device__ inline void cp_apply_column(cx<R>* col, const cx<R>* vs, int j, int mb, double tau, double* nrm,
-                                       int c, int l, int lane) {
+                                       int c, int l, int lane, const double* extra) {
   typedef cx<R> C;
   R wr = 0, wi = 0;
   for (int r = j + lane; r < mb; r += 64) {
@@ -1163,6 +1163,7 @@ __device__ inline void cp_apply_column(cx<R>* col, const cx<R>* vs, int j, int m
   const double nw2 = nrm[l] - (fr * fr + fi * fi);
   if (nw2 <= cp_recompute_ratio<R>() * nrm[c + l]) {
     tail = wave_sum(tail);
+    if (extra) tail += extra[l];
     if (lane == 0) {
       nrm[l] = tail;
       nrm[c + l] = tail;
@@ -1188,7 +1189,8 @@ __global__ __launch_bounds__(CP_NT) void k_cpqr(const CpqrDescT<R>* cps, double 
   C* B = Cd.b;
   const int mb = Cd.mb, c = Cd.c;
   const int64_t ld = mb;
-  const int kmax = min(mb, c);
+  const int cpiv = Cd.cpiv;
+  const int kmax = min(min(mb, c), cpiv);
   double* nrm = Cd.nrm;
   if (init) {
     for (int l = wave; l < c; l += nw) {
@@ -1199,16 +1201,26 @@ __global__ __launch_bounds__(CP_NT) void k_cpqr(const CpqrDescT<R>* cps, double 
       }
       p = wave_sum(p);
       if (lane == 0) {
+        if (Cd.extra) p += Cd.extra[l];
         nrm[l] = p;
         nrm[c + l] = p;
         Cd.piv[l] = l;
       }
     }
+    __syncthreads();
+    __threadfence_block();
+    // restricted pivoting: the threshold refers to the largest column of the whole matrix
+    double big = 0;
+    if (cpiv < c) {
+      int bi = -1;
+      for (int l = tid; l < c; l += CP_NT) argmax_pair(big, bi, nrm[l], l);
+      block_argmax<CP_NT>(big, bi, redv, redi, &big);
+    }
     if (tid == 0) {
       Cd.state[0] = 0;
       Cd.state[1] = -1;
       Cd.state[2] = 0;
-      *Cd.r11 = 0.0;
+      *Cd.r11 = sqrt(big);
     }
     __syncthreads();
     __threadfence_block();
@@ -1219,7 +1231,7 @@ __global__ __launch_bounds__(CP_NT) void k_cpqr(const CpqrDescT<R>* cps, double 
   while (j < target) {
     double best = -1.0;
     int bi = -1;
-    for (int l = j + tid; l < c; l += CP_NT) argmax_pair(best, bi, nrm[l], l);
+    for (int l = j + tid; l < cpiv; l += CP_NT) argmax_pair(best, bi, nrm[l], l);
     const int p = block_argmax<CP_NT>(best, bi, redv, redi, nullptr);
     if (p != j) {
       for (int r = tid; r < mb; r += CP_NT) {
@@ -1247,7 +1259,7 @@ __global__ __launch_bounds__(CP_NT) void k_cpqr(const CpqrDescT<R>* cps, double 
     }
     const double xn = sqrt(block_sum<CP_NT>(part, redv));
     if (tid == 0) {
-      if (j == 0) r11 = xn;
+      if (j == 0 && cpiv >= c) r11 = xn;
       int stop = 0;
       if (xn == 0.0) stop = 1;
       else if (tol > 0.0 && xn <= tol * r11) stop = 1;
@@ -1271,7 +1283,8 @@ __global__ __launch_bounds__(CP_NT) void k_cpqr(const CpqrDescT<R>* cps, double 
     }
     __syncthreads();
     const double tau = sh_tau;
-    for (int l = j + 1 + wave; l < c; l += nw) cp_apply_column<R>(B + l * ld, vs, j, mb, tau, nrm, c, l, lane);
+    for (int l = j + 1 + wave; l < c; l += nw)
+      cp_apply_column<R>(B + l * ld, vs, j, mb, tau, nrm, c, l, lane, Cd.extra);
     __syncthreads();
     ++j;
   }
@@ -1307,6 +1320,7 @@ __global__ __launch_bounds__(256) void k_cpqr_init(const CpqrDescT<R>* cps, int 
   }
   p = wave_sum(p);
   if (lane == 0) {
+    if (Cd.extra) p += Cd.extra[l];
     Cd.nrm[l] = p;
     Cd.nrm[Cd.c + l] = p;
     Cd.piv[l] = l;
@@ -1327,7 +1341,8 @@ __global__ __launch_bounds__(256) void k_cpqr_pivot(const CpqrDescT<R>* cps, dou
   C* B = Cd.b;
   const int mb = Cd.mb, c = Cd.c;
   const int64_t ld = mb;
-  const int kmax = min(mb, c);
+  const int cpiv = Cd.cpiv;
+  const int kmax = min(min(mb, c), cpiv);
   const int target = (tol > 0.0) ? kmax : min(kmax, kmin ? kmin[blockIdx.x] : kmax);
   const int j = Cd.state[0];
   if (j >= target) {
@@ -1339,9 +1354,16 @@ __global__ __launch_bounds__(256) void k_cpqr_pivot(const CpqrDescT<R>* cps, dou
     return;
   }
   double* nrm = Cd.nrm;
+  double big = 0;
+  if (j == 0 && cpiv < c) {
+    // restricted pivoting: the threshold refers to the largest column of the whole matrix
+    int bb = -1;
+    for (int l = tid; l < c; l += 256) argmax_pair(big, bb, nrm[l], l);
+    block_argmax<256>(big, bb, redv, redi, &big);
+  }
   double best = -1.0;
   int bi = -1;
-  for (int l = j + tid; l < c; l += 256) argmax_pair(best, bi, nrm[l], l);
+  for (int l = j + tid; l < cpiv; l += 256) argmax_pair(best, bi, nrm[l], l);
   const int p = block_argmax<256>(best, bi, redv, redi, nullptr);
   if (p != j) {
     for (int r = tid; r < mb; r += 256) {
@@ -1369,8 +1391,9 @@ __global__ __launch_bounds__(256) void k_cpqr_pivot(const CpqrDescT<R>* cps, dou
   }
   const double xn = sqrt(block_sum<256>(part, redv));
   if (tid == 0) {
-    double r11 = (j == 0) ? xn : *Cd.r11;
-    if (j == 0) *Cd.r11 = xn;
+    const double first = (cpiv < c) ? sqrt(big) : xn;
+    double r11 = (j == 0) ? first : *Cd.r11;
+    if (j == 0) *Cd.r11 = first;
     int stop = 0;
     if (xn == 0.0) stop = 1;
     else if (tol > 0.0 && xn <= tol * r11) stop = 1;
@@ -1422,7 +1445,7 @@ __global__ __launch_bounds__(256) void k_cpqr_update(const CpqrDescT<R>* cps) {
   const double tau = *Cd.tau;
   for (int l = l0 + wave; l < min(l0 + 16, c); l += 4) {
     if (l <= j) continue;
-    cp_apply_column<R>(Cd.b + (int64_t)l * ld, vs, j, mb, tau, Cd.nrm, c, l, lane);
+    cp_apply_column<R>(Cd.b + (int64_t)l * ld, vs, j, mb, tau, Cd.nrm, c, l, lane, Cd.extra);
   }
 }
 
@@ -1514,16 +1537,62 @@ void la_cpqr_tsolve(const CpqrDescT<R>* d_cp, const int* d_k, int batch, int max
   }
 }
 
+// squared norms of rows kc.. of each column of a truncated QR
+template <class R>
+__global__ __launch_bounds__(256) void k_qr_tail_norms(const QrDescT<R>* qrs, double* const* outs) {
+  const QrDescT<R> Q = qrs[blockIdx.y];
+  double* out = outs[blockIdx.y];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l = blockIdx.x * 4 + wave;
+  if (l >= Q.c || !out) return;
+  double p = 0;
+  if (l >= Q.kc)
+    for (int r = Q.kc + lane; r < Q.m; r += 64) {
+      const cx<R> x = Q.a[r + (int64_t)l * Q.ld];
+      p += (double)x.re * x.re + (double)x.im * x.im;
+    }
+  p = wave_sum(p);
+  if (lane == 0) out[l] = p;
+}
+
+template <class R>
+void la_qr_tail_norms(const QrDescT<R>* d_qr, double* const* d_out, int batch, int max_c, hipStream_t s) {
+  if (batch <= 0 || max_c <= 0) return;
+  hipLaunchKernelGGL(k_qr_tail_norms<R>, dim3((max_c + 3) / 4, batch), dim3(256), 0, s, d_qr, d_out);
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_cpqr_judge(const CpqrDescT<R>* cps, const int* ks, double tol, int* accept) {
+  const CpqrDescT<R> Cd = cps[blockIdx.x];
+  __shared__ double redv[4];
+  __shared__ int redi[4];
+  const int k = ks[blockIdx.x];
+  double big = 0;
+  int bi = -1;
+  for (int l = k + (int)threadIdx.x; l < Cd.c; l += 256) argmax_pair(big, bi, Cd.nrm[l], l);
+  block_argmax<256>(big, bi, redv, redi, &big);
+  if (threadIdx.x == 0) {
+    const double r11 = *Cd.r11;
+    accept[blockIdx.x] = (Cd.c > 0 && Cd.state[0] >= k && big <= tol * tol * r11 * r11) ? 1 : 0;
+  }
+}
+
+template <class R>
+void la_cpqr_judge(const CpqrDescT<R>* d_cp, const int* d_k, double tol, int* d_accept, int batch, hipStream_t s) {
+  if (batch <= 0) return;
+  hipLaunchKernelGGL(k_cpqr_judge<R>, dim3(batch), dim3(256), 0, s, d_cp, d_k, tol, d_accept);
+}
+
 // Algorithmic work of the QR kernels for one m x c matrix, mirroring the launch sequence,
 // with z = 2 real_bytes bytes per complex entry.  Trailing update of an nrb x nc block by
 // jb reflectors: bytes z (2 nrb nc + 2 nrb jb) (the block read and written once, V and
 // V T^H read once), flops 16 nrb nc jb (two complex products).  Leaf factorisation of an
 // nrb x jb block: bytes z (2 nrb jb + 2 nrb PMX_QR_NB) (panel read and written, V and
 // V T^H written), flops 8 nrb jb^2.
-void la_geqrf_work(int m, int c, int real_bytes, double* upd_bytes, double* upd_flops, double* leaf_bytes,
+void la_geqrf_work(int m, int c, int kc, int real_bytes, double* upd_bytes, double* upd_flops, double* leaf_bytes,
                    double* leaf_flops) {
   const double z = 2.0 * real_bytes;
-  const int kmax = std::min(m, c);
+  const int kmax = std::min(kc, std::min(m, c));
   for (int j0 = 0; j0 < kmax; j0 += PMX_QR_NB) {
     const int jb = std::min(PMX_QR_NB, kmax - j0);
     const int nc = c - j0 - jb;
@@ -1565,7 +1634,9 @@ void la_getrf_work(int n, int real_bytes, double* bytes, double* flops) {
   template void la_getrs_small<R>(const LuDescT<R>*, const MatT<R>*, const MatT<R>*, int, int, int, hipStream_t); \
   template void la_geqrf_r<R>(const QrDescT<R>*, int, int, int, hipStream_t);                                \
   template void la_cpqr<R>(const CpqrDescT<R>*, int, int, double, const int*, int, int*, hipStream_t);       \
-  template void la_cpqr_tsolve<R>(const CpqrDescT<R>*, const int*, int, int, int, hipStream_t);
+  template void la_cpqr_tsolve<R>(const CpqrDescT<R>*, const int*, int, int, int, hipStream_t);             \
+  template void la_qr_tail_norms<R>(const QrDescT<R>*, double* const*, int, int, hipStream_t);              \
+  template void la_cpqr_judge<R>(const CpqrDescT<R>*, const int*, double, int*, int, hipStream_t);
 PMX_LA_INST(double)
 PMX_LA_INST(float)
 #undef PMX_LA_INST

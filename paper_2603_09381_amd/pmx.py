@@ -26,6 +26,7 @@ EXPORTS = [
     "pmx_last_error", "pmx_probe_bessel", "pmx_probe_diag_block", "pmx_probe_entries",
     "pmx_probe_zgemm", "pmx_probe_lu_solve", "pmx_probe_id", "pmx_plan_query",
     "pmx_probe_cgemm", "pmx_probe_lu_solve_c32", "pmx_probe_id_c32", "pmx_probe_apply",
+    "pmx_mlp_opts_default", "pmx_id_dataset", "pmx_mlp_train", "pmx_mlp_predict", "pmx_probe_mlp",
 ]
 
 
@@ -49,7 +50,8 @@ class Options(C.Structure):
     _fields_ = [("id_tol", C.c_double), ("proxy_ratio", C.c_double), ("proxy_min", C.c_int32),
                 ("proxy_rule", C.c_int32), ("near_rule", C.c_int32), ("precision", C.c_int32),
                 ("timing", C.c_int32), ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double),
-                ("solve_graph", C.c_int32), ("reserved", C.c_int32 * 8)]
+                ("solve_graph", C.c_int32), ("learned", C.c_int32), ("model_path", C.c_char_p),
+                ("reserved", C.c_int32 * 8)]
 
 
 class Info(C.Structure):
@@ -60,7 +62,12 @@ class Info(C.Structure):
                 ("t_kernel_ms", C.c_double * 16), ("n_kernel_launch", C.c_int32 * 16),
                 ("kernel_bytes", C.c_double * 16), ("kernel_flops", C.c_double * 16),
                 ("t_solve_ms", C.c_double), ("ir_iterations", C.c_int32), ("ir_residual", C.c_double),
-                ("ir_history", C.c_double * 16)]
+                ("ir_history", C.c_double * 16), ("id_learned", C.c_int32), ("id_fallback", C.c_int32)]
+
+
+class MlpOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("hidden", C.c_int32), ("layers", C.c_int32),
+                ("lr", C.c_float), ("wmse", C.c_float), ("seed", C.c_uint64)]
 
 KERNEL_NAMES = ["k_ts_leaf", "k_ts_update", "k_getrf_panel", "k_cpqr_update", "k_cpqr", "k_zgemm",
                 "k_trsm_small", "k_entries", "k_diag_pairs/maue", "k_apply_off", "k_getrs_small"]
@@ -103,12 +110,20 @@ def load(path=None):
     lib.pmx_probe_lu_solve_c32.argtypes = [C.c_int32, C.c_int32, vp, vp, C.c_int32, vp, ip, vp]
     lib.pmx_probe_id_c32.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, C.c_double, ip, vp, ip, vp, vp]
     lib.pmx_probe_apply.argtypes = [C.POINTER(Geometry), C.c_int32, vp, vp, vp]
+    fp = C.POINTER(C.c_float)
+    lib.pmx_mlp_opts_default.argtypes = [C.POINTER(MlpOpts)]
+    lib.pmx_mlp_opts_default.restype = None
+    lib.pmx_id_dataset.argtypes = [C.POINTER(Geometry), C.POINTER(Options), C.c_char_p, C.c_int32, vp]
+    lib.pmx_mlp_train.argtypes = [C.c_char_p, C.POINTER(MlpOpts), C.c_char_p, C.POINTER(C.c_double), vp]
+    lib.pmx_mlp_predict.argtypes = [C.c_char_p, C.POINTER(Geometry), C.POINTER(Options), fp, vp]
+    lib.pmx_probe_mlp.argtypes = [C.c_int32] * 4 + [fp, fp, fp, C.c_int32, C.c_float, fp, fp,
+                                                    C.POINTER(C.c_double), vp]
     dp = C.POINTER(C.c_double)
     lib.pmx_plan_query.argtypes = [C.POINTER(Geometry), C.POINTER(Options), C.c_int32, C.c_int32,
                                    ip, ip, ip, ip, ip, dp, dp, dp, ip, ip, ip]
     for name in EXPORTS:
         if name not in ("pmx_options_default", "pmx_factor_destroy", "pmx_status_string",
-                        "pmx_last_error"):
+                        "pmx_last_error", "pmx_mlp_opts_default"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -148,6 +163,8 @@ class _GeomKeep:
 
 
 def options(w=None, **kw):
+    """Solver options: the library's defaults, the workload's plan settings, then kw.  A
+    model_path string is kept alive by the returned structure's _keep attribute."""
     load()
     o = Options()
     _lib.pmx_options_default(C.byref(o))
@@ -158,6 +175,9 @@ def options(w=None, **kw):
         o.proxy_rule = 0 if w.proxy_paper_rule else 1
         o.near_rule = w.near_rule
     for k, v in kw.items():
+        if k == "model_path" and isinstance(v, str):
+            v = v.encode()
+            o._keep = v
         setattr(o, k, v)
     return o
 
@@ -365,3 +385,74 @@ def plan_query(w, opts=None):
         levels[lev[t]].append(dict(first=int(first[t]), center=(cen[2 * t], cen[2 * t + 1]), rc=rc[t],
                                    Rp=rp[t], P=int(P[t]), near=list(near[noff[t]:noff[t + 1]])))
     return levels
+
+
+# -- learned skeleton proposals -------------------------------------------------------
+NFEAT = 20
+NOUT = 8
+
+
+def mlp_opts(**kw):
+    load()
+    o = MlpOpts()
+    _lib.pmx_mlp_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def id_dataset(w, path, append=False, opts=None):
+    """Full leaf IDs of workload w -> training samples (one per leaf node) in file `path`."""
+    load()
+    keep = _GeomKeep(w)
+    o = options(w) if opts is None else opts
+    _check(_lib.pmx_id_dataset(C.byref(keep.g), C.byref(o), str(path).encode(), int(bool(append)), _stream()))
+
+
+def read_dataset(path):
+    """(X [n, 20], Y [n, 8]) of a training file (float32)."""
+    raw = open(path, "rb").read()
+    assert raw[:8] == b"PMXIDS01"
+    nin, nout = np.frombuffer(raw[8:16], np.int32)
+    n = int(np.frombuffer(raw[16:24], np.int64)[0])
+    rows = np.frombuffer(raw[24:24 + 4 * n * (nin + nout)], np.float32).reshape(n, nin + nout)
+    return rows[:, :nin].copy(), rows[:, nin:].copy()
+
+
+def mlp_train(data_path, model_path, **kw):
+    """Train the proposal network on the device; returns the last epoch's mean loss."""
+    load()
+    o = mlp_opts(**kw)
+    loss = C.c_double()
+    _check(_lib.pmx_mlp_train(str(data_path).encode(), C.byref(o), str(model_path).encode(), C.byref(loss),
+                              _stream()))
+    return loss.value
+
+
+def mlp_predict(model_path, w, opts=None):
+    """The network's outputs per boundary node of w: (n_nodes, 8) float32."""
+    load()
+    keep = _GeomKeep(w)
+    o = options(w) if opts is None else opts
+    out = np.zeros((int(w.node_off[-1]), NOUT), np.float32)
+    _check(_lib.pmx_mlp_predict(str(model_path).encode(), C.byref(keep.g), C.byref(o), _ptr(out, C.c_float),
+                                _stream()))
+    return out
+
+
+def probe_mlp(shape, params, X, labels, wmse=10.0):
+    """Forward + backward of the network on host arrays: shape (nin, nhidden, nlayer, nout),
+    params packed per layer (W out x in column major, then b), X (B, nin), labels (B, nout).
+    Returns (out (B, nout), grad (like params), loss)."""
+    load()
+    nin, nh, nl, nout = shape
+    p = np.ascontiguousarray(params, np.float32)
+    x = np.ascontiguousarray(X, np.float32)
+    y = np.ascontiguousarray(labels, np.float32)
+    B = x.shape[0]
+    out = np.zeros((B, nout), np.float32)
+    grad = np.zeros_like(p)
+    loss = C.c_double()
+    _check(_lib.pmx_probe_mlp(nin, nh, nl, nout, _ptr(p, C.c_float), _ptr(x, C.c_float), _ptr(y, C.c_float), B,
+                              wmse, _ptr(out, C.c_float), _ptr(grad, C.c_float), C.byref(loss), _stream()))
+    return out, grad, loss.value

@@ -233,5 +233,35 @@ def config3(m=400, box=24.0, seed=3, k_ext=12.0) -> Workload:
                      angles=2 * np.pi * np.arange(4) / 4, id_tol=1e-10, near_rule=1)
 
 
+def random_shape_grid(g, seed, k_ext, n=128, a_lo=0.25, a_hi=0.35, cmax=0.05, contrast=1.5, angles=None,
+                      id_tol=1e-10, name=None) -> Workload:
+    """g x g grid (spacing 1) of random smooth shapes r(t) = a(1 + sum_{m=2..6} c_m cos(m t + phi_m)),
+    a ~ U(a_lo, a_hi), c_m ~ U(-cmax, cmax), phi_m ~ U(0, 2 pi), rotation ~ U(0, 2 pi), drawn in
+    row-major cell order from default_rng(seed); k- = contrast k+, n nodes each."""
+    ij, c = _grid(g, g)
+    rng = np.random.default_rng(seed)
+    shapes = []
+    for _ in range(len(c)):
+        a = rng.uniform(a_lo, a_hi)
+        modes = [(mm, rng.uniform(-cmax, cmax), rng.uniform(0, 2 * np.pi)) for mm in range(2, 7)]
+        rot = rng.uniform(0.0, 2.0 * np.pi)
+        shapes.append((a, rot, modes))
+    ang = np.zeros(1) if angles is None else np.asarray(angles, float)
+    return _assemble(name or f"shapes{g}x{g}_k{k_ext:g}_s{seed}", c, shapes, np.full(len(c), n), k_ext,
+                     np.full(len(c), contrast * k_ext), angles=ang, id_tol=id_tol, grid=(g, g), grid_index=ij)
+
+
+def config5_train(i, g=32):
+    """Training geometry i of the learned-skeleton form: seed 5 + i, k+ a in [1, 8] through
+    k+ ~ U(1, 8) / 0.3 drawn from default_rng(1000 + i)."""
+    k = float(np.random.default_rng(1000 + i).uniform(1.0, 8.0)) / 0.3
+    return random_shape_grid(g, 5 + i, k)
+
+
+def config5(k_ext=10.0, g=32, seed=6):
+    """Evaluation grid of the learned-skeleton form: 32 x 32 random shapes, seed 6."""
+    return random_shape_grid(g, seed, k_ext)
+
+
 def plane_wave_angles(nrhs):
     return 2 * np.pi * np.arange(nrhs) / nrhs

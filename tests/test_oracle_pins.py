@@ -252,3 +252,50 @@ def test_planted_missing_interior_term_is_caught():
     good = np.linalg.norm(np.linalg.solve(A, f) - ref) / np.linalg.norm(ref)
     bad = np.linalg.norm(np.linalg.solve(A_bad, f) - ref) / np.linalg.norm(ref)
     assert good < 1e-13 and bad > 1e-2
+
+
+# ---- skeleton-proposal network oracle --------------------------------------------------
+def _mlp_case(shape, B, seed):
+    from oracle import mlp
+    rng = np.random.default_rng(seed)
+    _, npar = mlp.offsets(shape)
+    p = rng.standard_normal(npar) * 0.5
+    X = rng.standard_normal((B, shape[0]))
+    ns = shape[3] // 2
+    Y = np.concatenate([(rng.random((B, ns)) < 0.4).astype(float), rng.random((B, shape[3] - ns))], axis=1)
+    return p, X, Y
+
+
+def test_mlp_gradient_matches_finite_differences():
+    """The hand-written backward pass against central differences of the loss."""
+    from oracle import mlp
+    shape = (5, 7, 2, 4)
+    p, X, Y = _mlp_case(shape, 6, 3)
+    _, L, g = mlp.value_and_grad(p, shape, X, Y, 3.0)
+    h = 1e-6
+    fd = np.zeros_like(p)
+    for i in range(len(p)):
+        e = np.zeros_like(p)
+        e[i] = h
+        fd[i] = (mlp.value_and_grad(p + e, shape, X, Y, 3.0)[1] - mlp.value_and_grad(p - e, shape, X, Y, 3.0)[1]) / (2 * h)
+    assert np.abs(fd - g).max() < 1e-7 * max(1.0, np.abs(g).max())
+
+
+def test_mlp_without_hidden_layers_is_logistic_regression():
+    """No hidden layer and no regression weight: the gradient of the mean binary cross
+    entropy of a linear model is X^T (sigmoid(z) - y) / B (closed form)."""
+    from oracle import mlp
+    shape = (3, 1, 0, 2)
+    p, X, Y = _mlp_case(shape, 9, 4)
+    out, L, g = mlp.value_and_grad(p, shape, X, Y, 0.0)
+    (W, b), = mlp.unpack(p, shape)
+    z = X @ W.T + b
+    assert np.allclose(out, z)
+    s = 1.0 / (1.0 + np.exp(-z[:, :1]))
+    gW = np.zeros_like(W)
+    gW[0] = ((s[:, 0] - Y[:, 0])[:, None] * X).mean(axis=0)
+    gb = np.array([(s[:, 0] - Y[:, 0]).mean(), 0.0])
+    gref = mlp.pack([(gW, gb)])
+    assert np.allclose(g, gref, rtol=0, atol=1e-14)
+    Lref = np.mean(-Y[:, 0] * np.log(s[:, 0]) - (1 - Y[:, 0]) * np.log(1 - s[:, 0]))
+    assert abs(L - Lref) < 1e-12
