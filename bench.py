@@ -1,12 +1,19 @@
-"""Benchmark: factor + solve of the proxy fast direct solver on one MI355X.
+"""Benchmark: factor + solve of the proxy fast direct solver on one MI355X, tuned vs plain.
 
 Workload (default): 16x16 grid of rotated stars r(t) = 0.3(1 + 0.2 cos 5t), unit spacing,
-128 nodes each (N = 65536 unknowns), k+ = 10, k- = 15, ID tolerance 1e-10, four plane
-waves at angles 2 pi j / 4, FP64.  One step = factorisation + solve of the four
-right-hand sides; the boundary samples are host inputs, the densities stay in HBM.
-The JSON line reports unknowns per second over the timed steps, the roofline of the
-dominant kernel (device time from HIP events around its launches in the timed steps,
-algorithmic bytes counted by the library) and the CPU oracle's rate on a sample.
+128 nodes each (N = 65536 unknowns), k+ = 10, k- = 15, four plane waves at angles
+2 pi j / 4.  One step = factorisation + solve of the four right-hand sides (boundary samples
+are host inputs; densities stay in HBM).
+
+Forms, both held to a relative residual of 1e-10 / field error of 1e-8:
+  plain: FP64 throughout, ID tolerance 1e-10;
+  tuned: the factor in complex FP32 (FP32 MFMA QR, LU and Schur products, FP64 pivots) at
+         ID tolerance 1e-5, refined against the FP64 operator (dense on-the-fly apply) to
+         a relative residual of 1e-10; solves replay captured HIP graphs.
+`value` is the tuned form's unknowns per second over the timed steps.  The roofline object
+covers the tuned form's dominant kernel (device time from HIP events around its launches
+in the timed steps, algorithmic work counted by the library); cpu_baseline times the CPU
+oracle (dense solve) on a sample of the same workload.
 """
 from __future__ import annotations
 
@@ -24,8 +31,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "factor+solve seconds & unknowns/s at 1e-8 rel error: tuned vs plain, 1 GPU"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP64_PEAK_TFS = 78.6           # MI355X FP64 vector and matrix
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_ts_update_stars16.json")
+PEAK_TFS = {("mfma", 8): 78.6, ("mfma", 4): 157.3, ("alu", 8): 78.6, ("alu", 4): 157.3}
+# kernels whose algorithmic work the library counts: bound kind and element size (bytes of
+# the real type: 8 in the FP64 form, the factor's type otherwise; the apply is always FP64)
+COUNTED = {"k_ts_update": "mfma", "k_ts_leaf": "alu", "k_getrf_panel": "alu", "k_apply_off": "alu"}
+TRAFFIC_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = {"k_ts_update": ("la_kernels.hip", "la.h"), "k_ts_leaf": ("la_kernels.hip", "la.h"),
+                  "k_getrf_panel": ("la_kernels.hip", "la.h"), "k_apply_off": ("apply_kernels.hip", "assemble.h")}
+FORMS = {"plain": dict(precision=0, id_tol=1e-10),
+         "tuned": dict(precision=1, id_tol=1e-5, ir_tol=1e-10, solve_graph=1)}
 
 
 def parse():
@@ -36,6 +50,7 @@ def parse():
     p.add_argument("--grid", type=int, default=16, help="stars per side (16 = the 65536-unknown workload)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-check", action="store_true")
+    p.add_argument("--no-plain", action="store_true", help="time the tuned form only")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a 256 MiB device copy first (reference kernel for HBM counters)")
     p.add_argument("--no-timing", action="store_true", help="no HIP events around kernels")
@@ -74,26 +89,31 @@ def accuracy(w, x):
     return rel, ed
 
 
-def kernel_source_hash():
+def kernel_source_hash(kname):
     h = hashlib.sha256()
-    for f in ("la_kernels.hip", "la.h"):
+    for f in KERNEL_SOURCES.get(kname, ("la_kernels.hip", "la.h")):
         h.update(open(os.path.join(ROOT, "paper_2603_09381_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch(kname):
+def traffic_file(kname, workload_tag):
+    return os.path.join(TRAFFIC_DIR, f"traffic_{kname}_{workload_tag}.json")
+
+
+def traffic_per_launch(kname, workload_tag):
     """HBM bytes per launch from the committed PMC summary, if taken on this kernel source."""
     try:
-        d = json.load(open(TRAFFIC_FILE))
+        d = json.load(open(traffic_file(kname, workload_tag)))
     except Exception:
         return None
-    if d.get("kernel") != kname or d.get("source_hash") != kernel_source_hash():
+    if d.get("kernel") != kname or d.get("source_hash") != kernel_source_hash(kname):
         return None
     return d.get("bytes_per_launch")
 
 
-def roofline(info_list, names):
-    """Dominant kernel among those whose algorithmic work the library counts."""
+def roofline(info_list, names, real_bytes, workload_tag):
+    """The dominant kernel of the timed steps (largest summed device time); when the library
+    does not count that kernel's work, the dominant counted kernel, with the other named."""
     ms = np.zeros(16)
     nl = np.zeros(16)
     by = np.zeros(16)
@@ -103,32 +123,31 @@ def roofline(info_list, names):
         nl += np.array(info.n_kernel_launch[:16])
         by += np.array(info.kernel_bytes[:16])
         fl += np.array(info.kernel_flops[:16])
-    counted = [k for k in range(len(names)) if by[k] > 0 and ms[k] > 0]
+    live = [k for k in range(len(names)) if ms[k] > 0]
+    if not live:
+        return None, {}
+    top = max(live, key=lambda i: ms[i])
+    counted = [k for k in live if names[k] in COUNTED and fl[k] > 0]
     if not counted:
         return None, {}
-    k = max(counted, key=lambda i: ms[i])
+    k = top if top in counted else max(counted, key=lambda i: ms[i])
+    name = names[k]
     t = ms[k] * 1e-3
-    per_launch_us = 1e3 * ms[k] / nl[k]
-    tr = traffic_per_launch(names[k])
-    # the bound follows the kernel's algorithmic intensity against the FP64 ridge point
-    ridge = FP64_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    if fl[k] / by[k] > ridge:
-        roof = {"bound": "mfma", "achieved": fl[k] / t / 1e12, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": fl[k] / t / 1e12 / FP64_PEAK_TFS}
-    else:
-        roof = {"bound": "hbm", "achieved": by[k] / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": by[k] / t / 1e9 / HBM_PEAK_GBS}
-    roof.update({"traffic": tr, "kernel": names[k], "avg_launch_us": per_launch_us,
-            "algorithmic_flops_per_launch": fl[k] / nl[k],
-            "algorithmic_bytes_per_launch": by[k] / nl[k],
-            "launches_per_step": nl[k] / len(info_list),
-            "algorithmic_bytes_per_step": by[k] / len(info_list),
-            "hbm_gbs_algorithmic": by[k] / t / 1e9})
-    share = {names[i]: round(float(ms[i] / max(ms.sum(), 1e-9)), 4) for i in range(len(names)) if ms[i] > 0}
+    kind = COUNTED[name]
+    rb = 8 if name == "k_apply_off" else real_bytes
+    peak = PEAK_TFS[(kind, rb)]
+    roof = {"bound": kind, "achieved": fl[k] / t / 1e12, "peak": peak, "unit": "TFLOP/s",
+            "frac": fl[k] / t / 1e12 / peak, "traffic": traffic_per_launch(name, workload_tag),
+            "kernel": name, "avg_launch_us": 1e3 * ms[k] / nl[k],
+            "algorithmic_flops_per_launch": fl[k] / nl[k], "algorithmic_bytes_per_launch": by[k] / nl[k],
+            "launches_per_step": nl[k] / len(info_list), "hbm_gbs_algorithmic": by[k] / t / 1e9}
+    if k != top:
+        roof["dominant_overall"] = names[top]
+    share = {names[i]: round(float(ms[i] / max(ms.sum(), 1e-9)), 4) for i in live}
     return roof, share
 
 
-def summarize_pmc(fetch_csv, write_csv, kname="k_ts_update"):
+def summarize_pmc(fetch_csv, write_csv, kname, workload_tag):
     """HBM bytes per launch of `kname` from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE,
     KiB per dispatch), each scaled by what the same counter reads for the 256 MiB device
     copy that --copy-calibration runs first (expected 256 MiB fetched and 256 MiB written)."""
@@ -141,7 +160,7 @@ def summarize_pmc(fetch_csv, write_csv, kname="k_ts_update"):
                 continue
             v = float(r["Counter_Value"]) * 1024.0
             name = r["Kernel_Name"]
-            if name.startswith(kname + "("):
+            if name.startswith(kname + "(") or name.startswith("void " + kname + "<"):
                 per.append(v)
             elif "copy" in name.lower() and int(r["Grid_Size"]) > 1 << 20 and not copy:
                 copy.append(v)
@@ -153,16 +172,38 @@ def summarize_pmc(fetch_csv, write_csv, kname="k_ts_update"):
     ff = cf[0] / ref if cf else 1.0
     fw = cw[0] / ref if cw else 1.0
     per_launch = (np.mean(fetch) / ff + np.mean(write) / fw)
-    out = {"kernel": kname, "source_hash": kernel_source_hash(), "bytes_per_launch": per_launch,
-           "launches": len(fetch), "fetch_scale": ff, "write_scale": fw,
+    out = {"kernel": kname, "workload": workload_tag, "source_hash": kernel_source_hash(kname),
+           "bytes_per_launch": per_launch, "launches": len(fetch), "fetch_scale": ff, "write_scale": fw,
            "fetch_bytes_per_launch": np.mean(fetch) / ff, "write_bytes_per_launch": np.mean(write) / fw}
-    json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
+    json.dump(out, open(traffic_file(kname, workload_tag), "w"), indent=1)
     print(json.dumps(out))
+
+
+def run_form(pmx, w, kw, steps, warmup, timing):
+    import torch
+    opts = pmx.options(w, timing=timing, **kw)
+    for _ in range(warmup):
+        fac = pmx.Factor(w, opts)
+        fac.solve_plane_waves(w.angles)
+        fac.close()
+    torch.cuda.synchronize()
+    times, infos = [], []
+    dens = None
+    for i in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fac = pmx.Factor(w, opts)
+        dens = fac.solve_plane_waves(w.angles)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        infos.append(fac.info())
+        fac.close()
+    return times, infos, dens
 
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
-        summarize_pmc(sys.argv[2], sys.argv[3])
+        summarize_pmc(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
         return
     a = parse()
     if a.gpus != 1:
@@ -180,46 +221,42 @@ def main():
         del src, dst
     w = W.config2(a.grid)
     N = w.n_unknowns
-    opts = pmx.options(w, timing=0 if a.no_timing else 1)
-    for _ in range(a.warmup):
-        fac = pmx.Factor(w, opts)
-        fac.solve_plane_waves(w.angles)
-        fac.close()
-    torch.cuda.synchronize()
-    times, infos = [], []
-    dens = None
-    fac = None
-    for i in range(a.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        fac = pmx.Factor(w, opts)
-        dens = fac.solve_plane_waves(w.angles)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        infos.append(fac.info())
-        if i != a.steps - 1:
-            fac.close()
+    tag = f"stars{a.grid}"
+    timing = 0 if a.no_timing else 1
+    times, infos, dens = run_form(pmx, w, FORMS["tuned"], a.steps, a.warmup, timing)
     total = sum(times)
     info = infos[-1]
     res = {"metric": METRIC, "value": N * a.steps / total, "unit": "unknowns/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * total / a.steps,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128 (f64)",
-           "data": "synthetic",
-           "config": {"workload": f"{a.grid}x{a.grid} rotated stars, 128 nodes, k+=10, k-=15, tol 1e-10, "
-                                  f"4 plane waves (plain FP64 method)",
-                      "n_unknowns": N, "nrhs": len(w.angles), "root_size": info.root_size,
-                      "levels": info.levels, "precision": "fp64"}}
-    if not a.no_timing:
-        roof, share = roofline(infos, pmx.KERNEL_NAMES)
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "c64 factor, f64 residual (mixed)", "data": "synthetic",
+           "config": {"workload": f"{a.grid}x{a.grid} rotated stars, 128 nodes, k+=10, k-=15, 4 plane waves",
+                      "n_unknowns": N, "nrhs": len(w.angles), "tuned": FORMS["tuned"], "plain": FORMS["plain"],
+                      "root_size": info.root_size, "levels": info.levels,
+                      "refinement_steps": info.ir_iterations, "final_relative_residual": info.ir_residual}}
+    if timing:
+        roof, share = roofline(infos, pmx.KERNEL_NAMES, 4, tag)
         res["roofline"] = roof
         res["kernel_time_share"] = share
     else:
         res["roofline"] = None
     if not a.no_check:
-        x = pmx.dens_to_numpy(dens, w)
-        rel, ed = accuracy(w, x)
+        rel, ed = accuracy(w, pmx.dens_to_numpy(dens, w))
         res["accuracy"] = {"sampled_row_rel_residual": rel, "max_energy_defect": ed}
-    fac.close()
+    if not a.no_plain:
+        ptimes, pinfos, pdens = run_form(pmx, w, FORMS["plain"], a.steps, a.warmup, timing)
+        ptotal = sum(ptimes)
+        plain = {"value": N * a.steps / ptotal, "ms_per_step": 1e3 * ptotal / a.steps,
+                 "root_size": pinfos[-1].root_size}
+        if not a.no_check:
+            prel, ped = accuracy(w, pmx.dens_to_numpy(pdens, w))
+            plain["accuracy"] = {"sampled_row_rel_residual": prel, "max_energy_defect": ped}
+        if timing:
+            proof, pshare = roofline(pinfos, pmx.KERNEL_NAMES, 8, tag)
+            plain["roofline"] = proof
+            plain["kernel_time_share"] = pshare
+        res["plain"] = plain
+        res["speedup_vs_plain"] = res["value"] / plain["value"]
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res), flush=True)

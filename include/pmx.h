@@ -104,12 +104,12 @@ typedef struct {
   double t_phase_ms[16];     /* host wall time of phases: 0 self blocks, 1 level compression,
                                 3 top LU */
   /* with options.timing = 1: per-kernel device time from HIP events around every launch of
-   * the factorisation (index: 0 QR leaf blocks, 1 QR trailing update, 2 LU panel, 3 CPQR
+   * the factorisation and of the solves (which then launch kernel by kernel instead of
+   * replaying graphs), summed over them (index: 0 QR leaf blocks, 1 QR trailing update, 2 LU panel, 3 CPQR
    * update, 4 CPQR single-workgroup, 5 complex GEMM, 6 small triangular solves, 7 entry
    * assembly, 8 self blocks, 9 dense operator apply of refinement residuals, 10 fused
-   * substitutions of few right-hand sides; 9 and 10 run in solves, which are not timed),
-   * launch counts, and the algorithmic bytes and flops of the kernels whose work the
-   * library counts (0, 1, 2). */
+   * substitutions of few right-hand sides), launch counts, and the algorithmic bytes and
+   * flops of the kernels whose work the library counts (0, 1, 2, 9). */
   double t_kernel_ms[16];
   int32_t n_kernel_launch[16];
   double kernel_bytes[16];

@@ -1544,7 +1544,8 @@ hipGraphExec_t capture_graph(hipStream_t gs, Fn&& fn) {
 // run a launch sequence, through its captured graph when graphs are on
 template <class Fn>
 void run_seq(pmx_factor* F, hipGraphExec_t& g, Fn&& fn) {
-  if (!F->opts.solve_graph) {
+  // with per-kernel timing the sequence runs launch by launch, bracketed by events
+  if (!F->opts.solve_graph || g_ktimer) {
     fn();
     return;
   }
@@ -1604,6 +1605,24 @@ void upload_angles(pmx_factor* F, const double* angles) {
   SolveState& S = *F->ss;
   std::copy(angles, angles + S.nrhs, S.h_angles.begin());
   HIPCHK(hipMemcpyAsync(S.d_angles, S.h_angles.data(), S.nrhs * sizeof(double), hipMemcpyHostToDevice, F->gs));
+}
+
+// Algorithmic work of one dense operator apply, per pair of nodes on different
+// inclusions: 6 flops for the distance, 94 for H0 and H1 by their large-argument
+// expansion (two series of 10 terms in 1/z for each of P and Q, 20 for the phase and the
+// amplitude), 30 for the four kernel factors, and 32 per right-hand side for the four
+// complex multiply-adds into the value and derivative rows.  Bytes: the node data (x, y,
+// normal, weight) and the densities read once, the partial sums of every source split
+// written once.
+void count_apply_work(pmx_factor* F, int nrhs) {
+  double pairs = (double)F->n_nodes * F->n_nodes;
+  for (int j = 0; j < F->m; ++j) {
+    const double n = (double)(F->node_off[j + 1] - F->node_off[j]);
+    pairs -= n * n;
+  }
+  const double N2 = 2.0 * F->n_nodes;
+  F->info.kernel_flops[PK_APPLY] += pairs * (130.0 + 32.0 * nrhs);
+  F->info.kernel_bytes[PK_APPLY] += 8.0 * 5 * F->n_nodes + 16.0 * N2 * nrhs * (1 + F->ss->apply.nsplit);
 }
 
 // FP64 factor: right-hand side into the leaf vectors, one solve pass, solution to xout.
@@ -1666,6 +1685,7 @@ void solve_refined(pmx_factor* F, int nrhs, const double* angles, const zd* rhs)
       launch_dense_apply(S.apply, gs);
       launch_norms(S.apply, S.r, gs);
     });
+    count_apply_work(F, nrhs);
     const std::vector<double> rn = read_norms(S.apply, gs);
     rel = 0;
     for (int c = 0; c < nrhs; ++c) rel = std::max(rel, fn[c] > 0 ? std::sqrt(rn[c] / fn[c]) : std::sqrt(rn[c]));
@@ -1685,6 +1705,14 @@ void solve_refined(pmx_factor* F, int nrhs, const double* angles, const zd* rhs)
 // as graphs), ordered after the caller's stream and before its later work.
 void solve_any(pmx_factor* F, int nrhs, const double* angles, const zd* rhs, zd* dens, hipStream_t s) {
   const double t0 = now_ms();
+  std::unique_ptr<KernelTimer> kt;
+  if (F->opts.timing) {
+    kt.reset(new KernelTimer());
+    g_ktimer = kt.get();
+  }
+  struct Reset {
+    ~Reset() { g_ktimer = nullptr; }
+  } reset_timer;
   HIPCHK(hipEventRecord(F->ev_in, s));
   HIPCHK(hipStreamWaitEvent(F->gs, F->ev_in, 0));
   pmx_status late = PMX_OK;
@@ -1707,6 +1735,7 @@ void solve_any(pmx_factor* F, int nrhs, const double* angles, const zd* rhs, zd*
   HIPCHK(hipEventRecord(F->ev_out, F->gs));
   HIPCHK(hipStreamWaitEvent(s, F->ev_out, 0));
   sync_check(F->gs);
+  if (kt) kt->collect(F->info.t_kernel_ms, F->info.n_kernel_launch);
   F->info.t_solve_ms = now_ms() - t0;
   if (late != PMX_OK) throw PmxErr{late, late_msg};
 }
