@@ -13,93 +13,113 @@
 // reduced by a second kernel, in a fixed order).
 #include "assemble.h"
 #include "bessel.h"
+#include "hankel_fast.h"
 #include "ktimer.h"
 
 #include <algorithm>
 
-#define APPLY_TS 128
+// Source data of a group of NR right-hand sides, packed per source node so that every
+// lane of a wave reads the same address (scalar loads): x, y, normal, owning inclusion,
+// then per right-hand side the weighted densities w q and w u.
+#define APPLY_SRC(NR) (5 + 4 * (NR))
 
 template <int NR>
-__global__ __launch_bounds__(256) void k_apply_off(ApplyArgs A, int r0, int per_split) {
-  __shared__ double sx[APPLY_TS], sy[APPLY_TS], snx[APPLY_TS], sny[APPLY_TS];
-  __shared__ int sown[APPLY_TS];
-  __shared__ zd sq[NR][APPLY_TS], su[NR][APPLY_TS];
-  const int tid = threadIdx.x;
+__global__ void k_apply_pack(ApplyArgs A, int r0, double* pk) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= A.n_nodes) return;
+  const int own = A.owner[b];
+  const int64_t o = A.node_off[own];
+  const int64_t n = A.node_off[own + 1] - o;
+  const double w = A.w[b];
+  double* p = pk + (int64_t)b * APPLY_SRC(NR);
+  p[0] = A.x[b];
+  p[1] = A.y[b];
+  p[2] = A.nx[b];
+  p[3] = A.ny[b];
+  p[4] = (double)own;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    zd q = zmk(0, 0), u = zmk(0, 0);
+    if (r0 + r < A.nrhs) {
+      const zd* col = A.xin + (int64_t)(r0 + r) * A.ld + 2 * o + (b - o);
+      q = col[0];
+      u = col[n];
+    }
+    p[5 + 4 * r] = w * q.re;
+    p[6 + 4 * r] = w * q.im;
+    p[7 + 4 * r] = w * u.re;
+    p[8 + 4 * r] = w * u.im;
+  }
+}
+
+// The general evaluation, for waves with an argument below 24 (pairs of close inclusions):
+// out of line, so that its many series constants do not take registers in the loop.
+__device__ __noinline__ bes4 bessel01_near(double z) { return bessel01(z); }
+
+template <int NR>
+__global__ __launch_bounds__(256) void k_apply_off(ApplyArgs A, const double* __restrict__ pk, int r0,
+                                                   int per_split) {
+  constexpr int S = APPLY_SRC(NR);
   const int N = A.n_nodes;
-  const int a = blockIdx.x * 256 + tid;
-  const bool active = a < N;
+  const int a_raw = blockIdx.x * 256 + threadIdx.x;
+  const bool active = a_raw < N;
+  const int a = active ? a_raw : N - 1;   // idle lanes follow the last node and write nothing
   const int b0 = blockIdx.y * per_split;
   const int b1 = min(b0 + per_split, N);
   const int nr = min(NR, A.nrhs - r0);
-  double ax = 0, ay = 0, anx = 0, any = 0;
-  int aown = -1;
-  if (active) {
-    ax = A.x[a];
-    ay = A.y[a];
-    anx = A.nx[a];
-    any = A.ny[a];
-    aown = A.owner[a];
-  }
+  const double ax = A.x[a], ay = A.y[a], anx = A.nx[a], any = A.ny[a];
+  const int aown = A.owner[a];
+  const double downa = (double)aown;
   const double k = A.k, eps = A.eps;
-  const double ke = k / eps;
-  zd val[NR], der[NR];
+  const double ik = 1.0 / k, ke = k / eps;
+  double vr[NR], vi[NR], dr[NR], di[NR];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    val[r] = zmk(0, 0);
-    der[r] = zmk(0, 0);
-  }
-  for (int t0 = b0; t0 < b1; t0 += APPLY_TS) {
-    const int nt = min(APPLY_TS, b1 - t0);
-    if (tid < APPLY_TS) {
-      const int b = t0 + tid;
-      if (tid < nt) {
-        const int own = A.owner[b];
-        const int64_t o = A.node_off[own];
-        const int64_t n = A.node_off[own + 1] - o;
-        const double w = A.w[b];
-        sx[tid] = A.x[b];
-        sy[tid] = A.y[b];
-        snx[tid] = A.nx[b];
-        sny[tid] = A.ny[b];
-        sown[tid] = own;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          zd q = zmk(0, 0), u = zmk(0, 0);
-          if (r < nr) {
-            const zd* col = A.xin + (int64_t)(r0 + r) * A.ld + 2 * o + (b - o);
-            q = col[0];
-            u = col[n];
-          }
-          sq[r][tid] = zscale(q, w);
-          su[r][tid] = zscale(u, w);
-        }
-      }
+  for (int r = 0; r < NR; ++r) vr[r] = vi[r] = dr[r] = di[r] = 0.0;
+  for (int j = b0; j < b1; ++j) {
+    const double* p = pk + (int64_t)j * S;
+    const double sown = p[4];
+    if (__all(sown == downa)) {
+      // the whole wave sits on this source's inclusion: skip to the inclusion's end
+      j = (int)min((int64_t)b1, A.node_off[(int)sown + 1]) - 1;
+      continue;
     }
-    __syncthreads();
-    if (active) {
-      for (int j = 0; j < nt; ++j) {
-        if (sown[j] == aown) continue;
-        const double d1 = ax - sx[j], d2 = ay - sy[j];
-        const double r = sqrt(d1 * d1 + d2 * d2);
-        const double ir = 1.0 / r;
-        const bes4 h = bessel01(k * r);
-        const double nsd = (snx[j] * d1 + sny[j] * d2) * ir;
-        const double ntd = (anx * d1 + any * d2) * ir;
-        const double aa = ntd * nsd;
-        const double bc = (anx * snx[j] + any * sny[j] - 2.0 * aa) * ir;
-        const zd c1 = zmk(-eps * h.j0, -eps * h.y0);
-        const zd c2 = zmk(k * nsd * h.j1, k * nsd * h.y1);
-        const zd c3 = zmk(k * ntd * h.j1, k * ntd * h.y1);
-        const zd c4 = zmk(ke * (k * aa * h.j0 + bc * h.j1), ke * (k * aa * h.y0 + bc * h.y1));
-#pragma unroll
-        for (int rr = 0; rr < NR; ++rr) {
-          const zd q = sq[rr][j], u = su[rr][j];
-          val[rr] = zfma(c1, q, zfma(c2, u, val[rr]));
-          der[rr] = zfma(c3, q, zfma(c4, u, der[rr]));
-        }
-      }
+    if (sown == downa) continue;
+    const double d1 = ax - p[0], d2 = ay - p[1];
+    const double dd = d1 * d1 + d2 * d2;
+    const double ir = rsqrt_nr(dd);
+    const double z = k * (dd * ir);
+    double J0, J1, Y0, Y1;
+    // the large-argument path with as many terms as the wave's smallest argument needs
+    if (__all(z >= 60.0)) {
+      hankel_far<12>(z, ir * ik, J0, J1, Y0, Y1);
+    } else if (__all(z >= 35.0)) {
+      hankel_far<16>(z, ir * ik, J0, J1, Y0, Y1);
+    } else if (__all(z >= 24.0)) {
+      hankel_far<20>(z, ir * ik, J0, J1, Y0, Y1);
+    } else {
+      const bes4 h = bessel01_near(z);
+      J0 = h.j0;
+      J1 = h.j1;
+      Y0 = h.y0;
+      Y1 = h.y1;
     }
-    __syncthreads();
+    const double nsd = (p[2] * d1 + p[3] * d2) * ir;
+    const double ntd = (anx * d1 + any * d2) * ir;
+    const double aa = ntd * nsd;
+    const double bc = (anx * p[2] + any * p[3] - 2.0 * aa) * ir;
+    // c1 = -e+ H0, c2 = k nsd H1, c3 = k ntd H1, c4 = (k/e+)(k aa H0 + bc H1)
+    const double c1r = -eps * J0, c1i = -eps * Y0;
+    const double c2r = k * nsd * J1, c2i = k * nsd * Y1;
+    const double c3r = k * ntd * J1, c3i = k * ntd * Y1;
+    const double c4r = ke * (k * aa * J0 + bc * J1), c4i = ke * (k * aa * Y0 + bc * Y1);
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) {
+      const double qr = p[5 + 4 * rr], qi = p[6 + 4 * rr], ur = p[7 + 4 * rr], ui = p[8 + 4 * rr];
+      vr[rr] = fma(c1r, qr, fma(-c1i, qi, fma(c2r, ur, fma(-c2i, ui, vr[rr]))));
+      vi[rr] = fma(c1r, qi, fma(c1i, qr, fma(c2r, ui, fma(c2i, ur, vi[rr]))));
+      dr[rr] = fma(c3r, qr, fma(-c3i, qi, fma(c4r, ur, fma(-c4i, ui, dr[rr]))));
+      di[rr] = fma(c3r, qi, fma(c3i, qr, fma(c4r, ui, fma(c4i, ur, di[rr]))));
+    }
   }
   if (!active) return;
   const int64_t o = A.node_off[aown];
@@ -110,8 +130,8 @@ __global__ __launch_bounds__(256) void k_apply_off(ApplyArgs A, int r0, int per_
     if (r < nr) {
       zd* col = out + (int64_t)(r0 + r) * A.ld + 2 * o + (a - o);
       // times i/4
-      col[0] = zmk(-0.25 * val[r].im, 0.25 * val[r].re);
-      col[n] = zmk(-0.25 * der[r].im, 0.25 * der[r].re);
+      col[0] = zmk(-0.25 * vi[r], 0.25 * vr[r]);
+      col[n] = zmk(-0.25 * di[r], 0.25 * dr[r]);
     }
   }
 }
@@ -133,29 +153,37 @@ int apply_splits(int n_nodes, int nrhs) {
   const int chunks = (nrhs + 7) / 8;
   int ns = (2048 + nwg * chunks - 1) / (nwg * chunks);
   ns = std::max(1, std::min(ns, 64));
-  // at least one full source tile per split
-  ns = std::min(ns, std::max(1, n_nodes / APPLY_TS));
+  // at least 128 sources per split
+  ns = std::min(ns, std::max(1, n_nodes / 128));
   return ns;
+}
+
+int64_t apply_pack_size(int n_nodes, int nrhs) { return (int64_t)n_nodes * APPLY_SRC(std::min(nrhs, 8) <= 1 ? 1 : (std::min(nrhs, 8) <= 2 ? 2 : (std::min(nrhs, 8) <= 4 ? 4 : 8))); }
+
+template <int NR>
+static void apply_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipStream_t s) {
+  const int per = (A.n_nodes + nsplit - 1) / nsplit;
+  hipLaunchKernelGGL(k_apply_pack<NR>, dim3((A.n_nodes + 255) / 256), dim3(256), 0, s, A, r0, pk);
+  KScope ks(PK_APPLY, s);
+  hipLaunchKernelGGL(k_apply_off<NR>, dim3((A.n_nodes + 255) / 256, nsplit), dim3(256), 0, s, A,
+                     (const double*)pk, r0, per);
 }
 
 void asm_apply_off(const ApplyArgs& A, int nsplit, hipStream_t s) {
   if (A.n_nodes <= 0 || A.nrhs <= 0) return;
-  const int per = (A.n_nodes + nsplit - 1) / nsplit;
-  dim3 grid((A.n_nodes + 255) / 256, nsplit);
-  KScope ks(PK_APPLY, s);
   for (int r0 = 0; r0 < A.nrhs;) {
     const int left = A.nrhs - r0;
     if (left == 1) {
-      hipLaunchKernelGGL(k_apply_off<1>, grid, dim3(256), 0, s, A, r0, per);
+      apply_group<1>(A, A.pack, r0, nsplit, s);
       r0 += 1;
     } else if (left == 2) {
-      hipLaunchKernelGGL(k_apply_off<2>, grid, dim3(256), 0, s, A, r0, per);
+      apply_group<2>(A, A.pack, r0, nsplit, s);
       r0 += 2;
     } else if (left <= 4) {
-      hipLaunchKernelGGL(k_apply_off<4>, grid, dim3(256), 0, s, A, r0, per);
+      apply_group<4>(A, A.pack, r0, nsplit, s);
       r0 += 4;
     } else {
-      hipLaunchKernelGGL(k_apply_off<8>, grid, dim3(256), 0, s, A, r0, per);
+      apply_group<8>(A, A.pack, r0, nsplit, s);
       r0 += 8;
     }
   }

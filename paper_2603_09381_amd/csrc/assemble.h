@@ -142,8 +142,10 @@ struct ApplyArgs {
   int nrhs;
   int64_t ld;
   zd* part;
+  double* pack;          // [apply_pack_size] packed source data of one group of right-hand sides
 };
 int apply_splits(int n_nodes, int nrhs);
+int64_t apply_pack_size(int n_nodes, int nrhs);
 void asm_apply_off(const ApplyArgs& a, int nsplit, hipStream_t s);
 // out = sf f + sa (ydiag + sum_p part[p]) elementwise over total entries (f may be NULL)
 void asm_apply_finish(const zd* f, const zd* ydiag, const zd* part, int nsplit, int64_t total, double sf, double sa,

@@ -1447,6 +1447,7 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   aa.nrhs = nrhs;
   aa.ld = N2;
   aa.part = D.part;
+  aa.pack = A.alloc<double>(apply_pack_size(F->n_nodes, nrhs));
   D.f = f;
   D.out = out;
   D.nrhs = nrhs;

@@ -377,6 +377,109 @@ __global__ __launch_bounds__(256) void k_getrf_panel(const LuDescT<R>* lus, int 
   }
 }
 
+// The same panel step with the panel held in registers: thread t owns rows j0 + t + NT q
+// (q < RPT) of the panel's columns, so a column step costs a block argmax, one exchange
+// of two rows through LDS and register updates, instead of global read-modify-writes.
+// Pivots, tie-breaks and the order of the updates are those of k_getrf_panel.
+template <class R, int NT, int RPT>
+__global__ __launch_bounds__(NT) void k_getrf_panel_reg(const LuDescT<R>* lus, int j0, int* info) {
+  typedef cx<R> C;
+  const LuDescT<R> L = lus[blockIdx.x];
+  const int jb = min(PMX_LU_NB, L.n - j0);
+  if (jb <= 0) return;
+  __shared__ double redv[NT / 64];
+  __shared__ int redi[NT / 64];
+  __shared__ C prow[PMX_LU_NB], crow[PMX_LU_NB];
+  const int tid = threadIdx.x;
+  C* A = L.a;
+  const int64_t ld = L.ld;
+  C P[RPT][PMX_LU_NB];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = j0 + tid + NT * q;
+    const int ci = min(i, L.n - 1);
+#pragma unroll
+    for (int c = 0; c < PMX_LU_NB; ++c) P[q][c] = A[ci + (int64_t)(j0 + min(c, jb - 1)) * ld];
+  }
+#pragma unroll 1
+  for (int c = 0; c < jb; ++c) {
+    const int col = j0 + c;
+    double best = -1.0;
+    int bi = -1;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int i = j0 + tid + NT * q;
+      C v = P[q][0];
+#pragma unroll
+      for (int cc = 1; cc < PMX_LU_NB; ++cc)
+        if (cc == c) v = P[q][cc];
+      if (i >= col && i < L.n) argmax_pair(best, bi, fabs((double)v.re) + fabs((double)v.im), i);
+    }
+    double bestv;
+    const int p = block_argmax<NT>(best, bi, redv, redi, &bestv);
+    if (tid == 0) {
+      L.ipiv[col] = p;
+      if (bestv == 0.0 && info && info[blockIdx.x] == 0) info[blockIdx.x] = col + 1;
+    }
+    // exchange rows col and p through LDS
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int i = j0 + tid + NT * q;
+      if (i == p) {
+#pragma unroll
+        for (int cc = 0; cc < PMX_LU_NB; ++cc) prow[cc] = P[q][cc];
+      }
+      if (i == col) {
+#pragma unroll
+        for (int cc = 0; cc < PMX_LU_NB; ++cc) crow[cc] = P[q][cc];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int i = j0 + tid + NT * q;
+      if (i == p && p != col) {
+#pragma unroll
+        for (int cc = 0; cc < PMX_LU_NB; ++cc) P[q][cc] = crow[cc];
+      }
+      if (i == col) {
+#pragma unroll
+        for (int cc = 0; cc < PMX_LU_NB; ++cc) P[q][cc] = prow[cc];
+      }
+    }
+    const C piv = prow[c];
+    if (piv.re != R(0) || piv.im != R(0)) {
+      const C inv = zdiv(cmk<R>(1, 0), piv);
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int i = j0 + tid + NT * q;
+        if (i > col && i < L.n) {
+          C l = P[q][0];
+#pragma unroll
+          for (int cc = 1; cc < PMX_LU_NB; ++cc)
+            if (cc == c) l = P[q][cc];
+          l = zmul(l, inv);
+#pragma unroll
+          for (int cc = 0; cc < PMX_LU_NB; ++cc) {
+            if (cc == c) P[q][cc] = l;
+            else if (cc > c) P[q][cc] = zsub(P[q][cc], zmul(l, prow[cc]));
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = j0 + tid + NT * q;
+    if (i < L.n) {
+#pragma unroll
+      for (int cc = 0; cc < PMX_LU_NB; ++cc)
+        if (cc < jb) A[i + (int64_t)(j0 + cc) * ld] = P[q][cc];
+    }
+  }
+}
+
 // apply the swaps of panel [j0, j0+jb) to the columns outside the panel
 template <class R>
 __global__ void k_laswp_panel(const LuDescT<R>* lus, int j0) {
@@ -461,8 +564,18 @@ void la_getrf(const LuDescT<R>* d_lu, int batch, int max_n, int* d_info, hipStre
   if (batch <= 0 || max_n <= 0) return;
   for (int j0 = 0; j0 < max_n; j0 += PMX_LU_NB) {
     {
+      // panel rows max_n - j0: in registers when they fit without spilling (512 rows, 1024
+      // in FP32), else the global-memory kernel
       KScope ks(PK_GETRF_PANEL, s);
-      hipLaunchKernelGGL(k_getrf_panel<R>, dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      const int rows = max_n - j0;
+      if (rows <= 256)
+        hipLaunchKernelGGL((k_getrf_panel_reg<R, 256, 1>), dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      else if (rows <= 512)
+        hipLaunchKernelGGL((k_getrf_panel_reg<R, 256, 2>), dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      else if (rows <= 1024 && sizeof(R) == 4)
+        hipLaunchKernelGGL((k_getrf_panel_reg<R, 512, 2>), dim3(batch), dim3(512), 0, s, d_lu, j0, d_info);
+      else
+        hipLaunchKernelGGL(k_getrf_panel<R>, dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
     }
     hipLaunchKernelGGL(k_laswp_panel<R>, dim3((max_n + 255) / 256, batch), dim3(256), 0, s, d_lu, j0);
     int rem = max_n - j0 - PMX_LU_NB;

@@ -79,9 +79,11 @@ def test_id_fp32(pmx, m, c):
         assert 0.6 ** k < 1e2 * tol and 0.6 ** max(k - 8, 0) > tol * 1e-2, k
 
 
-@pytest.mark.parametrize("g,n", [(2, 64), (3, 48)])
-def test_dense_apply_against_oracle(pmx, g, n):
-    w = W.star_grid(g, n=n, k_ext=10.0, k_int=15.0, seed=5)
+@pytest.mark.parametrize("g,n,k", [(2, 64, 10.0), (3, 48, 10.0), (4, 48, 45.0)])
+def test_dense_apply_against_oracle(pmx, g, n, k):
+    """k = 45 on a 4x4 grid puts k r between about 20 and 190: every branch of the apply's
+    Hankel evaluation (series, Chebyshev, 20-, 16- and 12-term expansions)."""
+    w = W.star_grid(g, n=n, k_ext=k, k_int=1.5 * k, seed=5)
     A = dense.assemble(dense.Geometry(w))
     x = crandn(w.n_unknowns, 3)
     ref = A @ x
