@@ -11,9 +11,10 @@ Forms, both held to a relative residual of 1e-10 / field error of 1e-8:
          ID tolerance 1e-5, refined against the FP64 operator (dense on-the-fly apply) to
          a relative residual of 1e-10; solves replay captured HIP graphs.
 `value` is the tuned form's unknowns per second over the timed steps.  The roofline object
-covers the tuned form's dominant kernel (device time from HIP events around its launches
-in the timed steps, algorithmic work counted by the library); cpu_baseline times the CPU
-oracle (dense solve) on a sample of the same workload.
+covers the tuned form's dominant kernel (found in the warm-up steps, which time every
+kernel; in the timed steps HIP events bracket that kernel's launches only), with the
+algorithmic work counted by the library; kernel_time_share comes from the warm-up steps.
+cpu_baseline times the CPU oracle (dense solve) on a sample of the same workload.
 """
 from __future__ import annotations
 
@@ -111,26 +112,39 @@ def traffic_per_launch(kname, workload_tag):
     return d.get("bytes_per_launch")
 
 
-def roofline(info_list, names, real_bytes, workload_tag):
-    """The dominant kernel of the timed steps (largest summed device time); when the library
-    does not count that kernel's work, the dominant counted kernel, with the other named."""
-    ms = np.zeros(16)
-    nl = np.zeros(16)
-    by = np.zeros(16)
-    fl = np.zeros(16)
+def _sums(info_list):
+    ms, nl, by, fl = (np.zeros(16) for _ in range(4))
     for info in info_list:
         ms += np.array(info.t_kernel_ms[:16])
         nl += np.array(info.n_kernel_launch[:16])
         by += np.array(info.kernel_bytes[:16])
         fl += np.array(info.kernel_flops[:16])
+    return ms, nl, by, fl
+
+
+def dominant_kernel(info_list, names):
+    """From steps that timed every kernel: the index of the dominant kernel whose work the
+    library counts (largest summed device time), the overall dominant one, and the time
+    shares."""
+    ms, _, _, fl = _sums(info_list)
     live = [k for k in range(len(names)) if ms[k] > 0]
     if not live:
-        return None, {}
+        return None, None, {}
     top = max(live, key=lambda i: ms[i])
     counted = [k for k in live if names[k] in COUNTED and fl[k] > 0]
-    if not counted:
-        return None, {}
-    k = top if top in counted else max(counted, key=lambda i: ms[i])
+    k = None if not counted else (top if top in counted else max(counted, key=lambda i: ms[i]))
+    share = {names[i]: round(float(ms[i] / max(ms.sum(), 1e-9)), 4) for i in live}
+    return k, top, share
+
+
+def roofline(info_list, k, top, names, real_bytes, workload_tag):
+    """Kernel k over the timed steps: algorithmic work counted by the library divided by
+    the device time of its launches (HIP events on its launch stream)."""
+    if k is None:
+        return None
+    ms, nl, by, fl = _sums(info_list)
+    if ms[k] <= 0 or nl[k] <= 0:
+        return None
     name = names[k]
     t = ms[k] * 1e-3
     kind = COUNTED[name]
@@ -141,17 +155,24 @@ def roofline(info_list, names, real_bytes, workload_tag):
             "kernel": name, "avg_launch_us": 1e3 * ms[k] / nl[k],
             "algorithmic_flops_per_launch": fl[k] / nl[k], "algorithmic_bytes_per_launch": by[k] / nl[k],
             "launches_per_step": nl[k] / len(info_list), "hbm_gbs_algorithmic": by[k] / t / 1e9}
-    if k != top:
+    if top is not None and top != k:
         roof["dominant_overall"] = names[top]
-    share = {names[i]: round(float(ms[i] / max(ms.sum(), 1e-9)), 4) for i in live}
-    return roof, share
+    return roof
 
 
 def summarize_pmc(fetch_csv, write_csv, kname, workload_tag):
     """HBM bytes per launch of `kname` from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE,
     KiB per dispatch), each scaled by what the same counter reads for the 256 MiB device
-    copy that --copy-calibration runs first (expected 256 MiB fetched and 256 MiB written)."""
+    copy that --copy-calibration runs first (expected 256 MiB fetched and 256 MiB written).
+    `kname` may carry template arguments ("k_ts_update<double>") to pick one instantiation;
+    the summary is stored under the plain name."""
     import csv
+    base = kname.split("<")[0]
+
+    def matches(name):
+        if "<" in kname:
+            return name.startswith("void " + kname)
+        return name.startswith(kname + "(") or name.startswith("void " + kname + "<")
 
     def load(path, counter):
         per, copy = [], []
@@ -160,10 +181,10 @@ def summarize_pmc(fetch_csv, write_csv, kname, workload_tag):
                 continue
             v = float(r["Counter_Value"]) * 1024.0
             name = r["Kernel_Name"]
-            if name.startswith(kname + "(") or name.startswith("void " + kname + "<"):
+            if matches(name):
                 per.append(v)
-            elif "copy" in name.lower() and int(r["Grid_Size"]) > 1 << 20 and not copy:
-                copy.append(v)
+            elif name.startswith("__amd_rocclr_copyBuffer") and not copy:
+                copy.append(v)   # the first runtime copy of the run: the 256 MiB calibration copy
         return per, copy
 
     fetch, cf = load(fetch_csv, "FETCH_SIZE")
@@ -172,21 +193,30 @@ def summarize_pmc(fetch_csv, write_csv, kname, workload_tag):
     ff = cf[0] / ref if cf else 1.0
     fw = cw[0] / ref if cw else 1.0
     per_launch = (np.mean(fetch) / ff + np.mean(write) / fw)
-    out = {"kernel": kname, "workload": workload_tag, "source_hash": kernel_source_hash(kname),
+    out = {"kernel": base, "instantiation": kname, "workload": workload_tag, "source_hash": kernel_source_hash(base),
            "bytes_per_launch": per_launch, "launches": len(fetch), "fetch_scale": ff, "write_scale": fw,
            "fetch_bytes_per_launch": np.mean(fetch) / ff, "write_bytes_per_launch": np.mean(write) / fw}
-    json.dump(out, open(traffic_file(kname, workload_tag), "w"), indent=1)
+    json.dump(out, open(traffic_file(base, workload_tag), "w"), indent=1)
     print(json.dumps(out))
 
 
 def run_form(pmx, w, kw, steps, warmup, timing):
+    """Warm-up steps time every kernel (time shares, dominant kernel); the timed steps time
+    only the dominant counted kernel, so that events around the other launches do not
+    slow the step (and solve sequences without it replay their graphs)."""
     import torch
+    names = pmx.KERNEL_NAMES
+    winfos = []
     opts = pmx.options(w, timing=timing, **kw)
     for _ in range(warmup):
         fac = pmx.Factor(w, opts)
         fac.solve_plane_waves(w.angles)
+        winfos.append(fac.info())
         fac.close()
     torch.cuda.synchronize()
+    k, top, share = dominant_kernel(winfos, names) if timing else (None, None, {})
+    if k is not None:
+        opts = pmx.options(w, timing=timing, timing_kernels=1 << k, **kw)
     times, infos = [], []
     dens = None
     for i in range(steps):
@@ -198,7 +228,9 @@ def run_form(pmx, w, kw, steps, warmup, timing):
         times.append(time.perf_counter() - t0)
         infos.append(fac.info())
         fac.close()
-    return times, infos, dens
+    if timing and k is None:     # no warm-up: every kernel was timed in the timed steps
+        k, top, share = dominant_kernel(infos, names)
+    return times, infos, dens, (k, top, share)
 
 
 def main():
@@ -221,9 +253,9 @@ def main():
         del src, dst
     w = W.config2(a.grid)
     N = w.n_unknowns
-    tag = f"stars{a.grid}"
+    tag = f"stars{a.grid}"   # traffic summaries are per form: <tag>_tuned, <tag>_plain
     timing = 0 if a.no_timing else 1
-    times, infos, dens = run_form(pmx, w, FORMS["tuned"], a.steps, a.warmup, timing)
+    times, infos, dens, dom = run_form(pmx, w, FORMS["tuned"], a.steps, a.warmup, timing)
     total = sum(times)
     info = infos[-1]
     res = {"metric": METRIC, "value": N * a.steps / total, "unit": "unknowns/s", "n_gpus": 1,
@@ -235,16 +267,15 @@ def main():
                       "root_size": info.root_size, "levels": info.levels,
                       "refinement_steps": info.ir_iterations, "final_relative_residual": info.ir_residual}}
     if timing:
-        roof, share = roofline(infos, pmx.KERNEL_NAMES, 4, tag)
-        res["roofline"] = roof
-        res["kernel_time_share"] = share
+        res["roofline"] = roofline(infos, dom[0], dom[1], pmx.KERNEL_NAMES, 4, tag + "_tuned")
+        res["kernel_time_share"] = dom[2]
     else:
         res["roofline"] = None
     if not a.no_check:
         rel, ed = accuracy(w, pmx.dens_to_numpy(dens, w))
         res["accuracy"] = {"sampled_row_rel_residual": rel, "max_energy_defect": ed}
     if not a.no_plain:
-        ptimes, pinfos, pdens = run_form(pmx, w, FORMS["plain"], a.steps, a.warmup, timing)
+        ptimes, pinfos, pdens, pdom = run_form(pmx, w, FORMS["plain"], a.steps, a.warmup, timing)
         ptotal = sum(ptimes)
         plain = {"value": N * a.steps / ptotal, "ms_per_step": 1e3 * ptotal / a.steps,
                  "root_size": pinfos[-1].root_size}
@@ -252,9 +283,8 @@ def main():
             prel, ped = accuracy(w, pmx.dens_to_numpy(pdens, w))
             plain["accuracy"] = {"sampled_row_rel_residual": prel, "max_energy_defect": ped}
         if timing:
-            proof, pshare = roofline(pinfos, pmx.KERNEL_NAMES, 8, tag)
-            plain["roofline"] = proof
-            plain["kernel_time_share"] = pshare
+            plain["roofline"] = roofline(pinfos, pdom[0], pdom[1], pmx.KERNEL_NAMES, 8, tag + "_plain")
+            plain["kernel_time_share"] = pdom[2]
         res["plain"] = plain
         res["speedup_vs_plain"] = res["value"] / plain["value"]
     if not a.no_cpu_baseline:

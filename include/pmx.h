@@ -89,7 +89,13 @@ typedef struct {
                            within id_tol |R_11| of their span (both IDs of both pairs of the
                            cell); otherwise the cell's IDs take the full CPQR */
   const char* model_path;  /* network file written by pmx_mlp_train (read at create) */
-  int32_t reserved[8];
+  uint32_t timing_kernels; /* with timing = 1: bit k selects kernel k of pmx_info.t_kernel_ms
+                              for timing; 0: every kernel.  Solve sequences run launch by
+                              launch (not as graphs) only when one of their kernels is timed */
+  int32_t reserved0;
+  const char* tune_path;   /* launch-parameter table written by pmx_autotune (read at create);
+                              NULL: built-in rules */
+  int32_t reserved[4];
 } pmx_options;
 
 typedef struct {
@@ -103,9 +109,9 @@ typedef struct {
   double t_factor_ms;        /* wall time of pmx_factor_create (host clock, synchronised) */
   double t_phase_ms[16];     /* host wall time of phases: 0 self blocks, 1 level compression,
                                 3 top LU */
-  /* with options.timing = 1: per-kernel device time from HIP events around every launch of
-   * the factorisation and of the solves (which then launch kernel by kernel instead of
-   * replaying graphs), summed over them (index: 0 QR leaf blocks, 1 QR trailing update, 2 LU panel, 3 CPQR
+  /* with options.timing = 1: per-kernel device time from HIP events around every launch
+   * (of the kernels selected by options.timing_kernels) of the factorisation and of the
+   * solves, summed over them (index: 0 QR leaf blocks, 1 QR trailing update, 2 LU panel, 3 CPQR
    * update, 4 CPQR single-workgroup, 5 complex GEMM, 6 small triangular solves, 7 entry
    * assembly, 8 self blocks, 9 dense operator apply of refinement residuals, 10 fused
    * substitutions of few right-hand sides), launch counts, and the algorithmic bytes and
@@ -128,7 +134,7 @@ typedef struct pmx_factor pmx_factor;
 
 /* Fills defaults: id_tol 1e-10, proxy_ratio 1.5, proxy_min 0, proxy_rule 0, near_rule 0,
  * precision 0, timing 0, ir_max_iter 10, ir_tol 1e-10, solve_graph 1, learned 0,
- * model_path NULL. */
+ * model_path NULL, timing_kernels 0, tune_path NULL. */
 void pmx_options_default(pmx_options* o);
 
 /* Builds the plan and the whole compressed factorisation on `hip_stream`.  Returns when
@@ -157,6 +163,22 @@ pmx_status pmx_far_field(const pmx_factor* f, int32_t nrhs, const pmx_c64* dens,
                          const double* dirs, pmx_c64* out, void* hip_stream);
 
 pmx_status pmx_factor_info(const pmx_factor* f, pmx_info* info);
+
+/* Autotuner of the launch parameters of the batched form.  Launches whose kernel has
+ * alternatives (the LU panel kernel, the column-pivoted QR variant, the level-solve
+ * variant, the dense apply's right-hand-side grouping and source splits) look their
+ * choice up in a table keyed by the real type and size buckets of the launch; without a
+ * table (or for a key it lacks) a built-in rule applies.  This call builds such a table
+ * for a workload: it factors geom with opts (their timing, graph and table settings
+ * ignored) and solves nrhs plane waves (angles 2 pi j / nrhs) while recording every
+ * tunable launch shape, then times every candidate of every recorded shape on device
+ * buffers of that shape (fixed seeded fills; best of reps timed runs after one warm-up;
+ * the apply on the factor's own state, within a 30 s budget) and writes the fastest per
+ * key to the text file `path` ("knob real_bytes a b c choice # candidate:us ...").
+ * Factors created with options.tune_path = path use it.  nrhs in [1, 256], reps in
+ * [1, 50].  Allocates device memory of the factor's size plus the largest timing case. */
+pmx_status pmx_autotune(const pmx_geometry* geom, const pmx_options* opts, int32_t nrhs, int32_t reps,
+                        const char* path, void* hip_stream);
 
 /* Releases everything the factor holds; accepts NULL. */
 void pmx_factor_destroy(pmx_factor* f);

@@ -12,7 +12,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 HIP_SOURCES = ["la_kernels.hip", "assemble_kernels.hip", "apply_kernels.hip", "mlp_kernels.hip", "learn.cpp",
-               "factor.cpp"]
+               "tune.cpp", "factor.cpp"]
 HOST_SOURCES = ["plan.cpp"]
 
 

@@ -148,17 +148,17 @@ __global__ void k_apply_finish(const zd* f, const zd* ydiag, const zd* part, int
   out[i] = v;
 }
 
-int apply_splits(int n_nodes, int nrhs) {
+// source splits so that one launch has about wg_target workgroups, with at least 128
+// sources per split
+int apply_splits(int n_nodes, int wg_target) {
   const int nwg = (n_nodes + 255) / 256;
-  const int chunks = (nrhs + 7) / 8;
-  int ns = (2048 + nwg * chunks - 1) / (nwg * chunks);
+  int ns = (wg_target + nwg - 1) / nwg;
   ns = std::max(1, std::min(ns, 64));
-  // at least 128 sources per split
   ns = std::min(ns, std::max(1, n_nodes / 128));
   return ns;
 }
 
-int64_t apply_pack_size(int n_nodes, int nrhs) { return (int64_t)n_nodes * APPLY_SRC(std::min(nrhs, 8) <= 1 ? 1 : (std::min(nrhs, 8) <= 2 ? 2 : (std::min(nrhs, 8) <= 4 ? 4 : 8))); }
+int64_t apply_pack_size(int n_nodes, int nr_max) { return (int64_t)n_nodes * APPLY_SRC(nr_max); }
 
 template <int NR>
 static void apply_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipStream_t s) {
@@ -169,23 +169,20 @@ static void apply_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipS
                      (const double*)pk, r0, per);
 }
 
-void asm_apply_off(const ApplyArgs& A, int nsplit, hipStream_t s) {
+// right-hand sides in groups of nr_max (1, 2, 4 or 8); a last smaller group takes the
+// smallest of those sizes that holds it
+void asm_apply_off(const ApplyArgs& A, int nsplit, int nr_max, hipStream_t s) {
   if (A.n_nodes <= 0 || A.nrhs <= 0) return;
   for (int r0 = 0; r0 < A.nrhs;) {
     const int left = A.nrhs - r0;
-    if (left == 1) {
-      apply_group<1>(A, A.pack, r0, nsplit, s);
-      r0 += 1;
-    } else if (left == 2) {
-      apply_group<2>(A, A.pack, r0, nsplit, s);
-      r0 += 2;
-    } else if (left <= 4) {
-      apply_group<4>(A, A.pack, r0, nsplit, s);
-      r0 += 4;
-    } else {
-      apply_group<8>(A, A.pack, r0, nsplit, s);
-      r0 += 8;
+    const int g = left >= nr_max ? nr_max : (left <= 1 ? 1 : left <= 2 ? 2 : left <= 4 ? 4 : 8);
+    switch (g) {
+      case 1: apply_group<1>(A, A.pack, r0, nsplit, s); break;
+      case 2: apply_group<2>(A, A.pack, r0, nsplit, s); break;
+      case 4: apply_group<4>(A, A.pack, r0, nsplit, s); break;
+      default: apply_group<8>(A, A.pack, r0, nsplit, s); break;
     }
+    r0 += g;
   }
 }
 

@@ -144,9 +144,13 @@ struct ApplyArgs {
   zd* part;
   double* pack;          // [apply_pack_size] packed source data of one group of right-hand sides
 };
-int apply_splits(int n_nodes, int nrhs);
-int64_t apply_pack_size(int n_nodes, int nrhs);
-void asm_apply_off(const ApplyArgs& a, int nsplit, hipStream_t s);
+// source splits giving about wg_target workgroups per launch
+int apply_splits(int n_nodes, int wg_target);
+// doubles of the packed source data for groups of up to nr_max right-hand sides
+int64_t apply_pack_size(int n_nodes, int nr_max);
+// partial sums part[split] of the off-diagonal operator, right-hand sides in groups of
+// nr_max (1, 2, 4, 8) per thread
+void asm_apply_off(const ApplyArgs& a, int nsplit, int nr_max, hipStream_t s);
 // out = sf f + sa (ydiag + sum_p part[p]) elementwise over total entries (f may be NULL)
 void asm_apply_finish(const zd* f, const zd* ydiag, const zd* part, int nsplit, int64_t total, double sf, double sa,
                       zd* out, hipStream_t s);

@@ -35,6 +35,7 @@
 #include "learn.h"
 #include "plan.h"
 #include "ktimer.h"
+#include "tune.h"
 
 thread_local KernelTimer* g_ktimer = nullptr;
 
@@ -215,6 +216,8 @@ struct pmx_factor {
   std::unique_ptr<SolveState> ss;
   // learned leaf IDs: the network's outputs per leaf node (PMX_NOUT x nodes, leaf order)
   std::vector<float> leaf_pred;
+  // launch-parameter table of options.tune_path (NULL: built-in rules)
+  std::unique_ptr<TuneTable> tune;
   ~pmx_factor();
   DevGeom geom() const { return DevGeom{x, y, nx, ny, w, speed, kappa, n_nodes}; }
   ExtParams ext() const { return ExtParams{k_ext, eps_ext}; }
@@ -1310,6 +1313,15 @@ void build_program(pmx_factor* F, int nrhs, hipStream_t s) {
   P.nrhs = nrhs;
 }
 
+// level solves of `batch` LU factors of size <= n: the fused kernel (few right-hand
+// sides) or the blocked one, by default the fused one up to PMX_GETRS_SMALL_MAX
+template <class R>
+bool getrs_fused(int n, int batch, int nrhs) {
+  const int v = tune_choice(TK_GETRS, (int)sizeof(R), tune_bucket_size(n), tune_bucket_batch(batch),
+                            tune_bucket_pow2(nrhs), nrhs <= PMX_GETRS_SMALL_MAX ? 0 : 1, n, batch, nrhs);
+  return v == 0 && nrhs <= PMX_GETRS_SMALL_MAX;
+}
+
 // the launches of one solve pass on the leaf vectors P.leaf (in place); no host work
 template <class R>
 void launch_program(pmx_factor* F, hipStream_t s) {
@@ -1321,7 +1333,7 @@ void launch_program(pmx_factor* F, hipStream_t s) {
   for (int l = 0; l < nl; ++l) {
     const LevelData<R>& L = T.lev[l];
     SolveLevel<R>& S = P.lv[l];
-    if (nrhs <= PMX_GETRS_SMALL_MAX)
+    if (getrs_fused<R>(L.max_s, L.ncell, nrhs))
       la_getrs_small(L.d_lu, S.d_bm, S.d_w, L.ncell, L.max_s, nrhs, s);
     else
       la_getrs(L.d_lu, S.d_bm, L.ncell, L.max_s, nrhs, s);
@@ -1333,7 +1345,7 @@ void launch_program(pmx_factor* F, hipStream_t s) {
     (void)top;
     asm_gather(S.G, S.d_par, S.n_par, S.max_par, nrhs, s);
   }
-  if (nrhs <= PMX_GETRS_SMALL_MAX)
+  if (getrs_fused<R>(T.root_s, 1, nrhs))
     la_getrs_small(T.d_lu_root, P.d_bm_root, P.d_w_root, 1, T.root_s, nrhs, s);
   else
     la_getrs(T.d_lu_root, P.d_bm_root, 1, T.root_s, nrhs, s);
@@ -1401,7 +1413,7 @@ GatherDescT<RD>* gather_to_leaf(const LeafMap& M, cx<RD>* leaf, int nrhs, Arena&
 // self blocks from FP64 storage (block of inclusion incl[t] at offset doff[t], 2 n x 2 n)
 // by batched MFMA products, the blocks between inclusions evaluated on the fly.
 struct DenseApply {
-  int nrhs = -1, nsplit = 1, nblk = 1;
+  int nrhs = -1, nsplit = 1, nblk = 1, nr_max = 8;
   int64_t total = 0;
   zd *ydiag = nullptr, *part = nullptr;
   double* d_norm = nullptr;
@@ -1417,7 +1429,13 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
                        hipStream_t s) {
   const int64_t N2 = 2 * (int64_t)F->n_nodes;
   D.total = N2 * nrhs;
-  D.nsplit = apply_splits(F->n_nodes, nrhs);
+  // right-hand sides per thread and workgroups per launch: built-in 8 and 2048, or the
+  // launch-parameter table's choice for this node count and right-hand-side count
+  const int ta = tune_bucket_pow2(F->n_nodes), tb = tune_bucket_pow2(nrhs);
+  D.nr_max = tune_choice(TK_APPLY_NR, 8, ta, tb, 0, 8, F->n_nodes, nrhs, 0);
+  if (D.nr_max != 1 && D.nr_max != 2 && D.nr_max != 4 && D.nr_max != 8) D.nr_max = 8;
+  const int wg = std::max(64, std::min(1 << 20, tune_choice(TK_APPLY_WG, 8, ta, tb, 0, 2048, F->n_nodes, nrhs, 0)));
+  D.nsplit = apply_splits(F->n_nodes, wg);
   D.ydiag = A.alloc<zd>(D.total);
   D.part = A.alloc<zd>(D.total * D.nsplit);
   D.nblk = (int)std::min<int64_t>(64, (N2 + 4095) / 4096);
@@ -1447,7 +1465,7 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   aa.nrhs = nrhs;
   aa.ld = N2;
   aa.part = D.part;
-  aa.pack = A.alloc<double>(apply_pack_size(F->n_nodes, nrhs));
+  aa.pack = A.alloc<double>(apply_pack_size(F->n_nodes, 8));
   D.f = f;
   D.out = out;
   D.nrhs = nrhs;
@@ -1455,7 +1473,7 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
 
 void launch_dense_apply(const DenseApply& D, hipStream_t s) {
   la_zgemm_list(OP_N, OP_N, D.d_ga, D.n_ga, D.max_s, D.nrhs, zmk(1, 0), zmk(0, 0), s);
-  asm_apply_off(D.aa, D.nsplit, s);
+  asm_apply_off(D.aa, D.nsplit, D.nr_max, s);
   if (D.f)
     asm_apply_finish(D.f, D.ydiag, D.part, D.nsplit, D.total, 1.0, -1.0, D.out, s);
   else
@@ -1545,8 +1563,9 @@ hipGraphExec_t capture_graph(hipStream_t gs, Fn&& fn) {
 // run a launch sequence, through its captured graph when graphs are on
 template <class Fn>
 void run_seq(pmx_factor* F, hipGraphExec_t& g, Fn&& fn) {
-  // with per-kernel timing the sequence runs launch by launch, bracketed by events
-  if (!F->opts.solve_graph || g_ktimer) {
+  // with per-kernel timing of a kernel of the sequence it runs launch by launch, bracketed
+  // by events
+  if (!F->opts.solve_graph || (g_ktimer && (g_ktimer->mask & PK_SOLVE_MASK))) {
     fn();
     return;
   }
@@ -1709,11 +1728,17 @@ void solve_any(pmx_factor* F, int nrhs, const double* angles, const zd* rhs, zd*
   std::unique_ptr<KernelTimer> kt;
   if (F->opts.timing) {
     kt.reset(new KernelTimer());
+    if (F->opts.timing_kernels) kt->mask = F->opts.timing_kernels;
     g_ktimer = kt.get();
   }
   struct Reset {
-    ~Reset() { g_ktimer = nullptr; }
-  } reset_timer;
+    const TuneTable* prev;
+    ~Reset() {
+      g_ktimer = nullptr;
+      g_tune = prev;
+    }
+  } reset_timer{g_tune};
+  g_tune = F->tune.get();
   HIPCHK(hipEventRecord(F->ev_in, s));
   HIPCHK(hipStreamWaitEvent(F->gs, F->ev_in, 0));
   pmx_status late = PMX_OK;
@@ -1889,6 +1914,70 @@ void leaf_predictions(pmx_factor* F, const pmx_geometry* g, const char* path, hi
   }
 }
 
+// Autotuner, dense apply: times the right-hand-side grouping and source-split candidates
+// of the recorded apply shapes on the factor's own apply state (after a solve), best of
+// reps launches after a warm-up, within a time budget (candidates in a fixed order, the
+// built-in choice first), and stores the fastest pair.
+void tune_apply(pmx_factor* F, const TuneRecorder& rec, TuneTable& t, int reps, hipStream_t s) {
+  if (!F->ss || F->ss->nrhs <= 0 || F->opts.precision == 0) return;
+  DenseApply& D = F->ss->apply;
+  const int ta = tune_bucket_pow2(F->n_nodes), tb = tune_bucket_pow2(D.nrhs);
+  const uint64_t knr = tune_key(TK_APPLY_NR, 8, ta, tb, 0), kwg = tune_key(TK_APPLY_WG, 8, ta, tb, 0);
+  if (!rec.dims.count(knr) || !rec.dims.count(kwg)) return;
+  int cnr[8], nnr = 0, cwg[8], nwg = 0;
+  tune_candidates(TK_APPLY_NR, 8, F->n_nodes, D.nrhs, 0, cnr, &nnr);
+  tune_candidates(TK_APPLY_WG, 8, F->n_nodes, D.nrhs, 0, cwg, &nwg);
+  std::vector<std::pair<int, int>> cand{{8, 2048}};
+  for (int i = 0; i < nnr; ++i)
+    for (int j = 0; j < nwg; ++j)
+      if (!(cnr[i] == 8 && cwg[j] == 2048)) cand.push_back({cnr[i], cwg[j]});
+  Arena tmp;
+  std::map<int, zd*> parts;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } ev{e0, e1};
+  ApplyArgs aa = D.aa;
+  const double budget_ms = 30000.0;
+  double spent = 0, best = 1e300;
+  int bi = 0;
+  std::string note;
+  for (size_t c = 0; c < cand.size() && spent < budget_ms; ++c) {
+    const int ns = apply_splits(F->n_nodes, cand[c].second);
+    if (!parts.count(ns)) parts[ns] = tmp.alloc<zd>(D.total * ns);
+    aa.part = parts[ns];
+    double tbest = 1e300;
+    for (int r = 0; r <= reps; ++r) {
+      HIPCHK(hipEventRecord(e0, s));
+      asm_apply_off(aa, ns, cand[c].first, s);
+      HIPCHK(hipEventRecord(e1, s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      spent += ms;
+      if (r > 0 || ms > 500.0f) tbest = std::min(tbest, (double)ms);   // long launches: no separate warm-up
+      if (ms > 500.0f && r >= 1) break;
+    }
+    note += (note.empty() ? "" : " ") + std::to_string(cand[c].first) + "/" + std::to_string(cand[c].second) + ":" +
+            std::to_string((int64_t)std::llround(1e3 * tbest));
+    if (tbest < best) {
+      best = tbest;
+      bi = (int)c;
+    }
+  }
+  HIPCHK(hipGetLastError());
+  t.val[knr] = cand[bi].first;
+  t.val[kwg] = cand[bi].second;
+  t.note[knr] = "nr/wg:us " + note;
+  t.note[kwg] = "chosen with apply_nr";
+}
+
 template <class Fn>
 pmx_status guarded(Fn&& fn) {
   try {
@@ -1941,15 +2030,27 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
     std::unique_ptr<pmx_factor> F(new pmx_factor());
     std::memset(&F->info, 0, sizeof(F->info));
     F->opts = o;
+    if (o.tune_path) {
+      F->tune.reset(new TuneTable());
+      const std::string e = tune_load(o.tune_path, *F->tune);
+      if (!e.empty()) fail(PMX_EINVAL, e);
+    }
+    F->opts.tune_path = nullptr;   // read here only
     const double t0 = now_ms();
     std::unique_ptr<KernelTimer> kt;
     if (o.timing) {
       kt.reset(new KernelTimer());
+      if (o.timing_kernels) kt->mask = o.timing_kernels;
       g_ktimer = kt.get();
     }
     struct Reset {
-      ~Reset() { g_ktimer = nullptr; }
-    } reset_timer;
+      const TuneTable* prev;
+      ~Reset() {
+        g_ktimer = nullptr;
+        g_tune = prev;
+      }
+    } reset_timer{g_tune};
+    g_tune = F->tune.get();
     make_plan(geom, o, F->plan);
     HIPCHK(hipStreamCreateWithFlags(&F->gs, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&F->ev_in, hipEventDisableTiming));
@@ -1970,6 +2071,45 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
       kt->collect(F->info.t_kernel_ms, F->info.n_kernel_launch);
     }
     *out = F.release();
+  });
+}
+
+pmx_status pmx_autotune(const pmx_geometry* geom, const pmx_options* opts, int32_t nrhs, int32_t reps,
+                        const char* path, void* hip_stream) {
+  return guarded([&] {
+    if (!geom || !path || nrhs < 1 || nrhs > 256 || reps < 1 || reps > 50) fail(PMX_EINVAL, "bad arguments to pmx_autotune");
+    pmx_options o;
+    pmx_options_default(&o);
+    if (opts) o = *opts;
+    o.timing = 0;
+    o.tune_path = nullptr;
+    o.solve_graph = 0;
+    hipStream_t s = (hipStream_t)hip_stream;
+    TuneRecorder rec;
+    struct RecReset {
+      ~RecReset() { g_tune_rec = nullptr; }
+    } rec_reset;
+    // pass 1: the workload with every tunable launch shape recorded
+    g_tune_rec = &rec;
+    pmx_factor* raw = nullptr;
+    pmx_status st = pmx_factor_create(geom, &o, hip_stream, &raw);
+    if (st != PMX_OK) throw PmxErr{st, g_last_error};
+    std::unique_ptr<pmx_factor> F(raw);
+    Arena tmp;
+    zd* dens = tmp.alloc<zd>(2 * (int64_t)F->n_nodes * nrhs);
+    std::vector<double> ang(nrhs);
+    for (int r = 0; r < nrhs; ++r) ang[r] = 2.0 * M_PI * r / nrhs;
+    st = pmx_solve_plane_waves(F.get(), nrhs, ang.data(), (pmx_c64*)dens, hip_stream);
+    if (st != PMX_OK) throw PmxErr{st, g_last_error};
+    g_tune_rec = nullptr;
+    // pass 2: every candidate of every recorded shape, timed
+    TuneTable t;
+    const std::string e = tune_linear_algebra(rec, t, reps, s);
+    if (!e.empty()) fail(PMX_EHIP, e);
+    tune_apply(F.get(), rec, t, reps, s);
+    sync_check(s);
+    const std::string w = tune_save(path, t);
+    if (!w.empty()) fail(PMX_EINVAL, w);
   });
 }
 

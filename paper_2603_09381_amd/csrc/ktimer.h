@@ -1,6 +1,7 @@
 // Optional per-kernel timing with HIP events on the launch stream.  When a KernelTimer is
-// active for the calling thread, every instrumented launch is bracketed by two events;
-// after the stream has been synchronised, collect() sums the elapsed times per kernel.
+// active for the calling thread, every instrumented launch of a kernel in its mask is
+// bracketed by two events; after the stream has been synchronised, collect() sums the
+// elapsed times per kernel.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -21,7 +22,11 @@ enum PmxKernelId {
   PK_COUNT = 11
 };
 
+// kernels launched by solve sequences (captured as graphs unless one of them is timed)
+constexpr unsigned PK_SOLVE_MASK = (1u << PK_ZGEMM) | (1u << PK_TRSM) | (1u << PK_APPLY) | (1u << PK_GETRS);
+
 struct KernelTimer {
+  unsigned mask = ~0u;   // bit k: time the launches of kernel k
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   struct Rec {
@@ -60,7 +65,7 @@ struct KScope {
   int kid;
   hipStream_t s;
   KScope(int k, hipStream_t st) : kid(k), s(st) {
-    if (g_ktimer) {
+    if (g_ktimer && ((g_ktimer->mask >> k) & 1u)) {
       e0 = g_ktimer->get();
       if (e0) (void)hipEventRecord(e0, s);
     }

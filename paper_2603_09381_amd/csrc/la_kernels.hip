@@ -16,6 +16,7 @@
 // norm of the trailing part of the pivot column, which is what the threshold tests.
 #include "la.h"
 #include "ktimer.h"
+#include "tune.h"
 
 #include <algorithm>
 
@@ -559,23 +560,55 @@ __global__ __launch_bounds__(256) void k_lu_perm(const LuDescT<R>* lus) {
   for (int i = threadIdx.x; i < L.n; i += 256) L.perm[i] = pl[i];
 }
 
+// whether panel variant v holds `rows` panel rows (registers: 256, 512, 1024 rows; the
+// 1024-row variant spills in FP64)
+template <class R>
+static bool lu_panel_fits(int v, int rows) {
+  switch (v) {
+    case 0: return rows <= 256;
+    case 1: return rows <= 512;
+    case 2: return sizeof(R) == 4 && rows <= 1024;
+    case 3: return true;
+    default: return false;
+  }
+}
+
+template <class R>
+void la_lu_panel(int variant, const LuDescT<R>* d_lu, int batch, int j0, int* d_info, hipStream_t s) {
+  KScope ks(PK_GETRF_PANEL, s);
+  switch (variant) {
+    case 0:
+      hipLaunchKernelGGL((k_getrf_panel_reg<R, 256, 1>), dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_getrf_panel_reg<R, 256, 2>), dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      break;
+    case 2:
+      if (sizeof(R) == 4) {
+        hipLaunchKernelGGL((k_getrf_panel_reg<R, 512, 2>), dim3(batch), dim3(512), 0, s, d_lu, j0, d_info);
+        break;
+      }
+      [[fallthrough]];
+    default:
+      hipLaunchKernelGGL(k_getrf_panel<R>, dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      break;
+  }
+}
+
 template <class R>
 void la_getrf(const LuDescT<R>* d_lu, int batch, int max_n, int* d_info, hipStream_t s) {
   if (batch <= 0 || max_n <= 0) return;
   for (int j0 = 0; j0 < max_n; j0 += PMX_LU_NB) {
     {
-      // panel rows max_n - j0: in registers when they fit without spilling (512 rows, 1024
-      // in FP32), else the global-memory kernel
-      KScope ks(PK_GETRF_PANEL, s);
+      // panel rows max_n - j0: by default in registers when they fit without spilling (512
+      // rows, 1024 in FP32), else the global-memory kernel; a launch-parameter table may
+      // choose another variant that holds the rows
       const int rows = max_n - j0;
-      if (rows <= 256)
-        hipLaunchKernelGGL((k_getrf_panel_reg<R, 256, 1>), dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
-      else if (rows <= 512)
-        hipLaunchKernelGGL((k_getrf_panel_reg<R, 256, 2>), dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
-      else if (rows <= 1024 && sizeof(R) == 4)
-        hipLaunchKernelGGL((k_getrf_panel_reg<R, 512, 2>), dim3(batch), dim3(512), 0, s, d_lu, j0, d_info);
-      else
-        hipLaunchKernelGGL(k_getrf_panel<R>, dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      const int dflt = rows <= 256 ? 0 : rows <= 512 ? 1 : (rows <= 1024 && sizeof(R) == 4) ? 2 : 3;
+      int v = tune_choice(TK_LU_PANEL, (int)sizeof(R), tune_bucket_size(rows), tune_bucket_batch(batch), 0, dflt,
+                          rows, batch, 0);
+      if (!lu_panel_fits<R>(v, rows)) v = dflt;
+      la_lu_panel<R>(v, d_lu, batch, j0, d_info, s);
     }
     hipLaunchKernelGGL(k_laswp_panel<R>, dim3((max_n + 255) / 256, batch), dim3(256), 0, s, d_lu, j0);
     int rem = max_n - j0 - PMX_LU_NB;
@@ -1571,7 +1604,9 @@ void la_cpqr(const CpqrDescT<R>* d_cp, int batch, int max_c, double tol, const i
     (void)hipFuncSetAttribute((const void*)k_cpqr<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     (void)hipFuncSetAttribute((const void*)k_cpqr_update<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   }
-  if (max_c < PMX_CPQR_MULTI_MIN) {
+  const int mode = tune_choice(TK_CPQR, (int)sizeof(R), tune_bucket_size(max_c), tune_bucket_batch(batch), 0,
+                               max_c < PMX_CPQR_MULTI_MIN ? 0 : 1, max_c, batch, 0);
+  if (mode == 0) {
     KScope ks(PK_CPQR, s);
     hipLaunchKernelGGL(k_cpqr<R>, dim3(batch), dim3(CP_NT), shm, s, d_cp, tol, d_kmin, init);
     return;
@@ -1743,6 +1778,7 @@ void la_getrf_work(int n, int real_bytes, double* bytes, double* flops) {
 #define PMX_LA_INST(R)                                                                                       \
   template void la_zgemm_list<R>(int, int, const GemmArgsT<R>*, int, int, int, cx<R>, cx<R>, hipStream_t);  \
   template void la_getrf<R>(const LuDescT<R>*, int, int, int*, hipStream_t);                                 \
+  template void la_lu_panel<R>(int, const LuDescT<R>*, int, int, int*, hipStream_t);                         \
   template void la_getrs<R>(const LuDescT<R>*, const MatT<R>*, int, int, int, hipStream_t);                  \
   template void la_getrs_small<R>(const LuDescT<R>*, const MatT<R>*, const MatT<R>*, int, int, int, hipStream_t); \
   template void la_geqrf_r<R>(const QrDescT<R>*, int, int, int, hipStream_t);                                \

@@ -27,6 +27,7 @@ EXPORTS = [
     "pmx_probe_zgemm", "pmx_probe_lu_solve", "pmx_probe_id", "pmx_plan_query",
     "pmx_probe_cgemm", "pmx_probe_lu_solve_c32", "pmx_probe_id_c32", "pmx_probe_apply",
     "pmx_mlp_opts_default", "pmx_id_dataset", "pmx_mlp_train", "pmx_mlp_predict", "pmx_probe_mlp",
+    "pmx_autotune",
 ]
 
 
@@ -51,7 +52,8 @@ class Options(C.Structure):
                 ("proxy_rule", C.c_int32), ("near_rule", C.c_int32), ("precision", C.c_int32),
                 ("timing", C.c_int32), ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double),
                 ("solve_graph", C.c_int32), ("learned", C.c_int32), ("model_path", C.c_char_p),
-                ("reserved", C.c_int32 * 8)]
+                ("timing_kernels", C.c_uint32), ("reserved0", C.c_int32), ("tune_path", C.c_char_p),
+                ("reserved", C.c_int32 * 4)]
 
 
 class Info(C.Structure):
@@ -118,6 +120,7 @@ def load(path=None):
     lib.pmx_mlp_predict.argtypes = [C.c_char_p, C.POINTER(Geometry), C.POINTER(Options), fp, vp]
     lib.pmx_probe_mlp.argtypes = [C.c_int32] * 4 + [fp, fp, fp, C.c_int32, C.c_float, fp, fp,
                                                     C.POINTER(C.c_double), vp]
+    lib.pmx_autotune.argtypes = [C.POINTER(Geometry), C.POINTER(Options), C.c_int32, C.c_int32, C.c_char_p, vp]
     dp = C.POINTER(C.c_double)
     lib.pmx_plan_query.argtypes = [C.POINTER(Geometry), C.POINTER(Options), C.c_int32, C.c_int32,
                                    ip, ip, ip, ip, ip, dp, dp, dp, ip, ip, ip]
@@ -174,11 +177,13 @@ def options(w=None, **kw):
         o.proxy_min = w.proxy_min
         o.proxy_rule = 0 if w.proxy_paper_rule else 1
         o.near_rule = w.near_rule
+    keep = []
     for k, v in kw.items():
-        if k == "model_path" and isinstance(v, str):
+        if k in ("model_path", "tune_path") and isinstance(v, str):
             v = v.encode()
-            o._keep = v
+            keep.append(v)
         setattr(o, k, v)
+    o._keep = keep
     return o
 
 
@@ -407,6 +412,26 @@ def id_dataset(w, path, append=False, opts=None):
     keep = _GeomKeep(w)
     o = options(w) if opts is None else opts
     _check(_lib.pmx_id_dataset(C.byref(keep.g), C.byref(o), str(path).encode(), int(bool(append)), _stream()))
+
+
+def autotune(w, path, nrhs=None, reps=3, **kw):
+    """Launch-parameter table for workload w (options as options(w, **kw)) written to
+    `path`; factors take it through options(..., tune_path=path)."""
+    load()
+    keep = _GeomKeep(w)
+    o = options(w, **kw)
+    n = len(w.angles) if nrhs is None else int(nrhs)
+    _check(_lib.pmx_autotune(C.byref(keep.g), C.byref(o), n, int(reps), str(path).encode(), _stream()))
+
+
+def read_tune_table(path):
+    """{(knob, real_bytes, a, b, c): choice} of a launch-parameter table."""
+    out = {}
+    for line in open(path):
+        line = line.split("#", 1)[0].split()
+        if len(line) == 6:
+            out[(line[0],) + tuple(int(v) for v in line[1:5])] = int(line[5])
+    return out
 
 
 def read_dataset(path):

@@ -128,3 +128,46 @@ def test_grid_assignment_one_centre_per_cell():
     w = W.config3(m=40, box=12.0, seed=5)
     ij = fast.grid_assignment(w.centers)
     assert len({tuple(r) for r in ij}) == w.m and ij.min() >= 0
+
+
+def _create_opts(w, **okw):
+    lib = pmx.load()
+    keep = pmx._GeomKeep(w)
+    o = pmx.options(w, **okw)
+    h = C.c_void_p()
+    st = lib.pmx_factor_create(C.byref(keep.g), C.byref(o), None, C.byref(h))
+    if st == 0:
+        lib.pmx_factor_destroy(h)
+    return st, lib.pmx_last_error().decode()
+
+
+def test_launch_table_is_validated_before_any_device_work(tmp_path):
+    """A launch-parameter table is read at create, before the first HIP call: a missing
+    file, a malformed line, an unknown knob and a key out of range are argument errors
+    that name the file and line."""
+    w = W.star_grid(2, n=64)
+    st, msg = _create_opts(w, tune_path=str(tmp_path / "missing.txt"))
+    assert st == 1 and "missing.txt" in msg
+    cases = {"bad.txt": ("lu_panel 8 2 1\n", ":1: malformed"),
+             "knob.txt": ("# comment\nwarp_size 8 0 0 0 64\n", ":2: unknown knob"),
+             "range.txt": ("cpqr 16 0 0 0 1\n", ":1: key out of range")}
+    for name, (text, want) in cases.items():
+        p = tmp_path / name
+        p.write_text(text)
+        st, msg = _create_opts(w, tune_path=str(p))
+        assert st == 1 and want in msg, (name, msg)
+
+
+def test_valid_launch_table_passes_validation(tmp_path):
+    """A well-formed table gets past the table check: on a machine without a GPU the call
+    then fails at its first HIP call, not with an argument error."""
+    import torch
+    p = tmp_path / "ok.txt"
+    p.write_text("# pmx launch-parameter table\nlu_panel 8 2 1 0 3  # 0:10 1:20 3:30\ngetrs 4 6 0 2 1\n"
+                 "apply_nr 8 15 2 0 4\napply_wg 8 15 2 0 1024\n")
+    st, msg = _create_opts(W.star_grid(2, n=64), tune_path=str(p))
+    if torch.cuda.is_available():
+        assert st == 0, msg
+    else:
+        assert st != 1, msg
+    assert pmx.read_tune_table(p)[("lu_panel", 8, 2, 1, 0)] == 3
