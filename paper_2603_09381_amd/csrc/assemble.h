@@ -131,7 +131,13 @@ void asm_build_l(const LDescT<R>* d, int batch, int max_s, int max_k, hipStream_
 void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s);
 // Dense FP64 operator apply between different inclusions (on the fly, exterior kernels),
 // for a block of right-hand sides in the density layout (ld = 2 n_nodes, per inclusion
-// [q; u]); partial sums of nsplit source ranges go to part [nsplit][nrhs][ld].
+// [q; u]).  Targets are taken in waves of 64 consecutive nodes.  Each wave has a sorted
+// list of "near" source inclusions: its own inclusions and every inclusion that may come
+// within k+ r < 24 of one of its targets (bounding circles).  The far kernel takes the
+// other inclusions of each of nsplit source ranges (whole inclusions, split_incl) with the
+// large-argument Hankel expansion; the near kernel takes the near lists (split in
+// nsplit_near parts), skipping pairs on the same inclusion.  Partial sums go to
+// part [nsplit + nsplit_near][nrhs][ld].
 struct ApplyArgs {
   const double *x, *y, *nx, *ny, *w;
   const int* owner;
@@ -143,13 +149,21 @@ struct ApplyArgs {
   int64_t ld;
   zd* part;
   double* pack;          // [apply_pack_size] packed source data of one group of right-hand sides
+  const int* near_off;   // [n_waves + 1]
+  const int* near_idx;   // near inclusions of each wave, ascending
+  const int* split_incl; // [nsplit + 1] first inclusion of each far source range
+  int nsplit_near;
 };
+// arguments at or above this value of k+ r use the large-argument expansion only
+#define PMX_APPLY_FAR_Z 24.0
 // source splits giving about wg_target workgroups per launch
 int apply_splits(int n_nodes, int wg_target);
+// near-list splits giving about wg_target one-wave workgroups per launch
+int apply_near_splits(int n_nodes, int wg_target);
 // doubles of the packed source data for groups of up to nr_max right-hand sides
 int64_t apply_pack_size(int n_nodes, int nr_max);
-// partial sums part[split] of the off-diagonal operator, right-hand sides in groups of
-// nr_max (1, 2, 4, 8) per thread
+// partial sums of the off-diagonal operator (far ranges, then near parts), right-hand
+// sides in groups of nr_max (1, 2, 4, 8) per thread
 void asm_apply_off(const ApplyArgs& a, int nsplit, int nr_max, hipStream_t s);
 // out = sf f + sa (ydiag + sum_p part[p]) elementwise over total entries (f may be NULL)
 void asm_apply_finish(const zd* f, const zd* ydiag, const zd* part, int nsplit, int64_t total, double sf, double sa,

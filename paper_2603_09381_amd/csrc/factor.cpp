@@ -1414,6 +1414,7 @@ GatherDescT<RD>* gather_to_leaf(const LeafMap& M, cx<RD>* leaf, int nrhs, Arena&
 // by batched MFMA products, the blocks between inclusions evaluated on the fly.
 struct DenseApply {
   int nrhs = -1, nsplit = 1, nblk = 1, nr_max = 8;
+  int nslots = 1;                 // partial-sum slots: nsplit far ranges + near parts
   int64_t total = 0;
   zd *ydiag = nullptr, *part = nullptr;
   double* d_norm = nullptr;
@@ -1423,6 +1424,85 @@ struct DenseApply {
   const zd* f = nullptr;
   zd* out = nullptr;
 };
+
+// Near lists of the dense apply: for each wave of 64 consecutive target nodes, the
+// inclusions that may come within k+ r < PMX_APPLY_FAR_Z of one of its targets (bounding
+// circles of the wave's nodes and of each inclusion), ascending; the wave's own
+// inclusions are always on it.  Candidates come from a uniform grid of the inclusion
+// centres whose spacing covers the largest possible reach.
+void apply_near_lists(pmx_factor* F, std::vector<int>& off, std::vector<int>& idx, hipStream_t s) {
+  std::vector<double> hx, hy;
+  download(hx, F->x, F->n_nodes, s);
+  download(hy, F->y, F->n_nodes, s);
+  const int m = F->m, N = F->n_nodes, nw = (N + 63) / 64;
+  auto circle = [&](int64_t b0, int64_t b1, double& cx, double& cy, double& r) {
+    double x0 = hx[b0], x1 = hx[b0], y0 = hy[b0], y1 = hy[b0];
+    for (int64_t b = b0; b < b1; ++b) {
+      x0 = std::min(x0, hx[b]);
+      x1 = std::max(x1, hx[b]);
+      y0 = std::min(y0, hy[b]);
+      y1 = std::max(y1, hy[b]);
+    }
+    cx = 0.5 * (x0 + x1);
+    cy = 0.5 * (y0 + y1);
+    double r2 = 0;
+    for (int64_t b = b0; b < b1; ++b) r2 = std::max(r2, (hx[b] - cx) * (hx[b] - cx) + (hy[b] - cy) * (hy[b] - cy));
+    r = std::sqrt(r2);
+  };
+  std::vector<double> ix(m), iy(m), ir(m), wx(nw), wy(nw), wr(nw);
+  double rimax = 0, rwmax = 0;
+  for (int j = 0; j < m; ++j) {
+    circle(F->node_off[j], F->node_off[j + 1], ix[j], iy[j], ir[j]);
+    rimax = std::max(rimax, ir[j]);
+  }
+  for (int w = 0; w < nw; ++w) {
+    circle(64 * (int64_t)w, std::min<int64_t>(64 * (int64_t)w + 64, N), wx[w], wy[w], wr[w]);
+    rwmax = std::max(rwmax, wr[w]);
+  }
+  // reach in distance, with a margin for the rounding of the kernels' z
+  const double reach = PMX_APPLY_FAR_Z / F->k_ext * (1.0 + 1e-9) + 1e-12;
+  const double h = reach + rimax + rwmax;
+  double gx0 = ix[0], gy0 = iy[0];
+  for (int j = 0; j < m; ++j) {
+    gx0 = std::min(gx0, ix[j]);
+    gy0 = std::min(gy0, iy[j]);
+  }
+  std::map<std::pair<int64_t, int64_t>, std::vector<int>> grid;
+  for (int j = 0; j < m; ++j)
+    grid[{(int64_t)std::floor((ix[j] - gx0) / h), (int64_t)std::floor((iy[j] - gy0) / h)}].push_back(j);
+  off.assign(nw + 1, 0);
+  idx.clear();
+  std::vector<int> cand;
+  for (int w = 0; w < nw; ++w) {
+    cand.clear();
+    const int64_t cxw = (int64_t)std::floor((wx[w] - gx0) / h), cyw = (int64_t)std::floor((wy[w] - gy0) / h);
+    for (int64_t dx = -1; dx <= 1; ++dx)
+      for (int64_t dy = -1; dy <= 1; ++dy) {
+        auto it = grid.find({cxw + dx, cyw + dy});
+        if (it == grid.end()) continue;
+        for (int j : it->second) {
+          const double d = std::hypot(wx[w] - ix[j], wy[w] - iy[j]);
+          if (d - wr[w] - ir[j] < reach) cand.push_back(j);
+        }
+      }
+    std::sort(cand.begin(), cand.end());
+    idx.insert(idx.end(), cand.begin(), cand.end());
+    off[w + 1] = (int)idx.size();
+  }
+}
+
+// first inclusion of each of (about) nsplit far source ranges of equal node counts
+std::vector<int> apply_split_incl(const pmx_factor* F, int nsplit) {
+  std::vector<int> b{0};
+  for (int sp = 1; sp < nsplit; ++sp) {
+    const int64_t target = (int64_t)F->n_nodes * sp / nsplit;
+    int j = (int)(std::lower_bound(F->node_off.begin(), F->node_off.end(), target) - F->node_off.begin());
+    j = std::min(j, F->m);
+    if (j > b.back() && j < F->m) b.push_back(j);
+  }
+  b.push_back(F->m);
+  return b;
+}
 
 void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vector<int>& incl,
                        const std::vector<int64_t>& doff, const zd* x, const zd* f, zd* out, DenseApply& D, Arena& A,
@@ -1435,9 +1515,14 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   D.nr_max = tune_choice(TK_APPLY_NR, 8, ta, tb, 0, 8, F->n_nodes, nrhs, 0);
   if (D.nr_max != 1 && D.nr_max != 2 && D.nr_max != 4 && D.nr_max != 8) D.nr_max = 8;
   const int wg = std::max(64, std::min(1 << 20, tune_choice(TK_APPLY_WG, 8, ta, tb, 0, 2048, F->n_nodes, nrhs, 0)));
-  D.nsplit = apply_splits(F->n_nodes, wg);
+  const std::vector<int> split = apply_split_incl(F, apply_splits(F->n_nodes, wg));
+  D.nsplit = (int)split.size() - 1;
+  std::vector<int> noff, nidx;
+  apply_near_lists(F, noff, nidx, s);
+  const int nnear = apply_near_splits(F->n_nodes, wg);
+  D.nslots = D.nsplit + nnear;
   D.ydiag = A.alloc<zd>(D.total);
-  D.part = A.alloc<zd>(D.total * D.nsplit);
+  D.part = A.alloc<zd>(D.total * D.nslots);
   D.nblk = (int)std::min<int64_t>(64, (N2 + 4095) / 4096);
   D.d_norm = A.alloc<double>((int64_t)D.nblk * nrhs);
   std::vector<GemmArgs> ga(incl.size());
@@ -1466,6 +1551,10 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   aa.ld = N2;
   aa.part = D.part;
   aa.pack = A.alloc<double>(apply_pack_size(F->n_nodes, 8));
+  aa.near_off = A.upload(noff, s);
+  aa.near_idx = A.upload(nidx, s);
+  aa.split_incl = A.upload(split, s);
+  aa.nsplit_near = nnear;
   D.f = f;
   D.out = out;
   D.nrhs = nrhs;
@@ -1475,9 +1564,9 @@ void launch_dense_apply(const DenseApply& D, hipStream_t s) {
   la_zgemm_list(OP_N, OP_N, D.d_ga, D.n_ga, D.max_s, D.nrhs, zmk(1, 0), zmk(0, 0), s);
   asm_apply_off(D.aa, D.nsplit, D.nr_max, s);
   if (D.f)
-    asm_apply_finish(D.f, D.ydiag, D.part, D.nsplit, D.total, 1.0, -1.0, D.out, s);
+    asm_apply_finish(D.f, D.ydiag, D.part, D.nslots, D.total, 1.0, -1.0, D.out, s);
   else
-    asm_apply_finish(nullptr, D.ydiag, D.part, D.nsplit, D.total, 0.0, 1.0, D.out, s);
+    asm_apply_finish(nullptr, D.ydiag, D.part, D.nslots, D.total, 0.0, 1.0, D.out, s);
 }
 
 // squared column norms of v (density layout, nrhs columns), partial sums on the device
@@ -1642,7 +1731,7 @@ void count_apply_work(pmx_factor* F, int nrhs) {
   }
   const double N2 = 2.0 * F->n_nodes;
   F->info.kernel_flops[PK_APPLY] += pairs * (130.0 + 32.0 * nrhs);
-  F->info.kernel_bytes[PK_APPLY] += 8.0 * 5 * F->n_nodes + 16.0 * N2 * nrhs * (1 + F->ss->apply.nsplit);
+  F->info.kernel_bytes[PK_APPLY] += 8.0 * 5 * F->n_nodes + 16.0 * N2 * nrhs * (1 + F->ss->apply.nslots);
 }
 
 // FP64 factor: right-hand side into the leaf vectors, one solve pass, solution to xout.
@@ -1948,10 +2037,16 @@ void tune_apply(pmx_factor* F, const TuneRecorder& rec, TuneTable& t, int reps, 
   double spent = 0, best = 1e300;
   int bi = 0;
   std::string note;
+  std::map<int, int*> splits;
   for (size_t c = 0; c < cand.size() && spent < budget_ms; ++c) {
-    const int ns = apply_splits(F->n_nodes, cand[c].second);
-    if (!parts.count(ns)) parts[ns] = tmp.alloc<zd>(D.total * ns);
-    aa.part = parts[ns];
+    const std::vector<int> split = apply_split_incl(F, apply_splits(F->n_nodes, cand[c].second));
+    const int ns = (int)split.size() - 1;
+    aa.nsplit_near = apply_near_splits(F->n_nodes, cand[c].second);
+    const int slots = ns + aa.nsplit_near;
+    if (!parts.count(slots)) parts[slots] = tmp.alloc<zd>(D.total * slots);
+    if (!splits.count(ns)) splits[ns] = tmp.upload(split, s);
+    aa.part = parts[slots];
+    aa.split_incl = splits[ns];
     double tbest = 1e300;
     for (int r = 0; r <= reps; ++r) {
       HIPCHK(hipEventRecord(e0, s));

@@ -86,7 +86,9 @@ template <class R>
 void la_getrf(const LuDescT<R>* d_lu, int batch, int max_n, int* d_info, hipStream_t s);
 // One panel step [j0, j0 + PMX_LU_NB) of the LU of every matrix with a given kernel:
 // 0 registers (256 threads x 1 row, <= 256 panel rows), 1 registers (256 x 2, <= 512),
-// 2 registers (512 x 2, <= 1024, FP32 only), 3 global memory (any size).
+// 2 registers (512 x 2, <= 1024, FP32 only), 3 global memory (any size); registers with
+// the column loop unrolled: 4 (256 x 1, <= 256), 6 (512 x 1, <= 512), 8 (1024 x 1,
+// <= 1024, FP32 only).
 template <class R>
 void la_lu_panel(int variant, const LuDescT<R>* d_lu, int batch, int j0, int* d_info, hipStream_t s);
 // Solve A X = B in place in B (n x nrhs per entry) using the LU of getrf.

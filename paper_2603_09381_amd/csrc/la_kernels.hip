@@ -109,22 +109,55 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-// argmax of (val, idx): larger val wins, ties go to the smaller index
+// argmax of (val, idx): larger val wins, ties go to the smaller index (evaluated without
+// branches)
 __device__ inline void argmax_pair(double& v, int& i, double v2, int i2) {
-  if (v2 > v || (v2 == v && i2 >= 0 && (i < 0 || i2 < i))) {
-    v = v2;
-    i = i2;
-  }
+  const bool take = (v2 > v) | ((v2 == v) & (i2 >= 0) & ((i < 0) | (i2 < i)));
+  v = take ? v2 : v;
+  i = take ? i2 : i;
+}
+
+// Argmax of (value, index) over the 64 lanes of a wave with DPP moves (larger value wins,
+// ties go to the smaller index, a total order, so the result does not depend on the
+// combination order); lanes a move does not reach keep their own pair.  Returned to
+// every lane through lane 63.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ inline void dpp_argmax_step(double& v, int& i) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xf, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xf, false);
+  const int i2 = __builtin_amdgcn_update_dpp(i, i, CTRL, ROWMASK, 0xf, false);
+  argmax_pair(v, i, __hiloint2double(hi2, lo2), i2);
+}
+
+__device__ inline void wave_argmax(double& v, int& i) {
+  dpp_argmax_step<0xB1>(v, i);        // quad_perm [1,0,3,2]
+  dpp_argmax_step<0x4E>(v, i);        // quad_perm [2,3,0,1]
+  dpp_argmax_step<0x141>(v, i);       // row_half_mirror
+  dpp_argmax_step<0x140>(v, i);       // row_mirror
+  dpp_argmax_step<0x142, 0xA>(v, i);  // row_bcast15 into rows 1 and 3
+  dpp_argmax_step<0x143, 0xC>(v, i);  // row_bcast31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  v = __hiloint2double(hi, lo);
+  i = __builtin_amdgcn_readlane(i, 63);
+}
+
+// value of lane l (uniform l) of every lane's v, as a scalar
+__device__ inline double readlane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline float readlane(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+template <class R>
+__device__ inline cx<R> readlane(cx<R> v, int l) {
+  return cmk<R>(readlane(v.re, l), readlane(v.im, l));
 }
 
 template <int NT>
 __device__ inline int block_argmax(double v, int i, double* redv, int* redi, double* outv) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    double v2 = __shfl_xor(v, o, 64);
-    int i2 = __shfl_xor(i, o, 64);
-    argmax_pair(v, i, v2, i2);
-  }
+  wave_argmax(v, i);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) {
@@ -277,47 +310,56 @@ struct TrsmArgs {
   int nb, nrhs;
 };
 
+// X = T^-1 B for a triangle T (nb <= 32, lower or upper, unit or not) and the columns of
+// B: one thread per column, held in registers with the loops over the triangle unrolled
+// (compile-time register indices); T and the inverses of its diagonal are read from LDS
+// at wave-uniform addresses.
 template <class R, bool UPPER, bool UNIT, class F>
 __global__ __launch_bounds__(64) void k_trsm_small(F f) {
   typedef cx<R> C;
   TrsmArgs<R> a;
   if (!f(blockIdx.y, a)) return;
-  __shared__ C Ts[32][33];
-  __shared__ C xs[32][64];
+  __shared__ C Ts[32][32];
+  __shared__ C dinv[32];
   const int tid = threadIdx.x;
-  const int col = blockIdx.x * 64 + tid;
   if (blockIdx.x * 64 >= a.nrhs) return;
-  for (int e = tid; e < a.nb * a.nb; e += 64) {
-    int r = e % a.nb, c = e / a.nb;
+  const int nb = a.nb;
+  for (int e = tid; e < nb * nb; e += 64) {
+    const int r = e % nb, c = e / nb;
     Ts[r][c] = a.T[r + (int64_t)c * a.ldt];
   }
+  if (!UNIT && tid < nb) dinv[tid] = zrecip(a.T[tid + (int64_t)tid * a.ldt]);
+  const int col = blockIdx.x * 64 + tid;
   const bool active = col < a.nrhs;
-  if (active) {
-#pragma unroll 8
-    for (int i = 0; i < a.nb; ++i) xs[i][tid] = a.B[i + (int64_t)col * a.ldb];
-  }
+  const int cl = active ? col : a.nrhs - 1;   // idle lanes follow the last column and store nothing
+  C x[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) x[i] = (i < nb) ? a.B[i + (int64_t)cl * a.ldb] : cmk<R>(0, 0);
   __syncthreads();
-  if (active) {
-    if (!UPPER) {
-      for (int i = 0; i < a.nb; ++i) {
-        C xi = xs[i][tid];
-        if (!UNIT) {
-          xi = zdiv(xi, Ts[i][i]);
-          xs[i][tid] = xi;
-        }
-        for (int r = i + 1; r < a.nb; ++r) xs[r][tid] = zsub(xs[r][tid], zmul(Ts[r][i], xi));
-      }
-    } else {
-      for (int i = a.nb - 1; i >= 0; --i) {
-        C xi = xs[i][tid];
-        if (!UNIT) {
-          xi = zdiv(xi, Ts[i][i]);
-          xs[i][tid] = xi;
-        }
-        for (int r = 0; r < i; ++r) xs[r][tid] = zsub(xs[r][tid], zmul(Ts[r][i], xi));
+  if (!UPPER) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      if (i < nb) {
+        if (!UNIT) x[i] = zmul(x[i], dinv[i]);
+#pragma unroll
+        for (int r = i + 1; r < 32; ++r)
+          if (r < nb) x[r] = zsub(x[r], zmul(Ts[r][i], x[i]));
       }
     }
-    for (int i = 0; i < a.nb; ++i) a.B[i + (int64_t)col * a.ldb] = xs[i][tid];
+  } else {
+#pragma unroll
+    for (int i = 31; i >= 0; --i) {
+      if (i < nb) {
+        if (!UNIT) x[i] = zmul(x[i], dinv[i]);
+#pragma unroll
+        for (int r = 0; r < i; ++r) x[r] = zsub(x[r], zmul(Ts[r][i], x[i]));
+      }
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+      if (i < nb) a.B[i + (int64_t)col * a.ldb] = x[i];
   }
 }
 
@@ -481,6 +523,99 @@ __global__ __launch_bounds__(NT) void k_getrf_panel_reg(const LuDescT<R>* lus, i
   }
 }
 
+// The panel step with the rows held in registers and the column loop unrolled, so that
+// every column index is a compile-time register index, and row exchanges made virtual:
+// each thread keeps its rows in place and tracks the row position pos they hold in the
+// exchanged order (the exchange of rows col and p swaps two positions, no data moves).
+// Per column: local candidates among positions >= col, a DPP wave argmax (ties to the
+// smaller position, as k_getrf_panel), wave maxima through LDS and a barrier; the pivot's
+// owner writes the pivot row's columns c.. to LDS, a barrier; every row at a position
+// below col is eliminated with it.  Each LDS buffer is rewritten only after the next
+// barrier, which every thread reaches after its reads.  At the end every row is written
+// at its position, which leaves the panel as after the explicit exchanges.
+template <class R, int NT, int RPT>
+__global__ __launch_bounds__(NT) void k_getrf_panel_u(const LuDescT<R>* lus, int j0, int* info) {
+  typedef cx<R> C;
+  constexpr int NB = PMX_LU_NB, NW = NT / 64;
+  const LuDescT<R> L = lus[blockIdx.x];
+  const int jb = min(NB, L.n - j0);
+  if (jb <= 0) return;
+  __shared__ double sv[NW];
+  __shared__ int si[NW];
+  __shared__ C prow[NB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  C* A = L.a;
+  const int64_t ld = L.ld;
+  C P[RPT][NB];
+  int pos[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int i = j0 + tid + NT * q;
+    pos[q] = i < L.n ? i : -1;   // -1: no row
+    const int ci = min(i, L.n - 1);
+#pragma unroll
+    for (int c = 0; c < NB; ++c) P[q][c] = A[ci + (int64_t)(j0 + min(c, jb - 1)) * ld];
+  }
+#pragma clang loop unroll(full)
+  for (int c = 0; c < NB; ++c) {
+    if (c >= jb) continue;   // uniform: the panel's last columns (no barrier is skipped by part of the block)
+    const int col = j0 + c;
+    double best = -1.0;
+    int bi = -1;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+      if (pos[q] >= col) argmax_pair(best, bi, fabs((double)P[q][c].re) + fabs((double)P[q][c].im), pos[q]);
+    wave_argmax(best, bi);
+    if (lane == 0) {
+      sv[wave] = best;
+      si[wave] = bi;
+    }
+    __syncthreads();
+    double bv = sv[0];
+    int p = si[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) argmax_pair(bv, p, sv[w], si[w]);
+    if (tid == 0) {
+      L.ipiv[col] = p;
+      if (bv == 0.0 && info && info[blockIdx.x] == 0) info[blockIdx.x] = col + 1;
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      if (pos[q] == p) {
+#pragma unroll
+        for (int cc = c; cc < NB; ++cc) prow[cc] = P[q][cc];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {   // exchange of positions col and p
+      const int pq = pos[q];
+      pos[q] = (pq == p) ? col : (pq == col ? p : pq);
+    }
+    const C piv = prow[c];
+    if (piv.re != R(0) || piv.im != R(0)) {
+      const C inv = zrecip(piv);
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        if (pos[q] > col) {
+          const C l = zmul(P[q][c], inv);
+          P[q][c] = l;
+#pragma unroll
+          for (int cc = c + 1; cc < NB; ++cc) P[q][cc] = zsub(P[q][cc], zmul(l, prow[cc]));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    if (pos[q] >= 0) {
+#pragma unroll
+      for (int cc = 0; cc < NB; ++cc)
+        if (cc < jb) A[pos[q] + (int64_t)(j0 + cc) * ld] = P[q][cc];
+    }
+  }
+}
+
 // apply the swaps of panel [j0, j0+jb) to the columns outside the panel
 template <class R>
 __global__ void k_laswp_panel(const LuDescT<R>* lus, int j0) {
@@ -569,6 +704,9 @@ static bool lu_panel_fits(int v, int rows) {
     case 1: return rows <= 512;
     case 2: return sizeof(R) == 4 && rows <= 1024;
     case 3: return true;
+    case 4: return rows <= 256;
+    case 6: return rows <= 512;
+    case 8: return sizeof(R) == 4 && rows <= 1024;
     default: return false;
   }
 }
@@ -588,6 +726,20 @@ void la_lu_panel(int variant, const LuDescT<R>* d_lu, int batch, int j0, int* d_
         hipLaunchKernelGGL((k_getrf_panel_reg<R, 512, 2>), dim3(batch), dim3(512), 0, s, d_lu, j0, d_info);
         break;
       }
+      hipLaunchKernelGGL(k_getrf_panel<R>, dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_getrf_panel_u<R, 256, 1>), dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      break;
+    case 6:
+      hipLaunchKernelGGL((k_getrf_panel_u<R, 512, 1>), dim3(batch), dim3(512), 0, s, d_lu, j0, d_info);
+      break;
+    case 8:
+      if (sizeof(R) == 4) {
+        hipLaunchKernelGGL((k_getrf_panel_u<float, 1024, 1>), dim3(batch), dim3(1024), 0, s,
+                           (const LuDescT<float>*)d_lu, j0, d_info);
+        break;
+      }
       [[fallthrough]];
     default:
       hipLaunchKernelGGL(k_getrf_panel<R>, dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
@@ -600,11 +752,11 @@ void la_getrf(const LuDescT<R>* d_lu, int batch, int max_n, int* d_info, hipStre
   if (batch <= 0 || max_n <= 0) return;
   for (int j0 = 0; j0 < max_n; j0 += PMX_LU_NB) {
     {
-      // panel rows max_n - j0: by default in registers when they fit without spilling (512
-      // rows, 1024 in FP32), else the global-memory kernel; a launch-parameter table may
-      // choose another variant that holds the rows
+      // panel rows max_n - j0: by default the unrolled register kernels when the rows fit
+      // one per thread (512 rows, 1024 in FP32), else the global-memory kernel; a
+      // launch-parameter table may choose another variant that holds the rows
       const int rows = max_n - j0;
-      const int dflt = rows <= 256 ? 0 : rows <= 512 ? 1 : (rows <= 1024 && sizeof(R) == 4) ? 2 : 3;
+      const int dflt = rows <= 256 ? 4 : rows <= 512 ? 6 : (rows <= 1024 && sizeof(R) == 4) ? 8 : 3;
       int v = tune_choice(TK_LU_PANEL, (int)sizeof(R), tune_bucket_size(rows), tune_bucket_batch(batch), 0, dflt,
                           rows, batch, 0);
       if (!lu_panel_fits<R>(v, rows)) v = dflt;
@@ -796,7 +948,7 @@ __global__ __launch_bounds__(GS_NT) void k_getrs_small(const LuDescT<R>* lus, co
         C x = (lane < jb) ? W.p[j0 + lane + (int64_t)(c0 + c) * W.ld] : cmk<R>(0, 0);
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
-          const C xk = cmk<R>(__shfl(x.re, k, 64), __shfl(x.im, k, 64));
+          const C xk = readlane(x, k);
           if (lane > k && k < jb) x = zsub(x, zmul(lrow[k], xk));
         }
         if (lane < jb) {
@@ -823,7 +975,7 @@ __global__ __launch_bounds__(GS_NT) void k_getrs_small(const LuDescT<R>* lus, co
         for (int k = 31; k >= 0; --k) {
           if (k < jb) {
             if (lane == k) x = zdiv(x, urow[k]);
-            const C xk = cmk<R>(__shfl(x.re, k, 64), __shfl(x.im, k, 64));
+            const C xk = readlane(x, k);
             if (lane < k) x = zsub(x, zmul(urow[k], xk));
           }
         }
@@ -1305,7 +1457,7 @@ __device__ inline void cp_apply_column(cx<R>* col, const cx<R>* vs, int j, int m
     else first = nv;
   }
   // norm downdating with recomputation on cancellation
-  const double fr = __shfl((double)first.re, 0, 64), fi = __shfl((double)first.im, 0, 64);
+  const double fr = readlane((double)first.re, 0), fi = readlane((double)first.im, 0);
   const double nw2 = nrm[l] - (fr * fr + fi * fi);
   if (nw2 <= cp_recompute_ratio<R>() * nrm[c + l]) {
     tail = wave_sum(tail);

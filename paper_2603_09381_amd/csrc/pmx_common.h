@@ -61,6 +61,16 @@ __host__ __device__ inline cx<R> zdiv(cx<R> a, cx<R> b) {
     return cmk<R>((a.re * r + a.im) / d, (a.im * r - a.re) / d);
   }
 }
+// 1 / b by Smith's algorithm (the quotients of zdiv with a = 1, one division for both)
+template <class R>
+__host__ __device__ inline cx<R> zrecip(cx<R> b) {
+  if (fabs(b.re) >= fabs(b.im)) {
+    const R r = b.im / b.re, t = R(1) / (b.re + b.im * r);
+    return cmk<R>(t, -r * t);
+  }
+  const R r = b.re / b.im, t = R(1) / (b.re * r + b.im);
+  return cmk<R>(r * t, -t);
+}
 template <class R>
 __host__ __device__ inline cx<R> zfma(cx<R> a, cx<R> b, cx<R> c) {  // a*b + c
   return cmk<R>(fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im)));

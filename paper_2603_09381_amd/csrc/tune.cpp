@@ -129,6 +129,9 @@ void tune_candidates(int knob, int rb, int64_t d0, int64_t d1, int64_t d2, int* 
       if (d0 <= 512) out[(*n)++] = 1;
       if (rb == 4 && d0 <= 1024) out[(*n)++] = 2;
       out[(*n)++] = 3;
+      if (d0 <= 256) out[(*n)++] = 4;
+      if (d0 <= 512) out[(*n)++] = 6;
+      if (rb == 4 && d0 <= 1024) out[(*n)++] = 8;
       break;
     case TK_CPQR:
       out[(*n)++] = 0;
@@ -350,10 +353,10 @@ std::string tune_linear_algebra(const TuneRecorder& rec, TuneTable& t, int reps,
     if (knob != TK_LU_PANEL && knob != TK_CPQR && knob != TK_GETRS) continue;
     const int64_t d0 = kv.second[0], d1 = kv.second[1], d2 = kv.second[2];
     if (d0 <= 0 || d1 <= 0) continue;
-    int cand[8], nc = 0;
+    int cand[16], nc = 0;
     tune_candidates(knob, rb, d0, d1, d2, cand, &nc);
     if (nc < 2) continue;
-    double us[8];
+    double us[16];
     std::string e;
     if (knob == TK_LU_PANEL)
       e = rb == 8 ? time_lu_panel<double>(d0, d1, cand, nc, us, reps, s) : time_lu_panel<float>(d0, d1, cand, nc, us, reps, s);

@@ -79,17 +79,34 @@ def test_id_fp32(pmx, m, c):
         assert 0.6 ** k < 1e2 * tol and 0.6 ** max(k - 8, 0) > tol * 1e-2, k
 
 
-@pytest.mark.parametrize("g,n,k", [(2, 64, 10.0), (3, 48, 10.0), (4, 48, 45.0)])
-def test_dense_apply_against_oracle(pmx, g, n, k):
+@pytest.mark.parametrize("g,n,k,nrhs", [(2, 64, 10.0, 3), (3, 48, 10.0, 3), (4, 48, 45.0, 3), (2, 64, 1.0, 1),
+                                        (3, 48, 30.0, 5), (4, 64, 60.0, 16)])
+def test_dense_apply_against_oracle(pmx, g, n, k, nrhs):
     """k = 45 on a 4x4 grid puts k r between about 20 and 190: every branch of the apply's
-    Hankel evaluation (series, Chebyshev, 20-, 16- and 12-term expansions)."""
+    Hankel evaluation (near pairs: series, Chebyshev, 20-term expansion; far pairs: 20-,
+    16- and 12-term expansions).  k = 1 makes every inclusion near every wave; 432 nodes
+    (3 x 48) leave a partial last wave; 5 and 16 right-hand sides take groups of 4 + 1 and
+    8 + 8."""
     w = W.star_grid(g, n=n, k_ext=k, k_int=1.5 * k, seed=5)
     A = dense.assemble(dense.Geometry(w))
-    x = crandn(w.n_unknowns, 3)
+    x = crandn(w.n_unknowns, nrhs)
     ref = A @ x
     got = pmx.probe_apply(w, x)
     err = np.abs(got - ref).max() / np.abs(ref).max()
     print("dense apply rel err", err)
+    assert err < 1e-12
+
+
+def test_dense_apply_scattered_uneven(pmx):
+    """Scattered inclusions with uneven node counts: waves straddle inclusions of different
+    sizes and the near lists come from bounding circles of mixed radii."""
+    w = W.config3(m=14, box=7.0, seed=3)
+    A = dense.assemble(dense.Geometry(w))
+    x = crandn(w.n_unknowns, 4)
+    ref = A @ x
+    got = pmx.probe_apply(w, x)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("scattered dense apply rel err", err, "nodes", w.n_unknowns // 2)
     assert err < 1e-12
 
 
