@@ -8,7 +8,7 @@ are host inputs; densities stay in HBM).
 Forms, both held to a relative residual of 1e-10 / field error of 1e-8:
   plain: FP64 throughout, ID tolerance 1e-10;
   tuned: the factor in complex FP32 (FP32 MFMA QR, LU and Schur products, FP64 pivots) at
-         ID tolerance 1e-5, refined against the FP64 operator (dense on-the-fly apply) to
+         ID tolerance 1e-4, refined against the FP64 operator (dense on-the-fly apply) to
          a relative residual of 1e-10; solves replay captured HIP graphs.
 `value` is the tuned form's unknowns per second over the timed steps.  The roofline object
 covers the tuned form's dominant kernel (found in the warm-up steps, which time every
@@ -40,7 +40,7 @@ TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = {"k_ts_update": ("la_kernels.hip", "la.h"), "k_ts_leaf": ("la_kernels.hip", "la.h"),
                   "k_getrf_panel": ("la_kernels.hip", "la.h"), "k_apply_off": ("apply_kernels.hip", "assemble.h")}
 FORMS = {"plain": dict(precision=0, id_tol=1e-10),
-         "tuned": dict(precision=1, id_tol=1e-5, ir_tol=1e-10, solve_graph=1)}
+         "tuned": dict(precision=1, id_tol=1e-4, ir_tol=1e-10, solve_graph=1)}
 
 
 def parse():
