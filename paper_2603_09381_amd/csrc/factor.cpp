@@ -56,20 +56,74 @@ struct PmxErr {
 
 void fail(pmx_status st, const std::string& msg) { throw PmxErr{st, msg}; }
 
-// Device allocations owned by one object, released together.
+// Device blocks kept for reuse within one factorisation: the per-level temporaries of the
+// factorisation are released level by level; giving their blocks back to hipFree would
+// synchronise the device each time, and hipMalloc them anew costs host time.  Blocks come
+// in size classes of one eighth of an octave (at least 256 bytes) and are reused only by
+// later work of the same stream (the factorisation's), so stream order protects them.
+// Host staging buffers of uploads are kept as well (an asynchronous copy may still read
+// them).  Everything is freed when the pool is destroyed, after the stream is idle.
+class DevPool {
+ public:
+  ~DevPool() {
+    for (auto& kv : free_)
+      for (void* p : kv.second) (void)hipFree(p);
+  }
+  static size_t size_class(size_t n) {
+    if (n <= 256) return 256;
+    size_t oct = 1;
+    while (oct * 2 <= n) oct *= 2;
+    const size_t step = std::max<size_t>(oct / 8, 256);
+    return (n + step - 1) / step * step;
+  }
+  void* get(size_t n) {
+    const size_t c = size_class(n);
+    auto it = free_.find(c);
+    if (it != free_.end() && !it->second.empty()) {
+      void* p = it->second.back();
+      it->second.pop_back();
+      return p;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, c) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
+  }
+  void put(void* p, size_t n) { free_[size_class(n)].push_back(p); }
+  void retire(std::vector<std::vector<char>>& host) {
+    for (auto& h : host) retired_.push_back(std::move(h));
+    host.clear();
+  }
+
+ private:
+  std::map<size_t, std::vector<void*>> free_;
+  std::vector<std::vector<char>> retired_;
+};
+
+// Device allocations owned by one object, released together (to a pool when it has one).
 class Arena {
  public:
+  Arena() = default;
+  explicit Arena(DevPool* pool) : pool_(pool) {}
   ~Arena() { release(); }
   template <class T>
   T* alloc(size_t n) {
     if (n == 0) n = 1;
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, n * sizeof(T));
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      fail(PMX_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    if (pool_) {
+      p = pool_->get(n * sizeof(T));
+      if (!p) fail(PMX_ENOMEM, "device allocation of " + std::to_string(n * sizeof(T)) + " bytes failed");
+    } else {
+      hipError_t e = hipMalloc(&p, n * sizeof(T));
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(PMX_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+      }
     }
     ptrs_.push_back(p);
+    sizes_.push_back(n * sizeof(T));
     bytes_ += n * sizeof(T);
     return (T*)p;
   }
@@ -85,15 +139,23 @@ class Arena {
     return p;
   }
   void release() {
-    for (void* p : ptrs_) (void)hipFree(p);
+    if (pool_) {
+      for (size_t i = 0; i < ptrs_.size(); ++i) pool_->put(ptrs_[i], sizes_[i]);
+      pool_->retire(keep_);
+    } else {
+      for (void* p : ptrs_) (void)hipFree(p);
+    }
     ptrs_.clear();
+    sizes_.clear();
     keep_.clear();
     bytes_ = 0;
   }
   double bytes() const { return (double)bytes_; }
 
  private:
+  DevPool* pool_ = nullptr;
   std::vector<void*> ptrs_;
+  std::vector<size_t> sizes_;
   std::vector<std::vector<char>> keep_;
   size_t bytes_ = 0;
 };
@@ -191,6 +253,8 @@ struct Tier {
 struct SolveState;
 
 struct pmx_factor {
+  // reuse of the factorisation's temporary device blocks (declared first: destroyed last)
+  DevPool pool;
   // geometry (device)
   int m = 0, n_nodes = 0;
   double k_ext = 0, eps_ext = 1;
@@ -644,7 +708,7 @@ void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>&
                     hipStream_t s) {
   const int nc = L.ncell;
   const double tol = F->opts.id_tol;
-  Arena tmp;
+  Arena tmp(&F->pool);
   ProxyTable PT = make_proxies(tmp, cells, s);
   // ---- the four interpolative decompositions of every cell (learned proposals first at
   // the leaves when a model is loaded, the full CPQR for every cell they do not settle)
@@ -1062,7 +1126,7 @@ void factor_all(pmx_factor* F, hipStream_t s) {
   L0.ipiv = F->arena.alloc<int>(L0.tot_s);
   L0.perm = F->arena.alloc<int>(L0.tot_s);
   {
-    Arena tmp;
+    Arena tmp(&F->pool);
     if (F->opts.precision == 0) {
       assemble_diag(F, tmp, incl, (zd*)L0.D, L0.offD, s);
     } else {
@@ -1079,7 +1143,7 @@ void factor_all(pmx_factor* F, hipStream_t s) {
   LevelData<R> cur = std::move(L0);
   for (size_t lv = 0; lv < plan.size(); ++lv) {
     if (lv > 0) {
-      Arena tmp;
+      Arena tmp(&F->pool);
       LevelData<R> nxt;
       merge_level(F, T.lev.back(), plan[lv], nxt, tmp, s);
       sync_check(s);
@@ -1096,7 +1160,7 @@ void factor_all(pmx_factor* F, hipStream_t s) {
       T.root_cols = cur.cols;
       std::vector<LuDescT<R>> lu{LuDescT<R>{T.Droot, T.root_s, T.root_s, T.ipiv_root, T.perm_root}};
       T.d_lu_root = F->arena.upload(lu, s);
-      Arena tmp;
+      Arena tmp(&F->pool);
       int* d_info = tmp.alloc<int>(1);
       HIPCHK(hipMemsetAsync(d_info, 0, sizeof(int), s));
       la_getrf(T.d_lu_root, 1, T.root_s, d_info, s);
