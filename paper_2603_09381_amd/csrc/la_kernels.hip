@@ -1064,13 +1064,14 @@ __device__ inline int ts_phys(int lr, int L, int jb, int j0, const TsGeom& g) {
 }
 
 // One block of one tree level: Householder QR of its rows of the panel, entirely in LDS.
-// Columns are owned cyclically by the four waves (column q by wave q % 4), each lane
-// holding rows lane + 64k; a column's dot products are reduced inside its owner wave, so a
-// step costs two barriers: the owner of column i forms the reflector, then every wave
+// Columns are owned cyclically by the NT / 64 waves (column q by wave q % (NT / 64)), each
+// lane holding rows lane + 64k; a column's dot products are reduced inside its owner wave,
+// so a step costs two barriers: the owner of column i forms the reflector, then every wave
 // applies it to its own columns and forms its share of the compact-WY inner products.
-// The Householder norm is accumulated in FP64 for both real types.
-template <class R>
-__global__ __launch_bounds__(PMX_TS_BR) void k_ts_leaf(const QrDescT<R>* qrs, int j0, int L) {
+// More waves share the columns of a step among more SIMDs for the same LDS.  The
+// Householder norm is accumulated in FP64 for both real types.
+template <class R, int NT>
+__global__ __launch_bounds__(NT) void k_ts_leaf(const QrDescT<R>* qrs, int j0, int L) {
   typedef cx<R> C;
   const QrDescT<R> Q = qrs[blockIdx.y];
   const int kmax = Q.kc;
@@ -1082,7 +1083,7 @@ __global__ __launch_bounds__(PMX_TS_BR) void k_ts_leaf(const QrDescT<R>* qrs, in
   const int b = blockIdx.x;
   if (b >= ts_sel(L, g.nb0, g.nb1, g.nb2, g.nb3)) return;
   const int nrb = min(PMX_TS_BR, ts_sel(L, g.mr0, g.mr1, g.mr2, g.mr3) - b * PMX_TS_BR);
-  constexpr int NW = PMX_TS_BR / 64;           // waves
+  constexpr int NW = NT / 64;                  // waves
   constexpr int RPL = PMX_TS_BR / 64;          // rows per lane
   __shared__ C Ps[PMX_QR_NB][PMX_TS_BR];       // panel block, column major; R above, V below
   __shared__ C vs[PMX_TS_BR];                  // current reflector
@@ -1093,7 +1094,7 @@ __global__ __launch_bounds__(PMX_TS_BR) void k_ts_leaf(const QrDescT<R>* qrs, in
   const int phys = (t < nrb) ? ts_phys(b * PMX_TS_BR + t, L, jb, j0, g) : -1;
   C* A = Q.a;
   const int64_t ld = Q.ld;
-  {
+  if (t < PMX_TS_BR) {
     const int pr = phys >= 0 ? phys : j0;
     C tmpv[PMX_QR_NB];
 #pragma unroll
@@ -1199,6 +1200,7 @@ __global__ __launch_bounds__(PMX_TS_BR) void k_ts_leaf(const QrDescT<R>* qrs, in
   if (phys >= 0 && t < jb) {
     for (int i = 0; i < jb; ++i) A[phys + (int64_t)(j0 + i) * ld] = (i >= t) ? Ps[i][t] : cmk<R>(0, 0);
   }
+  if (t >= PMX_TS_BR) return;
   const int64_t wo = ts_sel64(L, g.wo0, g.wo1, g.wo2, g.wo3) + (int64_t)b * PMX_TS_BR * PMX_QR_NB;
   C* V = Q.v + wo;
   C* VT = Q.t + wo;
@@ -1380,6 +1382,10 @@ void la_geqrf_r(const QrDescT<R>* d_qr, int batch, int max_m, int max_c, hipStre
   const int64_t cap = (int64_t)PMX_TS_BR * (PMX_TS_BR / PMX_QR_NB) * (PMX_TS_BR / PMX_QR_NB) * (PMX_TS_BR / PMX_QR_NB);
   if (max_m > cap) return;
   const int kmax = min(max_m, max_c);
+  // threads per leaf block: built-in 512, or the launch-parameter table's choice for the
+  // shape of this call
+  const int v = tune_choice(TK_TS_LEAF, (int)sizeof(R), tune_bucket_size(max_m), tune_bucket_batch(batch),
+                            tune_bucket_size(max_c), 512, max_m, batch, max_c);
   for (int j0 = 0; j0 < kmax; j0 += PMX_QR_NB) {
     int mr = max_m - j0;
     const int nc = max_c - j0 - 1;
@@ -1387,7 +1393,13 @@ void la_geqrf_r(const QrDescT<R>* d_qr, int batch, int max_m, int max_c, hipStre
       const int nb = (mr + PMX_TS_BR - 1) / PMX_TS_BR;
       {
         KScope ks(PK_TS_LEAF, s);
-        hipLaunchKernelGGL(k_ts_leaf<R>, dim3(nb, batch), dim3(PMX_TS_BR), 0, s, d_qr, j0, L);
+        if (v == 1024 && sizeof(R) == 4)   // FP64 spills at 1024 threads
+          hipLaunchKernelGGL((k_ts_leaf<float, 1024>), dim3(nb, batch), dim3(1024), 0, s,
+                             (const QrDescT<float>*)d_qr, j0, L);
+        else if (v == 256)
+          hipLaunchKernelGGL((k_ts_leaf<R, 256>), dim3(nb, batch), dim3(256), 0, s, d_qr, j0, L);
+        else
+          hipLaunchKernelGGL((k_ts_leaf<R, 512>), dim3(nb, batch), dim3(512), 0, s, d_qr, j0, L);
       }
       if (nc > 0) {
         KScope ks(PK_TS_UPDATE, s);

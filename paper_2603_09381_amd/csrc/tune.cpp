@@ -17,7 +17,7 @@ thread_local TuneRecorder* g_tune_rec = nullptr;
 thread_local TuneForce g_tune_force;
 
 namespace {
-const char* const kKnobNames[TK_COUNT] = {"lu_panel", "cpqr", "getrs", "apply_nr", "apply_wg"};
+const char* const kKnobNames[TK_COUNT] = {"lu_panel", "cpqr", "getrs", "apply_nr", "apply_wg", "ts_leaf"};
 const int64_t kSizeBounds[] = {64, 128, 256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192, 12288, 16384};
 }  // namespace
 
@@ -147,6 +147,10 @@ void tune_candidates(int knob, int rb, int64_t d0, int64_t d1, int64_t d2, int* 
       break;
     case TK_APPLY_WG:
       for (int v : {512, 1024, 2048, 4096, 8192}) out[(*n)++] = v;
+      break;
+    case TK_TS_LEAF:
+      for (int v : {256, 512, 1024})
+        if (v < 1024 || rb == 4) out[(*n)++] = v;
       break;
     default:
       break;
@@ -338,6 +342,32 @@ std::string time_getrs(int64_t n, int64_t batch, int64_t nrhs, const int* cand, 
   return hipGetLastError() == hipSuccess ? "" : "a tuning launch failed";
 }
 
+template <class R>
+std::string time_qr(int64_t m, int64_t batch, int64_t c, const int* cand, int nc, double* us, int reps, hipStream_t s) {
+  Bufs B;
+  const int64_t kc = std::min(m, c), ws = la_geqrf_workspace((int)m);
+  cx<R>* a = B.get<cx<R>>(m * c * batch);
+  cx<R>* r = B.get<cx<R>>(kc * c * batch);
+  cx<R>* v = B.get<cx<R>>(ws * batch);
+  cx<R>* t = B.get<cx<R>>(ws * batch);
+  if (!B.err.empty()) return B.err;
+  std::vector<QrDescT<R>> d(batch);
+  for (int64_t b = 0; b < batch; ++b)
+    d[b] = QrDescT<R>{a + b * m * c, m, (int)m, (int)c, r + b * kc * c, v + b * ws, t + b * ws, (int)kc};
+  QrDescT<R>* dd = B.put(d, s);
+  if (!B.err.empty()) return B.err;
+  Timer T;
+  const TuneForce saved = g_tune_force;
+  for (int i = 0; i < nc; ++i) {
+    g_tune_force = TuneForce{TK_TS_LEAF, cand[i]};
+    us[i] = T.best_us(
+        reps, s, [&] { fill<R>(a, m, c, batch, 0x5eed0005ull, 0.0, 0.0, s); },
+        [&] { la_geqrf_r<R>(dd, (int)batch, (int)m, (int)c, s); });
+  }
+  g_tune_force = saved;
+  return hipGetLastError() == hipSuccess ? "" : "a tuning launch failed";
+}
+
 std::string note_of(const int* cand, const double* us, int nc) {
   std::ostringstream o;
   for (int i = 0; i < nc; ++i) o << (i ? " " : "") << cand[i] << ':' << (int64_t)std::llround(us[i]);
@@ -350,7 +380,7 @@ std::string tune_linear_algebra(const TuneRecorder& rec, TuneTable& t, int reps,
   for (const auto& kv : rec.dims) {
     int knob, rb, a, b, c;
     tune_unkey(kv.first, knob, rb, a, b, c);
-    if (knob != TK_LU_PANEL && knob != TK_CPQR && knob != TK_GETRS) continue;
+    if (knob != TK_LU_PANEL && knob != TK_CPQR && knob != TK_GETRS && knob != TK_TS_LEAF) continue;
     const int64_t d0 = kv.second[0], d1 = kv.second[1], d2 = kv.second[2];
     if (d0 <= 0 || d1 <= 0) continue;
     int cand[16], nc = 0;
@@ -362,6 +392,8 @@ std::string tune_linear_algebra(const TuneRecorder& rec, TuneTable& t, int reps,
       e = rb == 8 ? time_lu_panel<double>(d0, d1, cand, nc, us, reps, s) : time_lu_panel<float>(d0, d1, cand, nc, us, reps, s);
     else if (knob == TK_CPQR)
       e = rb == 8 ? time_cpqr<double>(d0, d1, cand, nc, us, reps, s) : time_cpqr<float>(d0, d1, cand, nc, us, reps, s);
+    else if (knob == TK_TS_LEAF)
+      e = rb == 8 ? time_qr<double>(d0, d1, d2, cand, nc, us, reps, s) : time_qr<float>(d0, d1, d2, cand, nc, us, reps, s);
     else
       e = rb == 8 ? time_getrs<double>(d0, d1, d2, cand, nc, us, reps, s)
                   : time_getrs<float>(d0, d1, d2, cand, nc, us, reps, s);

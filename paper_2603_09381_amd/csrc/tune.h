@@ -27,7 +27,9 @@ enum TuneKnob : int {
   TK_APPLY_NR = 3,  // dense operator apply by nodes, right-hand sides: right-hand sides per
                     // thread group (1, 2, 4 or 8)
   TK_APPLY_WG = 4,  // dense operator apply: workgroups a launch aims at (source splits)
-  TK_COUNT = 5
+  TK_TS_LEAF = 5,   // Householder QR by rows, batch, columns: threads per leaf block (256, 512,
+                    // 1024 in FP32)
+  TK_COUNT = 6
 };
 
 const char* tune_knob_name(int knob);
@@ -71,7 +73,7 @@ std::string tune_load(const std::string& path, TuneTable& t);
 // Candidate choices of a knob for a recorded shape (d0, d1, d2) and real type size rb.
 void tune_candidates(int knob, int rb, int64_t d0, int64_t d1, int64_t d2, int* out, int* n);
 
-// Times the candidates of every recorded LU-panel, CPQR and level-solve key on device
+// Times the candidates of every recorded LU-panel, CPQR, level-solve and QR key on device
 // buffers of the recorded shape (a fixed seeded fill), best of `reps` runs each, and
 // stores the fastest in t.  Returns an error text, empty on success.
 std::string tune_linear_algebra(const TuneRecorder& rec, TuneTable& t, int reps, hipStream_t s);

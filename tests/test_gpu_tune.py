@@ -16,7 +16,7 @@ from paper_2603_09381_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 VALID = {"lu_panel": {0, 1, 2, 3, 4, 6, 8}, "cpqr": {0, 1}, "getrs": {0, 1}, "apply_nr": {1, 2, 4, 8},
-         "apply_wg": {512, 1024, 2048, 4096, 8192}}
+         "apply_wg": {512, 1024, 2048, 4096, 8192}, "ts_leaf": {256, 512, 1024}}
 FORMS = {0: dict(precision=0, id_tol=1e-10), 1: dict(precision=1, id_tol=1e-5, ir_tol=1e-10),
          2: dict(precision=2, id_tol=1e-6, ir_tol=1e-10)}
 BOUND = {0: 5e-9, 1: 1e-8, 2: 1e-8}
