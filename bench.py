@@ -38,7 +38,8 @@ PEAK_TFS = {("mfma", 8): 78.6, ("mfma", 4): 157.3, ("alu", 8): 78.6, ("alu", 4):
 COUNTED = {"k_ts_update": "mfma", "k_ts_leaf": "alu", "k_getrf_panel": "alu", "k_apply_off": "alu"}
 TRAFFIC_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = {"k_ts_update": ("la_kernels.hip", "la.h"), "k_ts_leaf": ("la_kernels.hip", "la.h"),
-                  "k_getrf_panel": ("la_kernels.hip", "la.h"), "k_apply_off": ("apply_kernels.hip", "assemble.h")}
+                  "k_getrf_panel": ("la_kernels.hip", "la.h"),
+                  "k_apply_off": ("apply_kernels.hip", "assemble.h", "hankel_fast.h", "bessel.h")}
 FORMS = {"plain": dict(precision=0, id_tol=1e-10),
          "tuned": dict(precision=1, id_tol=1e-4, ir_tol=1e-10, solve_graph=1)}
 
@@ -160,29 +161,36 @@ def roofline(info_list, k, top, names, real_bytes, workload_tag):
     return roof
 
 
+# timer slots that cover several kernels launched back to back (summed per launch)
+SLOT_KERNELS = {"k_apply_off": ("k_apply_far", "k_apply_near")}
+
+
 def summarize_pmc(fetch_csv, write_csv, kname, workload_tag):
     """HBM bytes per launch of `kname` from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE,
     KiB per dispatch), each scaled by what the same counter reads for the 256 MiB device
     copy that --copy-calibration runs first (expected 256 MiB fetched and 256 MiB written).
     `kname` may carry template arguments ("k_ts_update<double>") to pick one instantiation;
-    the summary is stored under the plain name."""
+    a timer slot of several kernels (k_apply_off: far and near parts) sums the mean of each
+    part.  The summary is stored under the plain name."""
     import csv
     base = kname.split("<")[0]
+    parts = SLOT_KERNELS.get(kname, (kname,))
 
-    def matches(name):
-        if "<" in kname:
-            return name.startswith("void " + kname)
-        return name.startswith(kname + "(") or name.startswith("void " + kname + "<")
+    def matches(name, part):
+        if "<" in part:
+            return name.startswith("void " + part)
+        return name.startswith(part + "(") or name.startswith("void " + part + "<")
 
     def load(path, counter):
-        per, copy = [], []
+        per, copy = {p: [] for p in parts}, []
         for r in csv.DictReader(open(path)):
             if r["Counter_Name"] != counter:
                 continue
             v = float(r["Counter_Value"]) * 1024.0
             name = r["Kernel_Name"]
-            if matches(name):
-                per.append(v)
+            hit = [p for p in parts if matches(name, p)]
+            if hit:
+                per[hit[0]].append(v)
             elif name.startswith("__amd_rocclr_copyBuffer") and not copy:
                 copy.append(v)   # the first runtime copy of the run: the 256 MiB calibration copy
         return per, copy
@@ -192,10 +200,12 @@ def summarize_pmc(fetch_csv, write_csv, kname, workload_tag):
     ref = float(256 << 20)
     ff = cf[0] / ref if cf else 1.0
     fw = cw[0] / ref if cw else 1.0
-    per_launch = (np.mean(fetch) / ff + np.mean(write) / fw)
-    out = {"kernel": base, "instantiation": kname, "workload": workload_tag, "source_hash": kernel_source_hash(base),
-           "bytes_per_launch": per_launch, "launches": len(fetch), "fetch_scale": ff, "write_scale": fw,
-           "fetch_bytes_per_launch": np.mean(fetch) / ff, "write_bytes_per_launch": np.mean(write) / fw}
+    fb = sum(np.mean(fetch[p]) for p in parts) / ff
+    wb = sum(np.mean(write[p]) for p in parts) / fw
+    out = {"kernel": base, "instantiation": kname, "parts": list(parts), "workload": workload_tag,
+           "source_hash": kernel_source_hash(base), "bytes_per_launch": fb + wb,
+           "launches": len(fetch[parts[0]]), "fetch_scale": ff, "write_scale": fw,
+           "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb}
     json.dump(out, open(traffic_file(base, workload_tag), "w"), indent=1)
     print(json.dumps(out))
 
