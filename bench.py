@@ -10,6 +10,8 @@ Forms, both held to a relative residual of 1e-10 / field error of 1e-8:
   tuned: the factor in complex FP32 (FP32 MFMA QR, LU and Schur products, FP64 pivots) at
          ID tolerance 1e-4, refined against the FP64 operator (dense on-the-fly apply) to
          a relative residual of 1e-10; solves replay captured HIP graphs.
+Before the timed steps each form gets a launch-parameter table from the library's autotuner
+(pmx_autotune on this workload; --no-autotune keeps the built-in rules).
 `value` is the tuned form's unknowns per second over the timed steps.  The roofline object
 covers the tuned form's dominant kernel (found in the warm-up steps, which time every
 kernel; in the timed steps HIP events bracket that kernel's launches only), with the
@@ -56,6 +58,8 @@ def parse():
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a 256 MiB device copy first (reference kernel for HBM counters)")
     p.add_argument("--no-timing", action="store_true", help="no HIP events around kernels")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="built-in launch rules instead of a launch-parameter table tuned before the timed steps")
     return p.parse_args()
 
 
@@ -265,7 +269,19 @@ def main():
     N = w.n_unknowns
     tag = f"stars{a.grid}"   # traffic summaries are per form: <tag>_tuned, <tag>_plain
     timing = 0 if a.no_timing else 1
-    times, infos, dens, dom = run_form(pmx, w, FORMS["tuned"], a.steps, a.warmup, timing)
+    forms = {k: dict(v) for k, v in FORMS.items()}
+    tune_s = {}
+    if not a.no_autotune:
+        # launch-parameter tables for this GPU and workload, built before (outside) the timed steps
+        import tempfile
+        tdir = tempfile.mkdtemp(prefix="pmx_tune_")
+        for name in ("tuned", "plain") if not a.no_plain else ("tuned",):
+            path = os.path.join(tdir, f"{name}.txt")
+            t0 = time.perf_counter()
+            pmx.autotune(w, path, reps=2, **forms[name])
+            tune_s[name] = time.perf_counter() - t0
+            forms[name]["tune_path"] = path
+    times, infos, dens, dom = run_form(pmx, w, forms["tuned"], a.steps, a.warmup, timing)
     total = sum(times)
     info = infos[-1]
     res = {"metric": METRIC, "value": N * a.steps / total, "unit": "unknowns/s", "n_gpus": 1,
@@ -275,7 +291,10 @@ def main():
            "config": {"workload": f"{a.grid}x{a.grid} rotated stars, 128 nodes, k+=10, k-=15, 4 plane waves",
                       "n_unknowns": N, "nrhs": len(w.angles), "tuned": FORMS["tuned"], "plain": FORMS["plain"],
                       "root_size": info.root_size, "levels": info.levels,
-                      "refinement_steps": info.ir_iterations, "final_relative_residual": info.ir_residual}}
+                      "refinement_steps": info.ir_iterations, "final_relative_residual": info.ir_residual,
+                      "launch_table": ("autotuned before the timed steps, s: " +
+                                       ", ".join(f"{k} {v:.1f}" for k, v in tune_s.items())) if tune_s
+                                      else "built-in rules"}}
     if timing:
         res["roofline"] = roofline(infos, dom[0], dom[1], pmx.KERNEL_NAMES, 4, tag + "_tuned")
         res["kernel_time_share"] = dom[2]
@@ -285,7 +304,7 @@ def main():
         rel, ed = accuracy(w, pmx.dens_to_numpy(dens, w))
         res["accuracy"] = {"sampled_row_rel_residual": rel, "max_energy_defect": ed}
     if not a.no_plain:
-        ptimes, pinfos, pdens, pdom = run_form(pmx, w, FORMS["plain"], a.steps, a.warmup, timing)
+        ptimes, pinfos, pdens, pdom = run_form(pmx, w, forms["plain"], a.steps, a.warmup, timing)
         ptotal = sum(ptimes)
         plain = {"value": N * a.steps / ptotal, "ms_per_step": 1e3 * ptotal / a.steps,
                  "root_size": pinfos[-1].root_size}

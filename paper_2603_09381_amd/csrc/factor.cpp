@@ -1573,12 +1573,12 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
                        hipStream_t s) {
   const int64_t N2 = 2 * (int64_t)F->n_nodes;
   D.total = N2 * nrhs;
-  // right-hand sides per thread and workgroups per launch: built-in 8 and 2048, or the
+  // right-hand sides per thread and workgroups per launch: built-in 8 and 8192, or the
   // launch-parameter table's choice for this node count and right-hand-side count
   const int ta = tune_bucket_pow2(F->n_nodes), tb = tune_bucket_pow2(nrhs);
   D.nr_max = tune_choice(TK_APPLY_NR, 8, ta, tb, 0, 8, F->n_nodes, nrhs, 0);
   if (D.nr_max != 1 && D.nr_max != 2 && D.nr_max != 4 && D.nr_max != 8) D.nr_max = 8;
-  const int wg = std::max(64, std::min(1 << 20, tune_choice(TK_APPLY_WG, 8, ta, tb, 0, 2048, F->n_nodes, nrhs, 0)));
+  const int wg = std::max(64, std::min(1 << 20, tune_choice(TK_APPLY_WG, 8, ta, tb, 0, 8192, F->n_nodes, nrhs, 0)));
   const std::vector<int> split = apply_split_incl(F, apply_splits(F->n_nodes, wg));
   D.nsplit = (int)split.size() - 1;
   std::vector<int> noff, nidx;
@@ -2080,10 +2080,10 @@ void tune_apply(pmx_factor* F, const TuneRecorder& rec, TuneTable& t, int reps, 
   int cnr[8], nnr = 0, cwg[8], nwg = 0;
   tune_candidates(TK_APPLY_NR, 8, F->n_nodes, D.nrhs, 0, cnr, &nnr);
   tune_candidates(TK_APPLY_WG, 8, F->n_nodes, D.nrhs, 0, cwg, &nwg);
-  std::vector<std::pair<int, int>> cand{{8, 2048}};
+  std::vector<std::pair<int, int>> cand{{8, 8192}};
   for (int i = 0; i < nnr; ++i)
     for (int j = 0; j < nwg; ++j)
-      if (!(cnr[i] == 8 && cwg[j] == 2048)) cand.push_back({cnr[i], cwg[j]});
+      if (!(cnr[i] == 8 && cwg[j] == 8192)) cand.push_back({cnr[i], cwg[j]});
   Arena tmp;
   std::map<int, zd*> parts;
   hipEvent_t e0, e1;
