@@ -44,14 +44,17 @@ pmx_status pmx_probe_cgemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32
 
 /* LU with partial pivoting of a batch of n x n matrices (device, in place) and solve with
  * nrhs right-hand sides B [batch][n x nrhs] (device, in place).  ipiv (device) [batch][n].
- * info (host) [batch]: first zero pivot (1-based) or 0.  Up to 64 right-hand sides take the
- * fused substitution kernel of the solves, more the blocked one of the factorisation. */
+ * info (host) [batch]: first zero pivot (1-based) or 0.  variant selects the solve kernel:
+ * 0 the fused substitution of the solves (<= 64 right-hand sides), 1 the blocked solve of
+ * the factorisation, 2 the fused substitution with the solution in LDS (n x 4 complex
+ * <= 128 KiB), -1 the solves' built-in rule; a variant that does not hold the shape falls
+ * back to the built-in rule. */
 pmx_status pmx_probe_lu_solve(int32_t batch, int32_t n, pmx_c64* A, int32_t* ipiv, int32_t nrhs,
-                              pmx_c64* B, int32_t* info, void* stream);
+                              pmx_c64* B, int32_t* info, int32_t variant, void* stream);
 
 /* As pmx_probe_lu_solve in complex FP32. */
 pmx_status pmx_probe_lu_solve_c32(int32_t batch, int32_t n, pmx_c32* A, int32_t* ipiv, int32_t nrhs,
-                                  pmx_c32* B, int32_t* info, void* stream);
+                                  pmx_c32* B, int32_t* info, int32_t variant, void* stream);
 
 /* Interpolative decomposition of a batch of m x c matrices (device, destroyed): QR, then
  * column-pivoted QR with threshold rank |R_jj| > tol |R_11|; k = max(rank, kmin[b]) pivots

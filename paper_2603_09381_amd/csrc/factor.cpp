@@ -1377,13 +1377,28 @@ void build_program(pmx_factor* F, int nrhs, hipStream_t s) {
   P.nrhs = nrhs;
 }
 
-// level solves of `batch` LU factors of size <= n: the fused kernel (few right-hand
-// sides) or the blocked one, by default the fused one up to PMX_GETRS_SMALL_MAX
+// level solves of `batch` LU factors of size <= n: 0 the fused kernel (few right-hand
+// sides), 1 the blocked one, 2 the LDS-resident one; by default 2 when its LDS block fits,
+// else 0 up to PMX_GETRS_SMALL_MAX right-hand sides, else 1
 template <class R>
-bool getrs_fused(int n, int batch, int nrhs) {
-  const int v = tune_choice(TK_GETRS, (int)sizeof(R), tune_bucket_size(n), tune_bucket_batch(batch),
-                            tune_bucket_pow2(nrhs), nrhs <= PMX_GETRS_SMALL_MAX ? 0 : 1, n, batch, nrhs);
-  return v == 0 && nrhs <= PMX_GETRS_SMALL_MAX;
+int getrs_variant(int n, int batch, int nrhs) {
+  const bool lds_ok = la_getrs_lds_bytes(n, (int)sizeof(R)) <= 128 * 1024;
+  const int dflt = lds_ok ? 2 : (nrhs <= PMX_GETRS_SMALL_MAX ? 0 : 1);
+  int v = tune_choice(TK_GETRS, (int)sizeof(R), tune_bucket_size(n), tune_bucket_batch(batch), tune_bucket_pow2(nrhs),
+                      dflt, n, batch, nrhs);
+  if ((v == 2 && !lds_ok) || (v == 0 && nrhs > PMX_GETRS_SMALL_MAX) || v < 0 || v > 2) v = dflt;
+  return v;
+}
+
+template <class R>
+void level_getrs(const LuDescT<R>* d_lu, const MatT<R>* d_bm, const MatT<R>* d_w, int batch, int n, int nrhs,
+                 hipStream_t s) {
+  const int v = getrs_variant<R>(n, batch, nrhs);
+  if (v == 2 && la_getrs_lds(d_lu, d_bm, batch, n, nrhs, s)) return;
+  if (v == 0)
+    la_getrs_small(d_lu, d_bm, d_w, batch, n, nrhs, s);
+  else
+    la_getrs(d_lu, d_bm, batch, n, nrhs, s);
 }
 
 // the launches of one solve pass on the leaf vectors P.leaf (in place); no host work
@@ -1397,10 +1412,7 @@ void launch_program(pmx_factor* F, hipStream_t s) {
   for (int l = 0; l < nl; ++l) {
     const LevelData<R>& L = T.lev[l];
     SolveLevel<R>& S = P.lv[l];
-    if (getrs_fused<R>(L.max_s, L.ncell, nrhs))
-      la_getrs_small(L.d_lu, S.d_bm, S.d_w, L.ncell, L.max_s, nrhs, s);
-    else
-      la_getrs(L.d_lu, S.d_bm, L.ncell, L.max_s, nrhs, s);
+    level_getrs(L.d_lu, S.d_bm, S.d_w, L.ncell, L.max_s, nrhs, s);
     asm_gather(S.F, S.d_up, S.n_up, S.max_up, nrhs, s);
     if (S.n_ga) la_zgemm_list(OP_N, OP_N, S.d_ga, S.n_ga, L.max_k, nrhs, one, one, s);
     asm_convert(S.G, S.Ry, S.tot_k * nrhs, s);
@@ -1409,10 +1421,7 @@ void launch_program(pmx_factor* F, hipStream_t s) {
     (void)top;
     asm_gather(S.G, S.d_par, S.n_par, S.max_par, nrhs, s);
   }
-  if (getrs_fused<R>(T.root_s, 1, nrhs))
-    la_getrs_small(T.d_lu_root, P.d_bm_root, P.d_w_root, 1, T.root_s, nrhs, s);
-  else
-    la_getrs(T.d_lu_root, P.d_bm_root, 1, T.root_s, nrhs, s);
+  level_getrs(T.d_lu_root, P.d_bm_root, P.d_w_root, 1, T.root_s, nrhs, s);
   for (int l = nl - 1; l >= 0; --l) {
     const LevelData<R>& L = T.lev[l];
     SolveLevel<R>& S = P.lv[l];
@@ -1946,10 +1955,11 @@ void probe_gemm(int batch, int m, int n, int k, int opa, int opb, const cx<R>* A
 }
 
 template <class R>
-void probe_lu(int batch, int n, cx<R>* A, int* ipiv, int nrhs, cx<R>* B, int* info, hipStream_t s) {
-  if (batch <= 0 || n <= 0 || nrhs < 0 || !A || !ipiv || (nrhs > 0 && !B) || !info) fail(PMX_EINVAL, "bad arguments");
+void probe_lu(int batch, int n, cx<R>* A, int* ipiv, int nrhs, cx<R>* B, int* info, int variant, hipStream_t s) {
+  if (batch <= 0 || n <= 0 || nrhs < 0 || !A || !ipiv || (nrhs > 0 && !B) || !info || variant < -1 || variant > 2)
+    fail(PMX_EINVAL, "bad arguments");
   Arena tmp;
-  const bool small = nrhs > 0 && nrhs <= PMX_GETRS_SMALL_MAX;
+  const bool small = nrhs > 0;
   int* perm = small ? tmp.alloc<int>((int64_t)batch * n) : nullptr;
   cx<R>* work = small ? tmp.alloc<cx<R>>((int64_t)batch * n * nrhs) : nullptr;
   std::vector<LuDescT<R>> lu(batch);
@@ -1963,12 +1973,18 @@ void probe_lu(int batch, int n, cx<R>* A, int* ipiv, int nrhs, cx<R>* B, int* in
   int* d_info = tmp.alloc<int>(batch);
   HIPCHK(hipMemsetAsync(d_info, 0, batch * sizeof(int), s));
   la_getrf<R>(d_lu, batch, n, d_info, s);
-  // few right-hand sides: the fused solve of the solve passes; more: the blocked solve of
-  // the factorisation
-  if (small)
-    la_getrs_small<R>(d_lu, tmp.upload(bm, s), tmp.upload(wm, s), batch, n, nrhs, s);
-  else if (nrhs > 0)
-    la_getrs<R>(d_lu, tmp.upload(bm, s), batch, n, nrhs, s);
+  if (nrhs > 0) {
+    const MatT<R>* d_bm = tmp.upload(bm, s);
+    const MatT<R>* d_wm = tmp.upload(wm, s);
+    if (variant < 0) {
+      level_getrs<R>(d_lu, d_bm, d_wm, batch, n, nrhs, s);
+    } else {
+      TuneForce saved = g_tune_force;
+      g_tune_force = TuneForce{TK_GETRS, variant};
+      level_getrs<R>(d_lu, d_bm, d_wm, batch, n, nrhs, s);
+      g_tune_force = saved;
+    }
+  }
   std::vector<int> hi;
   download(hi, d_info, batch, s);
   std::copy(hi.begin(), hi.end(), info);
@@ -2391,13 +2407,15 @@ pmx_status pmx_probe_cgemm(int32_t batch, int32_t m, int32_t n, int32_t k, int32
 }
 
 pmx_status pmx_probe_lu_solve(int32_t batch, int32_t n, pmx_c64* A, int32_t* ipiv, int32_t nrhs, pmx_c64* B,
-                              int32_t* info, void* stream) {
-  return guarded([&] { probe_lu<double>(batch, n, (zd*)A, ipiv, nrhs, (zd*)B, info, (hipStream_t)stream); });
+                              int32_t* info, int32_t variant, void* stream) {
+  return guarded(
+      [&] { probe_lu<double>(batch, n, (zd*)A, ipiv, nrhs, (zd*)B, info, variant, (hipStream_t)stream); });
 }
 
 pmx_status pmx_probe_lu_solve_c32(int32_t batch, int32_t n, pmx_c32* A, int32_t* ipiv, int32_t nrhs, pmx_c32* B,
-                                  int32_t* info, void* stream) {
-  return guarded([&] { probe_lu<float>(batch, n, (zf*)A, ipiv, nrhs, (zf*)B, info, (hipStream_t)stream); });
+                                  int32_t* info, int32_t variant, void* stream) {
+  return guarded(
+      [&] { probe_lu<float>(batch, n, (zf*)A, ipiv, nrhs, (zf*)B, info, variant, (hipStream_t)stream); });
 }
 
 pmx_status pmx_probe_id(int32_t batch, int32_t m, int32_t c, pmx_c64* M, double tol, const int32_t* kmin,

@@ -98,6 +98,13 @@ void la_getrs(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max_n, 
 // workgroup per matrix and group of right-hand sides running the permutation and both
 // substitutions; needs LuDesc::perm and a workspace per entry (w[b].p, n x nrhs, ld >= n).
 #define PMX_GETRS_SMALL_MAX 64
+// The same with each workgroup's solution block (max_n x 4 right-hand sides) in LDS, any
+// number of right-hand sides (4 per workgroup); returns false, launching nothing, when the
+// block exceeds 128 KiB.
+template <class R>
+bool la_getrs_lds(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max_n, int max_nrhs, hipStream_t s);
+// LDS bytes la_getrs_lds needs for max_n rows
+inline size_t la_getrs_lds_bytes(int max_n, int real_bytes) { return (size_t)max_n * 4 * 2 * real_bytes; }
 template <class R>
 void la_getrs_small(const LuDescT<R>* d_lu, const MatT<R>* d_b, const MatT<R>* d_w, int batch, int max_n,
                     int max_nrhs, hipStream_t s);

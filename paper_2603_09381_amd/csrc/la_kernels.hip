@@ -991,6 +991,148 @@ __global__ __launch_bounds__(GS_NT) void k_getrs_small(const LuDescT<R>* lus, co
   }
 }
 
+// The same solve with the whole solution block x (n x NRC) held in LDS: no global round
+// trips for x between the steps, diagonal blocks of BS rows (one lane per row, solved
+// values broadcast by readlane), and NT threads so that every thread has about one row
+// of each trailing update, whose BS factors it loads in two halves.  Rows beyond n and
+// right-hand sides beyond the matrix's count are padded with zeros and not stored.
+template <class R, int NRC, int NT, int BS>
+__global__ __launch_bounds__(NT) void k_getrs_lds(const LuDescT<R>* lus, const MatT<R>* bs) {
+  typedef cx<R> C;
+  constexpr int HB = BS / 2;
+  const LuDescT<R> L = lus[blockIdx.x];
+  const MatT<R> B = bs[blockIdx.x];
+  const int n = L.n;
+  const int c0 = blockIdx.y * NRC;
+  const int nc = min(NRC, B.n - c0);
+  if (n <= 0 || nc <= 0) return;
+  extern __shared__ char gs_smem[];
+  C* xs = reinterpret_cast<C*>(gs_smem);   // xs[c * n + i]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const C* A = L.a;
+  const int64_t ld = L.ld;
+  for (int e = tid; e < n * NRC; e += NT) {
+    const int i = e % n, c = e / n;
+    xs[e] = (c < nc) ? B.p[L.perm[i] + (int64_t)(c0 + c) * B.ld] : cmk<R>(0, 0);
+  }
+  __syncthreads();
+  // forward: L unit lower
+  for (int j0 = 0; j0 < n; j0 += BS) {
+    const int jb = min(BS, n - j0);
+    if (wave < NRC) {
+      const int r = j0 + min(lane, jb - 1);
+      C lrow[BS];
+#pragma unroll
+      for (int k = 0; k < BS; ++k) lrow[k] = A[r + (int64_t)(j0 + min(k, jb - 1)) * ld];
+      C x = (lane < jb) ? xs[wave * n + j0 + lane] : cmk<R>(0, 0);
+#pragma unroll
+      for (int k = 0; k < BS; ++k) {
+        const C xk = readlane(x, k);
+        if (lane > k && k < jb) x = zsub(x, zmul(lrow[k], xk));
+      }
+      if (lane < jb) xs[wave * n + j0 + lane] = x;
+    }
+    __syncthreads();
+    for (int i = j0 + jb + tid; i < n; i += NT) {
+      C acc[NRC];
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) acc[c] = xs[c * n + i];
+#pragma unroll
+      for (int h = 0; h < BS; h += HB) {
+        C l[HB];
+#pragma unroll
+        for (int k = 0; k < HB; ++k) l[k] = A[i + (int64_t)(j0 + min(h + k, jb - 1)) * ld];
+#pragma unroll
+        for (int k = 0; k < HB; ++k)
+          if (h + k < jb) {
+#pragma unroll
+            for (int c = 0; c < NRC; ++c) acc[c] = zsub(acc[c], zmul(l[k], xs[c * n + j0 + h + k]));
+          }
+      }
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) xs[c * n + i] = acc[c];
+    }
+    __syncthreads();
+  }
+  // backward: U upper with its diagonal
+  for (int j0 = ((n - 1) / BS) * BS; j0 >= 0; j0 -= BS) {
+    const int jb = min(BS, n - j0);
+    if (wave < NRC) {
+      const int r = j0 + min(lane, jb - 1);
+      C urow[BS];
+#pragma unroll
+      for (int k = 0; k < BS; ++k) urow[k] = A[r + (int64_t)(j0 + min(k, jb - 1)) * ld];
+      C dinv = urow[0];
+#pragma unroll
+      for (int k = 1; k < BS; ++k)
+        if (k == lane) dinv = urow[k];
+      dinv = zrecip(dinv);
+      C x = (lane < jb) ? xs[wave * n + j0 + lane] : cmk<R>(0, 0);
+#pragma unroll
+      for (int k = BS - 1; k >= 0; --k) {
+        if (k < jb) {
+          if (lane == k) x = zmul(x, dinv);
+          const C xk = readlane(x, k);
+          if (lane < k) x = zsub(x, zmul(urow[k], xk));
+        }
+      }
+      if (lane < jb) xs[wave * n + j0 + lane] = x;
+    }
+    __syncthreads();
+    for (int i = tid; i < j0; i += NT) {
+      C acc[NRC];
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) acc[c] = xs[c * n + i];
+#pragma unroll
+      for (int h = 0; h < BS; h += HB) {
+        C l[HB];
+#pragma unroll
+        for (int k = 0; k < HB; ++k) l[k] = A[i + (int64_t)(j0 + min(h + k, jb - 1)) * ld];
+#pragma unroll
+        for (int k = 0; k < HB; ++k)
+          if (h + k < jb) {
+#pragma unroll
+            for (int c = 0; c < NRC; ++c) acc[c] = zsub(acc[c], zmul(l[k], xs[c * n + j0 + h + k]));
+          }
+      }
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) xs[c * n + i] = acc[c];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * nc; e += NT) {
+    const int i = e % n, c = e / n;
+    B.p[i + (int64_t)(c0 + c) * B.ld] = xs[c * n + i];
+  }
+}
+
+// LDS-resident level solve for up to 4 right-hand sides per workgroup; false when the
+// solution block does not fit (the caller then uses another variant)
+template <class R>
+bool la_getrs_lds(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max_n, int max_nrhs, hipStream_t s) {
+  constexpr int NRC = 4;
+  const size_t shm = (size_t)max_n * NRC * sizeof(cx<R>);
+  if (shm > 128 * 1024 || max_n <= 0) return false;
+  constexpr int BS = sizeof(R) == 4 ? 64 : 32;
+  const dim3 grid(batch, (max_nrhs + NRC - 1) / NRC);
+  KScope ks(PK_GETRS, s);
+  if (max_n <= 256) {
+    auto k = k_getrs_lds<R, NRC, 256, BS>;
+    if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k, grid, dim3(256), shm, s, d_lu, d_b);
+  } else if (max_n <= 512) {
+    auto k = k_getrs_lds<R, NRC, 512, BS>;
+    if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k, grid, dim3(512), shm, s, d_lu, d_b);
+  } else {
+    // 1024 threads leave 128 registers each: half the diagonal block
+    auto k = k_getrs_lds<R, NRC, 1024, BS / 2>;
+    if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k, grid, dim3(1024), shm, s, d_lu, d_b);
+  }
+  return true;
+}
+
 template <class R>
 void la_getrs_small(const LuDescT<R>* d_lu, const MatT<R>* d_b, const MatT<R>* d_w, int batch, int max_n,
                     int max_nrhs, hipStream_t s) {
@@ -1945,6 +2087,7 @@ void la_getrf_work(int n, int real_bytes, double* bytes, double* flops) {
   template void la_lu_panel<R>(int, const LuDescT<R>*, int, int, int*, hipStream_t);                         \
   template void la_getrs<R>(const LuDescT<R>*, const MatT<R>*, int, int, int, hipStream_t);                  \
   template void la_getrs_small<R>(const LuDescT<R>*, const MatT<R>*, const MatT<R>*, int, int, int, hipStream_t); \
+  template bool la_getrs_lds<R>(const LuDescT<R>*, const MatT<R>*, int, int, int, hipStream_t);                \
   template void la_geqrf_r<R>(const QrDescT<R>*, int, int, int, hipStream_t);                                \
   template void la_cpqr<R>(const CpqrDescT<R>*, int, int, double, const int*, int, int*, hipStream_t);       \
   template void la_cpqr_tsolve<R>(const CpqrDescT<R>*, const int*, int, int, int, hipStream_t);             \

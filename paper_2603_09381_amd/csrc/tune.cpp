@@ -137,9 +137,10 @@ void tune_candidates(int knob, int rb, int64_t d0, int64_t d1, int64_t d2, int* 
       out[(*n)++] = 0;
       out[(*n)++] = 1;
       break;
-    case TK_GETRS:      // d2: right-hand sides
+    case TK_GETRS:      // d0: size, d2: right-hand sides
       if (d2 <= PMX_GETRS_SMALL_MAX) out[(*n)++] = 0;
       out[(*n)++] = 1;
+      if (la_getrs_lds_bytes((int)d0, rb) <= 128 * 1024) out[(*n)++] = 2;
       break;
     case TK_APPLY_NR:   // d1: right-hand sides
       for (int v : {1, 2, 4, 8})
@@ -334,6 +335,7 @@ std::string time_getrs(int64_t n, int64_t batch, int64_t nrhs, const int* cand, 
     us[i] = T.best_us(
         reps, s, [&] { fill<R>(rhs, n, nrhs, batch, 0x5eed0004ull, 0.0, 0.0, s); },
         [&] {
+          if (cand[i] == 2 && la_getrs_lds<R>(dd, db, (int)batch, (int)n, (int)nrhs, s)) return;
           if (cand[i] == 0)
             la_getrs_small<R>(dd, db, dw, (int)batch, (int)n, (int)nrhs, s);
           else

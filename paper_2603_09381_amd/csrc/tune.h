@@ -23,7 +23,8 @@ enum TuneKnob : int {
                     // 1 multi-workgroup steps
   TK_GETRS = 2,     // level LU solves by size, batch, right-hand sides: 0 one fused kernel per
                     // cell (<= 64 right-hand sides), 1 blocked (row swaps, triangular blocks, MFMA
-                    // updates)
+                    // updates), 2 one fused kernel per cell and 4 right-hand sides with the
+                    // solution in LDS (size x 4 x complex <= 128 KiB)
   TK_APPLY_NR = 3,  // dense operator apply by nodes, right-hand sides: right-hand sides per
                     // thread group (1, 2, 4 or 8)
   TK_APPLY_WG = 4,  // dense operator apply: workgroups a launch aims at (source splits)

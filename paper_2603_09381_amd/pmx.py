@@ -106,10 +106,10 @@ def load(path=None):
     ip = C.POINTER(C.c_int32)
     lib.pmx_probe_entries.argtypes = [C.POINTER(Geometry), C.c_int32, ip, ip, C.c_int32, ip, ip, vp, vp]
     lib.pmx_probe_zgemm.argtypes = [C.c_int32] * 6 + [vp, vp, vp, vp]
-    lib.pmx_probe_lu_solve.argtypes = [C.c_int32, C.c_int32, vp, vp, C.c_int32, vp, ip, vp]
+    lib.pmx_probe_lu_solve.argtypes = [C.c_int32, C.c_int32, vp, vp, C.c_int32, vp, ip, C.c_int32, vp]
     lib.pmx_probe_id.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, C.c_double, ip, vp, ip, vp, vp]
     lib.pmx_probe_cgemm.argtypes = [C.c_int32] * 6 + [vp, vp, vp, vp]
-    lib.pmx_probe_lu_solve_c32.argtypes = [C.c_int32, C.c_int32, vp, vp, C.c_int32, vp, ip, vp]
+    lib.pmx_probe_lu_solve_c32.argtypes = [C.c_int32, C.c_int32, vp, vp, C.c_int32, vp, ip, C.c_int32, vp]
     lib.pmx_probe_id_c32.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, C.c_double, ip, vp, ip, vp, vp]
     lib.pmx_probe_apply.argtypes = [C.POINTER(Geometry), C.c_int32, vp, vp, vp]
     fp = C.POINTER(C.c_float)
@@ -317,7 +317,7 @@ def probe_zgemm(A, B, opa=0, opb=0, fp32=False):
     return Ct.transpose(-1, -2).cpu().numpy()
 
 
-def probe_lu_solve(A, B, fp32=False):
+def probe_lu_solve(A, B, fp32=False, variant=-1):
     import torch
     load()
     ct = _ctype(fp32)
@@ -329,7 +329,7 @@ def probe_lu_solve(A, B, fp32=False):
     info = np.zeros(batch, np.int32)
     fn = _lib.pmx_probe_lu_solve_c32 if fp32 else _lib.pmx_probe_lu_solve
     _check(fn(batch, n, C.c_void_p(At.data_ptr()), C.c_void_p(piv.data_ptr()), nrhs,
-              C.c_void_p(Bt.data_ptr()), _ptr(info, C.c_int32), _stream()))
+              C.c_void_p(Bt.data_ptr()), _ptr(info, C.c_int32), int(variant), _stream()))
     return (At.transpose(-1, -2).cpu().numpy(), piv.cpu().numpy(), Bt.transpose(-1, -2).cpu().numpy(), info)
 
 

@@ -42,12 +42,13 @@ def test_cgemm_fp32(pmx, opa, opb, m, n, k):
     assert np.abs(got - ref).max() < 4e-7 * np.sqrt(max(k, 1)) * scale
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (31, 3), (100, 40), (257, 7), (120, 70)])
-def test_lu_solve_fp32(pmx, n, nrhs):
+@pytest.mark.parametrize("variant", [-1, 0, 1, 2])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (31, 3), (100, 40), (257, 7), (120, 70), (1000, 4), (600, 6)])
+def test_lu_solve_fp32(pmx, n, nrhs, variant):
     batch = 3
     A = c64(crandn(batch, n, n) + 2 * np.sqrt(n) * np.eye(n))
     B = c64(crandn(batch, n, nrhs))
-    _, _, X, info = pmx.probe_lu_solve(A, B, fp32=True)
+    _, _, X, info = pmx.probe_lu_solve(A, B, fp32=True, variant=variant)
     assert (info == 0).all()
     ref = np.linalg.solve(A, B)
     # backward stable: residual of the FP32 solution ~ n u32 |A| |x|

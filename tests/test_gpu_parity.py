@@ -46,13 +46,17 @@ def test_zgemm(pmx, opa, opb, m, n, k):
     assert np.abs(got - ref).max() < 1e-13 * scale * max(1, k)
 
 
+@pytest.mark.parametrize("variant", [-1, 0, 1, 2])
 @pytest.mark.parametrize("n,nrhs", [(1, 1), (31, 3), (64, 1), (100, 40), (257, 7), (33, 5), (100, 80),
-                                    (300, 65), (1100, 4)])
-def test_lu_solve(pmx, n, nrhs):
+                                    (300, 65), (1100, 4), (700, 9)])
+def test_lu_solve(pmx, n, nrhs, variant):
+    """Every level-solve kernel: fused substitution, blocked, LDS-resident (FP64: 32-row
+    diagonal blocks, 16 above 512 rows; ragged tails; 4 right-hand sides per workgroup,
+    so 9 leaves a partial group), and the built-in choice."""
     batch = 4
     A = crandn(batch, n, n) + 2 * np.sqrt(n) * np.eye(n)
     B = crandn(batch, n, nrhs)
-    _, piv, X, info = pmx.probe_lu_solve(A, B)
+    _, piv, X, info = pmx.probe_lu_solve(A, B, variant=variant)
     assert (info == 0).all()
     ref = np.linalg.solve(A, B)
     assert np.abs(X - ref).max() < 1e-11 * max(1.0, np.abs(ref).max())
