@@ -1,5 +1,5 @@
-// Dense FP64 application of the PMCHWT (Omit) Nystrom operator, evaluated on the fly, for
-// the residual r = f - A x of iterative refinement (arXiv 2603.09381, Sec. 2.2 system).
+// Dense FP64 application of the PMCHWT (Omit) Nystrom operator for the residual
+// r = f - A x of iterative refinement (arXiv 2603.09381, Sec. 2.2 system).
 //
 // The self blocks A_ii are applied as a batched FP64 MFMA product with the stored Kress
 // blocks.  The blocks between different inclusions use only k+ and the source's trapezoid
@@ -9,16 +9,27 @@
 //   der += (i/4) [ k (n_t.d/r) H1 q~ + (k/e+) (k a H0 + b H1) u~ ],
 // a = (n_t.d)(n_s.d)/r^2, b = (n_t.n_s - 2 a)/r, d = x_t - x_s: the four operators S, D,
 // D*, N of Sec. 2.1 written out.  One thread owns one target node and NR right-hand
-// sides; sources are read with wave-uniform (scalar) loads, in a far kernel (pairs with
-// k+ r >= 24, large-argument expansion only) over source ranges and a near kernel over
-// each wave's near inclusions; partial sums are reduced by a third kernel in a fixed
-// order.
+// sides.
+//
+// Near inclusions (see ApplyArgs) are summed pair by pair with those formulas.  Every other
+// inclusion j acts through Graf's addition theorem about its centre c: for |y - c| <
+// |x - c|, H0(k|x - y|) = sum_n H_n(k rho_x) e^{i n th_x} J_n(k rho_y) e^{-i n th_y}, so
+// with R_n(y) = J_n(k rho_y) e^{-i n th_y}, O_n(x) = H_n(k rho_x) e^{i n th_x} and the
+// normal derivative d_nu R_n = (k/2)(-nu R_{n+1} + conj(nu) R_{n-1}) (nu = n_x + i n_y),
+//   val = (i/4) sum_n O_n A_n,  der = (i/4)(k/2) sum_n O_n (nu_t B_{n+1} - conj(nu_t) B_{n-1}),
+//   A_n = -e+ Mq_n + Mu_n,  B_n = -Mq_n + Mu_n / e+,
+//   Mq_n = sum_y R_n q~,  Mu_n = (k/2) sum_y (-nu R_{n+1} + conj(nu) R_{n-1}) u~.
+// The truncation order of a (wave, inclusion) pair is the larger of the order the sources'
+// J_n decay needs and ceil(39.2 / ln(rho_min / r_j)) (rho_min: the centre's distance to the
+// wave's bounding circle), so that dropped terms stay below 1e-17 of the kept ones.
 #include "assemble.h"
 #include "bessel.h"
 #include "hankel_fast.h"
 #include "ktimer.h"
 
 #include <algorithm>
+#include <cmath>
+#include <type_traits>
 
 // Source data of a group of NR right-hand sides, packed per source node so that every
 // lane of a wave reads the same address (scalar loads): x, y, normal, owning inclusion,
@@ -133,12 +144,189 @@ __device__ inline void apply_store(const ApplyArgs& A, zd* out, int r0, int nr, 
   }
 }
 
-// Far part: every source inclusion of range blockIdx.y outside the wave's near list.  All
-// arguments are >= PMX_APPLY_FAR_Z, so the large-argument expansion alone serves, with as
-// many terms as the wave's smallest argument needs.  No per-lane branch in the loop.
+__device__ inline double wave_sum_a(double v) {
+  auto mv = [](double x, auto ctrl, auto rowmask) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), decltype(ctrl)::value, decltype(rowmask)::value, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), decltype(ctrl)::value, decltype(rowmask)::value, 0xf, false);
+    return __hiloint2double(hi, lo);
+  };
+  using I = std::integral_constant<int, 0xf>;
+  v += mv(v, std::integral_constant<int, 0xB1>{}, I{});     // quad_perm [1,0,3,2]
+  v += mv(v, std::integral_constant<int, 0x4E>{}, I{});     // quad_perm [2,3,0,1]
+  v += mv(v, std::integral_constant<int, 0x141>{}, I{});    // row_half_mirror
+  v += mv(v, std::integral_constant<int, 0x140>{}, I{});    // row_mirror
+  v += mv(v, std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});   // row_bcast15
+  v += mv(v, std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});   // row_bcast31
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// The general evaluation for waves with an argument below 24 (expansions of nearby
+// inclusions): out of line, so that its constants do not take registers in the far loop.
+__device__ __noinline__ bes4 bessel01_mid(double z) {
+  pmx_ctab tab = (pmx_ctab)pmx_far_table.v, ser = (pmx_ctab)pmx_series_table.v;
+  return bessel01_t(z, tab, ser);
+}
+
+// Expansion coefficients of every inclusion (one wave per inclusion, its nodes 64 at a
+// time).  J_0 .. J_{PMAX+3} of k rho_y by Miller's backward recurrence from order
+// PMAX + 27 + k r_j (normalised by J_0 + 2 sum J_2k = 1, a first pass finding the norm),
+// R_{+-m} = J_m e^{-+i m th} (R_{-m} = (-1)^m J_m e^{+i m th}), and the three sums
+// Mq_n = sum R_n q~, U+_n = sum R_n nu u~, U-_n = sum R_n conj(nu) u~ reduced over the wave
+// and accumulated in LDS; then Mu_n = (k/2)(-U+_{n+1} + U-_{n-1}) and the records.
+constexpr int P2M_MO = PMX_APPLY_PMAX + 3;   // orders -P2M_MO .. P2M_MO accumulated
+
 template <int NR>
-__global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __restrict__ pk, int r0) {
+__global__ __launch_bounds__(64) void k_apply_p2m(ApplyArgs A, const double* __restrict__ pk, int r0) {
   constexpr int S = APPLY_SRC(NR);
+  constexpr int NM = 2 * P2M_MO + 1;
+  __shared__ double acc[NM][NR][6];           // per order: Mq, U+, U- (re, im)
+  const int j = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int e = lane; e < NM * NR * 6; e += 64) (&acc[0][0][0])[e] = 0.0;
+  __syncthreads();
+  const double cx = A.incl_geo[4 * j], cy = A.incl_geo[4 * j + 1], rj = A.incl_geo[4 * j + 2];
+  const double k = A.k;
+  const int nstart = P2M_MO + 24 + (int)ceil(k * rj);
+  const int64_t b0 = A.node_off[j], b1 = A.node_off[j + 1];
+  for (int64_t c0 = b0; c0 < b1; c0 += 64) {
+    const int64_t bn = c0 + lane;
+    const bool valid = bn < b1;
+    const double* p = pk + (valid ? bn : b1 - 1) * S;
+    const double dx = p[0] - cx, dy = p[1] - cy;
+    const double rho = fmax(sqrt(dx * dx + dy * dy), 1e-30 * (1.0 + rj));   // a node at the centre stays finite
+    const double z = k * rho;
+    const double er = dx / rho, ei = -dy / rho;     // e^{-i th}
+    const double nur = p[2], nui = p[3];
+    double qr[NR], qi[NR], ur[NR], ui[NR];
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) {
+      const double f = valid ? 1.0 : 0.0;
+      qr[rr] = f * p[5 + 4 * rr];
+      qi[rr] = f * p[6 + 4 * rr];
+      ur[rr] = f * p[7 + 4 * rr];
+      ui[rr] = f * p[8 + 4 * rr];
+    }
+    // pass 1: the norm of the backward recurrence
+    const double iz2 = 2.0 / z;
+    double jp = 0.0, jc = 1e-280, nrm = (nstart % 2 == 0) ? 2.0 * jc : 0.0;
+    for (int m = nstart; m >= 1; --m) {
+      const double jm = m * iz2 * jc - jp;
+      jp = jc;
+      jc = jm;
+      if (((m - 1) & 1) == 0) nrm += (m - 1 == 0) ? jm : 2.0 * jm;
+    }
+    const double inv = 1.0 / nrm;
+    // e^{-i P2M_MO th} by repeated squaring
+    double Er = 1.0, Ei = 0.0, br = er, bi = ei;
+    for (int e = P2M_MO; e > 0; e >>= 1) {
+      if (e & 1) {
+        const double t = Er * br - Ei * bi;
+        Ei = Er * bi + Ei * br;
+        Er = t;
+      }
+      const double t = br * br - bi * bi;
+      bi = 2.0 * br * bi;
+      br = t;
+    }
+    // pass 2: the same recurrence, accumulating orders P2M_MO .. 0
+    jp = 0.0;
+    jc = 1e-280;
+    for (int m = nstart; m >= 0; --m) {
+      if (m <= P2M_MO) {
+        const double Jm = jc * inv;
+        const double sg = (m & 1) ? -1.0 : 1.0;
+        // R_m = Jm (Er + i Ei), R_-m = sg Jm (Er - i Ei)
+        const double Rpr = Jm * Er, Rpi = Jm * Ei, Rmr = sg * Jm * Er, Rmi = -sg * Jm * Ei;
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) {
+          const double vur = nur * ur[rr] - nui * ui[rr], vui = nur * ui[rr] + nui * ur[rr];      // nu u
+          const double wur = nur * ur[rr] + nui * ui[rr], wui = nur * ui[rr] - nui * ur[rr];      // conj(nu) u
+          double t[12];
+          t[0] = Rpr * qr[rr] - Rpi * qi[rr];
+          t[1] = Rpr * qi[rr] + Rpi * qr[rr];
+          t[2] = Rpr * vur - Rpi * vui;
+          t[3] = Rpr * vui + Rpi * vur;
+          t[4] = Rpr * wur - Rpi * wui;
+          t[5] = Rpr * wui + Rpi * wur;
+          t[6] = Rmr * qr[rr] - Rmi * qi[rr];
+          t[7] = Rmr * qi[rr] + Rmi * qr[rr];
+          t[8] = Rmr * vur - Rmi * vui;
+          t[9] = Rmr * vui + Rmi * vur;
+          t[10] = Rmr * wur - Rmi * wui;
+          t[11] = Rmr * wui + Rmi * wur;
+#pragma unroll
+          for (int q = 0; q < 12; ++q) t[q] = wave_sum_a(t[q]);
+          if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) acc[P2M_MO + m][rr][q] += t[q];
+            if (m > 0) {
+#pragma unroll
+              for (int q = 0; q < 6; ++q) acc[P2M_MO - m][rr][q] += t[6 + q];
+            }
+          }
+        }
+        // e^{-i (m-1) th} = e^{-i m th} e^{+i th}
+        const double t = Er * er + Ei * ei;
+        Ei = Ei * er - Er * ei;
+        Er = t;
+      }
+      if (m == 0) break;
+      const double jm = m * iz2 * jc - jp;
+      jp = jc;
+      jc = jm;
+    }
+  }
+  __syncthreads();
+  // records: A_n = -e Mq_n + Mu_n, B_n = -Mq_n + Mu_n / e, Mu_n = (k/2)(-U+_{n+1} + U-_{n-1})
+  const double eps = A.eps, hk = 0.5 * k;
+  auto coefAB = [&](int n, int rr, int ab, double& re, double& im) {
+    if (n < -(P2M_MO - 1) || n > P2M_MO - 1) {
+      re = im = 0.0;
+      return;
+    }
+    const double* a0 = acc[P2M_MO + n][rr];
+    const double* ap = acc[P2M_MO + n + 1][rr];
+    const double* am = acc[P2M_MO + n - 1][rr];
+    const double mur = hk * (-ap[2] + am[4]), mui = hk * (-ap[3] + am[5]);
+    if (ab == 0) {
+      re = -eps * a0[0] + mur;
+      im = -eps * a0[1] + mui;
+    } else {
+      re = -a0[0] + mur / eps;
+      im = -a0[1] + mui / eps;
+    }
+  };
+  zd* rec = A.coef + (int64_t)j * PMX_APPLY_NREC * NR * 6;
+  for (int e = lane; e < PMX_APPLY_NREC * NR; e += 64) {
+    const int m = e / NR, rr = e % NR;
+    double re, im;
+    zd* o = rec + ((int64_t)m * NR + rr) * 6;
+    coefAB(m, rr, 0, re, im);
+    o[0] = zmk(re, im);
+    coefAB(-m, rr, 0, re, im);
+    o[1] = m ? zmk(re, im) : zmk(0, 0);
+    coefAB(m + 1, rr, 1, re, im);
+    o[2] = zmk(re, im);
+    coefAB(-m + 1, rr, 1, re, im);
+    o[3] = m ? zmk(re, im) : zmk(0, 0);
+    coefAB(m - 1, rr, 1, re, im);
+    o[4] = zmk(re, im);
+    coefAB(-m - 1, rr, 1, re, im);
+    o[5] = m ? zmk(re, im) : zmk(0, 0);
+  }
+}
+
+// Far part: every inclusion of range blockIdx.y outside the wave's near list, through its
+// expansion: per lane rho, th of the target about the centre, H0 and H1 (large-argument
+// expansion when the whole wave allows it), then orders m = 0 .. p+1 by the upward
+// recurrence H_{m+1} = (2m/z) H_m - H_{m-1} (stable for the Hankel function) and
+// e^{i(m+1)th} = e^{i m th} e^{i th}; O_{-m} = (-1)^m H_m e^{-i m th}.  The sums
+// S1 = sum O_m B_{m+1}, S2 = sum O_m B_{m-1} are kept over all inclusions and turned into
+// derivative rows once at the end.
+template <int NR>
+__global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __restrict__ cf, int r0) {
   const int N = A.n_nodes;
   const int a_raw = blockIdx.x * 256 + threadIdx.x;
   const bool active = a_raw < N;
@@ -147,11 +335,11 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
   if (wv >= (N + 63) / 64) return;        // a wave past the last target (no barrier follows)
   const int nr = min(NR, A.nrhs - r0);
   const double ax = A.x[a], ay = A.y[a], anx = A.nx[a], any = A.ny[a];
-  const double k = A.k, eps = A.eps;
-  const double ik = 1.0 / k, ke = k / eps;
-  double vr[NR], vi[NR], dr[NR], di[NR];
+  const double k = A.k, ik = 1.0 / k;
+  const double wcx = A.wave_geo[4 * wv], wcy = A.wave_geo[4 * wv + 1], wr = A.wave_geo[4 * wv + 2];
+  double vr[NR], vi[NR], s1r[NR], s1i[NR], s2r[NR], s2i[NR];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) vr[r] = vi[r] = dr[r] = di[r] = 0.0;
+  for (int r = 0; r < NR; ++r) vr[r] = vi[r] = s1r[r] = s1i[r] = s2r[r] = s2i[r] = 0.0;
   int q = A.near_off[wv];
   const int qe = A.near_off[wv + 1];
   const int j0 = A.split_incl[blockIdx.y], j1 = A.split_incl[blockIdx.y + 1];
@@ -166,25 +354,80 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
       nxt = q < qe ? A.near_idx[q] : 0x7fffffff;
       continue;
     }
-    const int b1 = (int)A.node_off[j + 1];
-    for (int b = (int)A.node_off[j]; b < b1; ++b) {
+    const double cx = A.incl_geo[4 * j], cy = A.incl_geo[4 * j + 1], rj = A.incl_geo[4 * j + 2];
+    const double pj = A.incl_geo[4 * j + 3];
+    // truncation order of the pair (uniform)
+    const double rmin = sqrt((wcx - cx) * (wcx - cx) + (wcy - cy) * (wcy - cy)) - wr;
+    const double pr = fmax(pj, ceil(39.2 / log(rmin / rj)));
+    const int p = __builtin_amdgcn_readfirstlane((int)fmin(pr, (double)PMX_APPLY_PMAX));
+    const double dx = ax - cx, dy = ay - cy;
+    const double irho = rsqrt_nr(dx * dx + dy * dy);
+    const double z = k * ((dx * dx + dy * dy) * irho);
+    const double er = dx * irho, ei = dy * irho;   // e^{i th}
+    double H0r, H1r, H0i, H1i;
+    if (__all(z >= 24.0)) {
       pmx_ctab tab = (pmx_ctab)pmx_far_table.v;
-      asm volatile("" : "+s"(tab));   // re-read the coefficients in every iteration
-      const double* p = pk + (int64_t)b * S;
-      const double d1 = ax - p[0], d2 = ay - p[1];
-      const double ir = rsqrt_nr(d1 * d1 + d2 * d2);
-      const double z = k * ((d1 * d1 + d2 * d2) * ir);
-      double J0, J1, Y0, Y1;
+      asm volatile("" : "+s"(tab));
       if (__all(z >= 60.0))
-        hankel_far_t<12>(z, ir * ik, tab, J0, J1, Y0, Y1);
+        hankel_far_t<12>(z, irho * ik, tab, H0r, H1r, H0i, H1i);
       else if (__all(z >= 35.0))
-        hankel_far_t<16>(z, ir * ik, tab, J0, J1, Y0, Y1);
+        hankel_far_t<16>(z, irho * ik, tab, H0r, H1r, H0i, H1i);
       else
-        hankel_far_t<20>(z, ir * ik, tab, J0, J1, Y0, Y1);
-      apply_pair<NR>(J0, J1, Y0, Y1, ir, d1, d2, anx, any, p, k, eps, ke, 1.0, vr, vi, dr, di);
+        hankel_far_t<20>(z, irho * ik, tab, H0r, H1r, H0i, H1i);
+    } else {
+      const bes4 h = bessel01_mid(z);
+      H0r = h.j0;
+      H0i = h.y0;
+      H1r = h.j1;
+      H1i = h.y1;
+    }
+    const double iz2 = 2.0 / z;
+    // m = 0 .. p + 1: Hc = H_m, Hp = H_{m-1}, (Emr, Emi) = e^{i m th}
+    double Hcr = H0r, Hci = H0i, Hpr = -H1r, Hpi = -H1i;   // H_{-1} = -H_1
+    double Emr = 1.0, Emi = 0.0;
+    const double* rec = cf + (int64_t)j * PMX_APPLY_NREC * NR * 12;
+    for (int m = 0; m <= p + 1; ++m) {
+      const double sg = (m & 1) ? -1.0 : 1.0;
+      const double Opr = Hcr * Emr - Hci * Emi, Opi = Hcr * Emi + Hci * Emr;               // O_m
+      const double Omr = sg * (Hcr * Emr + Hci * Emi), Omi = sg * (Hci * Emr - Hcr * Emi);  // O_-m
+      const double* o = rec + (int64_t)m * NR * 12;
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr) {
+        // A_m, A_-m, B_m+1, B_-m+1, B_m-1, B_-m-1 (wave-uniform addresses: scalar loads)
+        const double* c = o + rr * 12;
+        vr[rr] += Opr * c[0] - Opi * c[1] + Omr * c[2] - Omi * c[3];
+        vi[rr] += Opr * c[1] + Opi * c[0] + Omr * c[3] + Omi * c[2];
+        s1r[rr] += Opr * c[4] - Opi * c[5] + Omr * c[6] - Omi * c[7];
+        s1i[rr] += Opr * c[5] + Opi * c[4] + Omr * c[7] + Omi * c[6];
+        s2r[rr] += Opr * c[8] - Opi * c[9] + Omr * c[10] - Omi * c[11];
+        s2i[rr] += Opr * c[9] + Opi * c[8] + Omr * c[11] + Omi * c[10];
+      }
+      // H_{m+1} = (2m/z) H_m - H_{m-1}; e^{i(m+1)th}
+      const double f = m * iz2;
+      double Hnr = f * Hcr - Hpr, Hni = f * Hci - Hpi;
+      if (m == 0) {
+        Hnr = H1r;
+        Hni = H1i;
+      }
+      Hpr = Hcr;
+      Hpi = Hci;
+      Hcr = Hnr;
+      Hci = Hni;
+      const double t = Emr * er - Emi * ei;
+      Emi = Emr * ei + Emi * er;
+      Emr = t;
     }
   }
-  if (active) apply_store<NR>(A, A.part + (int64_t)blockIdx.y * A.nrhs * A.ld, r0, nr, a, vr, vi, dr, di);
+  if (!active) return;
+  // der = (k/2)(nu S1 - conj(nu) S2)
+  const double hk = 0.5 * k;
+  double dr[NR], di[NR];
+#pragma unroll
+  for (int rr = 0; rr < NR; ++rr) {
+    dr[rr] = hk * (anx * s1r[rr] - any * s1i[rr] - (anx * s2r[rr] + any * s2i[rr]));
+    di[rr] = hk * (anx * s1i[rr] + any * s1r[rr] - (anx * s2i[rr] - any * s2r[rr]));
+  }
+  apply_store<NR>(A, A.part + (int64_t)blockIdx.y * A.nrhs * A.ld, r0, nr, a, vr, vi, dr, di);
 }
 
 // Near part: one wave per workgroup; part blockIdx.y of the wave's near list, every
@@ -256,12 +499,22 @@ int apply_near_splits(int n_nodes, int wg_target) {
 
 int64_t apply_pack_size(int n_nodes, int nr_max) { return (int64_t)n_nodes * APPLY_SRC(nr_max); }
 
+int64_t apply_coef_size(int n_incl, int nr_max) { return (int64_t)n_incl * PMX_APPLY_NREC * nr_max * 6; }
+
+int apply_source_order(double kr) {
+  for (int p = 1; p < 1000; ++p)
+    if (p > 0.5 * M_E * kr + 2 && std::pow(0.5 * M_E * kr / p, p) <= 1e-17) return p;
+  return 1000;
+}
+
 template <int NR>
 static void apply_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipStream_t s) {
   hipLaunchKernelGGL(k_apply_pack<NR>, dim3((A.n_nodes + 255) / 256), dim3(256), 0, s, A, r0, pk);
   KScope ks(PK_APPLY, s);
-  hipLaunchKernelGGL(k_apply_far<NR>, dim3((A.n_nodes + 255) / 256, nsplit), dim3(256), 0, s, A, (const double*)pk,
-                     r0);
+  const int m = (int)A.n_incl;
+  hipLaunchKernelGGL(k_apply_p2m<NR>, dim3(m), dim3(64), 0, s, A, (const double*)pk, r0);
+  hipLaunchKernelGGL(k_apply_far<NR>, dim3((A.n_nodes + 255) / 256, nsplit), dim3(256), 0, s, A,
+                     (const double*)A.coef, r0);
   hipLaunchKernelGGL(k_apply_near<NR>, dim3((A.n_nodes + 63) / 64, A.nsplit_near), dim3(64), 0, s, A,
                      (const double*)pk, r0, nsplit);
 }

@@ -129,15 +129,23 @@ template <class R>
 void asm_build_l(const LDescT<R>* d, int batch, int max_s, int max_k, hipStream_t s);
 // y[i] += a x[i] for complex FP64 arrays
 void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s);
-// Dense FP64 operator apply between different inclusions (on the fly, exterior kernels),
-// for a block of right-hand sides in the density layout (ld = 2 n_nodes, per inclusion
-// [q; u]).  Targets are taken in waves of 64 consecutive nodes.  Each wave has a sorted
-// list of "near" source inclusions: its own inclusions and every inclusion that may come
-// within k+ r < 24 of one of its targets (bounding circles).  The far kernel takes the
-// other inclusions of each of nsplit source ranges (whole inclusions, split_incl) with the
-// large-argument Hankel expansion; the near kernel takes the near lists (split in
-// nsplit_near parts), skipping pairs on the same inclusion.  Partial sums go to
-// part [nsplit + nsplit_near][nrhs][ld].
+// Dense FP64 operator apply between different inclusions (exterior kernels), for a block
+// of right-hand sides in the density layout (ld = 2 n_nodes, per inclusion [q; u]).
+// Targets are taken in waves of 64 consecutive nodes.  Each wave has a sorted list of
+// "near" inclusions: its own inclusions, every inclusion whose centre is closer to the
+// wave's bounding circle than PMX_APPLY_RATIO times its radius, and every inclusion whose
+// expansion would need more than PMX_APPLY_PMAX orders.  Near inclusions are applied pair
+// by pair (near kernel, split in nsplit_near parts, same-inclusion pairs left out).  Every
+// other inclusion is applied through its multipole expansion about its centre (Graf's
+// addition theorem): coefficients per inclusion from its sources (p2m kernel), evaluated
+// at each target to the order its distance needs (far kernel, over nsplit ranges of whole
+// inclusions, split_incl).  Partial sums go to part [nsplit + nsplit_near][nrhs][ld].
+#define PMX_APPLY_RATIO 3.0
+#define PMX_APPLY_PMAX 48
+// coefficient records per inclusion: orders m = 0 .. PMX_APPLY_PMAX + 1, per right-hand side
+// six complex numbers A_m, A_-m, B_m+1, B_-m+1, B_m-1, B_-m-1 (A: value rows, B: normal
+// derivative rows; the -m entries are zero for m = 0)
+#define PMX_APPLY_NREC (PMX_APPLY_PMAX + 2)
 struct ApplyArgs {
   const double *x, *y, *nx, *ny, *w;
   const int* owner;
@@ -153,15 +161,22 @@ struct ApplyArgs {
   const int* near_idx;   // near inclusions of each wave, ascending
   const int* split_incl; // [nsplit + 1] first inclusion of each far source range
   int nsplit_near;
+  const double* incl_geo;  // per inclusion: centre x, y, radius, order needed by the sources' decay
+  const double* wave_geo;  // per wave: bounding-circle centre x, y, radius, unused
+  zd* coef;              // [n_incl][PMX_APPLY_NREC][nr][6] expansion records of one group
+  int n_incl;
 };
-// arguments at or above this value of k+ r use the large-argument expansion only
-#define PMX_APPLY_FAR_Z 24.0
+// orders needed for the sources of an inclusion of radius r: the smallest p with
+// (e k r / 2p)^p <= 1e-17 and p > e k r / 2 + 2
+int apply_source_order(double kr);
 // source splits giving about wg_target workgroups per launch
 int apply_splits(int n_nodes, int wg_target);
 // near-list splits giving about wg_target one-wave workgroups per launch
 int apply_near_splits(int n_nodes, int wg_target);
 // doubles of the packed source data for groups of up to nr_max right-hand sides
 int64_t apply_pack_size(int n_nodes, int nr_max);
+// complex entries of the expansion records for groups of up to nr_max right-hand sides
+int64_t apply_coef_size(int n_incl, int nr_max);
 // partial sums of the off-diagonal operator (far ranges, then near parts), right-hand
 // sides in groups of nr_max (1, 2, 4, 8) per thread
 void asm_apply_off(const ApplyArgs& a, int nsplit, int nr_max, hipStream_t s);

@@ -1488,6 +1488,7 @@ GatherDescT<RD>* gather_to_leaf(const LeafMap& M, cx<RD>* leaf, int nrhs, Arena&
 struct DenseApply {
   int nrhs = -1, nsplit = 1, nblk = 1, nr_max = 8;
   int nslots = 1;                 // partial-sum slots: nsplit far ranges + near parts
+  double flops_fixed = 0, flops_rhs = 0;   // algorithmic work of one apply (counted with timing)
   int64_t total = 0;
   zd *ydiag = nullptr, *part = nullptr;
   double* d_norm = nullptr;
@@ -1498,16 +1499,29 @@ struct DenseApply {
   zd* out = nullptr;
 };
 
-// Near lists of the dense apply: for each wave of 64 consecutive target nodes, the
-// inclusions that may come within k+ r < PMX_APPLY_FAR_Z of one of its targets (bounding
-// circles of the wave's nodes and of each inclusion), ascending; the wave's own
-// inclusions are always on it.  Candidates come from a uniform grid of the inclusion
-// centres whose spacing covers the largest possible reach.
-void apply_near_lists(pmx_factor* F, std::vector<int>& off, std::vector<int>& idx, hipStream_t s) {
+// Geometry of the dense apply: bounding circles (centre, radius) of every inclusion (with
+// the expansion order its sources need) and of every wave of 64 consecutive target nodes,
+// and per wave the sorted list of near inclusions: those whose centre is closer than
+// PMX_APPLY_RATIO times their radius to the wave's circle (its own inclusions among them)
+// and those whose expansion would need more than PMX_APPLY_PMAX orders.  Candidates come
+// from a uniform grid of the inclusion centres whose spacing covers the largest reach.
+// With `count`, the algorithmic work per right-hand side and the fixed part are returned:
+// per near pair 32 and 130 flops (the pair formulas), per (target, far inclusion)
+// (p + 2) 48 and 100 + 26 (p + 2) flops (orders m = 0 .. p + 1: six complex multiply-adds
+// per right-hand side, the two O's and the recurrences; H0, H1 and the geometry once), per
+// source node and order 72 flops per right-hand side for the expansion sums.
+struct ApplyGeo {
+  std::vector<int> off, idx;
+  std::vector<double> incl, wave;
+  double flops_fixed = 0, flops_rhs = 0;
+};
+
+void apply_geometry(pmx_factor* F, ApplyGeo& G, bool count, hipStream_t s) {
   std::vector<double> hx, hy;
   download(hx, F->x, F->n_nodes, s);
   download(hy, F->y, F->n_nodes, s);
   const int m = F->m, N = F->n_nodes, nw = (N + 63) / 64;
+  const double k = F->k_ext;
   auto circle = [&](int64_t b0, int64_t b1, double& cx, double& cy, double& r) {
     double x0 = hx[b0], x1 = hx[b0], y0 = hy[b0], y1 = hy[b0];
     for (int64_t b = b0; b < b1; ++b) {
@@ -1522,45 +1536,80 @@ void apply_near_lists(pmx_factor* F, std::vector<int>& off, std::vector<int>& id
     for (int64_t b = b0; b < b1; ++b) r2 = std::max(r2, (hx[b] - cx) * (hx[b] - cx) + (hy[b] - cy) * (hy[b] - cy));
     r = std::sqrt(r2);
   };
-  std::vector<double> ix(m), iy(m), ir(m), wx(nw), wy(nw), wr(nw);
+  G.incl.assign(4 * (size_t)m, 0.0);
+  G.wave.assign(4 * (size_t)nw, 0.0);
   double rimax = 0, rwmax = 0;
+  std::vector<int> always;   // expansions beyond the largest order: near for every wave
   for (int j = 0; j < m; ++j) {
-    circle(F->node_off[j], F->node_off[j + 1], ix[j], iy[j], ir[j]);
-    rimax = std::max(rimax, ir[j]);
+    double* g = &G.incl[4 * (size_t)j];
+    circle(F->node_off[j], F->node_off[j + 1], g[0], g[1], g[2]);
+    g[3] = (double)apply_source_order(k * g[2]);
+    rimax = std::max(rimax, g[2]);
+    if (g[3] > PMX_APPLY_PMAX) always.push_back(j);
   }
   for (int w = 0; w < nw; ++w) {
-    circle(64 * (int64_t)w, std::min<int64_t>(64 * (int64_t)w + 64, N), wx[w], wy[w], wr[w]);
-    rwmax = std::max(rwmax, wr[w]);
+    double* g = &G.wave[4 * (size_t)w];
+    circle(64 * (int64_t)w, std::min<int64_t>(64 * (int64_t)w + 64, N), g[0], g[1], g[2]);
+    rwmax = std::max(rwmax, g[2]);
   }
-  // reach in distance, with a margin for the rounding of the kernels' z
-  const double reach = PMX_APPLY_FAR_Z / F->k_ext * (1.0 + 1e-9) + 1e-12;
-  const double h = reach + rimax + rwmax;
-  double gx0 = ix[0], gy0 = iy[0];
+  const double h = PMX_APPLY_RATIO * rimax * (1.0 + 1e-9) + rwmax + 1e-12;
+  double gx0 = G.incl[0], gy0 = G.incl[1];
   for (int j = 0; j < m; ++j) {
-    gx0 = std::min(gx0, ix[j]);
-    gy0 = std::min(gy0, iy[j]);
+    gx0 = std::min(gx0, G.incl[4 * (size_t)j]);
+    gy0 = std::min(gy0, G.incl[4 * (size_t)j + 1]);
   }
   std::map<std::pair<int64_t, int64_t>, std::vector<int>> grid;
   for (int j = 0; j < m; ++j)
-    grid[{(int64_t)std::floor((ix[j] - gx0) / h), (int64_t)std::floor((iy[j] - gy0) / h)}].push_back(j);
-  off.assign(nw + 1, 0);
-  idx.clear();
+    grid[{(int64_t)std::floor((G.incl[4 * (size_t)j] - gx0) / h), (int64_t)std::floor((G.incl[4 * (size_t)j + 1] - gy0) / h)}]
+        .push_back(j);
+  G.off.assign(nw + 1, 0);
+  G.idx.clear();
   std::vector<int> cand;
+  std::vector<char> isnear(count ? m : 0, 0);
+  double near_pairs = 0, far_orders = 0, far_pairs = 0;
   for (int w = 0; w < nw; ++w) {
-    cand.clear();
-    const int64_t cxw = (int64_t)std::floor((wx[w] - gx0) / h), cyw = (int64_t)std::floor((wy[w] - gy0) / h);
+    const double *gw = &G.wave[4 * (size_t)w];
+    cand.assign(always.begin(), always.end());
+    const int64_t cxw = (int64_t)std::floor((gw[0] - gx0) / h), cyw = (int64_t)std::floor((gw[1] - gy0) / h);
     for (int64_t dx = -1; dx <= 1; ++dx)
       for (int64_t dy = -1; dy <= 1; ++dy) {
         auto it = grid.find({cxw + dx, cyw + dy});
         if (it == grid.end()) continue;
         for (int j : it->second) {
-          const double d = std::hypot(wx[w] - ix[j], wy[w] - iy[j]);
-          if (d - wr[w] - ir[j] < reach) cand.push_back(j);
+          const double* g = &G.incl[4 * (size_t)j];
+          const double rmin = std::hypot(gw[0] - g[0], gw[1] - g[1]) - gw[2];
+          if (rmin < PMX_APPLY_RATIO * g[2] && g[3] <= PMX_APPLY_PMAX) cand.push_back(j);
         }
       }
     std::sort(cand.begin(), cand.end());
-    idx.insert(idx.end(), cand.begin(), cand.end());
-    off[w + 1] = (int)idx.size();
+    G.idx.insert(G.idx.end(), cand.begin(), cand.end());
+    G.off[w + 1] = (int)G.idx.size();
+    if (count) {
+      const double nt = (double)(std::min(64 * w + 64, N) - 64 * w);
+      for (int j : cand) {
+        isnear[j] = 1;
+        near_pairs += nt * (double)(F->node_off[j + 1] - F->node_off[j]);
+      }
+      for (int j = 0; j < m; ++j) {
+        if (isnear[j]) continue;
+        const double* g = &G.incl[4 * (size_t)j];
+        const double rmin = std::hypot(gw[0] - g[0], gw[1] - g[1]) - gw[2];
+        const double p = std::min((double)PMX_APPLY_PMAX, std::max(g[3], std::ceil(39.2 / std::log(rmin / g[2]))));
+        far_orders += nt * (p + 2);
+        far_pairs += nt;
+      }
+      for (int j : cand) isnear[j] = 0;
+    }
+  }
+  if (count) {
+    // near pairs include each target's own inclusion, which the apply leaves out
+    for (int j = 0; j < m; ++j) {
+      const double n = (double)(F->node_off[j + 1] - F->node_off[j]);
+      near_pairs -= n * n;
+    }
+    const double p2m = (double)N * (2 * (PMX_APPLY_PMAX + 3) + 1);
+    G.flops_rhs = 32.0 * near_pairs + 48.0 * far_orders + 72.0 * p2m;
+    G.flops_fixed = 130.0 * near_pairs + 100.0 * far_pairs + 26.0 * far_orders;
   }
 }
 
@@ -1590,8 +1639,10 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   const int wg = std::max(64, std::min(1 << 20, tune_choice(TK_APPLY_WG, 8, ta, tb, 0, 8192, F->n_nodes, nrhs, 0)));
   const std::vector<int> split = apply_split_incl(F, apply_splits(F->n_nodes, wg));
   D.nsplit = (int)split.size() - 1;
-  std::vector<int> noff, nidx;
-  apply_near_lists(F, noff, nidx, s);
+  ApplyGeo G;
+  apply_geometry(F, G, F->opts.timing != 0, s);
+  D.flops_fixed = G.flops_fixed;
+  D.flops_rhs = G.flops_rhs;
   const int nnear = apply_near_splits(F->n_nodes, wg);
   D.nslots = D.nsplit + nnear;
   D.ydiag = A.alloc<zd>(D.total);
@@ -1624,10 +1675,14 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   aa.ld = N2;
   aa.part = D.part;
   aa.pack = A.alloc<double>(apply_pack_size(F->n_nodes, 8));
-  aa.near_off = A.upload(noff, s);
-  aa.near_idx = A.upload(nidx, s);
+  aa.near_off = A.upload(G.off, s);
+  aa.near_idx = A.upload(G.idx, s);
   aa.split_incl = A.upload(split, s);
   aa.nsplit_near = nnear;
+  aa.incl_geo = A.upload(G.incl, s);
+  aa.wave_geo = A.upload(G.wave, s);
+  aa.coef = A.alloc<zd>(apply_coef_size(F->m, 8));
+  aa.n_incl = F->m;
   D.f = f;
   D.out = out;
   D.nrhs = nrhs;
@@ -1789,22 +1844,16 @@ void upload_angles(pmx_factor* F, const double* angles) {
   HIPCHK(hipMemcpyAsync(S.d_angles, S.h_angles.data(), S.nrhs * sizeof(double), hipMemcpyHostToDevice, F->gs));
 }
 
-// Algorithmic work of one dense operator apply, per pair of nodes on different
-// inclusions: 6 flops for the distance, 94 for H0 and H1 by their large-argument
-// expansion (two series of 10 terms in 1/z for each of P and Q, 20 for the phase and the
-// amplitude), 30 for the four kernel factors, and 32 per right-hand side for the four
-// complex multiply-adds into the value and derivative rows.  Bytes: the node data (x, y,
-// normal, weight) and the densities read once, the partial sums of every source split
-// written once.
+// Algorithmic work of one dense operator apply (the near pairs, the far expansions and the
+// expansion sums; apply_geometry counts them).  Bytes: the node data (x, y, normal,
+// weight) and the densities read once, the expansion records written and read once, the
+// partial sums of every slot written once.
 void count_apply_work(pmx_factor* F, int nrhs) {
-  double pairs = (double)F->n_nodes * F->n_nodes;
-  for (int j = 0; j < F->m; ++j) {
-    const double n = (double)(F->node_off[j + 1] - F->node_off[j]);
-    pairs -= n * n;
-  }
+  const DenseApply& D = F->ss->apply;
   const double N2 = 2.0 * F->n_nodes;
-  F->info.kernel_flops[PK_APPLY] += pairs * (130.0 + 32.0 * nrhs);
-  F->info.kernel_bytes[PK_APPLY] += 8.0 * 5 * F->n_nodes + 16.0 * N2 * nrhs * (1 + F->ss->apply.nslots);
+  F->info.kernel_flops[PK_APPLY] += D.flops_fixed + D.flops_rhs * nrhs;
+  F->info.kernel_bytes[PK_APPLY] += 8.0 * 5 * F->n_nodes + 16.0 * N2 * nrhs * (1 + D.nslots) +
+                                    2.0 * 16.0 * 6.0 * PMX_APPLY_NREC * F->m * nrhs;
 }
 
 // FP64 factor: right-hand side into the leaf vectors, one solve pass, solution to xout.
@@ -2434,6 +2483,7 @@ pmx_status pmx_probe_apply(const pmx_geometry* geom, int32_t nrhs, const pmx_c64
     if (nrhs <= 0 || !x || !y || (const void*)x == (const void*)y) fail(PMX_EINVAL, "bad arguments");
     hipStream_t s = (hipStream_t)stream;
     pmx_factor F;
+    pmx_options_default(&F.opts);
     upload_geometry(&F, geom, s);
     Arena tmp;
     std::vector<int> incl(geom->m);
