@@ -108,7 +108,9 @@ typedef struct {
   double bytes_factor;       /* device bytes held by the factor */
   double t_factor_ms;        /* wall time of pmx_factor_create (host clock, synchronised) */
   double t_phase_ms[16];     /* host wall time of phases: 0 self blocks, 1 level compression,
-                                3 top LU */
+                                2 level merges, 3 top LU, 4 plan; solves: 5 set-up of the
+                                solve state for a new right-hand-side count, 6 of it the
+                                operator apply set-up */
   /* with options.timing = 1: per-kernel device time from HIP events around every launch
    * (of the kernels selected by options.timing_kernels) of the factorisation and of the
    * solves, summed over them (index: 0 QR leaf blocks, 1 QR trailing update, 2 LU panel, 3 CPQR
@@ -180,8 +182,16 @@ pmx_status pmx_factor_info(const pmx_factor* f, pmx_info* info);
 pmx_status pmx_autotune(const pmx_geometry* geom, const pmx_options* opts, int32_t nrhs, int32_t reps,
                         const char* path, void* hip_stream);
 
-/* Releases everything the factor holds; accepts NULL. */
+/* Releases everything the factor holds; accepts NULL.  The factor's device blocks go to
+ * a process-wide cache (after a device synchronisation), from which later factors take
+ * their blocks before calling hipMalloc; see pmx_device_cache. */
 void pmx_factor_destroy(pmx_factor* f);
+
+/* Process-wide cache of device blocks left by destroyed factors (default limit 8 GiB).
+ * limit >= 0 sets the limit and frees cached blocks beyond it (0 frees them all); limit < 0
+ * keeps it.  held (may be NULL) receives the bytes the cache holds afterwards.  Factors
+ * that cannot allocate empty the cache and try again.  Thread-safe.  Errors: none. */
+pmx_status pmx_device_cache(int64_t limit, int64_t* held);
 
 /* Learned skeleton proposals (the leaf IDs of Sec. 3 as training labels).
  *

@@ -24,6 +24,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -63,11 +64,62 @@ void fail(pmx_status st, const std::string& msg) { throw PmxErr{st, msg}; }
 // later work of the same stream (the factorisation's), so stream order protects them.
 // Host staging buffers of uploads are kept as well (an asynchronous copy may still read
 // them).  Everything is freed when the pool is destroyed, after the stream is idle.
+// Device blocks of destroyed factors, kept for later factors of the process so that a
+// factorisation in steady state calls no hipMalloc: at most g_cache_limit bytes, blocks
+// keyed by size class.  A block enters the cache only after the device has finished the
+// work of the factor that held it.
+std::mutex g_cache_mu;
+std::map<size_t, std::vector<void*>> g_cache;
+size_t g_cache_bytes = 0;
+size_t g_cache_limit = (size_t)8 << 30;
+
+void* cache_take(size_t c) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = g_cache.find(c);
+  if (it == g_cache.end() || it->second.empty()) return nullptr;
+  void* p = it->second.back();
+  it->second.pop_back();
+  g_cache_bytes -= c;
+  return p;
+}
+
+// frees cached blocks until at most `keep` bytes remain; returns the bytes freed
+size_t cache_trim(size_t keep) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  size_t freed = 0;
+  for (auto it = g_cache.rbegin(); it != g_cache.rend() && g_cache_bytes > keep; ++it)
+    while (!it->second.empty() && g_cache_bytes > keep) {
+      (void)hipFree(it->second.back());
+      it->second.pop_back();
+      g_cache_bytes -= it->first;
+      freed += it->first;
+    }
+  return freed;
+}
+
+// Device blocks of one factor.  Temporary buffers of the factorisation are released level
+// by level; giving their blocks back to hipFree would synchronise the device each time,
+// and hipMalloc them anew costs host time.  Blocks come in size classes of one eighth of
+// an octave (at least 256 bytes) and are reused by later work of the factor, in stream
+// order: the factorisation's stream, then the solve stream, which waits for it.  Host
+// staging buffers of uploads are kept as well (an asynchronous copy may still read them).
+// When the pool is destroyed, the device is synchronised and the blocks go to the
+// process cache (beyond its limit, to hipFree).
 class DevPool {
  public:
   ~DevPool() {
+    if (free_.empty()) return;
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> lk(g_cache_mu);
     for (auto& kv : free_)
-      for (void* p : kv.second) (void)hipFree(p);
+      for (void* p : kv.second) {
+        if (g_cache_bytes + kv.first <= g_cache_limit) {
+          g_cache[kv.first].push_back(p);
+          g_cache_bytes += kv.first;
+        } else {
+          (void)hipFree(p);
+        }
+      }
   }
   static size_t size_class(size_t n) {
     if (n <= 256) return 256;
@@ -84,10 +136,15 @@ class DevPool {
       it->second.pop_back();
       return p;
     }
+    if (void* p = cache_take(c)) return p;
     void* p = nullptr;
     if (hipMalloc(&p, c) != hipSuccess) {
       (void)hipGetLastError();
-      return nullptr;
+      // the cached blocks of earlier factors may be what is missing
+      if (cache_trim(0) == 0 || hipMalloc(&p, c) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
     }
     return p;
   }
@@ -108,6 +165,10 @@ class Arena {
   Arena() = default;
   explicit Arena(DevPool* pool) : pool_(pool) {}
   ~Arena() { release(); }
+  void set_pool(DevPool* pool) {
+    release();
+    pool_ = pool;
+  }
   template <class T>
   T* alloc(size_t n) {
     if (n == 0) n = 1;
@@ -282,6 +343,10 @@ struct pmx_factor {
   std::vector<float> leaf_pred;
   // launch-parameter table of options.tune_path (NULL: built-in rules)
   std::unique_ptr<TuneTable> tune;
+  pmx_factor() : arena(&pool) {
+    t64.prog.arena.set_pool(&pool);
+    t32.prog.arena.set_pool(&pool);
+  }
   ~pmx_factor();
   DevGeom geom() const { return DevGeom{x, y, nx, ny, w, speed, kappa, n_nodes}; }
   ExtParams ext() const { return ExtParams{k_ext, eps_ext}; }
@@ -1143,11 +1208,13 @@ void factor_all(pmx_factor* F, hipStream_t s) {
   LevelData<R> cur = std::move(L0);
   for (size_t lv = 0; lv < plan.size(); ++lv) {
     if (lv > 0) {
+      const double tm = now_ms();
       Arena tmp(&F->pool);
       LevelData<R> nxt;
       merge_level(F, T.lev.back(), plan[lv], nxt, tmp, s);
       sync_check(s);
       cur = std::move(nxt);
+      F->info.t_phase_ms[2] += now_ms() - tm;
     }
     if (plan[lv].size() == 1) {
       // root: dense partial-pivoted LU of the top compressed system
@@ -1735,6 +1802,7 @@ struct SolveState {
   DenseApply apply;
   hipGraphExec_t g_plane = nullptr, g_general = nullptr, g_iter = nullptr;
   Arena arena;
+  explicit SolveState(DevPool* pool) : arena(pool) {}
   void drop_graphs() {
     for (hipGraphExec_t* g : {&g_plane, &g_general, &g_iter})
       if (*g) {
@@ -1794,6 +1862,7 @@ template <class R>
 void ensure_state(pmx_factor* F, int nrhs) {
   SolveState& S = *F->ss;
   if (S.nrhs == nrhs) return;
+  const double t0 = now_ms();
   S.reset();
   hipStream_t s = F->gs;
   Arena& A = S.arena;
@@ -1832,10 +1901,13 @@ void ensure_state(pmx_factor* F, int nrhs) {
     S.d_leaf64_to_f = gather_to_dens(S.map, S.f, nrhs, A, s);
     S.d_r_to_leaf = gather_to_leaf(S.map, leaf, nrhs, A, s);
     S.d_leaf_to_x = gather_to_dens(S.map, S.xout, nrhs, A, s);
+    const double ta = now_ms();
     build_dense_apply(F, nrhs, F->Dself, F->selfIncl, F->selfOff, S.xout, S.f, S.r, S.apply, A, s);
+    F->info.t_phase_ms[6] += now_ms() - ta;
   }
   HIPCHK(hipStreamSynchronize(s));
   S.nrhs = nrhs;
+  F->info.t_phase_ms[5] += now_ms() - t0;
 }
 
 void upload_angles(pmx_factor* F, const double* angles) {
@@ -2276,10 +2348,11 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
     } reset_timer{g_tune};
     g_tune = F->tune.get();
     make_plan(geom, o, F->plan);
+    F->info.t_phase_ms[4] = now_ms() - t0;
     HIPCHK(hipStreamCreateWithFlags(&F->gs, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&F->ev_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&F->ev_out, hipEventDisableTiming));
-    F->ss.reset(new SolveState());
+    F->ss.reset(new SolveState(&F->pool));
     if (o.learned) leaf_predictions(F.get(), geom, o.model_path, s);
     upload_geometry(F.get(), geom, s);
     if (o.precision == 1) {
@@ -2376,6 +2449,22 @@ pmx_status pmx_factor_info(const pmx_factor* f, pmx_info* info) {
 }
 
 void pmx_factor_destroy(pmx_factor* f) { delete f; }
+
+pmx_status pmx_device_cache(int64_t limit, int64_t* held) {
+  return guarded([&] {
+    if (limit >= 0) {
+      {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        g_cache_limit = (size_t)limit;
+      }
+      cache_trim((size_t)limit);
+    }
+    if (held) {
+      std::lock_guard<std::mutex> lk(g_cache_mu);
+      *held = (int64_t)g_cache_bytes;
+    }
+  });
+}
 
 const char* pmx_status_string(pmx_status s) {
   switch (s) {

@@ -30,20 +30,53 @@ uint64_t morton_code(uint32_t i, uint32_t j) {
 
 namespace {
 
-struct NodeSet {
-  std::vector<double> x, y;
-};
-
-double min_dist(const NodeSet& s, double cx, double cy) {
-  double d = std::numeric_limits<double>::infinity();
-  for (size_t i = 0; i < s.x.size(); ++i) d = std::min(d, std::hypot(s.x[i] - cx, s.y[i] - cy));
-  return d;
+// Nearest and farthest node of the inclusions incl from (cx, cy), as std::hypot distances
+// (the values the rest of the plan, and its tests, are defined with).  Squared distances
+// find the extremes; hypot is then evaluated only for the nodes whose squared distance
+// lies within a relative 1e-12 of an extreme, which contains every node hypot can rank
+// first (squared distances are off by a few ulps at most).
+void node_range(const std::vector<int>& incl, const int64_t* node_off, const double* x, const double* y, double cx,
+                double cy, double& dmin, double& dmax) {
+  // four independent running extrema (min and max are exact, so the order is free)
+  double lo[4], hi[4];
+  for (int q = 0; q < 4; ++q) {
+    lo[q] = std::numeric_limits<double>::infinity();
+    hi[q] = 0;
+  }
+  for (int j : incl) {
+    int64_t i = node_off[j];
+    const int64_t e = node_off[j + 1];
+    for (; i + 4 <= e; i += 4)
+      for (int q = 0; q < 4; ++q) {
+        const double dx = x[i + q] - cx, dy = y[i + q] - cy;
+        const double d2 = dx * dx + dy * dy;
+        lo[q] = d2 < lo[q] ? d2 : lo[q];
+        hi[q] = d2 > hi[q] ? d2 : hi[q];
+      }
+    for (; i < e; ++i) {
+      const double dx = x[i] - cx, dy = y[i] - cy;
+      const double d2 = dx * dx + dy * dy;
+      lo[0] = d2 < lo[0] ? d2 : lo[0];
+      hi[0] = d2 > hi[0] ? d2 : hi[0];
+    }
+  }
+  const double lo2 = std::min(std::min(lo[0], lo[1]), std::min(lo[2], lo[3]));
+  const double hi2 = std::max(std::max(hi[0], hi[1]), std::max(hi[2], hi[3]));
+  const double lo_cut = lo2 * (1.0 + 1e-12), hi_cut = hi2 * (1.0 - 1e-12);
+  dmin = std::numeric_limits<double>::infinity();
+  dmax = 0;
+  for (int j : incl)
+    for (int64_t i = node_off[j]; i < node_off[j + 1]; ++i) {
+      const double dx = x[i] - cx, dy = y[i] - cy;
+      const double d2 = dx * dx + dy * dy;
+      if (d2 <= lo_cut) dmin = std::min(dmin, std::hypot(dx, dy));
+      if (d2 >= hi_cut) dmax = std::max(dmax, std::hypot(dx, dy));
+    }
 }
 
 void near_and_proxy(const PlanOptions& o, const double* centers, const int64_t* node_off, const double* x,
                     const double* y, std::vector<CellPlan>& cells) {
   const int nc = (int)cells.size();
-  std::vector<NodeSet> pts(nc);
   for (int t = 0; t < nc; ++t) {
     CellPlan& c = cells[t];
     double sx = 0, sy = 0;
@@ -53,61 +86,72 @@ void near_and_proxy(const PlanOptions& o, const double* centers, const int64_t* 
     }
     c.cx = sx / (double)c.incl.size();
     c.cy = sy / (double)c.incl.size();
-    for (int j : c.incl)
-      for (int64_t i = node_off[j]; i < node_off[j + 1]; ++i) {
-        pts[t].x.push_back(x[i]);
-        pts[t].y.push_back(y[i]);
-      }
-    double rc = 0;
-    for (size_t i = 0; i < pts[t].x.size(); ++i) rc = std::max(rc, std::hypot(pts[t].x[i] - c.cx, pts[t].y[i] - c.cy));
-    c.rc = rc;
+    double lo, hi;
+    node_range(c.incl, node_off, x, y, c.cx, c.cy, lo, hi);
+    c.rc = hi;
   }
   if (nc == 1) return;
   const double inf = std::numeric_limits<double>::infinity();
+  std::vector<double> lb(nc), ub(nc), dmin(nc);
+  std::vector<char> isnear(nc);
+  std::vector<std::pair<double, int>> cand;
   for (int t = 0; t < nc; ++t) {
     CellPlan& c = cells[t];
-    // lower bounds |c_t - c_s| - r_s on the node distance, to visit cells nearest first
-    std::vector<std::pair<double, int>> order;
-    order.reserve(nc - 1);
-    for (int s = 0; s < nc; ++s)
-      if (s != t) {
-        double lb = std::hypot(cells[s].cx - c.cx, cells[s].cy - c.cy) - cells[s].rc;
-        order.push_back({lb - 1e-9 * (1.0 + std::fabs(lb)), s});  // safe lower bound
-      }
-    std::sort(order.begin(), order.end());
-    std::vector<double> dmin(nc, -1.0);
+    // bounds |c_t - c_s| -+ r_s on the distance from the centre of t to the nodes of s
+    // (widened by a relative 1e-9 against rounding); exact distances are computed only
+    // for the cells the bounds cannot settle
+    for (int s = 0; s < nc; ++s) {
+      const double ex = cells[s].cx - c.cx, ey = cells[s].cy - c.cy;
+      const double cd = std::sqrt(ex * ex + ey * ey);
+      const double l = cd - cells[s].rc, u = cd + cells[s].rc;
+      lb[s] = l - 1e-9 * (1.0 + std::fabs(l));
+      ub[s] = u + 1e-9 * (1.0 + u);
+      dmin[s] = -1.0;
+      isnear[s] = 0;
+    }
     auto dist = [&](int s) {
-      if (dmin[s] < 0) dmin[s] = min_dist(pts[s], c.cx, c.cy);
+      if (dmin[s] < 0) {
+        double lo, hi;
+        node_range(cells[s].incl, node_off, x, y, c.cx, c.cy, lo, hi);
+        dmin[s] = lo;
+      }
       return dmin[s];
     };
-    std::vector<char> isnear(nc, 0);
     if (o.near_rule == 0)
       for (int s = 0; s < nc; ++s)
         if (s != t && std::abs(cells[s].I - c.I) + std::abs(cells[s].J - c.J) == 1) isnear[s] = 1;
     double rho = inf, Rp = 0;
     bool anyfar = false;
     for (;;) {
-      rho = inf;
+      // rho: the nearest node of a far cell; only cells whose lower bound reaches below
+      // the smallest upper bound can hold it
+      double u = inf;
       anyfar = false;
-      for (auto& pr : order) {
-        if (isnear[pr.second]) continue;
-        anyfar = true;
-        if (pr.first > rho) break;
+      for (int s = 0; s < nc; ++s)
+        if (s != t && !isnear[s]) {
+          anyfar = true;
+          u = std::min(u, ub[s]);
+        }
+      cand.clear();
+      for (int s = 0; s < nc; ++s)
+        if (s != t && !isnear[s] && lb[s] <= u) cand.push_back({lb[s], s});
+      std::sort(cand.begin(), cand.end());
+      rho = inf;
+      for (const auto& pr : cand) {
+        if (pr.first > rho) break;   // nearest first: later cells cannot come closer
         rho = std::min(rho, dist(pr.second));
       }
       if (o.proxy_rule == 0 && anyfar)
         Rp = std::max(o.proxy_ratio * c.rc, 0.9 * rho);
       else
         Rp = o.proxy_ratio * c.rc;
+      // every far cell with a node inside the proxy circle becomes near
       bool added = false;
-      for (auto& pr : order) {
-        if (pr.first > Rp) break;
-        if (isnear[pr.second]) continue;
-        if (dist(pr.second) <= Rp) {
-          isnear[pr.second] = 1;
+      for (int s = 0; s < nc; ++s)
+        if (s != t && !isnear[s] && lb[s] <= Rp && dist(s) <= Rp) {
+          isnear[s] = 1;
           added = true;
         }
-      }
       if (!added) break;
     }
     c.near.clear();

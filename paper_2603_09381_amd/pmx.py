@@ -27,7 +27,7 @@ EXPORTS = [
     "pmx_probe_zgemm", "pmx_probe_lu_solve", "pmx_probe_id", "pmx_plan_query",
     "pmx_probe_cgemm", "pmx_probe_lu_solve_c32", "pmx_probe_id_c32", "pmx_probe_apply",
     "pmx_mlp_opts_default", "pmx_id_dataset", "pmx_mlp_train", "pmx_mlp_predict", "pmx_probe_mlp",
-    "pmx_autotune",
+    "pmx_autotune", "pmx_device_cache",
 ]
 
 
@@ -121,6 +121,7 @@ def load(path=None):
     lib.pmx_probe_mlp.argtypes = [C.c_int32] * 4 + [fp, fp, fp, C.c_int32, C.c_float, fp, fp,
                                                     C.POINTER(C.c_double), vp]
     lib.pmx_autotune.argtypes = [C.POINTER(Geometry), C.POINTER(Options), C.c_int32, C.c_int32, C.c_char_p, vp]
+    lib.pmx_device_cache.argtypes = [C.c_int64, C.POINTER(C.c_int64)]
     dp = C.POINTER(C.c_double)
     lib.pmx_plan_query.argtypes = [C.POINTER(Geometry), C.POINTER(Options), C.c_int32, C.c_int32,
                                    ip, ip, ip, ip, ip, dp, dp, dp, ip, ip, ip]
@@ -412,6 +413,15 @@ def id_dataset(w, path, append=False, opts=None):
     keep = _GeomKeep(w)
     o = options(w) if opts is None else opts
     _check(_lib.pmx_id_dataset(C.byref(keep.g), C.byref(o), str(path).encode(), int(bool(append)), _stream()))
+
+
+def device_cache(limit=-1):
+    """Bytes of device blocks the library keeps from destroyed factors for later ones; a
+    limit >= 0 first sets the cache limit and frees what exceeds it (0 empties it)."""
+    load()
+    held = C.c_int64(0)
+    _check(_lib.pmx_device_cache(int(limit), C.byref(held)))
+    return held.value
 
 
 def autotune(w, path, nrhs=None, reps=3, **kw):
