@@ -181,6 +181,9 @@ __global__ __launch_bounds__(256) void k_zgemm(F f, cx<R> alpha, cx<R> beta) {
   typedef typename AccT<R>::type V4;
   GemmArgsT<R> g;
   if (!f(blockIdx.z, g)) return;
+  const auto gA = gbl(g.A);
+  const auto gB = gbl(g.B);
+  const auto gC = gbl(g.C);
   const int tm = blockIdx.x * 64, tn = blockIdx.y * 64;
   if (tm >= g.m || tn >= g.n) return;
   __shared__ C As[8][64 + 1];
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(256) void k_zgemm(F f, cx<R> alpha, cx<R> beta) {
       }
       const int gi = tm + i, gk = k0 + kk;
       const int ci = min(gi, g.m - 1), ck = min(gk, g.k - 1);
-      C v = (OPA == OP_N) ? g.A[ci + (int64_t)ck * g.lda] : g.A[ck + (int64_t)ci * g.lda];
+      C v = (OPA == OP_N) ? gA[ci + (int64_t)ck * g.lda] : gA[ck + (int64_t)ci * g.lda];
       if (OPA == OP_C) v.im = -v.im;
       As[kk][i] = (gi < g.m && gk < g.k) ? v : cmk<R>(0, 0);
     }
@@ -224,7 +227,7 @@ __global__ __launch_bounds__(256) void k_zgemm(F f, cx<R> alpha, cx<R> beta) {
       }
       const int gj = tn + j, gk = k0 + kk;
       const int cj = min(gj, g.n - 1), ck = min(gk, g.k - 1);
-      C v = (OPB == OP_N) ? g.B[ck + (int64_t)cj * g.ldb] : g.B[cj + (int64_t)ck * g.ldb];
+      C v = (OPB == OP_N) ? gB[ck + (int64_t)cj * g.ldb] : gB[cj + (int64_t)ck * g.ldb];
       if (OPB == OP_C) v.im = -v.im;
       Bs[kk][j] = (gj < g.n && gk < g.k) ? v : cmk<R>(0, 0);
     }
@@ -260,7 +263,7 @@ __global__ __launch_bounds__(256) void k_zgemm(F f, cx<R> alpha, cx<R> beta) {
         const int col = tn + wn + bj * 16 + (lane & 15);
         if (row < g.m && col < g.n) {
           C v = zmul(alpha, cmk<R>(accR[bi][bj][r], accI[bi][bj][r]));
-          C* cp = g.C + row + (int64_t)col * g.ldc;
+          auto cp = gC + row + (int64_t)col * g.ldc;
           if (use_beta) v = zfma(beta, *cp, v);
           *cp = v;
         }
@@ -273,6 +276,78 @@ static void launch_zgemm(F f, int batch, int max_m, int max_n, cx<R> alpha, cx<R
   dim3 grid((max_m + 63) / 64, (max_n + 63) / 64, batch);
   KScope ks(PK_ZGEMM, s);
   hipLaunchKernelGGL((k_zgemm<R, OPA, OPB, F>), grid, dim3(256), 0, s, f, alpha, beta);
+}
+
+// C = alpha A B + beta C for few columns of B (n <= NB, both operands untransposed): the
+// product is bound by reading A, which MFMA tiles of 64 columns would mostly waste.  A
+// workgroup of four waves takes 64 rows of one matrix; wave w accumulates the k range
+// [w kc, (w + 1) kc) with one row per lane (the column-major A is read 64 consecutive
+// rows at a time, coalesced) and the row of B of each k read at a wave-uniform address;
+// the four partial sums are added through LDS.
+template <class R, int NB, class F>
+__global__ __launch_bounds__(256) void k_zgemm_skinny(F f, cx<R> alpha, cx<R> beta) {
+  typedef cx<R> C;
+  GemmArgsT<R> g;
+  if (!f(blockIdx.z, g)) return;
+  const auto gB = gbl(g.B);
+  const int tm = blockIdx.x * 64;
+  if (tm >= g.m) return;
+  __shared__ C red[3][NB][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = min(tm + lane, g.m - 1);
+  const int kc = (g.k + 3) / 4;
+  const int k0 = min(wave * kc, g.k), k1 = min(k0 + kc, g.k);
+  const int n = min(g.n, NB);
+  R ar[NB], ai[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) ar[j] = ai[j] = R(0);
+  const auto Ap = gbl(g.A) + row;
+#pragma unroll 4
+  for (int kk = k0; kk < k1; ++kk) {
+    const C a = Ap[(int64_t)kk * g.lda];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (j < n) {
+        const C b = gB[kk + (int64_t)j * g.ldb];
+        ar[j] = fma(a.re, b.re, ar[j]);
+        ar[j] = fma(-a.im, b.im, ar[j]);
+        ai[j] = fma(a.re, b.im, ai[j]);
+        ai[j] = fma(a.im, b.re, ai[j]);
+      }
+    }
+  }
+  if (wave > 0) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) red[wave - 1][j][lane] = cmk<R>(ar[j], ai[j]);
+  }
+  __syncthreads();
+  if (wave > 0 || tm + lane >= g.m) return;
+  const bool use_beta = (beta.re != R(0) || beta.im != R(0));
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j < n) {
+      C v = cmk<R>(ar[j], ai[j]);
+#pragma unroll
+      for (int w = 0; w < 3; ++w) v = zadd(v, red[w][j][lane]);
+      v = zmul(alpha, v);
+      auto cp = gbl(g.C) + (tm + lane) + (int64_t)j * g.ldc;
+      if (use_beta) v = zfma(beta, *cp, v);
+      *cp = v;
+    }
+  }
+}
+
+template <class R, class F>
+static bool launch_zgemm_skinny(F f, int batch, int max_m, int max_n, cx<R> alpha, cx<R> beta, hipStream_t s) {
+  if (max_n > 8) return false;
+  if (batch <= 0 || max_m <= 0 || max_n <= 0) return true;
+  dim3 grid((max_m + 63) / 64, 1, batch);
+  KScope ks(PK_ZGEMM, s);
+  if (max_n <= 4)
+    hipLaunchKernelGGL((k_zgemm_skinny<R, 4, F>), grid, dim3(256), 0, s, f, alpha, beta);
+  else
+    hipLaunchKernelGGL((k_zgemm_skinny<R, 8, F>), grid, dim3(256), 0, s, f, alpha, beta);
+  return true;
 }
 
 template <class R>
@@ -288,6 +363,7 @@ template <class R>
 void la_zgemm_list(int opa, int opb, const GemmArgsT<R>* d_list, int batch, int max_m, int max_n, cx<R> alpha,
                    cx<R> beta, hipStream_t s) {
   FList<R> f{d_list};
+  if (opa == OP_N && opb == OP_N && launch_zgemm_skinny<R>(f, batch, max_m, max_n, alpha, beta, s)) return;
 #define PMX_G(A, B)                                                \
   if (opa == A && opb == B) {                                      \
     launch_zgemm<R, A, B>(f, batch, max_m, max_n, alpha, beta, s); \
@@ -319,6 +395,8 @@ __global__ __launch_bounds__(64) void k_trsm_small(F f) {
   typedef cx<R> C;
   TrsmArgs<R> a;
   if (!f(blockIdx.y, a)) return;
+  const auto gT = gbl(a.T);
+  const auto gB = gbl(a.B);
   __shared__ C Ts[32][32];
   __shared__ C dinv[32];
   const int tid = threadIdx.x;
@@ -326,15 +404,15 @@ __global__ __launch_bounds__(64) void k_trsm_small(F f) {
   const int nb = a.nb;
   for (int e = tid; e < nb * nb; e += 64) {
     const int r = e % nb, c = e / nb;
-    Ts[r][c] = a.T[r + (int64_t)c * a.ldt];
+    Ts[r][c] = gT[r + (int64_t)c * a.ldt];
   }
-  if (!UNIT && tid < nb) dinv[tid] = zrecip(a.T[tid + (int64_t)tid * a.ldt]);
+  if (!UNIT && tid < nb) dinv[tid] = zrecip(gT[tid + (int64_t)tid * a.ldt]);
   const int col = blockIdx.x * 64 + tid;
   const bool active = col < a.nrhs;
   const int cl = active ? col : a.nrhs - 1;   // idle lanes follow the last column and store nothing
   C x[32];
 #pragma unroll
-  for (int i = 0; i < 32; ++i) x[i] = (i < nb) ? a.B[i + (int64_t)cl * a.ldb] : cmk<R>(0, 0);
+  for (int i = 0; i < 32; ++i) x[i] = (i < nb) ? gB[i + (int64_t)cl * a.ldb] : cmk<R>(0, 0);
   __syncthreads();
   if (!UPPER) {
 #pragma unroll
@@ -359,7 +437,7 @@ __global__ __launch_bounds__(64) void k_trsm_small(F f) {
   if (active) {
 #pragma unroll
     for (int i = 0; i < 32; ++i)
-      if (i < nb) a.B[i + (int64_t)col * a.ldb] = x[i];
+      if (i < nb) gB[i + (int64_t)col * a.ldb] = x[i];
   }
 }
 
@@ -382,7 +460,7 @@ __global__ __launch_bounds__(256) void k_getrf_panel(const LuDescT<R>* lus, int 
   __shared__ double redv[4];
   __shared__ int redi[4];
   const int tid = threadIdx.x;
-  C* A = L.a;
+  const auto A = gbl(L.a);
   const int64_t ld = L.ld;
   for (int c = j0; c < j0 + jb; ++c) {
     double best = -1.0;
@@ -395,7 +473,7 @@ __global__ __launch_bounds__(256) void k_getrf_panel(const LuDescT<R>* lus, int 
     double bestv;
     const int p = block_argmax<256>(best, bi, redv, redi, &bestv);
     if (tid == 0) {
-      L.ipiv[c] = p;
+      gbl(L.ipiv)[c] = p;
       if (bestv == 0.0 && info && info[blockIdx.x] == 0) info[blockIdx.x] = c + 1;
     }
     if (p != c) {
@@ -434,7 +512,7 @@ __global__ __launch_bounds__(NT) void k_getrf_panel_reg(const LuDescT<R>* lus, i
   __shared__ int redi[NT / 64];
   __shared__ C prow[PMX_LU_NB], crow[PMX_LU_NB];
   const int tid = threadIdx.x;
-  C* A = L.a;
+  const auto A = gbl(L.a);
   const int64_t ld = L.ld;
   C P[RPT][PMX_LU_NB];
 #pragma unroll
@@ -461,7 +539,7 @@ __global__ __launch_bounds__(NT) void k_getrf_panel_reg(const LuDescT<R>* lus, i
     double bestv;
     const int p = block_argmax<NT>(best, bi, redv, redi, &bestv);
     if (tid == 0) {
-      L.ipiv[col] = p;
+      gbl(L.ipiv)[col] = p;
       if (bestv == 0.0 && info && info[blockIdx.x] == 0) info[blockIdx.x] = col + 1;
     }
     // exchange rows col and p through LDS
@@ -544,7 +622,7 @@ __global__ __launch_bounds__(NT) void k_getrf_panel_u(const LuDescT<R>* lus, int
   __shared__ int si[NW];
   __shared__ C prow[NB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  C* A = L.a;
+  const auto A = gbl(L.a);
   const int64_t ld = L.ld;
   C P[RPT][NB];
   int pos[RPT];
@@ -576,7 +654,7 @@ __global__ __launch_bounds__(NT) void k_getrf_panel_u(const LuDescT<R>* lus, int
 #pragma unroll
     for (int w = 1; w < NW; ++w) argmax_pair(bv, p, sv[w], si[w]);
     if (tid == 0) {
-      L.ipiv[col] = p;
+      gbl(L.ipiv)[col] = p;
       if (bv == 0.0 && info && info[blockIdx.x] == 0) info[blockIdx.x] = col + 1;
     }
 #pragma unroll
@@ -627,7 +705,7 @@ __global__ void k_laswp_panel(const LuDescT<R>* lus, int j0) {
   if (col >= j0) col += jb;
   cx<R>* A = L.a + col * L.ld;
   for (int c = j0; c < j0 + jb; ++c) {
-    int p = L.ipiv[c];
+    int p = gbl(L.ipiv)[c];
     if (p != c) {
       cx<R> t = A[c];
       A[c] = A[p];
@@ -686,13 +764,13 @@ __global__ __launch_bounds__(256) void k_lu_perm(const LuDescT<R>* lus) {
   __syncthreads();
   if (threadIdx.x == 0)
     for (int i = 0; i < L.n; ++i) {
-      const int p = L.ipiv[i];
+      const int p = gbl(L.ipiv)[i];
       const int t = pl[i];
       pl[i] = pl[p];
       pl[p] = t;
     }
   __syncthreads();
-  for (int i = threadIdx.x; i < L.n; i += 256) L.perm[i] = pl[i];
+  for (int i = threadIdx.x; i < L.n; i += 256) gbl(L.perm)[i] = pl[i];
 }
 
 // whether panel variant v holds `rows` panel rows (registers: 256, 512, 1024 rows; the
@@ -785,7 +863,7 @@ __global__ void k_laswp_rhs(const LuDescT<R>* lus, const MatT<R>* bs) {
   if (col >= B.n) return;
   cx<R>* x = B.p + col * B.ld;
   for (int c = 0; c < L.n; ++c) {
-    int p = L.ipiv[c];
+    int p = gbl(L.ipiv)[c];
     if (p != c) {
       cx<R> t = x[c];
       x[c] = x[p];
@@ -895,15 +973,17 @@ template <class R, int NRC>
 __device__ inline void getrs_update(const cx<R>* A, int64_t ld, cx<R>* W, int64_t ldw, int c0, int nc, int i0, int i1,
                                     int j0, int jb, const cx<R> (*xb)[NRC]) {
   typedef cx<R> C;
+  const auto Ag = gbl(A);
+  const auto Wg = gbl(W);
   for (int i = i0 + (int)threadIdx.x; i < i1; i += GS_NT) {
     C acc[NRC];
 #pragma unroll
-    for (int c = 0; c < NRC; ++c) acc[c] = (c < nc) ? W[i + (int64_t)(c0 + c) * ldw] : cmk<R>(0, 0);
+    for (int c = 0; c < NRC; ++c) acc[c] = (c < nc) ? Wg[i + (int64_t)(c0 + c) * ldw] : cmk<R>(0, 0);
 #pragma unroll
     for (int h = 0; h < 32; h += 16) {
       C l[16];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) l[k] = A[i + (int64_t)(j0 + min(h + k, jb - 1)) * ld];
+      for (int k = 0; k < 16; ++k) l[k] = Ag[i + (int64_t)(j0 + min(h + k, jb - 1)) * ld];
 #pragma unroll
       for (int k = 0; k < 16; ++k)
         if (h + k < jb) {
@@ -913,7 +993,7 @@ __device__ inline void getrs_update(const cx<R>* A, int64_t ld, cx<R>* W, int64_
     }
 #pragma unroll
     for (int c = 0; c < NRC; ++c)
-      if (c < nc) W[i + (int64_t)(c0 + c) * ldw] = acc[c];
+      if (c < nc) Wg[i + (int64_t)(c0 + c) * ldw] = acc[c];
   }
 }
 
@@ -928,12 +1008,12 @@ __global__ __launch_bounds__(GS_NT) void k_getrs_small(const LuDescT<R>* lus, co
   const int nc = min(NRC, B.n - c0);
   if (n <= 0 || nc <= 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const C* A = L.a;
+  const auto A = gbl(L.a);
   const int64_t ld = L.ld;
   __shared__ C xb[32][NRC];
   for (int e = tid; e < n * nc; e += GS_NT) {
     const int i = e % n, c = e / n;
-    W.p[i + (int64_t)(c0 + c) * W.ld] = B.p[L.perm[i] + (int64_t)(c0 + c) * B.ld];
+    gbl(W.p)[i + (int64_t)(c0 + c) * W.ld] = gbl(B.p)[gbl(L.perm)[i] + (int64_t)(c0 + c) * B.ld];
   }
   __syncthreads();
   // forward: L unit lower
@@ -1009,11 +1089,13 @@ __global__ __launch_bounds__(NT) void k_getrs_lds(const LuDescT<R>* lus, const M
   extern __shared__ char gs_smem[];
   C* xs = reinterpret_cast<C*>(gs_smem);   // xs[c * n + i]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const C* A = L.a;
+  const auto A = gbl(L.a);
+  const auto Bp = gbl(B.p);
+  const auto perm = gbl(L.perm);
   const int64_t ld = L.ld;
   for (int e = tid; e < n * NRC; e += NT) {
     const int i = e % n, c = e / n;
-    xs[e] = (c < nc) ? B.p[L.perm[i] + (int64_t)(c0 + c) * B.ld] : cmk<R>(0, 0);
+    xs[e] = (c < nc) ? Bp[perm[i] + (int64_t)(c0 + c) * B.ld] : cmk<R>(0, 0);
   }
   __syncthreads();
   // forward: L unit lower
@@ -1102,7 +1184,7 @@ __global__ __launch_bounds__(NT) void k_getrs_lds(const LuDescT<R>* lus, const M
   }
   for (int e = tid; e < n * nc; e += NT) {
     const int i = e % n, c = e / n;
-    B.p[i + (int64_t)(c0 + c) * B.ld] = xs[c * n + i];
+    Bp[i + (int64_t)(c0 + c) * B.ld] = xs[c * n + i];
   }
 }
 
@@ -1234,7 +1316,7 @@ __global__ __launch_bounds__(NT) void k_ts_leaf(const QrDescT<R>* qrs, int j0, i
   __shared__ double sh_tau;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int phys = (t < nrb) ? ts_phys(b * PMX_TS_BR + t, L, jb, j0, g) : -1;
-  C* A = Q.a;
+  const auto A = gbl(Q.a);
   const int64_t ld = Q.ld;
   if (t < PMX_TS_BR) {
     const int pr = phys >= 0 ? phys : j0;
@@ -1344,8 +1426,8 @@ __global__ __launch_bounds__(NT) void k_ts_leaf(const QrDescT<R>* qrs, int j0, i
   }
   if (t >= PMX_TS_BR) return;
   const int64_t wo = ts_sel64(L, g.wo0, g.wo1, g.wo2, g.wo3) + (int64_t)b * PMX_TS_BR * PMX_QR_NB;
-  C* V = Q.v + wo;
-  C* VT = Q.t + wo;
+  const auto V = gbl(Q.v) + wo;
+  const auto VT = gbl(Q.t) + wo;
   C vrow[PMX_QR_NB];
 #pragma unroll
   for (int i = 0; i < PMX_QR_NB; ++i) {
@@ -1385,14 +1467,14 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDescT<R>* qrs, int j0
   if (b >= ts_sel(L, g.nb0, g.nb1, g.nb2, g.nb3)) return;
   const int nrb = min(PMX_TS_BR, ts_sel(L, g.mr0, g.mr1, g.mr2, g.mr3) - b * PMX_TS_BR);
   const int64_t wo = ts_sel64(L, g.wo0, g.wo1, g.wo2, g.wo3) + (int64_t)b * PMX_TS_BR * PMX_QR_NB;
-  const C* V = Q.v + wo;
-  const C* VT = Q.t + wo;
+  const auto V = gbl(Q.v) + wo;
+  const auto VT = gbl(Q.t) + wo;
   __shared__ C Vs[TSU_ROWS][PMX_QR_NB + 1];
   __shared__ C As[TSU_ROWS][64 + 1];
   __shared__ C Ws[PMX_QR_NB][64 + 1];
   __shared__ int rows[TSU_ROWS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  C* A = Q.a;
+  const auto A = gbl(Q.a);
   const int64_t ld = Q.ld;
   const int ccol0 = j0 + jb + c0;
   // W = V^H A_b: output PMX_QR_NB x 64 as (NB/16) x 4 blocks of 16x16, NB/16 per wave
@@ -1486,7 +1568,7 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDescT<R>* qrs, int j0
         const int col = (cbk0 + q) * 16 + (lane & 15);
         const int pr = rows[row];
         if (pr >= 0 && c0 + col < nc) {
-          C* ap = A + pr + (int64_t)(ccol0 + col) * ld;
+          const auto ap = A + pr + (int64_t)(ccol0 + col) * ld;
           *ap = zsub(*ap, cmk<R>(dR[q][r], dI[q][r]));
         }
       }
@@ -1590,9 +1672,12 @@ __device__ constexpr double cp_recompute_ratio<float>() {
 // apply the current reflector (vs, rows j..mb-1) to column l and downdate its norm;
 // one wave per column, lane 0 ends with row j
 template <class R>
-__device__ inline void cp_apply_column(cx<R>* col, const cx<R>* vs, int j, int mb, double tau, double* nrm,
-                                       int c, int l, int lane, const double* extra) {
+__device__ inline void cp_apply_column(cx<R>* col_, const cx<R>* vs, int j, int mb, double tau, double* nrm_,
+                                       int c, int l, int lane, const double* extra_) {
   typedef cx<R> C;
+  const auto col = gbl(col_);
+  const auto nrm = gbl(nrm_);
+  const auto extra = gbl(extra_);
   R wr = 0, wi = 0;
   for (int r = j + lane; r < mb; r += 64) {
     const C t = zcmul(vs[r - j], col[r]);
@@ -1638,12 +1723,12 @@ __global__ __launch_bounds__(CP_NT) void k_cpqr(const CpqrDescT<R>* cps, double 
   __shared__ C sh_scale;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nw = CP_NT / 64;
-  C* B = Cd.b;
+  const auto B = gbl(Cd.b);
   const int mb = Cd.mb, c = Cd.c;
   const int64_t ld = mb;
   const int cpiv = Cd.cpiv;
   const int kmax = min(min(mb, c), cpiv);
-  double* nrm = Cd.nrm;
+  const auto nrm = gbl(Cd.nrm);
   if (init) {
     for (int l = wave; l < c; l += nw) {
       double p = 0;
@@ -1790,7 +1875,7 @@ __global__ __launch_bounds__(256) void k_cpqr_pivot(const CpqrDescT<R>* cps, dou
   __shared__ int sh_stop;
   __shared__ C sh_scale;
   const int tid = threadIdx.x;
-  C* B = Cd.b;
+  const auto B = gbl(Cd.b);
   const int mb = Cd.mb, c = Cd.c;
   const int64_t ld = mb;
   const int cpiv = Cd.cpiv;
@@ -1805,7 +1890,7 @@ __global__ __launch_bounds__(256) void k_cpqr_pivot(const CpqrDescT<R>* cps, dou
     }
     return;
   }
-  double* nrm = Cd.nrm;
+  const auto nrm = gbl(Cd.nrm);
   double big = 0;
   if (j == 0 && cpiv < c) {
     // restricted pivoting: the threshold refers to the largest column of the whole matrix
@@ -1892,7 +1977,7 @@ __global__ __launch_bounds__(256) void k_cpqr_update(const CpqrDescT<R>* cps) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int mb = Cd.mb, c = Cd.c;
   const int64_t ld = mb;
-  for (int r = j + tid; r < mb; r += 256) vs[r - j] = Cd.v[r - j];
+  for (int r = j + tid; r < mb; r += 256) vs[r - j] = gbl(Cd.v)[r - j];
   __syncthreads();
   const double tau = *Cd.tau;
   for (int l = l0 + wave; l < min(l0 + 16, c); l += 4) {

@@ -11,6 +11,23 @@ struct cx {
 typedef cx<double> zd;
 typedef cx<float> zf;
 
+// The same pointer in the global address space.  Pointers read from descriptors in memory
+// are generic to the compiler, which then emits flat loads and stores: those also count
+// against the LDS wait counter, so every wait for an LDS read waits for the outstanding
+// global loads as well, and at most 15 can be in flight.  Accesses through the returned
+// pointer compile to global_load / global_store.  Only for device memory.
+template <class T>
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ inline __attribute__((address_space(1))) T* gbl(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+#else
+// the host pass only checks kernel bodies; it keeps the pointer as it is
+__host__ __device__ inline T* gbl(T* p) {
+  return p;
+}
+#endif
+
 template <class R>
 __host__ __device__ inline cx<R> cmk(R r, R i) {
   cx<R> z;

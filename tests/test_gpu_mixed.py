@@ -29,7 +29,8 @@ def c64(a):
 
 
 @pytest.mark.parametrize("opa,opb", [(0, 0), (0, 1), (0, 2), (1, 0), (2, 0), (2, 2)])
-@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (37, 5, 70), (130, 129, 17), (64, 64, 0), (16, 16, 4)])
+@pytest.mark.parametrize("m,n,k", [(1, 1, 1), (37, 5, 70), (130, 129, 17), (64, 64, 0), (16, 16, 4), (256, 4, 256),
+                                   (300, 7, 600)])
 def test_cgemm_fp32(pmx, opa, opb, m, n, k):
     batch = 3
     A = c64(crandn(batch, m, k) if opa == 0 else crandn(batch, k, m))

@@ -46,6 +46,21 @@ def test_zgemm(pmx, opa, opb, m, n, k):
     assert np.abs(got - ref).max() < 1e-13 * scale * max(1, k)
 
 
+@pytest.mark.parametrize("m,n,k", [(256, 4, 256), (300, 8, 1000), (65, 3, 2), (130, 6, 129), (64, 1, 5),
+                                   (1, 4, 3), (200, 4, 0)])
+def test_zgemm_few_columns(pmx, m, n, k):
+    """Untransposed products with at most 8 columns take the row-per-lane kernel (4- and
+    8-column instances, k split over four waves with ragged ends, rows beyond a multiple of
+    64, k = 0)."""
+    batch = 3
+    A = crandn(batch, m, k)
+    B = crandn(batch, k, n)
+    ref = A @ B
+    got = pmx.probe_zgemm(A, B, 0, 0)
+    scale = max(1.0, np.abs(ref).max())
+    assert np.abs(got - ref).max() < 1e-13 * scale * max(1, k)
+
+
 @pytest.mark.parametrize("variant", [-1, 0, 1, 2])
 @pytest.mark.parametrize("n,nrhs", [(1, 1), (31, 3), (64, 1), (100, 40), (257, 7), (33, 5), (100, 80),
                                     (300, 65), (1100, 4), (700, 9)])
