@@ -1077,7 +1077,7 @@ __global__ __launch_bounds__(GS_NT) void k_getrs_small(const LuDescT<R>* lus, co
 // of each trailing update, whose BS factors it loads in two halves.  Rows beyond n and
 // right-hand sides beyond the matrix's count are padded with zeros and not stored.
 template <class R, int NRC, int NT, int BS>
-__global__ __launch_bounds__(NT) void k_getrs_lds(const LuDescT<R>* lus, const MatT<R>* bs) {
+__global__ __launch_bounds__(NT) void k_getrs_lds_wide(const LuDescT<R>* lus, const MatT<R>* bs) {
   typedef cx<R> C;
   constexpr int HB = BS / 2;
   const LuDescT<R> L = lus[blockIdx.x];
@@ -1188,29 +1188,226 @@ __global__ __launch_bounds__(NT) void k_getrs_lds(const LuDescT<R>* lus, const M
   }
 }
 
+// The LDS-resident solve with its waves in two roles and the loads of the factor issued one
+// block ahead.  Wave 0 solves the diagonal blocks (one lane per row of the block, the four
+// right-hand sides at once, solved values broadcast by readlane).  The other NTT threads own
+// fixed rows (thread t: rows t + q NTT, q < RPT) and keep their rows of the solution block
+// in registers across the whole sweep; per block they subtract the block's contribution,
+// with the block's factor columns of their first row already in registers, and store a row
+// to LDS only when it enters the next diagonal block.  Right after its use, each role issues
+// the loads of the next block (wave 0: the next diagonal block's row; the others: the next
+// block's columns of their first row), so that the loads overlap the other role's work
+// instead of following it.  Two barriers per block.  Rows beyond n and right-hand sides
+// beyond the matrix's count are padded with zeros and not stored; the block of a lane
+// beyond the block's rows is clamped to its last row.
+template <class R, int NTT, int RPT, int BS, int NRC>
+__global__ __launch_bounds__(64 + NTT) void k_getrs_lds(const LuDescT<R>* lus, const MatT<R>* bs) {
+  typedef cx<R> C;
+  constexpr int NT = 64 + NTT;
+  const LuDescT<R> L = lus[blockIdx.x];
+  const MatT<R> B = bs[blockIdx.x];
+  const int n = L.n;
+  const int c0 = blockIdx.y * NRC;
+  const int nc = min(NRC, B.n - c0);
+  if (n <= 0 || nc <= 0) return;
+  extern __shared__ char gs_smem[];
+  C* xs = reinterpret_cast<C*>(gs_smem);   // xs[c * n + i]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const bool dw = tid < 64;
+  const int t = tid - 64;
+  const auto A = gbl(L.a);
+  const auto Bp = gbl(B.p);
+  const auto perm = gbl(L.perm);
+  const int64_t ld = L.ld;
+  for (int e = tid; e < n * NRC; e += NT) {
+    const int i = e % n, c = e / n;
+    xs[e] = (c < nc) ? Bp[perm[i] + (int64_t)(c0 + c) * B.ld] : cmk<R>(0, 0);
+  }
+  C buf[BS];             // wave 0: its row of the diagonal block; others: the block of their first row
+  C acc[RPT][NRC];       // others: their rows of the solution block (wave 0: the block's values)
+#define PMX_GS_LOAD(r, j, jb)                                                    \
+  _Pragma("unroll") for (int k = 0; k < BS; ++k) buf[k] = A[(r) + (int64_t)((j) + min(k, (jb) - 1)) * ld]
+  // ---- forward: L unit lower
+  {
+    const int jb = min(BS, n);
+    if (dw) {
+      PMX_GS_LOAD(min(lane, jb - 1), 0, jb);
+    } else if (t >= jb && t < n) {
+      PMX_GS_LOAD(t, 0, jb);
+    }
+  }
+  __syncthreads();
+  if (!dw) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = t + q * NTT;
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) acc[q][c] = (r < n) ? xs[c * n + r] : cmk<R>(0, 0);
+    }
+  }
+  for (int j0 = 0; j0 < n; j0 += BS) {
+    const int jb = min(BS, n - j0);
+    const int j1 = j0 + BS;
+    const int jb1 = min(BS, n - j1);
+    if (dw) {
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) acc[0][c] = (lane < jb) ? xs[c * n + j0 + lane] : cmk<R>(0, 0);
+#pragma unroll
+      for (int k = 0; k < BS; ++k) {
+        if (k < jb) {
+#pragma unroll
+          for (int c = 0; c < NRC; ++c) {
+            const C xk = readlane(acc[0][c], k);
+            if (lane > k) acc[0][c] = zsub(acc[0][c], zmul(buf[k], xk));
+          }
+        }
+      }
+      if (lane < jb) {
+#pragma unroll
+        for (int c = 0; c < NRC; ++c) xs[c * n + j0 + lane] = acc[0][c];
+      }
+      if (j1 < n) PMX_GS_LOAD(j1 + min(lane, jb1 - 1), j1, jb1);
+    }
+    __syncthreads();
+    if (!dw) {
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int r = t + q * NTT;
+        if (r >= j0 + jb && r < n) {
+          if (q > 0) PMX_GS_LOAD(r, j0, jb);
+#pragma unroll
+          for (int k = 0; k < BS; ++k) {
+            if (k < jb) {
+#pragma unroll
+              for (int c = 0; c < NRC; ++c) acc[q][c] = zsub(acc[q][c], zmul(buf[k], xs[c * n + j0 + k]));
+            }
+          }
+          if (r < j1 + jb1) {
+#pragma unroll
+            for (int c = 0; c < NRC; ++c) xs[c * n + r] = acc[q][c];
+          }
+        }
+      }
+      if (j1 < n && t >= j1 + jb1 && t < n) PMX_GS_LOAD(t, j1, jb1);
+    }
+    __syncthreads();
+  }
+  // ---- backward: U upper with its diagonal
+  const int jl = ((n - 1) / BS) * BS;
+  {
+    const int jb = n - jl;
+    if (dw) {
+      PMX_GS_LOAD(jl + min(lane, jb - 1), jl, jb);
+    } else if (t < jl) {
+      PMX_GS_LOAD(t, jl, jb);
+    }
+  }
+  if (!dw) {
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = t + q * NTT;
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) acc[q][c] = (r < n) ? xs[c * n + r] : cmk<R>(0, 0);
+    }
+  }
+  for (int j0 = jl; j0 >= 0; j0 -= BS) {
+    const int jb = min(BS, n - j0);
+    const int j1 = j0 - BS;
+    if (dw) {
+      C dinv = buf[0];
+#pragma unroll
+      for (int k = 1; k < BS; ++k)
+        if (k == lane) dinv = buf[k];
+      dinv = zrecip(dinv);
+#pragma unroll
+      for (int c = 0; c < NRC; ++c) acc[0][c] = (lane < jb) ? xs[c * n + j0 + lane] : cmk<R>(0, 0);
+#pragma unroll
+      for (int k = BS - 1; k >= 0; --k) {
+        if (k < jb) {
+#pragma unroll
+          for (int c = 0; c < NRC; ++c) {
+            if (lane == k) acc[0][c] = zmul(acc[0][c], dinv);
+            const C xk = readlane(acc[0][c], k);
+            if (lane < k) acc[0][c] = zsub(acc[0][c], zmul(buf[k], xk));
+          }
+        }
+      }
+      if (lane < jb) {
+#pragma unroll
+        for (int c = 0; c < NRC; ++c) xs[c * n + j0 + lane] = acc[0][c];
+      }
+      if (j1 >= 0) PMX_GS_LOAD(j1 + min(lane, BS - 1), j1, BS);
+    }
+    __syncthreads();
+    if (!dw) {
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int r = t + q * NTT;
+        if (r < j0) {
+          if (q > 0) PMX_GS_LOAD(r, j0, jb);
+#pragma unroll
+          for (int k = 0; k < BS; ++k) {
+            if (k < jb) {
+#pragma unroll
+              for (int c = 0; c < NRC; ++c) acc[q][c] = zsub(acc[q][c], zmul(buf[k], xs[c * n + j0 + k]));
+            }
+          }
+          if (r >= j1) {
+#pragma unroll
+            for (int c = 0; c < NRC; ++c) xs[c * n + r] = acc[q][c];
+          }
+        }
+      }
+      if (j1 >= 0 && t < j1) PMX_GS_LOAD(t, j1, BS);
+    }
+    __syncthreads();
+  }
+#undef PMX_GS_LOAD
+  for (int e = tid; e < n * nc; e += NT) {
+    const int i = e % n, c = e / n;
+    Bp[i + (int64_t)(c0 + c) * B.ld] = xs[c * n + i];
+  }
+}
+
 // LDS-resident level solve for up to 4 right-hand sides per workgroup; false when the
 // solution block does not fit (the caller then uses another variant)
 template <class R>
 bool la_getrs_lds(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max_n, int max_nrhs, hipStream_t s) {
-  constexpr int NRC = 4;
-  const size_t shm = (size_t)max_n * NRC * sizeof(cx<R>);
-  if (shm > 128 * 1024 || max_n <= 0) return false;
-  constexpr int BS = sizeof(R) == 4 ? 64 : 32;
-  const dim3 grid(batch, (max_nrhs + NRC - 1) / NRC);
+  const size_t shm4 = (size_t)max_n * 4 * sizeof(cx<R>);
+  if (shm4 > 128 * 1024 || max_n <= 0) return false;
+  // few matrices: one workgroup per right-hand side, so that more compute units share the
+  // sequential sweeps (each reads the factor once more); many: four right-hand sides each
+  const int nrc = (batch * max_nrhs <= 256 && max_n <= 1920) ? 1 : 4;
+  const size_t shm = (size_t)max_n * nrc * sizeof(cx<R>);
+  const dim3 grid(batch, (max_nrhs + nrc - 1) / nrc);
   KScope ks(PK_GETRS, s);
-  if (max_n <= 256) {
-    auto k = k_getrs_lds<R, NRC, 256, BS>;
-    if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k, grid, dim3(256), shm, s, d_lu, d_b);
-  } else if (max_n <= 512) {
-    auto k = k_getrs_lds<R, NRC, 512, BS>;
-    if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k, grid, dim3(512), shm, s, d_lu, d_b);
+  auto go = [&](auto kern, int nt) {
+    if (shm > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(kern, grid, dim3(nt), shm, s, d_lu, d_b);
+  };
+  // blocks of 32 rows (FP32) or 16 (FP64): the row held in registers stays at 64 of them
+  constexpr int BS = sizeof(R) == 4 ? 32 : 16;
+  if (nrc == 1) {
+    if (max_n <= 256)
+      go(k_getrs_lds<R, 256, 1, BS, 1>, 320);
+    else if (max_n <= 448)
+      go(k_getrs_lds<R, 448, 1, BS, 1>, 512);
+    else if (max_n <= 960)
+      go(k_getrs_lds<R, 960, 1, BS, 1>, 1024);
+    else
+      go(k_getrs_lds<R, 960, 2, BS, 1>, 1024);
+  } else if (max_n <= 256) {
+    go(k_getrs_lds<R, 256, 1, BS, 4>, 320);
+  } else if (max_n <= 448) {
+    go(k_getrs_lds<R, 448, 1, BS, 4>, 512);
+  } else if (max_n <= 960) {
+    go(k_getrs_lds<R, 960, 1, BS, 4>, 1024);
+  } else if (max_n <= 1920) {
+    go(k_getrs_lds<R, 960, 2, BS, 4>, 1024);
   } else {
-    // 1024 threads leave 128 registers each: half the diagonal block
-    auto k = k_getrs_lds<R, NRC, 1024, BS / 2>;
-    if (shm > 64 * 1024) (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k, grid, dim3(1024), shm, s, d_lu, d_b);
+    // 1024 threads leave 128 registers each: diagonal blocks of 32 (FP32) or 16 rows
+    go(k_getrs_lds_wide<R, 4, 1024, sizeof(R) == 4 ? 32 : 16>, 1024);
   }
   return true;
 }
