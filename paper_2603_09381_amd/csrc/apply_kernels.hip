@@ -20,8 +20,8 @@
 //   A_n = -e+ Mq_n + Mu_n,  B_n = -Mq_n + Mu_n / e+,
 //   Mq_n = sum_y R_n q~,  Mu_n = (k/2) sum_y (-nu R_{n+1} + conj(nu) R_{n-1}) u~.
 // The truncation order of a (wave, inclusion) pair is the larger of the order the sources'
-// J_n decay needs and ceil(39.2 / ln(rho_min / r_j)) (rho_min: the centre's distance to the
-// wave's bounding circle), so that dropped terms stay below 1e-17 of the kept ones.
+// J_n decay needs and ceil(PMX_APPLY_TRUNC / ln(rho_min / r_j)) (rho_min: the centre's distance
+// to the wave's bounding circle), so that dropped terms stay below about 1e-17 of the kept ones.
 #include "assemble.h"
 #include "bessel.h"
 #include "hankel_fast.h"
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
     const double pj = A.incl_geo[4 * j + 3];
     // truncation order of the pair (uniform)
     const double rmin = sqrt((wcx - cx) * (wcx - cx) + (wcy - cy) * (wcy - cy)) - wr;
-    const double pr = fmax(pj, ceil(39.2 / log(rmin / rj)));
+    const double pr = fmax(pj, ceil(PMX_APPLY_TRUNC / log(rmin / rj)));
     const int p = __builtin_amdgcn_readfirstlane((int)fmin(pr, (double)PMX_APPLY_PMAX));
     const double dx = ax - cx, dy = ay - cy;
     const double irho = rsqrt_nr(dx * dx + dy * dy);

@@ -142,6 +142,9 @@ void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s);
 // inclusions, split_incl).  Partial sums go to part [nsplit + nsplit_near][nrhs][ld].
 #define PMX_APPLY_RATIO 3.0
 #define PMX_APPLY_PMAX 48
+// truncation of a far pair: orders until (r_j / rho_min)^p <= e^-PMX_APPLY_TRUNC, about 1e-17
+// (on the star grids the sources' own order, from k r_j, is the larger one for most pairs)
+#define PMX_APPLY_TRUNC 39.2
 // coefficient records per inclusion: orders m = 0 .. PMX_APPLY_PMAX + 1, per right-hand side
 // six complex numbers A_m, A_-m, B_m+1, B_-m+1, B_m-1, B_-m-1 (A: value rows, B: normal
 // derivative rows; the -m entries are zero for m = 0)

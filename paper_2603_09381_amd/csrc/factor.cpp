@@ -1661,7 +1661,7 @@ void apply_geometry(pmx_factor* F, ApplyGeo& G, bool count, hipStream_t s) {
         if (isnear[j]) continue;
         const double* g = &G.incl[4 * (size_t)j];
         const double rmin = std::hypot(gw[0] - g[0], gw[1] - g[1]) - gw[2];
-        const double p = std::min((double)PMX_APPLY_PMAX, std::max(g[3], std::ceil(39.2 / std::log(rmin / g[2]))));
+        const double p = std::min((double)PMX_APPLY_PMAX, std::max(g[3], std::ceil(PMX_APPLY_TRUNC / std::log(rmin / g[2]))));
         far_orders += nt * (p + 2);
         far_pairs += nt;
       }
