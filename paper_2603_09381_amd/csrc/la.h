@@ -39,7 +39,7 @@ struct QrDescT {     // tall matrix M (m x c), factored by Householder, R writte
   int m, c;
   cx<R>* r;          // [kc x c], leading dimension kc
   cx<R>* v;          // workspace: la_geqrf_workspace(m) reflector entries
-  cx<R>* t;          // workspace: as v, the reflectors times T^H (compact WY)
+  cx<R>* t;          // workspace: as v, the triangular factors T of the blocks (compact WY)
   int kc;            // columns triangularised (min(m, c) for a full QR; fewer: the reflectors
                      // of the first kc columns are applied to all others, rows kc.. of
                      // the remaining columns keep their component orthogonal to the first kc)

@@ -1435,14 +1435,14 @@ void la_getrs_small(const LuDescT<R>* d_lu, const MatT<R>* d_b, const MatT<R>* d
 // level L-1 becomes row b*jb + r of level L), factored the same way until a single block
 // remains, whose R is the panel's R in rows j0 .. j0+jb-1.  After each tree level the
 // trailing columns of the same rows receive the block reflectors
-// Q_b^H = I - V_b T_b^H V_b^H (one fused kernel: W = V^H A, A -= (V T^H) W).  Only R is
+// Q_b^H = I - V_b T_b^H V_b^H (one fused kernel: W = V^H A, A -= V (T^H W)).  Only R is
 // kept, so the order of the untouched remaining rows is free.
 #define PMX_TS_BR 256
 
 struct TsGeom {
   int mr0, mr1, mr2, mr3;        // rows of tree levels 0..3
   int nb0, nb1, nb2, nb3;        // blocks of tree levels 0..3
-  int64_t wo0, wo1, wo2, wo3;    // workspace offsets of the levels' V / VT blocks
+  int64_t wo0, wo1, wo2, wo3;    // workspace offsets of the levels' V and T blocks
   int nlev;
 };
 
@@ -1484,16 +1484,22 @@ __device__ inline int ts_phys(int lr, int L, int jb, int j0, const TsGeom& g) {
   return j0 + lr;
 }
 
-// One block of one tree level: Householder QR of its rows of the panel, entirely in LDS.
+// One block of one tree level: Householder QR of its rows of the panel, in registers.
 // Columns are owned cyclically by the NT / 64 waves (column q by wave q % (NT / 64)), each
-// lane holding rows lane + 64k; a column's dot products are reduced inside its owner wave,
-// so a step costs two barriers: the owner of column i forms the reflector, then every wave
-// applies it to its own columns and forms its share of the compact-WY inner products.
-// More waves share the columns of a step among more SIMDs for the same LDS.  The
-// Householder norm is accumulated in FP64 for both real types.
+// lane holding rows lane + 64 k of them.  Step i: the owner of column i forms the
+// reflector (norm accumulated in FP64 for both real types) and publishes it in LDS; after
+// one barrier every wave applies it to its later columns and forms the compact-WY inner
+// products z_q = V_q^H v of its earlier ones, the partial sums of all its columns reduced
+// together.  Reflectors and inner products are double-buffered, so that a step needs one
+// barrier; the column i - 1 of T (T[0:i-1, i-1] = -tau T z) is formed at step i, each
+// thread on its own row of T.  Written back: R in the block's first rows, V and T to the
+// workspace (V column-major, BR rows; T row-major, PMX_QR_NB x PMX_QR_NB, upper triangular).
 template <class R, int NT>
 __global__ __launch_bounds__(NT) void k_ts_leaf(const QrDescT<R>* qrs, int j0, int L) {
   typedef cx<R> C;
+  constexpr int NW = NT / 64;                  // waves
+  constexpr int RPL = PMX_TS_BR / 64;          // rows per lane
+  constexpr int CPW = PMX_QR_NB / NW;          // columns per wave
   const QrDescT<R> Q = qrs[blockIdx.y];
   const int kmax = Q.kc;
   const int jb = min(PMX_QR_NB, kmax - j0);
@@ -1504,40 +1510,49 @@ __global__ __launch_bounds__(NT) void k_ts_leaf(const QrDescT<R>* qrs, int j0, i
   const int b = blockIdx.x;
   if (b >= ts_sel(L, g.nb0, g.nb1, g.nb2, g.nb3)) return;
   const int nrb = min(PMX_TS_BR, ts_sel(L, g.mr0, g.mr1, g.mr2, g.mr3) - b * PMX_TS_BR);
-  constexpr int NW = NT / 64;                  // waves
-  constexpr int RPL = PMX_TS_BR / 64;          // rows per lane
-  __shared__ C Ps[PMX_QR_NB][PMX_TS_BR];       // panel block, column major; R above, V below
-  __shared__ C vs[PMX_TS_BR];                  // current reflector
+  __shared__ C vs[2][PMX_TS_BR];               // reflectors of even and odd steps
+  __shared__ C zs[2][PMX_QR_NB];               // inner products of even and odd steps
   __shared__ C Ts[PMX_QR_NB][PMX_QR_NB + 1];
-  __shared__ C zs[PMX_QR_NB];
-  __shared__ double sh_tau;
+  __shared__ double taus[2];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int phys = (t < nrb) ? ts_phys(b * PMX_TS_BR + t, L, jb, j0, g) : -1;
   const auto A = gbl(Q.a);
   const int64_t ld = Q.ld;
-  if (t < PMX_TS_BR) {
-    const int pr = phys >= 0 ? phys : j0;
-    C tmpv[PMX_QR_NB];
+  int phys[RPL];
 #pragma unroll
-    for (int i = 0; i < PMX_QR_NB; ++i) tmpv[i] = A[pr + (int64_t)min(j0 + i, Q.c - 1) * ld];
-#pragma unroll
-    for (int i = 0; i < PMX_QR_NB; ++i) Ps[i][t] = (phys >= 0 && i < jb) ? tmpv[i] : cmk<R>(0, 0);
+  for (int k = 0; k < RPL; ++k) {
+    const int r = lane + 64 * k;
+    phys[k] = (r < nrb) ? ts_phys(b * PMX_TS_BR + r, L, jb, j0, g) : -1;
   }
-  __syncthreads();
+  C P[CPW][RPL];
+#pragma unroll
+  for (int m = 0; m < CPW; ++m) {
+    const int q = wave + NW * m;
+    const int64_t co = (int64_t)min(j0 + q, Q.c - 1) * ld;
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) P[m][k] = (phys[k] >= 0 && q < jb) ? A[phys[k] + co] : cmk<R>(0, 0);
+  }
   const int nref = min(jb, nrb);
   for (int i = 0; i < nref; ++i) {
-    if (wave == (i % NW)) {
-      // owner wave: norm, Householder parameters (every lane computes them), reflector
+    const int bi = i & 1;
+    if (wave == i % NW) {
+      const int om = i / NW;
       C x[RPL];
+#pragma unroll
+      for (int m = 0; m < CPW; ++m)
+        if (m == om) {
+#pragma unroll
+          for (int k = 0; k < RPL; ++k) x[k] = P[m][k];
+        }
       double p = 0;
+      C a = x[0];
 #pragma unroll
       for (int k = 0; k < RPL; ++k) {
         const int r = lane + 64 * k;
-        x[k] = Ps[i][r];
         if (r >= i) p += (double)x[k].re * x[k].re + (double)x[k].im * x[k].im;
+        if (k == (i >> 6)) a = x[k];
       }
       const double xn = sqrt(wave_sum(p));
-      const C alpha = Ps[i][i];
+      const C alpha = readlane(a, i & 63);
       const double aa = sqrt((double)alpha.re * alpha.re + (double)alpha.im * alpha.im);
       double tau;
       C beta, scale;
@@ -1560,91 +1575,107 @@ __global__ __launch_bounds__(NT) void k_ts_leaf(const QrDescT<R>* qrs, int j0, i
       for (int k = 0; k < RPL; ++k) {
         const int r = lane + 64 * k;
         const C v = (r == i) ? cmk<R>(1, 0) : ((r > i) ? zmul(x[k], scale) : cmk<R>(0, 0));
-        vs[r] = v;
-        if (r > i) Ps[i][r] = v;
-        if (r == i) Ps[i][i] = beta;
+        vs[bi][r] = v;
+        x[k] = (r == i) ? beta : ((r > i) ? v : x[k]);
       }
+#pragma unroll
+      for (int m = 0; m < CPW; ++m)
+        if (m == om) {
+#pragma unroll
+          for (int k = 0; k < RPL; ++k) P[m][k] = x[k];
+        }
       if (lane == 0) {
-        sh_tau = tau;
+        taus[bi] = tau;
         Ts[i][i] = cmk<R>(tau, 0);
       }
     }
     __syncthreads();
-    const R tau = (R)sh_tau;
+    if (i >= 1 && t < i - 1) {   // T[0:i-1, i-1] = -tau_{i-1} T[0:i-1, 0:i-1] z_{i-1}, one row per thread
+      const int c = i - 1;
+      C s2 = cmk<R>(0, 0);
+      for (int jj = t; jj < c; ++jj) s2 = zadd(s2, zmul(Ts[t][jj], zs[c & 1][jj]));
+      Ts[t][c] = zscale(s2, -Ts[c][c].re);
+    }
+    const R tau = (R)taus[bi];
     C vr[RPL];
 #pragma unroll
-    for (int k = 0; k < RPL; ++k) vr[k] = vs[lane + 64 * k];
-    for (int q = wave; q < jb; q += NW) {
-      if (q > i) {
-        // w = v^H P[:, q]; P[:, q] -= tau v w
-        C pq[RPL];
-        R wr = 0, wi = 0;
+    for (int k = 0; k < RPL; ++k) vr[k] = vs[bi][lane + 64 * k];
+    R dr[CPW], di[CPW];
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) {
-          pq[k] = Ps[q][lane + 64 * k];
-          const C pr = zcmul(vr[k], pq[k]);
-          wr += pr.re;
-          wi += pr.im;
-        }
-        const C w = zscale(cmk<R>(wave_sum(wr), wave_sum(wi)), tau);
+    for (int m = 0; m < CPW; ++m) {
+      const int q = wave + NW * m;
+      R sr = 0, si = 0;
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) {
-          const int r = lane + 64 * k;
-          if (r >= i) Ps[q][r] = zsub(pq[k], zmul(vr[k], w));
-        }
-      } else if (q < i) {
-        // z_q = V_q^H v for the compact-WY factor
-        R zr = 0, zi = 0;
-#pragma unroll
-        for (int k = 0; k < RPL; ++k) {
-          const int r = lane + 64 * k;
-          const C vq = (r == q) ? cmk<R>(1, 0) : ((r > q) ? Ps[q][r] : cmk<R>(0, 0));
-          const C pr = zcmul(vq, vr[k]);
-          zr += pr.re;
-          zi += pr.im;
-        }
-        zr = wave_sum(zr);
-        zi = wave_sum(zi);
-        if (lane == 0) zs[q] = cmk<R>(zr, zi);
+      for (int k = 0; k < RPL; ++k) {
+        const int r = lane + 64 * k;
+        // column q's reflector for q < i (unit diagonal, zero above), the column itself for q > i
+        const C cq = (q > i) ? P[m][k] : ((r == q) ? cmk<R>(1, 0) : ((r > q) ? P[m][k] : cmk<R>(0, 0)));
+        const C pr = zcmul(vr[k], cq);   // conj(v) c_q
+        sr += pr.re;
+        si += pr.im;
       }
+      dr[m] = sr;
+      di[m] = si;
     }
-    __syncthreads();
-    if (t < i) {  // T[0:i, i] = -tau T[0:i, 0:i] z, one row per thread
-      C s2 = cmk<R>(0, 0);
-#pragma unroll 8
-      for (int jj = t; jj < i; ++jj) s2 = zadd(s2, zmul(Ts[t][jj], zs[jj]));
-      Ts[t][i] = zscale(s2, -tau);
+#pragma unroll
+    for (int m = 0; m < CPW; ++m) {
+      dr[m] = wave_sum(dr[m]);
+      di[m] = wave_sum(di[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < CPW; ++m) {
+      const int q = wave + NW * m;
+      if (q > i && q < jb) {
+        const C w = zscale(cmk<R>(dr[m], di[m]), tau);
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+          const int r = lane + 64 * k;
+          if (r >= i) P[m][k] = zsub(P[m][k], zmul(vr[k], w));
+        }
+      } else if (q < i && lane == 0) {
+        zs[bi][q] = cmk<R>(dr[m], -di[m]);   // V_q^H v = conj(v^H V_q)
+      }
     }
   }
   __syncthreads();
-  // write back: R in the block's first rows, the reflectors V and V T^H to the workspace
-  if (phys >= 0 && t < jb) {
-    for (int i = 0; i < jb; ++i) A[phys + (int64_t)(j0 + i) * ld] = (i >= t) ? Ps[i][t] : cmk<R>(0, 0);
+  if (nref >= 1 && t < nref - 1) {
+    const int c = nref - 1;
+    C s2 = cmk<R>(0, 0);
+    for (int jj = t; jj < c; ++jj) s2 = zadd(s2, zmul(Ts[t][jj], zs[c & 1][jj]));
+    Ts[t][c] = zscale(s2, -Ts[c][c].re);
   }
-  if (t >= PMX_TS_BR) return;
+  __syncthreads();
+  // write back: R in the block's first rows, the reflectors V and T to the workspace
+  if (phys[0] >= 0 && lane < jb) {
+#pragma unroll
+    for (int m = 0; m < CPW; ++m) {
+      const int q = wave + NW * m;
+      if (q < jb) A[phys[0] + (int64_t)(j0 + q) * ld] = (q >= lane) ? P[m][0] : cmk<R>(0, 0);
+    }
+  }
   const int64_t wo = ts_sel64(L, g.wo0, g.wo1, g.wo2, g.wo3) + (int64_t)b * PMX_TS_BR * PMX_QR_NB;
   const auto V = gbl(Q.v) + wo;
-  const auto VT = gbl(Q.t) + wo;
-  C vrow[PMX_QR_NB];
+  const auto Tw = gbl(Q.t) + wo;
 #pragma unroll
-  for (int i = 0; i < PMX_QR_NB; ++i) {
-    C v = cmk<R>(0, 0);
-    if (i < nref && t < nrb) v = (t == i) ? cmk<R>(1, 0) : ((t > i) ? Ps[i][t] : cmk<R>(0, 0));
-    vrow[i] = v;
-    V[t + (int64_t)i * PMX_TS_BR] = v;
+  for (int m = 0; m < CPW; ++m) {
+    const int q = wave + NW * m;
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+      const int r = lane + 64 * k;
+      C v = cmk<R>(0, 0);
+      if (q < nref && r < nrb) v = (r == q) ? cmk<R>(1, 0) : ((r > q) ? P[m][k] : cmk<R>(0, 0));
+      V[r + (int64_t)q * PMX_TS_BR] = v;
+    }
   }
-#pragma unroll
-  for (int j = 0; j < PMX_QR_NB; ++j) {
-    C s2 = cmk<R>(0, 0);
-#pragma unroll
-    for (int i = j; i < PMX_QR_NB; ++i)
-      if (i < nref) s2 = zadd(s2, zmul(vrow[i], zconj(Ts[j][i])));
-    VT[t + (int64_t)j * PMX_TS_BR] = (j < nref) ? s2 : cmk<R>(0, 0);
+  for (int e = t; e < PMX_QR_NB * PMX_QR_NB; e += NT) {
+    const int r = e / PMX_QR_NB, c = e % PMX_QR_NB;
+    Tw[e] = (r <= c && c < nref) ? Ts[r][c] : cmk<R>(0, 0);
   }
 }
 
-// trailing update of one block of one tree level: A_b -= (V T^H) (V^H A_b), 64 columns per
-// workgroup, rows streamed through LDS in slices of 32, both products on 16x16x4 MFMA
+// trailing update of one block of one tree level: A_b -= V (T^H (V^H A_b)), 64 columns per
+// workgroup, rows streamed through LDS in slices of 32, both products with V on 16x16x4
+// MFMA, the small product with T^H (PMX_QR_NB x PMX_QR_NB times PMX_QR_NB x 64) in between
 #define TSU_ROWS 32
 template <class R>
 __global__ __launch_bounds__(256) void k_ts_update(const QrDescT<R>* qrs, int j0, int L) {
@@ -1665,7 +1696,7 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDescT<R>* qrs, int j0
   const int nrb = min(PMX_TS_BR, ts_sel(L, g.mr0, g.mr1, g.mr2, g.mr3) - b * PMX_TS_BR);
   const int64_t wo = ts_sel64(L, g.wo0, g.wo1, g.wo2, g.wo3) + (int64_t)b * PMX_TS_BR * PMX_QR_NB;
   const auto V = gbl(Q.v) + wo;
-  const auto VT = gbl(Q.t) + wo;
+  const auto Tw = gbl(Q.t) + wo;
   __shared__ C Vs[TSU_ROWS][PMX_QR_NB + 1];
   __shared__ C As[TSU_ROWS][64 + 1];
   __shared__ C Ws[PMX_QR_NB][64 + 1];
@@ -1725,8 +1756,28 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDescT<R>* qrs, int j0
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       Ws[q * 16 + mfma_row<R>(lane, r)][wave * 16 + (lane & 15)] = cmk<R>(accR[q][r], accI[q][r]);
+  // W <- T^H W, T upper triangular (row-major in the workspace), staged in the A slice's space
+  C(*Tl)[PMX_QR_NB + 1] = reinterpret_cast<C(*)[PMX_QR_NB + 1]>(&As[0][0]);
+  static_assert(TSU_ROWS * (64 + 1) >= PMX_QR_NB * (PMX_QR_NB + 1), "T fits in the A slice");
+  for (int e = tid; e < PMX_QR_NB * PMX_QR_NB; e += 256) Tl[e / PMX_QR_NB][e % PMX_QR_NB] = Tw[e];
   __syncthreads();
-  // A_b -= VT W: a 32 x 64 slice is 2 x 4 blocks of 16x16, two per wave
+  {
+    constexpr int PER = PMX_QR_NB * 64 / 256;   // outputs per thread, one column
+    const int col = tid & 63, i0 = (tid >> 6) * PER;
+    C w2[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = i0 + u;
+      C acc = cmk<R>(0, 0);
+      for (int j = 0; j <= i; ++j) acc = zadd(acc, zmul(zconj(Tl[j][i]), Ws[j][col]));
+      w2[u] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) Ws[i0 + u][col] = w2[u];
+  }
+  __syncthreads();
+  // A_b -= V W: a 32 x 64 slice is 2 x 4 blocks of 16x16, two per wave
   const int rbk = wave & 1;
   const int cbk0 = (wave >> 1) * 2;
   for (int rb = 0; rb < nrb; rb += TSU_ROWS) {
@@ -1738,7 +1789,7 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDescT<R>* qrs, int j0
       C tv[PMX_QR_NB / 8];
 #pragma unroll
       for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
-        tv[pass] = VT[rb + rr + (int64_t)(cc + 8 * pass) * PMX_TS_BR];
+        tv[pass] = V[rb + rr + (int64_t)(cc + 8 * pass) * PMX_TS_BR];
 #pragma unroll
       for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
         Vs[rr][cc + 8 * pass] = (rb + rr < nrb) ? tv[pass] : cmk<R>(0, 0);
@@ -1784,7 +1835,7 @@ __global__ void k_copy_r(const QrDescT<R>* qrs) {
 }
 
 int64_t la_geqrf_workspace(int m) {
-  // V (and V T^H) blocks of every tree level for a matrix with m rows
+  // V blocks (and, in the second workspace, T blocks) of every tree level for m rows
   int64_t tot = 0;
   int mr = m;
   for (int L = 0; L < PMX_TS_MAXLEV; ++L) {
@@ -2321,10 +2372,10 @@ void la_cpqr_judge(const CpqrDescT<R>* d_cp, const int* d_k, double tol, int* d_
 
 // Algorithmic work of the QR kernels for one m x c matrix, mirroring the launch sequence,
 // with z = 2 real_bytes bytes per complex entry.  Trailing update of an nrb x nc block by
-// jb reflectors: bytes z (2 nrb nc + 2 nrb jb) (the block read and written once, V and
-// V T^H read once), flops 16 nrb nc jb (two complex products).  Leaf factorisation of an
-// nrb x jb block: bytes z (2 nrb jb + 2 nrb PMX_QR_NB) (panel read and written, V and
-// V T^H written), flops 8 nrb jb^2.
+// jb reflectors: bytes z (2 nrb nc + nrb jb + jb^2) (the block read and written once, V and
+// T read once), flops 16 nrb nc jb + 4 jb^2 nc (the products with V and with T^H).  Leaf
+// factorisation of an nrb x jb block: bytes z (2 nrb jb + nrb PMX_QR_NB + PMX_QR_NB^2)
+// (panel read and written, V and T written), flops 8 nrb jb^2.
 void la_geqrf_work(int m, int c, int kc, int real_bytes, double* upd_bytes, double* upd_flops, double* leaf_bytes,
                    double* leaf_flops) {
   const double z = 2.0 * real_bytes;
@@ -2337,11 +2388,11 @@ void la_geqrf_work(int m, int c, int kc, int real_bytes, double* upd_bytes, doub
       const int nb = (mr + PMX_TS_BR - 1) / PMX_TS_BR;
       for (int b = 0; b < nb; ++b) {
         const double nrb = std::min(PMX_TS_BR, mr - b * PMX_TS_BR);
-        *leaf_bytes += z * (2 * nrb * jb + 2 * nrb * PMX_QR_NB);
+        *leaf_bytes += z * (2 * nrb * jb + nrb * PMX_QR_NB + PMX_QR_NB * PMX_QR_NB);
         *leaf_flops += 8.0 * nrb * jb * jb;
         if (nc > 0) {
-          *upd_bytes += z * (2 * nrb * nc + 2 * nrb * jb);
-          *upd_flops += 16.0 * nrb * nc * jb;
+          *upd_bytes += z * (2 * nrb * nc + nrb * jb + (double)jb * jb);
+          *upd_flops += 16.0 * nrb * nc * jb + 4.0 * jb * jb * nc;
         }
       }
       if (nb <= 1) break;
