@@ -13,6 +13,7 @@
 //   [[-(e+ S+ + e- S-), D+ + D-], [-(D*+ + D*-), N+/e+ + N-/e-]].
 #include "assemble.h"
 #include "bessel.h"
+#include "hankel_fast.h"
 #include "ktimer.h"
 
 struct Pt {
@@ -45,11 +46,18 @@ __device__ inline Pt fetch_pt(const DevGeom& g, const DevProxy& p, int code) {
 
 // One entry of the exterior (Omit off-diagonal) operator between target t (row type)
 // and source s (column type, carrying its quadrature weight).
+// constant-memory copies of the coefficient tables (one per translation unit)
+static __constant__ FarTable pmx_far_table = make_far_table();
+static __constant__ SeriesTable pmx_series_table = make_series_table();
+
 __device__ inline zd omit_entry(const Pt& t, const Pt& s, const ExtParams& e) {
   const double d1 = t.x - s.x, d2 = t.y - s.y;
   const double r = sqrt(d1 * d1 + d2 * d2);
   const double ir = 1.0 / r;
-  const bes4 b = bessel01(e.k * r);
+  // coefficient tables read through scalar loads at each use (kept out of vector registers)
+  pmx_ctab tab = (pmx_ctab)pmx_far_table.v, ser = (pmx_ctab)pmx_series_table.v;
+  asm volatile("" : "+s"(tab), "+s"(ser));
+  const bes4 b = bessel01_t(e.k * r, tab, ser);
   if (t.type == 0) {
     if (s.type == 0) {  // -e+ (i/4) H0 w
       const double f = 0.25 * e.eps * s.w;

@@ -154,3 +154,37 @@ __device__ inline bes4 bessel01_t(double z, pmx_ctab t, pmx_ctab s) {
   }
   return r;
 }
+
+// Coefficients of hankel_far_t in constant memory (signed expansion terms, then the
+// sine and cosine polynomials)
+struct FarTable {
+  double v[PMX_FAR_TABLE_SIZE];
+};
+constexpr FarTable make_far_table() {
+  FarTable t{};
+  for (int i = 0; i < 10; ++i) {
+    const double sg = (i & 1) ? -1.0 : 1.0;
+    t.v[i] = sg * pmx_asym0[2 * i];
+    t.v[10 + i] = sg * pmx_asym0[2 * i + 1];
+    t.v[20 + i] = sg * pmx_asym1[2 * i];
+    t.v[30 + i] = sg * pmx_asym1[2 * i + 1];
+  }
+  for (int k = 0; k < PMX_SIN_NC; ++k) t.v[40 + k] = pmx_sin_c[k];
+  for (int k = 0; k < PMX_COS_NC; ++k) t.v[49 + k] = pmx_cos_c[k];
+  return t;
+}
+
+// power-series coefficients of bessel01_t: J0, J1, then Y0's and Y1's remainders
+struct SeriesTable {
+  double v[4 * PMX_SERIES_TERMS];
+};
+constexpr SeriesTable make_series_table() {
+  SeriesTable t{};
+  for (int k = 0; k < PMX_SERIES_TERMS; ++k) {
+    t.v[k] = pmx_ser_j0[k];
+    t.v[PMX_SERIES_TERMS + k] = pmx_ser_j1[k];
+    t.v[2 * PMX_SERIES_TERMS + k] = pmx_ser_y0h[k];
+    t.v[3 * PMX_SERIES_TERMS + k] = pmx_ser_y1h[k];
+  }
+  return t;
+}
