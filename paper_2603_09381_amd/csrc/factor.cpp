@@ -140,13 +140,24 @@ class DevPool {
     void* p = nullptr;
     if (hipMalloc(&p, c) != hipSuccess) {
       (void)hipGetLastError();
-      // the cached blocks of earlier factors may be what is missing
-      if (cache_trim(0) == 0 || hipMalloc(&p, c) != hipSuccess) {
+      // what is missing may be held by the cached blocks of earlier factors or by this
+      // pool's idle blocks of other sizes: free both (after the device has finished with
+      // them) and try once more
+      cache_trim(0);
+      release_idle();
+      if (hipMalloc(&p, c) != hipSuccess) {
         (void)hipGetLastError();
         return nullptr;
       }
     }
     return p;
+  }
+  void release_idle() {
+    if (free_.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto& kv : free_)
+      for (void* p : kv.second) (void)hipFree(p);
+    free_.clear();
   }
   void put(void* p, size_t n) { free_[size_class(n)].push_back(p); }
   void retire(std::vector<std::vector<char>>& host) {

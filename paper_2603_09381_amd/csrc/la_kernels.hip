@@ -1227,6 +1227,21 @@ __global__ __launch_bounds__(64 + NTT) void k_getrs_lds(const LuDescT<R>* lus, c
   C acc[RPT][NRC];       // others: their rows of the solution block (wave 0: the block's values)
 #define PMX_GS_LOAD(r, j, jb)                                                    \
   _Pragma("unroll") for (int k = 0; k < BS; ++k) buf[k] = A[(r) + (int64_t)((j) + min(k, (jb) - 1)) * ld]
+  // a row's update by the solved block: without per-column branches for full blocks, so
+  // that the LDS reads of the solved values can be issued ahead of their use
+#define PMX_GS_UPDATE(q)                                                                   \
+  if (jb == BS) {                                                                          \
+    _Pragma("unroll") for (int k = 0; k < BS; ++k)                                         \
+      _Pragma("unroll") for (int c = 0; c < NRC; ++c)                                      \
+        acc[q][c] = zsub(acc[q][c], zmul(buf[k], xs[c * n + j0 + k]));                    \
+  } else {                                                                                 \
+    _Pragma("unroll") for (int k = 0; k < BS; ++k) {                                       \
+      if (k < jb) {                                                                        \
+        _Pragma("unroll") for (int c = 0; c < NRC; ++c)                                    \
+          acc[q][c] = zsub(acc[q][c], zmul(buf[k], xs[c * n + j0 + k]));                  \
+      }                                                                                    \
+    }                                                                                      \
+  }
   // ---- forward: L unit lower
   {
     const int jb = min(BS, n);
@@ -1275,13 +1290,7 @@ __global__ __launch_bounds__(64 + NTT) void k_getrs_lds(const LuDescT<R>* lus, c
         const int r = t + q * NTT;
         if (r >= j0 + jb && r < n) {
           if (q > 0) PMX_GS_LOAD(r, j0, jb);
-#pragma unroll
-          for (int k = 0; k < BS; ++k) {
-            if (k < jb) {
-#pragma unroll
-              for (int c = 0; c < NRC; ++c) acc[q][c] = zsub(acc[q][c], zmul(buf[k], xs[c * n + j0 + k]));
-            }
-          }
+          PMX_GS_UPDATE(q);
           if (r < j1 + jb1) {
 #pragma unroll
             for (int c = 0; c < NRC; ++c) xs[c * n + r] = acc[q][c];
@@ -1345,13 +1354,7 @@ __global__ __launch_bounds__(64 + NTT) void k_getrs_lds(const LuDescT<R>* lus, c
         const int r = t + q * NTT;
         if (r < j0) {
           if (q > 0) PMX_GS_LOAD(r, j0, jb);
-#pragma unroll
-          for (int k = 0; k < BS; ++k) {
-            if (k < jb) {
-#pragma unroll
-              for (int c = 0; c < NRC; ++c) acc[q][c] = zsub(acc[q][c], zmul(buf[k], xs[c * n + j0 + k]));
-            }
-          }
+          PMX_GS_UPDATE(q);
           if (r >= j1) {
 #pragma unroll
             for (int c = 0; c < NRC; ++c) xs[c * n + r] = acc[q][c];
@@ -1363,6 +1366,7 @@ __global__ __launch_bounds__(64 + NTT) void k_getrs_lds(const LuDescT<R>* lus, c
     __syncthreads();
   }
 #undef PMX_GS_LOAD
+#undef PMX_GS_UPDATE
   for (int e = tid; e < n * nc; e += NT) {
     const int i = e % n, c = e / n;
     Bp[i + (int64_t)(c0 + c) * B.ld] = xs[c * n + i];
