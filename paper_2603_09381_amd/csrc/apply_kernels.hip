@@ -266,7 +266,7 @@ __global__ __launch_bounds__(64) void k_apply_p2m(ApplyArgs A, const double* __r
       im = -a0[1] + mui / eps;
     }
   };
-  zd* rec = A.coef + (int64_t)j * PMX_APPLY_NREC * NR * 6;
+  zd* rec = A.coef + (int64_t)j * PMX_APPLY_NRECA * NR * 6;
   for (int e = lane; e < PMX_APPLY_NREC * NR; e += 64) {
     const int m = e / NR, rr = e % NR;
     double re, im;
@@ -286,12 +286,130 @@ __global__ __launch_bounds__(64) void k_apply_p2m(ApplyArgs A, const double* __r
   }
 }
 
-// Far part: every inclusion of range blockIdx.y outside the wave's near list, through its
-// expansion: per lane rho, th of the target about the centre, H0 and H1 (large-argument
-// expansion when the whole wave allows it), then orders m = 0 .. p+1 by the upward
-// recurrence H_{m+1} = (2m/z) H_m - H_{m-1} (stable for the Hankel function) and
-// e^{i(m+1)th} = e^{i m th} e^{i th}; O_{-m} = (-1)^m H_m e^{-i m th}.  The sums
-// S1 = sum O_m B_{m+1}, S2 = sum O_m B_{m-1} are kept over all inclusions and turned into
+// Cluster expansions from their children's, by the regular translation: with
+// R_n(v) = J_n(k|v|) e^{-i n arg v}, R_m(u + d) = sum_n R_{m-n}(d) R_n(u) for all u, d, so for
+// a child whose centre is d from the cluster's, A^_m = sum_n R_{m-n}(d) A_n and the same for
+// B.  One workgroup per cluster of the level (at most four children, the quadtree's).  Lane
+// c of the first wave computes child c's J_nu(k|d|), nu = 0 .. M2M_NU, by Miller's backward
+// recurrence (rescaled against overflow, normalised by J_0 + 2 sum J_2k = 1); the table of
+// R_nu(d), nu = -M2M_NU .. M2M_NU, follows.  Per child the workgroup stages the child's A_n
+// and B_n in LDS, and each thread accumulates its (order, right-hand side) outputs.  The
+// records are then written as p2m writes them, orders up to PMX_APPLY_PMAXC + 1.
+constexpr int M2M_MO = PMX_APPLY_PMAXC + 2;                // outputs for orders -M2M_MO .. M2M_MO
+constexpr int M2M_NM = 2 * M2M_MO + 1;
+constexpr int M2M_NU = M2M_MO + PMX_APPLY_NRECA + 1;       // translation orders |m - n| <= M2M_NU
+constexpr int M2M_NI = 2 * PMX_APPLY_NRECA + 1;            // child orders -NRECA .. NRECA
+constexpr int M2M_KIDS = 4;
+
+template <int NR>
+__global__ __launch_bounds__(256) void k_apply_m2m(ApplyArgs A, int c0) {
+  const int c = c0 + blockIdx.x;
+  const int sc = A.n_incl + c;
+  const double Cx = A.incl_geo[4 * sc], Cy = A.incl_geo[4 * sc + 1];
+  const double k = A.k;
+  const int q0 = A.kid_off[c], nk = min(A.kid_off[c + 1] - q0, M2M_KIDS);
+  __shared__ double jt[M2M_KIDS][M2M_NU + 1];
+  __shared__ zd Rt[M2M_KIDS][2 * M2M_NU + 1];
+  __shared__ zd An[NR][M2M_NI], Bn[NR][M2M_NI];
+  __shared__ zd accA[M2M_NM][NR], accB[M2M_NM][NR];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < M2M_NM * NR; e += 256) {
+    accA[e / NR][e % NR] = zmk(0, 0);
+    accB[e / NR][e % NR] = zmk(0, 0);
+  }
+  if (tid < nk) {
+    const int ch = A.kid_idx[q0 + tid];
+    const double dx = A.incl_geo[4 * ch] - Cx, dy = A.incl_geo[4 * ch + 1] - Cy;
+    const double z = k * sqrt(dx * dx + dy * dy);
+    double* J = jt[tid];
+    if (!(z > 0.0)) {
+      J[0] = 1.0;
+      for (int nu = 1; nu <= M2M_NU; ++nu) J[nu] = 0.0;
+    } else {
+      const int nstart = M2M_NU + 30 + (int)ceil(z);
+      const double iz2 = 2.0 / z;
+      double jp = 0.0, jc = 1e-280, nrm = 0.0;
+      for (int m = nstart; m >= 1; --m) {
+        const double jm = m * iz2 * jc - jp;   // J_{m-1}, unnormalised
+        jp = jc;
+        jc = jm;
+        if (m - 1 <= M2M_NU) J[m - 1] = jc;
+        if (((m - 1) & 1) == 0) nrm += (m - 1 == 0) ? jc : 2.0 * jc;
+        if (fabs(jc) > 1e200) {   // rescale everything kept so far
+          jp *= 1e-200;
+          jc *= 1e-200;
+          nrm *= 1e-200;
+          for (int nu = m - 1; nu <= M2M_NU; ++nu) J[nu] *= 1e-200;
+        }
+      }
+      const double inv = 1.0 / nrm;
+      for (int nu = 0; nu <= M2M_NU; ++nu) J[nu] *= inv;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < nk * (2 * M2M_NU + 1); e += 256) {
+    const int kc = e / (2 * M2M_NU + 1), nu = e % (2 * M2M_NU + 1) - M2M_NU;
+    const int ch = A.kid_idx[q0 + kc];
+    const double dx = A.incl_geo[4 * ch] - Cx, dy = A.incl_geo[4 * ch + 1] - Cy;
+    const int anu = nu < 0 ? -nu : nu;
+    // R_nu(d) = J_nu e^{-i nu th}, J_{-nu} = (-1)^nu J_nu
+    const double Jv = ((nu < 0) && (anu & 1)) ? -jt[kc][anu] : jt[kc][anu];
+    double sn, cs;
+    sincos(nu * atan2(dy, dx), &sn, &cs);
+    Rt[kc][nu + M2M_NU] = zmk(Jv * cs, -Jv * sn);
+  }
+  for (int kc = 0; kc < nk; ++kc) {
+    const int ch = A.kid_idx[q0 + kc];
+    const int nrc = (ch < A.n_incl) ? PMX_APPLY_NREC : PMX_APPLY_NRECA;   // record rows of the child
+    const zd* rec = A.coef + (int64_t)ch * PMX_APPLY_NRECA * NR * 6;
+    __syncthreads();   // the previous child's A, B are read no more; the R table is complete
+    // stored: A_n for |n| <= nrc - 1, B_n for 2 - nrc <= n <= nrc; the rest is zero
+    for (int e = tid; e < NR * M2M_NI; e += 256) {
+      const int rr = e / M2M_NI, n = e % M2M_NI - PMX_APPLY_NRECA;
+      zd a = zmk(0, 0), b = zmk(0, 0);
+      if (n >= 1 - nrc && n <= nrc - 1) a = n >= 0 ? rec[((int64_t)n * NR + rr) * 6] : rec[((int64_t)(-n) * NR + rr) * 6 + 1];
+      if (n >= 2 - nrc && n <= nrc)
+        b = n >= 1 ? rec[((int64_t)(n - 1) * NR + rr) * 6 + 2] : rec[((int64_t)(1 - n) * NR + rr) * 6 + 3];
+      An[rr][n + PMX_APPLY_NRECA] = a;
+      Bn[rr][n + PMX_APPLY_NRECA] = b;
+    }
+    __syncthreads();
+    for (int e = tid; e < M2M_NM * NR; e += 256) {
+      const int m = e / NR - M2M_MO, rr = e % NR;
+      double ar = 0, ai = 0, br = 0, bi = 0;
+      for (int n = 1 - nrc; n <= nrc; ++n) {
+        const zd R = Rt[kc][m - n + M2M_NU];
+        const zd a = An[rr][n + PMX_APPLY_NRECA], b = Bn[rr][n + PMX_APPLY_NRECA];
+        ar += R.re * a.re - R.im * a.im;
+        ai += R.re * a.im + R.im * a.re;
+        br += R.re * b.re - R.im * b.im;
+        bi += R.re * b.im + R.im * b.re;
+      }
+      accA[m + M2M_MO][rr] = zadd(accA[m + M2M_MO][rr], zmk(ar, ai));
+      accB[m + M2M_MO][rr] = zadd(accB[m + M2M_MO][rr], zmk(br, bi));
+    }
+  }
+  __syncthreads();
+  zd* out = A.coef + (int64_t)sc * PMX_APPLY_NRECA * NR * 6;
+  for (int e = tid; e < PMX_APPLY_NRECA * NR; e += 256) {
+    const int m = e / NR, rr = e % NR;
+    zd* o = out + ((int64_t)m * NR + rr) * 6;
+    const zd z0 = zmk(0, 0);
+    o[0] = accA[M2M_MO + m][rr];
+    o[1] = m ? accA[M2M_MO - m][rr] : z0;
+    o[2] = accB[M2M_MO + m + 1][rr];
+    o[3] = m ? accB[M2M_MO - m + 1][rr] : z0;
+    o[4] = accB[M2M_MO + m - 1][rr];
+    o[5] = m ? accB[M2M_MO - m - 1][rr] : z0;
+  }
+}
+
+// Far part: part blockIdx.y of the wave's list of far sources (inclusions and clusters),
+// each through its expansion: per lane rho, th of the target about the source's centre, H0
+// and H1 (large-argument expansion when the whole wave allows it), then orders m = 0 .. p+1
+// by the upward recurrence H_{m+1} = (2m/z) H_m - H_{m-1} (stable for the Hankel function)
+// and e^{i(m+1)th} = e^{i m th} e^{i th}; O_{-m} = (-1)^m H_m e^{-i m th}.  The sums
+// S1 = sum O_m B_{m+1}, S2 = sum O_m B_{m-1} are kept over all sources and turned into
 // derivative rows once at the end.
 template <int NR>
 __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __restrict__ cf, int r0) {
@@ -308,26 +426,17 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
   double vr[NR], vi[NR], s1r[NR], s1i[NR], s2r[NR], s2i[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) vr[r] = vi[r] = s1r[r] = s1i[r] = s2r[r] = s2i[r] = 0.0;
-  int q = A.near_off[wv];
-  const int qe = A.near_off[wv + 1];
-  const int j0 = A.split_incl[blockIdx.y], j1 = A.split_incl[blockIdx.y + 1];
-  int nxt = q < qe ? A.near_idx[q] : 0x7fffffff;
-  while (nxt < j0) {
-    ++q;
-    nxt = q < qe ? A.near_idx[q] : 0x7fffffff;
-  }
-  for (int j = j0; j < j1; ++j) {
-    if (j == nxt) {
-      ++q;
-      nxt = q < qe ? A.near_idx[q] : 0x7fffffff;
-      continue;
-    }
+  const int fq0 = A.far_off[wv], flen = A.far_off[wv + 1] - fq0;
+  const int ns = gridDim.y, ys = blockIdx.y;
+  const int q0 = fq0 + (int)((int64_t)flen * ys / ns), q1 = fq0 + (int)((int64_t)flen * (ys + 1) / ns);
+  for (int q = q0; q < q1; ++q) {
+    const int j = A.far_idx[q];
     const double cx = A.incl_geo[4 * j], cy = A.incl_geo[4 * j + 1], rj = A.incl_geo[4 * j + 2];
     const double pj = A.incl_geo[4 * j + 3];
     // truncation order of the pair (uniform)
     const double rmin = sqrt((wcx - cx) * (wcx - cx) + (wcy - cy) * (wcy - cy)) - wr;
     const double pr = fmax(pj, ceil(PMX_APPLY_TRUNC / log(rmin / rj)));
-    const int p = __builtin_amdgcn_readfirstlane((int)fmin(pr, (double)PMX_APPLY_PMAX));
+    const int p = __builtin_amdgcn_readfirstlane((int)fmin(pr, (double)PMX_APPLY_PMAXC));
     const double dx = ax - cx, dy = ay - cy;
     const double irho = rsqrt_nr(dx * dx + dy * dy);
     const double z = k * ((dx * dx + dy * dy) * irho);
@@ -353,7 +462,7 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
     // m = 0 .. p + 1: Hc = H_m, Hp = H_{m-1}, (Emr, Emi) = e^{i m th}
     double Hcr = H0r, Hci = H0i, Hpr = -H1r, Hpi = -H1i;   // H_{-1} = -H_1
     double Emr = 1.0, Emi = 0.0;
-    const double* rec = cf + (int64_t)j * PMX_APPLY_NREC * NR * 12;
+    const double* rec = cf + (int64_t)j * PMX_APPLY_NRECA * NR * 12;
     for (int m = 0; m <= p + 1; ++m) {
       const double sg = (m & 1) ? -1.0 : 1.0;
       const double Opr = Hcr * Emr - Hci * Emi, Opi = Hcr * Emi + Hci * Emr;               // O_m
@@ -467,7 +576,7 @@ int apply_near_splits(int n_nodes, int wg_target) {
 
 int64_t apply_pack_size(int n_nodes, int nr_max) { return (int64_t)n_nodes * APPLY_SRC(nr_max); }
 
-int64_t apply_coef_size(int n_incl, int nr_max) { return (int64_t)n_incl * PMX_APPLY_NREC * nr_max * 6; }
+int64_t apply_coef_size(int n_src, int nr_max) { return (int64_t)n_src * PMX_APPLY_NRECA * nr_max * 6; }
 
 int apply_source_order(double kr) {
   for (int p = 1; p < 1000; ++p)
@@ -481,6 +590,9 @@ static void apply_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipS
   KScope ks(PK_APPLY, s);
   const int m = (int)A.n_incl;
   hipLaunchKernelGGL(k_apply_p2m<NR>, dim3(m), dim3(64), 0, s, A, (const double*)pk, r0);
+  for (int l = 0; l < A.n_lev; ++l)
+    if (A.lev_off[l + 1] > A.lev_off[l])
+      hipLaunchKernelGGL(k_apply_m2m<NR>, dim3(A.lev_off[l + 1] - A.lev_off[l]), dim3(256), 0, s, A, A.lev_off[l]);
   hipLaunchKernelGGL(k_apply_far<NR>, dim3((A.n_nodes + 255) / 256, nsplit), dim3(256), 0, s, A,
                      (const double*)A.coef, r0);
   hipLaunchKernelGGL(k_apply_near<NR>, dim3((A.n_nodes + 63) / 64, A.nsplit_near), dim3(64), 0, s, A,

@@ -131,24 +131,33 @@ void asm_build_l(const LDescT<R>* d, int batch, int max_s, int max_k, hipStream_
 void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s);
 // Dense FP64 operator apply between different inclusions (exterior kernels), for a block
 // of right-hand sides in the density layout (ld = 2 n_nodes, per inclusion [q; u]).
-// Targets are taken in waves of 64 consecutive nodes.  Each wave has a sorted list of
-// "near" inclusions: its own inclusions, every inclusion whose centre is closer to the
-// wave's bounding circle than PMX_APPLY_RATIO times its radius, and every inclusion whose
-// expansion would need more than PMX_APPLY_PMAX orders.  Near inclusions are applied pair
-// by pair (near kernel, split in nsplit_near parts, same-inclusion pairs left out).  Every
-// other inclusion is applied through its multipole expansion about its centre (Graf's
-// addition theorem): coefficients per inclusion from its sources (p2m kernel), evaluated
-// at each target to the order its distance needs (far kernel, over nsplit ranges of whole
-// inclusions, split_incl).  Partial sums go to part [nsplit + nsplit_near][nrhs][ld].
+// Targets are taken in waves of 64 consecutive nodes.  Sources are the inclusions and the
+// clusters of the plan's tree above them (source index: inclusions first, then the
+// clusters level by level upwards).  Every source has a multipole expansion about its
+// centre (Graf's addition theorem): an inclusion's coefficients come from its nodes (p2m
+// kernel), a cluster's from its children's by the regular translation (m2m kernel, one
+// launch per tree level).  Each wave has two host-built lists, from a walk down the tree:
+// far sources, taken through their expansions to the order the distance needs (far
+// kernel, the list split in nsplit parts), and near inclusions, applied pair by pair (near
+// kernel, split in nsplit_near parts, same-inclusion pairs left out).  A cluster is far
+// when its centre is farther than PMX_APPLY_RATIO cluster radii from the wave's circle and
+// PMX_APPLY_PMAXC orders suffice; otherwise its children are examined.  An inclusion
+// reached that way is near when its centre is closer than PMX_APPLY_RATIO radii or its
+// expansion would need more than PMX_APPLY_PMAX orders, else far.  Partial sums go to
+// part [nsplit + nsplit_near][nrhs][ld].
 #define PMX_APPLY_RATIO 3.0
 #define PMX_APPLY_PMAX 48
+#define PMX_APPLY_PMAXC 64   // largest order of a cluster expansion
 // truncation of a far pair: orders until (r_j / rho_min)^p <= e^-PMX_APPLY_TRUNC, about 1e-17
 // (on the star grids the sources' own order, from k r_j, is the larger one for most pairs)
 #define PMX_APPLY_TRUNC 39.2
-// coefficient records per inclusion: orders m = 0 .. PMX_APPLY_PMAX + 1, per right-hand side
+// coefficient records per source: orders m = 0 .. PMX_APPLY_PMAXC + 1, per right-hand side
 // six complex numbers A_m, A_-m, B_m+1, B_-m+1, B_m-1, B_-m-1 (A: value rows, B: normal
-// derivative rows; the -m entries are zero for m = 0)
+// derivative rows; the -m entries are zero for m = 0); an inclusion fills orders up to
+// PMX_APPLY_PMAX + 1 only
 #define PMX_APPLY_NREC (PMX_APPLY_PMAX + 2)
+#define PMX_APPLY_NRECA (PMX_APPLY_PMAXC + 2)
+#define PMX_APPLY_MAXLEV 32
 struct ApplyArgs {
   const double *x, *y, *nx, *ny, *w;
   const int* owner;
@@ -162,12 +171,17 @@ struct ApplyArgs {
   double* pack;          // [apply_pack_size] packed source data of one group of right-hand sides
   const int* near_off;   // [n_waves + 1]
   const int* near_idx;   // near inclusions of each wave, ascending
-  const int* split_incl; // [nsplit + 1] first inclusion of each far source range
+  const int* far_off;    // [n_waves + 1]
+  const int* far_idx;    // far sources of each wave
   int nsplit_near;
-  const double* incl_geo;  // per inclusion: centre x, y, radius, order needed by the sources' decay
+  const double* incl_geo;  // per source: centre x, y, radius, order needed by the sources' decay
   const double* wave_geo;  // per wave: bounding-circle centre x, y, radius, unused
-  zd* coef;              // [n_incl][PMX_APPLY_NREC][nr][6] expansion records of one group
-  int n_incl;
+  const int* kid_off;    // [n_clus + 1] children of each cluster (source indices)
+  const int* kid_idx;
+  zd* coef;              // [n_src][PMX_APPLY_NRECA][nr][6] expansion records of one group
+  int n_incl, n_clus;
+  int n_lev;             // cluster levels; level l holds clusters lev_off[l] .. lev_off[l + 1] - 1
+  int lev_off[PMX_APPLY_MAXLEV + 1];
 };
 // orders needed for the sources of an inclusion of radius r: the smallest p with
 // (e k r / 2p)^p <= 1e-17 and p > e k r / 2 + 2
@@ -179,7 +193,7 @@ int apply_near_splits(int n_nodes, int wg_target);
 // doubles of the packed source data for groups of up to nr_max right-hand sides
 int64_t apply_pack_size(int n_nodes, int nr_max);
 // complex entries of the expansion records for groups of up to nr_max right-hand sides
-int64_t apply_coef_size(int n_incl, int nr_max);
+int64_t apply_coef_size(int n_src, int nr_max);
 // partial sums of the off-diagonal operator (far ranges, then near parts), right-hand
 // sides in groups of nr_max (1, 2, 4, 8) per thread
 void asm_apply_off(const ApplyArgs& a, int nsplit, int nr_max, hipStream_t s);

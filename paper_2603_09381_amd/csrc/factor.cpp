@@ -1565,7 +1565,8 @@ GatherDescT<RD>* gather_to_leaf(const LeafMap& M, cx<RD>* leaf, int nrhs, Arena&
 // by batched MFMA products, the blocks between inclusions evaluated on the fly.
 struct DenseApply {
   int nrhs = -1, nsplit = 1, nblk = 1, nr_max = 8;
-  int nslots = 1;                 // partial-sum slots: nsplit far ranges + near parts
+  int nslots = 1;                 // partial-sum slots: nsplit far-list parts + near parts
+  int n_src = 0;                  // expansion sources: inclusions and clusters
   double flops_fixed = 0, flops_rhs = 0;   // algorithmic work of one apply (counted with timing)
   int64_t total = 0;
   zd *ydiag = nullptr, *part = nullptr;
@@ -1577,20 +1578,29 @@ struct DenseApply {
   zd* out = nullptr;
 };
 
-// Geometry of the dense apply: bounding circles (centre, radius) of every inclusion (with
-// the expansion order its sources need) and of every wave of 64 consecutive target nodes,
-// and per wave the sorted list of near inclusions: those whose centre is closer than
-// PMX_APPLY_RATIO times their radius to the wave's circle (its own inclusions among them)
-// and those whose expansion would need more than PMX_APPLY_PMAX orders.  Candidates come
-// from a uniform grid of the inclusion centres whose spacing covers the largest reach.
-// With `count`, the algorithmic work per right-hand side and the fixed part are returned:
-// per near pair 32 and 130 flops (the pair formulas), per (target, far inclusion)
-// (p + 2) 48 and 100 + 26 (p + 2) flops (orders m = 0 .. p + 1: six complex multiply-adds
-// per right-hand side, the two O's and the recurrences; H0, H1 and the geometry once), per
-// source node and order 72 flops per right-hand side for the expansion sums.
+// Geometry of the dense apply.  Sources: every inclusion and every cell of the plan's tree
+// above the leaves except the root (a cluster), each with its bounding circle (centre,
+// radius) and the expansion order its sources need; waves of 64 consecutive target nodes
+// with theirs.  Per wave, a walk down the tree from the top clusters gives the list of far
+// sources (a cluster whose centre is farther than PMX_APPLY_RATIO radii from the wave's
+// circle and whose order stays within PMX_APPLY_PMAXC; an inclusion reached because its
+// parent was opened, when it is not near) and the sorted list of near inclusions (closer
+// than PMX_APPLY_RATIO radii, or needing more than PMX_APPLY_PMAX orders).  A cluster is
+// never taken whole when its own order exceeds PMX_APPLY_PMAXC or it holds an inclusion
+// that is near for every wave.  With `count`, the algorithmic work per right-hand side and
+// the fixed part are returned: per near pair 32 and 130 flops (the pair formulas); per
+// (target, far source) of order p, (p + 2) 48 and 100 + 26 (p + 2) flops (orders
+// m = 0 .. p + 1: six complex multiply-adds per right-hand side, the two O's and the
+// recurrences; H0, H1 and the geometry once); per source node and order 72 flops per
+// right-hand side for the expansion sums; per cluster, child and translated pair of
+// orders 16 flops per right-hand side (two complex multiply-adds).
 struct ApplyGeo {
-  std::vector<int> off, idx;
-  std::vector<double> incl, wave;
+  std::vector<int> off, idx;        // near inclusions per wave
+  std::vector<int> foff, fidx;      // far sources per wave
+  std::vector<double> incl, wave;   // per source (inclusions, then clusters) and per wave
+  std::vector<int> kid_off, kid_idx;
+  std::vector<int> lev_off;         // clusters of tree level 1, 2, ...: lev_off[l] .. lev_off[l + 1] - 1
+  int n_clus = 0;
   double flops_fixed = 0, flops_rhs = 0;
 };
 
@@ -1600,84 +1610,145 @@ void apply_geometry(pmx_factor* F, ApplyGeo& G, bool count, hipStream_t s) {
   download(hy, F->y, F->n_nodes, s);
   const int m = F->m, N = F->n_nodes, nw = (N + 63) / 64;
   const double k = F->k_ext;
-  auto circle = [&](int64_t b0, int64_t b1, double& cx, double& cy, double& r) {
-    double x0 = hx[b0], x1 = hx[b0], y0 = hy[b0], y1 = hy[b0];
-    for (int64_t b = b0; b < b1; ++b) {
+  const auto& plan = F->plan;
+  // bounding circle of the nodes of the inclusions in `incs` (all nodes of inclusion j: node_off)
+  auto circle = [&](const int* incs, int ninc, double& cx, double& cy, double& r) {
+    const int64_t f0 = F->node_off[incs[0]];
+    double x0 = hx[f0], x1 = hx[f0], y0 = hy[f0], y1 = hy[f0];
+    for (int q = 0; q < ninc; ++q)
+      for (int64_t b = F->node_off[incs[q]]; b < F->node_off[incs[q] + 1]; ++b) {
+        x0 = std::min(x0, hx[b]);
+        x1 = std::max(x1, hx[b]);
+        y0 = std::min(y0, hy[b]);
+        y1 = std::max(y1, hy[b]);
+      }
+    cx = 0.5 * (x0 + x1);
+    cy = 0.5 * (y0 + y1);
+    double r2 = 0;
+    for (int q = 0; q < ninc; ++q)
+      for (int64_t b = F->node_off[incs[q]]; b < F->node_off[incs[q] + 1]; ++b)
+        r2 = std::max(r2, (hx[b] - cx) * (hx[b] - cx) + (hy[b] - cy) * (hy[b] - cy));
+    r = std::sqrt(r2);
+  };
+  // clusters: plan levels 1 .. L - 2 (the root level is left out)
+  const int L = (int)plan.size();
+  const int nclev = std::max(0, std::min(L - 2, PMX_APPLY_MAXLEV));
+  std::vector<std::vector<int>> cid(L);
+  G.lev_off.assign(1, 0);
+  int nc = 0;
+  for (int l = 1; l <= nclev; ++l) {
+    cid[l].resize(plan[l].size());
+    for (size_t t = 0; t < plan[l].size(); ++t) cid[l][t] = nc++;
+    G.lev_off.push_back(nc);
+  }
+  G.n_clus = nc;
+  const int nsrc = m + nc;
+  G.incl.assign(4 * (size_t)nsrc, 0.0);
+  G.wave.assign(4 * (size_t)nw, 0.0);
+  std::vector<char> always(m, 0), usable(nc, 0), holds_always(nc, 0);
+  for (int j = 0; j < m; ++j) {
+    double* g = &G.incl[4 * (size_t)j];
+    circle(&j, 1, g[0], g[1], g[2]);
+    g[3] = (double)apply_source_order(k * g[2]);
+    if (g[3] > PMX_APPLY_PMAX) always[j] = 1;
+  }
+  G.kid_off.assign(1, 0);
+  G.kid_idx.clear();
+  double m2m_terms = 0;
+  for (int l = 1; l <= nclev; ++l)
+    for (size_t t = 0; t < plan[l].size(); ++t) {
+      const CellPlan& cp = plan[l][t];
+      const int c = cid[l][t];
+      double* g = &G.incl[4 * (size_t)(m + c)];
+      circle(cp.incl.data(), (int)cp.incl.size(), g[0], g[1], g[2]);
+      g[3] = (double)apply_source_order(k * g[2]);
+      bool ha = false;
+      if (cp.children.size() > 4) fail(PMX_EGEOM, "a tree cell with more than four children");
+      for (int ch : cp.children) {
+        int src;
+        if (l == 1) {
+          src = plan[0][ch].incl[0];
+          ha = ha || always[src];
+          m2m_terms += 2.0 * (2 * (PMX_APPLY_PMAXC + 2) + 1) * (2 * PMX_APPLY_NREC);
+        } else {
+          src = m + cid[l - 1][ch];
+          ha = ha || holds_always[cid[l - 1][ch]];
+          m2m_terms += 2.0 * (2 * (PMX_APPLY_PMAXC + 2) + 1) * (2 * PMX_APPLY_NRECA);
+        }
+        G.kid_idx.push_back(src);
+      }
+      G.kid_off.push_back((int)G.kid_idx.size());
+      holds_always[c] = ha;
+      usable[c] = !ha && g[3] <= PMX_APPLY_PMAXC;
+    }
+  for (int w = 0; w < nw; ++w) {
+    const int lo = 64 * w, hi = std::min(64 * w + 64, N);
+    double* g = &G.wave[4 * (size_t)w];
+    // the wave's nodes lie in consecutive inclusions: their circle over that node range
+    double x0 = hx[lo], x1 = hx[lo], y0 = hy[lo], y1 = hy[lo];
+    for (int b = lo; b < hi; ++b) {
       x0 = std::min(x0, hx[b]);
       x1 = std::max(x1, hx[b]);
       y0 = std::min(y0, hy[b]);
       y1 = std::max(y1, hy[b]);
     }
-    cx = 0.5 * (x0 + x1);
-    cy = 0.5 * (y0 + y1);
+    g[0] = 0.5 * (x0 + x1);
+    g[1] = 0.5 * (y0 + y1);
     double r2 = 0;
-    for (int64_t b = b0; b < b1; ++b) r2 = std::max(r2, (hx[b] - cx) * (hx[b] - cx) + (hy[b] - cy) * (hy[b] - cy));
-    r = std::sqrt(r2);
-  };
-  G.incl.assign(4 * (size_t)m, 0.0);
-  G.wave.assign(4 * (size_t)nw, 0.0);
-  double rimax = 0, rwmax = 0;
-  std::vector<int> always;   // expansions beyond the largest order: near for every wave
-  for (int j = 0; j < m; ++j) {
-    double* g = &G.incl[4 * (size_t)j];
-    circle(F->node_off[j], F->node_off[j + 1], g[0], g[1], g[2]);
-    g[3] = (double)apply_source_order(k * g[2]);
-    rimax = std::max(rimax, g[2]);
-    if (g[3] > PMX_APPLY_PMAX) always.push_back(j);
+    for (int b = lo; b < hi; ++b) r2 = std::max(r2, (hx[b] - g[0]) * (hx[b] - g[0]) + (hy[b] - g[1]) * (hy[b] - g[1]));
+    g[2] = std::sqrt(r2);
   }
-  for (int w = 0; w < nw; ++w) {
-    double* g = &G.wave[4 * (size_t)w];
-    circle(64 * (int64_t)w, std::min<int64_t>(64 * (int64_t)w + 64, N), g[0], g[1], g[2]);
-    rwmax = std::max(rwmax, g[2]);
-  }
-  const double h = PMX_APPLY_RATIO * rimax * (1.0 + 1e-9) + rwmax + 1e-12;
-  double gx0 = G.incl[0], gy0 = G.incl[1];
-  for (int j = 0; j < m; ++j) {
-    gx0 = std::min(gx0, G.incl[4 * (size_t)j]);
-    gy0 = std::min(gy0, G.incl[4 * (size_t)j + 1]);
-  }
-  std::map<std::pair<int64_t, int64_t>, std::vector<int>> grid;
-  for (int j = 0; j < m; ++j)
-    grid[{(int64_t)std::floor((G.incl[4 * (size_t)j] - gx0) / h), (int64_t)std::floor((G.incl[4 * (size_t)j + 1] - gy0) / h)}]
-        .push_back(j);
+  // the walk: top clusters (or every inclusion when there are none)
+  std::vector<int> top;
+  if (nclev >= 1)
+    for (size_t t = 0; t < plan[nclev].size(); ++t) top.push_back(m + cid[nclev][t]);
+  else
+    for (int j = 0; j < m; ++j) top.push_back(j);
   G.off.assign(nw + 1, 0);
+  G.foff.assign(nw + 1, 0);
   G.idx.clear();
-  std::vector<int> cand;
-  std::vector<char> isnear(count ? m : 0, 0);
+  G.fidx.clear();
+  std::vector<int> stack, nearv, farv;
   double near_pairs = 0, far_orders = 0, far_pairs = 0;
   for (int w = 0; w < nw; ++w) {
-    const double *gw = &G.wave[4 * (size_t)w];
-    cand.assign(always.begin(), always.end());
-    const int64_t cxw = (int64_t)std::floor((gw[0] - gx0) / h), cyw = (int64_t)std::floor((gw[1] - gy0) / h);
-    for (int64_t dx = -1; dx <= 1; ++dx)
-      for (int64_t dy = -1; dy <= 1; ++dy) {
-        auto it = grid.find({cxw + dx, cyw + dy});
-        if (it == grid.end()) continue;
-        for (int j : it->second) {
-          const double* g = &G.incl[4 * (size_t)j];
-          const double rmin = std::hypot(gw[0] - g[0], gw[1] - g[1]) - gw[2];
-          if (rmin < PMX_APPLY_RATIO * g[2] && g[3] <= PMX_APPLY_PMAX) cand.push_back(j);
+    const double* gw = &G.wave[4 * (size_t)w];
+    const double nt = (double)(std::min(64 * w + 64, N) - 64 * w);
+    nearv.clear();
+    farv.clear();
+    stack.assign(top.rbegin(), top.rend());
+    while (!stack.empty()) {
+      const int sidx = stack.back();
+      stack.pop_back();
+      const double* g = &G.incl[4 * (size_t)sidx];
+      const double rmin = std::hypot(gw[0] - g[0], gw[1] - g[1]) - gw[2];
+      if (sidx >= m) {
+        const int c = sidx - m;
+        if (usable[c] && rmin >= PMX_APPLY_RATIO * g[2]) {
+          const double p = std::max(g[3], std::ceil(PMX_APPLY_TRUNC / std::log(rmin / g[2])));
+          if (p <= PMX_APPLY_PMAXC) {
+            farv.push_back(sidx);
+            far_orders += nt * (p + 2);
+            far_pairs += nt;
+            continue;
+          }
         }
-      }
-    std::sort(cand.begin(), cand.end());
-    G.idx.insert(G.idx.end(), cand.begin(), cand.end());
-    G.off[w + 1] = (int)G.idx.size();
-    if (count) {
-      const double nt = (double)(std::min(64 * w + 64, N) - 64 * w);
-      for (int j : cand) {
-        isnear[j] = 1;
-        near_pairs += nt * (double)(F->node_off[j + 1] - F->node_off[j]);
-      }
-      for (int j = 0; j < m; ++j) {
-        if (isnear[j]) continue;
-        const double* g = &G.incl[4 * (size_t)j];
-        const double rmin = std::hypot(gw[0] - g[0], gw[1] - g[1]) - gw[2];
+        for (int q = G.kid_off[c + 1] - 1; q >= G.kid_off[c]; --q) stack.push_back(G.kid_idx[q]);
+      } else if (always[sidx] || rmin < PMX_APPLY_RATIO * g[2]) {
+        nearv.push_back(sidx);
+        near_pairs += nt * (double)(F->node_off[sidx + 1] - F->node_off[sidx]);
+      } else {
         const double p = std::min((double)PMX_APPLY_PMAX, std::max(g[3], std::ceil(PMX_APPLY_TRUNC / std::log(rmin / g[2]))));
+        farv.push_back(sidx);
         far_orders += nt * (p + 2);
         far_pairs += nt;
       }
-      for (int j : cand) isnear[j] = 0;
     }
+    std::sort(nearv.begin(), nearv.end());
+    std::sort(farv.begin(), farv.end());
+    G.idx.insert(G.idx.end(), nearv.begin(), nearv.end());
+    G.fidx.insert(G.fidx.end(), farv.begin(), farv.end());
+    G.off[w + 1] = (int)G.idx.size();
+    G.foff[w + 1] = (int)G.fidx.size();
   }
   if (count) {
     // near pairs include each target's own inclusion, which the apply leaves out
@@ -1686,22 +1757,9 @@ void apply_geometry(pmx_factor* F, ApplyGeo& G, bool count, hipStream_t s) {
       near_pairs -= n * n;
     }
     const double p2m = (double)N * (2 * (PMX_APPLY_PMAX + 3) + 1);
-    G.flops_rhs = 32.0 * near_pairs + 48.0 * far_orders + 72.0 * p2m;
+    G.flops_rhs = 32.0 * near_pairs + 48.0 * far_orders + 72.0 * p2m + 8.0 * m2m_terms;
     G.flops_fixed = 130.0 * near_pairs + 100.0 * far_pairs + 26.0 * far_orders;
   }
-}
-
-// first inclusion of each of (about) nsplit far source ranges of equal node counts
-std::vector<int> apply_split_incl(const pmx_factor* F, int nsplit) {
-  std::vector<int> b{0};
-  for (int sp = 1; sp < nsplit; ++sp) {
-    const int64_t target = (int64_t)F->n_nodes * sp / nsplit;
-    int j = (int)(std::lower_bound(F->node_off.begin(), F->node_off.end(), target) - F->node_off.begin());
-    j = std::min(j, F->m);
-    if (j > b.back() && j < F->m) b.push_back(j);
-  }
-  b.push_back(F->m);
-  return b;
 }
 
 void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vector<int>& incl,
@@ -1715,8 +1773,7 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   D.nr_max = tune_choice(TK_APPLY_NR, 8, ta, tb, 0, 8, F->n_nodes, nrhs, 0);
   if (D.nr_max != 1 && D.nr_max != 2 && D.nr_max != 4 && D.nr_max != 8) D.nr_max = 8;
   const int wg = std::max(64, std::min(1 << 20, tune_choice(TK_APPLY_WG, 8, ta, tb, 0, 8192, F->n_nodes, nrhs, 0)));
-  const std::vector<int> split = apply_split_incl(F, apply_splits(F->n_nodes, wg));
-  D.nsplit = (int)split.size() - 1;
+  D.nsplit = apply_splits(F->n_nodes, wg);
   ApplyGeo G;
   apply_geometry(F, G, F->opts.timing != 0, s);
   D.flops_fixed = G.flops_fixed;
@@ -1755,12 +1812,19 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   aa.pack = A.alloc<double>(apply_pack_size(F->n_nodes, 8));
   aa.near_off = A.upload(G.off, s);
   aa.near_idx = A.upload(G.idx, s);
-  aa.split_incl = A.upload(split, s);
+  aa.far_off = A.upload(G.foff, s);
+  aa.far_idx = A.upload(G.fidx, s);
   aa.nsplit_near = nnear;
   aa.incl_geo = A.upload(G.incl, s);
   aa.wave_geo = A.upload(G.wave, s);
-  aa.coef = A.alloc<zd>(apply_coef_size(F->m, 8));
+  aa.kid_off = A.upload(G.kid_off, s);
+  aa.kid_idx = A.upload(G.kid_idx, s);
+  aa.coef = A.alloc<zd>(apply_coef_size(F->m + G.n_clus, 8));
   aa.n_incl = F->m;
+  aa.n_clus = G.n_clus;
+  aa.n_lev = (int)G.lev_off.size() - 1;
+  for (int l = 0; l <= aa.n_lev; ++l) aa.lev_off[l] = G.lev_off[l];
+  D.n_src = F->m + G.n_clus;
   D.f = f;
   D.out = out;
   D.nrhs = nrhs;
@@ -1936,7 +2000,7 @@ void count_apply_work(pmx_factor* F, int nrhs) {
   const double N2 = 2.0 * F->n_nodes;
   F->info.kernel_flops[PK_APPLY] += D.flops_fixed + D.flops_rhs * nrhs;
   F->info.kernel_bytes[PK_APPLY] += 8.0 * 5 * F->n_nodes + 16.0 * N2 * nrhs * (1 + D.nslots) +
-                                    2.0 * 16.0 * 6.0 * PMX_APPLY_NREC * F->m * nrhs;
+                                    2.0 * 16.0 * 6.0 * PMX_APPLY_NRECA * D.n_src * nrhs;
 }
 
 // FP64 factor: right-hand side into the leaf vectors, one solve pass, solution to xout.
@@ -2249,16 +2313,12 @@ void tune_apply(pmx_factor* F, const TuneRecorder& rec, TuneTable& t, int reps, 
   double spent = 0, best = 1e300;
   int bi = 0;
   std::string note;
-  std::map<int, int*> splits;
   for (size_t c = 0; c < cand.size() && spent < budget_ms; ++c) {
-    const std::vector<int> split = apply_split_incl(F, apply_splits(F->n_nodes, cand[c].second));
-    const int ns = (int)split.size() - 1;
+    const int ns = apply_splits(F->n_nodes, cand[c].second);
     aa.nsplit_near = apply_near_splits(F->n_nodes, cand[c].second);
     const int slots = ns + aa.nsplit_near;
     if (!parts.count(slots)) parts[slots] = tmp.alloc<zd>(D.total * slots);
-    if (!splits.count(ns)) splits[ns] = tmp.upload(split, s);
     aa.part = parts[slots];
-    aa.split_incl = splits[ns];
     double tbest = 1e300;
     for (int r = 0; r <= reps; ++r) {
       HIPCHK(hipEventRecord(e0, s));
@@ -2584,6 +2644,7 @@ pmx_status pmx_probe_apply(const pmx_geometry* geom, int32_t nrhs, const pmx_c64
     hipStream_t s = (hipStream_t)stream;
     pmx_factor F;
     pmx_options_default(&F.opts);
+    make_plan(geom, F.opts, F.plan);   // the tree of the expansion clusters
     upload_geometry(&F, geom, s);
     Arena tmp;
     std::vector<int> incl(geom->m);

@@ -112,6 +112,23 @@ def test_dense_apply_scattered_uneven(pmx):
     assert err < 1e-12
 
 
+@pytest.mark.parametrize("g,n,nrhs,nrow", [(12, 16, 2, 96), (16, 128, 4, 48)])
+def test_dense_apply_clusters_sampled_rows(pmx, g, n, nrhs, nrow):
+    """Grids large enough that the apply takes clusters of 2x2 and 4x4 inclusions through
+    translated expansions (the 16x16 grid of 128-node stars is the benchmark's): sampled rows
+    of A x against the oracle's on-the-fly row evaluation."""
+    w = W.star_grid(g, n=n, k_ext=10.0, k_int=15.0, seed=5)
+    w.angles = 2 * np.pi * np.arange(nrhs) / nrhs
+    x = crandn(w.n_unknowns, nrhs)
+    got = pmx.probe_apply(w, x)
+    rows = np.sort(np.random.default_rng(11).choice(w.n_unknowns, size=nrow, replace=False))
+    f = dense.rhs(dense.Geometry(w), w.angles)[rows]
+    ref = f - dense.residual_rows(w, x, rows)
+    err = np.abs(got[rows] - ref).max() / np.abs(ref).max()
+    print("cluster apply rel err", err, "N", w.n_unknowns)
+    assert err < 1e-12
+
+
 def _mixed(pmx, w, **kw):
     import torch
     o = pmx.options(w, precision=1, id_tol=kw.pop("id_tol", 1e-6), **kw)
