@@ -171,7 +171,7 @@ def roofline(info_list, k, top, names, real_bytes, workload_tag):
 
 
 # timer slots that cover several kernels launched back to back (summed per launch)
-SLOT_KERNELS = {"k_apply_off": ("k_apply_p2m", "k_apply_far", "k_apply_near")}
+SLOT_KERNELS = {"k_apply_off": ("k_apply_p2m", "k_apply_m2m", "k_apply_far", "k_apply_near")}
 
 
 def summarize_pmc(fetch_csv, write_csv, kname, workload_tag):
@@ -179,8 +179,9 @@ def summarize_pmc(fetch_csv, write_csv, kname, workload_tag):
     KiB per dispatch), each scaled by what the same counter reads for the 256 MiB device
     copy that --copy-calibration runs first (expected 256 MiB fetched and 256 MiB written).
     `kname` may carry template arguments ("k_ts_update<double>") to pick one instantiation;
-    a timer slot of several kernels (k_apply_off: far and near parts) sums the mean of each
-    part.  The summary is stored under the plain name."""
+    a timer slot of several kernels (k_apply_off: expansions, translations, far and near
+    parts) sums each part's dispatches per launch of the slot (the first part's dispatch
+    count).  The summary is stored under the plain name."""
     import csv
     base = kname.split("<")[0]
     parts = SLOT_KERNELS.get(kname, (kname,))
@@ -209,8 +210,9 @@ def summarize_pmc(fetch_csv, write_csv, kname, workload_tag):
     ref = float(256 << 20)
     ff = cf[0] / ref if cf else 1.0
     fw = cw[0] / ref if cw else 1.0
-    fb = sum(np.mean(fetch[p]) for p in parts) / ff
-    wb = sum(np.mean(write[p]) for p in parts) / fw
+    nl = len(fetch[parts[0]])
+    fb = sum(np.sum(fetch[p]) for p in parts) / nl / ff
+    wb = sum(np.sum(write[p]) for p in parts) / nl / fw
     out = {"kernel": base, "instantiation": kname, "parts": list(parts), "workload": workload_tag,
            "source_hash": kernel_source_hash(base), "bytes_per_launch": fb + wb,
            "launches": len(fetch[parts[0]]), "fetch_scale": ff, "write_scale": fw,
