@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <future>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -323,6 +324,9 @@ struct Tier {
 };
 
 struct SolveState;
+namespace {
+struct ApplyGeo;
+}
 
 struct pmx_factor {
   // reuse of the factorisation's temporary device blocks (declared first: destroyed last)
@@ -354,6 +358,9 @@ struct pmx_factor {
   std::vector<float> leaf_pred;
   // launch-parameter table of options.tune_path (NULL: built-in rules)
   std::unique_ptr<TuneTable> tune;
+  // refined forms: the operator apply's geometry (tree walk per target wave), built on a
+  // host thread while the device factors; read by the first solve
+  std::future<std::shared_ptr<ApplyGeo>> apply_geo;
   pmx_factor() : arena(&pool) {
     t64.prog.arena.set_pool(&pool);
     t32.prog.arena.set_pool(&pool);
@@ -1604,10 +1611,8 @@ struct ApplyGeo {
   double flops_fixed = 0, flops_rhs = 0;
 };
 
-void apply_geometry(pmx_factor* F, ApplyGeo& G, bool count, hipStream_t s) {
-  std::vector<double> hx, hy;
-  download(hx, F->x, F->n_nodes, s);
-  download(hy, F->y, F->n_nodes, s);
+void apply_geometry(const pmx_factor* F, const std::vector<double>& hx, const std::vector<double>& hy, ApplyGeo& G,
+                    bool count) {
   const int m = F->m, N = F->n_nodes, nw = (N + 63) / 64;
   const double k = F->k_ext;
   const auto& plan = F->plan;
@@ -1775,7 +1780,14 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   const int wg = std::max(64, std::min(1 << 20, tune_choice(TK_APPLY_WG, 8, ta, tb, 0, 8192, F->n_nodes, nrhs, 0)));
   D.nsplit = apply_splits(F->n_nodes, wg);
   ApplyGeo G;
-  apply_geometry(F, G, F->opts.timing != 0, s);
+  if (F->apply_geo.valid()) {
+    G = *F->apply_geo.get();
+  } else {
+    std::vector<double> hx, hy;
+    download(hx, F->x, F->n_nodes, s);
+    download(hy, F->y, F->n_nodes, s);
+    apply_geometry(F, hx, hy, G, F->opts.timing != 0);
+  }
   D.flops_fixed = G.flops_fixed;
   D.flops_rhs = G.flops_rhs;
   const int nnear = apply_near_splits(F->n_nodes, wg);
@@ -2426,6 +2438,19 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
     F->ss.reset(new SolveState(&F->pool));
     if (o.learned) leaf_predictions(F.get(), geom, o.model_path, s);
     upload_geometry(F.get(), geom, s);
+    if (o.precision != 0) {
+      // host copies of the coordinates (the caller's arrays may go away after this call)
+      const int64_t N = geom->node_off[geom->m];
+      auto hx = std::make_shared<std::vector<double>>(geom->x, geom->x + N);
+      auto hy = std::make_shared<std::vector<double>>(geom->y, geom->y + N);
+      const pmx_factor* Fc = F.get();
+      const bool count = o.timing != 0;
+      F->apply_geo = std::async(std::launch::async, [Fc, hx, hy, count] {
+        auto G = std::make_shared<ApplyGeo>();
+        apply_geometry(Fc, *hx, *hy, *G, count);
+        return G;
+      });
+    }
     if (o.precision == 1) {
       factor_all<float>(F.get(), s);
       fill_info<float>(F.get());
