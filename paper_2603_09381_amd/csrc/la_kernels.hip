@@ -694,22 +694,49 @@ __global__ __launch_bounds__(NT) void k_getrf_panel_u(const LuDescT<R>* lus, int
   }
 }
 
-// apply the swaps of panel [j0, j0+jb) to the columns outside the panel
+// apply the swaps of panel [j0, j0+jb) to the columns outside the panel.  The swaps are
+// composed first (one lane, in LDS: cont[r] = the row whose entry ends in row r), so that
+// each thread (one column) loads every affected entry at once and stores them after: the
+// rows j0 .. j0+jb-1 and the pivot rows, at most 2 PMX_LU_NB entries, with no chain of
+// dependent loads.
 template <class R>
-__global__ void k_laswp_panel(const LuDescT<R>* lus, int j0) {
+__global__ __launch_bounds__(64) void k_laswp_panel(const LuDescT<R>* lus, int j0) {
+  typedef cx<R> C;
+  extern __shared__ int cont[];   // [n]
   const LuDescT<R> L = lus[blockIdx.y];
-  const int jb = min(PMX_LU_NB, L.n - j0);
+  const int n = L.n;
+  const int jb = min(PMX_LU_NB, n - j0);
   if (jb <= 0) return;
-  int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= L.n - jb) return;
+  if ((int)(blockIdx.x * 64) >= n - jb) return;
+  const auto ipiv = gbl(L.ipiv);
+  for (int r = threadIdx.x; r < n; r += 64) cont[r] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int c = j0; c < j0 + jb; ++c) {
+      const int p = ipiv[c];
+      const int t = cont[c];
+      cont[c] = cont[p];
+      cont[p] = t;
+    }
+  }
+  __syncthreads();
+  int col = blockIdx.x * 64 + threadIdx.x;
+  if (col >= n - jb) return;
   if (col >= j0) col += jb;
-  cx<R>* A = L.a + col * L.ld;
-  for (int c = j0; c < j0 + jb; ++c) {
-    int p = gbl(L.ipiv)[c];
-    if (p != c) {
-      cx<R> t = A[c];
-      A[c] = A[p];
-      A[p] = t;
+  const auto A = gbl(L.a) + (int64_t)col * L.ld;
+  C v[2 * PMX_LU_NB];
+#pragma unroll
+  for (int c = 0; c < PMX_LU_NB; ++c) {
+    if (c < jb) {
+      v[c] = A[cont[j0 + c]];
+      v[PMX_LU_NB + c] = A[cont[ipiv[j0 + c]]];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < PMX_LU_NB; ++c) {
+    if (c < jb) {
+      A[j0 + c] = v[c];
+      A[ipiv[j0 + c]] = v[PMX_LU_NB + c];
     }
   }
 }
@@ -840,7 +867,10 @@ void la_getrf(const LuDescT<R>* d_lu, int batch, int max_n, int* d_info, hipStre
       if (!lu_panel_fits<R>(v, rows)) v = dflt;
       la_lu_panel<R>(v, d_lu, batch, j0, d_info, s);
     }
-    hipLaunchKernelGGL(k_laswp_panel<R>, dim3((max_n + 255) / 256, batch), dim3(256), 0, s, d_lu, j0);
+    const size_t shm = (size_t)max_n * sizeof(int);
+    if (shm > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)k_laswp_panel<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_laswp_panel<R>, dim3((max_n + 63) / 64, batch), dim3(64), shm, s, d_lu, j0);
     int rem = max_n - j0 - PMX_LU_NB;
     if (rem > 0) {
       launch_trsm_small<R, false, true>(FLuTrsm<R>{d_lu, j0}, batch, rem, s);
@@ -855,20 +885,46 @@ void la_getrf(const LuDescT<R>* d_lu, int batch, int max_n, int* d_info, hipStre
 
 // ---------------------------------------------------------------------------------
 // getrs
+// B <- P B: row i of the result is row perm[i] of B (from getrf, or composed here from
+// ipiv by one lane when the factor has none).  Each workgroup stages ncol columns in LDS
+// and writes them back permuted: two coalesced passes instead of a chain of swaps.
 template <class R>
-__global__ void k_laswp_rhs(const LuDescT<R>* lus, const MatT<R>* bs) {
+__global__ __launch_bounds__(256) void k_laswp_rhs(const LuDescT<R>* lus, const MatT<R>* bs, int ncol) {
+  typedef cx<R> C;
+  extern __shared__ char ls_smem[];
   const LuDescT<R> L = lus[blockIdx.y];
   const MatT<R> B = bs[blockIdx.y];
-  int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= B.n) return;
-  cx<R>* x = B.p + col * B.ld;
-  for (int c = 0; c < L.n; ++c) {
-    int p = gbl(L.ipiv)[c];
-    if (p != c) {
-      cx<R> t = x[c];
-      x[c] = x[p];
-      x[p] = t;
+  const int n = L.n;
+  const int c0 = blockIdx.x * ncol;
+  if (n <= 0 || c0 >= B.n) return;
+  const int nc = min(ncol, B.n - c0);
+  int* cont = reinterpret_cast<int*>(ls_smem);                       // [n]
+  C* col = reinterpret_cast<C*>(ls_smem + ((n * sizeof(int) + 15) / 16) * 16);   // [ncol][n]
+  const auto Bp = gbl(B.p);
+  if (L.perm) {
+    const auto perm = gbl(L.perm);
+    for (int r = threadIdx.x; r < n; r += 256) cont[r] = perm[r];
+  } else {
+    for (int r = threadIdx.x; r < n; r += 256) cont[r] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const auto ipiv = gbl(L.ipiv);
+      for (int c = 0; c < n; ++c) {
+        const int p = ipiv[c];
+        const int t = cont[c];
+        cont[c] = cont[p];
+        cont[p] = t;
+      }
     }
+  }
+  for (int e = threadIdx.x; e < n * nc; e += 256) {
+    const int i = e % n, c = e / n;
+    col[c * n + i] = Bp[i + (int64_t)(c0 + c) * B.ld];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * nc; e += 256) {
+    const int i = e % n, c = e / n;
+    Bp[i + (int64_t)(c0 + c) * B.ld] = col[c * n + cont[i]];
   }
 }
 
@@ -943,7 +999,15 @@ template <class R>
 void la_getrs(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max_n, int max_nrhs, hipStream_t s) {
   if (batch <= 0 || max_n <= 0 || max_nrhs <= 0) return;
   const cx<R> one = cmk<R>(1, 0), mone = cmk<R>(-1, 0);
-  hipLaunchKernelGGL(k_laswp_rhs<R>, dim3((max_nrhs + 63) / 64, batch), dim3(64), 0, s, d_lu, d_b);
+  {
+    // columns staged per workgroup: about 32 KiB of LDS, at least one
+    const size_t cb = (size_t)max_n * sizeof(cx<R>);
+    const int ncol = (int)std::max<size_t>(1, std::min<size_t>(16, (32 * 1024) / cb));
+    const size_t shm = ((size_t)max_n * sizeof(int) + 15) / 16 * 16 + (size_t)ncol * cb;
+    if (shm > 64 * 1024)
+      (void)hipFuncSetAttribute((const void*)k_laswp_rhs<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipLaunchKernelGGL(k_laswp_rhs<R>, dim3((max_nrhs + ncol - 1) / ncol, batch), dim3(256), shm, s, d_lu, d_b, ncol);
+  }
   const int nblk = (max_n + PMX_LU_NB - 1) / PMX_LU_NB;
   for (int bk = 0; bk < nblk; ++bk) {
     int j0 = bk * PMX_LU_NB;
