@@ -402,9 +402,19 @@ __global__ __launch_bounds__(64) void k_trsm_small(F f) {
   const int tid = threadIdx.x;
   if (blockIdx.x * 64 >= a.nrhs) return;
   const int nb = a.nb;
-  for (int e = tid; e < nb * nb; e += 64) {
-    const int r = e % nb, c = e / nb;
-    Ts[r][c] = gT[r + (int64_t)c * a.ldt];
+  {
+    // all loads of the triangle issued before the LDS stores (nb^2 <= 16 x 64)
+    C tv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = min(tid + 64 * q, nb * nb - 1);
+      tv[q] = gT[e % nb + (int64_t)(e / nb) * a.ldt];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 64 * q;
+      if (e < nb * nb) Ts[e % nb][e / nb] = tv[q];
+    }
   }
   if (!UNIT && tid < nb) dinv[tid] = zrecip(gT[tid + (int64_t)tid * a.ldt]);
   const int col = blockIdx.x * 64 + tid;
@@ -917,9 +927,19 @@ __global__ __launch_bounds__(256) void k_laswp_rhs(const LuDescT<R>* lus, const 
       }
     }
   }
-  for (int e = threadIdx.x; e < n * nc; e += 256) {
-    const int i = e % n, c = e / n;
-    col[c * n + i] = Bp[i + (int64_t)(c0 + c) * B.ld];
+  // eight loads in flight per thread before their LDS stores
+  for (int e0 = threadIdx.x; e0 < n * nc; e0 += 256 * 8) {
+    C t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = min(e0 + 256 * u, n * nc - 1);
+      t[u] = Bp[e % n + (int64_t)(c0 + e / n) * B.ld];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + 256 * u;
+      if (e < n * nc) col[(e / n) * n + e % n] = t[u];
+    }
   }
   __syncthreads();
   for (int e = threadIdx.x; e < n * nc; e += 256) {
