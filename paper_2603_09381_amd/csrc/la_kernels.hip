@@ -280,29 +280,30 @@ static void launch_zgemm(F f, int batch, int max_m, int max_n, cx<R> alpha, cx<R
 
 // C = alpha A B + beta C for few columns of B (n <= NB, both operands untransposed): the
 // product is bound by reading A, which MFMA tiles of 64 columns would mostly waste.  A
-// workgroup of four waves takes 64 rows of one matrix; wave w accumulates the k range
+// workgroup of eight waves takes 64 rows of one matrix; wave w accumulates the k range
 // [w kc, (w + 1) kc) with one row per lane (the column-major A is read 64 consecutive
-// rows at a time, coalesced) and the row of B of each k read at a wave-uniform address;
-// the four partial sums are added through LDS.
+// rows at a time, coalesced, eight loads in flight) and the row of B of each k read at a
+// wave-uniform address; the eight partial sums are added through LDS.
 template <class R, int NB, class F>
-__global__ __launch_bounds__(256) void k_zgemm_skinny(F f, cx<R> alpha, cx<R> beta) {
+__global__ __launch_bounds__(512) void k_zgemm_skinny(F f, cx<R> alpha, cx<R> beta) {
   typedef cx<R> C;
+  constexpr int NW = 8;   // waves splitting k
   GemmArgsT<R> g;
   if (!f(blockIdx.z, g)) return;
   const auto gB = gbl(g.B);
   const int tm = blockIdx.x * 64;
   if (tm >= g.m) return;
-  __shared__ C red[3][NB][64];
+  __shared__ C red[NW - 1][NB][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = min(tm + lane, g.m - 1);
-  const int kc = (g.k + 3) / 4;
+  const int kc = (g.k + NW - 1) / NW;
   const int k0 = min(wave * kc, g.k), k1 = min(k0 + kc, g.k);
   const int n = min(g.n, NB);
   R ar[NB], ai[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) ar[j] = ai[j] = R(0);
   const auto Ap = gbl(g.A) + row;
-#pragma unroll 4
+#pragma unroll 8
   for (int kk = k0; kk < k1; ++kk) {
     const C a = Ap[(int64_t)kk * g.lda];
 #pragma unroll
@@ -328,7 +329,7 @@ __global__ __launch_bounds__(256) void k_zgemm_skinny(F f, cx<R> alpha, cx<R> be
     if (j < n) {
       C v = cmk<R>(ar[j], ai[j]);
 #pragma unroll
-      for (int w = 0; w < 3; ++w) v = zadd(v, red[w][j][lane]);
+      for (int w = 0; w < NW - 1; ++w) v = zadd(v, red[w][j][lane]);
       v = zmul(alpha, v);
       auto cp = gbl(g.C) + (tm + lane) + (int64_t)j * g.ldc;
       if (use_beta) v = zfma(beta, *cp, v);
@@ -344,9 +345,9 @@ static bool launch_zgemm_skinny(F f, int batch, int max_m, int max_n, cx<R> alph
   dim3 grid((max_m + 63) / 64, 1, batch);
   KScope ks(PK_ZGEMM, s);
   if (max_n <= 4)
-    hipLaunchKernelGGL((k_zgemm_skinny<R, 4, F>), grid, dim3(256), 0, s, f, alpha, beta);
+    hipLaunchKernelGGL((k_zgemm_skinny<R, 4, F>), grid, dim3(512), 0, s, f, alpha, beta);
   else
-    hipLaunchKernelGGL((k_zgemm_skinny<R, 8, F>), grid, dim3(256), 0, s, f, alpha, beta);
+    hipLaunchKernelGGL((k_zgemm_skinny<R, 8, F>), grid, dim3(512), 0, s, f, alpha, beta);
   return true;
 }
 
@@ -1465,7 +1466,7 @@ bool la_getrs_lds(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max
   if (shm4 > 128 * 1024 || max_n <= 0) return false;
   // few matrices: one workgroup per right-hand side, so that more compute units share the
   // sequential sweeps (each reads the factor once more); many: four right-hand sides each
-  const int nrc = (batch * max_nrhs <= 256 && max_n <= 1920) ? 1 : 4;
+  const int nrc = (batch * max_nrhs <= 256 && max_n <= 1792) ? 1 : 4;
   const size_t shm = (size_t)max_n * nrc * sizeof(cx<R>);
   const dim3 grid(batch, (max_nrhs + nrc - 1) / nrc);
   KScope ks(PK_GETRS, s);
@@ -1476,15 +1477,18 @@ bool la_getrs_lds(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max
   };
   // blocks of 32 rows (FP32) or 16 (FP64): the row held in registers stays at 64 of them
   constexpr int BS = sizeof(R) == 4 ? 32 : 16;
+  // one right-hand side per workgroup: 512 threads and diagonal blocks of 64 rows (FP32) or
+  // 32 (FP64), half the sequential steps; the row-owning threads take up to four rows each
+  constexpr int BS1 = sizeof(R) == 4 ? 64 : 32;
   if (nrc == 1) {
-    if (max_n <= 256)
-      go(k_getrs_lds<R, 256, 1, BS, 1>, 320);
-    else if (max_n <= 448)
-      go(k_getrs_lds<R, 448, 1, BS, 1>, 512);
-    else if (max_n <= 960)
-      go(k_getrs_lds<R, 960, 1, BS, 1>, 1024);
+    if (max_n <= 448)
+      go(k_getrs_lds<R, 448, 1, BS1, 1>, 512);
+    else if (max_n <= 896)
+      go(k_getrs_lds<R, 448, 2, BS1, 1>, 512);
+    else if (max_n <= 1344)
+      go(k_getrs_lds<R, 448, 3, BS1, 1>, 512);
     else
-      go(k_getrs_lds<R, 960, 2, BS, 1>, 1024);
+      go(k_getrs_lds<R, 448, 4, BS1, 1>, 512);
   } else if (max_n <= 256) {
     go(k_getrs_lds<R, 256, 1, BS, 4>, 320);
   } else if (max_n <= 448) {

@@ -50,7 +50,7 @@ def test_zgemm(pmx, opa, opb, m, n, k):
                                    (1, 4, 3), (200, 4, 0)])
 def test_zgemm_few_columns(pmx, m, n, k):
     """Untransposed products with at most 8 columns take the row-per-lane kernel (4- and
-    8-column instances, k split over four waves with ragged ends, rows beyond a multiple of
+    8-column instances, k split over eight waves with ragged ends, rows beyond a multiple of
     64, k = 0)."""
     batch = 3
     A = crandn(batch, m, k)
