@@ -1220,7 +1220,9 @@ void factor_all(pmx_factor* F, hipStream_t s) {
       assemble_diag(F, tmp, incl, F->Dself, L0.offD, s);
       asm_convert(F->Dself, L0.D, td, s);
     }
-    sync_check(s);
+    // no synchronisation: the temporaries go back to the pool, whose blocks only later
+    // work of this stream reuses, and the host goes on building the next descriptors
+    HIPCHK(hipGetLastError());
   }
   F->info.t_phase_ms[0] += now_ms() - t0;
   LevelData<R> cur = std::move(L0);
@@ -1230,7 +1232,7 @@ void factor_all(pmx_factor* F, hipStream_t s) {
       Arena tmp(&F->pool);
       LevelData<R> nxt;
       merge_level(F, T.lev.back(), plan[lv], nxt, tmp, s);
-      sync_check(s);
+      HIPCHK(hipGetLastError());
       cur = std::move(nxt);
       F->info.t_phase_ms[2] += now_ms() - tm;
     }
