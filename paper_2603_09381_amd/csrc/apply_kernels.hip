@@ -302,7 +302,7 @@ constexpr int M2M_NI = 2 * PMX_APPLY_NRECA + 1;            // child orders -NREC
 constexpr int M2M_KIDS = 4;
 
 template <int NR>
-__global__ __launch_bounds__(256) void k_apply_m2m(ApplyArgs A, int c0) {
+__global__ __launch_bounds__(512) void k_apply_m2m(ApplyArgs A, int c0) {
   const int c = c0 + blockIdx.x;
   const int sc = A.n_incl + c;
   const double Cx = A.incl_geo[4 * sc], Cy = A.incl_geo[4 * sc + 1];
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(256) void k_apply_m2m(ApplyArgs A, int c0) {
   __shared__ zd An[NR][M2M_NI], Bn[NR][M2M_NI];
   __shared__ zd accA[M2M_NM][NR], accB[M2M_NM][NR];
   const int tid = threadIdx.x;
-  for (int e = tid; e < M2M_NM * NR; e += 256) {
+  for (int e = tid; e < M2M_NM * NR; e += 512) {
     accA[e / NR][e % NR] = zmk(0, 0);
     accB[e / NR][e % NR] = zmk(0, 0);
   }
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void k_apply_m2m(ApplyArgs A, int c0) {
     }
   }
   __syncthreads();
-  for (int e = tid; e < nk * (2 * M2M_NU + 1); e += 256) {
+  for (int e = tid; e < nk * (2 * M2M_NU + 1); e += 512) {
     const int kc = e / (2 * M2M_NU + 1), nu = e % (2 * M2M_NU + 1) - M2M_NU;
     const int ch = A.kid_idx[q0 + kc];
     const double dx = A.incl_geo[4 * ch] - Cx, dy = A.incl_geo[4 * ch + 1] - Cy;
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void k_apply_m2m(ApplyArgs A, int c0) {
     const zd* rec = A.coef + (int64_t)ch * PMX_APPLY_NRECA * NR * 6;
     __syncthreads();   // the previous child's A, B are read no more; the R table is complete
     // stored: A_n for |n| <= nrc - 1, B_n for 2 - nrc <= n <= nrc; the rest is zero
-    for (int e = tid; e < NR * M2M_NI; e += 256) {
+    for (int e = tid; e < NR * M2M_NI; e += 512) {
       const int rr = e / M2M_NI, n = e % M2M_NI - PMX_APPLY_NRECA;
       zd a = zmk(0, 0), b = zmk(0, 0);
       if (n >= 1 - nrc && n <= nrc - 1) a = n >= 0 ? rec[((int64_t)n * NR + rr) * 6] : rec[((int64_t)(-n) * NR + rr) * 6 + 1];
@@ -374,9 +374,10 @@ __global__ __launch_bounds__(256) void k_apply_m2m(ApplyArgs A, int c0) {
       Bn[rr][n + PMX_APPLY_NRECA] = b;
     }
     __syncthreads();
-    for (int e = tid; e < M2M_NM * NR; e += 256) {
+    for (int e = tid; e < M2M_NM * NR; e += 512) {
       const int m = e / NR - M2M_MO, rr = e % NR;
       double ar = 0, ai = 0, br = 0, bi = 0;
+#pragma unroll 4
       for (int n = 1 - nrc; n <= nrc; ++n) {
         const zd R = Rt[kc][m - n + M2M_NU];
         const zd a = An[rr][n + PMX_APPLY_NRECA], b = Bn[rr][n + PMX_APPLY_NRECA];
@@ -391,7 +392,7 @@ __global__ __launch_bounds__(256) void k_apply_m2m(ApplyArgs A, int c0) {
   }
   __syncthreads();
   zd* out = A.coef + (int64_t)sc * PMX_APPLY_NRECA * NR * 6;
-  for (int e = tid; e < PMX_APPLY_NRECA * NR; e += 256) {
+  for (int e = tid; e < PMX_APPLY_NRECA * NR; e += 512) {
     const int m = e / NR, rr = e % NR;
     zd* o = out + ((int64_t)m * NR + rr) * 6;
     const zd z0 = zmk(0, 0);
@@ -592,7 +593,7 @@ static void apply_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipS
   hipLaunchKernelGGL(k_apply_p2m<NR>, dim3(m), dim3(64), 0, s, A, (const double*)pk, r0);
   for (int l = 0; l < A.n_lev; ++l)
     if (A.lev_off[l + 1] > A.lev_off[l])
-      hipLaunchKernelGGL(k_apply_m2m<NR>, dim3(A.lev_off[l + 1] - A.lev_off[l]), dim3(256), 0, s, A, A.lev_off[l]);
+      hipLaunchKernelGGL(k_apply_m2m<NR>, dim3(A.lev_off[l + 1] - A.lev_off[l]), dim3(512), 0, s, A, A.lev_off[l]);
   hipLaunchKernelGGL(k_apply_far<NR>, dim3((A.n_nodes + 255) / 256, nsplit), dim3(256), 0, s, A,
                      (const double*)A.coef, r0);
   hipLaunchKernelGGL(k_apply_near<NR>, dim3((A.n_nodes + 63) / 64, A.nsplit_near), dim3(64), 0, s, A,

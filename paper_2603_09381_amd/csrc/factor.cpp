@@ -1661,7 +1661,7 @@ void apply_geometry(const pmx_factor* F, const std::vector<double>& hx, const st
   }
   G.kid_off.assign(1, 0);
   G.kid_idx.clear();
-  double m2m_terms = 0;
+  std::vector<double> cterms(nc, 0.0);   // translation terms per cluster
   for (int l = 1; l <= nclev; ++l)
     for (size_t t = 0; t < plan[l].size(); ++t) {
       const CellPlan& cp = plan[l][t];
@@ -1676,11 +1676,11 @@ void apply_geometry(const pmx_factor* F, const std::vector<double>& hx, const st
         if (l == 1) {
           src = plan[0][ch].incl[0];
           ha = ha || always[src];
-          m2m_terms += 2.0 * (2 * (PMX_APPLY_PMAXC + 2) + 1) * (2 * PMX_APPLY_NREC);
+          cterms[c] += 2.0 * (2 * (PMX_APPLY_PMAXC + 2) + 1) * (2 * PMX_APPLY_NREC);
         } else {
           src = m + cid[l - 1][ch];
           ha = ha || holds_always[cid[l - 1][ch]];
-          m2m_terms += 2.0 * (2 * (PMX_APPLY_PMAXC + 2) + 1) * (2 * PMX_APPLY_NRECA);
+          cterms[c] += 2.0 * (2 * (PMX_APPLY_PMAXC + 2) + 1) * (2 * PMX_APPLY_NRECA);
         }
         G.kid_idx.push_back(src);
       }
@@ -1688,6 +1688,17 @@ void apply_geometry(const pmx_factor* F, const std::vector<double>& hx, const st
       holds_always[c] = ha;
       usable[c] = !ha && g[3] <= PMX_APPLY_PMAXC;
     }
+  // levels above the last one with a usable cluster need no translated records (a parent
+  // is never usable when none of its level is: its radius and order only grow)
+  while (G.lev_off.size() > 1) {
+    const int l0 = G.lev_off[G.lev_off.size() - 2], l1 = G.lev_off.back();
+    bool any = false;
+    for (int c = l0; c < l1; ++c) any = any || usable[c];
+    if (any) break;
+    G.lev_off.pop_back();
+  }
+  double m2m_terms = 0;
+  for (int c = 0; c < G.lev_off.back(); ++c) m2m_terms += cterms[c];
   for (int w = 0; w < nw; ++w) {
     const int lo = 64 * w, hi = std::min(64 * w + 64, N);
     double* g = &G.wave[4 * (size_t)w];
