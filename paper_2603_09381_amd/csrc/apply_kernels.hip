@@ -137,8 +137,9 @@ __device__ __noinline__ bes4 bessel01_mid(double z) {
   return bessel01_t(z, tab, ser);
 }
 
-// Expansion coefficients of every inclusion (one wave per inclusion, its nodes 64 at a
-// time).  J_0 .. J_{PMAX+3} of k rho_y by Miller's backward recurrence from order
+// Expansion coefficients of every inclusion (one workgroup of four waves per inclusion, its
+// nodes 64 at a time; every wave runs the recurrences, wave w reduces the orders m = w mod 4,
+// so that four reduction chains proceed at once).  J_0 .. J_{PMAX+3} of k rho_y by Miller's backward recurrence from order
 // PMAX + 27 + k r_j (normalised by J_0 + 2 sum J_2k = 1, a first pass finding the norm),
 // R_{+-m} = J_m e^{-+i m th} (R_{-m} = (-1)^m J_m e^{+i m th}), and the three sums
 // Mq_n = sum R_n q~, U+_n = sum R_n nu u~, U-_n = sum R_n conj(nu) u~ reduced over the wave
@@ -146,13 +147,13 @@ __device__ __noinline__ bes4 bessel01_mid(double z) {
 constexpr int P2M_MO = PMX_APPLY_PMAX + 3;   // orders -P2M_MO .. P2M_MO accumulated
 
 template <int NR>
-__global__ __launch_bounds__(64) void k_apply_p2m(ApplyArgs A, const double* __restrict__ pk, int r0) {
+__global__ __launch_bounds__(256) void k_apply_p2m(ApplyArgs A, const double* __restrict__ pk, int r0) {
   constexpr int S = APPLY_SRC(NR);
   constexpr int NM = 2 * P2M_MO + 1;
   __shared__ double acc[NM][NR][6];           // per order: Mq, U+, U- (re, im)
   const int j = blockIdx.x;
-  const int lane = threadIdx.x;
-  for (int e = lane; e < NM * NR * 6; e += 64) (&acc[0][0][0])[e] = 0.0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < NM * NR * 6; e += 256) (&acc[0][0][0])[e] = 0.0;
   __syncthreads();
   const double cx = A.incl_geo[4 * j], cy = A.incl_geo[4 * j + 1], rj = A.incl_geo[4 * j + 2];
   const double k = A.k;
@@ -209,6 +210,7 @@ __global__ __launch_bounds__(64) void k_apply_p2m(ApplyArgs A, const double* __r
         const double Rpr = Jm * Er, Rpi = Jm * Ei, Rmr = sg * Jm * Er, Rmi = -sg * Jm * Ei;
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) {
+          if ((m & 3) != wave) break;   // another wave reduces this order
           const double vur = nur * ur[rr] - nui * ui[rr], vui = nur * ui[rr] + nui * ur[rr];      // nu u
           const double wur = nur * ur[rr] + nui * ui[rr], wui = nur * ui[rr] - nui * ur[rr];      // conj(nu) u
           double t[12];
@@ -267,7 +269,7 @@ __global__ __launch_bounds__(64) void k_apply_p2m(ApplyArgs A, const double* __r
     }
   };
   zd* rec = A.coef + (int64_t)j * PMX_APPLY_NRECA * NR * 6;
-  for (int e = lane; e < PMX_APPLY_NREC * NR; e += 64) {
+  for (int e = threadIdx.x; e < PMX_APPLY_NREC * NR; e += 256) {
     const int m = e / NR, rr = e % NR;
     double re, im;
     zd* o = rec + ((int64_t)m * NR + rr) * 6;
@@ -590,7 +592,7 @@ static void apply_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipS
   hipLaunchKernelGGL(k_apply_pack<NR>, dim3((A.n_nodes + 255) / 256), dim3(256), 0, s, A, r0, pk);
   KScope ks(PK_APPLY, s);
   const int m = (int)A.n_incl;
-  hipLaunchKernelGGL(k_apply_p2m<NR>, dim3(m), dim3(64), 0, s, A, (const double*)pk, r0);
+  hipLaunchKernelGGL(k_apply_p2m<NR>, dim3(m), dim3(256), 0, s, A, (const double*)pk, r0);
   for (int l = 0; l < A.n_lev; ++l)
     if (A.lev_off[l + 1] > A.lev_off[l])
       hipLaunchKernelGGL(k_apply_m2m<NR>, dim3(A.lev_off[l + 1] - A.lev_off[l]), dim3(512), 0, s, A, A.lev_off[l]);
