@@ -535,6 +535,7 @@ __global__ __launch_bounds__(64) void k_apply_near(ApplyArgs A, const double* __
   for (int q = q0; q < q1; ++q) {
     const int j = A.near_idx[q];
     const bool self = (j == aown);
+    if (__all(self)) continue;   // the whole wave lies on inclusion j: its self block, applied separately
     const int b1 = (int)A.node_off[j + 1];
     for (int b = (int)A.node_off[j]; b < b1; ++b) {
       pmx_ctab tab = (pmx_ctab)pmx_far_table.v, ser = (pmx_ctab)pmx_series_table.v;
