@@ -27,8 +27,9 @@ def _solve(pmx, w, **kw):
 def test_cache_reuse_and_release(pmx, form):
     w = W.sub_grid(W.config2(), 4)
     ref = dense.solve(w)
-    pmx.device_cache(0)
+    pmx.device_cache(0)                  # empties the cache (and sets its limit to 0)
     assert pmx.device_cache() == 0
+    pmx.device_cache(8 << 30)            # the default limit: destroyed factors fill it again
     x1 = _solve(pmx, w, **form)
     held = pmx.device_cache()
     print("cache after one factor:", held, "bytes")
