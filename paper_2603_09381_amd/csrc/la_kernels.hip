@@ -1465,8 +1465,9 @@ bool la_getrs_lds(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max
   const size_t shm4 = (size_t)max_n * 4 * sizeof(cx<R>);
   if (shm4 > 128 * 1024 || max_n <= 0) return false;
   // few matrices: one workgroup per right-hand side, so that more compute units share the
-  // sequential sweeps (each reads the factor once more); many: four right-hand sides each
-  const int nrc = (batch * max_nrhs <= 256 && max_n <= 1792) ? 1 : 4;
+  // sequential sweeps (each reads the factor once more); more: two, then four right-hand
+  // sides each
+  const int nrc = (batch * max_nrhs <= 256 && max_n <= 1792) ? 1 : (batch * max_nrhs <= 1024 && max_n <= 1920) ? 2 : 4;
   const size_t shm = (size_t)max_n * nrc * sizeof(cx<R>);
   const dim3 grid(batch, (max_nrhs + nrc - 1) / nrc);
   KScope ks(PK_GETRS, s);
@@ -1489,6 +1490,15 @@ bool la_getrs_lds(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max
       go(k_getrs_lds<R, 448, 3, BS1, 1>, 512);
     else
       go(k_getrs_lds<R, 448, 4, BS1, 1>, 512);
+  } else if (nrc == 2) {
+    if (max_n <= 256)
+      go(k_getrs_lds<R, 256, 1, BS, 2>, 320);
+    else if (max_n <= 448)
+      go(k_getrs_lds<R, 448, 1, BS, 2>, 512);
+    else if (max_n <= 960)
+      go(k_getrs_lds<R, 960, 1, BS, 2>, 1024);
+    else
+      go(k_getrs_lds<R, 960, 2, BS, 2>, 1024);
   } else if (max_n <= 256) {
     go(k_getrs_lds<R, 256, 1, BS, 4>, 320);
   } else if (max_n <= 448) {
