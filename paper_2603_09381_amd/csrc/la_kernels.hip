@@ -389,66 +389,80 @@ struct TrsmArgs {
 
 // X = T^-1 B for a triangle T (nb <= 32, lower or upper, unit or not) and the columns of
 // B: one thread per column, held in registers with the loops over the triangle unrolled
-// (compile-time register indices); T and the inverses of its diagonal are read from LDS
-// at wave-uniform addresses.
+// (compile-time register indices).  The triangle goes to LDS padded to 32 x 32 with the
+// identity, so the unrolled substitution runs the same 32 steps for every nb with no
+// branch; column i of T is stored as a row of LDS and read at wave-uniform addresses.  The
+// 64 columns of B pass through LDS so that global loads and stores run down columns
+// (32 consecutive rows per half wave) rather than one column per lane.
 template <class R, bool UPPER, bool UNIT, class F>
 __global__ __launch_bounds__(64) void k_trsm_small(F f) {
   typedef cx<R> C;
   TrsmArgs<R> a;
   if (!f(blockIdx.y, a)) return;
+  if (blockIdx.x * 64 >= a.nrhs) return;
   const auto gT = gbl(a.T);
   const auto gB = gbl(a.B);
-  __shared__ C Ts[32][32];
+  __shared__ C Tt[32][32];        // Tt[c][r] = T[r][c]; identity outside nb x nb
   __shared__ C dinv[32];
+  __shared__ C Bs[64][33];        // Bs[column][row]
   const int tid = threadIdx.x;
-  if (blockIdx.x * 64 >= a.nrhs) return;
   const int nb = a.nb;
+  const int rr = tid & 31, ch = tid >> 5;
+  const int rc = min(rr, nb - 1);
+  const int cbase = blockIdx.x * 64;
+  const int nrhs = a.nrhs;
   {
-    // all loads of the triangle issued before the LDS stores (nb^2 <= 16 x 64)
     C tv[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int e = min(tid + 64 * q, nb * nb - 1);
-      tv[q] = gT[e % nb + (int64_t)(e / nb) * a.ldt];
+      const int c = min(ch + 2 * q, nb - 1);
+      tv[q] = gT[rc + (int64_t)c * a.ldt];
+    }
+    C bv[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      const int c = min(cbase + ch + 2 * q, nrhs - 1);
+      bv[q] = gB[rc + (int64_t)c * a.ldb];
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int e = tid + 64 * q;
-      if (e < nb * nb) Ts[e % nb][e / nb] = tv[q];
+      const int c = ch + 2 * q;
+      const bool in = rr < nb && c < nb;
+      const bool keep = UPPER ? (rr < c) : (rr > c);
+      Tt[c][rr] = (in && keep) ? tv[q] : cmk<R>(0, 0);
+      if (!UNIT && rr == c) dinv[c] = in ? zrecip(tv[q]) : cmk<R>(1, 0);
     }
+#pragma unroll
+    for (int q = 0; q < 32; ++q) Bs[ch + 2 * q][rr] = (rr < nb) ? bv[q] : cmk<R>(0, 0);
   }
-  if (!UNIT && tid < nb) dinv[tid] = zrecip(gT[tid + (int64_t)tid * a.ldt]);
-  const int col = blockIdx.x * 64 + tid;
-  const bool active = col < a.nrhs;
-  const int cl = active ? col : a.nrhs - 1;   // idle lanes follow the last column and store nothing
+  __syncthreads();
   C x[32];
 #pragma unroll
-  for (int i = 0; i < 32; ++i) x[i] = (i < nb) ? gB[i + (int64_t)cl * a.ldb] : cmk<R>(0, 0);
-  __syncthreads();
+  for (int i = 0; i < 32; ++i) x[i] = Bs[tid][i];
   if (!UPPER) {
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
-      if (i < nb) {
-        if (!UNIT) x[i] = zmul(x[i], dinv[i]);
+      if (!UNIT) x[i] = zmul(x[i], dinv[i]);
 #pragma unroll
-        for (int r = i + 1; r < 32; ++r)
-          if (r < nb) x[r] = zsub(x[r], zmul(Ts[r][i], x[i]));
-      }
+      for (int r = i + 1; r < 32; ++r) x[r] = zsub(x[r], zmul(Tt[i][r], x[i]));
     }
   } else {
 #pragma unroll
     for (int i = 31; i >= 0; --i) {
-      if (i < nb) {
-        if (!UNIT) x[i] = zmul(x[i], dinv[i]);
+      if (!UNIT) x[i] = zmul(x[i], dinv[i]);
 #pragma unroll
-        for (int r = 0; r < i; ++r) x[r] = zsub(x[r], zmul(Ts[r][i], x[i]));
-      }
+      for (int r = 0; r < i; ++r) x[r] = zsub(x[r], zmul(Tt[i][r], x[i]));
     }
   }
-  if (active) {
 #pragma unroll
-    for (int i = 0; i < 32; ++i)
-      if (i < nb) gB[i + (int64_t)col * a.ldb] = x[i];
+  for (int i = 0; i < 32; ++i) Bs[tid][i] = x[i];
+  __syncthreads();
+  if (rr < nb) {
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      const int c = cbase + ch + 2 * q;
+      if (c < nrhs) gB[rr + (int64_t)c * a.ldb] = Bs[ch + 2 * q][rr];
+    }
   }
 }
 
