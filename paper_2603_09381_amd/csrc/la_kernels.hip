@@ -1940,6 +1940,162 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDescT<R>* qrs, int j0
   }
 }
 
+// FP32 form of the trailing update: the block's rows of A (up to PMX_TS_BR x 64, 64 complex
+// values per thread) stay in registers between the two products, so A is read from memory
+// once instead of twice; the product V W goes through LDS, and the updated slice is written
+// down columns (32 consecutive rows per half wave) instead of one column per lane.
+__global__ __launch_bounds__(256) void k_ts_update_f32(const QrDescT<float>* qrs, int j0, int L) {
+  typedef float R;
+  typedef cx<R> C;
+  typedef typename AccT<R>::type V4;
+  constexpr int NS = PMX_TS_BR / TSU_ROWS;
+  const QrDescT<R> Q = qrs[blockIdx.z];
+  const int kmax = Q.kc;
+  const int jb = min(PMX_QR_NB, kmax - j0);
+  const int nc = Q.c - j0 - jb;
+  if (jb <= 0 || nc <= 0) return;
+  const int c0 = blockIdx.x * 64;
+  if (c0 >= nc) return;
+  TsGeom g;
+  ts_geom(Q.m, j0, jb, g);
+  if (L >= g.nlev) return;
+  const int b = blockIdx.y;
+  if (b >= ts_sel(L, g.nb0, g.nb1, g.nb2, g.nb3)) return;
+  const int nrb = min(PMX_TS_BR, ts_sel(L, g.mr0, g.mr1, g.mr2, g.mr3) - b * PMX_TS_BR);
+  const int64_t wo = ts_sel64(L, g.wo0, g.wo1, g.wo2, g.wo3) + (int64_t)b * PMX_TS_BR * PMX_QR_NB;
+  const auto V = gbl(Q.v) + wo;
+  const auto Tw = gbl(Q.t) + wo;
+  __shared__ C Vs[TSU_ROWS][PMX_QR_NB + 1];
+  __shared__ C As[TSU_ROWS][64 + 1];
+  __shared__ C Ws[PMX_QR_NB][64 + 1];
+  __shared__ int rows[PMX_TS_BR];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const auto A = gbl(Q.a);
+  const int64_t ld = Q.ld;
+  const int ccol0 = j0 + jb + c0;
+  for (int i = tid; i < PMX_TS_BR; i += 256) rows[i] = (i < nrb) ? ts_phys(b * PMX_TS_BR + i, L, jb, j0, g) : -1;
+  const int rr = tid & (TSU_ROWS - 1);
+  const int cc = tid >> 5;
+  constexpr int RB = PMX_QR_NB / 16;
+  V4 accR[RB], accI[RB];
+#pragma unroll
+  for (int q = 0; q < RB; ++q) {
+    accR[q] = V4{0, 0, 0, 0};
+    accI[q] = V4{0, 0, 0, 0};
+  }
+  C ar[NS][8];   // thread's entries of A: slice sl, row rr, columns cc + 8 p
+  __syncthreads();
+  // W = V^H A_b
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int rb = sl * TSU_ROWS;
+    if (rb < nrb) {
+      const int pr = rows[rb + rr];
+      const int prc = pr >= 0 ? pr : j0;
+      C tv[PMX_QR_NB / 8];
+#pragma unroll
+      for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
+        tv[pass] = V[rb + rr + (int64_t)(cc + 8 * pass) * PMX_TS_BR];
+#pragma unroll
+      for (int pass = 0; pass < 8; ++pass)
+        ar[sl][pass] = A[prc + (int64_t)(ccol0 + min(cc + 8 * pass, nc - 1 - c0)) * ld];
+#pragma unroll
+      for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
+        Vs[rr][cc + 8 * pass] = (rb + rr < nrb) ? tv[pass] : cmk<R>(0, 0);
+#pragma unroll
+      for (int pass = 0; pass < 8; ++pass)
+        As[rr][cc + 8 * pass] = (pr >= 0 && c0 + cc + 8 * pass < nc) ? ar[sl][pass] : cmk<R>(0, 0);
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < TSU_ROWS; kk += 4) {
+        const C bb = As[kk + (lane >> 4)][wave * 16 + (lane & 15)];
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+          const C a = Vs[kk + (lane >> 4)][q * 16 + (lane & 15)];
+          accR[q] = mfma16(a.re, bb.re, accR[q]);
+          accR[q] = mfma16(a.im, bb.im, accR[q]);
+          accI[q] = mfma16(a.re, bb.im, accI[q]);
+          accI[q] = mfma16(-a.im, bb.re, accI[q]);
+        }
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RB; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      Ws[q * 16 + mfma_row<R>(lane, r)][wave * 16 + (lane & 15)] = cmk<R>(accR[q][r], accI[q][r]);
+  // W <- T^H W, T upper triangular (row-major in the workspace), staged in the A slice's space
+  C(*Tl)[PMX_QR_NB + 1] = reinterpret_cast<C(*)[PMX_QR_NB + 1]>(&As[0][0]);
+  for (int e = tid; e < PMX_QR_NB * PMX_QR_NB; e += 256) Tl[e / PMX_QR_NB][e % PMX_QR_NB] = Tw[e];
+  __syncthreads();
+  {
+    constexpr int PER = PMX_QR_NB * 64 / 256;
+    const int col = tid & 63, i0 = (tid >> 6) * PER;
+    C w2[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = i0 + u;
+      C acc = cmk<R>(0, 0);
+      for (int j = 0; j <= i; ++j) acc = zadd(acc, zmul(zconj(Tl[j][i]), Ws[j][col]));
+      w2[u] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) Ws[i0 + u][col] = w2[u];
+  }
+  __syncthreads();
+  // A_b -= V W, slice by slice: the 32 x 64 product on MFMA (2 x 4 blocks of 16x16, two per
+  // wave) into LDS, then subtracted from the registers and stored
+  const int rbk = wave & 1;
+  const int cbk0 = (wave >> 1) * 2;
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int rb = sl * TSU_ROWS;
+    if (rb < nrb) {
+      {
+        C tv[PMX_QR_NB / 8];
+#pragma unroll
+        for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
+          tv[pass] = V[rb + rr + (int64_t)(cc + 8 * pass) * PMX_TS_BR];
+#pragma unroll
+        for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
+          Vs[rr][cc + 8 * pass] = (rb + rr < nrb) ? tv[pass] : cmk<R>(0, 0);
+      }
+      __syncthreads();
+      V4 dR[2] = {V4{0, 0, 0, 0}, V4{0, 0, 0, 0}}, dI[2] = {V4{0, 0, 0, 0}, V4{0, 0, 0, 0}};
+#pragma unroll
+      for (int kk = 0; kk < PMX_QR_NB; kk += 4) {
+        const C a = Vs[rbk * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const C bb = Ws[kk + (lane >> 4)][(cbk0 + q) * 16 + (lane & 15)];
+          dR[q] = mfma16(a.re, bb.re, dR[q]);
+          dR[q] = mfma16(-a.im, bb.im, dR[q]);
+          dI[q] = mfma16(a.re, bb.im, dI[q]);
+          dI[q] = mfma16(a.im, bb.re, dI[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          As[rbk * 16 + mfma_row<R>(lane, r)][(cbk0 + q) * 16 + (lane & 15)] = cmk<R>(dR[q][r], dI[q][r]);
+      __syncthreads();
+      const int pr = rows[rb + rr];
+      if (pr >= 0) {
+#pragma unroll
+        for (int pass = 0; pass < 8; ++pass) {
+          const int col = cc + 8 * pass;
+          if (c0 + col < nc) A[pr + (int64_t)(ccol0 + col) * ld] = zsub(ar[sl][pass], As[rr][col]);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 template <class R>
 __global__ void k_copy_r(const QrDescT<R>* qrs) {
   const QrDescT<R> Q = qrs[blockIdx.y];
@@ -1991,7 +2147,11 @@ void la_geqrf_r(const QrDescT<R>* d_qr, int batch, int max_m, int max_c, hipStre
       }
       if (nc > 0) {
         KScope ks(PK_TS_UPDATE, s);
-        hipLaunchKernelGGL(k_ts_update<R>, dim3((nc + 63) / 64, nb, batch), dim3(256), 0, s, d_qr, j0, L);
+        if constexpr (sizeof(R) == 4)
+          hipLaunchKernelGGL(k_ts_update_f32, dim3((nc + 63) / 64, nb, batch), dim3(256), 0, s,
+                             reinterpret_cast<const QrDescT<float>*>(d_qr), j0, L);
+        else
+          hipLaunchKernelGGL(k_ts_update<R>, dim3((nc + 63) / 64, nb, batch), dim3(256), 0, s, d_qr, j0, L);
       }
       if (nb <= 1) break;
       mr = nb * PMX_QR_NB;
