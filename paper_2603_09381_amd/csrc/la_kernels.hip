@@ -2489,14 +2489,17 @@ __global__ __launch_bounds__(256) void k_cpqr_pivot(const CpqrDescT<R>* cps, dou
   }
 }
 
+// columns per workgroup of the update: one per wave, so that a column's dot product, update
+// and norm are the whole chain of a wave
+#define CPU_COLS 4
 template <class R>
 __global__ __launch_bounds__(256) void k_cpqr_update(const CpqrDescT<R>* cps) {
   typedef cx<R> C;
   const CpqrDescT<R> Cd = cps[blockIdx.y];
   if (Cd.c <= 0 || Cd.state[2]) return;
   const int j = Cd.state[3];
-  const int l0 = blockIdx.x * 16;
-  if (l0 + 16 <= j + 1 || l0 >= Cd.c) return;
+  const int l0 = blockIdx.x * CPU_COLS;
+  if (l0 + CPU_COLS <= j + 1 || l0 >= Cd.c) return;
   C* vs = reinterpret_cast<C*>(cp_lds);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int mb = Cd.mb, c = Cd.c;
@@ -2504,10 +2507,8 @@ __global__ __launch_bounds__(256) void k_cpqr_update(const CpqrDescT<R>* cps) {
   for (int r = j + tid; r < mb; r += 256) vs[r - j] = gbl(Cd.v)[r - j];
   __syncthreads();
   const double tau = *Cd.tau;
-  for (int l = l0 + wave; l < min(l0 + 16, c); l += 4) {
-    if (l <= j) continue;
-    cp_apply_column<R>(Cd.b + (int64_t)l * ld, vs, j, mb, tau, Cd.nrm, c, l, lane, Cd.extra);
-  }
+  const int l = l0 + wave;   // one column per wave
+  if (l > j && l < c) cp_apply_column<R>(Cd.b + (int64_t)l * ld, vs, j, mb, tau, Cd.nrm, c, l, lane, Cd.extra);
 }
 
 template <class R>
@@ -2528,7 +2529,7 @@ void la_cpqr(const CpqrDescT<R>* d_cp, int batch, int max_c, double tol, const i
   }
   (void)hipMemsetAsync(d_work, 0, sizeof(int), s);
   hipLaunchKernelGGL(k_cpqr_init<R>, dim3((max_c + 3) / 4, batch), dim3(256), 0, s, d_cp, init);
-  const int ucols = (max_c + 15) / 16;
+  const int ucols = (max_c + CPU_COLS - 1) / CPU_COLS;
   for (int it = 0; it <= max_c; ++it) {
     hipLaunchKernelGGL(k_cpqr_pivot<R>, dim3(batch), dim3(256), 0, s, d_cp, tol, d_kmin, d_work);
     {
