@@ -444,14 +444,14 @@ __global__ __launch_bounds__(64) void k_trsm_small(F f) {
     for (int i = 0; i < 32; ++i) {
       if (!UNIT) x[i] = zmul(x[i], dinv[i]);
 #pragma unroll
-      for (int r = i + 1; r < 32; ++r) x[r] = zsub(x[r], zmul(Tt[i][r], x[i]));
+      for (int r = i + 1; r < 32; ++r) x[r] = zfms(x[r], Tt[i][r], x[i]);
     }
   } else {
 #pragma unroll
     for (int i = 31; i >= 0; --i) {
       if (!UNIT) x[i] = zmul(x[i], dinv[i]);
 #pragma unroll
-      for (int r = 0; r < i; ++r) x[r] = zsub(x[r], zmul(Tt[i][r], x[i]));
+      for (int r = 0; r < i; ++r) x[r] = zfms(x[r], Tt[i][r], x[i]);
     }
   }
 #pragma unroll
@@ -516,7 +516,7 @@ __global__ __launch_bounds__(256) void k_getrf_panel(const LuDescT<R>* lus, int 
         C l = zmul(A[r + c * ld], inv);
         A[r + c * ld] = l;
         for (int cc = c + 1; cc < j0 + jb; ++cc)
-          A[r + cc * ld] = zsub(A[r + cc * ld], zmul(l, A[c + cc * ld]));
+          A[r + cc * ld] = zfms(A[r + cc * ld], l, A[c + cc * ld]);
       }
     }
     __syncthreads();
@@ -608,7 +608,7 @@ __global__ __launch_bounds__(NT) void k_getrf_panel_reg(const LuDescT<R>* lus, i
 #pragma unroll
           for (int cc = 0; cc < PMX_LU_NB; ++cc) {
             if (cc == c) P[q][cc] = l;
-            else if (cc > c) P[q][cc] = zsub(P[q][cc], zmul(l, prow[cc]));
+            else if (cc > c) P[q][cc] = zfms(P[q][cc], l, prow[cc]);
           }
         }
       }
@@ -704,7 +704,7 @@ __global__ __launch_bounds__(NT) void k_getrf_panel_u(const LuDescT<R>* lus, int
           const C l = zmul(P[q][c], inv);
           P[q][c] = l;
 #pragma unroll
-          for (int cc = c + 1; cc < NB; ++cc) P[q][cc] = zsub(P[q][cc], zmul(l, prow[cc]));
+          for (int cc = c + 1; cc < NB; ++cc) P[q][cc] = zfms(P[q][cc], l, prow[cc]);
         }
       }
     }
@@ -733,15 +733,22 @@ __global__ __launch_bounds__(64) void k_laswp_panel(const LuDescT<R>* lus, int j
   const int jb = min(PMX_LU_NB, n - j0);
   if (jb <= 0) return;
   if ((int)(blockIdx.x * 64) >= n - jb) return;
-  const auto ipiv = gbl(L.ipiv);
+  __shared__ int ipl[PMX_LU_NB];   // the panel's pivots, read from memory once, by jb lanes at once
   for (int r = threadIdx.x; r < n; r += 64) cont[r] = r;
+  if ((int)threadIdx.x < jb) ipl[threadIdx.x] = gbl(L.ipiv)[j0 + threadIdx.x];
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int c = j0; c < j0 + jb; ++c) {
-      const int p = ipiv[c];
-      const int t = cont[c];
-      cont[c] = cont[p];
-      cont[p] = t;
+    int pv[PMX_LU_NB];
+#pragma unroll
+    for (int c = 0; c < PMX_LU_NB; ++c) pv[c] = ipl[min(c, jb - 1)];
+#pragma unroll
+    for (int c = 0; c < PMX_LU_NB; ++c) {
+      if (c < jb) {
+        const int p = pv[c];
+        const int t = cont[j0 + c];
+        cont[j0 + c] = cont[p];
+        cont[p] = t;
+      }
     }
   }
   __syncthreads();
@@ -754,14 +761,14 @@ __global__ __launch_bounds__(64) void k_laswp_panel(const LuDescT<R>* lus, int j
   for (int c = 0; c < PMX_LU_NB; ++c) {
     if (c < jb) {
       v[c] = A[cont[j0 + c]];
-      v[PMX_LU_NB + c] = A[cont[ipiv[j0 + c]]];
+      v[PMX_LU_NB + c] = A[cont[ipl[c]]];
     }
   }
 #pragma unroll
   for (int c = 0; c < PMX_LU_NB; ++c) {
     if (c < jb) {
       A[j0 + c] = v[c];
-      A[ipiv[j0 + c]] = v[PMX_LU_NB + c];
+      A[ipl[c]] = v[PMX_LU_NB + c];
     }
   }
 }
@@ -1087,7 +1094,7 @@ __device__ inline void getrs_update(const cx<R>* A, int64_t ld, cx<R>* W, int64_
       for (int k = 0; k < 16; ++k)
         if (h + k < jb) {
 #pragma unroll
-          for (int c = 0; c < NRC; ++c) acc[c] = zsub(acc[c], zmul(l[k], xb[h + k][c]));
+          for (int c = 0; c < NRC; ++c) acc[c] = zfms(acc[c], l[k], xb[h + k][c]);
         }
     }
 #pragma unroll
@@ -1128,7 +1135,7 @@ __global__ __launch_bounds__(GS_NT) void k_getrs_small(const LuDescT<R>* lus, co
 #pragma unroll
         for (int k = 0; k < 32; ++k) {
           const C xk = readlane(x, k);
-          if (lane > k && k < jb) x = zsub(x, zmul(lrow[k], xk));
+          if (lane > k && k < jb) x = zfms(x, lrow[k], xk);
         }
         if (lane < jb) {
           xb[lane][c] = x;
@@ -1155,7 +1162,7 @@ __global__ __launch_bounds__(GS_NT) void k_getrs_small(const LuDescT<R>* lus, co
           if (k < jb) {
             if (lane == k) x = zdiv(x, urow[k]);
             const C xk = readlane(x, k);
-            if (lane < k) x = zsub(x, zmul(urow[k], xk));
+            if (lane < k) x = zfms(x, urow[k], xk);
           }
         }
         if (lane < jb) {
@@ -1209,7 +1216,7 @@ __global__ __launch_bounds__(NT) void k_getrs_lds_wide(const LuDescT<R>* lus, co
 #pragma unroll
       for (int k = 0; k < BS; ++k) {
         const C xk = readlane(x, k);
-        if (lane > k && k < jb) x = zsub(x, zmul(lrow[k], xk));
+        if (lane > k && k < jb) x = zfms(x, lrow[k], xk);
       }
       if (lane < jb) xs[wave * n + j0 + lane] = x;
     }
@@ -1227,7 +1234,7 @@ __global__ __launch_bounds__(NT) void k_getrs_lds_wide(const LuDescT<R>* lus, co
         for (int k = 0; k < HB; ++k)
           if (h + k < jb) {
 #pragma unroll
-            for (int c = 0; c < NRC; ++c) acc[c] = zsub(acc[c], zmul(l[k], xs[c * n + j0 + h + k]));
+            for (int c = 0; c < NRC; ++c) acc[c] = zfms(acc[c], l[k], xs[c * n + j0 + h + k]);
           }
       }
 #pragma unroll
@@ -1254,7 +1261,7 @@ __global__ __launch_bounds__(NT) void k_getrs_lds_wide(const LuDescT<R>* lus, co
         if (k < jb) {
           if (lane == k) x = zmul(x, dinv);
           const C xk = readlane(x, k);
-          if (lane < k) x = zsub(x, zmul(urow[k], xk));
+          if (lane < k) x = zfms(x, urow[k], xk);
         }
       }
       if (lane < jb) xs[wave * n + j0 + lane] = x;
@@ -1273,7 +1280,7 @@ __global__ __launch_bounds__(NT) void k_getrs_lds_wide(const LuDescT<R>* lus, co
         for (int k = 0; k < HB; ++k)
           if (h + k < jb) {
 #pragma unroll
-            for (int c = 0; c < NRC; ++c) acc[c] = zsub(acc[c], zmul(l[k], xs[c * n + j0 + h + k]));
+            for (int c = 0; c < NRC; ++c) acc[c] = zfms(acc[c], l[k], xs[c * n + j0 + h + k]);
           }
       }
 #pragma unroll
@@ -1332,12 +1339,12 @@ __global__ __launch_bounds__(64 + NTT) void k_getrs_lds(const LuDescT<R>* lus, c
   if (jb == BS) {                                                                          \
     _Pragma("unroll") for (int k = 0; k < BS; ++k)                                         \
       _Pragma("unroll") for (int c = 0; c < NRC; ++c)                                      \
-        acc[q][c] = zsub(acc[q][c], zmul(buf[k], xs[c * n + j0 + k]));                    \
+        acc[q][c] = zfms(acc[q][c], buf[k], xs[c * n + j0 + k]);                    \
   } else {                                                                                 \
     _Pragma("unroll") for (int k = 0; k < BS; ++k) {                                       \
       if (k < jb) {                                                                        \
         _Pragma("unroll") for (int c = 0; c < NRC; ++c)                                    \
-          acc[q][c] = zsub(acc[q][c], zmul(buf[k], xs[c * n + j0 + k]));                  \
+          acc[q][c] = zfms(acc[q][c], buf[k], xs[c * n + j0 + k]);                  \
       }                                                                                    \
     }                                                                                      \
   }
@@ -1372,7 +1379,7 @@ __global__ __launch_bounds__(64 + NTT) void k_getrs_lds(const LuDescT<R>* lus, c
 #pragma unroll
           for (int c = 0; c < NRC; ++c) {
             const C xk = readlane(acc[0][c], k);
-            if (lane > k) acc[0][c] = zsub(acc[0][c], zmul(buf[k], xk));
+            if (lane > k) acc[0][c] = zfms(acc[0][c], buf[k], xk);
           }
         }
       }
@@ -1436,7 +1443,7 @@ __global__ __launch_bounds__(64 + NTT) void k_getrs_lds(const LuDescT<R>* lus, c
           for (int c = 0; c < NRC; ++c) {
             if (lane == k) acc[0][c] = zmul(acc[0][c], dinv);
             const C xk = readlane(acc[0][c], k);
-            if (lane < k) acc[0][c] = zsub(acc[0][c], zmul(buf[k], xk));
+            if (lane < k) acc[0][c] = zfms(acc[0][c], buf[k], xk);
           }
         }
       }
@@ -1709,7 +1716,7 @@ __global__ __launch_bounds__(NT) void k_ts_leaf(const QrDescT<R>* qrs, int j0, i
     if (i >= 1 && t < i - 1) {   // T[0:i-1, i-1] = -tau_{i-1} T[0:i-1, 0:i-1] z_{i-1}, one row per thread
       const int c = i - 1;
       C s2 = cmk<R>(0, 0);
-      for (int jj = t; jj < c; ++jj) s2 = zadd(s2, zmul(Ts[t][jj], zs[c & 1][jj]));
+      for (int jj = t; jj < c; ++jj) s2 = zfma(Ts[t][jj], zs[c & 1][jj], s2);
       Ts[t][c] = zscale(s2, -Ts[c][c].re);
     }
     const R tau = (R)taus[bi];
@@ -1746,7 +1753,7 @@ __global__ __launch_bounds__(NT) void k_ts_leaf(const QrDescT<R>* qrs, int j0, i
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
           const int r = lane + 64 * k;
-          if (r >= i) P[m][k] = zsub(P[m][k], zmul(vr[k], w));
+          if (r >= i) P[m][k] = zfms(P[m][k], vr[k], w);
         }
       } else if (q < i && lane == 0) {
         zs[bi][q] = cmk<R>(dr[m], -di[m]);   // V_q^H v = conj(v^H V_q)
@@ -1757,7 +1764,7 @@ __global__ __launch_bounds__(NT) void k_ts_leaf(const QrDescT<R>* qrs, int j0, i
   if (nref >= 1 && t < nref - 1) {
     const int c = nref - 1;
     C s2 = cmk<R>(0, 0);
-    for (int jj = t; jj < c; ++jj) s2 = zadd(s2, zmul(Ts[t][jj], zs[c & 1][jj]));
+    for (int jj = t; jj < c; ++jj) s2 = zfma(Ts[t][jj], zs[c & 1][jj], s2);
     Ts[t][c] = zscale(s2, -Ts[c][c].re);
   }
   __syncthreads();
@@ -1885,7 +1892,7 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDescT<R>* qrs, int j0
     for (int u = 0; u < PER; ++u) {
       const int i = i0 + u;
       C acc = cmk<R>(0, 0);
-      for (int j = 0; j <= i; ++j) acc = zadd(acc, zmul(zconj(Tl[j][i]), Ws[j][col]));
+      for (int j = 0; j <= i; ++j) acc = zfma(zconj(Tl[j][i]), Ws[j][col], acc);
       w2[u] = acc;
     }
     __syncthreads();
@@ -2038,7 +2045,7 @@ __global__ __launch_bounds__(256) void k_ts_update_f32(const QrDescT<float>* qrs
     for (int u = 0; u < PER; ++u) {
       const int i = i0 + u;
       C acc = cmk<R>(0, 0);
-      for (int j = 0; j <= i; ++j) acc = zadd(acc, zmul(zconj(Tl[j][i]), Ws[j][col]));
+      for (int j = 0; j <= i; ++j) acc = zfma(zconj(Tl[j][i]), Ws[j][col], acc);
       w2[u] = acc;
     }
     __syncthreads();
@@ -2214,7 +2221,7 @@ __device__ inline void cp_apply_column(cx<R>* col_, const cx<R>* vs, int j, int 
   double tail = 0;
   C first = cmk<R>(0, 0);
   for (int r = j + lane; r < mb; r += 64) {
-    const C nv = zsub(col[r], zmul(vs[r - j], w));
+    const C nv = zfms(col[r], vs[r - j], w);
     col[r] = nv;
     if (r > j) tail += (double)nv.re * nv.re + (double)nv.im * nv.im;
     else first = nv;

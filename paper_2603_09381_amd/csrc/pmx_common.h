@@ -92,6 +92,10 @@ template <class R>
 __host__ __device__ inline cx<R> zfma(cx<R> a, cx<R> b, cx<R> c) {  // a*b + c
   return cmk<R>(fma(a.re, b.re, fma(-a.im, b.im, c.re)), fma(a.re, b.im, fma(a.im, b.re, c.im)));
 }
+template <class R>
+__host__ __device__ inline cx<R> zfms(cx<R> c, cx<R> a, cx<R> b) {  // c - a*b in four fused operations
+  return cmk<R>(fma(-a.re, b.re, fma(a.im, b.im, c.re)), fma(-a.re, b.im, fma(-a.im, b.re, c.im)));
+}
 
 #define PMX_PI 3.14159265358979323846264338327950288
 #define PMX_EULER 0.57721566490153286060651209008240243
