@@ -383,10 +383,10 @@ __global__ __launch_bounds__(512) void k_apply_m2m(ApplyArgs A, int c0) {
       for (int n = 1 - nrc; n <= nrc; ++n) {
         const zd R = Rt[kc][m - n + M2M_NU];
         const zd a = An[rr][n + PMX_APPLY_NRECA], b = Bn[rr][n + PMX_APPLY_NRECA];
-        ar += R.re * a.re - R.im * a.im;
-        ai += R.re * a.im + R.im * a.re;
-        br += R.re * b.re - R.im * b.im;
-        bi += R.re * b.im + R.im * b.re;
+        ar = fma(-R.im, a.im, fma(R.re, a.re, ar));
+        ai = fma(R.im, a.re, fma(R.re, a.im, ai));
+        br = fma(-R.im, b.im, fma(R.re, b.re, br));
+        bi = fma(R.im, b.re, fma(R.re, b.im, bi));
       }
       accA[m + M2M_MO][rr] = zadd(accA[m + M2M_MO][rr], zmk(ar, ai));
       accB[m + M2M_MO][rr] = zadd(accB[m + M2M_MO][rr], zmk(br, bi));
@@ -475,12 +475,13 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
       for (int rr = 0; rr < NR; ++rr) {
         // A_m, A_-m, B_m+1, B_-m+1, B_m-1, B_-m-1 (wave-uniform addresses: scalar loads)
         const double* c = o + rr * 12;
-        vr[rr] += Opr * c[0] - Opi * c[1] + Omr * c[2] - Omi * c[3];
-        vi[rr] += Opr * c[1] + Opi * c[0] + Omr * c[3] + Omi * c[2];
-        s1r[rr] += Opr * c[4] - Opi * c[5] + Omr * c[6] - Omi * c[7];
-        s1i[rr] += Opr * c[5] + Opi * c[4] + Omr * c[7] + Omi * c[6];
-        s2r[rr] += Opr * c[8] - Opi * c[9] + Omr * c[10] - Omi * c[11];
-        s2i[rr] += Opr * c[9] + Opi * c[8] + Omr * c[11] + Omi * c[10];
+        // four fused operations into each accumulator
+        vr[rr] = fma(-Omi, c[3], fma(Omr, c[2], fma(-Opi, c[1], fma(Opr, c[0], vr[rr]))));
+        vi[rr] = fma(Omi, c[2], fma(Omr, c[3], fma(Opi, c[0], fma(Opr, c[1], vi[rr]))));
+        s1r[rr] = fma(-Omi, c[7], fma(Omr, c[6], fma(-Opi, c[5], fma(Opr, c[4], s1r[rr]))));
+        s1i[rr] = fma(Omi, c[6], fma(Omr, c[7], fma(Opi, c[4], fma(Opr, c[5], s1i[rr]))));
+        s2r[rr] = fma(-Omi, c[11], fma(Omr, c[10], fma(-Opi, c[9], fma(Opr, c[8], s2r[rr]))));
+        s2i[rr] = fma(Omi, c[10], fma(Omr, c[11], fma(Opi, c[8], fma(Opr, c[9], s2i[rr]))));
       }
       // H_{m+1} = (2m/z) H_m - H_{m-1}; e^{i(m+1)th}
       const double f = m * iz2;
