@@ -1503,6 +1503,17 @@ bool la_getrs_lds(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max
   // 32 (FP64), half the sequential steps; the row-owning threads take up to four rows each
   constexpr int BS1 = sizeof(R) == 4 ? 64 : 32;
   if (nrc == 1) {
+    if constexpr (sizeof(R) == 4) {
+      // FP32 above 448 rows: 1024 threads with blocks of 32 rows, so that each row-owning
+      // thread has at most two rows (the first one's loads issued a block ahead)
+      if (max_n > 448) {
+        if (max_n <= 960)
+          go(k_getrs_lds<R, 960, 1, 32, 1>, 1024);
+        else
+          go(k_getrs_lds<R, 960, 2, 32, 1>, 1024);
+        return true;
+      }
+    }
     if (max_n <= 448)
       go(k_getrs_lds<R, 448, 1, BS1, 1>, 512);
     else if (max_n <= 896)
