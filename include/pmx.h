@@ -190,7 +190,8 @@ void pmx_factor_destroy(pmx_factor* f);
 /* Process-wide cache of device blocks left by destroyed factors (default limit 8 GiB).
  * limit >= 0 sets the limit and frees cached blocks beyond it (0 frees them all); limit < 0
  * keeps it.  held (may be NULL) receives the bytes the cache holds afterwards.  Factors
- * that cannot allocate empty the cache and try again.  Thread-safe.  Errors: none. */
+ * that cannot allocate empty the cache and try again.  limit 0 also frees the idle pinned
+ * host chunks that factors stage their uploads in.  Thread-safe.  Errors: none. */
 pmx_status pmx_device_cache(int64_t limit, int64_t* held);
 
 /* Learned skeleton proposals (the leaf IDs of Sec. 3 as training labels).

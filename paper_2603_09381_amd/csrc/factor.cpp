@@ -98,6 +98,40 @@ size_t cache_trim(size_t keep) {
   return freed;
 }
 
+// Pinned host chunks for the staging of uploads, shared by the process.  An asynchronous
+// copy from pageable memory waits for the stream to reach it, which takes away the host's
+// lead over the device at every upload; from pinned memory it is queued like a kernel.  A
+// factor's pool takes chunks as it needs them and gives them back when it is destroyed,
+// after the device has finished every copy that reads them.
+std::mutex g_pin_mu;
+std::vector<std::pair<void*, size_t>> g_pin_free;
+constexpr size_t PIN_CHUNK = (size_t)4 << 20;
+
+std::pair<void*, size_t> pin_take(size_t n) {
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    for (size_t i = 0; i < g_pin_free.size(); ++i)
+      if (g_pin_free[i].second >= n) {
+        const auto c = g_pin_free[i];
+        g_pin_free.erase(g_pin_free.begin() + (ptrdiff_t)i);
+        return c;
+      }
+  }
+  const size_t sz = (n + PIN_CHUNK - 1) / PIN_CHUNK * PIN_CHUNK;
+  void* p = nullptr;
+  if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return {nullptr, 0};
+  }
+  return {p, sz};
+}
+
+void pin_give(std::vector<std::pair<void*, size_t>>& v) {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  for (const auto& c : v) g_pin_free.push_back(c);
+  v.clear();
+}
+
 // Device blocks of one factor.  Temporary buffers of the factorisation are released level
 // by level; giving their blocks back to hipFree would synchronise the device each time,
 // and hipMalloc them anew costs host time.  Blocks come in size classes of one eighth of
@@ -109,8 +143,9 @@ size_t cache_trim(size_t keep) {
 class DevPool {
  public:
   ~DevPool() {
-    if (free_.empty()) return;
+    if (free_.empty() && pin_.empty()) return;
     (void)hipDeviceSynchronize();
+    pin_give(pin_);
     std::lock_guard<std::mutex> lk(g_cache_mu);
     for (auto& kv : free_)
       for (void* p : kv.second) {
@@ -165,10 +200,27 @@ class DevPool {
     for (auto& h : host) retired_.push_back(std::move(h));
     host.clear();
   }
+  // a pinned copy of n bytes of src, kept until the pool is destroyed; nullptr when no
+  // pinned memory can be had
+  const void* stage(const void* src, size_t n) {
+    const size_t n16 = (n + 15) / 16 * 16;
+    if (pin_.empty() || pin_used_ + n16 > pin_.back().second) {
+      const auto c = pin_take(n16);
+      if (!c.first) return nullptr;
+      pin_.push_back(c);
+      pin_used_ = 0;
+    }
+    char* d = (char*)pin_.back().first + pin_used_;
+    std::memcpy(d, src, n);
+    pin_used_ += n16;
+    return d;
+  }
 
  private:
   std::map<size_t, std::vector<void*>> free_;
   std::vector<std::vector<char>> retired_;
+  std::vector<std::pair<void*, size_t>> pin_;
+  size_t pin_used_ = 0;
 };
 
 // Device allocations owned by one object, released together (to a pool when it has one).
@@ -206,8 +258,13 @@ class Arena {
   T* upload(const std::vector<T>& v, hipStream_t s) {
     T* p = alloc<T>(v.size());
     if (!v.empty()) {
-      keep_.emplace_back((const char*)v.data(), (const char*)v.data() + v.size() * sizeof(T));
-      HIPCHK(hipMemcpyAsync(p, keep_.back().data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+      const size_t nb = v.size() * sizeof(T);
+      const void* src = pool_ ? pool_->stage(v.data(), nb) : nullptr;
+      if (!src) {
+        keep_.emplace_back((const char*)v.data(), (const char*)v.data() + nb);
+        src = keep_.back().data();
+      }
+      HIPCHK(hipMemcpyAsync(p, src, nb, hipMemcpyHostToDevice, s));
     }
     return p;
   }
@@ -2567,6 +2624,11 @@ pmx_status pmx_device_cache(int64_t limit, int64_t* held) {
         g_cache_limit = (size_t)limit;
       }
       cache_trim((size_t)limit);
+      if (limit == 0) {   // the idle pinned staging chunks go as well
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        for (const auto& c : g_pin_free) (void)hipHostFree(c.first);
+        g_pin_free.clear();
+      }
     }
     if (held) {
       std::lock_guard<std::mutex> lk(g_cache_mu);
