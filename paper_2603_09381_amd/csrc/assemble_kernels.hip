@@ -211,39 +211,55 @@ __global__ __launch_bounds__(256) void k_diag_pairs(DevGeom g, ExtParams e, cons
   d.scratch[a + (int64_t)b * n] = zadd(zscale(P.S, 1.0 / ep), zscale(M.S, 1.0 / em));
 }
 
-// W = X |x'|^-1 D_t   (X in scratch, W to scratch2)
+// W = X |x'|^-1 D_t   (X in scratch, W to scratch2).  The block's stencil and 1/|x'| go to
+// LDS first; the circulant index advances by one per term, so the loop has no division and
+// no modulo.
 __global__ __launch_bounds__(256) void k_diag_maue1(DevGeom g, const DiagDesc* ds, const double* dt) {
+  extern __shared__ double dm_lds[];   // [n] stencil, [n] 1/|x'|
   const DiagDesc d = ds[blockIdx.y];
   const int n = d.n;
+  if ((int)(blockIdx.x * blockDim.x) >= n * n) return;   // the whole workgroup
+  double* tbs = dm_lds;
+  double* isp = dm_lds + n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    tbs[i] = dt[d.tbl + i];
+    isp[i] = 1.0 / g.speed[d.node0 + i];
+  }
+  __syncthreads();
   const int e_idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (e_idx >= n * n) return;
   const int c = e_idx % n, b = e_idx / n;
-  const double* tb = dt + d.tbl;
   double sr = 0, si = 0;
+  int dd = (b == 0) ? 0 : n - b;   // (k - b) mod n at k = 0
   for (int k = 0; k < n; ++k) {
-    const int dd = ((k - b) % n + n) % n;
-    const double f = tb[dd] / g.speed[d.node0 + k];
+    const double f = tbs[dd] * isp[k];
     const zd x = d.scratch[c + (int64_t)k * n];
     sr = fma(x.re, f, sr);
     si = fma(x.im, f, si);
+    dd = (dd + 1 == n) ? 0 : dd + 1;
   }
   d.scratch2[c + (int64_t)b * n] = zmk(sr, si);
 }
 
-// A22 += |x'|^-1 D_t W
+// A22 += |x'|^-1 D_t W, the stencil in LDS as above
 __global__ __launch_bounds__(256) void k_diag_maue2(DevGeom g, const DiagDesc* ds, const double* dt) {
+  extern __shared__ double dm_lds[];   // [n] stencil
   const DiagDesc d = ds[blockIdx.y];
   const int n = d.n;
+  if ((int)(blockIdx.x * blockDim.x) >= n * n) return;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dm_lds[i] = dt[d.tbl + i];
+  __syncthreads();
   const int e_idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (e_idx >= n * n) return;
   const int a = e_idx % n, b = e_idx / n;
-  const double* tb = dt + d.tbl;
   double sr = 0, si = 0;
+  int dd = a;   // (a - c) mod n at c = 0
   for (int c = 0; c < n; ++c) {
-    const int dd = ((a - c) % n + n) % n;
     const zd w = d.scratch2[c + (int64_t)b * n];
-    sr = fma(tb[dd], w.re, sr);
-    si = fma(tb[dd], w.im, si);
+    const double t = dm_lds[dd];
+    sr = fma(t, w.re, sr);
+    si = fma(t, w.im, si);
+    dd = (dd == 0) ? n - 1 : dd - 1;
   }
   const double f = 1.0 / g.speed[d.node0 + a];
   const int64_t ld = 2 * n;
@@ -257,8 +273,13 @@ void asm_diag(DevGeom g, ExtParams e, const DiagDesc* d, int batch, int max_n, c
   dim3 grid((max_n * max_n + 255) / 256, batch);
   KScope ks(PK_DIAG, s);
   hipLaunchKernelGGL(k_diag_pairs, grid, dim3(256), 0, s, g, e, d, R);
-  hipLaunchKernelGGL(k_diag_maue1, grid, dim3(256), 0, s, g, d, dt);
-  hipLaunchKernelGGL(k_diag_maue2, grid, dim3(256), 0, s, g, d, dt);
+  const size_t shm = 2 * (size_t)max_n * sizeof(double);
+  if (shm > 64 * 1024) {
+    (void)hipFuncSetAttribute((const void*)k_diag_maue1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    (void)hipFuncSetAttribute((const void*)k_diag_maue2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+  }
+  hipLaunchKernelGGL(k_diag_maue1, grid, dim3(256), shm, s, g, d, dt);
+  hipLaunchKernelGGL(k_diag_maue2, grid, dim3(256), shm / 2, s, g, d, dt);
 }
 
 // ---------------------------------------------------------------------------------
