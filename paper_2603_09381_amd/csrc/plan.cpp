@@ -15,8 +15,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <future>
 #include <limits>
 #include <map>
+#include <thread>
 #include <utility>
 
 uint64_t morton_code(uint32_t i, uint32_t j) {
@@ -74,6 +76,9 @@ void node_range(const std::vector<int>& incl, const int64_t* node_off, const dou
     }
 }
 
+void near_cells(const PlanOptions& o, const int64_t* node_off, const double* x, const double* y,
+                std::vector<CellPlan>& cells, int t0, int t1);
+
 void near_and_proxy(const PlanOptions& o, const double* centers, const int64_t* node_off, const double* x,
                     const double* y, std::vector<CellPlan>& cells) {
   const int nc = (int)cells.size();
@@ -91,11 +96,24 @@ void near_and_proxy(const PlanOptions& o, const double* centers, const int64_t* 
     c.rc = hi;
   }
   if (nc == 1) return;
+  // each cell's near list and proxy depend only on the centres and radii above: the cells
+  // are split into contiguous ranges handled by up to four threads (the same plan)
+  const int nt = nc >= 64 ? std::min(4, std::max(1, (int)std::thread::hardware_concurrency() / 2)) : 1;
+  auto range = [&](int t0, int t1) { near_cells(o, node_off, x, y, cells, t0, t1); };
+  std::vector<std::future<void>> part;
+  for (int k = 1; k < nt; ++k) part.push_back(std::async(std::launch::async, range, nc * k / nt, nc * (k + 1) / nt));
+  range(0, nc / nt);
+  for (auto& f : part) f.get();
+}
+
+void near_cells(const PlanOptions& o, const int64_t* node_off, const double* x, const double* y,
+                std::vector<CellPlan>& cells, int t0, int t1) {
+  const int nc = (int)cells.size();
   const double inf = std::numeric_limits<double>::infinity();
   std::vector<double> lb(nc), ub(nc), dmin(nc);
   std::vector<char> isnear(nc);
   std::vector<std::pair<double, int>> cand;
-  for (int t = 0; t < nc; ++t) {
+  for (int t = t0; t < t1; ++t) {
     CellPlan& c = cells[t];
     // bounds |c_t - c_s| -+ r_s on the distance from the centre of t to the nodes of s
     // (widened by a relative 1e-9 against rounding); exact distances are computed only
