@@ -111,6 +111,11 @@ void asm_zero(cx<R>* p, int64_t n, hipStream_t s);
 // dst[i] = src[i] converted to the destination's real type
 template <class RS, class RD>
 void asm_convert(const cx<RS>* src, cx<RD>* dst, int64_t n, hipStream_t s);
+// blocks of FP64 complex entries, block t from src + soff[t] to dst + doff[t] (len[t]
+// entries), rounded to RD; the offset and length arrays in device memory
+template <class RD>
+void asm_convert_blocks(const zd* src, cx<RD>* dst, const int64_t* d_soff, const int64_t* d_doff,
+                        const int64_t* d_len, int nblocks, int64_t max_len, hipStream_t s);
 // far field: out[r * ndir + t] for densities dens (ld = 2 * n_nodes, per inclusion [q; u])
 void asm_far_field(DevGeom g, ExtParams e, const int* owner, const int64_t* node_off,
                    const zd* dens, int nrhs, const double* dirs, int ndir, zd* out, hipStream_t s);

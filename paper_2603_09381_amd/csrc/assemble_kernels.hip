@@ -11,6 +11,8 @@
 // Maue's identity N = |x'|^-1 D_t S |x'|^-1 D_t + k^2 S_nn (trigonometric
 // differentiation D_t), then combined as
 //   [[-(e+ S+ + e- S-), D+ + D-], [-(D*+ + D*-), N+/e+ + N-/e-]].
+#include <algorithm>
+
 #include "assemble.h"
 #include "bessel.h"
 #include "hankel_fast.h"
@@ -436,6 +438,24 @@ void asm_convert(const cx<RS>* src, cx<RD>* dst, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL((k_convert<RS, RD>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
 }
 
+// block t of dst = block of src at soff[t], rounded to RD (len[t] entries each)
+template <class RD>
+__global__ void k_convert_blocks(const zd* src, cx<RD>* dst, const int64_t* soff, const int64_t* doff,
+                                 const int64_t* len) {
+  const int t = blockIdx.y;
+  const int64_t n = len[t], so = soff[t], dof = doff[t];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[dof + i] = cmk<RD>((RD)src[so + i].re, (RD)src[so + i].im);
+}
+
+template <class RD>
+void asm_convert_blocks(const zd* src, cx<RD>* dst, const int64_t* d_soff, const int64_t* d_doff,
+                        const int64_t* d_len, int nblocks, int64_t max_len, hipStream_t s) {
+  if (nblocks <= 0 || max_len <= 0) return;
+  const unsigned gx = (unsigned)std::min<int64_t>(64, (max_len + 255) / 256);
+  hipLaunchKernelGGL(k_convert_blocks<RD>, dim3(gx, nblocks), dim3(256), 0, s, src, dst, d_soff, d_doff, d_len);
+}
+
 __global__ void k_axpy(zd* y, const zd* x, zd a, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = zfma(a, x[i], y[i]);
@@ -559,6 +579,10 @@ template void asm_gather<double, double>(const zd*, const GatherDescT<double>*, 
 template void asm_gather<float, float>(const zf*, const GatherDescT<float>*, int, int, int, hipStream_t, int);
 template void asm_gather<double, float>(const zd*, const GatherDescT<float>*, int, int, int, hipStream_t, int);
 template void asm_gather<float, double>(const zf*, const GatherDescT<double>*, int, int, int, hipStream_t, int);
+template void asm_convert_blocks<float>(const zd*, zf*, const int64_t*, const int64_t*, const int64_t*, int, int64_t,
+                                        hipStream_t);
+template void asm_convert_blocks<double>(const zd*, zd*, const int64_t*, const int64_t*, const int64_t*, int, int64_t,
+                                         hipStream_t);
 template void asm_convert<double, float>(const zd*, zf*, int64_t, hipStream_t);
 template void asm_convert<float, double>(const zf*, zd*, int64_t, hipStream_t);
 template void asm_convert<double, double>(const zd*, zd*, int64_t, hipStream_t);

@@ -400,8 +400,8 @@ struct pmx_factor {
   std::vector<std::vector<CellPlan>> plan;
   Tier<double> t64;   // precision 0
   Tier<float> t32;    // precision 1
-  // precision 1: the FP64 self blocks of the leaves (leaf order, offsets selfOff) for the
-  // refinement residual
+  // refined forms: the FP64 self blocks of the inclusions (inclusion order, offsets
+  // selfOff) for the refinement residual
   zd* Dself = nullptr;
   std::vector<int> selfIncl;
   std::vector<int64_t> selfOff;
@@ -586,6 +586,28 @@ void assemble_diag(pmx_factor* F, Arena& tmp, const std::vector<int>& incl, zd* 
   }
   DiagDesc* d_dd = tmp.upload(dd, s);
   asm_diag(F->geom(), F->ext(), d_dd, (int)incl.size(), maxn, T.R, T.dt, s);
+}
+
+// FP64 self blocks of every inclusion in inclusion order (the refined forms keep them for
+// the residual); they need the geometry but not the plan
+void self_blocks_by_inclusion(pmx_factor* F, hipStream_t s) {
+  const double t0 = now_ms();
+  std::vector<int> incl(F->m);
+  std::vector<int64_t> off(F->m);
+  int64_t td = 0;
+  for (int j = 0; j < F->m; ++j) {
+    incl[j] = j;
+    off[j] = td;
+    const int64_t n = F->node_off[j + 1] - F->node_off[j];
+    td += 4 * n * n;
+  }
+  F->Dself = F->arena.alloc<zd>(td);
+  F->selfIncl = incl;
+  F->selfOff = off;
+  Arena tmp(&F->pool);
+  assemble_diag(F, tmp, incl, F->Dself, off, s);
+  HIPCHK(hipGetLastError());
+  F->info.t_phase_ms[0] += now_ms() - t0;
 }
 
 struct ProxyTable {
@@ -1270,12 +1292,18 @@ void factor_all(pmx_factor* F, hipStream_t s) {
     if (F->opts.precision == 0) {
       assemble_diag(F, tmp, incl, (zd*)L0.D, L0.offD, s);
     } else {
-      // FP64 self blocks kept for the refinement residual; copies (rounded for FP32) factored
-      F->Dself = F->arena.alloc<zd>(td);
-      F->selfOff = L0.offD;
-      F->selfIncl = incl;
-      assemble_diag(F, tmp, incl, F->Dself, L0.offD, s);
-      asm_convert(F->Dself, L0.D, td, s);
+      // the FP64 self blocks (inclusion order, kept for the refinement residual) rounded
+      // block by block into leaf order, where they are factored
+      std::vector<int64_t> so(incl.size()), len(incl.size());
+      int64_t ml = 0;
+      for (size_t t = 0; t < incl.size(); ++t) {
+        so[t] = F->selfOff[incl[t]];
+        const int64_t n = F->node_off[incl[t] + 1] - F->node_off[incl[t]];
+        len[t] = 4 * n * n;
+        ml = std::max(ml, len[t]);
+      }
+      asm_convert_blocks(F->Dself, L0.D, tmp.upload(so, s), tmp.upload(L0.offD, s), tmp.upload(len, s),
+                         (int)incl.size(), ml, s);
     }
     // no synchronisation: the temporaries go back to the pool, whose blocks only later
     // work of this stream reuses, and the host goes on building the next descriptors
@@ -2500,14 +2528,27 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
       }
     } reset_timer{g_tune};
     g_tune = F->tune.get();
-    make_plan(geom, o, F->plan);
-    F->info.t_phase_ms[4] = now_ms() - t0;
+    // the plan is made on a host thread while the geometry and, in the refined forms, the
+    // FP64 self blocks (which need no plan) go to the device
+    double plan_ms = 0;
+    pmx_factor* Fp = F.get();
+    auto plan_job = std::async(std::launch::async, [geom, &o, Fp, &plan_ms] {
+      const double tp = now_ms();
+      make_plan(geom, o, Fp->plan);
+      plan_ms = now_ms() - tp;
+    });
     HIPCHK(hipStreamCreateWithFlags(&F->gs, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&F->ev_in, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&F->ev_out, hipEventDisableTiming));
     F->ss.reset(new SolveState(&F->pool));
-    if (o.learned) leaf_predictions(F.get(), geom, o.model_path, s);
+    if (o.learned) {
+      plan_job.get();
+      leaf_predictions(F.get(), geom, o.model_path, s);
+    }
     upload_geometry(F.get(), geom, s);
+    if (o.precision != 0) self_blocks_by_inclusion(F.get(), s);
+    if (plan_job.valid()) plan_job.get();
+    F->info.t_phase_ms[4] = plan_ms;
     if (o.precision != 0) {
       // host copies of the coordinates (the caller's arrays may go away after this call)
       const int64_t N = geom->node_off[geom->m];
