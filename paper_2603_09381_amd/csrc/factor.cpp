@@ -2537,16 +2537,21 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
       make_plan(geom, o, Fp->plan);
       plan_ms = now_ms() - tp;
     });
-    HIPCHK(hipStreamCreateWithFlags(&F->gs, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&F->ev_in, hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&F->ev_out, hipEventDisableTiming));
-    F->ss.reset(new SolveState(&F->pool));
-    if (o.learned) {
-      plan_job.get();
-      leaf_predictions(F.get(), geom, o.model_path, s);
+    try {
+      HIPCHK(hipStreamCreateWithFlags(&F->gs, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&F->ev_in, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&F->ev_out, hipEventDisableTiming));
+      F->ss.reset(new SolveState(&F->pool));
+      if (o.learned) {
+        plan_job.get();
+        leaf_predictions(F.get(), geom, o.model_path, s);
+      }
+      upload_geometry(F.get(), geom, s);
+      if (o.precision != 0) self_blocks_by_inclusion(F.get(), s);
+    } catch (...) {
+      if (plan_job.valid()) plan_job.get();   // an unsupported geometry is reported first
+      throw;
     }
-    upload_geometry(F.get(), geom, s);
-    if (o.precision != 0) self_blocks_by_inclusion(F.get(), s);
     if (plan_job.valid()) plan_job.get();
     F->info.t_phase_ms[4] = plan_ms;
     if (o.precision != 0) {
