@@ -675,6 +675,15 @@ void id_stage(pmx_factor* F, const LevelData<R>& L, const std::vector<CellPlan>&
   const double tol = F->opts.id_tol;
   std::vector<int> nearrows, nearcols;
   std::vector<int64_t> nro(nc), mid(nc);
+  {
+    size_t tot = 0;
+    for (int t = 0; t < nc; ++t) {
+      for (int sgm : cells[t].near) tot += (size_t)(L.s0[sgm] + L.s1[sgm]);
+      tot += 2 * (size_t)cells[t].P;
+    }
+    nearrows.reserve(tot);
+    nearcols.reserve(tot);
+  }
   for (int t = 0; t < nc; ++t) {
     nro[t] = (int64_t)nearrows.size();
     for (int sgm : cells[t].near) {
