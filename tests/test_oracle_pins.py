@@ -299,3 +299,78 @@ def test_mlp_without_hidden_layers_is_logistic_regression():
     assert np.allclose(g, gref, rtol=0, atol=1e-14)
     Lref = np.mean(-Y[:, 0] * np.log(s[:, 0]) - (1 - Y[:, 0]) * np.log(1 - s[:, 0]))
     assert abs(L - Lref) < 1e-12
+
+
+def test_residual_rows_equal_rows_of_the_assembled_system():
+    """residual_rows builds each row of f - A phi on its own (Kress self block of the row's
+    inclusion, trapezoid sums over every other inclusion).  The assembled system is pinned
+    by the Mie, multipole and Calderon tests; the row evaluation must reproduce its rows for
+    any phi, on q-rows and u-rows of the first, an inner and the last inclusion (Sec. 2.2,
+    block system)."""
+    w = W.star_grid(3, n=32, k_ext=10.0, k_int=15.0, seed=2, angles=[0.0, 1.1])
+    g = dense.Geometry(w)
+    A = dense.assemble(g)
+    f = dense.rhs(g, w.angles)
+    rng = np.random.default_rng(11)
+    phi = rng.standard_normal((A.shape[0], 2)) + 1j * rng.standard_normal((A.shape[0], 2))
+    last = A.shape[0] - 1
+    rows = np.array([0, 31, 32, 63, 64 * 4 + 7, 64 * 4 + 40, last - 32, last])
+    got = dense.residual_rows(w, phi, rows)
+    ref = (f - A @ phi)[rows]
+    scale = (np.abs(A) @ np.abs(phi) + np.abs(f))[rows]
+    assert np.all(np.abs(got - ref) <= 1e-14 * scale * 10), np.max(np.abs(got - ref) / scale)
+    # a row of the wrong block type or inclusion is far off: the check has teeth
+    wrong = (f - A @ phi)[(rows + 1) % A.shape[0]]
+    assert np.min(np.abs(wrong - got) / scale) > 1e-6
+    # at the dense solution the sampled residual vanishes to rounding
+    x = dense.solve(w)
+    r = dense.residual_rows(w, x, rows)
+    assert np.linalg.norm(r) <= 1e-13 * np.linalg.norm(f[rows])
+
+
+def test_residual_rows_vanish_at_the_multipole_solution():
+    """The closed-form (multipole) boundary data of the 2x2 disks leaves a residual at
+    discretisation level in every sampled row (Sec. 4.2 measures errors against such a
+    reference); a density off by 1e-6 does not."""
+    w = W.disk_grid(2, n=128, angles=[0.0])
+    g = dense.Geometry(w)
+    ep, em = dense.materials(w)
+    bnd, _, _ = analytic.multi_disk(w.centers, 0.4, w.k_ext, w.k_int[0], ep, em[0])
+    th = 2 * np.pi * np.arange(128) / 128
+    phi = np.concatenate([np.concatenate(bnd(j, th)) for j in range(4)])[:, None]
+    rows = np.arange(0, 1024, 37)
+    f = dense.rhs(g, w.angles)[rows]
+    r = dense.residual_rows(w, phi, rows)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(f)
+    bad = phi * (1 + 1e-6)
+    assert np.linalg.norm(dense.residual_rows(w, bad, rows)) > 1e-8 * np.linalg.norm(f)
+
+
+def test_energy_defect_closed_form_for_a_centred_point_source():
+    """u = (i/4) H0(k|x - z|) and q = du/dn on a circle of radius R about z: the radiated
+    flux gives Im int conj(u) du/dn ds = 1/4 (Green's identity out to infinity), and
+    |u|, |du/dn| are constant, so the defect is exactly 2 / (pi k R |H0(kR)| |H1(kR)|)."""
+    k, R = 7.0, 0.4
+    w = W.disk_grid(1, n=64, radius=R, k_ext=k, k_int=k)
+    g = dense.Geometry(w)
+    v, dv = _point_source(w.x, w.y, g.nx, g.ny, (0.0, 0.0), k)
+    ed = dense.energy_defect(g, np.concatenate([dv, v])[:, None])
+    ref = 2.0 / (np.pi * k * R * abs(sp.hankel1(0, k * R)) * abs(sp.hankel1(1, k * R)))
+    assert abs(ed[0, 0] - ref) <= 1e-13 * ref
+    assert ref > 1e-3
+
+
+def test_energy_defect_sees_a_source_inside_a_star():
+    """For a point source inside a star the weighted sum Im sum_b w_b conj(u_b) q_b is the
+    radiated flux 1/4 (trapezoid rule, spectrally accurate); for one outside it is 0."""
+    k = 10.0
+    w = W.star_grid(1, n=128, k_ext=k, k_int=k)
+    g = dense.Geometry(w)
+    for z, flux in (((0.05, -0.03), 0.25), ((0.9, 0.7), 0.0)):
+        v, dv = _point_source(w.x, w.y, g.nx, g.ny, z, k)
+        ed = dense.energy_defect(g, np.concatenate([dv, v])[:, None])[0, 0]
+        norm = np.sum(g.wt * np.abs(v) * np.abs(dv))
+        assert abs(ed * norm - flux) <= 1e-12 * norm, (z, ed * norm)
+    # a lossless transmission solution has none (Sec. 2.1 with real k+, k-)
+    x = dense.solve(W.star_grid(1, n=128, k_ext=k, k_int=15.0, angles=[0.3]))
+    assert np.max(np.abs(dense.energy_defect(g, x))) < 1e-11
