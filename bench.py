@@ -1,24 +1,28 @@
 """Benchmark: factor + solve of the proxy fast direct solver on one MI355X, tuned vs plain.
 
-Workload (default): 16x16 grid of rotated stars r(t) = 0.3(1 + 0.2 cos 5t), unit spacing,
-128 nodes each (N = 65536 unknowns), k+ = 10, k- = 15, four plane waves at angles
-2 pi j / 4.  One step = factorisation + solve of the four right-hand sides (boundary samples
-are host inputs; densities stay in HBM).
+Workload (default): 64x64 grid of rotated stars r(t) = 0.3(1 + 0.2 cos 5t), unit spacing,
+128 nodes each (N = 1,048,576 unknowns), k+ = 8, k- = 12, sixteen plane waves at angles
+2 pi j / 16.  One step = factorisation + solve of the sixteen right-hand sides (boundary
+samples are host inputs; the densities stay in HBM).
 
-Forms, both held to a relative residual of 1e-10 / field error of 1e-8:
+Forms, both held to a field error of 1e-8:
   plain: FP64 throughout, ID tolerance 1e-10;
   tuned: the factor in complex FP32 (FP32 MFMA QR, LU and Schur products, FP64 pivots) at
-         ID tolerance 1e-3, refined against the FP64 operator (near pairs directly, far
-         inclusions through multipole expansions) to a relative residual of 1e-10; solves
-         replay captured HIP graphs.
-Before the timed steps each form gets a launch-parameter table from the library's autotuner
-(pmx_autotune on this workload; --no-autotune keeps the built-in rules, --tune-dir keeps
-the tables and reuses them in later runs).
-`value` is the tuned form's unknowns per second over the timed steps.  The roofline object
-covers the tuned form's dominant kernel (found in the warm-up steps, which time every
-kernel; in the timed steps HIP events bracket that kernel's launches only), with the
-algorithmic work counted by the library; kernel_time_share comes from the warm-up steps.
-cpu_baseline times the CPU oracle (dense solve) on a sample of the same workload.
+         ID tolerance 1e-3, refined against the FP64 operator (self blocks, near pairs
+         directly, far sources through multipole expansions) to a relative residual of
+         1e-10; solves and operator applies replay captured HIP graphs.
+Accuracy: both forms against a reference solve (plain FP64 at ID tolerance 1e-12): relative
+2-norm error over all 2N x 16 entries (Sec. 4.2); the oracle's residual f - A x on sampled
+rows (each row evaluated in FP64 on the CPU); the energy defect of the lossless media.
+Launch parameters come from the library's autotuner: the tables committed under
+paper_2603_09381_amd/tables/ for this workload (--autotune tunes afresh before the timed
+steps).
+Timing: `value` is the tuned form's unknowns per second over the timed steps, which replay
+the solve and apply graphs; HIP events on the factor's stream bracket only the launches of
+the dominant kernel (the roofline object; for the tuned form the operator apply, a graph of
+its own).  kernel_time_share comes from the warm-up steps, which time every kernel (and
+so launch the solves kernel by kernel).  The plain form times fewer steps (--plain-steps).
+cpu_baseline times the CPU oracle (dense solve) on a corner of the same grid.
 """
 from __future__ import annotations
 
@@ -35,69 +39,125 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "factor+solve seconds & unknowns/s at 1e-8 rel error: tuned vs plain, 1 GPU"
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+TARGET_ERROR = 1e-8
 PEAK_TFS = {("mfma", 8): 78.6, ("mfma", 4): 157.3, ("alu", 8): 78.6, ("alu", 4): 157.3}
-# kernels whose algorithmic work the library counts: bound kind and element size (bytes of
-# the real type: 8 in the FP64 form, the factor's type otherwise; the apply is always FP64)
+# kernels whose algorithmic work the library counts: bound kind
 COUNTED = {"k_ts_update": "mfma", "k_ts_leaf": "alu", "k_getrf_panel": "alu", "k_apply_off": "alu"}
 TRAFFIC_DIR = os.path.join(ROOT, "profiles")
+TABLE_DIR = os.path.join(ROOT, "paper_2603_09381_amd", "tables")
 KERNEL_SOURCES = {"k_ts_update": ("la_kernels.hip", "la.h"), "k_ts_leaf": ("la_kernels.hip", "la.h"),
                   "k_getrf_panel": ("la_kernels.hip", "la.h"),
-                  "k_apply_off": ("apply_kernels.hip", "assemble.h", "hankel_fast.h", "bessel.h")}
+                  "k_apply_off": ("apply_kernels.hip", "assemble.h", "hankel_fast.h", "bessel.h",
+                                  "la_kernels.hip")}
 FORMS = {"plain": dict(precision=0, id_tol=1e-10),
          "tuned": dict(precision=1, id_tol=1e-3, ir_tol=1e-10, solve_graph=1)}
+REFERENCE = dict(precision=0, id_tol=1e-12)
 
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--grid", type=int, default=16, help="stars per side (16 = the 65536-unknown workload)")
+    p.add_argument("--plain-steps", type=int, default=2, help="timed steps of the plain form (at most --steps)")
+    p.add_argument("--grid", type=int, default=64, help="stars per side (64 = the 1,048,576-unknown workload)")
+    p.add_argument("--rows", type=int, default=8, help="rows of the oracle's sampled residual per form")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--no-check", action="store_true")
+    p.add_argument("--no-check", action="store_true", help="no reference solve and no oracle residual")
     p.add_argument("--no-plain", action="store_true", help="time the tuned form only")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a 256 MiB device copy first (reference kernel for HBM counters)")
-    p.add_argument("--no-timing", action="store_true", help="no HIP events around kernels")
+    p.add_argument("--no-timing", action="store_true", help="no HIP events at all (no roofline, no shares)")
+    p.add_argument("--autotune", action="store_true",
+                   help="tune the launch tables before the timed steps instead of loading the committed ones")
     p.add_argument("--tune-dir", default=None,
-                   help="keep the launch tables in this folder; a form whose table is already there "
-                        "loads it instead of tuning (a profiled run then uses the bench run's choices)")
-    p.add_argument("--no-autotune", action="store_true",
-                   help="built-in launch rules instead of a launch-parameter table tuned before the timed steps")
+                   help="with --autotune: write the tables here (default: a temporary folder)")
     return p.parse_args()
 
 
-def cpu_baseline(w_full):
-    """The oracle's dense solve (assembly, LU, solve) of the 6x6 corner of the same grid."""
-    from oracle import dense
-    from paper_2603_09381_amd import workloads as W
-    sub = W.sub_grid(w_full, 6)
-    t0 = time.perf_counter()
-    dense.solve(sub)
-    t = time.perf_counter() - t0
+def workload_tag(grid):
+    return f"stars{grid}"
+
+
+def _cores():
     try:
-        cores = len(os.sched_getaffinity(0))
+        return len(os.sched_getaffinity(0))
     except Exception:
-        cores = os.cpu_count()
-    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    return {"value": sub.n_unknowns / t, "unit": "unknowns/s", "cores": min(cores, threads),
-            "kind": "oracle",
-            "sample": f"dense PMCHWT-Omit Nystrom solve (Kress self blocks, LAPACK partial-pivot LU) of the "
-                      f"6x6 corner of the same star grid, N={sub.n_unknowns}, {len(sub.angles)} right-hand "
-                      f"sides, {t:.2f} s"}
+        return os.cpu_count()
 
 
-def accuracy(w, x):
-    """Relative residual on sampled rows (oracle row evaluation) and the energy defect."""
+def _dense_once(sub):
+    """The oracle's dense solve of a workload, assembly timed apart from LU + solve."""
+    import scipy.linalg as la
     from oracle import dense
-    rng = np.random.default_rng(7)
-    rows = np.sort(rng.choice(w.n_unknowns, size=48, replace=False))
+    t0 = time.perf_counter()
+    g = dense.Geometry(sub)
+    A = dense.assemble(g)
+    f = dense.rhs(g, sub.angles)
+    t1 = time.perf_counter()
+    lu = la.lu_factor(A, overwrite_a=True, check_finite=False)
+    la.lu_solve(lu, f, check_finite=False)
+    t2 = time.perf_counter()
+    return t1 - t0, t2 - t1
+
+
+def cpu_baseline(w_full, n_full):
+    """The oracle's dense solve (assembly, LAPACK partial-pivot LU, solve) of the 4x4 corner
+    of the same grid: median of 3 runs on every host core, one run on one thread, and the
+    dense method's time at the full size extrapolated from the medians (assembly ~N^2,
+    LU ~N^3)."""
+    from threadpoolctl import threadpool_limits
+    from paper_2603_09381_amd import workloads as W
+    sub = W.sub_grid(w_full, 4)
+    n0 = sub.n_unknowns
+    runs = [_dense_once(sub) for _ in range(3)]
+    tot = sorted(a + b for a, b in runs)
+    med = tot[1]
+    asm_med = sorted(a for a, _ in runs)[1]
+    lu_med = sorted(b for _, b in runs)[1]
+    with threadpool_limits(1):
+        a1, b1 = _dense_once(sub)
+    cores = _cores()
+    threads = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+    ratio = n_full / n0
+    extrap = asm_med * ratio ** 2 + lu_med * ratio ** 3
+    return {"value": n0 / med, "unit": "unknowns/s", "cores": threads, "kind": "oracle",
+            "sample": f"dense PMCHWT-Omit Nystrom solve (Kress self blocks, LAPACK partial-pivot LU) of the "
+                      f"4x4 corner of the same star grid, N={n0}, {len(sub.angles)} right-hand sides; "
+                      f"median of 3 runs on {threads} threads",
+            "seconds_median": med, "assembly_s_median": asm_med, "lu_solve_s_median": lu_med,
+            "single_thread": {"seconds": a1 + b1, "assembly_s": a1, "lu_solve_s": b1,
+                              "value": n0 / (a1 + b1)},
+            "extrapolated_full_size": {"label": "extrapolation, not a measurement: assembly x (N/N0)^2 + "
+                                                "LU+solve x (N/N0)^3 from the medians",
+                                       "n_unknowns": n_full, "seconds": extrap, "value": n_full / extrap},
+            "host": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return None
+
+
+def sampled_residual(w, x, nrows, seed=7):
+    """Relative residual of the oracle's FP64 rows f - A x on sampled rows (every right-hand
+    side)."""
+    from oracle import dense
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(w.n_unknowns, size=nrows, replace=False))
     r = dense.residual_rows(w, x, rows)
     f = dense.rhs(dense.Geometry(w), w.angles)[rows]
-    rel = float(np.linalg.norm(r) / np.linalg.norm(f))
-    ed = float(np.max(np.abs(dense.energy_defect(dense.Geometry(w), x))))
-    return rel, ed
+    return float(np.linalg.norm(r) / np.linalg.norm(f)), rows
+
+
+def energy(w, x):
+    from oracle import dense
+    return float(np.max(np.abs(dense.energy_defect(dense.Geometry(w), x))))
 
 
 def kernel_source_hash(kname):
@@ -107,19 +167,28 @@ def kernel_source_hash(kname):
     return h.hexdigest()[:16]
 
 
-def traffic_file(kname, workload_tag):
-    return os.path.join(TRAFFIC_DIR, f"traffic_{kname}_{workload_tag}.json")
+def traffic_file(kname, tag):
+    return os.path.join(TRAFFIC_DIR, f"traffic_{kname}_{tag}.json")
 
 
-def traffic_per_launch(kname, workload_tag):
-    """HBM bytes per launch from the committed PMC summary, if taken on this kernel source."""
+def traffic_per_launch(kname, tag, table_hash):
+    """HBM bytes per launch from the committed PMC summary, if it was taken on this kernel
+    source and this launch table."""
     try:
-        d = json.load(open(traffic_file(kname, workload_tag)))
+        d = json.load(open(traffic_file(kname, tag)))
     except Exception:
         return None
     if d.get("kernel") != kname or d.get("source_hash") != kernel_source_hash(kname):
         return None
+    if d.get("table_hash") != table_hash:
+        return None
     return d.get("bytes_per_launch")
+
+
+def table_hash(path):
+    if not path or not os.path.exists(path):
+        return None
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
 def _sums(info_list):
@@ -147,7 +216,7 @@ def dominant_kernel(info_list, names):
     return k, top, share
 
 
-def roofline(info_list, k, top, names, real_bytes, workload_tag):
+def roofline(info_list, k, top, names, real_bytes, tag, thash):
     """Kernel k over the timed steps: algorithmic work counted by the library divided by
     the device time of its launches (HIP events on its launch stream)."""
     if k is None:
@@ -161,7 +230,7 @@ def roofline(info_list, k, top, names, real_bytes, workload_tag):
     rb = 8 if name == "k_apply_off" else real_bytes
     peak = PEAK_TFS[(kind, rb)]
     roof = {"bound": kind, "achieved": fl[k] / t / 1e12, "peak": peak, "unit": "TFLOP/s",
-            "frac": fl[k] / t / 1e12 / peak, "traffic": traffic_per_launch(name, workload_tag),
+            "frac": fl[k] / t / 1e12 / peak, "traffic": traffic_per_launch(name, tag, thash),
             "kernel": name, "avg_launch_us": 1e3 * ms[k] / nl[k],
             "algorithmic_flops_per_launch": fl[k] / nl[k], "algorithmic_bytes_per_launch": by[k] / nl[k],
             "launches_per_step": nl[k] / len(info_list), "hbm_gbs_algorithmic": by[k] / t / 1e9}
@@ -170,26 +239,28 @@ def roofline(info_list, k, top, names, real_bytes, workload_tag):
     return roof
 
 
-# timer slots that cover several kernels launched back to back (summed per launch)
-SLOT_KERNELS = {"k_apply_off": ("k_apply_p2m", "k_apply_m2m", "k_apply_far", "k_apply_near")}
+# timer slots that cover several kernels launched back to back: the parts whose dispatches
+# are summed, and the part launched exactly once per launch of the slot
+SLOT_KERNELS = {"k_apply_off": (("k_apply_pack", "k_apply_p2m", "k_apply_m2m", "k_apply_far", "k_apply_near",
+                                 "k_zgemm<double", "k_apply_finish"), "k_apply_finish")}
 
 
-def summarize_pmc(fetch_csv, write_csv, kname, workload_tag):
+def summarize_pmc(fetch_csv, write_csv, kname, tag, table_path=None):
     """HBM bytes per launch of `kname` from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE,
     KiB per dispatch), each scaled by what the same counter reads for the 256 MiB device
     copy that --copy-calibration runs first (expected 256 MiB fetched and 256 MiB written).
     `kname` may carry template arguments ("k_ts_update<double>") to pick one instantiation;
-    a timer slot of several kernels (k_apply_off: expansions, translations, far and near
-    parts) sums each part's dispatches per launch of the slot (the first part's dispatch
-    count).  The summary is stored under the plain name."""
+    a timer slot of several kernels (k_apply_off: one operator apply) sums its parts'
+    dispatches and divides by the dispatches of its once-per-launch part.  The summary is
+    stored under the plain name, with the hash of the launch table the run used."""
     import csv
     base = kname.split("<")[0]
-    parts = SLOT_KERNELS.get(kname, (kname,))
+    parts, once = SLOT_KERNELS.get(kname, ((kname,), kname))
 
     def matches(name, part):
         if "<" in part:
-            return name.startswith("void " + part)
-        return name.startswith(part + "(") or name.startswith("void " + part + "<")
+            return name.startswith("void " + part) or name.startswith(part)
+        return name.startswith(part + "(") or name.startswith("void " + part + "<") or name == part
 
     def load(path, counter):
         per, copy = {p: [] for p in parts}, []
@@ -210,14 +281,15 @@ def summarize_pmc(fetch_csv, write_csv, kname, workload_tag):
     ref = float(256 << 20)
     ff = cf[0] / ref if cf else 1.0
     fw = cw[0] / ref if cw else 1.0
-    nl = len(fetch[parts[0]])
+    nl = len(fetch[once])
     fb = sum(np.sum(fetch[p]) for p in parts) / nl / ff
     wb = sum(np.sum(write[p]) for p in parts) / nl / fw
-    out = {"kernel": base, "instantiation": kname, "parts": list(parts), "workload": workload_tag,
-           "source_hash": kernel_source_hash(base), "bytes_per_launch": fb + wb,
-           "launches": len(fetch[parts[0]]), "fetch_scale": ff, "write_scale": fw,
-           "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb}
-    json.dump(out, open(traffic_file(base, workload_tag), "w"), indent=1)
+    out = {"kernel": base, "instantiation": kname, "parts": list(parts), "workload": tag,
+           "source_hash": kernel_source_hash(base), "table_hash": table_hash(table_path),
+           "bytes_per_launch": fb + wb, "launches": nl, "fetch_scale": ff, "write_scale": fw,
+           "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+           "dispatches": {p: len(fetch[p]) for p in parts}}
+    json.dump(out, open(traffic_file(base, tag), "w"), indent=1)
     print(json.dumps(out))
 
 
@@ -229,11 +301,12 @@ def run_form(pmx, w, kw, steps, warmup, timing):
     names = pmx.KERNEL_NAMES
     winfos = []
     opts = pmx.options(w, timing=timing, **kw)
-    for _ in range(warmup):
+    for i in range(warmup):
         fac = pmx.Factor(w, opts)
         fac.solve_plane_waves(w.angles)
         winfos.append(fac.info())
         fac.close()
+        print(f"bench: warm-up step {i + 1}/{warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     k, top, share = dominant_kernel(winfos, names) if timing else (None, None, {})
     if k is not None:
@@ -241,6 +314,7 @@ def run_form(pmx, w, kw, steps, warmup, timing):
     times, infos = [], []
     dens = None
     for i in range(steps):
+        dens = None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         fac = pmx.Factor(w, opts)
@@ -249,14 +323,20 @@ def run_form(pmx, w, kw, steps, warmup, timing):
         times.append(time.perf_counter() - t0)
         infos.append(fac.info())
         fac.close()
+        print(f"bench: timed step {i + 1}/{steps}: {times[-1]:.3f} s", file=sys.stderr, flush=True)
     if timing and k is None:     # no warm-up: every kernel was timed in the timed steps
         k, top, share = dominant_kernel(infos, names)
     return times, infos, dens, (k, top, share)
 
 
+def rel_error(a, b):
+    import torch
+    return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
-        summarize_pmc(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+        summarize_pmc(*sys.argv[2:7])
         return
     a = parse()
     if a.gpus != 1:
@@ -272,65 +352,105 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    w = W.config2(a.grid)
+    w = W.config4(a.grid)
     N = w.n_unknowns
-    tag = f"stars{a.grid}"   # traffic summaries are per form: <tag>_tuned, <tag>_plain
+    nrhs = len(w.angles)
+    tag = workload_tag(a.grid)
     timing = 0 if a.no_timing else 1
     forms = {k: dict(v) for k, v in FORMS.items()}
-    tune_s = {}
-    if not a.no_autotune:
-        # launch-parameter tables for this GPU and workload, built before (outside) the timed steps
-        import tempfile
-        tdir = a.tune_dir or tempfile.mkdtemp(prefix="pmx_tune_")
-        os.makedirs(tdir, exist_ok=True)
-        for name in ("tuned", "plain") if not a.no_plain else ("tuned",):
+    names = ("tuned", "plain") if not a.no_plain else ("tuned",)
+    table_note = {}
+    for name in names:
+        if a.autotune:
+            import tempfile
+            tdir = a.tune_dir or tempfile.mkdtemp(prefix="pmx_tune_")
+            os.makedirs(tdir, exist_ok=True)
             path = os.path.join(tdir, f"{tag}_{name}.txt")
-            if os.path.exists(path):
-                tune_s[name] = None
-            else:
-                t0 = time.perf_counter()
-                pmx.autotune(w, path, reps=2, **forms[name])
-                tune_s[name] = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            pmx.autotune(w, path, reps=2, **forms[name])
+            table_note[name] = f"autotuned before the timed steps ({time.perf_counter() - t0:.1f} s)"
+            print(f"bench: {name} launch table tuned", file=sys.stderr, flush=True)
+        else:
+            path = os.path.join(TABLE_DIR, f"{tag}_{name}.txt")
+            if not os.path.exists(path):
+                path = None
+            table_note[name] = (f"committed autotuner table {os.path.relpath(path, ROOT)}" if path
+                                else "built-in rules (no table for this workload)")
+        if path:
             forms[name]["tune_path"] = path
     times, infos, dens, dom = run_form(pmx, w, forms["tuned"], a.steps, a.warmup, timing)
     total = sum(times)
     info = infos[-1]
+    thash_t = table_hash(forms["tuned"].get("tune_path"))
     res = {"metric": METRIC, "value": N * a.steps / total, "unit": "unknowns/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * total / a.steps,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "c64 factor, f64 residual (mixed)", "data": "synthetic",
-           "config": {"workload": f"{a.grid}x{a.grid} rotated stars, 128 nodes, k+=10, k-=15, 4 plane waves",
-                      "n_unknowns": N, "nrhs": len(w.angles), "tuned": FORMS["tuned"], "plain": FORMS["plain"],
+           "config": {"workload": f"{a.grid}x{a.grid} rotated stars, 128 nodes, k+=8, k-=12, "
+                                  f"{nrhs} plane waves",
+                      "n_unknowns": N, "nrhs": nrhs, "tuned": FORMS["tuned"], "plain": FORMS["plain"],
+                      "reference": REFERENCE,
                       "root_size": info.root_size, "levels": info.levels,
                       "refinement_steps": info.ir_iterations, "final_relative_residual": info.ir_residual,
-                      "launch_table": ("autotuned before the timed steps, s: " +
-                                       ", ".join(f"{k} {v:.1f}" if v is not None else f"{k} loaded"
-                                                 for k, v in tune_s.items())) if tune_s
-                                      else "built-in rules"}}
+                      "factor_s": info.t_factor_ms * 1e-3, "solve_s": info.t_solve_ms * 1e-3,
+                      "launch_table": table_note}}
     if timing:
-        res["roofline"] = roofline(infos, dom[0], dom[1], pmx.KERNEL_NAMES, 4, tag + "_tuned")
+        res["roofline"] = roofline(infos, dom[0], dom[1], pmx.KERNEL_NAMES, 4, tag + "_tuned", thash_t)
         res["kernel_time_share"] = dom[2]
+        res["kernel_time_share_from"] = "warm-up steps with every kernel timed (solves launched kernel by kernel)"
     else:
         res["roofline"] = None
-    if not a.no_check:
-        rel, ed = accuracy(w, pmx.dens_to_numpy(dens, w))
-        res["accuracy"] = {"sampled_row_rel_residual": rel, "max_energy_defect": ed}
+    tuned_dens = dens
+    print("bench: tuned form done", file=sys.stderr, flush=True)
+    plain_dens = None
     if not a.no_plain:
-        ptimes, pinfos, pdens, pdom = run_form(pmx, w, forms["plain"], a.steps, a.warmup, timing)
+        psteps = max(1, min(a.plain_steps, a.steps))
+        ptimes, pinfos, plain_dens, pdom = run_form(pmx, w, forms["plain"], psteps, min(a.warmup, 1), timing)
         ptotal = sum(ptimes)
-        plain = {"value": N * a.steps / ptotal, "ms_per_step": 1e3 * ptotal / a.steps,
-                 "root_size": pinfos[-1].root_size}
-        if not a.no_check:
-            prel, ped = accuracy(w, pmx.dens_to_numpy(pdens, w))
-            plain["accuracy"] = {"sampled_row_rel_residual": prel, "max_energy_defect": ped}
+        plain = {"value": N * psteps / ptotal, "ms_per_step": 1e3 * ptotal / psteps, "steps": psteps,
+                 "warmup": min(a.warmup, 1), "root_size": pinfos[-1].root_size,
+                 "factor_s": pinfos[-1].t_factor_ms * 1e-3, "solve_s": pinfos[-1].t_solve_ms * 1e-3}
         if timing:
-            plain["roofline"] = roofline(pinfos, pdom[0], pdom[1], pmx.KERNEL_NAMES, 8, tag + "_plain")
+            plain["roofline"] = roofline(pinfos, pdom[0], pdom[1], pmx.KERNEL_NAMES, 8, tag + "_plain",
+                                         table_hash(forms["plain"].get("tune_path")))
             plain["kernel_time_share"] = pdom[2]
         res["plain"] = plain
         res["speedup_vs_plain"] = res["value"] / plain["value"]
+        print("bench: plain form done", file=sys.stderr, flush=True)
+    if not a.no_check:
+        acc = {"target_rel_error": TARGET_ERROR}
+        fac = pmx.Factor(w, pmx.options(w, **REFERENCE))
+        ref = fac.solve_plane_waves(w.angles)
+        torch.cuda.synchronize()
+        fac.close()
+        acc["reference"] = "plain FP64 solve at ID tolerance 1e-12 (same library, untimed)"
+        acc["tuned_rel_error_vs_ref"] = rel_error(tuned_dens, ref)
+        if plain_dens is not None:
+            acc["plain_rel_error_vs_ref"] = rel_error(plain_dens, ref)
+        print("bench: reference solve done", file=sys.stderr, flush=True)
+        ref_np = pmx.dens_to_numpy(ref, w)
+        del ref
+        acc["reference_oracle_rows_rel_residual"], rows = sampled_residual(w, ref_np, a.rows)
+        acc["reference_max_energy_defect"] = energy(w, ref_np)
+        del ref_np
+        x = pmx.dens_to_numpy(tuned_dens, w)
+        acc["tuned_oracle_rows_rel_residual"], _ = sampled_residual(w, x, a.rows)
+        acc["tuned_max_energy_defect"] = energy(w, x)
+        if plain_dens is not None:
+            x = pmx.dens_to_numpy(plain_dens, w)
+            acc["plain_oracle_rows_rel_residual"], _ = sampled_residual(w, x, a.rows)
+            acc["plain_max_energy_defect"] = energy(w, x)
+        acc["oracle_rows"] = [int(r) for r in rows]
+        worst = max(acc["tuned_rel_error_vs_ref"], acc.get("plain_rel_error_vs_ref", 0.0))
+        acc["meets_target"] = bool(worst <= TARGET_ERROR)
+        res["accuracy"] = acc
+        print("bench: accuracy checks done", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(w)
+        res["cpu_baseline"] = cpu_baseline(w, N)
     print(json.dumps(res), flush=True)
+    if not a.no_check and not res["accuracy"]["meets_target"]:
+        print("bench: a form misses the 1e-8 field error target", file=sys.stderr, flush=True)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -592,7 +592,6 @@ int apply_source_order(double kr) {
 template <int NR>
 static void apply_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipStream_t s) {
   hipLaunchKernelGGL(k_apply_pack<NR>, dim3((A.n_nodes + 255) / 256), dim3(256), 0, s, A, r0, pk);
-  KScope ks(PK_APPLY, s);
   const int m = (int)A.n_incl;
   hipLaunchKernelGGL(k_apply_p2m<NR>, dim3(m), dim3(256), 0, s, A, (const double*)pk, r0);
   for (int l = 0; l < A.n_lev; ++l)

@@ -116,9 +116,19 @@ void asm_convert(const cx<RS>* src, cx<RD>* dst, int64_t n, hipStream_t s);
 template <class RD>
 void asm_convert_blocks(const zd* src, cx<RD>* dst, const int64_t* d_soff, const int64_t* d_doff,
                         const int64_t* d_len, int nblocks, int64_t max_len, hipStream_t s);
-// far field: out[r * ndir + t] for densities dens (ld = 2 * n_nodes, per inclusion [q; u])
-void asm_far_field(DevGeom g, ExtParams e, const int* owner, const int64_t* node_off,
-                   const zd* dens, int nrhs, const double* dirs, int ndir, zd* out, hipStream_t s);
+// far field: out[r * ndir + t] for densities dens (ld = 2 * n_nodes, per inclusion [q; u]);
+// dirs is host memory [ndir] (angles), part device memory of far_field_part_bytes() for
+// the partial sums of the split node sum
+constexpr int PMX_FF_DIRS = 64;   // directions per launch, passed as kernel arguments
+struct FarDirs {
+  double c[PMX_FF_DIRS], s[PMX_FF_DIRS];   // cos, sin of the directions t0 .. t0 + nt - 1
+  int t0, nt;
+};
+int far_field_splits(int64_t n_nodes, int nrhs, int ndir);
+size_t far_field_part_bytes(int64_t n_nodes, int nrhs, int ndir);
+void asm_far_field(DevGeom g, ExtParams e, const int* owner, const int64_t* node_off, const zd* dens, int nrhs,
+                   const double* dirs, int ndir, zd* part, zd* out, hipStream_t s);
+
 // build the explicit L = blockdiag(Z_0^T, Z_1^T) (s x K) of a batch of cells
 template <class R>
 struct LDescT {

@@ -12,6 +12,7 @@
 // differentiation D_t), then combined as
 //   [[-(e+ S+ + e- S-), D+ + D-], [-(D*+ + D*-), N+/e+ + N-/e-]].
 #include <algorithm>
+#include <cmath>
 
 #include "assemble.h"
 #include "bessel.h"
@@ -468,55 +469,122 @@ void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s) {
 
 // ---------------------------------------------------------------------------------
 // u_inf(xh) = e^{i pi/4}/sqrt(8 pi k) sum_b w_b [-i k (xh.n_b) u_b - e+ q_b] e^{-i k xh.y_b}
-__global__ __launch_bounds__(256) void k_far_field(DevGeom g, ExtParams e, const int* owner,
-                                                    const int64_t* node_off, const zd* dens, int nrhs,
-                                                    const double* dirs, int ndir, zd* out) {
-  const int t = blockIdx.x, r = blockIdx.y;
-  double sx, cx;
-  sincos(dirs[t], &sx, &cx);
+// (Colton-Kress normalisation of the exterior representation of Sec. 2.1).
+//
+// The node sum is split into `nsplit` contiguous node ranges so that the grid fills the
+// chip also for few directions and right-hand sides; each workgroup sums PMX_FF_GROUP
+// directions of one right-hand side over one range (node data read once for the group)
+// and writes its partial sums, which a second kernel adds in split order (deterministic)
+// and scales by the normalisation.  Directions travel as kernel arguments, so the pair
+// needs no device copy of them.
+constexpr int PMX_FF_GROUP = 4;
+
+__global__ __launch_bounds__(256) void k_far_field_part(DevGeom g, ExtParams e, const int* owner,
+                                                         const int64_t* node_off, const zd* dens, int nrhs,
+                                                         FarDirs D, int ndir, int64_t chunk, zd* part) {
+  const int t0 = blockIdx.x * PMX_FF_GROUP, r = blockIdx.y, sp = blockIdx.z;
+  const int nt = min(PMX_FF_GROUP, D.nt - t0);
+  const int64_t lo = (int64_t)sp * chunk, hi = min((int64_t)g.n_nodes, lo + chunk);
   const int64_t ld = 2 * (int64_t)g.n_nodes;
-  double ar = 0, ai = 0;
-  for (int i = threadIdx.x; i < g.n_nodes; i += 256) {
+  double cx[PMX_FF_GROUP], sx[PMX_FF_GROUP], ar[PMX_FF_GROUP], ai[PMX_FF_GROUP];
+#pragma unroll
+  for (int a = 0; a < PMX_FF_GROUP; ++a) {
+    const int t = t0 + min(a, nt - 1);
+    cx[a] = D.c[t];
+    sx[a] = D.s[t];
+    ar[a] = 0;
+    ai[a] = 0;
+  }
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
     const int j = owner[i];
     const int64_t o = node_off[j];
     const int64_t n = node_off[j + 1] - o;
     const int64_t l = i - o;
     const zd q = dens[r * ld + 2 * o + l];
     const zd u = dens[r * ld + 2 * o + n + l];
-    const double xn = cx * g.nx[i] + sx * g.ny[i];
-    // -i k xn u - e q
-    const zd a = zmk(e.k * xn * u.im - e.eps * q.re, -e.k * xn * u.re - e.eps * q.im);
-    double s, c;
-    sincos(-e.k * (cx * g.x[i] + sx * g.y[i]), &s, &c);
-    const zd v = zmul(a, zmk(c, s));
-    ar = fma(g.w[i], v.re, ar);
-    ai = fma(g.w[i], v.im, ai);
+    const double px = g.x[i], py = g.y[i], nx = g.nx[i], ny = g.ny[i], wi = g.w[i];
+#pragma unroll
+    for (int a = 0; a < PMX_FF_GROUP; ++a) {
+      const double xn = cx[a] * nx + sx[a] * ny;
+      // -i k xn u - e q
+      const zd v = zmk(e.k * xn * u.im - e.eps * q.re, -e.k * xn * u.re - e.eps * q.im);
+      double s, c;
+      sincos(-e.k * (cx[a] * px + sx[a] * py), &s, &c);
+      const zd p = zmul(v, zmk(c, s));
+      ar[a] = fma(wi, p.re, ar[a]);
+      ai[a] = fma(wi, p.im, ai[a]);
+    }
   }
-  __shared__ double red[2][4];
-  for (int o = 32; o >= 1; o >>= 1) {
-    ar += __shfl_xor(ar, o, 64);
-    ai += __shfl_xor(ai, o, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = ar;
-    red[1][threadIdx.x >> 6] = ai;
+  __shared__ double red[2 * PMX_FF_GROUP][4];
+#pragma unroll
+  for (int a = 0; a < PMX_FF_GROUP; ++a) {
+    for (int o = 32; o >= 1; o >>= 1) {
+      ar[a] += __shfl_xor(ar[a], o, 64);
+      ai[a] += __shfl_xor(ai[a], o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[2 * a][threadIdx.x >> 6] = ar[a];
+      red[2 * a + 1][threadIdx.x >> 6] = ai[a];
+    }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double sr = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    double si = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-    const double amp = 1.0 / sqrt(8.0 * PMX_PI * e.k);
-    const double c4 = 0.70710678118654752440;
-    const zd ph = zmk(c4 * amp, c4 * amp);
-    out[(int64_t)r * ndir + t] = zmul(ph, zmk(sr, si));
+  if (threadIdx.x < nt) {
+    const int a = threadIdx.x;
+    const double sr = red[2 * a][0] + red[2 * a][1] + red[2 * a][2] + red[2 * a][3];
+    const double si = red[2 * a + 1][0] + red[2 * a + 1][1] + red[2 * a + 1][2] + red[2 * a + 1][3];
+    part[((int64_t)sp * nrhs + r) * ndir + D.t0 + t0 + a] = zmk(sr, si);
   }
 }
 
-void asm_far_field(DevGeom g, ExtParams e, const int* owner, const int64_t* node_off,
-                   const zd* dens, int nrhs, const double* dirs, int ndir, zd* out, hipStream_t s) {
+__global__ __launch_bounds__(256) void k_far_field_finish(const zd* part, int nsplit, int nrhs, int ndir, double k,
+                                                           zd* out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)nrhs * ndir;
+  if (i >= n) return;
+  double sr = 0, si = 0;
+  for (int sp = 0; sp < nsplit; ++sp) {
+    const zd v = part[(int64_t)sp * n + i];
+    sr += v.re;
+    si += v.im;
+  }
+  const double amp = 1.0 / sqrt(8.0 * PMX_PI * k);
+  const double c4 = 0.70710678118654752440;
+  out[i] = zmul(zmk(c4 * amp, c4 * amp), zmk(sr, si));
+}
+
+int far_field_splits(int64_t n_nodes, int nrhs, int ndir) {
+  // about 2048 workgroups in all, ranges of at least 2048 nodes, at most 256 ranges
+  const int64_t per = (int64_t)nrhs * ((ndir + PMX_FF_GROUP - 1) / PMX_FF_GROUP);
+  int64_t ns = std::max<int64_t>(1, (2048 + per - 1) / per);
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, (n_nodes + 2047) / 2048));
+  return (int)std::min<int64_t>(ns, 256);
+}
+
+size_t far_field_part_bytes(int64_t n_nodes, int nrhs, int ndir) {
+  return sizeof(zd) * (size_t)far_field_splits(n_nodes, nrhs, ndir) * (size_t)nrhs * (size_t)ndir;
+}
+
+void asm_far_field(DevGeom g, ExtParams e, const int* owner, const int64_t* node_off, const zd* dens, int nrhs,
+                   const double* dirs, int ndir, zd* part, zd* out, hipStream_t s) {
   if (nrhs <= 0 || ndir <= 0) return;
-  hipLaunchKernelGGL(k_far_field, dim3(ndir, nrhs), dim3(256), 0, s, g, e, owner, node_off, dens,
-                     nrhs, dirs, ndir, out);
+  const int nsplit = far_field_splits(g.n_nodes, nrhs, ndir);
+  const int64_t chunk = ((int64_t)g.n_nodes + nsplit - 1) / nsplit;
+  for (int t0 = 0; t0 < ndir; t0 += PMX_FF_DIRS) {
+    FarDirs D;
+    D.t0 = t0;
+    D.nt = std::min(PMX_FF_DIRS, ndir - t0);
+    for (int a = 0; a < PMX_FF_DIRS; ++a) {
+      const double th = dirs[t0 + std::min(a, D.nt - 1)];
+      D.c[a] = std::cos(th);
+      D.s[a] = std::sin(th);
+    }
+    const dim3 grid((D.nt + PMX_FF_GROUP - 1) / PMX_FF_GROUP, nrhs, nsplit);
+    hipLaunchKernelGGL(k_far_field_part, grid, dim3(256), 0, s, g, e, owner, node_off, dens, nrhs, D, ndir,
+                       chunk, part);
+  }
+  const int64_t n = (int64_t)nrhs * ndir;
+  hipLaunchKernelGGL(k_far_field_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nsplit, nrhs,
+                     ndir, e.k, out);
 }
 
 // ---------------------------------------------------------------------------------

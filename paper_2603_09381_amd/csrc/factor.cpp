@@ -1671,6 +1671,7 @@ struct DenseApply {
   int nslots = 1;                 // partial-sum slots: nsplit far-list parts + near parts
   int n_src = 0;                  // expansion sources: inclusions and clusters
   double flops_fixed = 0, flops_rhs = 0;   // algorithmic work of one apply (counted with timing)
+  double self_sq = 0;             // sum over inclusions of (2 n_j)^2: the FP64 self-block entries
   int64_t total = 0;
   zd *ydiag = nullptr, *part = nullptr;
   double* d_norm = nullptr;
@@ -1910,6 +1911,7 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
     int n2 = (int)(2 * (F->node_off[j + 1] - F->node_off[j]));
     ga[t] = GemmArgs{n2, nrhs, n2, dself + doff[t], n2, x + 2 * F->node_off[j], N2, D.ydiag + 2 * F->node_off[j], N2};
     D.max_s = std::max(D.max_s, n2);
+    D.self_sq += (double)n2 * n2;
   }
   D.d_ga = A.upload(ga, s);
   D.n_ga = (int)ga.size();
@@ -1994,11 +1996,11 @@ struct SolveState {
   void* d_r_to_leaf = nullptr;                     // refinement: r -> leaf vectors (factor type)
   void* d_leafr_to_x = nullptr;                    // refinement: leaf (factor type) += -> xout
   DenseApply apply;
-  hipGraphExec_t g_plane = nullptr, g_general = nullptr, g_iter = nullptr;
+  hipGraphExec_t g_plane = nullptr, g_general = nullptr, g_iter = nullptr, g_apply = nullptr;
   Arena arena;
   explicit SolveState(DevPool* pool) : arena(pool) {}
   void drop_graphs() {
-    for (hipGraphExec_t* g : {&g_plane, &g_general, &g_iter})
+    for (hipGraphExec_t* g : {&g_plane, &g_general, &g_iter, &g_apply})
       if (*g) {
         (void)hipGraphExecDestroy(*g);
         *g = nullptr;
@@ -2041,10 +2043,10 @@ hipGraphExec_t capture_graph(hipStream_t gs, Fn&& fn) {
 
 // run a launch sequence, through its captured graph when graphs are on
 template <class Fn>
-void run_seq(pmx_factor* F, hipGraphExec_t& g, Fn&& fn) {
-  // with per-kernel timing of a kernel of the sequence it runs launch by launch, bracketed
-  // by events
-  if (!F->opts.solve_graph || (g_ktimer && (g_ktimer->mask & PK_SOLVE_MASK))) {
+void run_seq(pmx_factor* F, hipGraphExec_t& g, unsigned kernels, Fn&& fn) {
+  // with per-kernel timing of a kernel launched inside the sequence (bit k of `kernels`:
+  // kernel k) it runs launch by launch, bracketed by events
+  if (!F->opts.solve_graph || (g_ktimer && (g_ktimer->mask & kernels))) {
     fn();
     return;
   }
@@ -2110,16 +2112,17 @@ void upload_angles(pmx_factor* F, const double* angles) {
   HIPCHK(hipMemcpyAsync(S.d_angles, S.h_angles.data(), S.nrhs * sizeof(double), hipMemcpyHostToDevice, F->gs));
 }
 
-// Algorithmic work of one dense operator apply (the near pairs, the far expansions and the
-// expansion sums; apply_geometry counts them).  Bytes: the node data (x, y, normal,
-// weight) and the densities read once, the expansion records written and read once, the
-// partial sums of every slot written once.
+// Algorithmic work of one operator apply: the near pairs, the far expansions and the
+// expansion sums (apply_geometry counts them) and the FP64 self-block product (8 flops per
+// complex multiply-add).  Bytes (inputs read once, the output written once): the node
+// data (x, y, normal, weight, owner), the self blocks, the densities and the right-hand
+// side, and the residual.  Expansion records and partial sums are the implementation's
+// own traffic and are not counted.
 void count_apply_work(pmx_factor* F, int nrhs) {
   const DenseApply& D = F->ss->apply;
   const double N2 = 2.0 * F->n_nodes;
-  F->info.kernel_flops[PK_APPLY] += D.flops_fixed + D.flops_rhs * nrhs;
-  F->info.kernel_bytes[PK_APPLY] += 8.0 * 5 * F->n_nodes + 16.0 * N2 * nrhs * (1 + D.nslots) +
-                                    2.0 * 16.0 * 6.0 * PMX_APPLY_NRECA * D.n_src * nrhs;
+  F->info.kernel_flops[PK_APPLY] += D.flops_fixed + D.flops_rhs * nrhs + 8.0 * D.self_sq * nrhs;
+  F->info.kernel_bytes[PK_APPLY] += 8.0 * 5 * F->n_nodes + 16.0 * D.self_sq + 16.0 * N2 * nrhs * 3;
 }
 
 // FP64 factor: right-hand side into the leaf vectors, one solve pass, solution to xout.
@@ -2131,14 +2134,14 @@ void solve_fp64(pmx_factor* F, int nrhs, const double* angles, const zd* rhs) {
   const LeafMap& M = S.map;
   if (angles) {
     upload_angles(F, angles);
-    run_seq(F, S.g_plane, [&] {
+    run_seq(F, S.g_plane, PK_SOLVE_MASK, [&] {
       asm_incident(F->geom(), F->ext(), S.d_node0, S.d_nn, S.d_off, M.ncell, S.maxn, S.d_angles, nrhs, leaf, gs);
       launch_program<double>(F, gs);
       asm_gather(leaf, S.d_leaf_to_x, 1, M.n2, nrhs, gs, 0);
     });
   } else {
     HIPCHK(hipMemcpyAsync(S.fin, rhs, 2 * (int64_t)F->n_nodes * nrhs * sizeof(zd), hipMemcpyDeviceToDevice, gs));
-    run_seq(F, S.g_general, [&] {
+    run_seq(F, S.g_general, PK_SOLVE_MASK, [&] {
       asm_gather(S.fin, S.d_fin_to_leaf, M.ncell, M.max_cell, nrhs, gs, 0);
       launch_program<double>(F, gs);
       asm_gather(leaf, S.d_leaf_to_x, 1, M.n2, nrhs, gs, 0);
@@ -2148,8 +2151,8 @@ void solve_fp64(pmx_factor* F, int nrhs, const double* angles, const zd* rhs) {
 
 // Refinement: the factor of type R as the inner solver of iterative refinement with the
 // FP64 operator, x_0 = 0, r_i = f - A x_i, x_{i+1} = x_i + solve(r_i), until
-// max_r |r_i| / |f| <= ir_tol.  One step (gathers, solve pass, operator apply, residual
-// norms) is one captured graph.
+// max_r |r_i| / |f| <= ir_tol.  One step is two captured graphs (the gathers and the solve
+// pass; the operator apply) and the residual norms.
 template <class R>
 void solve_refined(pmx_factor* F, int nrhs, const double* angles, const zd* rhs) {
   ensure_state<R>(F, nrhs);
@@ -2175,13 +2178,18 @@ void solve_refined(pmx_factor* F, int nrhs, const double* angles, const zd* rhs)
   int it = 0;
   for (int h = 0; h < 16; ++h) F->info.ir_history[h] = 0;
   for (it = 1; it <= maxit; ++it) {
-    run_seq(F, S.g_iter, [&] {
+    run_seq(F, S.g_iter, PK_SOLVE_MASK & ~(1u << PK_APPLY), [&] {
       asm_gather(S.r, r_to_leaf, M.ncell, M.max_cell, nrhs, gs, 0);
       launch_program<R>(F, gs);
       asm_gather(leaf, S.d_leaf_to_x, 1, M.n2, nrhs, gs, 1);
-      launch_dense_apply(S.apply, gs);
-      launch_norms(S.apply, S.r, gs);
     });
+    {
+      // the operator apply is a graph of its own, so that events can bracket it (timer
+      // slot k_apply_off: every kernel of one apply) while it still replays as a graph
+      KScope ks(PK_APPLY, gs);
+      run_seq(F, S.g_apply, 1u << PK_ZGEMM, [&] { launch_dense_apply(S.apply, gs); });
+    }
+    launch_norms(S.apply, S.r, gs);
     count_apply_work(F, nrhs);
     const std::vector<double> rn = read_norms(S.apply, gs);
     rel = 0;
@@ -2655,12 +2663,13 @@ pmx_status pmx_far_field(const pmx_factor* f, int32_t nrhs, const pmx_c64* dens,
     if (!f || !dens || !dirs || !out || nrhs <= 0 || ndir <= 0) fail(PMX_EINVAL, "bad arguments to pmx_far_field");
     hipStream_t s = (hipStream_t)hip_stream;
     Arena tmp;
-    std::vector<double> d(dirs, dirs + ndir);
-    asm_far_field(f->geom(), f->ext(), f->owner, f->d_node_off, (const zd*)dens, nrhs, tmp.upload(d, s), ndir,
-                  (zd*)out, s);
+    zd* part = tmp.alloc<zd>(far_field_part_bytes(f->n_nodes, nrhs, ndir) / sizeof(zd));
+    asm_far_field(f->geom(), f->ext(), f->owner, f->d_node_off, (const zd*)dens, nrhs, dirs, ndir, part, (zd*)out,
+                  s);
     sync_check(s);
   });
 }
+
 
 pmx_status pmx_factor_info(const pmx_factor* f, pmx_info* info) {
   return guarded([&] {

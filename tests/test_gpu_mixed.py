@@ -192,3 +192,29 @@ def test_mixed_scattered_uneven_against_dense(pmx):
     err = dense.rel_error(x, dense.solve(w))
     print(w.name, "mixed: iters", info.ir_iterations, "res", info.ir_residual, "err", err)
     assert info.ir_residual <= 1e-10 and err < 1e-8
+
+
+def test_stars16_tuned_and_plain_against_tight_reference(pmx):
+    """The 16x16 grid of stars (N = 65,536, four plane waves): the tuned form (FP32 factor
+    at ID tolerance 1e-3 refined to 1e-10) and the plain FP64 form (1e-10) against the plain
+    FP64 solve at ID tolerance 1e-12, by the relative 2-norm error over every entry (Sec.
+    4.2); the oracle's FP64 rows f - A x on sampled rows back the reference itself."""
+    import torch
+    w = W.config2()
+    out = {}
+    for name, kw in (("ref", dict(precision=0, id_tol=1e-12)), ("plain", dict(precision=0, id_tol=1e-10)),
+                     ("tuned", dict(precision=1, id_tol=1e-3, ir_tol=1e-10))):
+        print("stars16 form", name, flush=True)
+        fac = pmx.Factor(w, pmx.options(w, **kw))
+        out[name] = fac.solve_plane_waves(w.angles)
+        torch.cuda.synchronize()
+        fac.close()
+    ref = out["ref"]
+    errs = {k: float(torch.linalg.norm(out[k] - ref) / torch.linalg.norm(ref)) for k in ("plain", "tuned")}
+    rows = np.sort(np.random.default_rng(3).choice(w.n_unknowns, size=12, replace=False))
+    f = dense.rhs(dense.Geometry(w), w.angles)[rows]
+    res = {k: float(np.linalg.norm(dense.residual_rows(w, pmx.dens_to_numpy(out[k], w), rows)) / np.linalg.norm(f))
+           for k in ("ref", "tuned")}
+    print("stars16 rel error vs reference", errs, "oracle sampled residual", res)
+    assert errs["plain"] <= 1e-8 and errs["tuned"] <= 1e-8
+    assert res["ref"] <= 1e-10 and res["tuned"] <= 1e-9

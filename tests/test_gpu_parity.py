@@ -221,6 +221,36 @@ def test_far_field_against_oracle_and_mie(pmx):
     assert np.abs(ff - mie).max() < 1e-12 * np.abs(mie).max()
 
 
+def test_far_field_many_inclusions_and_right_hand_sides(pmx):
+    """4x4 stars, 4 plane waves: the far-field kernel on the GPU's own densities against the
+    oracle's evaluation of the same sum (every inclusion's q and u blocks, every right-hand
+    side), then reciprocity and the optical theorem on the GPU's output (the densities
+    carry the ID error, ~1e-9)."""
+    import torch
+    w = W.sub_grid(W.config2(), 4)
+    fac = pmx.Factor(w)
+    dens = fac.solve_plane_waves(w.angles)
+    torch.cuda.synchronize()
+    x = pmx.dens_to_numpy(dens, w)
+    nd = 720
+    th = 2 * np.pi * np.arange(nd) / nd
+    dirs = np.concatenate([w.angles, th])
+    ff = fac.far_field(dens, dirs).cpu().numpy().T          # (ndir, nrhs)
+    g = dense.Geometry(w)
+    ref = dense.far_field(g, x, dirs)
+    assert np.abs(ff - ref).max() < 1e-12 * np.abs(ref).max()
+    A = ff[:4]                                               # A[i, j] = u_inf(angle_i; incidence j)
+    for i in range(4):
+        for j in range(4):
+            assert abs(A[i, j] - A[(j + 2) % 4, (i + 2) % 4]) < 1e-8 * np.abs(A).max()
+    k = w.k_ext
+    for c in range(4):
+        lhs = np.sum(np.abs(ff[4:, c]) ** 2) * 2 * np.pi / nd
+        rhs = -np.sqrt(8 * np.pi / k) * np.real(np.exp(1j * np.pi / 4) * A[c, c])
+        assert abs(lhs - rhs) < 1e-8 * lhs
+    fac.close()
+
+
 def test_general_rhs_matches_plane_wave(pmx):
     import torch
     w = W.sub_grid(W.config2(), 2)
