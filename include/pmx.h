@@ -164,6 +164,20 @@ pmx_status pmx_solve(pmx_factor* f, int32_t nrhs, const pmx_c64* rhs, pmx_c64* d
 pmx_status pmx_far_field(const pmx_factor* f, int32_t nrhs, const pmx_c64* dens, int32_t ndir,
                          const double* dirs, pmx_c64* out, void* hip_stream);
 
+/* pmx_far_field without any device allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and result as pmx_far_field.  The partial sums of
+ * its split node sum live in a static array of 8 MiB per GPU, held by every GPU the
+ * library runs on until the process ends; it holds at most 524288 (right-hand side,
+ * direction) pairs, fewer when the node sum is split (small nrhs * ndir), and larger
+ * requests return PMX_EINVAL before any GPU work.  Calls no hipMalloc or hipFree and does
+ * not synchronise: the result is complete in stream order.  All calls on one GPU share the
+ * array: calls that overlap on one GPU (different streams or threads without ordering)
+ * race and may return wrong values; calls ordered on one stream do not.  Errors:
+ * PMX_EINVAL, PMX_EHIP. */
+pmx_status pmx_far_field_noalloc(const pmx_factor* f, int32_t nrhs, const pmx_c64* dens, int32_t ndir,
+                                 const double* dirs, pmx_c64* out, void* hip_stream);
+
 pmx_status pmx_factor_info(const pmx_factor* f, pmx_info* info);
 
 /* Autotuner of the launch parameters of the batched form.  Launches whose kernel has

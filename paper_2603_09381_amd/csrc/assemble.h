@@ -128,7 +128,11 @@ int far_field_splits(int64_t n_nodes, int nrhs, int ndir);
 size_t far_field_part_bytes(int64_t n_nodes, int nrhs, int ndir);
 void asm_far_field(DevGeom g, ExtParams e, const int* owner, const int64_t* node_off, const zd* dens, int nrhs,
                    const double* dirs, int ndir, zd* part, zd* out, hipStream_t s);
-
+// Device address of this GPU's copy of the static partial-sum array of the allocation-free
+// far field (PMX_FF_SCRATCH_BYTES, shared by every call on the GPU).
+constexpr size_t PMX_FF_SCRATCH_BYTES = (size_t)8 << 20;
+constexpr int PMX_MAX_DEVICES = 64;
+hipError_t far_field_scratch(zd** out);
 // build the explicit L = blockdiag(Z_0^T, Z_1^T) (s x K) of a batch of cells
 template <class R>
 struct LDescT {

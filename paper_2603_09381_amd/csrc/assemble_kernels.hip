@@ -13,6 +13,7 @@
 //   [[-(e+ S+ + e- S-), D+ + D-], [-(D*+ + D*-), N+/e+ + N-/e-]].
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "assemble.h"
 #include "bessel.h"
@@ -585,6 +586,34 @@ void asm_far_field(DevGeom g, ExtParams e, const int* owner, const int64_t* node
   const int64_t n = (int64_t)nrhs * ndir;
   hipLaunchKernelGGL(k_far_field_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nsplit, nrhs,
                      ndir, e.k, out);
+}
+
+// The partial sums of the allocation-free far field live in this file-scope array, one
+// copy per GPU, for the life of the process.  Host code never uses its name as an
+// address: the device address comes from hipGetSymbolAddress, taken once per device with
+// that device current, and is kept per device.
+static __device__ __align__(256) double scratch[PMX_FF_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[PMX_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t far_field_scratch(zd** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= PMX_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (zd*)g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------------

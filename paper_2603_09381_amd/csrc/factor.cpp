@@ -2670,6 +2670,31 @@ pmx_status pmx_far_field(const pmx_factor* f, int32_t nrhs, const pmx_c64* dens,
   });
 }
 
+pmx_status pmx_far_field_noalloc(const pmx_factor* f, int32_t nrhs, const pmx_c64* dens, int32_t ndir,
+                                 const double* dirs, pmx_c64* out, void* hip_stream) {
+  return guarded([&] {
+    if (!f || !dens || !dirs || !out || nrhs <= 0 || ndir <= 0)
+      fail(PMX_EINVAL, "bad arguments to pmx_far_field_noalloc");
+    const size_t need = far_field_part_bytes(f->n_nodes, nrhs, ndir);
+    if (need > PMX_FF_SCRATCH_BYTES)
+      fail(PMX_EINVAL, "pmx_far_field_noalloc: " + std::to_string(nrhs) + " right-hand sides x " +
+                           std::to_string(ndir) + " directions need " + std::to_string(need) +
+                           " bytes of partial sums, more than its static " + std::to_string(PMX_FF_SCRATCH_BYTES) +
+                           " (at most 524288 right-hand-side/direction pairs)");
+    zd* part = nullptr;
+    const hipError_t e = far_field_scratch(&part);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      fail(PMX_EHIP, std::string("pmx_far_field_noalloc: no device address for its static array: ") +
+                         hipGetErrorString(e));
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    asm_far_field(f->geom(), f->ext(), f->owner, f->d_node_off, (const zd*)dens, nrhs, dirs, ndir, part, (zd*)out,
+                  s);
+    const hipError_t le = hipGetLastError();
+    if (le != hipSuccess) fail(PMX_EHIP, std::string("pmx_far_field_noalloc launch: ") + hipGetErrorString(le));
+  });
+}
 
 pmx_status pmx_factor_info(const pmx_factor* f, pmx_info* info) {
   return guarded([&] {

@@ -27,7 +27,7 @@ EXPORTS = [
     "pmx_probe_zgemm", "pmx_probe_lu_solve", "pmx_probe_id", "pmx_plan_query",
     "pmx_probe_cgemm", "pmx_probe_lu_solve_c32", "pmx_probe_id_c32", "pmx_probe_apply",
     "pmx_mlp_opts_default", "pmx_id_dataset", "pmx_mlp_train", "pmx_mlp_predict", "pmx_probe_mlp",
-    "pmx_autotune", "pmx_device_cache",
+    "pmx_autotune", "pmx_device_cache", "pmx_far_field_noalloc",
 ]
 
 
@@ -94,6 +94,7 @@ def load(path=None):
     lib.pmx_solve_plane_waves.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), vp, vp]
     lib.pmx_solve.argtypes = [vp, C.c_int32, vp, vp, vp]
     lib.pmx_far_field.argtypes = [vp, C.c_int32, vp, C.c_int32, C.POINTER(C.c_double), vp, vp]
+    lib.pmx_far_field_noalloc.argtypes = [vp, C.c_int32, vp, C.c_int32, C.POINTER(C.c_double), vp, vp]
     lib.pmx_factor_info.argtypes = [vp, C.POINTER(Info)]
     lib.pmx_factor_destroy.argtypes = [vp]
     lib.pmx_factor_destroy.restype = None
@@ -247,6 +248,18 @@ class Factor:
         out = torch.empty((dens.shape[0], len(d)), dtype=torch.complex128, device=dens.device)
         _check(_lib.pmx_far_field(self.h, dens.shape[0], C.c_void_p(dens.data_ptr()), len(d), _ptr(d, C.c_double),
                                   C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def far_field_noalloc(self, dens, dirs, out=None):
+        """pmx_far_field_noalloc: the same pattern with the partial sums in the library's
+        static per-GPU array (no device allocation; `out` may be given)."""
+        import torch
+        d = np.ascontiguousarray(dirs, dtype=np.float64)
+        dens = dens.contiguous()
+        if out is None:
+            out = torch.empty((dens.shape[0], len(d)), dtype=torch.complex128, device=dens.device)
+        _check(_lib.pmx_far_field_noalloc(self.h, dens.shape[0], C.c_void_p(dens.data_ptr()), len(d),
+                                          _ptr(d, C.c_double), C.c_void_p(out.data_ptr()), _stream()))
         return out
 
 
