@@ -393,6 +393,10 @@ def main():
                       "root_size": info.root_size, "levels": info.levels,
                       "refinement_steps": info.ir_iterations, "final_relative_residual": info.ir_residual,
                       "factor_s": info.t_factor_ms * 1e-3, "solve_s": info.t_solve_ms * 1e-3,
+                      "refinement_history": [float(v) for v in info.ir_history[:info.ir_iterations]],
+                      "apply_fmm": dict(zip(("m2l_pairs", "mean_source_order", "mean_local_order", "local_expansions",
+                                             "l2l_pairs", "near_node_pairs", "direct_far_pairs", "table_bytes"),
+                                            [float(v) for v in info.apply_stats])),
                       "launch_table": table_note}}
     if timing:
         res["roofline"] = roofline(infos, dom[0], dom[1], pmx.KERNEL_NAMES, 4, tag + "_tuned", thash_t)

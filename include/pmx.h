@@ -110,7 +110,9 @@ typedef struct {
   double t_phase_ms[16];     /* host wall time of phases: 0 self blocks, 1 level compression,
                                 2 level merges, 3 top LU, 4 plan; solves: 5 set-up of the
                                 solve state for a new right-hand-side count, 6 of it the
-                                operator apply set-up */
+                                operator apply set-up; 7 the leaf level's IDs (part of 1:
+                                QR, CPQR, with learned proposals their judge and fallback),
+                                8 the learned proposals (features and network, at create) */
   /* with options.timing = 1: per-kernel device time from HIP events around every launch
    * (of the kernels selected by options.timing_kernels) of the factorisation and of the
    * solves, summed over them (index: 0 QR leaf blocks, 1 QR trailing update, 2 LU panel, 3 CPQR
@@ -130,6 +132,12 @@ typedef struct {
   double ir_history[16];     /* relative residual after each of the first 16 steps */
   int32_t id_learned;        /* leaf cells whose IDs the learned proposals settled */
   int32_t id_fallback;       /* leaf cells that fell back to the full CPQR */
+  /* refined forms, after the first solve: the operator apply's fast multipole structure:
+   * 0 translated (target, source) pairs, 1 their mean source order, 2 their mean local
+   * order, 3 local expansions, 4 parent-to-child translations, 5 near (target node, source
+   * node) pairs, 6 (target node, far source) pairs evaluated directly, 7 bytes of the
+   * translation tables */
+  double apply_stats[8];
 } pmx_info;
 
 typedef struct pmx_factor pmx_factor;

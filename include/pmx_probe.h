@@ -84,6 +84,17 @@ pmx_status pmx_probe_mlp(int32_t nin, int32_t nhidden, int32_t nlayer, int32_t n
                          const float* X, const float* labels, int32_t B, float wmse, float* out, float* grad,
                          double* loss, void* stream);
 
+/* Host only (no GPU work): the operator apply's structure for the refinement residual of a
+ * geometry, built as a factor's first solve builds it (plan, target waves, dual tree walk
+ * of the fast multipole part, the waves' walks).  stats [16]: 0-7 as pmx_info.apply_stats;
+ * 8 the longest translation list of a local expansion, 9 the mean; 10 the longest far list
+ * and 11 the longest near list of a wave; 12 with check != 0 the number of (wave, source
+ * inclusion) pairs not taken exactly once (near, through a far source of the wave, or
+ * through a translation into the wave's inclusion or an ancestor; none for the wave's own
+ * inclusion), else -1; 13 waves; 14 the largest local order; 15 pairs checked. */
+pmx_status pmx_probe_apply_structure(const pmx_geometry* geom, const pmx_options* opts, int32_t check,
+                                     double* stats);
+
 /* The quadtree plan, host only (no GPU): per level the number of cells; per cell its
  * centre, radius, proxy radius, proxy count and near list.  Buffers (host) are filled up
  * to their capacity; *n_levels, *n_cells_total and *n_near_total report the sizes

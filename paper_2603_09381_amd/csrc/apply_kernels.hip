@@ -407,6 +407,285 @@ __global__ __launch_bounds__(512) void k_apply_m2m(ApplyArgs A, int c0) {
   }
 }
 
+// ---------------------------------------------------------------------------------
+// Fast multipole part.  With O_n(v) = H_n(k|v|) e^{i n arg v} and I_m(v) = J_m(k|v|)
+// e^{i m arg v}, Graf's addition theorem gives, for |u| < |D|,
+//   O_n(u + D) = sum_m O_{n-m}(D) I_m(u)                         (M2L)
+// and, for all u, d,  I_m(u + d) = sum_l I_{m-l}(d) I_l(u)         (L2L).
+// A source's field sum_n X_n O_n(x - c_S) (X = A for value rows, B for derivative rows)
+// is therefore sum_m L_m I_m(x - c_T) near c_T with L_m = sum_n O_{n-m}(c_T - c_S) X_n,
+// a local expansion passes to a child as L'_l = sum_m I_{m-l}(c_C - c_P) L_m, and at a
+// target  val = (i/4) sum_m L^A_m I_m,  der = (i/4)(k/2) sum_m I_m (nu L^B_{m+1} -
+// conj(nu) L^B_{m-1})  (the normal derivative of I_m is (k/2)(nu I_{m-1} - conj(nu) I_{m+1})).
+
+// X_n (X = 0: A, 1: B) of source record rec for right-hand side rr (layout of the records
+// written by p2m and m2m: per order row m, A_m, A_-m, B_m+1, B_-m+1, B_m-1, B_-m-1, where
+// row 0 holds zeros in its -m entries); |n| <= the source's record order - 1 for A, and
+// 1 - n <= that order - 1 for B with n <= 0.
+template <int NR>
+__device__ inline zd rec_coef(const double* __restrict__ rec, int X, int n, int rr) {
+  int row, slot;
+  if (X == 0) {
+    row = n >= 0 ? n : -n;
+    slot = n >= 0 ? 0 : 1;
+  } else {   // B_n: the B_{m+1} entry of row n - 1, or for n <= 0 the B_{-m+1} entry of row 1 - n
+    row = n >= 1 ? n - 1 : 1 - n;
+    slot = n >= 1 ? 2 : 3;
+  }
+  const double* c = rec + ((int64_t)row * NR + rr) * 12 + 2 * slot;
+  return zmk(c[0], c[1]);
+}
+
+// O_nu(D), nu = -V .. V, of every M2L pair (one thread per pair): H0, H1 of k|D|, the
+// upward recurrence H_{nu+1} = (2 nu / z) H_nu - H_{nu-1} (stable for the Hankel function),
+// O_-nu = (-1)^nu H_nu e^{-i nu phi}.
+__global__ __launch_bounds__(256) void k_apply_m2l_tab(ApplyArgs A, int n_pairs) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n_pairs) return;
+  const int t = A.m2l_slot[q], S = A.m2l_src[q];
+  const int V = A.m2l_mmax[q] + 1 + A.m2l_nmax[q];
+  const double dx = A.loc_geo[2 * t] - A.incl_geo[4 * S], dy = A.loc_geo[2 * t + 1] - A.incl_geo[4 * S + 1];
+  const double z = A.k * sqrt(dx * dx + dy * dy), phi = atan2(dy, dx);
+  const bes4 h = bessel01_mid(z);
+  zd* out = A.m2l_tab + A.m2l_toff[q] + V;
+  double hcr = h.j0, hci = h.y0, hpr = -h.j1, hpi = -h.y1;   // H_0, H_{-1} = -H_1
+  const double iz2 = 2.0 / z;
+  for (int nu = 0; nu <= V; ++nu) {
+    double sn, cs;
+    sincos(nu * phi, &sn, &cs);
+    out[nu] = zmk(hcr * cs - hci * sn, hcr * sn + hci * cs);
+    if (nu > 0) {
+      const double sg = (nu & 1) ? -1.0 : 1.0;
+      out[-nu] = zmk(sg * (hcr * cs + hci * sn), sg * (hci * cs - hcr * sn));
+    }
+    double hnr = nu * iz2 * hcr - hpr, hni = nu * iz2 * hci - hpi;
+    if (nu == 0) {
+      hnr = h.j1;
+      hni = h.y1;
+    }
+    hpr = hcr;
+    hpi = hci;
+    hcr = hnr;
+    hci = hni;
+  }
+}
+
+// I_nu(d), nu = -W .. W, of every L2L pair (one thread per pair): J_nu(k|d|) by Miller's
+// backward recurrence (rescaled against overflow, normalised by J_0 + 2 sum J_2k = 1).
+__global__ __launch_bounds__(256) void k_apply_l2l_tab(ApplyArgs A, int n_pairs) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= n_pairs) return;
+  const int c = A.l2l_child[q], P = A.l2l_parent[q];
+  const int W = A.loc_p[P] + A.loc_p[c] + 2;
+  const double dx = A.loc_geo[2 * c] - A.loc_geo[2 * P], dy = A.loc_geo[2 * c + 1] - A.loc_geo[2 * P + 1];
+  const double z = A.k * sqrt(dx * dx + dy * dy), phi = atan2(dy, dx);
+  zd* out = A.l2l_tab + A.l2l_toff[q] + W;
+  if (!(z > 1e-300)) {   // coincident centres (a cluster with one child): the identity
+    for (int nu = -W; nu <= W; ++nu) out[nu] = zmk(nu == 0 ? 1.0 : 0.0, 0.0);
+    return;
+  }
+  const int nstart = W + 30 + (int)ceil(z);
+  const double iz2 = 2.0 / z;
+  double jp = 0.0, jc = 1e-280, nrm = 0.0;
+  for (int m = nstart; m >= 1; --m) {
+    const double jm = m * iz2 * jc - jp;   // J_{m-1}, unnormalised
+    jp = jc;
+    jc = jm;
+    if (m - 1 <= W) out[m - 1] = zmk(jc, 0.0);
+    if (((m - 1) & 1) == 0) nrm += (m - 1 == 0) ? jc : 2.0 * jc;
+    if (fabs(jc) > 1e200) {   // rescale everything kept so far
+      jp *= 1e-200;
+      jc *= 1e-200;
+      nrm *= 1e-200;
+      for (int nu = m - 1; nu <= W; ++nu) out[nu].re *= 1e-200;
+    }
+  }
+  const double inv = 1.0 / nrm;
+  for (int nu = 0; nu <= W; ++nu) {
+    const double J = out[nu].re * inv;
+    double sn, cs;
+    sincos(nu * phi, &sn, &cs);
+    out[nu] = zmk(J * cs, J * sn);
+    if (nu > 0) {
+      const double sg = (nu & 1) ? -J : J;
+      out[-nu] = zmk(sg * cs, -sg * sn);
+    }
+  }
+}
+
+void asm_apply_tables(const ApplyArgs& a, int n_m2l, int n_l2l, hipStream_t s) {
+  if (n_m2l > 0)
+    hipLaunchKernelGGL(k_apply_m2l_tab, dim3((n_m2l + 255) / 256), dim3(256), 0, s, a, n_m2l);
+  if (n_l2l > 0)
+    hipLaunchKernelGGL(k_apply_l2l_tab, dim3((n_l2l + 255) / 256), dim3(256), 0, s, a, n_l2l);
+}
+
+// The translated sources' coefficients in the layout the m2l kernel reads: per source,
+// X (A, B), order n = -PMX_FMM_NMAX .. PMX_FMM_NMAX and right-hand side, contiguous in the
+// right-hand side (one thread per entry; sources with expansion records only).
+constexpr int M2L_NX = 2 * PMX_FMM_NMAX + 1;                        // orders of a source
+
+template <int NR>
+__global__ __launch_bounds__(256) void k_apply_m2l_coef(ApplyArgs A, const double* __restrict__ cf, int nsrc) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)nsrc * 2 * M2L_NX * NR) return;
+  const int rr = (int)(e % NR);
+  const int n = (int)((e / NR) % M2L_NX) - PMX_FMM_NMAX;
+  const int X = (int)((e / (NR * M2L_NX)) % 2);
+  const int S = (int)(e / (2 * NR * M2L_NX));
+  const double* rec = cf + (int64_t)S * PMX_APPLY_NRECA * NR * 12;
+  A.cm[e] = rec_coef<NR>(rec, X, n, rr);
+}
+
+// Part of a local expansion: the translated sources of work item blockIdx.x (a run of at
+// most PMX_FMM_CHUNK pairs of one slot), one wave, into the item's partial sums.  Lane l holds
+// the order m = l - 32 in pass 0, and m = 32 + l (l < 32) or l - 96 (l >= 32) in pass 1,
+// of A and B for every right-hand side; a pair with orders |m| <= mmax + 1 runs pass 1 only
+// when mmax + 1 >= 32.  Per pair the wave stages its table O_nu in LDS (read per lane);
+// the source's coefficients A_n, B_n (|n| <= nmax) are wave-uniform (scalar loads).
+constexpr int M2L_TAB = 2 * (PMX_FMM_PL + 1 + PMX_FMM_NMAX) + 1;   // largest table
+
+template <int NR>
+__global__ __launch_bounds__(64) void k_apply_m2l(ApplyArgs A) {
+  __shared__ zd tab_s[M2L_TAB];
+  const int it = blockIdx.x;
+  const int t = A.m2l_item[3 * it];
+  const int lane = threadIdx.x;
+  const int p = A.loc_p[t];
+  const int q0 = A.m2l_item[3 * it + 1], q1 = A.m2l_item[3 * it + 2];
+  const int mj[2] = {lane - 32, lane < 32 ? lane + 32 : lane - 96};
+  zd* loc = A.m2l_part + (int64_t)it * 2 * PMX_FMM_NL * NR;
+  double ar[2][2][NR], ai[2][2][NR];
+#pragma unroll
+  for (int X = 0; X < 2; ++X)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr) ar[X][j][rr] = ai[X][j][rr] = 0.0;
+  for (int q = q0; q < q1; ++q) {
+    const int S = A.m2l_src[q], nmax = A.m2l_nmax[q], mm = A.m2l_mmax[q] + 1;
+    const int V = mm + nmax;
+    const zd* tab = A.m2l_tab + A.m2l_toff[q];
+    const zd* xa = A.cm + ((int64_t)S * 2 * M2L_NX + PMX_FMM_NMAX) * NR;   // A_n at xa[n NR + rr]
+    const zd* xb = xa + (int64_t)M2L_NX * NR;                             // B_n
+    __syncthreads();   // the previous pair's table is read no more
+    for (int e = lane; e < 2 * V + 1; e += 64) tab_s[e] = tab[e];
+    __syncthreads();
+    const int npass = mm >= 32 ? 2 : 1;
+    bool ok[2];
+    int mc[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      ok[j] = mj[j] >= -mm && mj[j] <= mm;
+      mc[j] = min(max(mj[j], -mm), mm);   // lanes outside the pair's orders read a valid entry and add 0
+    }
+#pragma unroll(NR <= 4 ? 2 : 1)
+    for (int n = -nmax; n <= nmax; ++n) {
+      zd x[2][NR];
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr) {
+        x[0][rr] = xa[n * NR + rr];
+        x[1][rr] = xb[n * NR + rr];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        if (j < npass) {
+          zd o = tab_s[n - mc[j] + V];
+          if (!ok[j]) o = zmk(0.0, 0.0);
+#pragma unroll
+          for (int X = 0; X < 2; ++X)
+#pragma unroll
+            for (int rr = 0; rr < NR; ++rr) {
+              ar[X][j][rr] = fma(o.re, x[X][rr].re, fma(-o.im, x[X][rr].im, ar[X][j][rr]));
+              ai[X][j][rr] = fma(o.re, x[X][rr].im, fma(o.im, x[X][rr].re, ai[X][j][rr]));
+            }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int m = mj[j];
+    if (m >= -(p + 1) && m <= p + 1) {
+#pragma unroll
+      for (int X = 0; X < 2; ++X)
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr)
+          loc[((int64_t)X * PMX_FMM_NL + (m + PMX_FMM_PL + 1)) * NR + rr] = zmk(ar[X][j][rr], ai[X][j][rr]);
+    }
+  }
+}
+
+// Local expansions from their items' partial sums, added in item order (one thread per
+// slot, X, order |m| <= p + 1 and right-hand side).
+template <int NR>
+__global__ __launch_bounds__(256) void k_apply_m2l_sum(ApplyArgs A) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)A.n_loc * 2 * PMX_FMM_NL * NR) return;
+  const int rr = (int)(e % NR);
+  const int mi = (int)((e / NR) % PMX_FMM_NL);
+  const int X = (int)((e / (NR * PMX_FMM_NL)) % 2);
+  const int t = (int)(e / (2 * NR * PMX_FMM_NL));
+  const int p = A.loc_p[t];
+  const int m = mi - (PMX_FMM_PL + 1);
+  if (m < -(p + 1) || m > p + 1) return;
+  const int i0 = A.m2l_item_off[t], i1 = A.m2l_item_off[t + 1];
+  const int64_t o = ((int64_t)X * PMX_FMM_NL + mi) * NR + rr;
+  zd acc = zmk(0.0, 0.0);
+  for (int it = i0; it < i1; ++it) acc = zadd(acc, A.m2l_part[(int64_t)it * 2 * PMX_FMM_NL * NR + o]);
+  A.loc[(int64_t)t * 2 * PMX_FMM_NL * NR + o] = acc;
+}
+
+// Parent-to-child translations of one tree level (one wave per child): L^C_l += sum_m
+// I_{m-l}(c_C - c_P) L^P_m for |l| <= p_C + 1, |m| <= p_P + 1.
+template <int NR>
+__global__ __launch_bounds__(64) void k_apply_l2l(ApplyArgs A, int q0) {
+  const int q = q0 + blockIdx.x;
+  const int c = A.l2l_child[q], P = A.l2l_parent[q];
+  const int lane = threadIdx.x;
+  const int pc = A.loc_p[c], pp = A.loc_p[P];
+  const int W = pp + pc + 2;
+  const int npass = (2 * pc + 3 + 63) / 64;
+  const zd* tab = A.l2l_tab + A.l2l_toff[q] + W;
+  zd* lc = A.loc + (int64_t)c * 2 * PMX_FMM_NL * NR;
+  const zd* lp = A.loc + (int64_t)P * 2 * PMX_FMM_NL * NR;
+  for (int X = 0; X < 2; ++X) {
+    double ar[3][NR], ai[3][NR];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr) ar[j][rr] = ai[j][rr] = 0.0;
+    for (int m = -(pp + 1); m <= pp + 1; ++m) {
+      zd x[NR];
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr) x[rr] = lp[((int64_t)X * PMX_FMM_NL + (m + PMX_FMM_PL + 1)) * NR + rr];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        if (j < npass) {
+          const int l = min(-(pc + 1) + lane + 64 * j, pc + 1);
+          const zd o = tab[m - l];
+#pragma unroll
+          for (int rr = 0; rr < NR; ++rr) {
+            ar[j][rr] = fma(o.re, x[rr].re, fma(-o.im, x[rr].im, ar[j][rr]));
+            ai[j][rr] = fma(o.re, x[rr].im, fma(o.im, x[rr].re, ai[j][rr]));
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int l = -(pc + 1) + lane + 64 * j;
+      if (j < npass && l <= pc + 1) {
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) {
+          zd* o = lc + ((int64_t)X * PMX_FMM_NL + (l + PMX_FMM_PL + 1)) * NR + rr;
+          *o = zadd(*o, zmk(ar[j][rr], ai[j][rr]));
+        }
+      }
+    }
+  }
+}
+
 // Far part: part blockIdx.y of the wave's list of far sources (inclusions and clusters),
 // each through its expansion: per lane rho, th of the target about the source's centre, H0
 // and H1 (large-argument expansion when the whole wave allows it), then orders m = 0 .. p+1
@@ -416,12 +695,12 @@ __global__ __launch_bounds__(512) void k_apply_m2m(ApplyArgs A, int c0) {
 // derivative rows once at the end.
 template <int NR>
 __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __restrict__ cf, int r0) {
-  const int N = A.n_nodes;
-  const int a_raw = blockIdx.x * 256 + threadIdx.x;
-  const bool active = a_raw < N;
-  const int a = active ? a_raw : N - 1;   // idle lanes follow the last node and write nothing
-  const int wv = __builtin_amdgcn_readfirstlane(a_raw >> 6);
-  if (wv >= (N + 63) / 64) return;        // a wave past the last target (no barrier follows)
+  const int wv = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * 256 + threadIdx.x) >> 6));
+  if (wv >= A.n_waves) return;            // a wave past the last target (no barrier follows)
+  const int lane = threadIdx.x & 63;
+  const int w0 = A.wave_node[2 * wv], wn = A.wave_node[2 * wv + 1];
+  const bool active = lane < wn;
+  const int a = w0 + (active ? lane : wn - 1);   // idle lanes follow the wave's last node and write nothing
   const int nr = min(NR, A.nrhs - r0);
   const double ax = A.x[a], ay = A.y[a], anx = A.nx[a], any = A.ny[a];
   const double k = A.k, ik = 1.0 / k;
@@ -499,6 +778,90 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
       Emr = t;
     }
   }
+  // the local expansion of the wave's inclusion (part 0 only): I_m(x - c_T) = J_m e^{i m th}
+  // with J_m by Miller's backward recurrence (a first pass for the norm J_0 + 2 sum J_2k),
+  // accumulated from the top order down, as S1 and S2 above with I_m in place of O_m
+  const int own = A.owner[w0];
+  const int slot = A.loc_id[own];
+  if (blockIdx.y == 0 && slot >= 0) {
+    const int p = A.loc_p[slot];
+    const zd* L = A.loc + (int64_t)slot * 2 * PMX_FMM_NL * NR;
+    const double ux = ax - A.loc_geo[2 * slot], uy = ay - A.loc_geo[2 * slot + 1];
+    const double rho = fmax(sqrt(ux * ux + uy * uy), 1e-300);
+    const double z = k * rho;
+    const double er = ux / rho, ei = uy / rho;   // e^{i th}
+    const int nstart = __builtin_amdgcn_readfirstlane(p + 26 + (int)ceil(k * wr + k * sqrt((wcx - A.loc_geo[2 * slot]) *
+                                                                                   (wcx - A.loc_geo[2 * slot]) +
+                                                                               (wcy - A.loc_geo[2 * slot + 1]) *
+                                                                                   (wcy - A.loc_geo[2 * slot + 1]))));
+    const double iz2 = 2.0 / fmax(z, 1e-300);
+    double jp = 0.0, jc = 1e-280, nrm = (nstart % 2 == 0) ? 2.0 * jc : 0.0;
+    for (int m = nstart; m >= 1; --m) {
+      const double jm = m * iz2 * jc - jp;
+      jp = jc;
+      jc = jm;
+      if (((m - 1) & 1) == 0) nrm += (m - 1 == 0) ? jm : 2.0 * jm;
+    }
+    const double inv = (z > 1e-12) ? 1.0 / nrm : 0.0;
+    // e^{i p th} by repeated squaring, then stepped down
+    double Er = 1.0, Ei = 0.0, br = er, bi = ei;
+    for (int e = p; e > 0; e >>= 1) {
+      if (e & 1) {
+        const double t = Er * br - Ei * bi;
+        Ei = Er * bi + Ei * br;
+        Er = t;
+      }
+      const double t = br * br - bi * bi;
+      bi = 2.0 * br * bi;
+      br = t;
+    }
+    jp = 0.0;
+    jc = 1e-280;
+    for (int m = nstart; m >= 0; --m) {
+      if (m <= p) {
+        // J_m; at the centre itself only J_0 = 1 survives
+        const double Jm = (z > 1e-12) ? jc * inv : (m == 0 ? 1.0 : 0.0);
+        const double sg = (m & 1) ? -1.0 : 1.0;
+        const double Ipr = Jm * Er, Ipi = Jm * Ei;                 // I_m
+        const double Imr = sg * Jm * Er, Imi = -sg * Jm * Ei;      // I_-m
+        const zd* la = L + (int64_t)(m + PMX_FMM_PL + 1) * NR;                   // L^A_m
+        const zd* lna = L + (int64_t)(-m + PMX_FMM_PL + 1) * NR;                 // L^A_-m
+        const zd* lb = L + (int64_t)(PMX_FMM_NL + m + PMX_FMM_PL + 1) * NR;      // L^B_m
+        const zd* lnb = L + (int64_t)(PMX_FMM_NL - m + PMX_FMM_PL + 1) * NR;     // L^B_-m
+#pragma unroll
+        for (int rr = 0; rr < NR; ++rr) {
+          zd c = la[rr];
+          vr[rr] = fma(Ipr, c.re, fma(-Ipi, c.im, vr[rr]));
+          vi[rr] = fma(Ipr, c.im, fma(Ipi, c.re, vi[rr]));
+          c = lb[NR + rr];   // L^B_{m+1}
+          s1r[rr] = fma(Ipr, c.re, fma(-Ipi, c.im, s1r[rr]));
+          s1i[rr] = fma(Ipr, c.im, fma(Ipi, c.re, s1i[rr]));
+          c = lb[-NR + rr];  // L^B_{m-1}
+          s2r[rr] = fma(Ipr, c.re, fma(-Ipi, c.im, s2r[rr]));
+          s2i[rr] = fma(Ipr, c.im, fma(Ipi, c.re, s2i[rr]));
+          if (m > 0) {
+            c = lna[rr];
+            vr[rr] = fma(Imr, c.re, fma(-Imi, c.im, vr[rr]));
+            vi[rr] = fma(Imr, c.im, fma(Imi, c.re, vi[rr]));
+            c = lnb[NR + rr];   // L^B_{-m+1}
+            s1r[rr] = fma(Imr, c.re, fma(-Imi, c.im, s1r[rr]));
+            s1i[rr] = fma(Imr, c.im, fma(Imi, c.re, s1i[rr]));
+            c = lnb[-NR + rr];  // L^B_{-m-1}
+            s2r[rr] = fma(Imr, c.re, fma(-Imi, c.im, s2r[rr]));
+            s2i[rr] = fma(Imr, c.im, fma(Imi, c.re, s2i[rr]));
+          }
+        }
+        // e^{i (m-1) th} = e^{i m th} e^{-i th}
+        const double t = Er * er + Ei * ei;
+        Ei = Ei * er - Er * ei;
+        Er = t;
+      }
+      if (m == 0) break;
+      const double jm = m * iz2 * jc - jp;
+      jp = jc;
+      jc = jm;
+    }
+  }
   if (!active) return;
   // der = (k/2)(nu S1 - conj(nu) S2)
   const double hk = 0.5 * k;
@@ -517,11 +880,10 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
 template <int NR>
 __global__ __launch_bounds__(64) void k_apply_near(ApplyArgs A, const double* __restrict__ pk, int r0, int slot0) {
   constexpr int S = APPLY_SRC(NR);
-  const int N = A.n_nodes;
   const int wv = blockIdx.x;
-  const int a_raw = wv * 64 + threadIdx.x;
-  const bool active = a_raw < N;
-  const int a = active ? a_raw : N - 1;
+  const int w0 = A.wave_node[2 * wv], wn = A.wave_node[2 * wv + 1];
+  const bool active = (int)threadIdx.x < wn;
+  const int a = w0 + (active ? (int)threadIdx.x : wn - 1);
   const int nr = min(NR, A.nrhs - r0);
   const double ax = A.x[a], ay = A.y[a], anx = A.nx[a], any = A.ny[a];
   const int aown = A.owner[a];
@@ -583,6 +945,8 @@ int64_t apply_pack_size(int n_nodes, int nr_max) { return (int64_t)n_nodes * APP
 
 int64_t apply_coef_size(int n_src, int nr_max) { return (int64_t)n_src * PMX_APPLY_NRECA * nr_max * 6; }
 
+int64_t apply_m2l_coef_size(int n_src, int nr_max) { return (int64_t)n_src * 2 * M2L_NX * nr_max; }
+
 int apply_source_order(double kr) {
   for (int p = 1; p < 1000; ++p)
     if (p > 0.5 * M_E * kr + 2 && std::pow(0.5 * M_E * kr / p, p) <= 1e-17) return p;
@@ -597,24 +961,59 @@ static void apply_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipS
   for (int l = 0; l < A.n_lev; ++l)
     if (A.lev_off[l + 1] > A.lev_off[l])
       hipLaunchKernelGGL(k_apply_m2m<NR>, dim3(A.lev_off[l + 1] - A.lev_off[l]), dim3(512), 0, s, A, A.lev_off[l]);
-  hipLaunchKernelGGL(k_apply_far<NR>, dim3((A.n_nodes + 255) / 256, nsplit), dim3(256), 0, s, A,
-                     (const double*)A.coef, r0);
-  hipLaunchKernelGGL(k_apply_near<NR>, dim3((A.n_nodes + 63) / 64, A.nsplit_near), dim3(64), 0, s, A,
-                     (const double*)pk, r0, nsplit);
+  if (A.n_loc > 0) {
+    const int nsrc = A.n_incl + A.lev_off[A.n_lev];   // sources with expansion records
+    const int64_t ncm = (int64_t)nsrc * 2 * M2L_NX * NR;
+    hipLaunchKernelGGL(k_apply_m2l_coef<NR>, dim3((unsigned)((ncm + 255) / 256)), dim3(256), 0, s, A,
+                       (const double*)A.coef, nsrc);
+    if (A.n_m2l_items > 0) hipLaunchKernelGGL(k_apply_m2l<NR>, dim3(A.n_m2l_items), dim3(64), 0, s, A);
+    const int64_t nl = (int64_t)A.n_loc * 2 * PMX_FMM_NL * NR;
+    hipLaunchKernelGGL(k_apply_m2l_sum<NR>, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s, A);
+    for (int l = 0; l < A.n_l2l_lev; ++l)
+      if (A.l2l_lev[l + 1] > A.l2l_lev[l])
+        hipLaunchKernelGGL(k_apply_l2l<NR>, dim3(A.l2l_lev[l + 1] - A.l2l_lev[l]), dim3(64), 0, s, A, A.l2l_lev[l]);
+  }
+  hipLaunchKernelGGL(k_apply_far<NR>, dim3((A.n_waves + 3) / 4, nsplit), dim3(256), 0, s, A, (const double*)A.coef,
+                     r0);
 }
 
-// right-hand sides in groups of nr_max (1, 2, 4 or 8); a last smaller group takes the
-// smallest of those sizes that holds it
+// near pairs of a group of right-hand sides (the Bessel functions of a pair are evaluated
+// once per group, so the near part takes the largest groups)
+template <int NR>
+static void near_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipStream_t s) {
+  hipLaunchKernelGGL(k_apply_pack<NR>, dim3((A.n_nodes + 255) / 256), dim3(256), 0, s, A, r0, pk);
+  hipLaunchKernelGGL(k_apply_near<NR>, dim3(A.n_waves, A.nsplit_near), dim3(64), 0, s, A, (const double*)pk, r0,
+                     nsplit);
+}
+
+// groups of g right-hand sides: g = nr_max while enough remain; a last smaller group takes
+// the smallest size of 1, 2, 4, 8 (16 for the near part) that holds it
+static int group_size(int left, int nr_max) {
+  return left >= nr_max ? nr_max : (left <= 1 ? 1 : left <= 2 ? 2 : left <= 4 ? 4 : left <= 8 ? 8 : 16);
+}
+
+// expansions, translations and far parts in groups of nr_max (1, 2, 4 or 8) right-hand
+// sides, then the near parts in groups of up to PMX_APPLY_NR_NEAR
 void asm_apply_off(const ApplyArgs& A, int nsplit, int nr_max, hipStream_t s) {
   if (A.n_nodes <= 0 || A.nrhs <= 0) return;
   for (int r0 = 0; r0 < A.nrhs;) {
-    const int left = A.nrhs - r0;
-    const int g = left >= nr_max ? nr_max : (left <= 1 ? 1 : left <= 2 ? 2 : left <= 4 ? 4 : 8);
+    const int g = group_size(A.nrhs - r0, nr_max);
     switch (g) {
       case 1: apply_group<1>(A, A.pack, r0, nsplit, s); break;
       case 2: apply_group<2>(A, A.pack, r0, nsplit, s); break;
       case 4: apply_group<4>(A, A.pack, r0, nsplit, s); break;
       default: apply_group<8>(A, A.pack, r0, nsplit, s); break;
+    }
+    r0 += g;
+  }
+  for (int r0 = 0; r0 < A.nrhs;) {
+    const int g = group_size(A.nrhs - r0, PMX_APPLY_NR_NEAR);
+    switch (g) {
+      case 1: near_group<1>(A, A.pack, r0, nsplit, s); break;
+      case 2: near_group<2>(A, A.pack, r0, nsplit, s); break;
+      case 4: near_group<4>(A, A.pack, r0, nsplit, s); break;
+      case 8: near_group<8>(A, A.pack, r0, nsplit, s); break;
+      default: near_group<16>(A, A.pack, r0, nsplit, s); break;
     }
     r0 += g;
   }

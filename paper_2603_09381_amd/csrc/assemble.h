@@ -150,15 +150,22 @@ void asm_build_l(const LDescT<R>* d, int batch, int max_s, int max_k, hipStream_
 void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s);
 // Dense FP64 operator apply between different inclusions (exterior kernels), for a block
 // of right-hand sides in the density layout (ld = 2 n_nodes, per inclusion [q; u]).
-// Targets are taken in waves of 64 consecutive nodes.  Sources are the inclusions and the
-// clusters of the plan's tree above them (source index: inclusions first, then the
-// clusters level by level upwards).  Every source has a multipole expansion about its
-// centre (Graf's addition theorem): an inclusion's coefficients come from its nodes (p2m
-// kernel), a cluster's from its children's by the regular translation (m2m kernel, one
-// launch per tree level).  Each wave has two host-built lists, from a walk down the tree:
-// far sources, taken through their expansions to the order the distance needs (far
-// kernel, the list split in nsplit parts), and near inclusions, applied pair by pair (near
-// kernel, split in nsplit_near parts, same-inclusion pairs left out).  A cluster is far
+// Targets are taken in waves of at most 64 consecutive nodes of one inclusion.  Tree
+// nodes are the inclusions and the clusters of the plan's tree above them (index:
+// inclusions first, then the clusters level by level upwards); each has a bounding circle.
+// Every tree node is a source with a multipole expansion about its centre (Graf's addition
+// theorem): an inclusion's coefficients come from its nodes (p2m kernel), a cluster's from
+// its children's by the regular translation (m2m kernel, one launch per tree level).
+// Far field (fast multipole method): a dual walk down the tree pairs target and source
+// nodes; a pair whose circles are well separated ((r~_T + r_S) <= PMX_FMM_RATIO |c_T - c_S|,
+// r~_T the radius about c_T of every circle below T) is translated into the target's
+// local expansion (m2l kernel, with the pair's table of O_nu(c_T - c_S) made once per
+// solve state); local expansions move down the tree (l2l kernel, one launch per level)
+// and are evaluated at the target nodes (inside the far kernel).  Pairs left over at an
+// inclusion (too close for a translation) start each of its waves' walks: far sources,
+// taken through their expansions to the order the distance needs (far kernel, the list
+// split in nsplit parts), and near inclusions, applied pair by pair (near kernel, split in
+// nsplit_near parts, same-inclusion pairs left out).  In a wave's walk a cluster is far
 // when its centre is farther than PMX_APPLY_RATIO cluster radii from the wave's circle and
 // PMX_APPLY_PMAXC orders suffice; otherwise its children are examined.  An inclusion
 // reached that way is near when its centre is closer than PMX_APPLY_RATIO radii or its
@@ -177,6 +184,18 @@ void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s);
 #define PMX_APPLY_NREC (PMX_APPLY_PMAX + 2)
 #define PMX_APPLY_NRECA (PMX_APPLY_PMAXC + 2)
 #define PMX_APPLY_MAXLEV 32
+#ifndef PMX_APPLY_NR_NEAR
+#define PMX_APPLY_NR_NEAR 8   // right-hand sides per group of the near part (8 or 16)
+#endif
+// fast multipole part: separation ratio of a translated pair, largest local order, and the
+// local-expansion orders kept per target (m = -(PMX_FMM_PL + 1) .. PMX_FMM_PL + 1)
+#ifndef PMX_FMM_RATIO
+#define PMX_FMM_RATIO (1.0 / 3.0)
+#endif
+#define PMX_FMM_PL 62     // at most 62: the m2l kernel's two passes hold orders -64 .. 63
+#define PMX_FMM_NMAX 48   // largest source order of a translated pair
+#define PMX_FMM_CHUNK 32  // translated pairs per work item of the m2l kernel
+#define PMX_FMM_NL (2 * PMX_FMM_PL + 3)
 struct ApplyArgs {
   const double *x, *y, *nx, *ny, *w;
   const int* owner;
@@ -201,7 +220,38 @@ struct ApplyArgs {
   int n_incl, n_clus;
   int n_lev;             // cluster levels; level l holds clusters lev_off[l] .. lev_off[l + 1] - 1
   int lev_off[PMX_APPLY_MAXLEV + 1];
+  const int* wave_node;  // [n_waves][2]: first node and node count of each target wave
+  int n_waves;
+  // fast multipole part
+  zd* loc;               // [n_loc][2][PMX_FMM_NL][nr] local expansions (A, B) of one group
+  zd* cm;                // [n_src][2][2 PMX_FMM_NMAX + 1][nr] translated sources' A_n, B_n
+  const int* loc_id;     // [n_src] slot in loc of each tree node, -1: no local expansion
+  const int* loc_p;      // [n_loc] order of each local expansion
+  const double* loc_geo; // [n_loc][2] its centre
+  int n_loc;
+  const int* m2l_item;   // [n_m2l_items][3]: slot, first and last + 1 pair of each work item
+  const int* m2l_item_off;  // [n_loc + 1] work items of each local expansion
+  int n_m2l_items;
+  zd* m2l_part;          // [n_m2l_items][2][PMX_FMM_NL][nr] partial local expansions
+  const int* m2l_off;    // [n_loc + 1] translated sources of each local expansion
+  const int* m2l_slot;   // local-expansion slot of each pair
+  const int* m2l_src;    // source tree node of each pair
+  const int* m2l_nmax;   // source order of each pair
+  const int* m2l_mmax;   // local order of each pair (<= the slot's order)
+  const int64_t* m2l_toff;  // offset of the pair's table O_nu(c_T - c_S), nu = -V .. V,
+                            // V = mmax + 1 + nmax (complex entries)
+  zd* m2l_tab;
+  const int* l2l_child;  // [n_l2l] child slot of each parent-to-child translation, grouped
+  const int* l2l_parent; //   by level from the top (l2l_lev[l] .. l2l_lev[l + 1] - 1)
+  const int64_t* l2l_toff;  // offset of the pair's table I_nu(c_C - c_P), nu = -W .. W,
+                            // W = p_P + p_C + 2
+  zd* l2l_tab;
+  int n_l2l_lev;
+  int l2l_lev[PMX_APPLY_MAXLEV + 2];
 };
+// tables of the translations (once per solve state): O_nu(D) of every M2L pair and
+// I_nu(d) of every L2L pair
+void asm_apply_tables(const ApplyArgs& a, int n_m2l, int n_l2l, hipStream_t s);
 // orders needed for the sources of an inclusion of radius r: the smallest p with
 // (e k r / 2p)^p <= 1e-17 and p > e k r / 2 + 2
 int apply_source_order(double kr);
@@ -213,6 +263,8 @@ int apply_near_splits(int n_nodes, int wg_target);
 int64_t apply_pack_size(int n_nodes, int nr_max);
 // complex entries of the expansion records for groups of up to nr_max right-hand sides
 int64_t apply_coef_size(int n_src, int nr_max);
+// complex entries of the translated sources' coefficients (m2l layout), the same groups
+int64_t apply_m2l_coef_size(int n_src, int nr_max);
 // partial sums of the off-diagonal operator (far ranges, then near parts), right-hand
 // sides in groups of nr_max (1, 2, 4, 8) per thread
 void asm_apply_off(const ApplyArgs& a, int nsplit, int nr_max, hipStream_t s);

@@ -22,6 +22,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <future>
 #include <map>
 #include <memory>
@@ -876,7 +877,7 @@ void id_stage(pmx_factor* F, const LevelData<R>& L, const std::vector<CellPlan>&
 // Compress one level whose active sets (L.rows, L.cols, s0, s1) and blocks D are set.
 template <class R>
 void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>& cells, const LearnedPlan* lp,
-                    hipStream_t s) {
+                    bool leaf, hipStream_t s) {
   const int nc = L.ncell;
   const double tol = F->opts.id_tol;
   Arena tmp(&F->pool);
@@ -884,7 +885,9 @@ void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>&
   // ---- the four interpolative decompositions of every cell (learned proposals first at
   // the leaves when a model is loaded, the full CPQR for every cell they do not settle)
   IdOut<R> io;
+  const double ti = now_ms();
   id_stage<R>(F, L, cells, PT, lp, io, tmp, s);
+  if (leaf) F->info.t_phase_ms[7] += now_ms() - ti;   // id_stage ends with its ranks downloaded
   F->info.id_learned += io.learned;
   F->info.id_fallback += io.fallback;
   const std::vector<int>& kq = io.kq;
@@ -1355,8 +1358,12 @@ void factor_all(pmx_factor* F, hipStream_t s) {
     const double tc = now_ms();
     LearnedPlan lp;
     const bool learned = (lv == 0 && !F->leaf_pred.empty());
-    if (learned) lp = learned_plan(F, cur.s0);
-    compress_level(F, cur, plan[lv], learned ? &lp : nullptr, s);
+    if (learned) {
+      const double tq = now_ms();
+      lp = learned_plan(F, cur.s0);
+      F->info.t_phase_ms[8] += now_ms() - tq;
+    }
+    compress_level(F, cur, plan[lv], learned ? &lp : nullptr, lv == 0, s);
     F->info.t_phase_ms[1] += now_ms() - tc;
     T.lev.push_back(std::move(cur));
     cur = LevelData<R>();
@@ -1672,6 +1679,7 @@ struct DenseApply {
   int n_src = 0;                  // expansion sources: inclusions and clusters
   double flops_fixed = 0, flops_rhs = 0;   // algorithmic work of one apply (counted with timing)
   double self_sq = 0;             // sum over inclusions of (2 n_j)^2: the FP64 self-block entries
+  double table_bytes = 0;         // translation tables of the fast multipole part
   int64_t total = 0;
   zd *ydiag = nullptr, *part = nullptr;
   double* d_norm = nullptr;
@@ -1702,15 +1710,35 @@ struct ApplyGeo {
   std::vector<int> off, idx;        // near inclusions per wave
   std::vector<int> foff, fidx;      // far sources per wave
   std::vector<double> incl, wave;   // per source (inclusions, then clusters) and per wave
+  std::vector<int> wave_node;       // per wave: first node, node count (one inclusion)
   std::vector<int> kid_off, kid_idx;
   std::vector<int> lev_off;         // clusters of tree level 1, 2, ...: lev_off[l] .. lev_off[l + 1] - 1
   int n_clus = 0;
+  // fast multipole part (see ApplyArgs)
+  std::vector<int> loc_id, loc_p;
+  std::vector<double> loc_geo;
+  std::vector<int> m2l_off, m2l_slot, m2l_src, m2l_nmax, m2l_mmax;
+  std::vector<int64_t> m2l_toff;
+  std::vector<int> l2l_child, l2l_parent, l2l_lev;
+  std::vector<int64_t> l2l_toff;
+  int64_t m2l_tab = 0, l2l_tab = 0;   // complex entries of the translation tables
   double flops_fixed = 0, flops_rhs = 0;
+  double stats[8] = {};               // pmx_info.apply_stats
 };
 
 void apply_geometry(const pmx_factor* F, const std::vector<double>& hx, const std::vector<double>& hy, ApplyGeo& G,
                     bool count) {
-  const int m = F->m, N = F->n_nodes, nw = (N + 63) / 64;
+  const int m = F->m, N = F->n_nodes;
+  // target waves: up to 64 consecutive nodes of one inclusion
+  G.wave_node.clear();
+  std::vector<int> wave_incl;
+  for (int j = 0; j < m; ++j)
+    for (int64_t o = F->node_off[j]; o < F->node_off[j + 1]; o += 64) {
+      G.wave_node.push_back((int)o);
+      G.wave_node.push_back((int)std::min<int64_t>(64, F->node_off[j + 1] - o));
+      wave_incl.push_back(j);
+    }
+  const int nw = (int)G.wave_node.size() / 2;
   const double k = F->k_ext;
   const auto& plan = F->plan;
   // bounding circle of the nodes of the inclusions in `incs` (all nodes of inclusion j: node_off)
@@ -1795,7 +1823,7 @@ void apply_geometry(const pmx_factor* F, const std::vector<double>& hx, const st
   double m2m_terms = 0;
   for (int c = 0; c < G.lev_off.back(); ++c) m2m_terms += cterms[c];
   for (int w = 0; w < nw; ++w) {
-    const int lo = 64 * w, hi = std::min(64 * w + 64, N);
+    const int lo = G.wave_node[2 * w], hi = lo + G.wave_node[2 * w + 1];
     double* g = &G.wave[4 * (size_t)w];
     // the wave's nodes lie in consecutive inclusions: their circle over that node range
     double x0 = hx[lo], x1 = hx[lo], y0 = hy[lo], y1 = hy[lo];
@@ -1811,12 +1839,149 @@ void apply_geometry(const pmx_factor* F, const std::vector<double>& hx, const st
     for (int b = lo; b < hi; ++b) r2 = std::max(r2, (hx[b] - g[0]) * (hx[b] - g[0]) + (hy[b] - g[1]) * (hy[b] - g[1]));
     g[2] = std::sqrt(r2);
   }
-  // the walk: top clusters (or every inclusion when there are none)
+  // tree: parents, the nested radius r~ (about the node's centre, covering every circle
+  // below it), and the top nodes (no parent)
+  const int nsrc_all = m + nc;
+  std::vector<int> parent(nsrc_all, -1), lvl(nsrc_all, 0);
+  for (int c = 0; c < nc; ++c)
+    for (int q = G.kid_off[c]; q < G.kid_off[c + 1]; ++q) parent[G.kid_idx[q]] = m + c;
+  for (int l = 1; l <= nclev; ++l)
+    for (size_t t = 0; t < plan[l].size(); ++t) lvl[m + cid[l][t]] = l;
+  std::vector<double> rt(nsrc_all);
+  for (int j = 0; j < m; ++j) rt[j] = G.incl[4 * (size_t)j + 2];
+  for (int c = 0; c < nc; ++c) {   // clusters are numbered level by level upwards
+    const double* g = &G.incl[4 * (size_t)(m + c)];
+    double r = g[2];
+    for (int q = G.kid_off[c]; q < G.kid_off[c + 1]; ++q) {
+      const int ch = G.kid_idx[q];
+      const double* gc = &G.incl[4 * (size_t)ch];
+      r = std::max(r, std::hypot(gc[0] - g[0], gc[1] - g[1]) + rt[ch]);
+    }
+    rt[m + c] = r;
+  }
   std::vector<int> top;
-  if (nclev >= 1)
-    for (size_t t = 0; t < plan[nclev].size(); ++t) top.push_back(m + cid[nclev][t]);
-  else
-    for (int j = 0; j < m; ++j) top.push_back(j);
+  for (int v = 0; v < nsrc_all; ++v)
+    if (parent[v] < 0 && (v >= m || nclev == 0)) top.push_back(v);
+  // local-expansion orders: the targets' own decay order or the separation's, whichever is
+  // larger; a node with an order above PMX_FMM_PL takes no local expansion
+  const int p_sep = (int)std::ceil(PMX_APPLY_TRUNC / std::log(1.0 / PMX_FMM_RATIO));
+  std::vector<int> ptgt(nsrc_all);
+  for (int v = 0; v < nsrc_all; ++v) ptgt[v] = std::max(apply_source_order(k * rt[v]), p_sep);
+  auto src_ok = [&](int v) { return v < m ? !always[v] : (bool)usable[v - m]; };
+  // a pair (T, S) is translated when its circles are separated by the ratio, both orders
+  // fit and the table's largest Hankel function stays far below the overflow threshold
+  // orders of a pair: the double series sum_n sum_m X_n O_{n-m}(D) I_m(u) (|u| <= r~_T)
+  // loses less than e^-PMX_APPLY_TRUNC beyond |n| = nmax when (r_S / (|D| - r~_T))^nmax is
+  // that small, and beyond |m| = mmax when (r~_T / (|D| - r_S))^mmax is; neither goes
+  // below the decay order of its own radius (the sources' J_n, the targets' J_m)
+  auto accept = [&](int T, int S, int& nmax, int& mmax) {
+    if (ptgt[T] > PMX_FMM_PL || !src_ok(S)) return false;
+    const double* gt = &G.incl[4 * (size_t)T];
+    const double* gs = &G.incl[4 * (size_t)S];
+    const double d = std::hypot(gt[0] - gs[0], gt[1] - gs[1]);
+    if (!(rt[T] + gs[2] <= PMX_FMM_RATIO * d)) return false;
+    nmax = std::max((int)gs[3], (int)std::ceil(PMX_APPLY_TRUNC / std::log((d - rt[T]) / gs[2])));
+    mmax = std::max(apply_source_order(k * rt[T]), (int)std::ceil(PMX_APPLY_TRUNC / std::log((d - gs[2]) / rt[T])));
+    mmax = std::min(mmax, ptgt[T]);
+    if (nmax > PMX_FMM_NMAX) return false;   // also within the stored records (PMX_APPLY_PMAX)
+    const double V = mmax + 1 + nmax, z = k * d;
+    if (V > z && V * std::log(2.0 * V / (M_E * z)) > 600.0) return false;
+    return true;
+  };
+  struct M2lPair {
+    int src, nmax, mmax;
+  };
+  std::vector<std::vector<M2lPair>> m2l(nsrc_all);
+  std::vector<std::vector<int>> leftover(m);
+  std::function<void(int, int)> walk = [&](int T, int S) {
+    if (T == S) {
+      if (T < m) return;
+      const int c = T - m;
+      for (int a = G.kid_off[c]; a < G.kid_off[c + 1]; ++a)
+        for (int b = G.kid_off[c]; b < G.kid_off[c + 1]; ++b) walk(G.kid_idx[a], G.kid_idx[b]);
+      return;
+    }
+    int nmax = 0, mmax = 0;
+    if (accept(T, S, nmax, mmax)) {
+      m2l[T].push_back({S, nmax, mmax});
+      return;
+    }
+    if (T < m) {   // a leaf target: its waves' walks take S, opening it as they need
+      leftover[T].push_back(S);
+      return;
+    }
+    if (S < m || rt[T] >= rt[S]) {
+      const int c = T - m;
+      for (int a = G.kid_off[c]; a < G.kid_off[c + 1]; ++a) walk(G.kid_idx[a], S);
+    } else {
+      const int c = S - m;
+      for (int b = G.kid_off[c]; b < G.kid_off[c + 1]; ++b) walk(T, G.kid_idx[b]);
+    }
+  };
+  for (int a : top)
+    for (int b : top) walk(a, b);
+  // local expansions: nodes with translated sources and everything below them, top down
+  std::vector<char> has_local(nsrc_all, 0);
+  std::vector<int> order;   // tree nodes from the top level down
+  for (int l = nclev; l >= 1; --l)
+    for (size_t t = 0; t < plan[l].size(); ++t) order.push_back(m + cid[l][t]);
+  for (int j = 0; j < m; ++j) order.push_back(j);
+  G.loc_id.assign(nsrc_all, -1);
+  G.loc_p.clear();
+  G.loc_geo.clear();
+  for (int v : order) {
+    has_local[v] = !m2l[v].empty() || (parent[v] >= 0 && has_local[parent[v]]);
+    if (!has_local[v]) continue;
+    if (ptgt[v] > PMX_FMM_PL) fail(PMX_EGEOM, "operator apply: a local expansion beyond its largest order");
+    G.loc_id[v] = (int)G.loc_p.size();
+    G.loc_p.push_back(ptgt[v]);
+    G.loc_geo.push_back(G.incl[4 * (size_t)v]);
+    G.loc_geo.push_back(G.incl[4 * (size_t)v + 1]);
+  }
+  const int nloc = (int)G.loc_p.size();
+  G.m2l_off.assign(1, 0);
+  G.m2l_slot.clear();
+  G.m2l_src.clear();
+  G.m2l_nmax.clear();
+  G.m2l_mmax.clear();
+  G.m2l_toff.clear();
+  G.m2l_tab = 0;
+  double m2l_terms = 0, l2l_terms = 0, l2p_terms = 0;
+  for (int v : order) {
+    const int t = G.loc_id[v];
+    if (t < 0) continue;
+    for (const M2lPair& pr : m2l[v]) {
+      const int V = pr.mmax + 1 + pr.nmax;
+      G.m2l_slot.push_back(t);
+      G.m2l_src.push_back(pr.src);
+      G.m2l_nmax.push_back(pr.nmax);
+      G.m2l_mmax.push_back(pr.mmax);
+      G.m2l_toff.push_back(G.m2l_tab);
+      G.m2l_tab += 2 * V + 1;
+      m2l_terms += 2.0 * (2 * pr.mmax + 3) * (2 * pr.nmax + 1);
+    }
+    G.m2l_off.push_back((int)G.m2l_src.size());
+  }
+  // parent-to-child translations, grouped by the child's level from the top
+  G.l2l_child.clear();
+  G.l2l_parent.clear();
+  G.l2l_toff.clear();
+  G.l2l_lev.assign(1, 0);
+  G.l2l_tab = 0;
+  for (int l = nclev; l >= 1; --l) {
+    for (int v : order) {
+      if (lvl[v] != l - 1 || (l - 1 == 0 && v >= m) || parent[v] < 0 || !has_local[parent[v]]) continue;
+      const int c = G.loc_id[v], P = G.loc_id[parent[v]];
+      const int W = ptgt[parent[v]] + ptgt[v] + 2;
+      G.l2l_child.push_back(c);
+      G.l2l_parent.push_back(P);
+      G.l2l_toff.push_back(G.l2l_tab);
+      G.l2l_tab += 2 * W + 1;
+      l2l_terms += 2.0 * (2 * ptgt[v] + 3) * (2 * ptgt[parent[v]] + 3);
+    }
+    G.l2l_lev.push_back((int)G.l2l_child.size());
+  }
+  // the waves' walks start from what their inclusion left over
   G.off.assign(nw + 1, 0);
   G.foff.assign(nw + 1, 0);
   G.idx.clear();
@@ -1825,10 +1990,12 @@ void apply_geometry(const pmx_factor* F, const std::vector<double>& hx, const st
   double near_pairs = 0, far_orders = 0, far_pairs = 0;
   for (int w = 0; w < nw; ++w) {
     const double* gw = &G.wave[4 * (size_t)w];
-    const double nt = (double)(std::min(64 * w + 64, N) - 64 * w);
+    const double nt = (double)G.wave_node[2 * w + 1];
+    const int own = wave_incl[w];
+    if (G.loc_id[own] >= 0) l2p_terms += nt * (2 * ptgt[own] + 1);
     nearv.clear();
     farv.clear();
-    stack.assign(top.rbegin(), top.rend());
+    stack.assign(leftover[own].rbegin(), leftover[own].rend());
     while (!stack.empty()) {
       const int sidx = stack.back();
       stack.pop_back();
@@ -1863,14 +2030,28 @@ void apply_geometry(const pmx_factor* F, const std::vector<double>& hx, const st
     G.off[w + 1] = (int)G.idx.size();
     G.foff[w + 1] = (int)G.fidx.size();
   }
-  if (count) {
-    // near pairs include each target's own inclusion, which the apply leaves out
-    for (int j = 0; j < m; ++j) {
-      const double n = (double)(F->node_off[j + 1] - F->node_off[j]);
-      near_pairs -= n * n;
+  {
+    double sn = 0, sm = 0;
+    for (size_t q = 0; q < G.m2l_nmax.size(); ++q) {
+      sn += G.m2l_nmax[q];
+      sm += G.m2l_mmax[q];
     }
+    const double np = std::max<double>(1.0, (double)G.m2l_nmax.size());
+    G.stats[0] = (double)G.m2l_nmax.size();
+    G.stats[1] = sn / np;
+    G.stats[2] = sm / np;
+    G.stats[3] = (double)nloc;
+    G.stats[4] = (double)G.l2l_child.size();
+    G.stats[5] = near_pairs;
+    G.stats[6] = far_pairs;
+    G.stats[7] = 16.0 * (double)(G.m2l_tab + G.l2l_tab);
+  }
+  if (count) {
     const double p2m = (double)N * (2 * (PMX_APPLY_PMAX + 3) + 1);
-    G.flops_rhs = 32.0 * near_pairs + 48.0 * far_orders + 72.0 * p2m + 8.0 * m2m_terms;
+    // translations: 8 flops per complex multiply-add; evaluation of a local expansion:
+    // three complex multiply-adds per order (value row, both derivative sums)
+    G.flops_rhs = 32.0 * near_pairs + 48.0 * far_orders + 72.0 * p2m + 8.0 * m2m_terms + 8.0 * m2l_terms +
+                  8.0 * l2l_terms + 24.0 * l2p_terms;
     G.flops_fixed = 130.0 * near_pairs + 100.0 * far_pairs + 26.0 * far_orders;
   }
 }
@@ -1898,6 +2079,7 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   }
   D.flops_fixed = G.flops_fixed;
   D.flops_rhs = G.flops_rhs;
+  for (int i = 0; i < 8; ++i) F->info.apply_stats[i] = G.stats[i];
   const int nnear = apply_near_splits(F->n_nodes, wg);
   D.nslots = D.nsplit + nnear;
   D.ydiag = A.alloc<zd>(D.total);
@@ -1930,7 +2112,7 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   aa.nrhs = nrhs;
   aa.ld = N2;
   aa.part = D.part;
-  aa.pack = A.alloc<double>(apply_pack_size(F->n_nodes, 8));
+  aa.pack = A.alloc<double>(apply_pack_size(F->n_nodes, PMX_APPLY_NR_NEAR));
   aa.near_off = A.upload(G.off, s);
   aa.near_idx = A.upload(G.idx, s);
   aa.far_off = A.upload(G.foff, s);
@@ -1945,6 +2127,53 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   aa.n_clus = G.n_clus;
   aa.n_lev = (int)G.lev_off.size() - 1;
   for (int l = 0; l <= aa.n_lev; ++l) aa.lev_off[l] = G.lev_off[l];
+  aa.wave_node = A.upload(G.wave_node, s);
+  aa.n_waves = (int)G.wave_node.size() / 2;
+  // fast multipole part: local expansions, translation lists and their tables (made here,
+  // once per solve state; they depend on the geometry only)
+  aa.n_loc = (int)G.loc_p.size();
+  aa.loc_id = A.upload(G.loc_id, s);
+  aa.loc_p = A.upload(G.loc_p, s);
+  aa.loc_geo = A.upload(G.loc_geo, s);
+  aa.loc = A.alloc<zd>((int64_t)std::max(1, aa.n_loc) * 2 * PMX_FMM_NL * 8);
+  aa.cm = A.alloc<zd>(apply_m2l_coef_size(F->m + G.n_clus, 8));
+  aa.m2l_off = A.upload(G.m2l_off, s);
+  {
+    // work items: runs of at most PMX_FMM_CHUNK pairs of one local expansion (every slot
+    // has at least one, so that its partial sums exist)
+    std::vector<int> item, item_off(1, 0);
+    for (int t = 0; t < (int)G.loc_p.size(); ++t) {
+      const int q0 = G.m2l_off[t], q1 = G.m2l_off[t + 1];
+      int q = q0;
+      do {
+        const int qe = std::min(q1, q + PMX_FMM_CHUNK);
+        item.push_back(t);
+        item.push_back(q);
+        item.push_back(qe);
+        q = qe;
+      } while (q < q1);
+      item_off.push_back((int)item.size() / 3);
+    }
+    aa.n_m2l_items = (int)item.size() / 3;
+    aa.m2l_item = A.upload(item, s);
+    aa.m2l_item_off = A.upload(item_off, s);
+    aa.m2l_part = A.alloc<zd>((int64_t)std::max(1, aa.n_m2l_items) * 2 * PMX_FMM_NL * 8);
+  }
+  aa.m2l_slot = A.upload(G.m2l_slot, s);
+  aa.m2l_src = A.upload(G.m2l_src, s);
+  aa.m2l_nmax = A.upload(G.m2l_nmax, s);
+  aa.m2l_mmax = A.upload(G.m2l_mmax, s);
+  aa.m2l_toff = A.upload(G.m2l_toff, s);
+  aa.m2l_tab = A.alloc<zd>(std::max<int64_t>(1, G.m2l_tab));
+  aa.l2l_child = A.upload(G.l2l_child, s);
+  aa.l2l_parent = A.upload(G.l2l_parent, s);
+  aa.l2l_toff = A.upload(G.l2l_toff, s);
+  aa.l2l_tab = A.alloc<zd>(std::max<int64_t>(1, G.l2l_tab));
+  if ((int)G.l2l_lev.size() > PMX_APPLY_MAXLEV + 2) fail(PMX_EGEOM, "operator apply: too many tree levels");
+  aa.n_l2l_lev = (int)G.l2l_lev.size() - 1;
+  for (int l = 0; l <= aa.n_l2l_lev; ++l) aa.l2l_lev[l] = G.l2l_lev[l];
+  asm_apply_tables(aa, (int)G.m2l_src.size(), (int)G.l2l_child.size(), s);
+  D.table_bytes = 16.0 * (double)(G.m2l_tab + G.l2l_tab);
   D.n_src = F->m + G.n_clus;
   D.f = f;
   D.out = out;
@@ -2561,7 +2790,9 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
       F->ss.reset(new SolveState(&F->pool));
       if (o.learned) {
         plan_job.get();
+        const double tl = now_ms();
         leaf_predictions(F.get(), geom, o.model_path, s);
+        F->info.t_phase_ms[8] = now_ms() - tl;
       }
       upload_geometry(F.get(), geom, s);
       if (o.precision != 0) self_blocks_by_inclusion(F.get(), s);
@@ -3018,6 +3249,84 @@ pmx_status pmx_probe_mlp(int32_t nin, int32_t nhidden, int32_t nlayer, int32_t n
     HIPCHK(hipMemcpyAsync(out, wk.Z[nl], (size_t)nout * B * 4, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(grad, G, off.back() * 4, hipMemcpyDeviceToHost, s));
     sync_check(s);
+  });
+}
+
+pmx_status pmx_probe_apply_structure(const pmx_geometry* geom, const pmx_options* opts, int32_t check,
+                                     double* stats) {
+  return guarded([&] {
+    pmx_options o;
+    pmx_options_default(&o);
+    if (opts) o = *opts;
+    validate(geom, &o);
+    if (!stats) fail(PMX_EINVAL, "NULL stats");
+    std::unique_ptr<pmx_factor> F(new pmx_factor());
+    F->opts = o;
+    F->m = geom->m;
+    F->node_off.assign(geom->node_off, geom->node_off + geom->m + 1);
+    F->n_nodes = (int)F->node_off.back();
+    F->k_ext = geom->k_ext;
+    make_plan(geom, o, F->plan);
+    const std::vector<double> hx(geom->x, geom->x + F->n_nodes), hy(geom->y, geom->y + F->n_nodes);
+    ApplyGeo G;
+    apply_geometry(F.get(), hx, hy, G, true);
+    const int m = F->m, nsrc = m + G.n_clus, nw = (int)G.wave_node.size() / 2;
+    for (int i = 0; i < 16; ++i) stats[i] = 0;
+    for (int i = 0; i < 8; ++i) stats[i] = G.stats[i];
+    const int nloc = (int)G.loc_p.size();
+    int mxl = 0, mxf = 0, mxn = 0, mxp = 0;
+    for (int t = 0; t < nloc; ++t) {
+      mxl = std::max(mxl, G.m2l_off[t + 1] - G.m2l_off[t]);
+      mxp = std::max(mxp, G.loc_p[t]);
+    }
+    for (int w = 0; w < nw; ++w) {
+      mxf = std::max(mxf, G.foff[w + 1] - G.foff[w]);
+      mxn = std::max(mxn, G.off[w + 1] - G.off[w]);
+    }
+    stats[8] = mxl;
+    stats[9] = nloc ? (double)G.m2l_src.size() / nloc : 0.0;
+    stats[10] = mxf;
+    stats[11] = mxn;
+    stats[12] = -1;
+    stats[13] = nw;
+    stats[14] = mxp;
+    if (check) {
+      // every (wave, source inclusion) pair of different inclusions must be taken exactly
+      // once: near, through a far source of the wave that holds it, or through a
+      // translation into the wave's inclusion or one of its ancestors from a source that
+      // holds it
+      std::vector<int> parent(nsrc, -1);
+      for (int c = 0; c < G.n_clus; ++c)
+        for (int q = G.kid_off[c]; q < G.kid_off[c + 1]; ++q) parent[G.kid_idx[q]] = m + c;
+      std::vector<std::vector<char>> holds(nsrc, std::vector<char>(m, 0));
+      for (int j = 0; j < m; ++j)
+        for (int v = j; v >= 0; v = parent[v]) holds[v][j] = 1;
+      std::vector<int> node_of(nloc, -1);
+      for (int v = 0; v < nsrc; ++v)
+        if (G.loc_id[v] >= 0) node_of[G.loc_id[v]] = v;
+      int64_t bad = 0, pairs = 0;
+      std::vector<int> cnt(m);
+      for (int w = 0; w < nw; ++w) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        int own = 0;
+        while (own + 1 <= m && F->node_off[own + 1] <= G.wave_node[2 * w]) ++own;
+        for (int q = G.off[w]; q < G.off[w + 1]; ++q) cnt[G.idx[q]] += 1;
+        for (int q = G.foff[w]; q < G.foff[w + 1]; ++q)
+          for (int j = 0; j < m; ++j) cnt[j] += holds[G.fidx[q]][j];
+        for (int v = own; v >= 0; v = parent[v]) {
+          const int t = G.loc_id[v];
+          if (t < 0) continue;
+          for (int q = G.m2l_off[t]; q < G.m2l_off[t + 1]; ++q)
+            for (int j = 0; j < m; ++j) cnt[j] += holds[G.m2l_src[q]][j];
+        }
+        for (int j = 0; j < m; ++j) {
+          bad += (j == own) ? (cnt[j] != 0) : (cnt[j] != 1);
+          ++pairs;
+        }
+      }
+      stats[12] = (double)bad;
+      stats[15] = (double)pairs;
+    }
   });
 }
 

@@ -27,7 +27,7 @@ EXPORTS = [
     "pmx_probe_zgemm", "pmx_probe_lu_solve", "pmx_probe_id", "pmx_plan_query",
     "pmx_probe_cgemm", "pmx_probe_lu_solve_c32", "pmx_probe_id_c32", "pmx_probe_apply",
     "pmx_mlp_opts_default", "pmx_id_dataset", "pmx_mlp_train", "pmx_mlp_predict", "pmx_probe_mlp",
-    "pmx_autotune", "pmx_device_cache", "pmx_far_field_noalloc",
+    "pmx_autotune", "pmx_device_cache", "pmx_far_field_noalloc", "pmx_probe_apply_structure",
 ]
 
 
@@ -64,7 +64,8 @@ class Info(C.Structure):
                 ("t_kernel_ms", C.c_double * 16), ("n_kernel_launch", C.c_int32 * 16),
                 ("kernel_bytes", C.c_double * 16), ("kernel_flops", C.c_double * 16),
                 ("t_solve_ms", C.c_double), ("ir_iterations", C.c_int32), ("ir_residual", C.c_double),
-                ("ir_history", C.c_double * 16), ("id_learned", C.c_int32), ("id_fallback", C.c_int32)]
+                ("ir_history", C.c_double * 16), ("id_learned", C.c_int32), ("id_fallback", C.c_int32),
+                ("apply_stats", C.c_double * 8)]
 
 
 class MlpOpts(C.Structure):
@@ -113,6 +114,8 @@ def load(path=None):
     lib.pmx_probe_lu_solve_c32.argtypes = [C.c_int32, C.c_int32, vp, vp, C.c_int32, vp, ip, C.c_int32, vp]
     lib.pmx_probe_id_c32.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, C.c_double, ip, vp, ip, vp, vp]
     lib.pmx_probe_apply.argtypes = [C.POINTER(Geometry), C.c_int32, vp, vp, vp]
+    lib.pmx_probe_apply_structure.argtypes = [C.POINTER(Geometry), C.POINTER(Options), C.c_int32,
+                                              C.POINTER(C.c_double)]
     fp = C.POINTER(C.c_float)
     lib.pmx_mlp_opts_default.argtypes = [C.POINTER(MlpOpts)]
     lib.pmx_mlp_opts_default.restype = None
@@ -374,6 +377,22 @@ def probe_apply(w, x):
     _check(_lib.pmx_probe_apply(C.byref(keep.g), xt.shape[0], C.c_void_p(xt.data_ptr()), C.c_void_p(y.data_ptr()),
                                 _stream()))
     return y.cpu().numpy().T.copy()
+
+
+APPLY_STRUCTURE_KEYS = ("m2l_pairs", "mean_source_order", "mean_local_order", "local_expansions", "l2l_pairs",
+                        "near_node_pairs", "direct_far_pairs", "table_bytes", "max_m2l_list", "mean_m2l_list",
+                        "max_far_list", "max_near_list", "coverage_violations", "waves", "max_local_order",
+                        "pairs_checked")
+
+
+def apply_structure(w, check=False, opts=None):
+    """Host-only structure of the refinement's operator apply for workload w (no GPU)."""
+    load()
+    keep = _GeomKeep(w)
+    o = options(w) if opts is None else opts
+    st = (C.c_double * 16)()
+    _check(_lib.pmx_probe_apply_structure(C.byref(keep.g), C.byref(o), int(bool(check)), st))
+    return dict(zip(APPLY_STRUCTURE_KEYS, [float(v) for v in st]))
 
 
 def plan_query(w, opts=None):

@@ -218,3 +218,21 @@ def test_stars16_tuned_and_plain_against_tight_reference(pmx):
     print("stars16 rel error vs reference", errs, "oracle sampled residual", res)
     assert errs["plain"] <= 1e-8 and errs["tuned"] <= 1e-8
     assert res["ref"] <= 1e-10 and res["tuned"] <= 1e-9
+
+
+def test_dense_apply_fast_multipole_sixteen_rhs(pmx):
+    """The benchmark's shape of the apply: 32x32 stars at k+ = 8 with sixteen right-hand
+    sides (translations on three tree levels, near groups of eight, expansion groups), on
+    sampled rows against the oracle's FP64 row evaluation."""
+    w = W.star_grid(32, n=128, k_ext=8.0, k_int=12.0, seed=4)
+    w.angles = 2 * np.pi * np.arange(16) / 16
+    st = pmx.apply_structure(w)
+    assert st["m2l_pairs"] > 1000 and st["l2l_pairs"] > 100
+    x = crandn(w.n_unknowns, 16)
+    got = pmx.probe_apply(w, x)
+    rows = np.sort(np.random.default_rng(12).choice(w.n_unknowns, size=10, replace=False))
+    f = dense.rhs(dense.Geometry(w), w.angles)[rows]
+    ref = f - dense.residual_rows(w, x, rows)
+    err = np.abs(got[rows] - ref).max() / np.abs(ref).max()
+    print("fast multipole apply rel err", err, "N", w.n_unknowns, st)
+    assert err < 1e-12

@@ -171,3 +171,20 @@ def test_valid_launch_table_passes_validation(tmp_path):
     else:
         assert st != 1, msg
     assert pmx.read_tune_table(p)[("lu_panel", 8, 2, 1, 0)] == 3
+
+
+@pytest.mark.parametrize("w", [W.sub_grid(W.config2(), 4), W.star_grid(12, n=16, k_ext=10.0, k_int=15.0, seed=5),
+                               W.config3(m=14, box=7.0, seed=3), W.config2(), W.config3(),
+                               W.star_grid(16, n=64, k_ext=40.0, k_int=60.0, seed=9)],
+                         ids=["stars4x4", "stars12x12_n16", "scattered14", "stars16x16", "scattered400",
+                              "stars16x16_k40"])
+def test_apply_structure_takes_every_pair_once(w):
+    """The refinement's operator apply splits the interactions between different inclusions
+    into near pairs, expansions evaluated per target wave, and translations into local
+    expansions of the target's inclusion or an ancestor.  Brute force over every (wave,
+    source inclusion) pair: each is taken exactly once, and the wave's own inclusion (its
+    self block, applied separately) never."""
+    st = pmx.apply_structure(w, check=True)
+    assert st["pairs_checked"] == st["waves"] * w.m
+    assert st["coverage_violations"] == 0
+    assert st["max_local_order"] <= 62 and st["max_near_list"] >= 1
