@@ -65,6 +65,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-check", action="store_true", help="no reference solve and no oracle residual")
     p.add_argument("--no-plain", action="store_true", help="time the tuned form only")
+    p.add_argument("--plain-only", action="store_true", help="time the plain form only (profiling runs)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a 256 MiB device copy first (reference kernel for HBM counters)")
     p.add_argument("--no-timing", action="store_true", help="no HIP events at all (no roofline, no shares)")
@@ -293,6 +294,36 @@ def summarize_pmc(fetch_csv, write_csv, kname, tag, table_path=None):
     print(json.dumps(out))
 
 
+def summarize_counters(csv_paths, out_md, title):
+    """Per-kernel sums of rocprofv3 --pmc counter files (one or more runs, each with its own
+    counters) as a markdown table: dispatches, every counter's total, and the derived FP64
+    VALU flops (64 lanes x (2 FMA + ADD + MUL + TRANS) per wave instruction, every lane
+    counted) and MFMA FP64/FP32 flops (MOPS x 512) where their counters are present."""
+    import csv
+    from collections import defaultdict
+    tot = defaultdict(lambda: defaultdict(float))
+    disp = defaultdict(set)
+    for path in csv_paths:
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            tot[name][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp[name].add(r.get("Dispatch_Id", r.get("Correlation_Id", "")))
+    counters = sorted({c for k in tot for c in tot[k]})
+    rows = sorted(tot, key=lambda k: -max(tot[k].values()))
+    lines = [f"# {title}", "", "| kernel | dispatches | " + " | ".join(counters) + " | FP64 VALU flops | MFMA F64 flops | MFMA F32 flops |",
+             "|---" * (len(counters) + 5) + "|"]
+    for k in rows:
+        c = tot[k]
+        v64 = 64.0 * (2 * c.get("SQ_INSTS_VALU_FMA_F64", 0) + c.get("SQ_INSTS_VALU_ADD_F64", 0) +
+                      c.get("SQ_INSTS_VALU_MUL_F64", 0) + c.get("SQ_INSTS_VALU_TRANS_F64", 0))
+        m64 = 512.0 * c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0)
+        m32 = 512.0 * c.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0)
+        lines.append(f"| {k[:60]} | {len(disp[k])} | " + " | ".join(f"{c.get(x, 0):.4g}" for x in counters) +
+                     f" | {v64:.4g} | {m64:.4g} | {m32:.4g} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines[:40]))
+
+
 def run_form(pmx, w, kw, steps, warmup, timing):
     """Warm-up steps time every kernel (time shares, dominant kernel); the timed steps time
     only the dominant counted kernel, so that events around the other launches do not
@@ -323,7 +354,10 @@ def run_form(pmx, w, kw, steps, warmup, timing):
         times.append(time.perf_counter() - t0)
         infos.append(fac.info())
         fac.close()
-        print(f"bench: timed step {i + 1}/{steps}: {times[-1]:.3f} s", file=sys.stderr, flush=True)
+        inf = infos[-1]
+        print(f"bench: timed step {i + 1}/{steps}: {times[-1]:.3f} s (factor {inf.t_factor_ms:.0f} ms, solve "
+              f"{inf.t_solve_ms:.0f} ms, solve set-up {inf.t_phase_ms[5]:.0f} ms, apply set-up {inf.t_phase_ms[6]:.0f} ms)",
+              file=sys.stderr, flush=True)
     if timing and k is None:     # no warm-up: every kernel was timed in the timed steps
         k, top, share = dominant_kernel(infos, names)
     return times, infos, dens, (k, top, share)
@@ -338,6 +372,10 @@ def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
         summarize_pmc(*sys.argv[2:7])
         return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
+        # --summarize-counters OUT.md TITLE CSV [CSV ...]
+        summarize_counters(sys.argv[4:], sys.argv[2], sys.argv[3])
+        return
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the solver is not sharded "
@@ -346,6 +384,9 @@ def main():
     import torch
     from paper_2603_09381_amd import pmx, workloads as W
     torch.cuda.set_device(0)
+    # device blocks of destroyed factors are kept for the next step's factor (the 1M-unknown
+    # FP64 factor holds ~37 GB; the GPU has 288 GB)
+    pmx.device_cache(64 << 30)
     if a.copy_calibration:
         src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -358,7 +399,7 @@ def main():
     tag = workload_tag(a.grid)
     timing = 0 if a.no_timing else 1
     forms = {k: dict(v) for k, v in FORMS.items()}
-    names = ("tuned", "plain") if not a.no_plain else ("tuned",)
+    names = ("plain",) if a.plain_only else (("tuned", "plain") if not a.no_plain else ("tuned",))
     table_note = {}
     for name in names:
         if a.autotune:
@@ -378,6 +419,11 @@ def main():
                                 else "built-in rules (no table for this workload)")
         if path:
             forms[name]["tune_path"] = path
+    if a.plain_only:   # profiling runs of the plain form: its timing only
+        ptimes, pinfos, _, pdom = run_form(pmx, w, forms["plain"], a.steps, a.warmup, timing)
+        print(json.dumps({"form": "plain", "ms_per_step": 1e3 * sum(ptimes) / len(ptimes),
+                          "kernel_time_share": pdom[2]}), flush=True)
+        return
     times, infos, dens, dom = run_form(pmx, w, forms["tuned"], a.steps, a.warmup, timing)
     total = sum(times)
     info = infos[-1]

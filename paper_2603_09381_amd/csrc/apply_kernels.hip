@@ -295,30 +295,35 @@ __global__ __launch_bounds__(256) void k_apply_p2m(ApplyArgs A, const double* __
 // c of the first wave computes child c's J_nu(k|d|), nu = 0 .. M2M_NU, by Miller's backward
 // recurrence (rescaled against overflow, normalised by J_0 + 2 sum J_2k = 1); the table of
 // R_nu(d), nu = -M2M_NU .. M2M_NU, follows.  Per child the workgroup stages the child's A_n
-// and B_n in LDS, and each thread accumulates its (order, right-hand side) outputs.  The
-// records are then written as p2m writes them, orders up to PMX_APPLY_PMAXC + 1.
+// and B_n in LDS, and each thread accumulates its (order, right-hand side) outputs in
+// registers: orders up to the cluster's own order + 2 (its sources' J_n decay; beyond,
+// the coefficients are below 1e-17 of the leading ones and are written as zeros), child
+// orders up to the child's order + 2.  The records are then written as p2m writes them,
+// orders up to PMX_APPLY_PMAXC + 1.
 constexpr int M2M_MO = PMX_APPLY_PMAXC + 2;                // outputs for orders -M2M_MO .. M2M_MO
 constexpr int M2M_NM = 2 * M2M_MO + 1;
 constexpr int M2M_NU = M2M_MO + PMX_APPLY_NRECA + 1;       // translation orders |m - n| <= M2M_NU
 constexpr int M2M_NI = 2 * PMX_APPLY_NRECA + 1;            // child orders -NRECA .. NRECA
 constexpr int M2M_KIDS = 4;
+constexpr int M2M_THREADS = 512;
+static_assert(M2M_NI >= M2M_NM, "the child stage holds the outputs at the end");
 
 template <int NR>
-__global__ __launch_bounds__(512) void k_apply_m2m(ApplyArgs A, int c0) {
+__global__ __launch_bounds__(M2M_THREADS) void k_apply_m2m(ApplyArgs A, int c0) {
+  constexpr int NOUT = (M2M_NM * NR + M2M_THREADS - 1) / M2M_THREADS;   // outputs per thread
   const int c = c0 + blockIdx.x;
   const int sc = A.n_incl + c;
   const double Cx = A.incl_geo[4 * sc], Cy = A.incl_geo[4 * sc + 1];
+  const int mo = min((int)A.incl_geo[4 * sc + 3], PMX_APPLY_PMAXC) + 2;   // orders kept
   const double k = A.k;
   const int q0 = A.kid_off[c], nk = min(A.kid_off[c + 1] - q0, M2M_KIDS);
   __shared__ double jt[M2M_KIDS][M2M_NU + 1];
   __shared__ zd Rt[M2M_KIDS][2 * M2M_NU + 1];
   __shared__ zd An[NR][M2M_NI], Bn[NR][M2M_NI];
-  __shared__ zd accA[M2M_NM][NR], accB[M2M_NM][NR];
   const int tid = threadIdx.x;
-  for (int e = tid; e < M2M_NM * NR; e += 512) {
-    accA[e / NR][e % NR] = zmk(0, 0);
-    accB[e / NR][e % NR] = zmk(0, 0);
-  }
+  double aar[NOUT], aai[NOUT], abr[NOUT], abi[NOUT];
+#pragma unroll
+  for (int i = 0; i < NOUT; ++i) aar[i] = aai[i] = abr[i] = abi[i] = 0.0;
   if (tid < nk) {
     const int ch = A.kid_idx[q0 + tid];
     const double dx = A.incl_geo[4 * ch] - Cx, dy = A.incl_geo[4 * ch + 1] - Cy;
@@ -349,7 +354,7 @@ __global__ __launch_bounds__(512) void k_apply_m2m(ApplyArgs A, int c0) {
     }
   }
   __syncthreads();
-  for (int e = tid; e < nk * (2 * M2M_NU + 1); e += 512) {
+  for (int e = tid; e < nk * (2 * M2M_NU + 1); e += M2M_THREADS) {
     const int kc = e / (2 * M2M_NU + 1), nu = e % (2 * M2M_NU + 1) - M2M_NU;
     const int ch = A.kid_idx[q0 + kc];
     const double dx = A.incl_geo[4 * ch] - Cx, dy = A.incl_geo[4 * ch + 1] - Cy;
@@ -363,10 +368,12 @@ __global__ __launch_bounds__(512) void k_apply_m2m(ApplyArgs A, int c0) {
   for (int kc = 0; kc < nk; ++kc) {
     const int ch = A.kid_idx[q0 + kc];
     const int nrc = (ch < A.n_incl) ? PMX_APPLY_NREC : PMX_APPLY_NRECA;   // record rows of the child
+    const int pch = min((int)A.incl_geo[4 * ch + 3], nrc - 1) + 2;        // child orders kept
+    const int nlo = max(1 - nrc, -pch), nhi = min(nrc, pch);
     const zd* rec = A.coef + (int64_t)ch * PMX_APPLY_NRECA * NR * 6;
     __syncthreads();   // the previous child's A, B are read no more; the R table is complete
     // stored: A_n for |n| <= nrc - 1, B_n for 2 - nrc <= n <= nrc; the rest is zero
-    for (int e = tid; e < NR * M2M_NI; e += 512) {
+    for (int e = tid; e < NR * M2M_NI; e += M2M_THREADS) {
       const int rr = e / M2M_NI, n = e % M2M_NI - PMX_APPLY_NRECA;
       zd a = zmk(0, 0), b = zmk(0, 0);
       if (n >= 1 - nrc && n <= nrc - 1) a = n >= 0 ? rec[((int64_t)n * NR + rr) * 6] : rec[((int64_t)(-n) * NR + rr) * 6 + 1];
@@ -376,11 +383,14 @@ __global__ __launch_bounds__(512) void k_apply_m2m(ApplyArgs A, int c0) {
       Bn[rr][n + PMX_APPLY_NRECA] = b;
     }
     __syncthreads();
-    for (int e = tid; e < M2M_NM * NR; e += 512) {
+#pragma unroll
+    for (int i = 0; i < NOUT; ++i) {
+      const int e = tid + M2M_THREADS * i;
       const int m = e / NR - M2M_MO, rr = e % NR;
+      if (e >= M2M_NM * NR || m < -mo || m > mo) continue;
       double ar = 0, ai = 0, br = 0, bi = 0;
 #pragma unroll 4
-      for (int n = 1 - nrc; n <= nrc; ++n) {
+      for (int n = nlo; n <= nhi; ++n) {
         const zd R = Rt[kc][m - n + M2M_NU];
         const zd a = An[rr][n + PMX_APPLY_NRECA], b = Bn[rr][n + PMX_APPLY_NRECA];
         ar = fma(-R.im, a.im, fma(R.re, a.re, ar));
@@ -388,22 +398,34 @@ __global__ __launch_bounds__(512) void k_apply_m2m(ApplyArgs A, int c0) {
         br = fma(-R.im, b.im, fma(R.re, b.re, br));
         bi = fma(R.im, b.re, fma(R.re, b.im, bi));
       }
-      accA[m + M2M_MO][rr] = zadd(accA[m + M2M_MO][rr], zmk(ar, ai));
-      accB[m + M2M_MO][rr] = zadd(accB[m + M2M_MO][rr], zmk(br, bi));
+      aar[i] += ar;
+      aai[i] += ai;
+      abr[i] += br;
+      abi[i] += bi;
     }
+  }
+  // the outputs, orders -M2M_MO .. M2M_MO, into the child stage (An: A, Bn: B)
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NOUT; ++i) {
+    const int e = tid + M2M_THREADS * i;
+    if (e >= M2M_NM * NR) continue;
+    const int mi = e / NR, rr = e % NR;
+    An[rr][mi] = zmk(aar[i], aai[i]);
+    Bn[rr][mi] = zmk(abr[i], abi[i]);
   }
   __syncthreads();
   zd* out = A.coef + (int64_t)sc * PMX_APPLY_NRECA * NR * 6;
-  for (int e = tid; e < PMX_APPLY_NRECA * NR; e += 512) {
+  for (int e = tid; e < PMX_APPLY_NRECA * NR; e += M2M_THREADS) {
     const int m = e / NR, rr = e % NR;
     zd* o = out + ((int64_t)m * NR + rr) * 6;
     const zd z0 = zmk(0, 0);
-    o[0] = accA[M2M_MO + m][rr];
-    o[1] = m ? accA[M2M_MO - m][rr] : z0;
-    o[2] = accB[M2M_MO + m + 1][rr];
-    o[3] = m ? accB[M2M_MO - m + 1][rr] : z0;
-    o[4] = accB[M2M_MO + m - 1][rr];
-    o[5] = m ? accB[M2M_MO - m - 1][rr] : z0;
+    o[0] = An[rr][M2M_MO + m];
+    o[1] = m ? An[rr][M2M_MO - m] : z0;
+    o[2] = Bn[rr][M2M_MO + m + 1];
+    o[3] = m ? Bn[rr][M2M_MO - m + 1] : z0;
+    o[4] = Bn[rr][M2M_MO + m - 1];
+    o[5] = m ? Bn[rr][M2M_MO - m - 1] : z0;
   }
 }
 
@@ -538,12 +560,15 @@ __global__ __launch_bounds__(256) void k_apply_m2l_coef(ApplyArgs A, const doubl
 }
 
 // Part of a local expansion: the translated sources of work item blockIdx.x (a run of at
-// most PMX_FMM_CHUNK pairs of one slot), one wave, into the item's partial sums.  Lane l holds
-// the order m = l - 32 in pass 0, and m = 32 + l (l < 32) or l - 96 (l >= 32) in pass 1,
-// of A and B for every right-hand side; a pair with orders |m| <= mmax + 1 runs pass 1 only
-// when mmax + 1 >= 32.  Per pair the wave stages its table O_nu in LDS (read per lane);
-// the source's coefficients A_n, B_n (|n| <= nmax) are wave-uniform (scalar loads).
+// most PMX_FMM_CHUNK pairs of one slot), one wave, into the item's partial sums.  Lane l
+// holds the orders m = l - 32 (pass 0), and 32 j + l or l - 32 (j + 2) for l < 32 or
+// l >= 32 (pass j = 1, 2), for every right-hand side; a pair with orders |m| <= mmax + 1
+// runs the passes that hold them.  A and B are summed one after the other.  Per pair the
+// wave stages its table O_nu in LDS (read per lane); the source's coefficients A_n, B_n
+// (|n| <= nmax) are wave-uniform (scalar loads).
 constexpr int M2L_TAB = 2 * (PMX_FMM_PL + 1 + PMX_FMM_NMAX) + 1;   // largest table
+constexpr int M2L_PASS = 3;                                         // |m| <= 95
+static_assert(PMX_FMM_PL + 1 <= 32 * M2L_PASS - 1, "local orders beyond the passes");
 
 template <int NR>
 __global__ __launch_bounds__(64) void k_apply_m2l(ApplyArgs A) {
@@ -553,65 +578,60 @@ __global__ __launch_bounds__(64) void k_apply_m2l(ApplyArgs A) {
   const int lane = threadIdx.x;
   const int p = A.loc_p[t];
   const int q0 = A.m2l_item[3 * it + 1], q1 = A.m2l_item[3 * it + 2];
-  const int mj[2] = {lane - 32, lane < 32 ? lane + 32 : lane - 96};
+  int mj[M2L_PASS];
+  mj[0] = lane - 32;
+#pragma unroll
+  for (int j = 1; j < M2L_PASS; ++j) mj[j] = lane < 32 ? 32 * j + lane : lane - 32 * (j + 2);
   zd* loc = A.m2l_part + (int64_t)it * 2 * PMX_FMM_NL * NR;
-  double ar[2][2][NR], ai[2][2][NR];
+  for (int X = 0; X < 2; ++X) {
+    double ar[M2L_PASS][NR], ai[M2L_PASS][NR];
 #pragma unroll
-  for (int X = 0; X < 2; ++X)
+    for (int j = 0; j < M2L_PASS; ++j)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int rr = 0; rr < NR; ++rr) ar[j][rr] = ai[j][rr] = 0.0;
+    for (int q = q0; q < q1; ++q) {
+      const int S = A.m2l_src[q], nmax = A.m2l_nmax[q], mm = A.m2l_mmax[q] + 1;
+      const int V = mm + nmax;
+      const zd* tab = A.m2l_tab + A.m2l_toff[q];
+      const zd* xs = A.cm + (((int64_t)S * 2 + X) * M2L_NX + PMX_FMM_NMAX) * NR;   // X_n at xs[n NR + rr]
+      __syncthreads();   // the previous pair's table is read no more
+      for (int e = lane; e < 2 * V + 1; e += 64) tab_s[e] = tab[e];
+      __syncthreads();
+      const int npass = mm <= 31 ? 1 : (mm <= 63 ? 2 : 3);
+      bool ok[M2L_PASS];
+      int mc[M2L_PASS];
 #pragma unroll
-      for (int rr = 0; rr < NR; ++rr) ar[X][j][rr] = ai[X][j][rr] = 0.0;
-  for (int q = q0; q < q1; ++q) {
-    const int S = A.m2l_src[q], nmax = A.m2l_nmax[q], mm = A.m2l_mmax[q] + 1;
-    const int V = mm + nmax;
-    const zd* tab = A.m2l_tab + A.m2l_toff[q];
-    const zd* xa = A.cm + ((int64_t)S * 2 * M2L_NX + PMX_FMM_NMAX) * NR;   // A_n at xa[n NR + rr]
-    const zd* xb = xa + (int64_t)M2L_NX * NR;                             // B_n
-    __syncthreads();   // the previous pair's table is read no more
-    for (int e = lane; e < 2 * V + 1; e += 64) tab_s[e] = tab[e];
-    __syncthreads();
-    const int npass = mm >= 32 ? 2 : 1;
-    bool ok[2];
-    int mc[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      ok[j] = mj[j] >= -mm && mj[j] <= mm;
-      mc[j] = min(max(mj[j], -mm), mm);   // lanes outside the pair's orders read a valid entry and add 0
-    }
-#pragma unroll(NR <= 4 ? 2 : 1)
-    for (int n = -nmax; n <= nmax; ++n) {
-      zd x[2][NR];
-#pragma unroll
-      for (int rr = 0; rr < NR; ++rr) {
-        x[0][rr] = xa[n * NR + rr];
-        x[1][rr] = xb[n * NR + rr];
+      for (int j = 0; j < M2L_PASS; ++j) {
+        ok[j] = mj[j] >= -mm && mj[j] <= mm;
+        mc[j] = min(max(mj[j], -mm), mm);   // lanes outside the pair's orders read a valid entry and add 0
       }
+#pragma unroll(NR <= 4 ? 2 : 1)
+      for (int n = -nmax; n <= nmax; ++n) {
+        zd x[NR];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        if (j < npass) {
-          zd o = tab_s[n - mc[j] + V];
-          if (!ok[j]) o = zmk(0.0, 0.0);
+        for (int rr = 0; rr < NR; ++rr) x[rr] = xs[n * NR + rr];
 #pragma unroll
-          for (int X = 0; X < 2; ++X)
+        for (int j = 0; j < M2L_PASS; ++j) {
+          if (j < npass) {
+            zd o = tab_s[n - mc[j] + V];
+            if (!ok[j]) o = zmk(0.0, 0.0);
 #pragma unroll
             for (int rr = 0; rr < NR; ++rr) {
-              ar[X][j][rr] = fma(o.re, x[X][rr].re, fma(-o.im, x[X][rr].im, ar[X][j][rr]));
-              ai[X][j][rr] = fma(o.re, x[X][rr].im, fma(o.im, x[X][rr].re, ai[X][j][rr]));
+              ar[j][rr] = fma(o.re, x[rr].re, fma(-o.im, x[rr].im, ar[j][rr]));
+              ai[j][rr] = fma(o.re, x[rr].im, fma(o.im, x[rr].re, ai[j][rr]));
             }
+          }
         }
       }
     }
-  }
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int m = mj[j];
-    if (m >= -(p + 1) && m <= p + 1) {
-#pragma unroll
-      for (int X = 0; X < 2; ++X)
+    for (int j = 0; j < M2L_PASS; ++j) {
+      const int m = mj[j];
+      if (m >= -(p + 1) && m <= p + 1) {
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr)
-          loc[((int64_t)X * PMX_FMM_NL + (m + PMX_FMM_PL + 1)) * NR + rr] = zmk(ar[X][j][rr], ai[X][j][rr]);
+          loc[((int64_t)X * PMX_FMM_NL + (m + PMX_FMM_PL + 1)) * NR + rr] = zmk(ar[j][rr], ai[j][rr]);
+      }
     }
   }
 }
@@ -960,7 +980,8 @@ static void apply_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipS
   hipLaunchKernelGGL(k_apply_p2m<NR>, dim3(m), dim3(256), 0, s, A, (const double*)pk, r0);
   for (int l = 0; l < A.n_lev; ++l)
     if (A.lev_off[l + 1] > A.lev_off[l])
-      hipLaunchKernelGGL(k_apply_m2m<NR>, dim3(A.lev_off[l + 1] - A.lev_off[l]), dim3(512), 0, s, A, A.lev_off[l]);
+      hipLaunchKernelGGL(k_apply_m2m<NR>, dim3(A.lev_off[l + 1] - A.lev_off[l]), dim3(M2M_THREADS), 0, s, A,
+                         A.lev_off[l]);
   if (A.n_loc > 0) {
     const int nsrc = A.n_incl + A.lev_off[A.n_lev];   // sources with expansion records
     const int64_t ncm = (int64_t)nsrc * 2 * M2L_NX * NR;

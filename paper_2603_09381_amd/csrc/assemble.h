@@ -173,7 +173,7 @@ void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s);
 // part [nsplit + nsplit_near][nrhs][ld].
 #define PMX_APPLY_RATIO 3.0
 #define PMX_APPLY_PMAX 48
-#define PMX_APPLY_PMAXC 64   // largest order of a cluster expansion
+#define PMX_APPLY_PMAXC 96   // largest order of a cluster expansion
 // truncation of a far pair: orders until (r_j / rho_min)^p <= e^-PMX_APPLY_TRUNC, about 1e-17
 // (on the star grids the sources' own order, from k r_j, is the larger one for most pairs)
 #define PMX_APPLY_TRUNC 39.2
@@ -192,8 +192,8 @@ void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s);
 #ifndef PMX_FMM_RATIO
 #define PMX_FMM_RATIO (1.0 / 3.0)
 #endif
-#define PMX_FMM_PL 62     // at most 62: the m2l kernel's two passes hold orders -64 .. 63
-#define PMX_FMM_NMAX 48   // largest source order of a translated pair
+#define PMX_FMM_PL 94     // at most 94: the m2l kernel's three passes hold orders -96 .. 95
+#define PMX_FMM_NMAX 80   // largest source order of a translated pair (<= PMX_APPLY_PMAXC)
 #define PMX_FMM_CHUNK 32  // translated pairs per work item of the m2l kernel
 #define PMX_FMM_NL (2 * PMX_FMM_PL + 3)
 struct ApplyArgs {

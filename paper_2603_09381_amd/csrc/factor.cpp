@@ -1883,7 +1883,7 @@ void apply_geometry(const pmx_factor* F, const std::vector<double>& hx, const st
     nmax = std::max((int)gs[3], (int)std::ceil(PMX_APPLY_TRUNC / std::log((d - rt[T]) / gs[2])));
     mmax = std::max(apply_source_order(k * rt[T]), (int)std::ceil(PMX_APPLY_TRUNC / std::log((d - gs[2]) / rt[T])));
     mmax = std::min(mmax, ptgt[T]);
-    if (nmax > PMX_FMM_NMAX) return false;   // also within the stored records (PMX_APPLY_PMAX)
+    if (nmax > (S < m ? std::min(PMX_FMM_NMAX, PMX_APPLY_PMAX) : PMX_FMM_NMAX)) return false;   // within the records
     const double V = mmax + 1 + nmax, z = k * d;
     if (V > z && V * std::log(2.0 * V / (M_E * z)) > 600.0) return false;
     return true;

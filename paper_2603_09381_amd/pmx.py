@@ -76,6 +76,20 @@ KERNEL_NAMES = ["k_ts_leaf", "k_ts_update", "k_getrf_panel", "k_cpqr_update", "k
                 "k_trsm_small", "k_entries", "k_diag_pairs/maue", "k_apply_off", "k_getrs_small"]
 
 
+def _check_one_hip_runtime():
+    """Exactly one HIP runtime may be mapped into the process: a second copy next to
+    torch's (the library bound to another libamdhip64) gives device pointers that one of
+    them does not know, and the first GPU call crashes."""
+    try:
+        maps = open("/proc/self/maps").read().splitlines()
+    except OSError:
+        return
+    paths = {os.path.realpath(l.split()[-1]) for l in maps if "libamdhip64.so" in l and "/" in l}
+    if len(paths) > 1:
+        raise RuntimeError("two HIP runtimes are loaded (" + ", ".join(sorted(paths)) + "); libpmx.so must bind "
+                           "to the one torch loaded")
+
+
 def load(path=None):
     """Load libpmx.so (once)."""
     global _lib
@@ -88,6 +102,7 @@ def load(path=None):
     if not os.path.exists(p):
         raise RuntimeError(f"libpmx.so is not built ({p}); run __graft_entry__.build()")
     lib = C.CDLL(p)
+    _check_one_hip_runtime()
     vp = C.c_void_p
     lib.pmx_options_default.argtypes = [C.POINTER(Options)]
     lib.pmx_options_default.restype = None

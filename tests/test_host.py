@@ -187,4 +187,4 @@ def test_apply_structure_takes_every_pair_once(w):
     st = pmx.apply_structure(w, check=True)
     assert st["pairs_checked"] == st["waves"] * w.m
     assert st["coverage_violations"] == 0
-    assert st["max_local_order"] <= 62 and st["max_near_list"] >= 1
+    assert st["max_local_order"] <= 94 and st["max_near_list"] >= 1
