@@ -934,6 +934,83 @@ __global__ __launch_bounds__(64) void k_apply_near(ApplyArgs A, const double* __
   if (active) apply_store<NR>(A, A.part + (int64_t)(slot0 + y) * A.nrhs * A.ld, r0, nr, a, vr, vi, dr, di);
 }
 
+// Near pairs through stored coefficients.  Every (wave, near inclusion) pair has a block of
+// the four coefficients of apply_pair (value row: -e+ H0, k (n_s.d/r) H1; derivative row:
+// k (n_t.d/r) H1, (k/e+)(k a H0 + b H1)) for each source node and target lane, made once per
+// solve state: entry (b, c, lane) of block q at near_blk[near_blk_off[q] + (4 b + c) 64 +
+// lane].  The apply then streams them (coalesced) against the weighted densities.
+__global__ __launch_bounds__(64) void k_apply_near_build(ApplyArgs A) {
+  const int wv = blockIdx.x;
+  const int w0 = A.wave_node[2 * wv], wn = A.wave_node[2 * wv + 1];
+  const int lane = threadIdx.x;
+  const int a = w0 + (lane < wn ? lane : wn - 1);
+  const double ax = A.x[a], ay = A.y[a], anx = A.nx[a], any = A.ny[a];
+  const double k = A.k, eps = A.eps, ke = k / eps;
+  for (int q = A.near_off[wv]; q < A.near_off[wv + 1]; ++q) {
+    const int j = A.near_idx[q];
+    const int bb0 = (int)A.node_off[j], b1 = (int)A.node_off[j + 1];
+    zd* blk = A.near_blk + A.near_blk_off[q];
+    for (int b = bb0; b < b1; ++b) {
+      pmx_ctab tab = (pmx_ctab)pmx_far_table.v, ser = (pmx_ctab)pmx_series_table.v;
+      asm volatile("" : "+s"(tab), "+s"(ser));
+      const double d1 = ax - A.x[b], d2 = ay - A.y[b];
+      const double dd = d1 * d1 + d2 * d2;
+      const double ir = rsqrt_nr(dd);
+      const bes4 h = bessel01_t(k * (dd * ir), tab, ser);
+      const double snx = A.nx[b], sny = A.ny[b];
+      const double nsd = (snx * d1 + sny * d2) * ir;
+      const double ntd = (anx * d1 + any * d2) * ir;
+      const double aa = ntd * nsd;
+      const double bc = (anx * snx + any * sny - 2.0 * aa) * ir;
+      zd* e = blk + (int64_t)(b - bb0) * 4 * 64 + lane;
+      e[0] = zmk(-eps * h.j0, -eps * h.y0);
+      e[64] = zmk(k * nsd * h.j1, k * nsd * h.y1);
+      e[128] = zmk(k * ntd * h.j1, k * ntd * h.y1);
+      e[192] = zmk(ke * (k * aa * h.j0 + bc * h.j1), ke * (k * aa * h.y0 + bc * h.y1));
+    }
+  }
+}
+
+void asm_apply_near_build(const ApplyArgs& a, hipStream_t s) {
+  if (a.near_blk && a.n_waves > 0) hipLaunchKernelGGL(k_apply_near_build, dim3(a.n_waves), dim3(64), 0, s, a);
+}
+
+template <int NR>
+__global__ __launch_bounds__(64) void k_apply_near_blk(ApplyArgs A, const double* __restrict__ pk, int r0, int slot0) {
+  constexpr int S = APPLY_SRC(NR);
+  const int wv = blockIdx.x;
+  const int w0 = A.wave_node[2 * wv], wn = A.wave_node[2 * wv + 1];
+  const int lane = threadIdx.x;
+  const bool active = lane < wn;
+  const int a = w0 + (active ? lane : wn - 1);
+  const int nr = min(NR, A.nrhs - r0);
+  double vr[NR], vi[NR], dr[NR], di[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) vr[r] = vi[r] = dr[r] = di[r] = 0.0;
+  const int qs = A.near_off[wv], len = A.near_off[wv + 1] - qs;
+  const int ns = A.nsplit_near, y = blockIdx.y;
+  const int q0 = qs + (int)((int64_t)len * y / ns), q1 = qs + (int)((int64_t)len * (y + 1) / ns);
+  for (int q = q0; q < q1; ++q) {
+    const int j = A.near_idx[q];
+    const int bb0 = (int)A.node_off[j], b1 = (int)A.node_off[j + 1];
+    const zd* blk = A.near_blk + A.near_blk_off[q] + lane;
+    for (int b = bb0; b < b1; ++b) {
+      const zd* e = blk + (int64_t)(b - bb0) * 4 * 64;
+      const zd c1 = e[0], c2 = e[64], c3 = e[128], c4 = e[192];
+      const double* p = pk + (int64_t)b * S;
+#pragma unroll
+      for (int rr = 0; rr < NR; ++rr) {
+        const double qr = p[5 + 4 * rr], qi = p[6 + 4 * rr], ur = p[7 + 4 * rr], ui = p[8 + 4 * rr];
+        vr[rr] = fma(c1.re, qr, fma(-c1.im, qi, fma(c2.re, ur, fma(-c2.im, ui, vr[rr]))));
+        vi[rr] = fma(c1.re, qi, fma(c1.im, qr, fma(c2.re, ui, fma(c2.im, ur, vi[rr]))));
+        dr[rr] = fma(c3.re, qr, fma(-c3.im, qi, fma(c4.re, ur, fma(-c4.im, ui, dr[rr]))));
+        di[rr] = fma(c3.re, qi, fma(c3.im, qr, fma(c4.re, ui, fma(c4.im, ur, di[rr]))));
+      }
+    }
+  }
+  if (active) apply_store<NR>(A, A.part + (int64_t)(slot0 + y) * A.nrhs * A.ld, r0, nr, a, vr, vi, dr, di);
+}
+
 // out = sf f + sa (ydiag + sum of the partial sums); f may be NULL
 __global__ void k_apply_finish(const zd* f, const zd* ydiag, const zd* part, int nsplit, int64_t total, double sf,
                                double sa, zd* out) {
@@ -1003,8 +1080,12 @@ static void apply_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipS
 template <int NR>
 static void near_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipStream_t s) {
   hipLaunchKernelGGL(k_apply_pack<NR>, dim3((A.n_nodes + 255) / 256), dim3(256), 0, s, A, r0, pk);
-  hipLaunchKernelGGL(k_apply_near<NR>, dim3(A.n_waves, A.nsplit_near), dim3(64), 0, s, A, (const double*)pk, r0,
-                     nsplit);
+  if (A.near_blk)
+    hipLaunchKernelGGL(k_apply_near_blk<NR>, dim3(A.n_waves, A.nsplit_near), dim3(64), 0, s, A, (const double*)pk,
+                       r0, nsplit);
+  else
+    hipLaunchKernelGGL(k_apply_near<NR>, dim3(A.n_waves, A.nsplit_near), dim3(64), 0, s, A, (const double*)pk, r0,
+                       nsplit);
 }
 
 // groups of g right-hand sides: g = nr_max while enough remain; a last smaller group takes
@@ -1027,8 +1108,10 @@ void asm_apply_off(const ApplyArgs& A, int nsplit, int nr_max, hipStream_t s) {
     }
     r0 += g;
   }
+  // stored coefficients: the largest groups (the coefficients are read once per group)
+  const int nr_near = A.near_blk ? 16 : PMX_APPLY_NR_NEAR;
   for (int r0 = 0; r0 < A.nrhs;) {
-    const int g = group_size(A.nrhs - r0, PMX_APPLY_NR_NEAR);
+    const int g = group_size(A.nrhs - r0, nr_near);
     switch (g) {
       case 1: near_group<1>(A, A.pack, r0, nsplit, s); break;
       case 2: near_group<2>(A, A.pack, r0, nsplit, s); break;

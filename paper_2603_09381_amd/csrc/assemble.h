@@ -220,6 +220,8 @@ struct ApplyArgs {
   int n_incl, n_clus;
   int n_lev;             // cluster levels; level l holds clusters lev_off[l] .. lev_off[l + 1] - 1
   int lev_off[PMX_APPLY_MAXLEV + 1];
+  zd* near_blk;          // stored near coefficients (see k_apply_near_build) or NULL
+  const int64_t* near_blk_off;  // per near-list entry: offset of its block
   const int* wave_node;  // [n_waves][2]: first node and node count of each target wave
   int n_waves;
   // fast multipole part
@@ -252,6 +254,11 @@ struct ApplyArgs {
 // tables of the translations (once per solve state): O_nu(D) of every M2L pair and
 // I_nu(d) of every L2L pair
 void asm_apply_tables(const ApplyArgs& a, int n_m2l, int n_l2l, hipStream_t s);
+// the stored near coefficients (once per solve state), when a.near_blk is set
+void asm_apply_near_build(const ApplyArgs& a, hipStream_t s);
+// budget of the stored near coefficients; beyond it (or for fewer than 4 right-hand sides)
+// the near pairs are evaluated in every apply
+#define PMX_APPLY_NEAR_BYTES ((int64_t)48 << 30)
 // orders needed for the sources of an inclusion of radius r: the smallest p with
 // (e k r / 2p)^p <= 1e-17 and p > e k r / 2 + 2
 int apply_source_order(double kr);

@@ -1680,6 +1680,7 @@ struct DenseApply {
   double flops_fixed = 0, flops_rhs = 0;   // algorithmic work of one apply (counted with timing)
   double self_sq = 0;             // sum over inclusions of (2 n_j)^2: the FP64 self-block entries
   double table_bytes = 0;         // translation tables of the fast multipole part
+  double near_pairs_stored = 0;   // near (target, source node) pairs with stored coefficients
   int64_t total = 0;
   zd *ydiag = nullptr, *part = nullptr;
   double* d_norm = nullptr;
@@ -2112,7 +2113,7 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   aa.nrhs = nrhs;
   aa.ld = N2;
   aa.part = D.part;
-  aa.pack = A.alloc<double>(apply_pack_size(F->n_nodes, PMX_APPLY_NR_NEAR));
+  aa.pack = A.alloc<double>(apply_pack_size(F->n_nodes, std::max(PMX_APPLY_NR_NEAR, 16)));
   aa.near_off = A.upload(G.off, s);
   aa.near_idx = A.upload(G.idx, s);
   aa.far_off = A.upload(G.foff, s);
@@ -2173,6 +2174,26 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   aa.n_l2l_lev = (int)G.l2l_lev.size() - 1;
   for (int l = 0; l <= aa.n_l2l_lev; ++l) aa.l2l_lev[l] = G.l2l_lev[l];
   asm_apply_tables(aa, (int)G.m2l_src.size(), (int)G.l2l_child.size(), s);
+  // near pairs: the four coefficients of every (target, source node) pair stored once, when
+  // they fit the budget and at least four right-hand sides share them
+  aa.near_blk = nullptr;
+  aa.near_blk_off = nullptr;
+  D.near_pairs_stored = 0;
+  {
+    std::vector<int64_t> boff(G.idx.size());
+    int64_t tot = 0;
+    for (size_t q = 0; q < G.idx.size(); ++q) {
+      boff[q] = tot;
+      const int j = G.idx[q];
+      tot += 4 * 64 * (F->node_off[j + 1] - F->node_off[j]);
+    }
+    if (nrhs >= 4 && tot > 0 && 16 * tot <= PMX_APPLY_NEAR_BYTES) {
+      aa.near_blk = A.alloc<zd>(tot);
+      aa.near_blk_off = A.upload(boff, s);
+      asm_apply_near_build(aa, s);
+      D.near_pairs_stored = G.stats[5];
+    }
+  }
   D.table_bytes = 16.0 * (double)(G.m2l_tab + G.l2l_tab);
   D.n_src = F->m + G.n_clus;
   D.f = f;
@@ -2350,8 +2371,12 @@ void upload_angles(pmx_factor* F, const double* angles) {
 void count_apply_work(pmx_factor* F, int nrhs) {
   const DenseApply& D = F->ss->apply;
   const double N2 = 2.0 * F->n_nodes;
-  F->info.kernel_flops[PK_APPLY] += D.flops_fixed + D.flops_rhs * nrhs + 8.0 * D.self_sq * nrhs;
-  F->info.kernel_bytes[PK_APPLY] += 8.0 * 5 * F->n_nodes + 16.0 * D.self_sq + 16.0 * N2 * nrhs * 3;
+  // with stored near coefficients, their evaluation (130 flops a pair) leaves the apply and
+  // their reading (four complex numbers a pair) enters it
+  F->info.kernel_flops[PK_APPLY] +=
+      D.flops_fixed - 130.0 * D.near_pairs_stored + D.flops_rhs * nrhs + 8.0 * D.self_sq * nrhs;
+  F->info.kernel_bytes[PK_APPLY] +=
+      8.0 * 5 * F->n_nodes + 16.0 * D.self_sq + 16.0 * N2 * nrhs * 3 + 64.0 * D.near_pairs_stored;
 }
 
 // FP64 factor: right-hand side into the leaf vectors, one solve pass, solution to xout.
