@@ -66,6 +66,8 @@ def parse():
     p.add_argument("--no-check", action="store_true", help="no reference solve and no oracle residual")
     p.add_argument("--no-plain", action="store_true", help="time the tuned form only")
     p.add_argument("--plain-only", action="store_true", help="time the plain form only (profiling runs)")
+    p.add_argument("--no-scattered", action="store_true",
+                   help="skip the secondary line: 400 scattered uneven inclusions (batched uneven cells)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="run a 256 MiB device copy first (reference kernel for HBM counters)")
     p.add_argument("--no-timing", action="store_true", help="no HIP events at all (no roofline, no shares)")
@@ -363,6 +365,27 @@ def run_form(pmx, w, kw, steps, warmup, timing):
     return times, infos, dens, (k, top, share)
 
 
+def scattered_line(pmx, W, steps=2):
+    """Secondary measurement, not the headline: 400 scattered inclusions of uneven shapes,
+    sizes and node counts (72..256) at k+ = 12 with per-inclusion contrasts (161,064
+    unknowns, 4 plane waves, adaptive quadtree of 7 levels): both forms, one warm-up and
+    `steps` timed factor + solve steps each, built-in launch rules, and the tuned form's
+    error against the plain one."""
+    import torch
+    w = W.config3()
+    out = {"workload": "400 scattered uneven inclusions, k+=12, N=%d, %d plane waves" % (w.n_unknowns, len(w.angles))}
+    dens = {}
+    for name, kw in (("tuned", FORMS["tuned"]), ("plain", FORMS["plain"])):
+        times, infos, d, _ = run_form(pmx, w, kw, steps, 1, 0)
+        out[name] = {"ms_per_step": 1e3 * sum(times) / steps, "unknowns_per_s": w.n_unknowns * steps / sum(times),
+                     "factor_ms": infos[-1].t_factor_ms, "solve_ms": infos[-1].t_solve_ms,
+                     "refinement_steps": infos[-1].ir_iterations}
+        dens[name] = d
+    out["tuned_rel_error_vs_plain"] = rel_error(dens["tuned"], dens["plain"])
+    torch.cuda.synchronize()
+    return out
+
+
 def rel_error(a, b):
     import torch
     return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
@@ -495,6 +518,9 @@ def main():
         acc["meets_target"] = bool(worst <= TARGET_ERROR)
         res["accuracy"] = acc
         print("bench: accuracy checks done", file=sys.stderr, flush=True)
+    if not a.no_scattered:
+        res["scattered_uneven"] = scattered_line(pmx, W)
+        print("bench: scattered workload done", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, N)
     print(json.dumps(res), flush=True)

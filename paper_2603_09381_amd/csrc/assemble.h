@@ -190,7 +190,7 @@ void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s);
 // fast multipole part: separation ratio of a translated pair, largest local order, and the
 // local-expansion orders kept per target (m = -(PMX_FMM_PL + 1) .. PMX_FMM_PL + 1)
 #ifndef PMX_FMM_RATIO
-#define PMX_FMM_RATIO (1.0 / 3.0)
+#define PMX_FMM_RATIO 0.5
 #endif
 #define PMX_FMM_PL 94     // at most 94: the m2l kernel's three passes hold orders -96 .. 95
 #define PMX_FMM_NMAX 80   // largest source order of a translated pair (<= PMX_APPLY_PMAXC)
