@@ -326,6 +326,24 @@ def summarize_counters(csv_paths, out_md, title):
     print("\n".join(lines[:40]))
 
 
+def summarize_stats(stats_csv, out_md, title, command):
+    """A rocprofv3 --kernel-trace --stats summary (run_kernel_stats.csv) as a markdown table,
+    with the command that made it."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# {title}", "", "Command (from the repository root, after `cd /tmp && export TMPDIR=/tmp`):", "",
+             "```", command, "```", "", f"Total kernel time: {tot / 1e6:.1f} ms.", "",
+             "| kernel | calls | total ms | average us | share |", "|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        t = float(r["TotalDurationNs"])
+        if t < 0.002 * tot:
+            continue
+        lines.append(f"| `{r['Name'].split('(')[0].replace('void ', '')[:70]}` | {r['Calls']} | {t / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {t / tot:.3f} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
 def run_form(pmx, w, kw, steps, warmup, timing):
     """Warm-up steps time every kernel (time shares, dominant kernel); the timed steps time
     only the dominant counted kernel, so that events around the other launches do not
@@ -394,6 +412,10 @@ def rel_error(a, b):
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-pmc":
         summarize_pmc(*sys.argv[2:7])
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-stats":
+        # --summarize-stats STATS.csv OUT.md TITLE COMMAND
+        summarize_stats(*sys.argv[2:6])
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
         # --summarize-counters OUT.md TITLE CSV [CSV ...]
