@@ -244,8 +244,9 @@ def roofline(info_list, k, top, names, real_bytes, tag, thash):
 
 # timer slots that cover several kernels launched back to back: the parts whose dispatches
 # are summed, and the part launched exactly once per launch of the slot
-SLOT_KERNELS = {"k_apply_off": (("k_apply_pack", "k_apply_p2m", "k_apply_m2m", "k_apply_far", "k_apply_near",
-                                 "k_zgemm<double", "k_apply_finish"), "k_apply_finish")}
+SLOT_KERNELS = {"k_apply_off": (("k_apply_pack", "k_apply_p2m", "k_apply_m2m", "k_apply_m2l_coef", "k_apply_m2l",
+                                 "k_apply_m2l_sum", "k_apply_l2l", "k_apply_far", "k_apply_near",
+                                 "k_apply_near_blk", "k_zgemm<double", "k_apply_finish"), "k_apply_finish")}
 
 
 def summarize_pmc(fetch_csv, write_csv, kname, tag, table_path=None):
@@ -296,7 +297,7 @@ def summarize_pmc(fetch_csv, write_csv, kname, tag, table_path=None):
     print(json.dumps(out))
 
 
-def summarize_counters(csv_paths, out_md, title):
+def summarize_counters(csv_paths, out_md, title, commands=()):
     """Per-kernel sums of rocprofv3 --pmc counter files (one or more runs, each with its own
     counters) as a markdown table: dispatches, every counter's total, and the derived FP64
     VALU flops (64 lanes x (2 FMA + ADD + MUL + TRANS) per wave instruction, every lane
@@ -312,7 +313,11 @@ def summarize_counters(csv_paths, out_md, title):
             disp[name].add(r.get("Dispatch_Id", r.get("Correlation_Id", "")))
     counters = sorted({c for k in tot for c in tot[k]})
     rows = sorted(tot, key=lambda k: -max(tot[k].values()))
-    lines = [f"# {title}", "", "| kernel | dispatches | " + " | ".join(counters) + " | FP64 VALU flops | MFMA F64 flops | MFMA F32 flops |",
+    lines = [f"# {title}", ""]
+    if commands:
+        lines += ["Commands (from the repository root, after `cd /tmp && export TMPDIR=/tmp`), one counter "
+                  "set per run:", "", "```"] + list(commands) + ["```", ""]
+    lines += ["| kernel | dispatches | " + " | ".join(counters) + " | FP64 VALU flops | MFMA F64 flops | MFMA F32 flops |",
              "|---" * (len(counters) + 5) + "|"]
     for k in rows:
         c = tot[k]
@@ -418,8 +423,11 @@ def main():
         summarize_stats(*sys.argv[2:6])
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
-        # --summarize-counters OUT.md TITLE CSV [CSV ...]
-        summarize_counters(sys.argv[4:], sys.argv[2], sys.argv[3])
+        # --summarize-counters OUT.md TITLE CSV [CSV ...] [--command CMD ...]
+        rest = sys.argv[4:]
+        csvs = [a for i, a in enumerate(rest) if a != "--command" and (i == 0 or rest[i - 1] != "--command")]
+        cmds = [rest[i + 1] for i, a in enumerate(rest) if a == "--command"]
+        summarize_counters(csvs, sys.argv[2], sys.argv[3], cmds)
         return
     a = parse()
     if a.gpus != 1:
@@ -433,8 +441,9 @@ def main():
     # FP64 factor holds ~37 GB; the GPU has 288 GB)
     pmx.device_cache(64 << 30)
     if a.copy_calibration:
-        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        src = torch.full((256 << 20,), 1, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
+        torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
