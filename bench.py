@@ -246,7 +246,8 @@ def roofline(info_list, k, top, names, real_bytes, tag, thash):
 # are summed, and the part launched exactly once per launch of the slot
 SLOT_KERNELS = {"k_apply_off": (("k_apply_pack", "k_apply_p2m", "k_apply_m2m", "k_apply_m2l_coef", "k_apply_m2l",
                                  "k_apply_m2l_sum", "k_apply_l2l", "k_apply_far", "k_apply_near",
-                                 "k_apply_near_blk", "k_zgemm<double", "k_apply_finish"), "k_apply_finish")}
+                                 "k_apply_near_blk", "k_zgemm<double", "k_apply_finish"), "k_apply_finish"),
+                "k_ts_update": (("k_ts_update_f64", "k_ts_update_f32"), None)}
 
 
 def summarize_pmc(fetch_csv, write_csv, kname, tag, table_path=None):
@@ -260,6 +261,7 @@ def summarize_pmc(fetch_csv, write_csv, kname, tag, table_path=None):
     import csv
     base = kname.split("<")[0]
     parts, once = SLOT_KERNELS.get(kname, ((kname,), kname))
+    # the slot's dispatches: a slot of one kernel per launch (once None) counts them all
 
     def matches(name, part):
         if "<" in part:
@@ -267,7 +269,7 @@ def summarize_pmc(fetch_csv, write_csv, kname, tag, table_path=None):
         return name.startswith(part + "(") or name.startswith("void " + part + "<") or name == part
 
     def load(path, counter):
-        per, copy = {p: [] for p in parts}, []
+        per, copy, elem = {p: [] for p in parts}, [], []
         for r in csv.DictReader(open(path)):
             if r["Counter_Name"] != counter:
                 continue
@@ -278,19 +280,24 @@ def summarize_pmc(fetch_csv, write_csv, kname, tag, table_path=None):
                 per[hit[0]].append(v)
             elif name.startswith("__amd_rocclr_copyBuffer") and not copy:
                 copy.append(v)   # the first runtime copy of the run: the 256 MiB calibration copy
-        return per, copy
+            elif "MulFunctor" in name and not elem:
+                elem.append(v)   # the first elementwise multiply: the 256 MiB elementwise copy
+        return per, copy, elem
 
-    fetch, cf = load(fetch_csv, "FETCH_SIZE")
-    write, cw = load(write_csv, "WRITE_SIZE")
+    fetch, cf, ef = load(fetch_csv, "FETCH_SIZE")
+    write, cw, ew = load(write_csv, "WRITE_SIZE")
     ref = float(256 << 20)
     ff = cf[0] / ref if cf else 1.0
     fw = cw[0] / ref if cw else 1.0
-    nl = len(fetch[once])
+    nl = len(fetch[once]) if once else sum(len(fetch[p]) for p in parts)
     fb = sum(np.sum(fetch[p]) for p in parts) / nl / ff
     wb = sum(np.sum(write[p]) for p in parts) / nl / fw
     out = {"kernel": base, "instantiation": kname, "parts": list(parts), "workload": tag,
            "source_hash": kernel_source_hash(base), "table_hash": table_hash(table_path),
            "bytes_per_launch": fb + wb, "launches": nl, "fetch_scale": ff, "write_scale": fw,
+           "elementwise_copy_fetch_scale": ef[0] / ref if ef else None,
+           "elementwise_copy_write_scale": ew[0] / ref if ew else None,
+           "unscaled_bytes_per_launch": (sum(np.sum(fetch[p]) for p in parts) + sum(np.sum(write[p]) for p in parts)) / nl,
            "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
            "dispatches": {p: len(fetch[p]) for p in parts}}
     json.dump(out, open(traffic_file(base, tag), "w"), indent=1)
@@ -444,7 +451,9 @@ def main():
         src = torch.full((256 << 20,), 1, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        dst.copy_(src)                                                     # the runtime's copy kernel
+        torch.cuda.synchronize()
+        torch.mul(src.view(torch.float32), 1.0, out=dst.view(torch.float32))   # an elementwise copy
         torch.cuda.synchronize()
         del src, dst
     w = W.config4(a.grid)

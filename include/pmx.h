@@ -95,7 +95,10 @@ typedef struct {
   int32_t reserved0;
   const char* tune_path;   /* launch-parameter table written by pmx_autotune (read at create);
                               NULL: built-in rules */
-  int32_t reserved[4];
+  int32_t refactor;        /* 1: keep the numeric phase of the factorisation (its buffers,
+                              descriptors and launch sequence) for pmx_factor_refactor; not
+                              with learned = 1 */
+  int32_t reserved[3];
 } pmx_options;
 
 typedef struct {
@@ -138,6 +141,16 @@ typedef struct {
    * node) pairs, 6 (target node, far source) pairs evaluated directly, 7 bytes of the
    * translation tables */
   double apply_stats[8];
+  /* host-side counts of the factorisation (create): kernel launches and host waits on the
+   * device (downloads of ranks, pivots and LU checks, CPQR progress polls) */
+  int64_t factor_launches;
+  int64_t factor_host_syncs;
+  /* last pmx_factor_refactor: launches from the host (1: the graph), kernel nodes of the
+   * replayed graph, host waits, and its host wall time (synchronised) */
+  int64_t refactor_launches;
+  int64_t refactor_graph_nodes;
+  int64_t refactor_host_syncs;
+  double t_refactor_ms;
 } pmx_info;
 
 typedef struct pmx_factor pmx_factor;
@@ -187,6 +200,20 @@ pmx_status pmx_far_field_noalloc(const pmx_factor* f, int32_t nrhs, const pmx_c6
                                  const double* dirs, pmx_c64* out, void* hip_stream);
 
 pmx_status pmx_factor_info(const pmx_factor* f, pmx_info* info);
+
+/* Factors again for new interior media of the same inclusions.  In the PMCHWT-Omit system
+ * (Sec. 2) the off-diagonal blocks, and with them every interpolative decomposition
+ * (skeletons, interpolation matrices, ranks) and every size, use the exterior kernels
+ * alone; only the self blocks depend on the interior media.  This call replays the
+ * numeric phase of the factorisation kept at create (options.refactor = 1): self blocks,
+ * Schur complements, parent blocks and the top LU, the same launches on the same device
+ * buffers, as one HIP graph captured at the first call, followed by one wait for the
+ * LU pivot checks.  k_int (host, [m]) > 0; eps_int (host, [m]) or NULL for
+ * eps_ext (k_int / k_ext)^2.  Later solves use the new media, and give bit for bit what a
+ * factor created with them gives.  Ordered after earlier work on hip_stream and on the
+ * factor's solves; returns when the factor is complete.  Errors: PMX_EINVAL (factor
+ * created without options.refactor, bad values), PMX_EHIP, PMX_ESINGULAR. */
+pmx_status pmx_factor_refactor(pmx_factor* f, const double* k_int, const double* eps_int, void* hip_stream);
 
 /* Autotuner of the launch parameters of the batched form.  Launches whose kernel has
  * alternatives (the LU panel kernel, the column-pivoted QR variant, the level-solve

@@ -537,9 +537,9 @@ __global__ __launch_bounds__(256) void k_apply_l2l_tab(ApplyArgs A, int n_pairs)
 
 void asm_apply_tables(const ApplyArgs& a, int n_m2l, int n_l2l, hipStream_t s) {
   if (n_m2l > 0)
-    hipLaunchKernelGGL(k_apply_m2l_tab, dim3((n_m2l + 255) / 256), dim3(256), 0, s, a, n_m2l);
+    PMX_LAUNCH(k_apply_m2l_tab, dim3((n_m2l + 255) / 256), dim3(256), 0, s, a, n_m2l);
   if (n_l2l > 0)
-    hipLaunchKernelGGL(k_apply_l2l_tab, dim3((n_l2l + 255) / 256), dim3(256), 0, s, a, n_l2l);
+    PMX_LAUNCH(k_apply_l2l_tab, dim3((n_l2l + 255) / 256), dim3(256), 0, s, a, n_l2l);
 }
 
 // The translated sources' coefficients in the layout the m2l kernel reads: per source,
@@ -972,7 +972,7 @@ __global__ __launch_bounds__(64) void k_apply_near_build(ApplyArgs A) {
 }
 
 void asm_apply_near_build(const ApplyArgs& a, hipStream_t s) {
-  if (a.near_blk && a.n_waves > 0) hipLaunchKernelGGL(k_apply_near_build, dim3(a.n_waves), dim3(64), 0, s, a);
+  if (a.near_blk && a.n_waves > 0) PMX_LAUNCH(k_apply_near_build, dim3(a.n_waves), dim3(64), 0, s, a);
 }
 
 template <int NR>
@@ -1052,26 +1052,26 @@ int apply_source_order(double kr) {
 
 template <int NR>
 static void apply_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipStream_t s) {
-  hipLaunchKernelGGL(k_apply_pack<NR>, dim3((A.n_nodes + 255) / 256), dim3(256), 0, s, A, r0, pk);
+  PMX_LAUNCH(k_apply_pack<NR>, dim3((A.n_nodes + 255) / 256), dim3(256), 0, s, A, r0, pk);
   const int m = (int)A.n_incl;
-  hipLaunchKernelGGL(k_apply_p2m<NR>, dim3(m), dim3(256), 0, s, A, (const double*)pk, r0);
+  PMX_LAUNCH(k_apply_p2m<NR>, dim3(m), dim3(256), 0, s, A, (const double*)pk, r0);
   for (int l = 0; l < A.n_lev; ++l)
     if (A.lev_off[l + 1] > A.lev_off[l])
-      hipLaunchKernelGGL(k_apply_m2m<NR>, dim3(A.lev_off[l + 1] - A.lev_off[l]), dim3(M2M_THREADS), 0, s, A,
+      PMX_LAUNCH(k_apply_m2m<NR>, dim3(A.lev_off[l + 1] - A.lev_off[l]), dim3(M2M_THREADS), 0, s, A,
                          A.lev_off[l]);
   if (A.n_loc > 0) {
     const int nsrc = A.n_incl + A.lev_off[A.n_lev];   // sources with expansion records
     const int64_t ncm = (int64_t)nsrc * 2 * M2L_NX * NR;
-    hipLaunchKernelGGL(k_apply_m2l_coef<NR>, dim3((unsigned)((ncm + 255) / 256)), dim3(256), 0, s, A,
+    PMX_LAUNCH(k_apply_m2l_coef<NR>, dim3((unsigned)((ncm + 255) / 256)), dim3(256), 0, s, A,
                        (const double*)A.coef, nsrc);
-    if (A.n_m2l_items > 0) hipLaunchKernelGGL(k_apply_m2l<NR>, dim3(A.n_m2l_items), dim3(64), 0, s, A);
+    if (A.n_m2l_items > 0) PMX_LAUNCH(k_apply_m2l<NR>, dim3(A.n_m2l_items), dim3(64), 0, s, A);
     const int64_t nl = (int64_t)A.n_loc * 2 * PMX_FMM_NL * NR;
-    hipLaunchKernelGGL(k_apply_m2l_sum<NR>, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s, A);
+    PMX_LAUNCH(k_apply_m2l_sum<NR>, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s, A);
     for (int l = 0; l < A.n_l2l_lev; ++l)
       if (A.l2l_lev[l + 1] > A.l2l_lev[l])
-        hipLaunchKernelGGL(k_apply_l2l<NR>, dim3(A.l2l_lev[l + 1] - A.l2l_lev[l]), dim3(64), 0, s, A, A.l2l_lev[l]);
+        PMX_LAUNCH(k_apply_l2l<NR>, dim3(A.l2l_lev[l + 1] - A.l2l_lev[l]), dim3(64), 0, s, A, A.l2l_lev[l]);
   }
-  hipLaunchKernelGGL(k_apply_far<NR>, dim3((A.n_waves + 3) / 4, nsplit), dim3(256), 0, s, A, (const double*)A.coef,
+  PMX_LAUNCH(k_apply_far<NR>, dim3((A.n_waves + 3) / 4, nsplit), dim3(256), 0, s, A, (const double*)A.coef,
                      r0);
 }
 
@@ -1079,12 +1079,12 @@ static void apply_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipS
 // once per group, so the near part takes the largest groups)
 template <int NR>
 static void near_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipStream_t s) {
-  hipLaunchKernelGGL(k_apply_pack<NR>, dim3((A.n_nodes + 255) / 256), dim3(256), 0, s, A, r0, pk);
+  PMX_LAUNCH(k_apply_pack<NR>, dim3((A.n_nodes + 255) / 256), dim3(256), 0, s, A, r0, pk);
   if (A.near_blk)
-    hipLaunchKernelGGL(k_apply_near_blk<NR>, dim3(A.n_waves, A.nsplit_near), dim3(64), 0, s, A, (const double*)pk,
+    PMX_LAUNCH(k_apply_near_blk<NR>, dim3(A.n_waves, A.nsplit_near), dim3(64), 0, s, A, (const double*)pk,
                        r0, nsplit);
   else
-    hipLaunchKernelGGL(k_apply_near<NR>, dim3(A.n_waves, A.nsplit_near), dim3(64), 0, s, A, (const double*)pk, r0,
+    PMX_LAUNCH(k_apply_near<NR>, dim3(A.n_waves, A.nsplit_near), dim3(64), 0, s, A, (const double*)pk, r0,
                        nsplit);
 }
 
@@ -1126,7 +1126,7 @@ void asm_apply_off(const ApplyArgs& A, int nsplit, int nr_max, hipStream_t s) {
 void asm_apply_finish(const zd* f, const zd* ydiag, const zd* part, int nsplit, int64_t total, double sf, double sa,
                       zd* out, hipStream_t s) {
   if (total <= 0) return;
-  hipLaunchKernelGGL(k_apply_finish, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, f, ydiag, part, nsplit,
+  PMX_LAUNCH(k_apply_finish, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, f, ydiag, part, nsplit,
                      total, sf, sa, out);
 }
 
@@ -1151,5 +1151,5 @@ __global__ __launch_bounds__(256) void k_colnorm2(const zd* a, int64_t n, int64_
 
 void asm_colnorm2(const zd* a, int64_t n, int ncol, int64_t ld, int nblk, double* part, hipStream_t s) {
   if (n <= 0 || ncol <= 0) return;
-  hipLaunchKernelGGL(k_colnorm2, dim3(nblk, ncol), dim3(256), 0, s, a, n, ld, part);
+  PMX_LAUNCH(k_colnorm2, dim3(nblk, ncol), dim3(256), 0, s, a, n, ld, part);
 }

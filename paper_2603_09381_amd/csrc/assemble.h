@@ -108,6 +108,8 @@ template <class R>
 void asm_identity(const Mat2T<R>* d, int batch, int max_n, hipStream_t s);
 template <class R>
 void asm_zero(cx<R>* p, int64_t n, hipStream_t s);
+// p[0 .. n) = 0 by a kernel (a node that graph capture records like any launch)
+void asm_zero_i32(int* p, int64_t n, hipStream_t s);
 // dst[i] = src[i] converted to the destination's real type
 template <class RS, class RD>
 void asm_convert(const cx<RS>* src, cx<RD>* dst, int64_t n, hipStream_t s);

@@ -105,7 +105,7 @@ void asm_geometry(const double* dx, const double* dy, const double* ddx, const d
                   const int* owner, const int64_t* node_off, double* nx, double* ny, double* w,
                   double* speed, double* kappa, int n_nodes, hipStream_t s) {
   if (n_nodes <= 0) return;
-  hipLaunchKernelGGL(k_geometry, dim3((n_nodes + 255) / 256), dim3(256), 0, s, dx, dy, ddx, ddy,
+  PMX_LAUNCH(k_geometry, dim3((n_nodes + 255) / 256), dim3(256), 0, s, dx, dy, ddx, ddy,
                      owner, node_off, nx, ny, w, speed, kappa, n_nodes);
 }
 
@@ -130,7 +130,7 @@ __global__ void k_tables(const int* ns, const int* tbl_off, double* R, double* d
 void asm_tables(const int* ns, const int* tbl_off, int ntbl, int max_n, double* R, double* dt,
                 hipStream_t s) {
   if (ntbl <= 0) return;
-  hipLaunchKernelGGL(k_tables, dim3((max_n + 127) / 128, ntbl), dim3(128), 0, s, ns, tbl_off, R, dt);
+  PMX_LAUNCH(k_tables, dim3((max_n + 127) / 128, ntbl), dim3(128), 0, s, ns, tbl_off, R, dt);
 }
 
 // ---------------------------------------------------------------------------------
@@ -276,14 +276,14 @@ void asm_diag(DevGeom g, ExtParams e, const DiagDesc* d, int batch, int max_n, c
   if (batch <= 0 || max_n <= 0) return;
   dim3 grid((max_n * max_n + 255) / 256, batch);
   KScope ks(PK_DIAG, s);
-  hipLaunchKernelGGL(k_diag_pairs, grid, dim3(256), 0, s, g, e, d, R);
+  PMX_LAUNCH(k_diag_pairs, grid, dim3(256), 0, s, g, e, d, R);
   const size_t shm = 2 * (size_t)max_n * sizeof(double);
   if (shm > 64 * 1024) {
     (void)hipFuncSetAttribute((const void*)k_diag_maue1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     (void)hipFuncSetAttribute((const void*)k_diag_maue2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
   }
-  hipLaunchKernelGGL(k_diag_maue1, grid, dim3(256), shm, s, g, d, dt);
-  hipLaunchKernelGGL(k_diag_maue2, grid, dim3(256), shm / 2, s, g, d, dt);
+  PMX_LAUNCH(k_diag_maue1, grid, dim3(256), shm, s, g, d, dt);
+  PMX_LAUNCH(k_diag_maue2, grid, dim3(256), shm / 2, s, g, d, dt);
 }
 
 // ---------------------------------------------------------------------------------
@@ -310,7 +310,7 @@ void asm_entries(DevGeom g, DevProxy p, ExtParams e, const EntryMatT<R>* d, int 
   if (batch <= 0 || max_a <= 0 || max_b <= 0) return;
   dim3 grid((max_a + ENT_ROWS - 1) / ENT_ROWS, (max_b + ENT_COLS - 1) / ENT_COLS, batch);
   KScope ks(PK_ENTRIES, s);
-  hipLaunchKernelGGL(k_entries<R>, grid, dim3(256), 0, s, g, p, e, d);
+  PMX_LAUNCH(k_entries<R>, grid, dim3(256), 0, s, g, p, e, d);
 }
 
 template <class R>
@@ -337,7 +337,7 @@ template <class R>
 void asm_parent(DevGeom g, ExtParams e, const ParentDescT<R>* d, int batch, int max_s, hipStream_t s) {
   if (batch <= 0 || max_s <= 0) return;
   int64_t tot = (int64_t)max_s * max_s;
-  hipLaunchKernelGGL(k_parent<R>, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, s, g, e, d);
+  PMX_LAUNCH(k_parent<R>, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, s, g, e, d);
 }
 
 // ---------------------------------------------------------------------------------
@@ -370,7 +370,7 @@ void asm_incident(DevGeom g, ExtParams e, const int* cell_node0, const int* cell
                   zd* f, hipStream_t s) {
   if (ncell <= 0 || nrhs <= 0) return;
   dim3 grid((2 * max_n + 127) / 128, nrhs, ncell);
-  hipLaunchKernelGGL(k_incident, grid, dim3(128), 0, s, g, e, cell_node0, cell_n, cell_off,
+  PMX_LAUNCH(k_incident, grid, dim3(128), 0, s, g, e, cell_node0, cell_n, cell_off,
                      angles, nrhs, f);
 }
 
@@ -395,9 +395,9 @@ void asm_gather(const cx<RS>* src, const GatherDescT<RD>* d, int batch, int max_
   if (batch <= 0 || max_rows <= 0 || max_cols <= 0) return;
   dim3 grid((max_rows + 63) / 64, (max_cols + 3) / 4, batch);
   if (acc)
-    hipLaunchKernelGGL((k_gather<RS, RD, true>), grid, dim3(256), 0, s, src, d);
+    PMX_LAUNCH((k_gather<RS, RD, true>), grid, dim3(256), 0, s, src, d);
   else
-    hipLaunchKernelGGL((k_gather<RS, RD, false>), grid, dim3(256), 0, s, src, d);
+    PMX_LAUNCH((k_gather<RS, RD, false>), grid, dim3(256), 0, s, src, d);
 }
 
 template <class R>
@@ -413,7 +413,7 @@ template <class R>
 void asm_identity(const Mat2T<R>* d, int batch, int max_n, hipStream_t s) {
   if (batch <= 0 || max_n <= 0) return;
   int64_t tot = (int64_t)max_n * max_n;
-  hipLaunchKernelGGL(k_identity<R>, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, s, d);
+  PMX_LAUNCH(k_identity<R>, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, s, d);
 }
 
 template <class R>
@@ -425,7 +425,17 @@ __global__ void k_zero(cx<R>* p, int64_t n) {
 template <class R>
 void asm_zero(cx<R>* p, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_zero<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  PMX_LAUNCH(k_zero<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+}
+
+__global__ void k_zero_i32(int* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+void asm_zero_i32(int* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  PMX_LAUNCH(k_zero_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
 }
 
 template <class RS, class RD>
@@ -437,7 +447,7 @@ __global__ void k_convert(const cx<RS>* src, cx<RD>* dst, int64_t n) {
 template <class RS, class RD>
 void asm_convert(const cx<RS>* src, cx<RD>* dst, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL((k_convert<RS, RD>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  PMX_LAUNCH((k_convert<RS, RD>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
 }
 
 // block t of dst = block of src at soff[t], rounded to RD (len[t] entries each)
@@ -455,7 +465,7 @@ void asm_convert_blocks(const zd* src, cx<RD>* dst, const int64_t* d_soff, const
                         const int64_t* d_len, int nblocks, int64_t max_len, hipStream_t s) {
   if (nblocks <= 0 || max_len <= 0) return;
   const unsigned gx = (unsigned)std::min<int64_t>(64, (max_len + 255) / 256);
-  hipLaunchKernelGGL(k_convert_blocks<RD>, dim3(gx, nblocks), dim3(256), 0, s, src, dst, d_soff, d_doff, d_len);
+  PMX_LAUNCH(k_convert_blocks<RD>, dim3(gx, nblocks), dim3(256), 0, s, src, dst, d_soff, d_doff, d_len);
 }
 
 __global__ void k_axpy(zd* y, const zd* x, zd a, int64_t n) {
@@ -465,7 +475,7 @@ __global__ void k_axpy(zd* y, const zd* x, zd a, int64_t n) {
 
 void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, x, a, n);
+  PMX_LAUNCH(k_axpy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, x, a, n);
 }
 
 // ---------------------------------------------------------------------------------
@@ -580,11 +590,11 @@ void asm_far_field(DevGeom g, ExtParams e, const int* owner, const int64_t* node
       D.s[a] = std::sin(th);
     }
     const dim3 grid((D.nt + PMX_FF_GROUP - 1) / PMX_FF_GROUP, nrhs, nsplit);
-    hipLaunchKernelGGL(k_far_field_part, grid, dim3(256), 0, s, g, e, owner, node_off, dens, nrhs, D, ndir,
+    PMX_LAUNCH(k_far_field_part, grid, dim3(256), 0, s, g, e, owner, node_off, dens, nrhs, D, ndir,
                        chunk, part);
   }
   const int64_t n = (int64_t)nrhs * ndir;
-  hipLaunchKernelGGL(k_far_field_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nsplit, nrhs,
+  PMX_LAUNCH(k_far_field_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nsplit, nrhs,
                      ndir, e.k, out);
 }
 
@@ -644,7 +654,7 @@ void asm_build_l(const LDescT<R>* d, int batch, int max_s, int max_k, hipStream_
   (void)max_k;
   if (batch <= 0 || max_s <= 0) return;
   dim3 grid((max_s + 127) / 128, 2, batch);
-  hipLaunchKernelGGL(k_build_l<R>, grid, dim3(128), 0, s, d);
+  PMX_LAUNCH(k_build_l<R>, grid, dim3(128), 0, s, d);
 }
 
 __global__ void k_probe_bessel(const double* z, int64_t n, double* out) {
@@ -659,7 +669,7 @@ __global__ void k_probe_bessel(const double* z, int64_t n, double* out) {
 
 void asm_probe_bessel(const double* z, int64_t n, double* out, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_probe_bessel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, n, out);
+  PMX_LAUNCH(k_probe_bessel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, z, n, out);
 }
 
 // explicit instantiations: storage in complex FP64 and complex FP32

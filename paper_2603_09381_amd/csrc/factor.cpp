@@ -43,6 +43,12 @@
 thread_local KernelTimer* g_ktimer = nullptr;
 
 namespace {
+thread_local int64_t g_launches = 0, g_syncs = 0;
+}
+void pmx_count_launch() { ++g_launches; }
+void pmx_count_sync() { ++g_syncs; }
+
+namespace {
 
 thread_local std::string g_last_error;
 
@@ -295,11 +301,13 @@ template <class T>
 void download(std::vector<T>& v, const T* d, size_t n, hipStream_t s) {
   v.resize(n);
   if (n) HIPCHK(hipMemcpyAsync(v.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+  pmx_count_sync();
   HIPCHK(hipStreamSynchronize(s));
 }
 
 void sync_check(hipStream_t s) {
   HIPCHK(hipGetLastError());
+  pmx_count_sync();
   HIPCHK(hipStreamSynchronize(s));
 }
 
@@ -386,6 +394,32 @@ namespace {
 struct ApplyGeo;
 }
 
+// The numeric phase of a factorisation kept for replays (options.refactor = 1): every
+// launch after the interpolative decompositions, bound to device buffers and descriptors
+// that live as long as the factor.  In the Omit form (Sec. 2) the IDs see exterior
+// kernels only, so skeletons, interpolation matrices, ranks and every size stay valid
+// when the interior media change; the self blocks, Schur complements, parent blocks and
+// the top LU are what a replay recomputes.
+struct NumProgram {
+  bool on = false;
+  std::vector<std::function<void(hipStream_t)>> steps;
+  std::vector<std::pair<const int*, int>> infos;   // LU pivot checks (device arrays)
+  struct Diag {                                     // self-block descriptors (interior media)
+    std::vector<DiagDesc> host;
+    DiagDesc* dev;
+    std::vector<int> incl;
+  };
+  std::vector<Diag> diags;
+  hipGraphExec_t graph = nullptr;
+  int64_t nodes = 0;
+  void add(std::function<void(hipStream_t)> f) {
+    if (on) steps.push_back(std::move(f));
+  }
+  ~NumProgram() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+  }
+};
+
 struct pmx_factor {
   // reuse of the factorisation's temporary device blocks (declared first: destroyed last)
   DevPool pool;
@@ -416,6 +450,8 @@ struct pmx_factor {
   std::vector<float> leaf_pred;
   // launch-parameter table of options.tune_path (NULL: built-in rules)
   std::unique_ptr<TuneTable> tune;
+  // options.refactor = 1: the numeric phase as a replayable launch sequence
+  NumProgram num;
   // refined forms: the operator apply's geometry (tree walk per target wave), built on a
   // host thread while the device factors; read by the first solve
   std::future<std::shared_ptr<ApplyGeo>> apply_geo;
@@ -440,6 +476,19 @@ Tier<float>& tier<float>(pmx_factor* F) {
 }
 
 namespace {
+
+// One launch step of the numeric phase: run now, and kept when the factor keeps its
+// numeric program.  f takes the stream and may hold only values and device pointers that
+// outlive the factor's creation.
+template <class Fn>
+void num_step(pmx_factor* F, hipStream_t s, Fn f) {
+  f(s);
+  F->num.add(std::function<void(hipStream_t)>(f));
+}
+
+// Device memory of the numeric phase: the factor's own arena when the program is kept,
+// else the level's temporaries.
+inline Arena& num_arena(pmx_factor* F, Arena& tmp) { return F->num.on ? F->arena : tmp; }
 
 void validate(const pmx_geometry* g, const pmx_options* o) {
   if (!g) fail(PMX_EINVAL, "geometry is NULL");
@@ -557,8 +606,9 @@ Tables make_tables(Arena& A, const std::vector<int>& ns_all, hipStream_t s) {
 }
 
 // Leaf self blocks for the given inclusions into out[off_i], ld 2 n_i.
-void assemble_diag(pmx_factor* F, Arena& tmp, const std::vector<int>& incl, zd* D,
+void assemble_diag(pmx_factor* F, Arena& tmp_, const std::vector<int>& incl, zd* D,
                    const std::vector<int64_t>& offD, hipStream_t s) {
+  Arena& tmp = num_arena(F, tmp_);
   std::vector<int> ns;
   for (int j : incl) ns.push_back((int)(F->node_off[j + 1] - F->node_off[j]));
   Tables T = make_tables(tmp, ns, s);
@@ -586,7 +636,12 @@ void assemble_diag(pmx_factor* F, Arena& tmp, const std::vector<int>& incl, zd* 
     so += (int64_t)d.n * d.n;
   }
   DiagDesc* d_dd = tmp.upload(dd, s);
-  asm_diag(F->geom(), F->ext(), d_dd, (int)incl.size(), maxn, T.R, T.dt, s);
+  const DevGeom g = F->geom();
+  const ExtParams e = F->ext();
+  const int cnt = (int)incl.size();
+  const double *tr = T.R, *tdt = T.dt;
+  num_step(F, s, [=](hipStream_t st) { asm_diag(g, e, d_dd, cnt, maxn, tr, tdt, st); });
+  if (F->num.on) F->num.diags.push_back(NumProgram::Diag{dd, d_dd, incl});
 }
 
 // FP64 self blocks of every inclusion in inclusion order (the refined forms keep them for
@@ -729,13 +784,15 @@ void id_stage(pmx_factor* F, const LevelData<R>& L, const std::vector<CellPlan>&
       totC += c;
     }
   cx<R>* Mb = tmp.alloc<cx<R>>(totM);
-  io.Rb = tmp.alloc<cx<R>>(totR);
+  // R factors (whose T blocks the row interpolation reads) and pivots outlive the level
+  // when the numeric phase is kept for replays
+  io.Rb = num_arena(F, tmp).alloc<cx<R>>(totR);
   cx<R>* Vb = tmp.alloc<cx<R>>(totV);
   cx<R>* VTb = tmp.alloc<cx<R>>(totV);
   cx<R>* CVb = tmp.alloc<cx<R>>(totC);
   double* taub = tmp.alloc<double>(nid);
   int* d_work = tmp.alloc<int>(1);
-  io.pivb = tmp.alloc<int>(totC);
+  io.pivb = num_arena(F, tmp).alloc<int>(totC);
   double* nrmb = tmp.alloc<double>(2 * totC);
   double* extrab = tmp.alloc<double>(totC);
   int* stb = tmp.alloc<int>(4 * nid);
@@ -977,8 +1034,12 @@ void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>&
     GatherDescT<R>* d_gd = tmp.upload(gd, s);
     asm_gather(Rb, d_gd, (int)gd.size(), maxr, maxcc, s);
   }
-  // ---- L, LU(D), Y = D^-1 L
-  asm_zero(L.Y, ty_, s);
+  // ---- L, LU(D), Y = D^-1 L (from here on the numeric phase: steps kept for replays)
+  Arena& NA = num_arena(F, tmp);
+  {
+    cx<R>* Y = L.Y;
+    num_step(F, s, [=](hipStream_t st) { asm_zero(Y, ty_, st); });
+  }
   {
     std::vector<LDescT<R>> ld(nc);
     for (int t = 0; t < nc; ++t) {
@@ -997,8 +1058,9 @@ void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>&
       d.ldt0 = mb0;
       d.ldt1 = mb1;
     }
-    LDescT<R>* d_ld = tmp.upload(ld, s);
-    asm_build_l(d_ld, nc, L.max_s, L.max_k, s);
+    LDescT<R>* d_ld = NA.upload(ld, s);
+    const int ms = L.max_s, mk = L.max_k;
+    num_step(F, s, [=](hipStream_t st) { asm_build_l(d_ld, nc, ms, mk, st); });
   }
   std::vector<LuDescT<R>> lu(nc);
   for (int t = 0; t < nc; ++t) {
@@ -1006,9 +1068,15 @@ void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>&
     lu[t] = LuDescT<R>{L.D + L.offD[t], sz, sz, L.ipiv + L.offS[t], L.perm + L.offS[t]};
   }
   L.d_lu = A.upload(lu, s);
-  int* d_info = tmp.alloc<int>(nc);
-  HIPCHK(hipMemsetAsync(d_info, 0, nc * sizeof(int), s));
-  la_getrf(L.d_lu, nc, L.max_s, d_info, s);
+  int* d_info = NA.alloc<int>(nc);
+  {
+    const LuDescT<R>* dl = L.d_lu;
+    const int ms = L.max_s;
+    num_step(F, s, [=](hipStream_t st) {
+      asm_zero_i32(d_info, nc, st);
+      la_getrf(dl, nc, ms, d_info, st);
+    });
+  }
   for (int t = 0; t < nc; ++t)
     la_getrf_work(L.s0[t] + L.s1[t], (int)sizeof(R), &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
   std::vector<MatT<R>> ym(nc);
@@ -1016,13 +1084,17 @@ void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>&
     int sz = L.s0[t] + L.s1[t];
     ym[t] = MatT<R>{L.Y + L.offY[t], sz, sz, L.k0[t] + L.k1[t]};
   }
-  MatT<R>* d_ym = tmp.upload(ym, s);
-  la_getrs(L.d_lu, d_ym, nc, L.max_s, L.max_k, s);
+  {
+    MatT<R>* d_ym = NA.upload(ym, s);
+    const LuDescT<R>* dl = L.d_lu;
+    const int ms = L.max_s, mk = L.max_k;
+    num_step(F, s, [=](hipStream_t st) { la_getrs(dl, d_ym, nc, ms, mk, st); });
+  }
   // ---- M = R Y: skeleton rows of Y plus T times its redundant rows
-  cx<R>* Mm = tmp.alloc<cx<R>>(ta);
+  cx<R>* Mm = NA.alloc<cx<R>>(ta);
   int64_t totred = 0;
   for (int t = 0; t < nc; ++t) totred += (int64_t)(L.s0[t] + L.s1[t] - L.k0[t] - L.k1[t]) * (L.k0[t] + L.k1[t]);
-  cx<R>* Red = tmp.alloc<cx<R>>(std::max<int64_t>(totred, 1));
+  cx<R>* Red = NA.alloc<cx<R>>(std::max<int64_t>(totred, 1));
   {
     std::vector<RowSrc> rs;
     std::vector<int64_t> rso;
@@ -1077,44 +1149,56 @@ void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>&
         ro += (int64_t)nr * K;
       }
     }
-    RowSrc* d_rs = tmp.upload(rs, s);
+    RowSrc* d_rs = NA.upload(rs, s);
     for (size_t i = 0; i < gd.size(); ++i) gd[i].src = d_rs + rso[i];
-    GatherDescT<R>* d_gd = tmp.upload(gd, s);
-    asm_gather(L.Y, d_gd, (int)gd.size(), maxr, L.max_k, s);
+    GatherDescT<R>* d_gd = NA.upload(gd, s);
+    const cx<R>* Y = L.Y;
+    const int ngd = (int)gd.size(), mk = L.max_k;
+    num_step(F, s, [=](hipStream_t st) { asm_gather(Y, d_gd, ngd, maxr, mk, st); });
     if (!ga.empty()) {
-      GemmArgsT<R>* d_ga = tmp.upload(ga, s);
-      la_zgemm_list(OP_N, OP_N, d_ga, (int)ga.size(), L.max_k, L.max_k, cmk<R>(1, 0), cmk<R>(1, 0), s);
+      GemmArgsT<R>* d_ga = NA.upload(ga, s);
+      const int nga = (int)ga.size();
+      num_step(F, s, [=](hipStream_t st) {
+        la_zgemm_list(OP_N, OP_N, d_ga, nga, mk, mk, cmk<R>(1, 0), cmk<R>(1, 0), st);
+      });
     }
   }
   // ---- At = M^-1
+  int* d_info2 = NA.alloc<int>(nc);
   {
     std::vector<LuDescT<R>> lm(nc);
     std::vector<Mat2T<R>> id(nc);
     std::vector<MatT<R>> am(nc);
-    int* ipm = tmp.alloc<int>(std::max<int64_t>(tk, 1));
+    int* ipm = NA.alloc<int>(std::max<int64_t>(tk, 1));
     for (int t = 0; t < nc; ++t) {
       int K = L.k0[t] + L.k1[t];
       lm[t] = LuDescT<R>{Mm + L.offA[t], K, K, ipm + L.offK[t]};
       id[t] = Mat2T<R>{L.At + L.offA[t], K, K};
       am[t] = MatT<R>{L.At + L.offA[t], K, K, K};
     }
-    LuDescT<R>* d_lm = tmp.upload(lm, s);
-    Mat2T<R>* d_id = tmp.upload(id, s);
-    MatT<R>* d_am = tmp.upload(am, s);
-    int* d_info2 = tmp.alloc<int>(nc);
-    HIPCHK(hipMemsetAsync(d_info2, 0, nc * sizeof(int), s));
-    la_getrf(d_lm, nc, L.max_k, d_info2, s);
+    LuDescT<R>* d_lm = NA.upload(lm, s);
+    Mat2T<R>* d_id = NA.upload(id, s);
+    MatT<R>* d_am = NA.upload(am, s);
+    const int mk = L.max_k;
+    num_step(F, s, [=](hipStream_t st) {
+      asm_zero_i32(d_info2, nc, st);
+      la_getrf(d_lm, nc, mk, d_info2, st);
+      asm_identity(d_id, nc, mk, st);
+      la_getrs(d_lm, d_am, nc, mk, mk, st);
+    });
     for (int t = 0; t < nc; ++t)
       la_getrf_work(L.k0[t] + L.k1[t], (int)sizeof(R), &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
-    asm_identity(d_id, nc, L.max_k, s);
-    la_getrs(d_lm, d_am, nc, L.max_k, L.max_k, s);
-    std::vector<int> info;
-    download(info, d_info, nc, s);
-    for (int t = 0; t < nc; ++t)
-      if (info[t]) fail(PMX_ESINGULAR, "zero pivot in the LU of a cell block");
-    download(info, d_info2, nc, s);
-    for (int t = 0; t < nc; ++t)
-      if (info[t]) fail(PMX_ESINGULAR, "zero pivot in the LU of R D^-1 L");
+  }
+  std::vector<int> info;
+  download(info, d_info, nc, s);
+  for (int t = 0; t < nc; ++t)
+    if (info[t]) fail(PMX_ESINGULAR, "zero pivot in the LU of a cell block");
+  download(info, d_info2, nc, s);
+  for (int t = 0; t < nc; ++t)
+    if (info[t]) fail(PMX_ESINGULAR, "zero pivot in the LU of R D^-1 L");
+  if (F->num.on) {
+    F->num.infos.push_back({d_info, nc});
+    F->num.infos.push_back({d_info2, nc});
   }
   sync_check(s);
 }
@@ -1160,10 +1244,11 @@ void merge_level(pmx_factor* F, const LevelData<R>& C, const std::vector<CellPla
   P.D = F->arena.alloc<cx<R>>(td);
   P.ipiv = F->arena.alloc<int>(std::max<int64_t>(P.tot_s, 1));
   P.perm = F->arena.alloc<int>(std::max<int64_t>(P.tot_s, 1));
-  int* d_r = tmp.upload(P.rows, s);
-  int* d_c = tmp.upload(P.cols, s);
-  int* d_rl = tmp.upload(rloc, s);
-  int* d_cl = tmp.upload(cloc, s);
+  Arena& NA = num_arena(F, tmp);
+  int* d_r = NA.upload(P.rows, s);
+  int* d_c = NA.upload(P.cols, s);
+  int* d_rl = NA.upload(rloc, s);
+  int* d_cl = NA.upload(cloc, s);
   std::vector<ParentDescT<R>> pd(np);
   for (int p = 0; p < np; ++p) {
     ParentDescT<R>& d = pd[p];
@@ -1183,8 +1268,11 @@ void merge_level(pmx_factor* F, const LevelData<R>& C, const std::vector<CellPla
       d.kc[sl] = C.k0[c] + C.k1[c];
     }
   }
-  ParentDescT<R>* d_pd = tmp.upload(pd, s);
-  asm_parent(F->geom(), F->ext(), d_pd, np, P.max_s, s);
+  ParentDescT<R>* d_pd = NA.upload(pd, s);
+  const DevGeom g = F->geom();
+  const ExtParams e = F->ext();
+  const int ms = P.max_s;
+  num_step(F, s, [=](hipStream_t st) { asm_parent(g, e, d_pd, np, ms, st); });
 }
 
 // Leaf level: one inclusion per cell, active rows and columns all its nodes (value /
@@ -1314,8 +1402,12 @@ void factor_all(pmx_factor* F, hipStream_t s) {
         len[t] = 4 * n * n;
         ml = std::max(ml, len[t]);
       }
-      asm_convert_blocks(F->Dself, L0.D, tmp.upload(so, s), tmp.upload(L0.offD, s), tmp.upload(len, s),
-                         (int)incl.size(), ml, s);
+      Arena& NA = num_arena(F, tmp);
+      const int64_t *d_so = NA.upload(so, s), *d_do = NA.upload(L0.offD, s), *d_len = NA.upload(len, s);
+      const zd* src = F->Dself;
+      cx<R>* dst = L0.D;
+      const int cnt = (int)incl.size();
+      num_step(F, s, [=](hipStream_t st) { asm_convert_blocks(src, dst, d_so, d_do, d_len, cnt, ml, st); });
     }
     // no synchronisation: the temporaries go back to the pool, whose blocks only later
     // work of this stream reuses, and the host goes on building the next descriptors
@@ -1345,9 +1437,16 @@ void factor_all(pmx_factor* F, hipStream_t s) {
       std::vector<LuDescT<R>> lu{LuDescT<R>{T.Droot, T.root_s, T.root_s, T.ipiv_root, T.perm_root}};
       T.d_lu_root = F->arena.upload(lu, s);
       Arena tmp(&F->pool);
-      int* d_info = tmp.alloc<int>(1);
-      HIPCHK(hipMemsetAsync(d_info, 0, sizeof(int), s));
-      la_getrf(T.d_lu_root, 1, T.root_s, d_info, s);
+      int* d_info = num_arena(F, tmp).alloc<int>(1);
+      {
+        const LuDescT<R>* dl = T.d_lu_root;
+        const int rs = T.root_s;
+        num_step(F, s, [=](hipStream_t st) {
+          asm_zero_i32(d_info, 1, st);
+          la_getrf(dl, 1, rs, d_info, st);
+        });
+      }
+      if (F->num.on) F->num.infos.push_back({d_info, 1});
       la_getrf_work(T.root_s, (int)sizeof(R), &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
       std::vector<int> info;
       download(info, d_info, 1, s);
@@ -2778,6 +2877,9 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
     std::unique_ptr<pmx_factor> F(new pmx_factor());
     std::memset(&F->info, 0, sizeof(F->info));
     F->opts = o;
+    if (o.refactor && o.learned) fail(PMX_EINVAL, "refactor = 1 needs learned = 0");
+    F->num.on = o.refactor != 0;
+    const int64_t launches0 = g_launches, syncs0 = g_syncs;
     if (o.tune_path) {
       F->tune.reset(new TuneTable());
       const std::string e = tune_load(o.tune_path, *F->tune);
@@ -2848,6 +2950,8 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
       fill_info<double>(F.get());
     }
     F->info.t_factor_ms = now_ms() - t0;
+    F->info.factor_launches = g_launches - launches0;
+    F->info.factor_host_syncs = g_syncs - syncs0;
     if (kt) {
       HIPCHK(hipStreamSynchronize(s));
       kt->collect(F->info.t_kernel_ms, F->info.n_kernel_launch);
@@ -2956,6 +3060,75 @@ pmx_status pmx_factor_info(const pmx_factor* f, pmx_info* info) {
   return guarded([&] {
     if (!f || !info) fail(PMX_EINVAL, "NULL argument");
     *info = f->info;
+  });
+}
+
+pmx_status pmx_factor_refactor(pmx_factor* F, const double* k_int, const double* eps_int, void* hip_stream) {
+  return guarded([&] {
+    if (!F) fail(PMX_EINVAL, "factor is NULL");
+    if (!F->num.on) fail(PMX_EINVAL, "the factor was created without options.refactor = 1");
+    if (!k_int) fail(PMX_EINVAL, "k_int is NULL");
+    for (int j = 0; j < F->m; ++j) {
+      if (!(k_int[j] > 0) || !std::isfinite(k_int[j])) fail(PMX_EINVAL, "k_int must be positive");
+      if (eps_int && (!(eps_int[j] > 0) || !std::isfinite(eps_int[j]))) fail(PMX_EINVAL, "eps_int must be positive");
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    const double t0 = now_ms();
+    const int64_t launches0 = g_launches, syncs0 = g_syncs;
+    struct Reset {
+      const TuneTable* prev;
+      ~Reset() { g_tune = prev; }
+    } reset_tune{g_tune};
+    g_tune = F->tune.get();   // the launch choices of create, for the capture
+    KernelTimer* kt_prev = g_ktimer;
+    g_ktimer = nullptr;       // no events inside the captured sequence
+    struct ResetT {
+      KernelTimer* prev;
+      ~ResetT() { g_ktimer = prev; }
+    } reset_timer{kt_prev};
+    for (int j = 0; j < F->m; ++j) {
+      F->k_int[j] = k_int[j];
+      const double r = k_int[j] / F->k_ext;
+      F->eps_int[j] = eps_int ? eps_int[j] : F->eps_ext * r * r;
+    }
+    HIPCHK(hipEventRecord(F->ev_in, s));
+    HIPCHK(hipStreamWaitEvent(F->gs, F->ev_in, 0));
+    // the interior media enter through the self-block descriptors, rewritten in place
+    // (stream-ordered, before the replay; the previous call's replay has completed)
+    for (NumProgram::Diag& d : F->num.diags) {
+      for (size_t t = 0; t < d.incl.size(); ++t) {
+        d.host[t].k_int = F->k_int[d.incl[t]];
+        d.host[t].eps_int = F->eps_int[d.incl[t]];
+      }
+      HIPCHK(hipMemcpyAsync(d.dev, d.host.data(), d.host.size() * sizeof(DiagDesc), hipMemcpyHostToDevice, F->gs));
+    }
+    int64_t captured = 0;   // launches recorded into the graph (not made) by this call
+    if (!F->num.graph) {
+      const int64_t l0 = g_launches;
+      F->num.graph = capture_graph(F->gs, [&] {
+        for (auto& f : F->num.steps) f(F->gs);
+      });
+      F->num.nodes = captured = g_launches - l0;
+    }
+    pmx_count_launch();
+    HIPCHK(hipGraphLaunch(F->num.graph, F->gs));
+    // one wait for every LU pivot check of the replay
+    std::vector<std::vector<int>> hi(F->num.infos.size());
+    for (size_t i = 0; i < hi.size(); ++i) {
+      hi[i].resize(F->num.infos[i].second);
+      HIPCHK(hipMemcpyAsync(hi[i].data(), F->num.infos[i].first, hi[i].size() * sizeof(int), hipMemcpyDeviceToHost,
+                            F->gs));
+    }
+    sync_check(F->gs);
+    for (const std::vector<int>& v : hi)
+      for (int x : v)
+        if (x) fail(PMX_ESINGULAR, "zero pivot in an LU of the refactorisation");
+    HIPCHK(hipEventRecord(F->ev_out, F->gs));
+    HIPCHK(hipStreamWaitEvent(s, F->ev_out, 0));
+    F->info.refactor_launches = g_launches - launches0 - captured;
+    F->info.refactor_graph_nodes = F->num.nodes;
+    F->info.refactor_host_syncs = g_syncs - syncs0;
+    F->info.t_refactor_ms = now_ms() - t0;
   });
 }
 

@@ -275,7 +275,7 @@ static void launch_zgemm(F f, int batch, int max_m, int max_n, cx<R> alpha, cx<R
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
   dim3 grid((max_m + 63) / 64, (max_n + 63) / 64, batch);
   KScope ks(PK_ZGEMM, s);
-  hipLaunchKernelGGL((k_zgemm<R, OPA, OPB, F>), grid, dim3(256), 0, s, f, alpha, beta);
+  PMX_LAUNCH((k_zgemm<R, OPA, OPB, F>), grid, dim3(256), 0, s, f, alpha, beta);
 }
 
 // C = alpha A B + beta C for few columns of B (n <= NB, both operands untransposed): the
@@ -345,9 +345,9 @@ static bool launch_zgemm_skinny(F f, int batch, int max_m, int max_n, cx<R> alph
   dim3 grid((max_m + 63) / 64, 1, batch);
   KScope ks(PK_ZGEMM, s);
   if (max_n <= 4)
-    hipLaunchKernelGGL((k_zgemm_skinny<R, 4, F>), grid, dim3(512), 0, s, f, alpha, beta);
+    PMX_LAUNCH((k_zgemm_skinny<R, 4, F>), grid, dim3(512), 0, s, f, alpha, beta);
   else
-    hipLaunchKernelGGL((k_zgemm_skinny<R, 8, F>), grid, dim3(512), 0, s, f, alpha, beta);
+    PMX_LAUNCH((k_zgemm_skinny<R, 8, F>), grid, dim3(512), 0, s, f, alpha, beta);
   return true;
 }
 
@@ -471,7 +471,7 @@ static void launch_trsm_small(F f, int batch, int max_nrhs, hipStream_t s) {
   if (batch <= 0 || max_nrhs <= 0) return;
   dim3 grid((max_nrhs + 63) / 64, batch);
   KScope ks(PK_TRSM, s);
-  hipLaunchKernelGGL((k_trsm_small<R, UPPER, UNIT, F>), grid, dim3(64), 0, s, f);
+  PMX_LAUNCH((k_trsm_small<R, UPPER, UNIT, F>), grid, dim3(64), 0, s, f);
 }
 
 // ---------------------------------------------------------------------------------
@@ -719,6 +719,121 @@ __global__ __launch_bounds__(NT) void k_getrf_panel_u(const LuDescT<R>* lus, int
   }
 }
 
+// Panels taller than the register kernels hold (a few thousand rows by PMX_LU_NB columns,
+// cache-resident): the rows stay in memory, thread t taking rows j0 + t + NT q.  Per
+// column: a block argmax of the candidates found in the previous column's pass; the
+// explicit exchange of the pivot row with row col by the panel's jb threads, which also
+// stage in LDS the pivot and the pivot row's entries right of it (zeros elsewhere, so the
+// elimination needs no per-column mask); one pass over the rows below col that issues all
+// loads of a row's remaining columns at once, eliminates, stores, and takes the next
+// column's candidate.  Matrices of a batch may be smaller than the one that chose this
+// kernel, so a panel may be narrower than PMX_LU_NB (jb columns).  Pivots, ties (to the
+// smaller row) and the update order are those of k_getrf_panel.
+template <class R, int NT>
+__global__ __launch_bounds__(NT) void k_getrf_panel_t(const LuDescT<R>* lus, int j0, int* info) {
+  typedef cx<R> C;
+  constexpr int NB = PMX_LU_NB, NW = NT / 64;
+  const LuDescT<R> L = lus[blockIdx.x];
+  const int jb = min(NB, L.n - j0);
+  if (jb <= 0) return;
+  __shared__ double sv[NW];
+  __shared__ int si[NW];
+  __shared__ C prow[NB];
+  __shared__ C spiv;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = L.n;
+  const int ld = (int)L.ld;
+  const auto P = gbl(L.a) + (int64_t)j0 * L.ld;   // the panel's first column
+  double best = -1.0;
+  int bi = -1;
+  for (int r = j0 + tid; r < n; r += NT) {
+    const C v = P[r];
+    argmax_pair(best, bi, fabs((double)v.re) + fabs((double)v.im), r);
+  }
+#pragma unroll 1
+  for (int c = 0; c < jb; ++c) {
+    const int col = j0 + c;
+    wave_argmax(best, bi);
+    if (lane == 0) {
+      sv[wave] = best;
+      si[wave] = bi;
+    }
+    __syncthreads();
+    double bv = sv[0];
+    int p = si[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) argmax_pair(bv, p, sv[w], si[w]);
+    if (tid == 0) {
+      gbl(L.ipiv)[col] = p;
+      if (bv == 0.0 && info && info[blockIdx.x] == 0) info[blockIdx.x] = col + 1;
+    }
+    if (tid < NB) {
+      C b = cmk<R>(0, 0);
+      if (tid < jb) {
+        const auto pc = P + (int64_t)tid * ld;
+        const C a = pc[col];
+        b = pc[p];
+        if (p != col) {
+          pc[col] = b;
+          pc[p] = a;
+        }
+        if (tid == c) spiv = b;
+      }
+      prow[tid] = tid > c ? b : cmk<R>(0, 0);
+    }
+    __syncthreads();
+    const C piv = spiv;
+    const bool nz = piv.re != R(0) || piv.im != R(0);
+    const C inv = nz ? zrecip(piv) : cmk<R>(0, 0);
+    const C pn = prow[min(c + 1, NB - 1)];
+    best = -1.0;
+    bi = -1;
+    for (int r = j0 + tid; r < n; r += NT) {
+      if (r <= col) continue;
+      // c, jb and the LDS index base pass through an empty asm statement once per row:
+      // the per-column predicates and the pivot-row reads are then formed inside the loop
+      // instead of being hoisted out of it into registers that would not fit
+      int cr = c, jr = jb, zr = 0;
+      asm volatile("" : "+s"(cr));
+      asm volatile("" : "+s"(jr));
+      asm volatile("" : "+v"(zr));
+      const int o0 = r + c * ld;
+      const C l = zmul(P[o0], inv);
+      C nxt = P[o0 + (c + 1 < jb ? ld : 0)];
+      // the row's columns right of col in two halves of NB / 2, each with all its loads
+      // issued at once
+      constexpr int HB = NB / 2;
+      int o = o0;   // element offset of (r, cc), advanced one column at a time
+      if (nz) P[o0] = l;
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        C v[HB];
+        int os = o;
+#pragma unroll
+        for (int t = 0; t < HB; ++t) {
+          v[t] = cmk<R>(0, 0);
+          if (hh * HB + t > cr && hh * HB + t < jr) {
+            o += ld;
+            v[t] = P[o];
+          }
+        }
+        if (nz) {
+#pragma unroll
+          for (int t = 0; t < HB; ++t) v[t] = zfms(v[t], l, prow[hh * HB + t + zr]);
+#pragma unroll
+          for (int t = 0; t < HB; ++t)
+            if (hh * HB + t > cr && hh * HB + t < jr) {
+              os += ld;
+              P[os] = v[t];
+            }
+        }
+      }
+      if (nz) nxt = zfms(nxt, l, pn);
+      if (c + 1 < jb) argmax_pair(best, bi, fabs((double)nxt.re) + fabs((double)nxt.im), r);
+    }
+  }
+}
+
 // apply the swaps of panel [j0, j0+jb) to the columns outside the panel.  The swaps are
 // composed first (one lane, in LDS: cont[r] = the row whose entry ends in row r), so that
 // each thread (one column) loads every affected entry at once and stores them after: the
@@ -844,6 +959,7 @@ static bool lu_panel_fits(int v, int rows) {
     case 4: return rows <= 256;
     case 6: return rows <= 512;
     case 8: return sizeof(R) == 4 && rows <= 1024;
+    case 10: return true;
     default: return false;
   }
 }
@@ -853,33 +969,41 @@ void la_lu_panel(int variant, const LuDescT<R>* d_lu, int batch, int j0, int* d_
   KScope ks(PK_GETRF_PANEL, s);
   switch (variant) {
     case 0:
-      hipLaunchKernelGGL((k_getrf_panel_reg<R, 256, 1>), dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      PMX_LAUNCH((k_getrf_panel_reg<R, 256, 1>), dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
       break;
     case 1:
-      hipLaunchKernelGGL((k_getrf_panel_reg<R, 256, 2>), dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      PMX_LAUNCH((k_getrf_panel_reg<R, 256, 2>), dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
       break;
     case 2:
       if (sizeof(R) == 4) {
-        hipLaunchKernelGGL((k_getrf_panel_reg<R, 512, 2>), dim3(batch), dim3(512), 0, s, d_lu, j0, d_info);
+        PMX_LAUNCH((k_getrf_panel_reg<R, 512, 2>), dim3(batch), dim3(512), 0, s, d_lu, j0, d_info);
         break;
       }
-      hipLaunchKernelGGL(k_getrf_panel<R>, dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      PMX_LAUNCH(k_getrf_panel<R>, dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
       break;
     case 4:
-      hipLaunchKernelGGL((k_getrf_panel_u<R, 256, 1>), dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      PMX_LAUNCH((k_getrf_panel_u<R, 256, 1>), dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
       break;
     case 6:
-      hipLaunchKernelGGL((k_getrf_panel_u<R, 512, 1>), dim3(batch), dim3(512), 0, s, d_lu, j0, d_info);
+      PMX_LAUNCH((k_getrf_panel_u<R, 512, 1>), dim3(batch), dim3(512), 0, s, d_lu, j0, d_info);
       break;
     case 8:
       if (sizeof(R) == 4) {
-        hipLaunchKernelGGL((k_getrf_panel_u<float, 1024, 1>), dim3(batch), dim3(1024), 0, s,
+        PMX_LAUNCH((k_getrf_panel_u<float, 1024, 1>), dim3(batch), dim3(1024), 0, s,
                            (const LuDescT<float>*)d_lu, j0, d_info);
         break;
       }
       [[fallthrough]];
+    case 10:
+      if (sizeof(R) == 4)
+        PMX_LAUNCH((k_getrf_panel_t<float, 1024>), dim3(batch), dim3(1024), 0, s,
+                           (const LuDescT<float>*)d_lu, j0, d_info);
+      else
+        PMX_LAUNCH((k_getrf_panel_t<double, 512>), dim3(batch), dim3(512), 0, s,
+                           (const LuDescT<double>*)d_lu, j0, d_info);
+      break;
     default:
-      hipLaunchKernelGGL(k_getrf_panel<R>, dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
+      PMX_LAUNCH(k_getrf_panel<R>, dim3(batch), dim3(256), 0, s, d_lu, j0, d_info);
       break;
   }
 }
@@ -890,10 +1014,10 @@ void la_getrf(const LuDescT<R>* d_lu, int batch, int max_n, int* d_info, hipStre
   for (int j0 = 0; j0 < max_n; j0 += PMX_LU_NB) {
     {
       // panel rows max_n - j0: by default the unrolled register kernels when the rows fit
-      // one per thread (512 rows, 1024 in FP32), else the global-memory kernel; a
+      // one per thread (512 rows, 1024 in FP32), else the tall-panel kernel; a
       // launch-parameter table may choose another variant that holds the rows
       const int rows = max_n - j0;
-      const int dflt = rows <= 256 ? 4 : rows <= 512 ? 6 : (rows <= 1024 && sizeof(R) == 4) ? 8 : 3;
+      const int dflt = rows <= 256 ? 4 : rows <= 512 ? 6 : (rows <= 1024 && sizeof(R) == 4) ? 8 : 10;
       int v = tune_choice(TK_LU_PANEL, (int)sizeof(R), tune_bucket_size(rows), tune_bucket_batch(batch), 0, dflt,
                           rows, batch, 0);
       if (!lu_panel_fits<R>(v, rows)) v = dflt;
@@ -902,7 +1026,7 @@ void la_getrf(const LuDescT<R>* d_lu, int batch, int max_n, int* d_info, hipStre
     const size_t shm = (size_t)max_n * sizeof(int);
     if (shm > 64 * 1024)
       (void)hipFuncSetAttribute((const void*)k_laswp_panel<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k_laswp_panel<R>, dim3((max_n + 63) / 64, batch), dim3(64), shm, s, d_lu, j0);
+    PMX_LAUNCH(k_laswp_panel<R>, dim3((max_n + 63) / 64, batch), dim3(64), shm, s, d_lu, j0);
     int rem = max_n - j0 - PMX_LU_NB;
     if (rem > 0) {
       launch_trsm_small<R, false, true>(FLuTrsm<R>{d_lu, j0}, batch, rem, s);
@@ -912,7 +1036,7 @@ void la_getrf(const LuDescT<R>* d_lu, int batch, int max_n, int* d_info, hipStre
   const size_t shm = (size_t)max_n * sizeof(int);
   if (shm > 64 * 1024)
     (void)hipFuncSetAttribute((const void*)k_lu_perm<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-  hipLaunchKernelGGL(k_lu_perm<R>, dim3(batch), dim3(256), shm, s, d_lu);
+  PMX_LAUNCH(k_lu_perm<R>, dim3(batch), dim3(256), shm, s, d_lu);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1048,7 +1172,7 @@ void la_getrs(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max_n, 
     const size_t shm = ((size_t)max_n * sizeof(int) + 15) / 16 * 16 + (size_t)ncol * cb;
     if (shm > 64 * 1024)
       (void)hipFuncSetAttribute((const void*)k_laswp_rhs<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(k_laswp_rhs<R>, dim3((max_nrhs + ncol - 1) / ncol, batch), dim3(256), shm, s, d_lu, d_b, ncol);
+    PMX_LAUNCH(k_laswp_rhs<R>, dim3((max_nrhs + ncol - 1) / ncol, batch), dim3(256), shm, s, d_lu, d_b, ncol);
   }
   const int nblk = (max_n + PMX_LU_NB - 1) / PMX_LU_NB;
   for (int bk = 0; bk < nblk; ++bk) {
@@ -1495,7 +1619,7 @@ bool la_getrs_lds(const LuDescT<R>* d_lu, const MatT<R>* d_b, int batch, int max
   auto go = [&](auto kern, int nt) {
     if (shm > 64 * 1024)
       (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    hipLaunchKernelGGL(kern, grid, dim3(nt), shm, s, d_lu, d_b);
+    PMX_LAUNCH(kern, grid, dim3(nt), shm, s, d_lu, d_b);
   };
   // blocks of 32 rows (FP32) or 16 (FP64): the row held in registers stays at 64 of them
   constexpr int BS = sizeof(R) == 4 ? 32 : 16;
@@ -1552,11 +1676,11 @@ void la_getrs_small(const LuDescT<R>* d_lu, const MatT<R>* d_b, const MatT<R>* d
   if (batch <= 0 || max_n <= 0 || max_nrhs <= 0) return;
   KScope ks(PK_GETRS, s);
   if (max_nrhs <= 1) {
-    hipLaunchKernelGGL((k_getrs_small<R, 1>), dim3(batch, 1), dim3(GS_NT), 0, s, d_lu, d_b, d_w);
+    PMX_LAUNCH((k_getrs_small<R, 1>), dim3(batch, 1), dim3(GS_NT), 0, s, d_lu, d_b, d_w);
   } else if (max_nrhs <= 2) {
-    hipLaunchKernelGGL((k_getrs_small<R, 2>), dim3(batch, 1), dim3(GS_NT), 0, s, d_lu, d_b, d_w);
+    PMX_LAUNCH((k_getrs_small<R, 2>), dim3(batch, 1), dim3(GS_NT), 0, s, d_lu, d_b, d_w);
   } else {
-    hipLaunchKernelGGL((k_getrs_small<R, 4>), dim3(batch, (max_nrhs + 3) / 4), dim3(GS_NT), 0, s, d_lu, d_b, d_w);
+    PMX_LAUNCH((k_getrs_small<R, 4>), dim3(batch, (max_nrhs + 3) / 4), dim3(GS_NT), 0, s, d_lu, d_b, d_w);
   }
 }
 
@@ -1807,20 +1931,25 @@ __global__ __launch_bounds__(NT) void k_ts_leaf(const QrDescT<R>* qrs, int j0, i
   }
 }
 
-// trailing update of one block of one tree level: A_b -= V (T^H (V^H A_b)), 64 columns per
-// workgroup, rows streamed through LDS in slices of 32, both products with V on 16x16x4
-// MFMA, the small product with T^H (PMX_QR_NB x PMX_QR_NB times PMX_QR_NB x 64) in between
-#define TSU_ROWS 32
-template <class R>
-__global__ __launch_bounds__(256) void k_ts_update(const QrDescT<R>* qrs, int j0, int L) {
+// trailing update of one block of one tree level in FP64: A_b -= V (T^H (V^H A_b)) on 32
+// columns per workgroup.  Wave w owns columns 16 (w & 1) .. +15 and half w >> 1 of the
+// block's rows; each lane keeps its entries of A_b in registers for the whole update, in
+// the B-operand layout of the 16x16x4 FP64 MFMA of W = V^H A_b (lane j + 16 k holds rows
+// 4 s + k of every 16-row block), which is also the accumulator layout of the product V W,
+// so that A_b is read once and written once with no staging.  V comes from the workspace
+// (shared through the cache by the block's column tiles); the two halves' partial W are
+// summed in LDS, multiplied by T^H there, and read back as the B operand of V W.
+#define TSU64_COLS 32
+__global__ __launch_bounds__(256, 2) void k_ts_update_f64(const QrDescT<double>* qrs, int j0, int L) {
+  typedef double R;
   typedef cx<R> C;
-  typedef typename AccT<R>::type V4;
+  constexpr int NRB = PMX_TS_BR / 32;   // 16-row blocks per half
   const QrDescT<R> Q = qrs[blockIdx.z];
   const int kmax = Q.kc;
   const int jb = min(PMX_QR_NB, kmax - j0);
   const int nc = Q.c - j0 - jb;
   if (jb <= 0 || nc <= 0) return;
-  const int c0 = blockIdx.x * 64;
+  const int c0 = blockIdx.x * TSU64_COLS;
   if (c0 >= nc) return;
   TsGeom g;
   ts_geom(Q.m, j0, jb, g);
@@ -1831,79 +1960,89 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDescT<R>* qrs, int j0
   const int64_t wo = ts_sel64(L, g.wo0, g.wo1, g.wo2, g.wo3) + (int64_t)b * PMX_TS_BR * PMX_QR_NB;
   const auto V = gbl(Q.v) + wo;
   const auto Tw = gbl(Q.t) + wo;
-  __shared__ C Vs[TSU_ROWS][PMX_QR_NB + 1];
-  __shared__ C As[TSU_ROWS][64 + 1];
-  __shared__ C Ws[PMX_QR_NB][64 + 1];
-  __shared__ int rows[TSU_ROWS];
+  __shared__ C Ws[PMX_QR_NB][TSU64_COLS + 1];
+  __shared__ C Tl[PMX_QR_NB][PMX_QR_NB + 1];
+  __shared__ int rows[PMX_TS_BR];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cb = wave & 1, h = wave >> 1;
+  const int j = lane & 15, k = lane >> 4;
   const auto A = gbl(Q.a);
   const int64_t ld = Q.ld;
-  const int ccol0 = j0 + jb + c0;
-  // W = V^H A_b: output PMX_QR_NB x 64 as (NB/16) x 4 blocks of 16x16, NB/16 per wave
-  constexpr int RB = PMX_QR_NB / 16;
-  V4 accR[RB], accI[RB];
-#pragma unroll
-  for (int q = 0; q < RB; ++q) {
-    accR[q] = V4{0, 0, 0, 0};
-    accI[q] = V4{0, 0, 0, 0};
-  }
-  for (int rb = 0; rb < nrb; rb += TSU_ROWS) {
-    if (tid < TSU_ROWS) rows[tid] = (rb + tid < nrb) ? ts_phys(b * PMX_TS_BR + rb + tid, L, jb, j0, g) : -1;
-    __syncthreads();
-    {
-      const int rr = tid & (TSU_ROWS - 1);
-      const int cc = tid >> 5;
-      const int pr = rows[rr];
-      // the workspace rows exist up to PMX_TS_BR; matrix addresses are clamped
-      C tv[PMX_QR_NB / 8], ta[8];
-#pragma unroll
-      for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
-        tv[pass] = V[rb + rr + (int64_t)(cc + 8 * pass) * PMX_TS_BR];
-      const int prc = pr >= 0 ? pr : j0;
-#pragma unroll
-      for (int pass = 0; pass < 8; ++pass)
-        ta[pass] = A[prc + (int64_t)(ccol0 + min(cc + 8 * pass, nc - 1 - c0)) * ld];
-#pragma unroll
-      for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
-        Vs[rr][cc + 8 * pass] = (rb + rr < nrb) ? tv[pass] : cmk<R>(0, 0);
-#pragma unroll
-      for (int pass = 0; pass < 8; ++pass)
-        As[rr][cc + 8 * pass] = (pr >= 0 && c0 + cc + 8 * pass < nc) ? ta[pass] : cmk<R>(0, 0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TSU_ROWS; kk += 4) {
-      const C bb = As[kk + (lane >> 4)][wave * 16 + (lane & 15)];
-#pragma unroll
-      for (int q = 0; q < RB; ++q) {
-        const C a = Vs[kk + (lane >> 4)][q * 16 + (lane & 15)];
-        accR[q] = mfma16(a.re, bb.re, accR[q]);
-        accR[q] = mfma16(a.im, bb.im, accR[q]);
-        accI[q] = mfma16(a.re, bb.im, accI[q]);
-        accI[q] = mfma16(-a.im, bb.re, accI[q]);
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int q = 0; q < RB; ++q)
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      Ws[q * 16 + mfma_row<R>(lane, r)][wave * 16 + (lane & 15)] = cmk<R>(accR[q][r], accI[q][r]);
-  // W <- T^H W, T upper triangular (row-major in the workspace), staged in the A slice's space
-  C(*Tl)[PMX_QR_NB + 1] = reinterpret_cast<C(*)[PMX_QR_NB + 1]>(&As[0][0]);
-  static_assert(TSU_ROWS * (64 + 1) >= PMX_QR_NB * (PMX_QR_NB + 1), "T fits in the A slice");
+  for (int i = tid; i < PMX_TS_BR; i += 256) rows[i] = (i < nrb) ? ts_phys(b * PMX_TS_BR + i, L, jb, j0, g) : -1;
   for (int e = tid; e < PMX_QR_NB * PMX_QR_NB; e += 256) Tl[e / PMX_QR_NB][e % PMX_QR_NB] = Tw[e];
   __syncthreads();
+  const int cl = cb * 16 + j;                    // column within the tile
+  const bool cok = c0 + cl < nc;
+  const int64_t coff = (int64_t)(j0 + jb + c0 + min(cl, nc - 1 - c0)) * ld;
+  const int rbase = h * (PMX_TS_BR / 2);
+  C ar[NRB][4];
+  // complex products as three real ones (Gauss): for W = V^H A, p1 = sum vr ar,
+  // p2 = sum vi ai, p3 = sum (vr - vi)(ar + ai), so W = (p1 + p2) + i (p3 - p1 + p2)
+  d4 p1[2], p2[2], p3[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    p1[q] = d4{0, 0, 0, 0};
+    p2[q] = d4{0, 0, 0, 0};
+    p3[q] = d4{0, 0, 0, 0};
+  }
+  // W = V^H A_b over this half's rows: step s of row block rb takes rows rb * 16 + 4 s + k
+#pragma unroll
+  for (int rb = 0; rb < NRB; ++rb) {
+    const int r0 = rbase + rb * 16;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ar[rb][t] = cmk<R>(0, 0);
+    if (r0 < nrb) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int lr = r0 + 4 * t + k;
+        const int pr = rows[lr];
+        if (pr >= 0 && cok) ar[rb][t] = A[pr + coff];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int lr = r0 + 4 * t + k;
+        const bool rok = lr < nrb;
+        const R as = ar[rb][t].re + ar[rb][t].im;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const C a = rok ? V[lr + (int64_t)(q * 16 + j) * PMX_TS_BR] : cmk<R>(0, 0);
+          p1[q] = mfma16(a.re, ar[rb][t].re, p1[q]);
+          p2[q] = mfma16(a.im, ar[rb][t].im, p2[q]);
+          p3[q] = mfma16(a.re - a.im, as, p3[q]);
+        }
+      }
+    }
+  }
+  // sum the halves: accumulator element (q * 16 + k + 4 r, cl) in register r
+  if (h == 1) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        Ws[q * 16 + k + 4 * r][cl] = cmk<R>(p1[q][r] + p2[q][r], p3[q][r] - p1[q][r] + p2[q][r]);
+  }
+  __syncthreads();
+  if (h == 0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const C o = Ws[q * 16 + k + 4 * r][cl];
+        Ws[q * 16 + k + 4 * r][cl] =
+            cmk<R>(o.re + (p1[q][r] + p2[q][r]), o.im + (p3[q][r] - p1[q][r] + p2[q][r]));
+      }
+  }
+  __syncthreads();
+  // W <- T^H W, T upper triangular
   {
-    constexpr int PER = PMX_QR_NB * 64 / 256;   // outputs per thread, one column
-    const int col = tid & 63, i0 = (tid >> 6) * PER;
+    constexpr int PER = PMX_QR_NB * TSU64_COLS / 256;
+    const int col = tid % TSU64_COLS, i0 = (tid / TSU64_COLS) * PER;
     C w2[PER];
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int i = i0 + u;
       C acc = cmk<R>(0, 0);
-      for (int j = 0; j <= i; ++j) acc = zfma(zconj(Tl[j][i]), Ws[j][col], acc);
+      for (int jj = 0; jj <= i; ++jj) acc = zfma(zconj(Tl[jj][i]), Ws[jj][col], acc);
       w2[u] = acc;
     }
     __syncthreads();
@@ -1911,53 +2050,33 @@ __global__ __launch_bounds__(256) void k_ts_update(const QrDescT<R>* qrs, int j0
     for (int u = 0; u < PER; ++u) Ws[i0 + u][col] = w2[u];
   }
   __syncthreads();
-  // A_b -= V W: a 32 x 64 slice is 2 x 4 blocks of 16x16, two per wave
-  const int rbk = wave & 1;
-  const int cbk0 = (wave >> 1) * 2;
-  for (int rb = 0; rb < nrb; rb += TSU_ROWS) {
-    if (tid < TSU_ROWS) rows[tid] = (rb + tid < nrb) ? ts_phys(b * PMX_TS_BR + rb + tid, L, jb, j0, g) : -1;
-    __syncthreads();
-    {
-      const int rr = tid & (TSU_ROWS - 1);
-      const int cc = tid >> 5;
-      C tv[PMX_QR_NB / 8];
+  // A_b -= V W, row block by row block (Gauss: q1 = sum vr wr, q2 = sum vi wi,
+  // q3 = sum (vr + vi)(wr + wi), V W = (q1 - q2) + i (q3 - q1 - q2)); accumulator register
+  // t of lane (j, k) is row r0 + k + 4 t, the row whose entry the lane holds in ar[rb][t]
 #pragma unroll
-      for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
-        tv[pass] = V[rb + rr + (int64_t)(cc + 8 * pass) * PMX_TS_BR];
+  for (int rb = 0; rb < NRB; ++rb) {
+    const int r0 = rbase + rb * 16;
+    if (r0 < nrb) {
+      d4 q1 = d4{0, 0, 0, 0}, q2 = d4{0, 0, 0, 0}, q3 = d4{0, 0, 0, 0};
+      const bool rok = r0 + j < nrb;
 #pragma unroll
-      for (int pass = 0; pass < PMX_QR_NB / 8; ++pass)
-        Vs[rr][cc + 8 * pass] = (rb + rr < nrb) ? tv[pass] : cmk<R>(0, 0);
-    }
-    __syncthreads();
-    V4 dR[2] = {V4{0, 0, 0, 0}, V4{0, 0, 0, 0}}, dI[2] = {V4{0, 0, 0, 0}, V4{0, 0, 0, 0}};
+      for (int kk = 0; kk < PMX_QR_NB; kk += 4) {
+        const C a = rok ? V[r0 + j + (int64_t)(kk + k) * PMX_TS_BR] : cmk<R>(0, 0);
+        const C bb = Ws[kk + k][cl];
+        q1 = mfma16(a.re, bb.re, q1);
+        q2 = mfma16(a.im, bb.im, q2);
+        q3 = mfma16(a.re + a.im, bb.re + bb.im, q3);
+      }
 #pragma unroll
-    for (int kk = 0; kk < PMX_QR_NB; kk += 4) {
-      const C a = Vs[rbk * 16 + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const C bb = Ws[kk + (lane >> 4)][(cbk0 + q) * 16 + (lane & 15)];
-        dR[q] = mfma16(a.re, bb.re, dR[q]);
-        dR[q] = mfma16(-a.im, bb.im, dR[q]);
-        dI[q] = mfma16(a.re, bb.im, dI[q]);
-        dI[q] = mfma16(a.im, bb.re, dI[q]);
+      for (int t = 0; t < 4; ++t) {
+        const int pr = rows[r0 + 4 * t + k];
+        if (pr >= 0 && cok) A[pr + coff] = zsub(ar[rb][t], cmk<R>(q1[t] - q2[t], q3[t] - q1[t] - q2[t]));
       }
     }
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = rbk * 16 + mfma_row<R>(lane, r);
-        const int col = (cbk0 + q) * 16 + (lane & 15);
-        const int pr = rows[row];
-        if (pr >= 0 && c0 + col < nc) {
-          const auto ap = A + pr + (int64_t)(ccol0 + col) * ld;
-          *ap = zsub(*ap, cmk<R>(dR[q][r], dI[q][r]));
-        }
-      }
-    __syncthreads();
   }
 }
 
+#define TSU_ROWS 32
 // FP32 form of the trailing update: the block's rows of A (up to PMX_TS_BR x 64, 64 complex
 // values per thread) stay in registers between the two products, so A is read from memory
 // once instead of twice; the product V W goes through LDS, and the updated slice is written
@@ -2156,27 +2275,28 @@ void la_geqrf_r(const QrDescT<R>* d_qr, int batch, int max_m, int max_c, hipStre
       {
         KScope ks(PK_TS_LEAF, s);
         if (v == 1024 && sizeof(R) == 4)   // FP64 spills at 1024 threads
-          hipLaunchKernelGGL((k_ts_leaf<float, 1024>), dim3(nb, batch), dim3(1024), 0, s,
+          PMX_LAUNCH((k_ts_leaf<float, 1024>), dim3(nb, batch), dim3(1024), 0, s,
                              (const QrDescT<float>*)d_qr, j0, L);
         else if (v == 256)
-          hipLaunchKernelGGL((k_ts_leaf<R, 256>), dim3(nb, batch), dim3(256), 0, s, d_qr, j0, L);
+          PMX_LAUNCH((k_ts_leaf<R, 256>), dim3(nb, batch), dim3(256), 0, s, d_qr, j0, L);
         else
-          hipLaunchKernelGGL((k_ts_leaf<R, 512>), dim3(nb, batch), dim3(512), 0, s, d_qr, j0, L);
+          PMX_LAUNCH((k_ts_leaf<R, 512>), dim3(nb, batch), dim3(512), 0, s, d_qr, j0, L);
       }
       if (nc > 0) {
         KScope ks(PK_TS_UPDATE, s);
         if constexpr (sizeof(R) == 4)
-          hipLaunchKernelGGL(k_ts_update_f32, dim3((nc + 63) / 64, nb, batch), dim3(256), 0, s,
+          PMX_LAUNCH(k_ts_update_f32, dim3((nc + 63) / 64, nb, batch), dim3(256), 0, s,
                              reinterpret_cast<const QrDescT<float>*>(d_qr), j0, L);
         else
-          hipLaunchKernelGGL(k_ts_update<R>, dim3((nc + 63) / 64, nb, batch), dim3(256), 0, s, d_qr, j0, L);
+          PMX_LAUNCH(k_ts_update_f64, dim3((nc + TSU64_COLS - 1) / TSU64_COLS, nb, batch), dim3(256), 0, s,
+                             reinterpret_cast<const QrDescT<double>*>(d_qr), j0, L);
       }
       if (nb <= 1) break;
       mr = nb * PMX_QR_NB;
     }
   }
   int64_t tot = (int64_t)kmax * max_c;
-  hipLaunchKernelGGL(k_copy_r<R>, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, s, d_qr);
+  PMX_LAUNCH(k_copy_r<R>, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, s, d_qr);
 }
 
 // ---------------------------------------------------------------------------------
@@ -2542,21 +2662,22 @@ void la_cpqr(const CpqrDescT<R>* d_cp, int batch, int max_c, double tol, const i
                                max_c < PMX_CPQR_MULTI_MIN ? 0 : 1, max_c, batch, 0);
   if (mode == 0) {
     KScope ks(PK_CPQR, s);
-    hipLaunchKernelGGL(k_cpqr<R>, dim3(batch), dim3(CP_NT), shm, s, d_cp, tol, d_kmin, init);
+    PMX_LAUNCH(k_cpqr<R>, dim3(batch), dim3(CP_NT), shm, s, d_cp, tol, d_kmin, init);
     return;
   }
   (void)hipMemsetAsync(d_work, 0, sizeof(int), s);
-  hipLaunchKernelGGL(k_cpqr_init<R>, dim3((max_c + 3) / 4, batch), dim3(256), 0, s, d_cp, init);
+  PMX_LAUNCH(k_cpqr_init<R>, dim3((max_c + 3) / 4, batch), dim3(256), 0, s, d_cp, init);
   const int ucols = (max_c + CPU_COLS - 1) / CPU_COLS;
   for (int it = 0; it <= max_c; ++it) {
-    hipLaunchKernelGGL(k_cpqr_pivot<R>, dim3(batch), dim3(256), 0, s, d_cp, tol, d_kmin, d_work);
+    PMX_LAUNCH(k_cpqr_pivot<R>, dim3(batch), dim3(256), 0, s, d_cp, tol, d_kmin, d_work);
     {
       KScope ks(PK_CPQR_UPDATE, s);
-      hipLaunchKernelGGL(k_cpqr_update<R>, dim3(ucols, batch), dim3(256), shm, s, d_cp);
+      PMX_LAUNCH(k_cpqr_update<R>, dim3(ucols, batch), dim3(256), shm, s, d_cp);
     }
     if ((it & 15) == 15) {
       int nd = 0;
       (void)hipMemcpyAsync(&nd, d_work, sizeof(int), hipMemcpyDeviceToHost, s);
+      pmx_count_sync();
       (void)hipStreamSynchronize(s);
       if (nd >= batch) break;
     }
@@ -2640,7 +2761,7 @@ __global__ __launch_bounds__(256) void k_qr_tail_norms(const QrDescT<R>* qrs, do
 template <class R>
 void la_qr_tail_norms(const QrDescT<R>* d_qr, double* const* d_out, int batch, int max_c, hipStream_t s) {
   if (batch <= 0 || max_c <= 0) return;
-  hipLaunchKernelGGL(k_qr_tail_norms<R>, dim3((max_c + 3) / 4, batch), dim3(256), 0, s, d_qr, d_out);
+  PMX_LAUNCH(k_qr_tail_norms<R>, dim3((max_c + 3) / 4, batch), dim3(256), 0, s, d_qr, d_out);
 }
 
 template <class R>
@@ -2662,7 +2783,7 @@ __global__ __launch_bounds__(256) void k_cpqr_judge(const CpqrDescT<R>* cps, con
 template <class R>
 void la_cpqr_judge(const CpqrDescT<R>* d_cp, const int* d_k, double tol, int* d_accept, int batch, hipStream_t s) {
   if (batch <= 0) return;
-  hipLaunchKernelGGL(k_cpqr_judge<R>, dim3(batch), dim3(256), 0, s, d_cp, d_k, tol, d_accept);
+  PMX_LAUNCH(k_cpqr_judge<R>, dim3(batch), dim3(256), 0, s, d_cp, d_k, tol, d_accept);
 }
 
 // Algorithmic work of the QR kernels for one m x c matrix, mirroring the launch sequence,

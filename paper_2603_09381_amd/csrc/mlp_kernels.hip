@@ -2,6 +2,7 @@
 // tiles per 256-thread workgroup, each wave a 32x32 sub-tile), bias and ReLU, the loss
 // gradient, column sums and the Adam update.
 #include "mlp.h"
+#include "pmx_common.h"
 
 #include <algorithm>
 #include <cmath>
@@ -92,13 +93,13 @@ void mlp_sgemm(int opa, int opb, int m, int n, int k, float alpha, const float* 
   if (m <= 0 || n <= 0) return;
   dim3 grid((m + 63) / 64, (n + 63) / 64);
   if (opa == 0 && opb == 0)
-    hipLaunchKernelGGL((k_sgemm<0, 0>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+    PMX_LAUNCH((k_sgemm<0, 0>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
   else if (opa == 0 && opb == 1)
-    hipLaunchKernelGGL((k_sgemm<0, 1>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+    PMX_LAUNCH((k_sgemm<0, 1>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
   else if (opa == 1 && opb == 0)
-    hipLaunchKernelGGL((k_sgemm<1, 0>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+    PMX_LAUNCH((k_sgemm<1, 0>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
   else
-    hipLaunchKernelGGL((k_sgemm<1, 1>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+    PMX_LAUNCH((k_sgemm<1, 1>), grid, dim3(256), 0, s, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
 // Z[:, c] += b; H = relu(Z) (H may be NULL: the output layer keeps Z)
@@ -212,7 +213,7 @@ void mlp_forward(const MlpShape& sh, const float* params, const std::vector<int6
     float* Z = wk.Z[l + 1];
     mlp_sgemm(0, 0, out, B, in, 1.0f, W, out, H, in, 0.0f, Z, out, s);
     float* Hn = (l + 1 < nl) ? wk.H[l + 1] : nullptr;
-    hipLaunchKernelGGL(k_bias_relu, dim3(nblk((int64_t)out * B)), dim3(256), 0, s, Z, b, out, (int64_t)B, Hn);
+    PMX_LAUNCH(k_bias_relu, dim3(nblk((int64_t)out * B)), dim3(256), 0, s, Z, b, out, (int64_t)B, Hn);
     H = Hn;
   }
   wk.H[0] = const_cast<float*>(X);
@@ -220,7 +221,7 @@ void mlp_forward(const MlpShape& sh, const float* params, const std::vector<int6
 
 void mlp_loss_grad(const float* out, const float* labels, int nout, int nscore, float wmse, int B, float* dout,
                    float* loss_part, hipStream_t s) {
-  hipLaunchKernelGGL(k_loss_grad, dim3(nblk(B)), dim3(256), 0, s, out, labels, nout, nscore, wmse, B, dout,
+  PMX_LAUNCH(k_loss_grad, dim3(nblk(B)), dim3(256), 0, s, out, labels, nout, nscore, wmse, B, dout,
                      loss_part);
 }
 
@@ -232,10 +233,10 @@ void mlp_backward(const MlpShape& sh, const float* params, const std::vector<int
     const float* dZ = wk.dZ[l + 1];
     // dW = dZ H^T, db = row sums of dZ
     mlp_sgemm(0, 1, out, in, B, 1.0f, dZ, out, wk.H[l], in, 0.0f, grad + off[2 * l], out, s);
-    hipLaunchKernelGGL(k_rowsum, dim3(out), dim3(256), 0, s, dZ, out, B, grad + off[2 * l + 1]);
+    PMX_LAUNCH(k_rowsum, dim3(out), dim3(256), 0, s, dZ, out, B, grad + off[2 * l + 1]);
     if (l > 0) {
       mlp_sgemm(1, 0, in, B, out, 1.0f, W, out, dZ, out, 0.0f, wk.dH[l], in, s);
-      hipLaunchKernelGGL(k_relu_back, dim3(nblk((int64_t)in * B)), dim3(256), 0, s, wk.Z[l], wk.dH[l], wk.dZ[l],
+      PMX_LAUNCH(k_relu_back, dim3(nblk((int64_t)in * B)), dim3(256), 0, s, wk.Z[l], wk.dH[l], wk.dZ[l],
                          (int64_t)in * B);
     }
   }
@@ -244,15 +245,15 @@ void mlp_backward(const MlpShape& sh, const float* params, const std::vector<int
 void mlp_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
               int t, hipStream_t s) {
   const float c1 = 1.0f - std::pow(b1, (float)t), c2 = 1.0f - std::pow(b2, (float)t);
-  hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  PMX_LAUNCH(k_adam, dim3(nblk(n)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
 }
 
 void mlp_gather_cols(const float* src, const int64_t* idx, int n, int rows, float* dst, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_gather_cols, dim3(nblk((int64_t)n * rows)), dim3(256), 0, s, src, idx, n, rows, dst);
+  PMX_LAUNCH(k_gather_cols, dim3(nblk((int64_t)n * rows)), dim3(256), 0, s, src, idx, n, rows, dst);
 }
 
 void mlp_standardise(float* x, const float* mean, const float* istd, int rows, int64_t cols, hipStream_t s) {
   if (cols <= 0) return;
-  hipLaunchKernelGGL(k_standardise, dim3(nblk(rows * cols)), dim3(256), 0, s, x, mean, istd, rows, cols);
+  PMX_LAUNCH(k_standardise, dim3(nblk(rows * cols)), dim3(256), 0, s, x, mean, istd, rows, cols);
 }

@@ -3,6 +3,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Host-side counts, per host thread, of kernel launches and of host waits on the device
+// (the factorisation reports both per call).  Every launch goes through PMX_LAUNCH.
+void pmx_count_launch();
+void pmx_count_sync();
+#define PMX_LAUNCH(...)              \
+  do {                               \
+    pmx_count_launch();              \
+    hipLaunchKernelGGL(__VA_ARGS__); \
+  } while (0)
+
 // complex number over a real type R (double or float)
 template <class R>
 struct cx {

@@ -132,6 +132,7 @@ void tune_candidates(int knob, int rb, int64_t d0, int64_t d1, int64_t d2, int* 
       if (d0 <= 256) out[(*n)++] = 4;
       if (d0 <= 512) out[(*n)++] = 6;
       if (rb == 4 && d0 <= 1024) out[(*n)++] = 8;
+      out[(*n)++] = 10;
       break;
     case TK_CPQR:
       out[(*n)++] = 0;
@@ -194,7 +195,7 @@ void fill(cx<R>* p, int64_t rows, int64_t cols, int64_t count, uint64_t seed, do
   const int64_t total = rows * cols * count;
   if (total <= 0) return;
   const int blocks = (int)std::min<int64_t>(4096, (total + 255) / 256);
-  hipLaunchKernelGGL(k_tune_fill<R>, dim3(blocks), dim3(256), 0, s, p, rows, cols, count, seed, decay, diag);
+  PMX_LAUNCH(k_tune_fill<R>, dim3(blocks), dim3(256), 0, s, p, rows, cols, count, seed, decay, diag);
 }
 
 // device buffers of one timing case, released at the end of the case

@@ -18,7 +18,8 @@
 enum TuneKnob : int {
   TK_LU_PANEL = 0,  // LU panel kernel by panel rows, batch: 0 registers 256 x 1 row, 1 registers
                     // 256 x 2 rows, 2 registers 512 x 2 rows (FP32 only), 3 global memory;
-                    // unrolled columns: 4 256 x 1, 6 512 x 1, 8 1024 x 1 (FP32 only)
+                    // unrolled columns: 4 256 x 1, 6 512 x 1, 8 1024 x 1 (FP32 only);
+                    // 10 tall panels, rows in memory (1024 threads FP32, 512 FP64)
   TK_CPQR = 1,      // column-pivoted QR by columns, batch: 0 one workgroup per matrix,
                     // 1 multi-workgroup steps
   TK_GETRS = 2,     // level LU solves by size, batch, right-hand sides: 0 one fused kernel per

@@ -28,6 +28,7 @@ EXPORTS = [
     "pmx_probe_cgemm", "pmx_probe_lu_solve_c32", "pmx_probe_id_c32", "pmx_probe_apply",
     "pmx_mlp_opts_default", "pmx_id_dataset", "pmx_mlp_train", "pmx_mlp_predict", "pmx_probe_mlp",
     "pmx_autotune", "pmx_device_cache", "pmx_far_field_noalloc", "pmx_probe_apply_structure",
+    "pmx_factor_refactor",
 ]
 
 
@@ -53,7 +54,7 @@ class Options(C.Structure):
                 ("timing", C.c_int32), ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double),
                 ("solve_graph", C.c_int32), ("learned", C.c_int32), ("model_path", C.c_char_p),
                 ("timing_kernels", C.c_uint32), ("reserved0", C.c_int32), ("tune_path", C.c_char_p),
-                ("reserved", C.c_int32 * 4)]
+                ("refactor", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Info(C.Structure):
@@ -65,7 +66,10 @@ class Info(C.Structure):
                 ("kernel_bytes", C.c_double * 16), ("kernel_flops", C.c_double * 16),
                 ("t_solve_ms", C.c_double), ("ir_iterations", C.c_int32), ("ir_residual", C.c_double),
                 ("ir_history", C.c_double * 16), ("id_learned", C.c_int32), ("id_fallback", C.c_int32),
-                ("apply_stats", C.c_double * 8)]
+                ("apply_stats", C.c_double * 8), ("factor_launches", C.c_int64),
+                ("factor_host_syncs", C.c_int64), ("refactor_launches", C.c_int64),
+                ("refactor_graph_nodes", C.c_int64), ("refactor_host_syncs", C.c_int64),
+                ("t_refactor_ms", C.c_double)]
 
 
 class MlpOpts(C.Structure):
@@ -239,6 +243,18 @@ class Factor:
         i = Info()
         _check(_lib.pmx_factor_info(self.h, C.byref(i)))
         return i
+
+    def refactor(self, k_int, eps_int=None):
+        """pmx_factor_refactor: the kept numeric phase replayed for new interior media
+        (k_int per inclusion, eps_int per inclusion or None)."""
+        k = np.ascontiguousarray(k_int, dtype=np.float64)
+        if k.shape != (self.w.m,):
+            raise ValueError("k_int needs one value per inclusion")
+        e = None if eps_int is None else np.ascontiguousarray(eps_int, dtype=np.float64)
+        if e is not None and e.shape != (self.w.m,):
+            raise ValueError("eps_int needs one value per inclusion")
+        _check(_lib.pmx_factor_refactor(self.h, _ptr(k, C.c_double), None if e is None else _ptr(e, C.c_double),
+                                        _stream()))
 
     def solve_plane_waves(self, angles, out=None):
         import torch

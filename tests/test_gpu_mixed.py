@@ -57,6 +57,20 @@ def test_lu_solve_fp32(pmx, n, nrhs, variant):
     assert res < 1e-6 * n * np.abs(A).max() * np.abs(ref).max()
 
 
+def test_lu_tall_panels_fp32(pmx):
+    """FP32 panels above 1024 rows (the tall-panel kernel) on unshifted random matrices,
+    which pivot at almost every column: backward error of the solution."""
+    n, batch = 2100, 2
+    A = c64(crandn(batch, n, n))
+    B = c64(crandn(batch, n, 2))
+    _, piv, X, info = pmx.probe_lu_solve(A, B, fp32=True)
+    assert (info == 0).all()
+    for b in range(batch):
+        assert piv[b].min() >= 0 and piv[b].max() < n and (piv[b] >= np.arange(n)).all()
+        res = np.abs(A[b].astype(np.complex128) @ X[b].astype(np.complex128) - B[b]).max()
+        assert res < 1e-6 * n * np.abs(A[b]).max() * np.abs(X[b]).max()
+
+
 def _lowrank(m, c, r, decay):
     U = crandn(m, r)
     V = crandn(r, c)

@@ -77,6 +77,24 @@ def test_lu_solve(pmx, n, nrhs, variant):
     assert np.abs(X - ref).max() < 1e-11 * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("n", [300, 700, 1100])
+def test_lu_pivots_are_partial_pivoting(pmx, n):
+    """Unshifted random matrices pivot at almost every column: the row exchanges of the
+    register panels (up to 512 rows in FP64) and of the tall-panel kernel above them are
+    LAPACK's partial pivoting (largest |re| + |im| of the column, as izamax), entry for entry."""
+    import scipy.linalg as sl
+    batch = 2
+    A = crandn(batch, n, n)
+    B = crandn(batch, n, 3)
+    _, piv, X, info = pmx.probe_lu_solve(A, B)
+    assert (info == 0).all()
+    for b in range(batch):
+        _, ref_piv = sl.lu_factor(A[b])
+        assert np.array_equal(piv[b], ref_piv)
+        ref = np.linalg.solve(A[b], B[b])
+        assert np.linalg.norm(X[b] - ref) < 1e-9 * np.linalg.norm(ref)
+
+
 def test_lu_detects_singular(pmx):
     A = crandn(2, 40, 40)
     A[1, :, 7] = 0.0
@@ -91,7 +109,7 @@ def _lowrank(m, c, r, decay=None):
     return (U * s) @ V
 
 
-@pytest.mark.parametrize("m,c,r", [(300, 60, 20), (60, 60, 60), (40, 90, 25), (1000, 128, 128)])
+@pytest.mark.parametrize("m,c,r", [(300, 60, 20), (60, 60, 60), (40, 90, 25), (1000, 128, 128), (3000, 70, 30)])
 def test_id_residual_and_rank(pmx, m, c, r):
     batch = 3
     tol = 1e-10
