@@ -388,7 +388,10 @@ def run_form(pmx, w, kw, steps, warmup, timing):
         fac.close()
         inf = infos[-1]
         print(f"bench: timed step {i + 1}/{steps}: {times[-1]:.3f} s (factor {inf.t_factor_ms:.0f} ms, solve "
-              f"{inf.t_solve_ms:.0f} ms, solve set-up {inf.t_phase_ms[5]:.0f} ms, apply set-up {inf.t_phase_ms[6]:.0f} ms)",
+              f"{inf.t_solve_ms:.0f} ms, solve set-up {inf.t_phase_ms[5]:.0f} ms: program {inf.t_phase_ms[9]:.0f}, "
+              f"leaf maps {inf.t_phase_ms[10]:.0f}, apply {inf.t_phase_ms[6]:.0f} ms; factor phases: entries+IDs+Schur "
+              f"{inf.t_phase_ms[1]:.0f}, merge {inf.t_phase_ms[2]:.0f}, top {inf.t_phase_ms[3]:.0f}, leaf IDs "
+              f"{inf.t_phase_ms[7]:.0f} ms)",
               file=sys.stderr, flush=True)
     if timing and k is None:     # no warm-up: every kernel was timed in the timed steps
         k, top, share = dominant_kernel(infos, names)

@@ -115,7 +115,8 @@ typedef struct {
                                 solve state for a new right-hand-side count, 6 of it the
                                 operator apply set-up; 7 the leaf level's IDs (part of 1:
                                 QR, CPQR, with learned proposals their judge and fallback),
-                                8 the learned proposals (features and network, at create) */
+                                8 the learned proposals (features and network, at create),
+                                9 and 10 the solve program and the leaf maps (host parts of 5) */
   /* with options.timing = 1: per-kernel device time from HIP events around every launch
    * (of the kernels selected by options.timing_kernels) of the factorisation and of the
    * solves, summed over them (index: 0 QR leaf blocks, 1 QR trailing update, 2 LU panel, 3 CPQR

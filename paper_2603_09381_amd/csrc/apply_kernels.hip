@@ -137,115 +137,137 @@ __device__ __noinline__ bes4 bessel01_mid(double z) {
   return bessel01_t(z, tab, ser);
 }
 
-// Expansion coefficients of every inclusion (one workgroup of four waves per inclusion, its
-// nodes 64 at a time; every wave runs the recurrences, wave w reduces the orders m = w mod 4,
-// so that four reduction chains proceed at once).  J_0 .. J_{PMAX+3} of k rho_y by Miller's backward recurrence from order
-// PMAX + 27 + k r_j (normalised by J_0 + 2 sum J_2k = 1, a first pass finding the norm),
-// R_{+-m} = J_m e^{-+i m th} (R_{-m} = (-1)^m J_m e^{+i m th}), and the three sums
-// Mq_n = sum R_n q~, U+_n = sum R_n nu u~, U-_n = sum R_n conj(nu) u~ reduced over the wave
-// and accumulated in LDS; then Mu_n = (k/2)(-U+_{n+1} + U-_{n-1}) and the records.
+// Expansion coefficients of every inclusion (one workgroup per inclusion, its nodes 32 at a
+// time).  R_{+-m} = J_m e^{-+i m th} (R_{-m} = (-1)^m conj R_m), with J_0 .. J_{P2M_MO} of
+// k rho_y by Miller's backward recurrence from order PMAX + 27 + k r_j (normalised by
+// J_0 + 2 sum J_2k = 1, a first pass finding the norm), and the three sums
+// Mq_n = sum R_n q~, U+_n = sum R_n nu u~, U-_n = sum R_n conj(nu) u~ over the nodes; then
+// Mu_n = (k/2)(-U+_{n+1} + U-_{n-1}) and the records.  Per chunk of 32 nodes the eight
+// threads of a node each run its recurrence and store every eighth order of R_m in LDS
+// (node-major, so that the threads of consecutive orders read consecutive words), and the
+// node's three density products; then thread (|m|, kind) accumulates, over the chunk's
+// nodes, R_m and R_-m times its kind's products for every right-hand side in registers: no
+// reduction across lanes.  The sums go to LDS (the chunk buffers' space) at the end.
 constexpr int P2M_MO = PMX_APPLY_PMAX + 3;   // orders -P2M_MO .. P2M_MO accumulated
+constexpr int P2M_NC = 32;                   // nodes per chunk
+constexpr int P2M_OM = P2M_MO + 1;           // orders 0 .. P2M_MO in the table
 
 template <int NR>
 __global__ __launch_bounds__(256) void k_apply_p2m(ApplyArgs A, const double* __restrict__ pk, int r0) {
   constexpr int S = APPLY_SRC(NR);
   constexpr int NM = 2 * P2M_MO + 1;
-  __shared__ double acc[NM][NR][6];           // per order: Mq, U+, U- (re, im)
+  constexpr int TAB = P2M_NC * P2M_OM * 2 + P2M_NC * 3 * NR * 2;   // doubles of the chunk buffers
+  constexpr int ACC = NM * NR * 6;
+  __shared__ double sm[TAB > ACC ? TAB : ACC];
+  double* Rt = sm;                                  // [node][order] (re, im)
+  double* Vt = sm + P2M_NC * P2M_OM * 2;            // [node][kind][rhs] (re, im)
+  double(*acc)[NR][6] = reinterpret_cast<double(*)[NR][6]>(sm);   // after the chunks: [order][rhs][6]
   const int j = blockIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int e = threadIdx.x; e < NM * NR * 6; e += 256) (&acc[0][0][0])[e] = 0.0;
-  __syncthreads();
+  const int tid = threadIdx.x;
   const double cx = A.incl_geo[4 * j], cy = A.incl_geo[4 * j + 1], rj = A.incl_geo[4 * j + 2];
   const double k = A.k;
   const int nstart = P2M_MO + 24 + (int)ceil(k * rj);
   const int64_t b0 = A.node_off[j], b1 = A.node_off[j + 1];
-  for (int64_t c0 = b0; c0 < b1; c0 += 64) {
-    const int64_t bn = c0 + lane;
-    const bool valid = bn < b1;
-    const double* p = pk + (valid ? bn : b1 - 1) * S;
-    const double dx = p[0] - cx, dy = p[1] - cy;
-    const double rho = fmax(sqrt(dx * dx + dy * dy), 1e-30 * (1.0 + rj));   // a node at the centre stays finite
-    const double z = k * rho;
-    const double er = dx / rho, ei = -dy / rho;     // e^{-i th}
-    const double nur = p[2], nui = p[3];
-    double qr[NR], qi[NR], ur[NR], ui[NR];
+  // phase B roles: thread (|m|, kind) for |m| <= P2M_MO, kind 0 q, 1 nu u, 2 conj(nu) u
+  const bool acc_thread = tid < 3 * P2M_OM;
+  const int om = tid % P2M_OM, kind = tid / P2M_OM;
+  double pr[NR], pi[NR], mr[NR], mi[NR];     // sums for +|m| and -|m|
 #pragma unroll
-    for (int rr = 0; rr < NR; ++rr) {
-      const double f = valid ? 1.0 : 0.0;
-      qr[rr] = f * p[5 + 4 * rr];
-      qi[rr] = f * p[6 + 4 * rr];
-      ur[rr] = f * p[7 + 4 * rr];
-      ui[rr] = f * p[8 + 4 * rr];
-    }
-    // pass 1: the norm of the backward recurrence
-    const double iz2 = 2.0 / z;
-    double jp = 0.0, jc = 1e-280, nrm = (nstart % 2 == 0) ? 2.0 * jc : 0.0;
-    for (int m = nstart; m >= 1; --m) {
-      const double jm = m * iz2 * jc - jp;
-      jp = jc;
-      jc = jm;
-      if (((m - 1) & 1) == 0) nrm += (m - 1 == 0) ? jm : 2.0 * jm;
-    }
-    const double inv = 1.0 / nrm;
-    // e^{-i P2M_MO th} by repeated squaring
-    double Er = 1.0, Ei = 0.0, br = er, bi = ei;
-    for (int e = P2M_MO; e > 0; e >>= 1) {
-      if (e & 1) {
-        const double t = Er * br - Ei * bi;
-        Ei = Er * bi + Ei * br;
-        Er = t;
+  for (int rr = 0; rr < NR; ++rr) pr[rr] = pi[rr] = mr[rr] = mi[rr] = 0.0;
+  for (int64_t c0 = b0; c0 < b1; c0 += P2M_NC) {
+    {
+      // phase A: node nd of the chunk, part pt of its orders (m = pt mod 8)
+      const int nd = tid & (P2M_NC - 1), pt = tid / P2M_NC;
+      const int64_t bn = c0 + nd;
+      const bool valid = bn < b1;
+      const double* p = pk + (valid ? bn : b1 - 1) * S;
+      const double dx = p[0] - cx, dy = p[1] - cy;
+      const double rho = fmax(sqrt(dx * dx + dy * dy), 1e-30 * (1.0 + rj));   // a node at the centre stays finite
+      const double z = k * rho;
+      const double er = dx / rho, ei = -dy / rho;     // e^{-i th}
+      const double iz2 = 2.0 / z;
+      double jp = 0.0, jc = 1e-280, nrm = (nstart % 2 == 0) ? 2.0 * jc : 0.0;
+      for (int m = nstart; m >= 1; --m) {
+        const double jm = m * iz2 * jc - jp;
+        jp = jc;
+        jc = jm;
+        if (((m - 1) & 1) == 0) nrm += (m - 1 == 0) ? jm : 2.0 * jm;
       }
-      const double t = br * br - bi * bi;
-      bi = 2.0 * br * bi;
-      br = t;
+      const double inv = valid ? 1.0 / nrm : 0.0;   // a missing node contributes nothing
+      // e^{-i P2M_MO th} by repeated squaring
+      double Er = 1.0, Ei = 0.0, br = er, bi = ei;
+      for (int e = P2M_MO; e > 0; e >>= 1) {
+        if (e & 1) {
+          const double t = Er * br - Ei * bi;
+          Ei = Er * bi + Ei * br;
+          Er = t;
+        }
+        const double t = br * br - bi * bi;
+        bi = 2.0 * br * bi;
+        br = t;
+      }
+      jp = 0.0;
+      jc = 1e-280;
+      for (int m = nstart; m >= 0; --m) {
+        if (m <= P2M_MO) {
+          if ((m & 7) == pt) {
+            const double Jm = jc * inv;
+            Rt[(nd * P2M_OM + m) * 2] = Jm * Er;
+            Rt[(nd * P2M_OM + m) * 2 + 1] = Jm * Ei;
+          }
+          // e^{-i (m-1) th} = e^{-i m th} e^{+i th}
+          const double t = Er * er + Ei * ei;
+          Ei = Ei * er - Er * ei;
+          Er = t;
+        }
+        if (m == 0) break;
+        const double jm = m * iz2 * jc - jp;
+        jp = jc;
+        jc = jm;
+      }
+      // the node's density products, right-hand sides split over the node's eight threads
+      const double nur = p[2], nui = p[3];
+      for (int rr = pt; rr < NR; rr += 8) {
+        const double qr = p[5 + 4 * rr], qi = p[6 + 4 * rr], ur = p[7 + 4 * rr], ui = p[8 + 4 * rr];
+        double* v = Vt + (nd * 3 * NR) * 2;
+        v[(0 * NR + rr) * 2] = qr;
+        v[(0 * NR + rr) * 2 + 1] = qi;
+        v[(1 * NR + rr) * 2] = nur * ur - nui * ui;     // nu u
+        v[(1 * NR + rr) * 2 + 1] = nur * ui + nui * ur;
+        v[(2 * NR + rr) * 2] = nur * ur + nui * ui;     // conj(nu) u
+        v[(2 * NR + rr) * 2 + 1] = nur * ui - nui * ur;
+      }
     }
-    // pass 2: the same recurrence, accumulating orders P2M_MO .. 0
-    jp = 0.0;
-    jc = 1e-280;
-    for (int m = nstart; m >= 0; --m) {
-      if (m <= P2M_MO) {
-        const double Jm = jc * inv;
-        const double sg = (m & 1) ? -1.0 : 1.0;
-        // R_m = Jm (Er + i Ei), R_-m = sg Jm (Er - i Ei)
-        const double Rpr = Jm * Er, Rpi = Jm * Ei, Rmr = sg * Jm * Er, Rmi = -sg * Jm * Ei;
+    __syncthreads();
+    if (acc_thread) {
+      // phase B: R_m v and R_-m v = (-1)^m conj(R_m) v over the chunk's nodes
+      const int nn = (int)min<int64_t>(P2M_NC, b1 - c0);
+      for (int nd = 0; nd < nn; ++nd) {
+        const double rr_ = Rt[(nd * P2M_OM + om) * 2], ri_ = Rt[(nd * P2M_OM + om) * 2 + 1];
+        const double* v = Vt + (nd * 3 * NR + kind * NR) * 2;
 #pragma unroll
         for (int rr = 0; rr < NR; ++rr) {
-          if ((m & 3) != wave) break;   // another wave reduces this order
-          const double vur = nur * ur[rr] - nui * ui[rr], vui = nur * ui[rr] + nui * ur[rr];      // nu u
-          const double wur = nur * ur[rr] + nui * ui[rr], wui = nur * ui[rr] - nui * ur[rr];      // conj(nu) u
-          double t[12];
-          t[0] = Rpr * qr[rr] - Rpi * qi[rr];
-          t[1] = Rpr * qi[rr] + Rpi * qr[rr];
-          t[2] = Rpr * vur - Rpi * vui;
-          t[3] = Rpr * vui + Rpi * vur;
-          t[4] = Rpr * wur - Rpi * wui;
-          t[5] = Rpr * wui + Rpi * wur;
-          t[6] = Rmr * qr[rr] - Rmi * qi[rr];
-          t[7] = Rmr * qi[rr] + Rmi * qr[rr];
-          t[8] = Rmr * vur - Rmi * vui;
-          t[9] = Rmr * vui + Rmi * vur;
-          t[10] = Rmr * wur - Rmi * wui;
-          t[11] = Rmr * wui + Rmi * wur;
-#pragma unroll
-          for (int q = 0; q < 12; ++q) t[q] = wave_sum_a(t[q]);
-          if (lane == 0) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) acc[P2M_MO + m][rr][q] += t[q];
-            if (m > 0) {
-#pragma unroll
-              for (int q = 0; q < 6; ++q) acc[P2M_MO - m][rr][q] += t[6 + q];
-            }
-          }
+          const double vr = v[2 * rr], vi = v[2 * rr + 1];
+          pr[rr] = fma(rr_, vr, fma(-ri_, vi, pr[rr]));
+          pi[rr] = fma(rr_, vi, fma(ri_, vr, pi[rr]));
+          mr[rr] = fma(rr_, vr, fma(ri_, vi, mr[rr]));
+          mi[rr] = fma(rr_, vi, fma(-ri_, vr, mi[rr]));
         }
-        // e^{-i (m-1) th} = e^{-i m th} e^{+i th}
-        const double t = Er * er + Ei * ei;
-        Ei = Ei * er - Er * ei;
-        Er = t;
       }
-      if (m == 0) break;
-      const double jm = m * iz2 * jc - jp;
-      jp = jc;
-      jc = jm;
+    }
+    __syncthreads();
+  }
+  // the sums into acc[P2M_MO +- m][rr][2 kind ..]: the chunk buffers are free
+  if (acc_thread) {
+    const double sg = (om & 1) ? -1.0 : 1.0;
+#pragma unroll
+    for (int rr = 0; rr < NR; ++rr) {
+      acc[P2M_MO + om][rr][2 * kind] = pr[rr];
+      acc[P2M_MO + om][rr][2 * kind + 1] = pi[rr];
+      if (om > 0) {
+        acc[P2M_MO - om][rr][2 * kind] = sg * mr[rr];
+        acc[P2M_MO - om][rr][2 * kind + 1] = sg * mi[rr];
+      }
     }
   }
   __syncthreads();

@@ -108,6 +108,12 @@ template <class R>
 void asm_identity(const Mat2T<R>* d, int batch, int max_n, hipStream_t s);
 template <class R>
 void asm_zero(cx<R>* p, int64_t n, hipStream_t s);
+// Near row and column code lists of the cells of a level: cell t's list starts at nro[t]
+// and holds the codes rows / cols [offS[s], offS[s + 1]) of its near cells
+// s = nidx[noff[t] .. noff[t + 1]) in order, then its proxy points poff[t] .. + np[t]
+// (value type, then derivative type).  All arrays in device memory.
+void asm_near_lists(const int* rows, const int* cols, const int64_t* offS, const int* noff, const int* nidx,
+                    const int64_t* nro, const int* poff, const int* np, int ncell, int* nr, int* ncl, hipStream_t s);
 // p[0 .. n) = 0 by a kernel (a node that graph capture records like any launch)
 void asm_zero_i32(int* p, int64_t n, hipStream_t s);
 // dst[i] = src[i] converted to the destination's real type

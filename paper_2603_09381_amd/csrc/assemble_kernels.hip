@@ -428,6 +428,38 @@ void asm_zero(cx<R>* p, int64_t n, hipStream_t s) {
   PMX_LAUNCH(k_zero<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
 }
 
+// Near row and column code lists of every cell of a level (one workgroup per cell): the
+// active codes of its near cells in list order, then its proxy points, value type first.
+__global__ __launch_bounds__(256) void k_near_lists(const int* rows, const int* cols, const int64_t* offS,
+                                                     const int* noff, const int* nidx, const int64_t* nro,
+                                                     const int* poff, const int* np, int* nr, int* ncl) {
+  const int t = blockIdx.x;
+  int64_t o = nro[t];
+  for (int q = noff[t]; q < noff[t + 1]; ++q) {
+    const int sg = nidx[q];
+    const int64_t b = offS[sg];
+    const int len = (int)(offS[sg + 1] - b);
+    for (int i = threadIdx.x; i < len; i += 256) {
+      nr[o + i] = rows[b + i];
+      ncl[o + i] = cols[b + i];
+    }
+    o += len;
+  }
+  const int P = np[t], p0 = poff[t];
+  for (int i = threadIdx.x; i < 2 * P; i += 256) {
+    const int ty = i / P, k = i - ty * P;
+    const int c = pmx_code_proxy(p0 + k, ty);
+    nr[o + i] = c;
+    ncl[o + i] = c;
+  }
+}
+
+void asm_near_lists(const int* rows, const int* cols, const int64_t* offS, const int* noff, const int* nidx,
+                    const int64_t* nro, const int* poff, const int* np, int ncell, int* nr, int* ncl, hipStream_t s) {
+  if (ncell <= 0) return;
+  PMX_LAUNCH(k_near_lists, dim3(ncell), dim3(256), 0, s, rows, cols, offS, noff, nidx, nro, poff, np, nr, ncl);
+}
+
 __global__ void k_zero_i32(int* p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;

@@ -729,35 +729,31 @@ void id_stage(pmx_factor* F, const LevelData<R>& L, const std::vector<CellPlan>&
               const LearnedPlan* lp, IdOut<R>& io, Arena& tmp, hipStream_t s) {
   const int nc = L.ncell;
   const double tol = F->opts.id_tol;
-  std::vector<int> nearrows, nearcols;
+  // near code lists, built on the device from the level's code arrays (the host only
+  // sums their lengths)
   std::vector<int64_t> nro(nc), mid(nc);
-  {
-    size_t tot = 0;
-    for (int t = 0; t < nc; ++t) {
-      for (int sgm : cells[t].near) tot += (size_t)(L.s0[sgm] + L.s1[sgm]);
-      tot += 2 * (size_t)cells[t].P;
-    }
-    nearrows.reserve(tot);
-    nearcols.reserve(tot);
-  }
+  std::vector<int> noff(nc + 1), nidx, poff(nc), np(nc);
+  int64_t tot = 0;
   for (int t = 0; t < nc; ++t) {
-    nro[t] = (int64_t)nearrows.size();
+    nro[t] = tot;
+    noff[t] = (int)nidx.size();
     for (int sgm : cells[t].near) {
-      nearrows.insert(nearrows.end(), L.rows.begin() + L.offS[sgm], L.rows.begin() + L.offS[sgm] + L.s0[sgm] + L.s1[sgm]);
-      nearcols.insert(nearcols.end(), L.cols.begin() + L.offS[sgm], L.cols.begin() + L.offS[sgm] + L.s0[sgm] + L.s1[sgm]);
+      nidx.push_back(sgm);
+      tot += L.s0[sgm] + L.s1[sgm];
     }
-    for (int ty = 0; ty < 2; ++ty)
-      for (int k = 0; k < cells[t].P; ++k) {
-        nearrows.push_back(pmx_code_proxy(PT.off[t] + k, ty));
-        nearcols.push_back(pmx_code_proxy(PT.off[t] + k, ty));
-      }
-    mid[t] = (int64_t)nearrows.size() - nro[t];
+    tot += 2 * (int64_t)cells[t].P;
+    poff[t] = PT.off[t];
+    np[t] = cells[t].P;
+    mid[t] = tot - nro[t];
     if (mid[t] == 0) fail(PMX_EGEOM, "a cell has neither near cells nor a proxy circle");
   }
-  int* d_nr = tmp.upload(nearrows, s);
-  int* d_ncol = tmp.upload(nearcols, s);
+  noff[nc] = (int)nidx.size();
   int* d_rows = tmp.upload(L.rows, s);
   int* d_cols = tmp.upload(L.cols, s);
+  int* d_nr = tmp.alloc<int>(std::max<int64_t>(tot, 1));
+  int* d_ncol = tmp.alloc<int>(std::max<int64_t>(tot, 1));
+  asm_near_lists(d_rows, d_cols, tmp.upload(L.offS, s), tmp.upload(noff, s), tmp.upload(nidx, s), tmp.upload(nro, s),
+                 tmp.upload(poff, s), tmp.upload(np, s), nc, d_nr, d_ncol, s);
   const int nid = 4 * nc;
   io.idm.assign(nid, 0);
   io.idc.assign(nid, 0);
@@ -2411,8 +2407,12 @@ void ensure_state(pmx_factor* F, int nrhs) {
   S.reset();
   hipStream_t s = F->gs;
   Arena& A = S.arena;
+  const double tp = now_ms();
   build_program<R>(F, nrhs, s);
+  const double tl = now_ms();
+  F->info.t_phase_ms[9] += tl - tp;
   build_leaf_map(F, nrhs, S.map, A, s);
+  F->info.t_phase_ms[10] += now_ms() - tl;
   const std::vector<CellPlan>& leaves = F->plan[0];
   const int nc = (int)leaves.size();
   std::vector<int> node0(nc), nn(nc);

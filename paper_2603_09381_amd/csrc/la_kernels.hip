@@ -175,8 +175,14 @@ __device__ inline int block_argmax(double v, int i, double* redv, int* redi, dou
 
 // ---------------------------------------------------------------------------------
 // ZGEMM
+// C = alpha op(A) op(B) + beta C on 64 x 64 tiles, four waves of 32 x 32 (2 x 2 blocks of
+// 16 x 16 MFMA).  The k loop moves 16 at a time through LDS; the next slice's global loads
+// are issued into registers before the current slice is multiplied, so they are in flight
+// during the MFMAs.  Complex products as three real ones (Gauss): p1 = sum ar br,
+// p2 = sum ai bi, p3 = sum (ar + ai)(br + bi), C = (p1 - p2) + i (p3 - p1 - p2).
+#define ZG_KS 16
 template <class R, int OPA, int OPB, class F>
-__global__ __launch_bounds__(256) void k_zgemm(F f, cx<R> alpha, cx<R> beta) {
+__global__ __launch_bounds__(256, 2) void k_zgemm(F f, cx<R> alpha, cx<R> beta) {
   typedef cx<R> C;
   typedef typename AccT<R>::type V4;
   GemmArgsT<R> g;
@@ -186,68 +192,96 @@ __global__ __launch_bounds__(256) void k_zgemm(F f, cx<R> alpha, cx<R> beta) {
   const auto gC = gbl(g.C);
   const int tm = blockIdx.x * 64, tn = blockIdx.y * 64;
   if (tm >= g.m || tn >= g.n) return;
-  __shared__ C As[8][64 + 1];
-  __shared__ C Bs[8][64 + 1];
+  __shared__ C As[ZG_KS][64 + 1];
+  __shared__ C Bs[ZG_KS][64 + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  V4 accR[2][2], accI[2][2];
+  V4 p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      accR[a][b] = V4{0, 0, 0, 0};
-      accI[a][b] = V4{0, 0, 0, 0};
+      p1[a][b] = V4{0, 0, 0, 0};
+      p2[a][b] = V4{0, 0, 0, 0};
+      p3[a][b] = V4{0, 0, 0, 0};
     }
-  for (int k0 = 0; k0 < g.k; k0 += 8) {
+  // slice loads: 64 x 16 of A and 16 x 64 of B, four entries each per thread
+  constexpr int NP = 64 * ZG_KS / 256;
+  C ra[NP], rb[NP];
+  auto a_pos = [&](int pass, int& i, int& kk) {
+    if (OPA == OP_N) {
+      i = tid & 63;
+      kk = (tid >> 6) + 4 * pass;
+    } else {
+      kk = tid & (ZG_KS - 1);
+      i = (tid / ZG_KS) + (256 / ZG_KS) * pass;
+    }
+  };
+  auto b_pos = [&](int pass, int& j, int& kk) {
+    if (OPB == OP_N) {
+      kk = tid & (ZG_KS - 1);
+      j = (tid / ZG_KS) + (256 / ZG_KS) * pass;
+    } else {
+      j = tid & 63;
+      kk = (tid >> 6) + 4 * pass;
+    }
+  };
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < NP; ++pass) {
       int i, kk;
-      if (OPA == OP_N) {
-        i = tid & 63;
-        kk = (tid >> 6) + 4 * pass;
-      } else {
-        kk = tid & 7;
-        i = (tid >> 3) + 32 * pass;
-      }
+      a_pos(pass, i, kk);
       const int gi = tm + i, gk = k0 + kk;
       const int ci = min(gi, g.m - 1), ck = min(gk, g.k - 1);
       C v = (OPA == OP_N) ? gA[ci + (int64_t)ck * g.lda] : gA[ck + (int64_t)ci * g.lda];
       if (OPA == OP_C) v.im = -v.im;
-      As[kk][i] = (gi < g.m && gk < g.k) ? v : cmk<R>(0, 0);
+      ra[pass] = (gi < g.m && gk < g.k) ? v : cmk<R>(0, 0);
     }
 #pragma unroll
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < NP; ++pass) {
       int j, kk;
-      if (OPB == OP_N) {
-        kk = tid & 7;
-        j = (tid >> 3) + 32 * pass;
-      } else {
-        j = tid & 63;
-        kk = (tid >> 6) + 4 * pass;
-      }
+      b_pos(pass, j, kk);
       const int gj = tn + j, gk = k0 + kk;
       const int cj = min(gj, g.n - 1), ck = min(gk, g.k - 1);
       C v = (OPB == OP_N) ? gB[ck + (int64_t)cj * g.ldb] : gB[cj + (int64_t)ck * g.ldb];
       if (OPB == OP_C) v.im = -v.im;
-      Bs[kk][j] = (gj < g.n && gk < g.k) ? v : cmk<R>(0, 0);
+      rb[pass] = (gj < g.n && gk < g.k) ? v : cmk<R>(0, 0);
+    }
+  };
+  load(0);
+  for (int k0 = 0; k0 < g.k; k0 += ZG_KS) {
+#pragma unroll
+    for (int pass = 0; pass < NP; ++pass) {
+      int i, kk;
+      a_pos(pass, i, kk);
+      As[kk][i] = ra[pass];
+      int j, kb;
+      b_pos(pass, j, kb);
+      Bs[kb][j] = rb[pass];
     }
     __syncthreads();
+    if (k0 + ZG_KS < g.k) load(k0 + ZG_KS);
 #pragma unroll
-    for (int ks = 0; ks < 8; ks += 4) {
+    for (int ks = 0; ks < ZG_KS; ks += 4) {
       C a[2], b[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         a[t] = As[ks + (lane >> 4)][wm + t * 16 + (lane & 15)];
         b[t] = Bs[ks + (lane >> 4)][wn + t * 16 + (lane & 15)];
       }
+      R as[2], bs[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        as[t] = a[t].re + a[t].im;
+        bs[t] = b[t].re + b[t].im;
+      }
 #pragma unroll
       for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
-          accR[bi][bj] = mfma16(a[bi].re, b[bj].re, accR[bi][bj]);
-          accR[bi][bj] = mfma16(-a[bi].im, b[bj].im, accR[bi][bj]);
-          accI[bi][bj] = mfma16(a[bi].re, b[bj].im, accI[bi][bj]);
-          accI[bi][bj] = mfma16(a[bi].im, b[bj].re, accI[bi][bj]);
+          p1[bi][bj] = mfma16(a[bi].re, b[bj].re, p1[bi][bj]);
+          p2[bi][bj] = mfma16(a[bi].im, b[bj].im, p2[bi][bj]);
+          p3[bi][bj] = mfma16(as[bi], bs[bj], p3[bi][bj]);
         }
     }
     __syncthreads();
@@ -262,7 +296,8 @@ __global__ __launch_bounds__(256) void k_zgemm(F f, cx<R> alpha, cx<R> beta) {
         const int row = tm + wm + bi * 16 + mfma_row<R>(lane, r);
         const int col = tn + wn + bj * 16 + (lane & 15);
         if (row < g.m && col < g.n) {
-          C v = zmul(alpha, cmk<R>(accR[bi][bj][r], accI[bi][bj][r]));
+          const R x1 = p1[bi][bj][r], x2 = p2[bi][bj][r], x3 = p3[bi][bj][r];
+          C v = zmul(alpha, cmk<R>(x1 - x2, x3 - x1 - x2));
           auto cp = gC + row + (int64_t)col * g.ldc;
           if (use_beta) v = zfma(beta, *cp, v);
           *cp = v;
@@ -280,14 +315,13 @@ static void launch_zgemm(F f, int batch, int max_m, int max_n, cx<R> alpha, cx<R
 
 // C = alpha A B + beta C for few columns of B (n <= NB, both operands untransposed): the
 // product is bound by reading A, which MFMA tiles of 64 columns would mostly waste.  A
-// workgroup of eight waves takes 64 rows of one matrix; wave w accumulates the k range
+// workgroup of NW waves takes 64 rows of one matrix; wave w accumulates the k range
 // [w kc, (w + 1) kc) with one row per lane (the column-major A is read 64 consecutive
 // rows at a time, coalesced, eight loads in flight) and the row of B of each k read at a
-// wave-uniform address; the eight partial sums are added through LDS.
-template <class R, int NB, class F>
-__global__ __launch_bounds__(512) void k_zgemm_skinny(F f, cx<R> alpha, cx<R> beta) {
+// wave-uniform address; the NW partial sums are added through LDS.
+template <class R, int NB, int NW, class F>
+__global__ __launch_bounds__(NW * 64) void k_zgemm_skinny(F f, cx<R> alpha, cx<R> beta) {
   typedef cx<R> C;
-  constexpr int NW = 8;   // waves splitting k
   GemmArgsT<R> g;
   if (!f(blockIdx.z, g)) return;
   const auto gB = gbl(g.B);
@@ -345,9 +379,9 @@ static bool launch_zgemm_skinny(F f, int batch, int max_m, int max_n, cx<R> alph
   dim3 grid((max_m + 63) / 64, 1, batch);
   KScope ks(PK_ZGEMM, s);
   if (max_n <= 4)
-    PMX_LAUNCH((k_zgemm_skinny<R, 4, F>), grid, dim3(512), 0, s, f, alpha, beta);
+    PMX_LAUNCH((k_zgemm_skinny<R, 4, 8, F>), grid, dim3(512), 0, s, f, alpha, beta);
   else
-    PMX_LAUNCH((k_zgemm_skinny<R, 8, F>), grid, dim3(512), 0, s, f, alpha, beta);
+    PMX_LAUNCH((k_zgemm_skinny<R, 8, 8, F>), grid, dim3(512), 0, s, f, alpha, beta);
   return true;
 }
 

@@ -1,8 +1,8 @@
 """GPU tests of the autotuner and the launch-parameter table.
 
 The table built for a workload holds one valid choice per recorded launch shape.  Factors
-that use it, and factors forced onto the alternative kernels of every knob (global-memory
-or wider register LU panels, multi- or single-workgroup column-pivoted QR, blocked or
+that use it, and factors forced onto the alternative kernels of every knob (global-memory,
+tall-panel or wider register LU panels, multi- or single-workgroup column-pivoted QR, blocked or
 fused level solves, other apply groupings and source splits), solve the same system: their
 solutions match the oracle's dense FP64 solve to the bound of their form (plain FP64 at ID
 tolerance 1e-10: 5e-9; refined forms, stopped at a relative residual of 1e-10: 1e-8).
@@ -15,7 +15,7 @@ from paper_2603_09381_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-VALID = {"lu_panel": {0, 1, 2, 3, 4, 6, 8}, "cpqr": {0, 1}, "getrs": {0, 1, 2}, "apply_nr": {1, 2, 4, 8},
+VALID = {"lu_panel": {0, 1, 2, 3, 4, 6, 8, 10}, "cpqr": {0, 1}, "getrs": {0, 1, 2}, "apply_nr": {1, 2, 4, 8},
          "apply_wg": {512, 1024, 2048, 4096, 8192}, "ts_leaf": {256, 512, 1024}}
 FORMS = {0: dict(precision=0, id_tol=1e-10), 1: dict(precision=1, id_tol=1e-5, ir_tol=1e-10),
          2: dict(precision=2, id_tol=1e-6, ir_tol=1e-10)}
@@ -83,8 +83,10 @@ def test_autotune_table_and_solve(pmx, tmp_path, form):
     (1, dict(lu=4, cpqr=1, getrs=0)),
     (0, dict(lu=4, cpqr=1, getrs=2)),
     (2, dict(lu=6, cpqr=0, getrs=2)),
+    (0, dict(lu=10, cpqr=1, getrs=1)),
+    (1, dict(lu=10, cpqr=0, getrs=2)),
 ], ids=["plain-global", "plain-wide", "fp32-global", "fp32-wide", "fp64ir-global", "plain-unrolled512",
-        "fp32-unrolled1024", "fp32-unrolled256", "plain-ldssolve", "fp64ir-ldssolve"])
+        "fp32-unrolled1024", "fp32-unrolled256", "plain-ldssolve", "fp64ir-ldssolve", "plain-tall", "fp32-tall"])
 def test_forced_alternatives_match_dense(pmx, tmp_path, form, table):
     w = W.sub_grid(W.config2(), 4)
     path = tmp_path / "forced.txt"
