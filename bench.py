@@ -509,7 +509,8 @@ def main():
                       "apply_fmm": dict(zip(("m2l_pairs", "mean_source_order", "mean_local_order", "local_expansions",
                                              "l2l_pairs", "near_node_pairs", "direct_far_pairs", "table_bytes"),
                                             [float(v) for v in info.apply_stats])),
-                      "launch_table": table_note}}
+                      "launch_table": table_note,
+                      "self_block_quadrature": "Kress log-product rule (options.quadrature = 0)"}}
     if timing:
         res["roofline"] = roofline(infos, dom[0], dom[1], pmx.KERNEL_NAMES, 4, tag + "_tuned", thash_t)
         res["kernel_time_share"] = dom[2]

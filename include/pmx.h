@@ -98,7 +98,10 @@ typedef struct {
   int32_t refactor;        /* 1: keep the numeric phase of the factorisation (its buffers,
                               descriptors and launch sequence) for pmx_factor_refactor; not
                               with learned = 1 */
-  int32_t reserved[3];
+  int32_t quadrature;      /* self blocks: 0 Kress' logarithmic product rule (spectral);
+                              1 the zeta-corrected trapezoid rule with 41 local correction
+                              points of Sec. 2.2 (needs >= 42 nodes per inclusion) */
+  int32_t reserved[2];
 } pmx_options;
 
 typedef struct {

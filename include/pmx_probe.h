@@ -24,6 +24,11 @@ pmx_status pmx_probe_bessel(const double* z, int64_t n, double* out, void* strea
 /* Self block A_jj of inclusion j (Sec. 2.2 Omit form, Kress quadrature): out (device)
  * 2n_j x 2n_j column major. */
 pmx_status pmx_probe_diag_block(const pmx_geometry* geom, int32_t j, pmx_c64* out, void* stream);
+/* As pmx_probe_diag_block with the self-block quadrature of pmx_options.quadrature (0 Kress,
+ * 1 zeta-corrected trapezoid, Sec. 2.2).  PMX_EINVAL for other values or fewer than 42
+ * nodes with quadrature 1. */
+pmx_status pmx_probe_diag_block_quad(const pmx_geometry* geom, int32_t j, int32_t quadrature, pmx_c64* out,
+                                     void* stream);
 
 /* Off-diagonal (exterior) matrix entries between boundary nodes: rows (host) [nr] node
  * indices with row types rtyp (0 value, 1 normal-derivative equation), cols (host) [nc]

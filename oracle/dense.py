@@ -37,12 +37,14 @@ class Geometry:
 
 
 def diagonal_block(g: Geometry, j):
-    """A_jj of the Omit form: both wavenumbers, Kress self-interaction quadrature."""
+    """A_jj of the Omit form: both wavenumbers; Kress self-interaction quadrature, or the
+    zeta-corrected trapezoid rule (41 points, Sec. 2.2) when the workload asks for it."""
     w = g.w
     s = g.nodes(j)
     args = (w.x[s], w.y[s], w.dx[s], w.dy[s], w.ddx[s], w.ddy[s])
-    Sp, Dp, Dsp, Np = layer.self_blocks(*args, w.k_ext)
-    Sm, Dm, Dsm, Nm = layer.self_blocks(*args, w.k_int[j])
+    blocks = layer.self_blocks_zeta if getattr(w, "quadrature", "kress") == "zeta" else layer.self_blocks
+    Sp, Dp, Dsp, Np = blocks(*args, w.k_ext)
+    Sm, Dm, Dsm, Nm = blocks(*args, w.k_int[j])
     ep, em = g.eps_p, g.eps_m[j]
     return np.block([[-(ep * Sp + em * Sm), Dp + Dm],
                      [-(Dsp + Dsm), Np / ep + Nm / em]])

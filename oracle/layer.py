@@ -9,8 +9,9 @@ Conventions (readings of the paper, each listed in the design notes):
     hypersingular operator of Sec. 2.1 (eqs. slp, dlp, d_slp, d_dlp);
   * off-diagonal blocks use the trapezoid rule on the equispaced parameter nodes;
     the self-interaction blocks use Kress' logarithmic product quadrature
-    (Colton & Kress, Inverse Acoustic and EM Scattering Theory, Sec. 3.5) and the
-    hypersingular operator is written through Maue's identity
+    (Colton & Kress, Inverse Acoustic and EM Scattering Theory, Sec. 3.5) or, as the paper
+    does (Sec. 2.2), the zeta-corrected trapezoid rule with 41 local correction points, and
+    the hypersingular operator is written through Maue's identity
     N = d/ds S d/ds + k^2 n.S n with trigonometric differentiation.
 The Bessel and Hankel functions come from scipy.special (a library primitive).
 """
@@ -78,6 +79,94 @@ def trig_diff_matrix(n):
         Dt = 0.5 * (-1.0) ** (a[:, None] - a[None, :]) / np.tan(diff / 2.0)
     np.fill_diagonal(Dt, 0.0)
     return Dt
+
+
+ZETA_P = 20   # correction half-width: 2 p + 1 = 41 local correction points (Sec. 2.2)
+
+
+def zeta_weights(p=ZETA_P):
+    """omega_0 .. omega_p of the zeta-corrected trapezoid rule for a logarithmic point
+    singularity (Wu and Martinsson, the correction the paper uses in Sec. 2.2).
+
+    For a 2 pi-periodic f(u) = A(u) ln|2 sin(u/2)| + B(u) with A, B smooth and h = 2 pi / n,
+    the punctured trapezoid sum h sum_{j != 0} f(jh) misses, beyond h B(0), the terms
+    h A(0) ln(h / 2 pi) + 2 sum_{k >= 1} zeta'(-2k) A^(2k)(0) h^(2k+1) / (2k)!
+    (the Navot expansion; ln|2 sin(u/2)| - ln|u| is smooth and vanishes at 0).  The
+    symmetric weights omega_l (l = -p..p, omega_-l = omega_l) reproduce the derivative sum
+    on polynomials of degree 2p: sum_l omega_l = 0 and sum_l omega_l l^(2k) = 2 zeta'(-2k),
+    k = 1..p.  The moment system is solved in 60-digit arithmetic (mpmath, a library
+    primitive for zeta').
+    """
+    import mpmath as mp
+    with mp.workdps(60):
+        M = mp.matrix(p + 1, p + 1)
+        rhs = mp.matrix(p + 1, 1)
+        for kk in range(p + 1):
+            for l in range(p + 1):
+                mult = 1 if l == 0 else 2
+                M[kk, l] = mult * (mp.mpf(1) if kk == 0 else mp.mpf(l) ** (2 * kk))
+            rhs[kk] = 0 if kk == 0 else 2 * mp.zeta(-2 * kk, derivative=1)
+        w = mp.lu_solve(M, rhs)
+        return np.array([float(w[l]) for l in range(p + 1)])
+
+
+def zeta_corrected(K, A, Bdiag, p=ZETA_P):
+    """Nystrom matrix of a kernel K(t_a, t_b) = A ln|2 sin((t_a - t_b)/2)| + B on n
+    equispaced nodes by the zeta-corrected trapezoid rule: off the diagonal h K; on row a,
+    h (B(t_a, t_a) + A(t_a, t_a) ln(h / 2 pi)) on the diagonal and h omega_|l| A(t_a, t_a+l)
+    added for |l| <= p (indices mod n).  K's diagonal is ignored."""
+    n = K.shape[0]
+    if n < 2 * p + 2:
+        raise ValueError("the zeta-corrected rule needs n >= 2p + 2 nodes")
+    h = 2.0 * np.pi / n
+    om = zeta_weights(p)
+    M = h * K.astype(complex)
+    a = np.arange(n)
+    M[a, a] = h * (Bdiag + A[a, a] * np.log(h / (2.0 * np.pi)))
+    for l in range(-p, p + 1):
+        b = (a + l) % n
+        M[a, b] += h * om[abs(l)] * A[a, b]
+    return M
+
+
+def self_blocks_zeta(x, y, dx, dy, ddx, ddy, k, p=ZETA_P):
+    """S, D, D*, N of one closed curve onto itself with the zeta-corrected trapezoid rule
+    (41 local correction points for p = 20, Sec. 2.2); N by Maue's identity as in
+    self_blocks.  Each kernel times |x'(tau)| is K1 ln(4 sin^2((t - tau)/2)) + K2, so A = 2 K1
+    multiplies ln|2 sin| and B = K2."""
+    n = len(x)
+    off = np.array([0, n])
+    speed, nx, ny, _, kappa = boundary_quantities(dx, dy, ddx, ddy, off)
+    eye = np.eye(n, dtype=bool)
+    d1 = x[:, None] - x[None, :]
+    d2 = y[:, None] - y[None, :]
+    r = np.hypot(d1, d2)
+    r[eye] = 1.0
+    kr = k * r
+    J0, J1 = sp.j0(kr), sp.j1(kr)
+    H0, H1 = h01(kr)
+    sb = speed[None, :]
+    ndy = (nx[None, :] * d1 + ny[None, :] * d2) / r
+    ndx = (nx[:, None] * d1 + ny[:, None] * d2) / r
+    nn = nx[:, None] * nx[None, :] + ny[:, None] * ny[None, :]
+    diag_s = (0.25j - EULER_GAMMA / (2 * np.pi) - np.log(k * speed / 2.0) / (2 * np.pi)) * speed
+    diag_d = -kappa * speed / (4 * np.pi)
+    # single layer: K1 = -J0 |x'| / 4 pi (its diagonal value -|x'| / 4 pi)
+    K1 = -J0 * sb / (4 * np.pi)
+    K1[eye] = -speed / (4 * np.pi)
+    S = zeta_corrected(0.25j * H0 * sb, 2 * K1, diag_s, p)
+    Snn = zeta_corrected(0.25j * H0 * nn * sb, 2 * K1 * nn, diag_s, p)
+    # double layer and its adjoint: K1 vanishes on the diagonal
+    K1 = -(k / (4 * np.pi)) * J1 * ndy * sb
+    K1[eye] = 0.0
+    D = zeta_corrected(0.25j * k * H1 * ndy * sb, 2 * K1, diag_d, p)
+    K1 = (k / (4 * np.pi)) * J1 * ndx * sb
+    K1[eye] = 0.0
+    Ds = zeta_corrected(-0.25j * k * H1 * ndx * sb, 2 * K1, diag_d, p)
+    Dt = trig_diff_matrix(n)
+    Linv = np.diag(1.0 / speed)
+    N = Linv @ Dt @ S @ Linv @ Dt + k * k * Snn
+    return S, D, Ds, N
 
 
 def self_blocks(x, y, dx, dy, ddx, ddy, k):

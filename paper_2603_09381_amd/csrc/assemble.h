@@ -84,7 +84,7 @@ typedef GatherDescT<double> GatherDesc;
 void asm_geometry(const double* dx, const double* dy, const double* ddx, const double* ddy,
                   const int* owner, const int64_t* node_off, double* nx, double* ny, double* w,
                   double* speed, double* kappa, int n_nodes, hipStream_t s);
-void asm_tables(const int* ns, const int* tbl_off, int ntbl, int max_n, double* R, double* dt,
+void asm_tables(const int* ns, const int* tbl_off, int ntbl, int max_n, double* R, double* dt, int quad,
                 hipStream_t s);
 void asm_diag(DevGeom g, ExtParams e, const DiagDesc* d, int batch, int max_n, const double* R,
               const double* dt, hipStream_t s);

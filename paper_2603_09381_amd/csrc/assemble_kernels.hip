@@ -7,7 +7,8 @@
 //   N  = (ik/4) [k H0 (n_x.d)(n_y.d)/r^2 - 2 H1 (n_x.d)(n_y.d)/r^3 + H1 (n_x.n_y)/r].
 // Off-diagonal blocks of the Omit form use only k+ and the trapezoid weight of the
 // source node (Sec. 2.2):  [[-e+ S, D], [-D*, N/e+]].  Self blocks use both k+ and
-// the inclusion's k- with Kress' logarithmic product quadrature and N written by
+// the inclusion's k- with Kress' logarithmic product quadrature, or the paper's
+// zeta-corrected trapezoid rule with 41 local correction points (Sec. 2.2), and N written by
 // Maue's identity N = |x'|^-1 D_t S |x'|^-1 D_t + k^2 S_nn (trigonometric
 // differentiation D_t), then combined as
 //   [[-(e+ S+ + e- S-), D+ + D-], [-(D*+ + D*-), N+/e+ + N-/e-]].
@@ -19,6 +20,7 @@
 #include "bessel.h"
 #include "hankel_fast.h"
 #include "ktimer.h"
+#include "zeta_table.h"
 
 struct Pt {
   double x, y, nx, ny, w;
@@ -111,7 +113,11 @@ void asm_geometry(const double* dx, const double* dy, const double* ddx, const d
 
 // Kress weights R_d = -(2pi/h) sum_{m<h} cos(m t_d)/m - (pi/h^2) cos(h t_d), n = 2h, and the
 // trigonometric differentiation stencil dt_d = (1/2)(-1)^d cot(t_d/2), t_d = 2 pi d / n.
-__global__ void k_tables(const int* ns, const int* tbl_off, double* R, double* dt) {
+// With quad = 1 R holds the zeta-corrected trapezoid rule instead (Sec. 2.2): the self-block
+// entry R_d K1 + q (K - K1 L_d) (L_d = ln 4 sin^2(t_d/2), q = 2 pi / n) then equals q K plus
+// the correction q w_|d| (2 K1) on the 2 P + 1 nearest nodes, and q (K2 + 2 K1 (ln(q/2pi) + w_0))
+// on the diagonal: R_0 = 2 q (ln(q / 2 pi) + w_0), R_d = q L_d + 2 q w_min(d, n-d) (0 beyond P).
+__global__ void k_tables(const int* ns, const int* tbl_off, double* R, double* dt, int quad) {
   const int t = blockIdx.y;
   const int n = ns[t];
   const int d = blockIdx.x * blockDim.x + threadIdx.x;
@@ -123,14 +129,26 @@ __global__ void k_tables(const int* ns, const int* tbl_off, double* R, double* d
     s += cos(2.0 * PMX_PI * ph / n) / m;
   }
   const double sign = (d & 1) ? -1.0 : 1.0;
-  R[tbl_off[t] + d] = -(2.0 * PMX_PI / h) * s - (PMX_PI / ((double)h * h)) * sign;
+  if (quad == 1) {
+    const double q = 2.0 * PMX_PI / n;
+    const int dm = min(d, n - d);
+    const double wz = dm <= PMX_ZETA_P ? pmx_zeta_w[dm] : 0.0;
+    if (d == 0) {
+      R[tbl_off[t]] = 2.0 * q * (log(q / (2.0 * PMX_PI)) + wz);
+    } else {
+      const double sn = sin(PMX_PI * d / n);
+      R[tbl_off[t] + d] = q * log(4.0 * sn * sn) + 2.0 * q * wz;
+    }
+  } else {
+    R[tbl_off[t] + d] = -(2.0 * PMX_PI / h) * s - (PMX_PI / ((double)h * h)) * sign;
+  }
   dt[tbl_off[t] + d] = d == 0 ? 0.0 : 0.5 * sign / tan(PMX_PI * d / n);
 }
 
-void asm_tables(const int* ns, const int* tbl_off, int ntbl, int max_n, double* R, double* dt,
+void asm_tables(const int* ns, const int* tbl_off, int ntbl, int max_n, double* R, double* dt, int quad,
                 hipStream_t s) {
   if (ntbl <= 0) return;
-  PMX_LAUNCH(k_tables, dim3((max_n + 127) / 128, ntbl), dim3(128), 0, s, ns, tbl_off, R, dt);
+  PMX_LAUNCH(k_tables, dim3((max_n + 127) / 128, ntbl), dim3(128), 0, s, ns, tbl_off, R, dt, quad);
 }
 
 // ---------------------------------------------------------------------------------

@@ -34,6 +34,7 @@
 #include "../../include/pmx.h"
 #include "../../include/pmx_probe.h"
 #include "assemble.h"
+#include "zeta_table.h"
 #include "la.h"
 #include "learn.h"
 #include "plan.h"
@@ -523,6 +524,11 @@ void validate(const pmx_geometry* g, const pmx_options* o) {
       if (o->ir_max_iter < 1 || o->ir_max_iter > 100) fail(PMX_EINVAL, "ir_max_iter must be in [1, 100]");
       if (!(o->ir_tol > 0) || o->ir_tol >= 1) fail(PMX_EINVAL, "ir_tol must be in (0, 1)");
     }
+    if (o->quadrature != 0 && o->quadrature != 1) fail(PMX_EINVAL, "quadrature must be 0 or 1");
+    if (o->quadrature == 1)
+      for (int j = 0; j < g->m; ++j)
+        if (g->node_off[j + 1] - g->node_off[j] < 2 * PMX_ZETA_P + 2)
+          fail(PMX_EINVAL, "the zeta-corrected rule needs at least 2 * 20 + 2 nodes per inclusion");
   }
 }
 
@@ -585,7 +591,7 @@ struct Tables {
   double *R = nullptr, *dt = nullptr;
 };
 
-Tables make_tables(Arena& A, const std::vector<int>& ns_all, hipStream_t s) {
+Tables make_tables(Arena& A, const std::vector<int>& ns_all, int quad, hipStream_t s) {
   Tables T;
   std::vector<int> ns, offs;
   int tot = 0, maxn = 0;
@@ -601,7 +607,7 @@ Tables make_tables(Arena& A, const std::vector<int>& ns_all, hipStream_t s) {
   T.dt = A.alloc<double>(tot);
   int* d_ns = A.upload(ns, s);
   int* d_off = A.upload(offs, s);
-  asm_tables(d_ns, d_off, (int)ns.size(), maxn, T.R, T.dt, s);
+  asm_tables(d_ns, d_off, (int)ns.size(), maxn, T.R, T.dt, quad, s);
   return T;
 }
 
@@ -611,7 +617,7 @@ void assemble_diag(pmx_factor* F, Arena& tmp_, const std::vector<int>& incl, zd*
   Arena& tmp = num_arena(F, tmp_);
   std::vector<int> ns;
   for (int j : incl) ns.push_back((int)(F->node_off[j + 1] - F->node_off[j]));
-  Tables T = make_tables(tmp, ns, s);
+  Tables T = make_tables(tmp, ns, F->opts.quadrature, s);
   int64_t scr = 0;
   int maxn = 0;
   for (int n : ns) {
@@ -3181,12 +3187,17 @@ pmx_status pmx_probe_bessel(const double* z, int64_t n, double* out, void* strea
   });
 }
 
-pmx_status pmx_probe_diag_block(const pmx_geometry* geom, int32_t j, pmx_c64* out, void* stream) {
+pmx_status pmx_probe_diag_block_quad(const pmx_geometry* geom, int32_t j, int32_t quadrature, pmx_c64* out,
+                                     void* stream) {
   return guarded([&] {
-    validate(geom, nullptr);
+    pmx_options o;
+    pmx_options_default(&o);
+    o.quadrature = quadrature;
+    validate(geom, &o);
     if (j < 0 || j >= geom->m || !out) fail(PMX_EINVAL, "bad inclusion index");
     hipStream_t s = (hipStream_t)stream;
     pmx_factor F;
+    F.opts = o;
     upload_geometry(&F, geom, s);
     Arena tmp;
     std::vector<int> incl{j};
@@ -3194,6 +3205,10 @@ pmx_status pmx_probe_diag_block(const pmx_geometry* geom, int32_t j, pmx_c64* ou
     assemble_diag(&F, tmp, incl, (zd*)out, off, s);
     sync_check(s);
   });
+}
+
+pmx_status pmx_probe_diag_block(const pmx_geometry* geom, int32_t j, pmx_c64* out, void* stream) {
+  return pmx_probe_diag_block_quad(geom, j, 0, out, stream);
 }
 
 pmx_status pmx_probe_entries(const pmx_geometry* geom, int32_t nr, const int32_t* rows, const int32_t* rtyp,

@@ -119,7 +119,9 @@ void la_geqrf_r(const QrDescT<R>* d_qr, int batch, int max_m, int max_c, hipStre
 // Runs steps until |R_jj| <= tol |R_11| (phase 1, tol > 0) or until the step count
 // reaches kmin[b] (continuation, tol <= 0; kmin may be NULL).  A zero column stops both.
 // Matrices with max_c >= PMX_CPQR_MULTI_MIN columns use the multi-workgroup variant, which
-// needs d_work (one device int) and synchronises the stream every 16 steps.
+// needs d_work (one device int) and synchronises the stream every 16 steps; a launch table
+// may choose its persistent form instead (the whole loop in one cooperative launch, no
+// host synchronisation).
 #define PMX_CPQR_MULTI_MIN 256
 template <class R>
 void la_cpqr(const CpqrDescT<R>* d_cp, int batch, int max_c, double tol, const int* d_kmin, int init,

@@ -137,6 +137,7 @@ void tune_candidates(int knob, int rb, int64_t d0, int64_t d1, int64_t d2, int* 
     case TK_CPQR:
       out[(*n)++] = 0;
       out[(*n)++] = 1;
+      out[(*n)++] = 2;
       break;
     case TK_GETRS:      // d0: size, d2: right-hand sides
       if (d2 <= PMX_GETRS_SMALL_MAX) out[(*n)++] = 0;

@@ -21,7 +21,7 @@ enum TuneKnob : int {
                     // unrolled columns: 4 256 x 1, 6 512 x 1, 8 1024 x 1 (FP32 only);
                     // 10 tall panels, rows in memory (1024 threads FP32, 512 FP64)
   TK_CPQR = 1,      // column-pivoted QR by columns, batch: 0 one workgroup per matrix,
-                    // 1 multi-workgroup steps
+                    // 1 multi-workgroup steps, 2 the same steps in one cooperative launch
   TK_GETRS = 2,     // level LU solves by size, batch, right-hand sides: 0 one fused kernel per
                     // cell (<= 64 right-hand sides), 1 blocked (row swaps, triangular blocks, MFMA
                     // updates), 2 one fused kernel per cell and 4 right-hand sides with the

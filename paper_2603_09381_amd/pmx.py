@@ -28,7 +28,7 @@ EXPORTS = [
     "pmx_probe_cgemm", "pmx_probe_lu_solve_c32", "pmx_probe_id_c32", "pmx_probe_apply",
     "pmx_mlp_opts_default", "pmx_id_dataset", "pmx_mlp_train", "pmx_mlp_predict", "pmx_probe_mlp",
     "pmx_autotune", "pmx_device_cache", "pmx_far_field_noalloc", "pmx_probe_apply_structure",
-    "pmx_factor_refactor",
+    "pmx_factor_refactor", "pmx_probe_diag_block_quad",
 ]
 
 
@@ -54,7 +54,7 @@ class Options(C.Structure):
                 ("timing", C.c_int32), ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double),
                 ("solve_graph", C.c_int32), ("learned", C.c_int32), ("model_path", C.c_char_p),
                 ("timing_kernels", C.c_uint32), ("reserved0", C.c_int32), ("tune_path", C.c_char_p),
-                ("refactor", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("refactor", C.c_int32), ("quadrature", C.c_int32), ("reserved", C.c_int32 * 2)]
 
 
 class Info(C.Structure):
@@ -75,6 +75,8 @@ class Info(C.Structure):
 class MlpOpts(C.Structure):
     _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("hidden", C.c_int32), ("layers", C.c_int32),
                 ("lr", C.c_float), ("wmse", C.c_float), ("seed", C.c_uint64)]
+
+QUADRATURE = {"kress": 0, "zeta": 1}   # self-block rule of pmx_options.quadrature
 
 KERNEL_NAMES = ["k_ts_leaf", "k_ts_update", "k_getrf_panel", "k_cpqr_update", "k_cpqr", "k_zgemm",
                 "k_trsm_small", "k_entries", "k_diag_pairs/maue", "k_apply_off", "k_getrs_small"]
@@ -124,6 +126,7 @@ def load(path=None):
     lib.pmx_last_error.restype = C.c_char_p
     lib.pmx_probe_bessel.argtypes = [vp, C.c_int64, vp, vp]
     lib.pmx_probe_diag_block.argtypes = [C.POINTER(Geometry), C.c_int32, vp, vp]
+    lib.pmx_probe_diag_block_quad.argtypes = [C.POINTER(Geometry), C.c_int32, C.c_int32, vp, vp]
     ip = C.POINTER(C.c_int32)
     lib.pmx_probe_entries.argtypes = [C.POINTER(Geometry), C.c_int32, ip, ip, C.c_int32, ip, ip, vp, vp]
     lib.pmx_probe_zgemm.argtypes = [C.c_int32] * 6 + [vp, vp, vp, vp]
@@ -201,6 +204,7 @@ def options(w=None, **kw):
         o.proxy_min = w.proxy_min
         o.proxy_rule = 0 if w.proxy_paper_rule else 1
         o.near_rule = w.near_rule
+        o.quadrature = QUADRATURE[getattr(w, "quadrature", "kress")]
     keep = []
     for k, v in kw.items():
         if k in ("model_path", "tune_path") and isinstance(v, str):
@@ -313,12 +317,14 @@ def probe_bessel(z):
 
 
 def probe_diag_block(w, j):
+    """The self block of inclusion j by the workload's quadrature (w.quadrature)."""
     import torch
     load()
     keep = _GeomKeep(w)
     n = int(w.node_off[j + 1] - w.node_off[j])
     out = torch.empty((2 * n, 2 * n), dtype=torch.complex128, device="cuda")
-    _check(_lib.pmx_probe_diag_block(C.byref(keep.g), j, C.c_void_p(out.data_ptr()), _stream()))
+    _check(_lib.pmx_probe_diag_block_quad(C.byref(keep.g), j, QUADRATURE[getattr(w, "quadrature", "kress")],
+                                          C.c_void_p(out.data_ptr()), _stream()))
     return out.cpu().numpy().T.copy()       # column major on the device
 
 

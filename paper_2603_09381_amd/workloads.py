@@ -46,6 +46,7 @@ class Workload:
     near_rule: int = 0           # 0: 4-adjacent + geometric, 1: geometric only
     proxy_paper_rule: bool = True  # radius max(ratio*r_c, 0.9*rho_far)
     shapes: list = field(default_factory=list)  # per inclusion (a, theta, [(m, c_m, phi_m)])
+    quadrature: str = "kress"    # self blocks: "kress" or "zeta" (the 41-point corrected trapezoid)
 
     @property
     def m(self) -> int:

@@ -292,3 +292,52 @@ def test_scattered_uneven_against_dense(pmx):
     print(w.name, "scattered vs dense", err, "levels", fac.info().levels)
     assert err < 5e-9
     assert np.max(np.abs(dense.energy_defect(dense.Geometry(w), x))) < 1e-8
+
+
+# ---------------------------------------------------------------------------------
+# the paper's zeta-corrected self-interaction quadrature (Sec. 2.2), options.quadrature = 1
+
+def _zeta(w):
+    import dataclasses
+    return dataclasses.replace(w, quadrature="zeta")
+
+
+@pytest.mark.parametrize("w", [W.single_disk(n=64), W.star_grid(1, n=128, k_ext=10.0, k_int=15.0),
+                               W.star_grid(1, n=200, k_ext=8.0, k_int=8.0 * np.sqrt(5.0))],
+                         ids=lambda w: w.name)
+def test_diag_block_zeta(pmx, w):
+    w = _zeta(w)
+    got = pmx.probe_diag_block(w, 0)
+    ref = dense.diagonal_block(dense.Geometry(w), 0)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(w.name, "zeta diag block rel err", err)
+    assert err < 1e-12
+
+
+def test_single_disk_zeta_against_mie(pmx):
+    w = _zeta(W.single_disk(n=128, angles=[0.0, 0.7]))
+    fac, x = _solve(pmx, w)
+    assert fac.opts.quadrature == 1
+    g = dense.Geometry(w)
+    q, u = dense.split_density(g, x)
+    th = 2 * np.pi * np.arange(128) / 128
+    for c, a in enumerate(w.angles):
+        qm, um = analytic.mie_boundary(th, w.k_ext, w.k_int[0], 0.4, g.eps_p, g.eps_m[0], angle=a)
+        ref = np.concatenate([qm, um])
+        err = np.linalg.norm(np.concatenate([q[:, c], u[:, c]]) - ref) / np.linalg.norm(ref)
+        assert err < 1e-10, err
+
+
+@pytest.mark.parametrize("g", [2, 4])
+def test_star_grid_zeta_against_dense(pmx, g):
+    w = _zeta(W.sub_grid(W.config2(), g))
+    fac, x = _solve(pmx, w)
+    err = dense.rel_error(x, dense.solve(w))
+    print(w.name, "zeta vs dense", err, "root", fac.info().root_size)
+    assert err < 5e-9
+
+
+def test_zeta_needs_enough_nodes(pmx):
+    w = _zeta(W.single_disk(n=32))
+    with pytest.raises(pmx.PmxError):
+        pmx.Factor(w)

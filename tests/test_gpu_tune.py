@@ -15,7 +15,7 @@ from paper_2603_09381_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-VALID = {"lu_panel": {0, 1, 2, 3, 4, 6, 8, 10}, "cpqr": {0, 1}, "getrs": {0, 1, 2}, "apply_nr": {1, 2, 4, 8},
+VALID = {"lu_panel": {0, 1, 2, 3, 4, 6, 8, 10}, "cpqr": {0, 1, 2}, "getrs": {0, 1, 2}, "apply_nr": {1, 2, 4, 8},
          "apply_wg": {512, 1024, 2048, 4096, 8192}, "ts_leaf": {256, 512, 1024}}
 FORMS = {0: dict(precision=0, id_tol=1e-10), 1: dict(precision=1, id_tol=1e-5, ir_tol=1e-10),
          2: dict(precision=2, id_tol=1e-6, ir_tol=1e-10)}
@@ -85,8 +85,11 @@ def test_autotune_table_and_solve(pmx, tmp_path, form):
     (2, dict(lu=6, cpqr=0, getrs=2)),
     (0, dict(lu=10, cpqr=1, getrs=1)),
     (1, dict(lu=10, cpqr=0, getrs=2)),
+    (0, dict(lu=4, cpqr=2, getrs=1)),
+    (1, dict(lu=8, cpqr=2, getrs=2)),
 ], ids=["plain-global", "plain-wide", "fp32-global", "fp32-wide", "fp64ir-global", "plain-unrolled512",
-        "fp32-unrolled1024", "fp32-unrolled256", "plain-ldssolve", "fp64ir-ldssolve", "plain-tall", "fp32-tall"])
+        "fp32-unrolled1024", "fp32-unrolled256", "plain-ldssolve", "fp64ir-ldssolve", "plain-tall", "fp32-tall",
+        "plain-cpqr-persistent", "fp32-cpqr-persistent"])
 def test_forced_alternatives_match_dense(pmx, tmp_path, form, table):
     w = W.sub_grid(W.config2(), 4)
     path = tmp_path / "forced.txt"

@@ -374,3 +374,110 @@ def test_energy_defect_sees_a_source_inside_a_star():
     # a lossless transmission solution has none (Sec. 2.1 with real k+, k-)
     x = dense.solve(W.star_grid(1, n=128, k_ext=k, k_int=15.0, angles=[0.3]))
     assert np.max(np.abs(dense.energy_defect(g, x))) < 1e-11
+
+
+# ---------------------------------------------------------------------------------
+# zeta-corrected trapezoid rule (the paper's self-interaction quadrature, Sec. 2.2)
+
+@pytest.mark.parametrize("n", [64, 100])
+def test_zeta_rule_on_log_times_trig(n):
+    """int_0^2pi cos(m u) ln|2 sin(u/2)| du = -pi/m and int ln|2 sin(u/2)| du = 0 (closed
+    forms): the 41-point corrected rule reproduces them for resolved m."""
+    h = 2 * np.pi / n
+    u = h * np.arange(n)
+    with np.errstate(divide="ignore"):
+        L = np.log(np.abs(2 * np.sin(u / 2)))
+    L[0] = 0.0
+    for m in range(0, 9):
+        K = np.zeros((n, n))
+        A = np.zeros((n, n))
+        K[0] = np.cos(m * u) * L
+        A[0] = np.cos(m * u)
+        got = layer.zeta_corrected(K, A, np.zeros(n))[0].sum().real
+        exact = 0.0 if m == 0 else -np.pi / m
+        assert abs(got - exact) < 1e-13, (m, got, exact)
+
+
+def test_zeta_rule_order():
+    """The plain punctured trapezoid with only the ln(h/2pi) term is O(h^3); the corrected
+    rule removes that error: on an integrand whose log coefficient has a tenth-order
+    Taylor expansion the two differ by the leading Navot term 2 zeta'(-2) A''(0) h^3 / 2."""
+    import mpmath as mp
+    n = 64
+    h = 2 * np.pi / n
+    u = h * np.arange(n)
+    with np.errstate(divide="ignore"):
+        L = np.log(np.abs(2 * np.sin(u / 2)))
+    L[0] = 0.0
+    A0 = np.cos(u)          # A''(0) = -1
+    K = np.zeros((n, n))
+    A = np.zeros((n, n))
+    K[0] = A0 * L
+    A[0] = A0
+    corrected = layer.zeta_corrected(K, A, np.zeros(n), p=1)[0].sum().real
+    plain = h * (K[0, 1:].sum() + np.log(h / (2 * np.pi)))
+    lead = 2 * float(mp.zeta(-2, derivative=1)) * (-1.0) * h ** 3 / 2
+    assert abs((corrected - plain) - lead) < 1e-3 * abs(lead)
+
+
+@pytest.mark.parametrize("k", [2 * np.pi, 4 * np.pi])
+def test_zeta_circle_eigenvalues(k):
+    """Zeta-corrected S, D, D* and N on a circle against the Graf closed forms, on the
+    modes the 41-point stencil resolves (|l| <= n/8)."""
+    n, R = 128, 0.4
+    w = _circle(n, R)
+    S, D, Ds, N = layer.self_blocks_zeta(w.x, w.y, w.dx, w.dy, w.ddx, w.ddy, k)
+    t = 2 * np.pi * np.arange(n) / n
+    z = k * R
+    for l in range(-n // 8, n // 8 + 1):
+        e = np.exp(1j * l * t)
+        J, H, Jp, Hp = sp.jv(l, z), sp.hankel1(l, z), sp.jvp(l, z), sp.h1vp(l, z)
+        lamS = 1j * np.pi * R / 2 * J * H
+        lamD = 1j * np.pi * k * R / 4 * (Jp * H + J * Hp)
+        lamN = 1j * np.pi * k * k * R / 2 * Jp * Hp
+        for M, lam, tol in ((S, lamS, 1e-13), (D, lamD, 1e-13), (Ds, lamD, 1e-13), (N, lamN, 1e-11)):
+            err = np.max(np.abs(M @ e - lam * e))
+            assert err <= tol * max(1.0, abs(lam)), (l, err, lam)
+
+
+def test_zeta_and_kress_agree_on_a_star():
+    """Two independent quadratures of the same operators on a star (k = 10), applied to a
+    smooth density: their difference is the zeta rule's own error, which must fall fast
+    with n (high order) and be below 1e-11 at n = 256."""
+    diffs = {}
+    for n in (128, 256):
+        w = W.star_grid(1, n=n, k_ext=10.0, k_int=10.0)
+        args = (w.x, w.y, w.dx, w.dy, w.ddx, w.ddy, 10.0)
+        Z = layer.self_blocks_zeta(*args)
+        Kr = layer.self_blocks(*args)
+        t = 2 * np.pi * np.arange(n) / n
+        phi = np.exp(np.cos(t)) * (1 + 0.3j * np.sin(2 * t))
+        diffs[n] = [np.max(np.abs(a @ phi - b @ phi)) / np.max(np.abs(b @ phi)) for a, b in zip(Z, Kr)]
+    assert max(diffs[256]) < 1e-11, diffs
+    assert diffs[256][0] < 1e-3 * diffs[128][0], diffs   # S: convergence order above 10
+
+
+def test_zeta_single_disk_against_mie():
+    """The dense solve with zeta-corrected self blocks on one disk matches the Mie series."""
+    import dataclasses
+    w = dataclasses.replace(W.single_disk(n=128, angles=[0.0, 0.7]), quadrature="zeta")
+    g = dense.Geometry(w)
+    x = dense.solve(w)
+    q, u = dense.split_density(g, x)
+    th = 2 * np.pi * np.arange(128) / 128
+    for c, a in enumerate(w.angles):
+        qm, um = analytic.mie_boundary(th, w.k_ext, w.k_int[0], 0.4, g.eps_p, g.eps_m[0], angle=a)
+        assert np.max(np.abs(u[:, c] - um)) < 1e-10 * np.max(np.abs(um))
+        assert np.max(np.abs(q[:, c] - qm)) < 1e-10 * np.max(np.abs(qm))
+
+
+def test_device_zeta_table_matches_the_oracle_weights():
+    """The library's generated weight table (its own derivation: exact Lagrange derivative
+    weights times zeta') against the oracle's moment-system solution."""
+    import os
+    import re
+    path = os.path.join(os.path.dirname(__file__), "..", "paper_2603_09381_amd", "csrc", "zeta_table.h")
+    vals = [float(v) for v in re.findall(r"^\s+([-0-9.e+]+),", open(path).read(), re.M)]
+    w = layer.zeta_weights()
+    assert len(vals) == len(w)
+    assert np.max(np.abs(np.array(vals) - w)) < 1e-15
