@@ -868,7 +868,7 @@ void id_stage(pmx_factor* F, const LevelData<R>& L, const std::vector<CellPlan>&
     asm_entries(F->geom(), PT.dev, F->ext(), d_em, nb, maxm, maxc, s);
     la_geqrf_r(d_qd, nb, maxm, maxc, s);
     if (learned) la_qr_tail_norms(d_qd, tmp.upload(tails, s), nb, maxc, s);
-    la_cpqr(d_cd, nb, maxc, tol, nullptr, 1, d_work, s);
+    HIPCHK(la_cpqr(d_cd, nb, maxc, tol, nullptr, 1, d_work, s));
     std::vector<int> st;
     download(st, stb, 4 * nid, s);
     // common ranks per pair, continuation
@@ -882,7 +882,7 @@ void id_stage(pmx_factor* F, const LevelData<R>& L, const std::vector<CellPlan>&
         kb[i + ty] = kb[i + 2 + ty] = k;
       }
     int* d_kb = tmp.upload(kb, s);
-    la_cpqr(d_cd, nb, maxc, 0.0, d_kb, 0, d_work, s);
+    HIPCHK(la_cpqr(d_cd, nb, maxc, 0.0, d_kb, 0, d_work, s));
     download(st, stb, 4 * nid, s);
     std::vector<char> ok(sel.size(), 1);
     if (learned) {
@@ -2700,7 +2700,7 @@ void probe_id(int batch, int m, int c, cx<R>* M, double tol, const int* kmin, in
   QrDescT<R>* d_qd = tmp.upload(qd, s);
   CpqrDescT<R>* d_cd = tmp.upload(cd, s);
   la_geqrf_r<R>(d_qd, batch, m, c, s);
-  la_cpqr<R>(d_cd, batch, c, tol, nullptr, 1, d_work, s);
+  HIPCHK(la_cpqr<R>(d_cd, batch, c, tol, nullptr, 1, d_work, s));
   std::vector<int> sth;
   download(sth, st, 4 * batch, s);
   std::vector<int> k(batch);
@@ -2710,7 +2710,7 @@ void probe_id(int batch, int m, int c, cx<R>* M, double tol, const int* kmin, in
     k[b] = std::max(1, std::min(k[b], mb));
   }
   int* d_k = tmp.upload(k, s);
-  la_cpqr<R>(d_cd, batch, c, 0.0, d_k, 0, d_work, s);
+  HIPCHK(la_cpqr<R>(d_cd, batch, c, 0.0, d_k, 0, d_work, s));
   download(sth, st, 4 * batch, s);
   for (int b = 0; b < batch; ++b) k[b] = std::min(k[b], sth[4 * b]);
   HIPCHK(hipMemcpyAsync(d_k, k.data(), batch * sizeof(int), hipMemcpyHostToDevice, s));

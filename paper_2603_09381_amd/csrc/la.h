@@ -121,11 +121,12 @@ void la_geqrf_r(const QrDescT<R>* d_qr, int batch, int max_m, int max_c, hipStre
 // Matrices with max_c >= PMX_CPQR_MULTI_MIN columns use the multi-workgroup variant, which
 // needs d_work (one device int) and synchronises the stream every 16 steps; a launch table
 // may choose its persistent form instead (the whole loop in one cooperative launch, no
-// host synchronisation).
+// host synchronisation).  Returns the first error of its progress polls (hipSuccess when
+// there is none; launch errors stay with the stream as for every launcher).
 #define PMX_CPQR_MULTI_MIN 256
 template <class R>
-void la_cpqr(const CpqrDescT<R>* d_cp, int batch, int max_c, double tol, const int* d_kmin, int init,
-             int* d_work, hipStream_t s);
+hipError_t la_cpqr(const CpqrDescT<R>* d_cp, int batch, int max_c, double tol, const int* d_kmin, int init,
+                   int* d_work, hipStream_t s);
 // T = R11^-1 R12 in place: R11 = b[0:k,0:k] upper, R12 = b[0:k,k:c]; k from d_k.
 template <class R>
 void la_cpqr_tsolve(const CpqrDescT<R>* d_cp, const int* d_k, int batch, int max_k, int max_c, hipStream_t s);

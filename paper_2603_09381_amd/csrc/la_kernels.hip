@@ -180,8 +180,9 @@ __device__ inline int block_argmax(double v, int i, double* redv, int* redi, dou
 // C = alpha op(A) op(B) + beta C on 64 x 64 tiles, four waves of 32 x 32 (2 x 2 blocks of
 // 16 x 16 MFMA).  The k loop moves 16 at a time through LDS; the next slice's global loads
 // are issued into registers before the current slice is multiplied, so they are in flight
-// during the MFMAs.  Complex products as three real ones (Gauss): p1 = sum ar br,
-// p2 = sum ai bi, p3 = sum (ar + ai)(br + bi), C = (p1 - p2) + i (p3 - p1 - p2).
+// during the MFMAs.  In FP64 complex products as three real ones (Gauss): p1 = sum ar br,
+// p2 = sum ai bi, p3 = sum (ar + ai)(br + bi), C = (p1 - p2) + i (p3 - p1 - p2); in FP32
+// as four.
 #define ZG_KS 16
 template <class R, int OPA, int OPB, class F>
 __global__ __launch_bounds__(256, 2) void k_zgemm(F f, cx<R> alpha, cx<R> beta) {
@@ -198,6 +199,10 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(F f, cx<R> alpha, cx<R> beta) 
   __shared__ C Bs[ZG_KS][64 + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  // three real products per complex one in FP64 only: in the FP32 factor the larger
+  // rounding of the Gauss form's imaginary part (p3 - p1 - p2 cancels) weakened the
+  // refinement's contraction enough to cost a whole extra step at 1M unknowns
+  constexpr bool ZG_GAUSS = sizeof(R) == 8;
   V4 p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -271,20 +276,33 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(F f, cx<R> alpha, cx<R> beta) 
         a[t] = As[ks + (lane >> 4)][wm + t * 16 + (lane & 15)];
         b[t] = Bs[ks + (lane >> 4)][wn + t * 16 + (lane & 15)];
       }
-      R as[2], bs[2];
+      if constexpr (ZG_GAUSS) {
+        R as[2], bs[2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        as[t] = a[t].re + a[t].im;
-        bs[t] = b[t].re + b[t].im;
-      }
-#pragma unroll
-      for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-          p1[bi][bj] = mfma16(a[bi].re, b[bj].re, p1[bi][bj]);
-          p2[bi][bj] = mfma16(a[bi].im, b[bj].im, p2[bi][bj]);
-          p3[bi][bj] = mfma16(as[bi], bs[bj], p3[bi][bj]);
+        for (int t = 0; t < 2; ++t) {
+          as[t] = a[t].re + a[t].im;
+          bs[t] = b[t].re + b[t].im;
         }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) {
+            p1[bi][bj] = mfma16(a[bi].re, b[bj].re, p1[bi][bj]);
+            p2[bi][bj] = mfma16(a[bi].im, b[bj].im, p2[bi][bj]);
+            p3[bi][bj] = mfma16(as[bi], bs[bj], p3[bi][bj]);
+          }
+      } else {
+        // real part in p1, imaginary part in p2
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) {
+            p1[bi][bj] = mfma16(a[bi].re, b[bj].re, p1[bi][bj]);
+            p1[bi][bj] = mfma16(-a[bi].im, b[bj].im, p1[bi][bj]);
+            p2[bi][bj] = mfma16(a[bi].re, b[bj].im, p2[bi][bj]);
+            p2[bi][bj] = mfma16(a[bi].im, b[bj].re, p2[bi][bj]);
+          }
+      }
     }
     __syncthreads();
   }
@@ -299,7 +317,7 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(F f, cx<R> alpha, cx<R> beta) 
         const int col = tn + wn + bj * 16 + (lane & 15);
         if (row < g.m && col < g.n) {
           const R x1 = p1[bi][bj][r], x2 = p2[bi][bj][r], x3 = p3[bi][bj][r];
-          C v = zmul(alpha, cmk<R>(x1 - x2, x3 - x1 - x2));
+          C v = zmul(alpha, ZG_GAUSS ? cmk<R>(x1 - x2, x3 - x1 - x2) : cmk<R>(x1, x2));
           auto cp = gC + row + (int64_t)col * g.ldc;
           if (use_beta) v = zfma(beta, *cp, v);
           *cp = v;
@@ -2740,9 +2758,9 @@ __global__ __launch_bounds__(256) void k_cpqr_persist(const CpqrDescT<R>* cps, i
 }
 
 template <class R>
-void la_cpqr(const CpqrDescT<R>* d_cp, int batch, int max_c, double tol, const int* d_kmin, int init, int* d_work,
-             hipStream_t s) {
-  if (batch <= 0 || max_c <= 0) return;
+hipError_t la_cpqr(const CpqrDescT<R>* d_cp, int batch, int max_c, double tol, const int* d_kmin, int init,
+                   int* d_work, hipStream_t s) {
+  if (batch <= 0 || max_c <= 0) return hipSuccess;
   size_t shm = (size_t)max_c * sizeof(cx<R>) + 16;
   if (shm > 64 * 1024) {
     (void)hipFuncSetAttribute((const void*)k_cpqr<R>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -2753,7 +2771,7 @@ void la_cpqr(const CpqrDescT<R>* d_cp, int batch, int max_c, double tol, const i
   if (mode == 0) {
     KScope ks(PK_CPQR, s);
     PMX_LAUNCH(k_cpqr<R>, dim3(batch), dim3(CP_NT), shm, s, d_cp, tol, d_kmin, init);
-    return;
+    return hipSuccess;
   }
   (void)hipMemsetAsync(d_work, 0, sizeof(int), s);
   PMX_LAUNCH(k_cpqr_init<R>, dim3((max_c + 3) / 4, batch), dim3(256), 0, s, d_cp, init);
@@ -2776,7 +2794,7 @@ void la_cpqr(const CpqrDescT<R>* d_cp, int batch, int max_c, double tol, const i
     pmx_count_launch();
     const hipError_t e = hipLaunchCooperativeKernel((const void*)k_cpqr_persist<R>, dim3(grid), dim3(256), args,
                                                     (unsigned)shm, s);
-    if (e == hipSuccess) return;
+    if (e == hipSuccess) return hipSuccess;
     (void)hipGetLastError();   // not launchable as one resident grid: the step-by-step loop below
   }
   for (int it = 0; it <= max_c; ++it) {
@@ -2787,12 +2805,14 @@ void la_cpqr(const CpqrDescT<R>* d_cp, int batch, int max_c, double tol, const i
     }
     if ((it & 15) == 15) {
       int nd = 0;
-      (void)hipMemcpyAsync(&nd, d_work, sizeof(int), hipMemcpyDeviceToHost, s);
+      hipError_t e = hipMemcpyAsync(&nd, d_work, sizeof(int), hipMemcpyDeviceToHost, s);
       pmx_count_sync();
-      (void)hipStreamSynchronize(s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return e;
       if (nd >= batch) break;
     }
   }
+  return hipSuccess;
 }
 
 // T = R11^-1 R12 in place
@@ -2949,7 +2969,7 @@ void la_getrf_work(int n, int real_bytes, double* bytes, double* flops) {
   template void la_getrs_small<R>(const LuDescT<R>*, const MatT<R>*, const MatT<R>*, int, int, int, hipStream_t); \
   template bool la_getrs_lds<R>(const LuDescT<R>*, const MatT<R>*, int, int, int, hipStream_t);                \
   template void la_geqrf_r<R>(const QrDescT<R>*, int, int, int, hipStream_t);                                \
-  template void la_cpqr<R>(const CpqrDescT<R>*, int, int, double, const int*, int, int*, hipStream_t);       \
+  template hipError_t la_cpqr<R>(const CpqrDescT<R>*, int, int, double, const int*, int, int*, hipStream_t);       \
   template void la_cpqr_tsolve<R>(const CpqrDescT<R>*, const int*, int, int, int, hipStream_t);             \
   template void la_qr_tail_norms<R>(const QrDescT<R>*, double* const*, int, int, hipStream_t);              \
   template void la_cpqr_judge<R>(const CpqrDescT<R>*, const int*, double, int*, int, hipStream_t);

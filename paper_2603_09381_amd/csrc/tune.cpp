@@ -296,14 +296,19 @@ std::string time_cpqr(int64_t c, int64_t batch, const int* cand, int nc, double*
   if (!B.err.empty()) return B.err;
   Timer T;
   const TuneForce saved = g_tune_force;
+  hipError_t poll = hipSuccess;   // the first error of the CPQR progress polls
   for (int i = 0; i < nc; ++i) {
     g_tune_force = TuneForce{TK_CPQR, cand[i]};
     // singular values decaying over 12 decades: the threshold rank at 1e-10 is ~5/6 c
     us[i] = T.best_us(
         reps, s, [&] { fill<R>(m, c, c, batch, 0x5eed0002ull, 12.0, 0.0, s); },
-        [&] { la_cpqr<R>(dd, (int)batch, (int)c, 1e-10, nullptr, 1, work, s); });
+        [&] {
+          const hipError_t e = la_cpqr<R>(dd, (int)batch, (int)c, 1e-10, nullptr, 1, work, s);
+          if (poll == hipSuccess) poll = e;
+        });
   }
   g_tune_force = saved;
+  if (poll != hipSuccess) return std::string("a CPQR progress poll failed: ") + hipGetErrorString(poll);
   return hipGetLastError() == hipSuccess ? "" : "a tuning launch failed";
 }
 
