@@ -8,8 +8,10 @@
  * side (-u^I_i; -q^I_i).  Solver: Sec. 3 (proxy method + interpolative decomposition
  * by column-pivoted QR with threshold rank, compressed system of eq. compressed,
  * recovery formula, multi-level recursion), top system by partial-pivoted LU (Sec. 4).
- * Self-interaction quadrature: Kress' logarithmic product rule (the paper uses a
- * zeta-corrected rule instead), hypersingular operator through Maue's identity.
+ * Self-interaction quadrature: Kress' logarithmic product rule or the paper's
+ * zeta-corrected trapezoid rule (options.quadrature), hypersingular operator through
+ * Maue's identity.  Trees: the grid quadtree of Sec. 4 or the k-means clustering with
+ * several inclusions per leaf of Sec. 4.4 (options.tree).
  *
  * Conventions.  Every function returns a pmx_status and never aborts; the text of the
  * last error of the calling thread is returned by pmx_last_error().  Host pointers are
@@ -69,7 +71,9 @@ typedef struct {
   double proxy_ratio;   /* proxy radius >= proxy_ratio * cell radius */
   int32_t proxy_min;    /* minimum number of proxy points (exact number if proxy_rule = 1) */
   int32_t proxy_rule;   /* 0: radius max(ratio r_c, 0.9 rho_far), adaptive count; 1: fixed */
-  int32_t near_rule;    /* 0: edge-adjacent cells + geometric test (Sec. 4); 1: geometric */
+  int32_t near_rule;    /* 0: edge-adjacent cells + geometric test (Sec. 4); 1: geometric
+                           (every cell with a node inside the proxy circle); 2: the
+                           eta-admissibility test below + geometric */
   int32_t precision;    /* 0: FP64 throughout.  1: mixed: the factor (assembly storage,
                            QR, CPQR data, LU, Schur products) in complex FP32 with FP64 column
                            norms and pivot decisions, used as the inner solver of iterative
@@ -101,6 +105,20 @@ typedef struct {
   int32_t quadrature;      /* self blocks: 0 Kress' logarithmic product rule (spectral);
                               1 the zeta-corrected trapezoid rule with 41 local correction
                               points of Sec. 2.2 (needs >= 42 nodes per inclusion) */
+  int32_t tree;            /* 0: quadtree over grid cells (Sec. 4; grid_ij, or the pruned grid
+                              of scattered inclusions), one inclusion per leaf.  1: the
+                              general arrangement of Sec. 4.4: a hierarchical k-means
+                              clustering of the inclusions (node means weighted by node
+                              counts, four clusters per split) with up to leaf_size
+                              inclusions per leaf; grid_ij is ignored; needs near_rule 1 or 2
+                              and learned = 0 */
+  int32_t leaf_size;       /* tree 1: at most this many inclusions per leaf, 1..4; a leaf of
+                              several inclusions is compressed as one cell (its own
+                              inclusions interact through its dense block) */
+  double eta;              /* near_rule 2 (Sec. 4.4): cells s, t of a level are near when
+                              eta |c_s - c_t| < max(2 r_s, 2 r_t) (r: farthest own node from
+                              the cell centre c), then the proxy-circle test of near_rule 1;
+                              eta > 0 */
   int32_t reserved[2];
 } pmx_options;
 
@@ -161,7 +179,8 @@ typedef struct pmx_factor pmx_factor;
 
 /* Fills defaults: id_tol 1e-10, proxy_ratio 1.5, proxy_min 0, proxy_rule 0, near_rule 0,
  * precision 0, timing 0, ir_max_iter 10, ir_tol 1e-10, solve_graph 1, learned 0,
- * model_path NULL, timing_kernels 0, tune_path NULL. */
+ * model_path NULL, timing_kernels 0, tune_path NULL, refactor 0, quadrature 0, tree 0,
+ * leaf_size 4, eta 1. */
 void pmx_options_default(pmx_options* o);
 
 /* Builds the plan and the whole compressed factorisation on `hip_stream`.  Returns when

@@ -100,7 +100,7 @@ pmx_status pmx_probe_mlp(int32_t nin, int32_t nhidden, int32_t nlayer, int32_t n
 pmx_status pmx_probe_apply_structure(const pmx_geometry* geom, const pmx_options* opts, int32_t check,
                                      double* stats);
 
-/* The quadtree plan, host only (no GPU): per level the number of cells; per cell its
+/* The plan's tree (either tree), host only (no GPU): per level the number of cells; per
  * centre, radius, proxy radius, proxy count and near list.  Buffers (host) are filled up
  * to their capacity; *n_levels, *n_cells_total and *n_near_total report the sizes
  * needed.  cell_level [cap_cells], cell_first_incl, cell_center [2 cap], cell_rc,
@@ -110,6 +110,16 @@ pmx_status pmx_plan_query(const pmx_geometry* geom, const pmx_options* opts, int
                           int32_t* n_near_total, int32_t* cell_level, int32_t* cell_first_incl,
                           double* cell_center, double* cell_rc, double* cell_rp, int32_t* cell_p,
                           int32_t* near_off, int32_t* near);
+
+/* The plan's membership, host only (no GPU), cells in the order of pmx_plan_query: per
+ * cell its inclusions (ascending) and its children (indices within the level below).
+ * Buffers (host) are filled up to their capacity; *n_cells_total, *n_incl_total and
+ * *n_child_total report the sizes needed.  incl_off [cap_cells + 1], incl [cap_incl],
+ * child_off [cap_cells + 1], child [cap_child]. */
+pmx_status pmx_plan_members(const pmx_geometry* geom, const pmx_options* opts, int32_t cap_cells,
+                            int32_t cap_incl, int32_t cap_child, int32_t* n_cells_total,
+                            int32_t* n_incl_total, int32_t* n_child_total, int32_t* incl_off,
+                            int32_t* incl, int32_t* child_off, int32_t* child);
 
 #ifdef __cplusplus
 }

@@ -32,6 +32,21 @@ Readings where the paper is silent (listed in the design notes):
     (the Omit property, Sec. 2.1);
   * number of proxy points P = max(P_min, 2 ceil(k+ R_p) + 2 ceil(ln tol / ln(r_c/rho_far)) + 16),
     or a fixed P when the workload fixes it; no proxy when no cell is far.
+
+General arrangements (Sec. 4.4, Discussions): cells from a k-means clustering, near pairs
+by eta-admissibility, several inclusions per leaf.  Readings (``kmeans_plan``):
+  * the clustered points are the inclusions, each at the mean of its nodes with its node
+    count as weight (k-means of the integration points with no inclusion split); four
+    clusters per split, depth by depth, while some cell of the depth holds more than
+    leaf_size inclusions (cells within the limit continue as single children);
+  * seeds: the member farthest from the weighted mean, then repeatedly the member
+    farthest from all seeds so far; Lloyd steps (nearest seed, then weighted means) until
+    no member changes cluster, at most 100;
+  * near when eta times the distance of the centres is below the larger of the two
+    diameters 2 r_c, then the same proxy-circle closure as above;
+  * with leaf_size > 1 the inclusions form level 0 and the leaves level 1; level 0 is not
+    compressed (the leaves' blocks hold their inclusions' self blocks and the exterior
+    blocks between them) and has no near lists.
 """
 from __future__ import annotations
 
@@ -92,9 +107,127 @@ def grid_assignment(centers):
     return out
 
 
+def node_means(w):
+    """Per inclusion: the mean of its nodes (plain left-to-right sums) and its node count."""
+    px, py, wt = [], [], []
+    for j in range(w.m):
+        a, b = int(w.node_off[j]), int(w.node_off[j + 1])
+        sx = sy = 0.0
+        for i in range(a, b):
+            sx += float(w.x[i])
+            sy += float(w.y[i])
+        n = float(b - a)
+        px.append(sx / n)
+        py.append(sy / n)
+        wt.append(n)
+    return px, py, wt
+
+
+def kmeans_split(S, px, py, wt):
+    """Weighted k-means of the inclusions S into at most four clusters (readings in the
+    module header): clusters in seed order, members in the order of S, empty ones dropped."""
+    n = len(S)
+    k = min(4, n)
+    sx = sy = sw = 0.0
+    for j in S:
+        sx += wt[j] * px[j]
+        sy += wt[j] * py[j]
+        sw += wt[j]
+    mx, my = sx / sw, sy / sw
+    best, bd = 0, -1.0
+    for i, j in enumerate(S):
+        dx, dy = px[j] - mx, py[j] - my
+        d = dx * dx + dy * dy
+        if d > bd:
+            best, bd = i, d
+    cx, cy = [px[S[best]]], [py[S[best]]]
+    dmin = [math.inf] * n
+    while len(cx) < k:
+        best, bd = -1, 0.0
+        for i, j in enumerate(S):
+            dx, dy = px[j] - cx[-1], py[j] - cy[-1]
+            dmin[i] = min(dmin[i], dx * dx + dy * dy)
+            if dmin[i] > bd:
+                best, bd = i, dmin[i]
+        if best < 0:
+            break
+        cx.append(px[S[best]])
+        cy.append(py[S[best]])
+    kk = len(cx)
+    a = [-1] * n
+    for _ in range(100):
+        moved = False
+        for i, j in enumerate(S):
+            b, bd = 0, math.inf
+            for c in range(kk):
+                dx, dy = px[j] - cx[c], py[j] - cy[c]
+                d = dx * dx + dy * dy
+                if d < bd:
+                    b, bd = c, d
+            if b != a[i]:
+                a[i] = b
+                moved = True
+        if not moved:
+            break
+        for c in range(kk):
+            sx = sy = sw = 0.0
+            for i, j in enumerate(S):
+                if a[i] == c:
+                    sx += wt[j] * px[j]
+                    sy += wt[j] * py[j]
+                    sw += wt[j]
+            if sw > 0:
+                cx[c], cy[c] = sx / sw, sy / sw
+    out = [[j for i, j in enumerate(S) if a[i] == c] for c in range(kk)]
+    return [q for q in out if q]
+
+
+def kmeans_plan(w):
+    """Tree of Sec. 4.4's general arrangements (readings in the module header)."""
+    g = dense.Geometry(w)
+    L = int(w.leaf_size)
+    if not 1 <= L <= 4:
+        raise ValueError("leaf_size must be in 1..4")
+    px, py, wt = node_means(w)
+    depth, parent = [[list(range(w.m))]], [[-1]]
+    while any(len(c) > L for c in depth[-1]):
+        nxt, par = [], []
+        for t, c in enumerate(depth[-1]):
+            parts = kmeans_split(c, px, py, wt) if len(c) > L else [c]
+            if len(c) > L and len(parts) < 2:
+                raise ValueError("inclusions whose node means coincide")
+            for q in parts:
+                nxt.append(q)
+                par.append(t)
+        depth.append(nxt)
+        parent.append(par)
+    D = len(depth) - 1
+    passthrough = L > 1
+    l0, first = [], []
+    for c in depth[D]:
+        first.append(len(l0))
+        l0.extend(Cell(0, (0, 0), [j]) for j in c)
+    first.append(len(l0))
+    levels = [l0]
+    for d in range(D if passthrough else D - 1, -1, -1):
+        cells = [Cell(len(levels), (0, 0), sorted(c)) for c in depth[d]]
+        if d == D:
+            for t, cell in enumerate(cells):
+                cell.children = list(range(first[t], first[t + 1]))
+        else:
+            for q, p in enumerate(parent[d + 1]):
+                cells[p].children.append(q)
+        levels.append(cells)
+    for lev, cells in enumerate(levels):
+        _near_and_proxy(w, g, cells, lists=not (lev == 0 and passthrough))
+    return levels
+
+
 def plan(w):
     """Tree, near lists and proxy circles for every level (grid workloads; scattered ones
-    through grid_assignment)."""
+    through grid_assignment; the k-means tree when the workload asks for it)."""
+    if getattr(w, "tree", "quad") == "kmeans":
+        return kmeans_plan(w)
     g = dense.Geometry(w)
     gi = np.asarray(w.grid_index) if w.grid_index is not None else grid_assignment(w.centers)
     levels = []
@@ -134,7 +267,7 @@ def _cell_nodes(g, cell):
     return g.x[idx], g.y[idx]
 
 
-def _near_and_proxy(w, g, cells):
+def _near_and_proxy(w, g, cells, lists=True):
     pts = [_cell_nodes(g, c) for c in cells]
     for c in cells:
         sx = sy = 0.0
@@ -145,7 +278,7 @@ def _near_and_proxy(w, g, cells):
     for t, c in enumerate(cells):
         px, py = pts[t]
         c.rc = float(np.max(np.hypot(px - c.center[0], py - c.center[1])))
-    if len(cells) == 1:
+    if len(cells) == 1 or not lists:
         return
     for t, c in enumerate(cells):
         dmin = np.array([np.min(np.hypot(pts[s][0] - c.center[0], pts[s][1] - c.center[1]))
@@ -154,6 +287,11 @@ def _near_and_proxy(w, g, cells):
         if w.near_rule == 0:
             for s, o in enumerate(cells):
                 if s != t and abs(o.coord[0] - c.coord[0]) + abs(o.coord[1] - c.coord[1]) == 1:
+                    near.add(s)
+        if w.near_rule == 2:   # eta-admissibility (Sec. 4.4): diameters 2 r_c
+            for s, o in enumerate(cells):
+                ex, ey = o.center[0] - c.center[0], o.center[1] - c.center[1]
+                if s != t and w.eta * math.sqrt(ex * ex + ey * ey) < 2.0 * max(c.rc, o.rc):
                     near.add(s)
         while True:
             far = [s for s in range(len(cells)) if s != t and s not in near]
@@ -257,6 +395,9 @@ class FastSolver:
         self.w = w
         self.g = dense.Geometry(w)
         self.tol = w.id_tol if tol is None else tol
+        if getattr(w, "tree", "quad") == "kmeans" and int(w.leaf_size) > 1:
+            raise NotImplementedError("the oracle's step-level solver takes one inclusion per leaf; "
+                                      "leaves of several inclusions are checked against the dense solve")
         self.levels = plan(w)
         self.data = []          # per level: list of dicts per cell
         self._factor()

@@ -433,6 +433,7 @@ struct pmx_factor {
   int* owner = nullptr;
   int64_t* d_node_off = nullptr;
   pmx_options opts;
+  int lev0 = 0;   // plan level of the first compressed cells (1: leaves of several inclusions)
   std::vector<std::vector<CellPlan>> plan;
   Tier<double> t64;   // precision 0
   Tier<float> t32;    // precision 1
@@ -525,6 +526,14 @@ void validate(const pmx_geometry* g, const pmx_options* o) {
       if (!(o->ir_tol > 0) || o->ir_tol >= 1) fail(PMX_EINVAL, "ir_tol must be in (0, 1)");
     }
     if (o->quadrature != 0 && o->quadrature != 1) fail(PMX_EINVAL, "quadrature must be 0 or 1");
+    if (o->near_rule < 0 || o->near_rule > 2) fail(PMX_EINVAL, "near_rule must be 0, 1 or 2");
+    if (o->near_rule == 2 && !(o->eta > 0 && std::isfinite(o->eta))) fail(PMX_EINVAL, "eta must be positive");
+    if (o->tree != 0 && o->tree != 1) fail(PMX_EINVAL, "tree must be 0 or 1");
+    if (o->tree == 1) {
+      if (o->leaf_size < 1 || o->leaf_size > 4) fail(PMX_EINVAL, "leaf_size must be in 1..4");
+      if (o->near_rule == 0) fail(PMX_EINVAL, "the k-means tree needs near_rule 1 or 2 (no grid adjacency)");
+      if (o->learned) fail(PMX_EINVAL, "learned proposals need the grid quadtree (tree 0)");
+    }
     if (o->quadrature == 1)
       for (int j = 0; j < g->m; ++j)
         if (g->node_off[j + 1] - g->node_off[j] < 2 * PMX_ZETA_P + 2)
@@ -540,6 +549,9 @@ PlanOptions plan_options(const pmx_geometry* g, const pmx_options& o) {
   p.proxy_rule = o.proxy_rule;
   p.id_tol = o.id_tol;
   p.k_ext = g->k_ext;
+  p.tree = o.tree;
+  p.leaf_size = o.leaf_size;
+  p.eta = o.eta;
   return p;
 }
 
@@ -1221,6 +1233,7 @@ void merge_level(pmx_factor* F, const LevelData<R>& C, const std::vector<CellPla
   int64_t td = 0;
   P.max_s = 0;
   for (int p = 0; p < np; ++p) {
+    if (cells[p].children.size() > 4) fail(PMX_EGEOM, "a tree cell with more than four children");
     P.offS[p] = (int64_t)P.rows.size();
     for (int ty = 0; ty < 2; ++ty)
       for (int sl = 0; sl < (int)cells[p].children.size(); ++sl) {
@@ -1277,8 +1290,9 @@ void merge_level(pmx_factor* F, const LevelData<R>& C, const std::vector<CellPla
   num_step(F, s, [=](hipStream_t st) { asm_parent(g, e, d_pd, np, ms, st); });
 }
 
-// Leaf level: one inclusion per cell, active rows and columns all its nodes (value /
-// q first, then derivative / u); returns the size of the self blocks.
+// Inclusion level (level 0 of the plan): one inclusion per cell, active rows and columns
+// all its nodes (value / q first, then derivative / u); returns the size of the self
+// blocks.
 template <class R>
 int64_t leaf_level(pmx_factor* F, LevelData<R>& L0, std::vector<int>& incl) {
   const std::vector<CellPlan>& leaves = F->plan[0];
@@ -1382,13 +1396,20 @@ void factor_all(pmx_factor* F, hipStream_t s) {
   Tier<R>& T = tier<R>(F);
   const double t0 = now_ms();
   const auto& plan = F->plan;
-  // leaf level
+  const size_t lev0 = (size_t)F->lev0;
+  // inclusion level (the leaf level unless leaves hold several inclusions)
   LevelData<R> L0;
   std::vector<int> incl;
   const int64_t td = leaf_level(F, L0, incl);
-  L0.D = F->arena.alloc<cx<R>>(td);
-  L0.ipiv = F->arena.alloc<int>(L0.tot_s);
-  L0.perm = F->arena.alloc<int>(L0.tot_s);
+  // self blocks that only enter the leaves' blocks need not outlive the merge
+  Arena pass(&F->pool);
+  if (lev0) {
+    L0.D = num_arena(F, pass).alloc<cx<R>>(td);
+  } else {
+    L0.D = F->arena.alloc<cx<R>>(td);
+    L0.ipiv = F->arena.alloc<int>(L0.tot_s);
+    L0.perm = F->arena.alloc<int>(L0.tot_s);
+  }
   {
     Arena tmp(&F->pool);
     if (F->opts.precision == 0) {
@@ -1417,8 +1438,28 @@ void factor_all(pmx_factor* F, hipStream_t s) {
   }
   F->info.t_phase_ms[0] += now_ms() - t0;
   LevelData<R> cur = std::move(L0);
-  for (size_t lv = 0; lv < plan.size(); ++lv) {
-    if (lv > 0) {
+  if (lev0) {
+    // leaves of several inclusions (Sec. 4.4): the inclusions enter whole, every node a
+    // skeleton node and the self block itself the block to merge, so that a leaf's block
+    // holds its self blocks and the exterior-kernel blocks between its inclusions
+    const double tm = now_ms();
+    cur.k0 = cur.s0;
+    cur.k1 = cur.s1;
+    cur.offK.assign(cur.offS.begin(), cur.offS.end() - 1);
+    cur.rskel = cur.rows;
+    cur.cskel = cur.cols;
+    cur.At = cur.D;
+    cur.offA = cur.offD;
+    cur.tot_k = cur.tot_s;
+    Arena tmp(&F->pool);
+    LevelData<R> nxt;
+    merge_level(F, cur, plan[lev0], nxt, tmp, s);
+    HIPCHK(hipGetLastError());
+    cur = std::move(nxt);
+    F->info.t_phase_ms[2] += now_ms() - tm;
+  }
+  for (size_t lv = lev0; lv < plan.size(); ++lv) {
+    if (lv > lev0) {
       const double tm = now_ms();
       Arena tmp(&F->pool);
       LevelData<R> nxt;
@@ -1458,13 +1499,13 @@ void factor_all(pmx_factor* F, hipStream_t s) {
     }
     const double tc = now_ms();
     LearnedPlan lp;
-    const bool learned = (lv == 0 && !F->leaf_pred.empty());
+    const bool learned = (lv == lev0 && !F->leaf_pred.empty());
     if (learned) {
       const double tq = now_ms();
       lp = learned_plan(F, cur.s0);
       F->info.t_phase_ms[8] += now_ms() - tq;
     }
-    compress_level(F, cur, plan[lv], learned ? &lp : nullptr, lv == 0, s);
+    compress_level(F, cur, plan[lv], learned ? &lp : nullptr, lv == lev0, s);
     F->info.t_phase_ms[1] += now_ms() - tc;
     T.lev.push_back(std::move(cur));
     cur = LevelData<R>();
@@ -1595,7 +1636,7 @@ void build_program(pmx_factor* F, int nrhs, hipStream_t s) {
     S.tot_k = L.tot_k;
     // parent right-hand sides
     const bool top = (l + 1 == nl);
-    const std::vector<CellPlan>& pc = F->plan[l + 1];
+    const std::vector<CellPlan>& pc = F->plan[l + 1 + F->lev0];
     cx<R>* dst = top ? P.Froot : P.lv[l + 1].F;
     std::vector<RowSrc> prs;
     std::vector<GatherDescT<R>> pgd;
@@ -1721,44 +1762,76 @@ void launch_program(pmx_factor* F, hipStream_t s) {
   }
 }
 
-// Row maps between the leaf cell vectors (per cell [2 n x nrhs], cells in leaf order) and
-// the density layout [nrhs][2 N] (per inclusion [q; u]).
+// Row maps between three layouts of a block of nrhs vectors:
+//  * leaf: the vectors of the first compressed level (the top system when there is none),
+//    per cell its active rows in order, column major with leading dimension = rows;
+//  * density: [nrhs][2 N], per inclusion [q; u] (value rows, then derivative rows);
+//  * inclusion: per level-0 cell of the plan in plan order, [q; u] with leading dimension
+//    2 n (what the plane-wave kernel writes).  With one inclusion per leaf it is the leaf
+//    layout; with leaves of several inclusions the leaf rows of an inclusion are not
+//    contiguous and the plane waves reach the leaves through the density layout.
 struct LeafMap {
   int n2 = 0, max_cell = 0, ncell = 0;
   std::vector<int64_t> leaf_off;    // per cell: first leaf entry / nrhs
   std::vector<int> cell_rows;
-  RowSrc *d_to_dens = nullptr, *d_to_leaf = nullptr;
+  bool same = true;                 // inclusion layout == leaf layout
+  RowSrc *d_to_dens = nullptr, *d_to_leaf = nullptr, *d_incl_to_dens = nullptr;
 };
 
-void build_leaf_map(pmx_factor* F, int nrhs, LeafMap& M, Arena& A, hipStream_t s) {
-  const std::vector<CellPlan>& leaves = F->plan[0];
+// rows, cols: the active codes of the leaf cells (node codes only), offsets offS [ncell + 1]
+void build_leaf_map(pmx_factor* F, int nrhs, const std::vector<int>& rows, const std::vector<int>& cols,
+                    const std::vector<int64_t>& offS, int ncell, LeafMap& M, Arena& A, hipStream_t s) {
+  const std::vector<int64_t>& no = F->node_off;
   M.n2 = 2 * F->n_nodes;
-  M.ncell = (int)leaves.size();
-  std::vector<RowSrc> to_dens(M.n2, RowSrc{0, 0}), to_leaf(M.n2, RowSrc{0, 0});
-  M.leaf_off.assign(M.ncell, 0);
-  M.cell_rows.assign(M.ncell, 0);
+  M.ncell = ncell;
+  std::vector<RowSrc> to_dens(M.n2, RowSrc{0, 0}), to_leaf(M.n2, RowSrc{0, 0}), incl_to_dens(M.n2, RowSrc{0, 0});
+  M.leaf_off.assign(ncell, 0);
+  M.cell_rows.assign(ncell, 0);
   M.max_cell = 0;
-  int64_t off = 0;
-  for (int t = 0; t < M.ncell; ++t) {
-    int j = leaves[t].incl[0];
-    int n = (int)(F->node_off[j + 1] - F->node_off[j]);
-    for (int r = 0; r < 2 * n; ++r) {
-      to_dens[2 * F->node_off[j] + r] = RowSrc{off * nrhs + r, 2 * n};
-      to_leaf[off + r] = RowSrc{2 * F->node_off[j] + r, M.n2};
+  // density index of a node code (2 node + type)
+  auto dens = [&](int code) {
+    const int64_t node = code >> 1;
+    const int ty = code & 1;
+    const int j = (int)(std::upper_bound(no.begin(), no.end(), node) - no.begin()) - 1;
+    return 2 * no[j] + ty * (no[j + 1] - no[j]) + (node - no[j]);
+  };
+  for (int t = 0; t < ncell; ++t) {
+    const int64_t off = offS[t];
+    const int sz = (int)(offS[t + 1] - off);
+    for (int r = 0; r < sz; ++r) {
+      if (rows[off + r] < 0 || cols[off + r] < 0) fail(PMX_EINVAL, "a leaf row that is not a boundary node");
+      to_leaf[off + r] = RowSrc{dens(rows[off + r]), M.n2};
+      to_dens[dens(cols[off + r])] = RowSrc{off * nrhs + r, sz};
     }
     M.leaf_off[t] = off;
-    M.cell_rows[t] = 2 * n;
-    M.max_cell = std::max(M.max_cell, 2 * n);
-    off += 2 * n;
+    M.cell_rows[t] = sz;
+    M.max_cell = std::max(M.max_cell, sz);
   }
+  int64_t o = 0;
+  for (const CellPlan& c : F->plan[0]) {
+    const int j = c.incl[0];
+    const int n2j = (int)(2 * (no[j + 1] - no[j]));
+    for (int r = 0; r < n2j; ++r) incl_to_dens[2 * no[j] + r] = RowSrc{o * nrhs + r, n2j};
+    o += n2j;
+  }
+  M.same = true;
+  for (int64_t i = 0; i < M.n2 && M.same; ++i)
+    M.same = incl_to_dens[i].off == to_dens[i].off && incl_to_dens[i].ld == to_dens[i].ld;
   M.d_to_dens = A.upload(to_dens, s);
   M.d_to_leaf = A.upload(to_leaf, s);
+  M.d_incl_to_dens = M.same ? M.d_to_dens : A.upload(incl_to_dens, s);
 }
 
 // descriptors: leaf vectors -> one density-layout buffer, and back per cell
 template <class RD>
 GatherDescT<RD>* gather_to_dens(const LeafMap& M, cx<RD>* dens, int nrhs, Arena& A, hipStream_t s) {
   std::vector<GatherDescT<RD>> gd{GatherDescT<RD>{M.d_to_dens, M.n2, nrhs, dens, M.n2}};
+  return A.upload(gd, s);
+}
+
+template <class RD>
+GatherDescT<RD>* gather_incl_to_dens(const LeafMap& M, cx<RD>* dens, int nrhs, Arena& A, hipStream_t s) {
+  std::vector<GatherDescT<RD>> gd{GatherDescT<RD>{M.d_incl_to_dens, M.n2, nrhs, dens, M.n2}};
   return A.upload(gd, s);
 }
 
@@ -2343,7 +2416,8 @@ struct SolveState {
   zd *f = nullptr, *r = nullptr, *leaf64 = nullptr;
   GatherDescT<double>* d_fin_to_leaf = nullptr;    // precision 0: fin -> leaf vectors
   GatherDescT<double>* d_leaf_to_x = nullptr;      // leaf (FP64) -> xout
-  GatherDescT<double>* d_leaf64_to_f = nullptr;    // refinement: plane-wave leaf -> f
+  GatherDescT<double>* d_leaf64_to_f = nullptr;    // plane waves (inclusion layout) -> f, or -> fin
+                                                   // when the leaf layout differs
   void* d_r_to_leaf = nullptr;                     // refinement: r -> leaf vectors (factor type)
   void* d_leafr_to_x = nullptr;                    // refinement: leaf (factor type) += -> xout
   DenseApply apply;
@@ -2417,7 +2491,15 @@ void ensure_state(pmx_factor* F, int nrhs) {
   build_program<R>(F, nrhs, s);
   const double tl = now_ms();
   F->info.t_phase_ms[9] += tl - tp;
-  build_leaf_map(F, nrhs, S.map, A, s);
+  {
+    const Tier<R>& T = tier<R>(F);
+    if (T.lev.empty()) {
+      const std::vector<int64_t> offS{0, (int64_t)T.root_rows.size()};
+      build_leaf_map(F, nrhs, T.root_rows, T.root_cols, offS, 1, S.map, A, s);
+    } else {
+      build_leaf_map(F, nrhs, T.lev[0].rows, T.lev[0].cols, T.lev[0].offS, T.lev[0].ncell, S.map, A, s);
+    }
+  }
   F->info.t_phase_ms[10] += now_ms() - tl;
   const std::vector<CellPlan>& leaves = F->plan[0];
   const int nc = (int)leaves.size();
@@ -2445,11 +2527,15 @@ void ensure_state(pmx_factor* F, int nrhs) {
   if (F->opts.precision == 0) {
     S.d_fin_to_leaf = gather_to_leaf(S.map, (zd*)leaf, nrhs, A, s);
     S.d_leaf_to_x = gather_to_dens(S.map, S.xout, nrhs, A, s);
+    if (!S.map.same) {   // plane waves: inclusion layout -> fin -> leaf vectors
+      S.leaf64 = A.alloc<zd>(total);
+      S.d_leaf64_to_f = gather_incl_to_dens(S.map, S.fin, nrhs, A, s);
+    }
   } else {
     S.f = A.alloc<zd>(total);
     S.r = A.alloc<zd>(total);
     S.leaf64 = A.alloc<zd>(total);
-    S.d_leaf64_to_f = gather_to_dens(S.map, S.f, nrhs, A, s);
+    S.d_leaf64_to_f = gather_incl_to_dens(S.map, S.f, nrhs, A, s);
     S.d_r_to_leaf = gather_to_leaf(S.map, leaf, nrhs, A, s);
     S.d_leaf_to_x = gather_to_dens(S.map, S.xout, nrhs, A, s);
     const double ta = now_ms();
@@ -2493,8 +2579,15 @@ void solve_fp64(pmx_factor* F, int nrhs, const double* angles, const zd* rhs) {
   const LeafMap& M = S.map;
   if (angles) {
     upload_angles(F, angles);
+    const int ninc = (int)F->plan[0].size();
     run_seq(F, S.g_plane, PK_SOLVE_MASK, [&] {
-      asm_incident(F->geom(), F->ext(), S.d_node0, S.d_nn, S.d_off, M.ncell, S.maxn, S.d_angles, nrhs, leaf, gs);
+      if (M.same) {
+        asm_incident(F->geom(), F->ext(), S.d_node0, S.d_nn, S.d_off, ninc, S.maxn, S.d_angles, nrhs, leaf, gs);
+      } else {
+        asm_incident(F->geom(), F->ext(), S.d_node0, S.d_nn, S.d_off, ninc, S.maxn, S.d_angles, nrhs, S.leaf64, gs);
+        asm_gather(S.leaf64, S.d_leaf64_to_f, 1, M.n2, nrhs, gs, 0);
+        asm_gather(S.fin, S.d_fin_to_leaf, M.ncell, M.max_cell, nrhs, gs, 0);
+      }
       launch_program<double>(F, gs);
       asm_gather(leaf, S.d_leaf_to_x, 1, M.n2, nrhs, gs, 0);
     });
@@ -2521,7 +2614,8 @@ void solve_refined(pmx_factor* F, int nrhs, const double* angles, const zd* rhs)
   const int64_t total = S.apply.total;
   if (angles) {
     upload_angles(F, angles);
-    asm_incident(F->geom(), F->ext(), S.d_node0, S.d_nn, S.d_off, M.ncell, S.maxn, S.d_angles, nrhs, S.leaf64, gs);
+    asm_incident(F->geom(), F->ext(), S.d_node0, S.d_nn, S.d_off, (int)F->plan[0].size(), S.maxn, S.d_angles,
+                 nrhs, S.leaf64, gs);
     asm_gather(S.leaf64, S.d_leaf64_to_f, 1, M.n2, nrhs, gs, 0);
   } else {
     HIPCHK(hipMemcpyAsync(S.f, rhs, total * sizeof(zd), hipMemcpyDeviceToDevice, gs));
@@ -2868,6 +2962,9 @@ void pmx_options_default(pmx_options* o) {
   o->solve_graph = 1;
   o->learned = 0;
   o->model_path = nullptr;
+  o->tree = 0;
+  o->leaf_size = 4;
+  o->eta = 1.0;
 }
 
 pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, void* hip_stream,
@@ -2883,6 +2980,7 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
     std::unique_ptr<pmx_factor> F(new pmx_factor());
     std::memset(&F->info, 0, sizeof(F->info));
     F->opts = o;
+    F->lev0 = plan_pass_through(plan_options(geom, o)) ? 1 : 0;
     if (o.refactor && o.learned) fail(PMX_EINVAL, "refactor = 1 needs learned = 0");
     F->num.on = o.refactor != 0;
     const int64_t launches0 = g_launches, syncs0 = g_syncs;
@@ -3321,6 +3419,7 @@ pmx_status pmx_id_dataset(const pmx_geometry* geom, const pmx_options* opts, con
     validate(geom, &o);
     if (!path) fail(PMX_EINVAL, "path is NULL");
     hipStream_t s = (hipStream_t)stream;
+    if (plan_pass_through(plan_options(geom, o))) fail(PMX_EINVAL, "leaf IDs need one inclusion per leaf");
     pmx_factor F;
     F.opts = o;
     make_plan(geom, o, F.plan);
@@ -3398,6 +3497,7 @@ pmx_status pmx_mlp_predict(const char* model_path, const pmx_geometry* geom, con
     if (opts) o = *opts;
     validate(geom, &o);
     if (!out) fail(PMX_EINVAL, "out is NULL");
+    if (plan_pass_through(plan_options(geom, o))) fail(PMX_EINVAL, "leaf predictions need one inclusion per leaf");
     pmx_factor F;
     F.opts = o;
     make_plan(geom, o, F.plan);
@@ -3580,6 +3680,44 @@ pmx_status pmx_plan_query(const pmx_geometry* geom, const pmx_options* opts, int
     *n_levels = (int)levels.size();
     *n_cells_total = tc;
     *n_near_total = tn;
+  });
+}
+
+pmx_status pmx_plan_members(const pmx_geometry* geom, const pmx_options* opts, int32_t cap_cells, int32_t cap_incl,
+                            int32_t cap_child, int32_t* n_cells_total, int32_t* n_incl_total, int32_t* n_child_total,
+                            int32_t* incl_off, int32_t* incl, int32_t* child_off, int32_t* child) {
+  return guarded([&] {
+    pmx_options o;
+    pmx_options_default(&o);
+    if (opts) o = *opts;
+    validate(geom, &o);
+    if (!n_cells_total || !n_incl_total || !n_child_total) fail(PMX_EINVAL, "NULL size outputs");
+    std::vector<std::vector<CellPlan>> levels;
+    make_plan(geom, o, levels);
+    int tc = 0, ti = 0, tk = 0;
+    for (auto& L : levels)
+      for (auto& c : L) {
+        if (tc < cap_cells) {
+          if (incl_off) incl_off[tc] = ti;
+          if (child_off) child_off[tc] = tk;
+        }
+        for (int v : c.incl) {
+          if (incl && ti < cap_incl) incl[ti] = v;
+          ++ti;
+        }
+        for (int v : c.children) {
+          if (child && tk < cap_child) child[tk] = v;
+          ++tk;
+        }
+        ++tc;
+      }
+    if (tc <= cap_cells) {
+      if (incl_off) incl_off[tc] = ti;
+      if (child_off) child_off[tc] = tk;
+    }
+    *n_cells_total = tc;
+    *n_incl_total = ti;
+    *n_child_total = tk;
   });
 }
 

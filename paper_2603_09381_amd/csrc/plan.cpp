@@ -11,6 +11,17 @@
 //  * P = max(P_min, 2 ceil(k+ R_p) + 2 ceil(ln tol / ln(r_c / rho_far)) + 16), or a
 //    fixed P and radius ratio r_c when the caller fixes them;
 //  * no proxy circle when every other cell of the level is near.
+// Sec. 4.4 (Discussions) names the extension to arbitrary arrangements: cells from a
+// k-means clustering, near pairs by an eta-admissibility test on the distance of the cell
+// centres against the cell diameters, several scatterers per leaf.  Readings used here:
+//  * the clustered points are the inclusions, each at the mean of its nodes and weighted
+//    by its node count (k-means on the integration points with no inclusion split), four
+//    clusters per split, top down until every cell holds at most leaf_size inclusions;
+//  * seeds: the member farthest from the weighted mean, then each time the member
+//    farthest from the seeds so far; Lloyd iterations (nearest centre, weighted mean)
+//    until no member moves, at most 100;
+//  * a cell's diameter is 2 r_c; near when eta |c_s - c_t| < max(2 r_c,s, 2 r_c,t), then
+//    the same proxy-circle closure as above.
 #include "plan.h"
 
 #include <algorithm>
@@ -80,7 +91,7 @@ void near_cells(const PlanOptions& o, const int64_t* node_off, const double* x, 
                 std::vector<CellPlan>& cells, int t0, int t1);
 
 void near_and_proxy(const PlanOptions& o, const double* centers, const int64_t* node_off, const double* x,
-                    const double* y, std::vector<CellPlan>& cells) {
+                    const double* y, std::vector<CellPlan>& cells, bool lists = true) {
   const int nc = (int)cells.size();
   for (int t = 0; t < nc; ++t) {
     CellPlan& c = cells[t];
@@ -95,7 +106,7 @@ void near_and_proxy(const PlanOptions& o, const double* centers, const int64_t* 
     node_range(c.incl, node_off, x, y, c.cx, c.cy, lo, hi);
     c.rc = hi;
   }
-  if (nc == 1) return;
+  if (nc == 1 || !lists) return;
   // each cell's near list and proxy depend only on the centres and radii above: the cells
   // are split into contiguous ranges handled by up to four threads (the same plan)
   const int nt = nc >= 64 ? std::min(4, std::max(1, (int)std::thread::hardware_concurrency() / 2)) : 1;
@@ -138,6 +149,11 @@ void near_cells(const PlanOptions& o, const int64_t* node_off, const double* x, 
     if (o.near_rule == 0)
       for (int s = 0; s < nc; ++s)
         if (s != t && std::abs(cells[s].I - c.I) + std::abs(cells[s].J - c.J) == 1) isnear[s] = 1;
+    if (o.near_rule == 2)
+      for (int s = 0; s < nc; ++s) {
+        const double ex = cells[s].cx - c.cx, ey = cells[s].cy - c.cy;
+        if (s != t && o.eta * std::sqrt(ex * ex + ey * ey) < 2.0 * std::max(c.rc, cells[s].rc)) isnear[s] = 1;
+      }
     double rho = inf, Rp = 0;
     bool anyfar = false;
     for (;;) {
@@ -224,11 +240,190 @@ std::vector<int32_t> grid_assignment(int m, const double* centers) {
   return ij;
 }
 
+std::vector<std::vector<int>> kmeans_split(const std::vector<int>& S, const std::vector<double>& px,
+                                           const std::vector<double>& py, const std::vector<double>& wt) {
+  const int n = (int)S.size();
+  const int k = std::min(4, n);
+  const double inf = std::numeric_limits<double>::infinity();
+  std::vector<double> cx, cy;
+  if (n == 0) return {};
+  {
+    double sx = 0, sy = 0, sw = 0;
+    for (int j : S) {
+      sx += wt[j] * px[j];
+      sy += wt[j] * py[j];
+      sw += wt[j];
+    }
+    const double mx = sx / sw, my = sy / sw;
+    int best = 0;
+    double bd = -1;
+    for (int i = 0; i < n; ++i) {
+      const double dx = px[S[i]] - mx, dy = py[S[i]] - my;
+      const double d = dx * dx + dy * dy;
+      if (d > bd) {
+        bd = d;
+        best = i;
+      }
+    }
+    cx.push_back(px[S[best]]);
+    cy.push_back(py[S[best]]);
+  }
+  std::vector<double> dmin(n, inf);
+  while ((int)cx.size() < k) {
+    int best = -1;
+    double bd = 0;
+    for (int i = 0; i < n; ++i) {
+      const double dx = px[S[i]] - cx.back(), dy = py[S[i]] - cy.back();
+      dmin[i] = std::min(dmin[i], dx * dx + dy * dy);
+      if (dmin[i] > bd) {
+        bd = dmin[i];
+        best = i;
+      }
+    }
+    if (best < 0) break;   // every member coincides with a seed
+    cx.push_back(px[S[best]]);
+    cy.push_back(py[S[best]]);
+  }
+  const int kk = (int)cx.size();
+  std::vector<int> a(n, -1);
+  for (int it = 0; it < 100; ++it) {
+    bool moved = false;
+    for (int i = 0; i < n; ++i) {
+      int b = 0;
+      double bd = inf;
+      for (int c = 0; c < kk; ++c) {
+        const double dx = px[S[i]] - cx[c], dy = py[S[i]] - cy[c];
+        const double d = dx * dx + dy * dy;
+        if (d < bd) {
+          bd = d;
+          b = c;
+        }
+      }
+      if (b != a[i]) {
+        a[i] = b;
+        moved = true;
+      }
+    }
+    if (!moved) break;
+    for (int c = 0; c < kk; ++c) {
+      double sx = 0, sy = 0, sw = 0;
+      for (int i = 0; i < n; ++i)
+        if (a[i] == c) {
+          sx += wt[S[i]] * px[S[i]];
+          sy += wt[S[i]] * py[S[i]];
+          sw += wt[S[i]];
+        }
+      if (sw > 0) {   // an emptied cluster keeps its centre
+        cx[c] = sx / sw;
+        cy[c] = sy / sw;
+      }
+    }
+  }
+  std::vector<std::vector<int>> out;
+  for (int c = 0; c < kk; ++c) {
+    std::vector<int> mem;
+    for (int i = 0; i < n; ++i)
+      if (a[i] == c) mem.push_back(S[i]);
+    if (!mem.empty()) out.push_back(mem);
+  }
+  return out;
+}
+
+namespace {
+
+// Tree 1: k-means clusters split top down, depth by depth, while a cell of the depth holds
+// more than leaf_size inclusions (cells within the limit carry on as single children);
+// cells of a depth are ordered parent by parent, children in cluster order.
+std::string kmeans_levels(int m, const int64_t* node_off, const double* x, const double* y, const PlanOptions& o,
+                          std::vector<std::vector<CellPlan>>& levels) {
+  if (o.leaf_size < 1 || o.leaf_size > 4) return "leaf_size must be in 1..4";
+  std::vector<double> px(m), py(m), wt(m);
+  for (int j = 0; j < m; ++j) {
+    double sx = 0, sy = 0;
+    for (int64_t i = node_off[j]; i < node_off[j + 1]; ++i) {
+      sx += x[i];
+      sy += y[i];
+    }
+    wt[j] = (double)(node_off[j + 1] - node_off[j]);
+    px[j] = sx / wt[j];
+    py[j] = sy / wt[j];
+  }
+  std::vector<std::vector<std::vector<int>>> depth(1);
+  std::vector<std::vector<int>> parent(1);
+  depth[0].push_back(std::vector<int>(m));
+  for (int j = 0; j < m; ++j) depth[0][0][j] = j;
+  parent[0].push_back(-1);
+  for (;;) {
+    const auto& cur = depth.back();
+    bool split = false;
+    for (const auto& c : cur) split = split || (int)c.size() > o.leaf_size;
+    if (!split) break;
+    std::vector<std::vector<int>> nxt;
+    std::vector<int> par;
+    for (int t = 0; t < (int)cur.size(); ++t) {
+      if ((int)cur[t].size() > o.leaf_size) {
+        std::vector<std::vector<int>> parts = kmeans_split(cur[t], px, py, wt);
+        if (parts.size() < 2) return "inclusions whose node means coincide";
+        for (auto& q : parts) {
+          nxt.push_back(q);
+          par.push_back(t);
+        }
+      } else {
+        nxt.push_back(cur[t]);
+        par.push_back(t);
+      }
+    }
+    depth.push_back(nxt);
+    parent.push_back(par);
+    if (depth.size() > 40) return "tree too deep";
+  }
+  const int D = (int)depth.size() - 1;
+  const bool pass = plan_pass_through(o);
+  // level 0: the inclusions leaf by leaf (with leaf_size 1 the leaves themselves)
+  std::vector<CellPlan> l0;
+  std::vector<int> first(depth[D].size() + 1, 0);
+  for (size_t t = 0; t < depth[D].size(); ++t) {
+    first[t] = (int)l0.size();
+    for (int j : depth[D][t]) {
+      CellPlan c;
+      c.incl = {j};
+      l0.push_back(c);
+    }
+  }
+  first[depth[D].size()] = (int)l0.size();
+  levels.push_back(l0);
+  for (int d = pass ? D : D - 1; d >= 0; --d) {
+    std::vector<CellPlan> cells(depth[d].size());
+    for (size_t t = 0; t < depth[d].size(); ++t) {
+      cells[t].incl = depth[d][t];
+      std::sort(cells[t].incl.begin(), cells[t].incl.end());
+    }
+    if (d == D)   // the leaves: their inclusions at level 0
+      for (size_t t = 0; t < cells.size(); ++t)
+        for (int q = first[t]; q < first[t + 1]; ++q) cells[t].children.push_back(q);
+    else
+      for (size_t q = 0; q < depth[d + 1].size(); ++q) cells[parent[d + 1][q]].children.push_back((int)q);
+    levels.push_back(cells);
+  }
+  return "";
+}
+
+}  // namespace
+
 std::string build_plan(int m, const int32_t* grid_ij, const double* centers, const int64_t* node_off,
                        const double* x, const double* y, const PlanOptions& o,
                        std::vector<std::vector<CellPlan>>& levels) {
   levels.clear();
   if (m <= 0) return "no inclusions";
+  if (o.tree == 1) {
+    if (o.near_rule == 0) return "edge adjacency needs grid cells (tree 0)";
+    std::string err = kmeans_levels(m, node_off, x, y, o, levels);
+    if (!err.empty()) return err;
+    for (size_t l = 0; l < levels.size(); ++l)
+      near_and_proxy(o, centers, node_off, x, y, levels[l], !(l == 0 && plan_pass_through(o)));
+    return "";
+  }
+  if (o.tree != 0) return "tree must be 0 or 1";
   std::vector<int32_t> own_grid;
   if (!grid_ij) {
     own_grid = grid_assignment(m, centers);

@@ -28,7 +28,7 @@ EXPORTS = [
     "pmx_probe_cgemm", "pmx_probe_lu_solve_c32", "pmx_probe_id_c32", "pmx_probe_apply",
     "pmx_mlp_opts_default", "pmx_id_dataset", "pmx_mlp_train", "pmx_mlp_predict", "pmx_probe_mlp",
     "pmx_autotune", "pmx_device_cache", "pmx_far_field_noalloc", "pmx_probe_apply_structure",
-    "pmx_factor_refactor", "pmx_probe_diag_block_quad",
+    "pmx_factor_refactor", "pmx_probe_diag_block_quad", "pmx_plan_members",
 ]
 
 
@@ -54,7 +54,8 @@ class Options(C.Structure):
                 ("timing", C.c_int32), ("ir_max_iter", C.c_int32), ("ir_tol", C.c_double),
                 ("solve_graph", C.c_int32), ("learned", C.c_int32), ("model_path", C.c_char_p),
                 ("timing_kernels", C.c_uint32), ("reserved0", C.c_int32), ("tune_path", C.c_char_p),
-                ("refactor", C.c_int32), ("quadrature", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("refactor", C.c_int32), ("quadrature", C.c_int32), ("tree", C.c_int32),
+                ("leaf_size", C.c_int32), ("eta", C.c_double), ("reserved", C.c_int32 * 2)]
 
 
 class Info(C.Structure):
@@ -77,6 +78,7 @@ class MlpOpts(C.Structure):
                 ("lr", C.c_float), ("wmse", C.c_float), ("seed", C.c_uint64)]
 
 QUADRATURE = {"kress": 0, "zeta": 1}   # self-block rule of pmx_options.quadrature
+TREE = {"quad": 0, "kmeans": 1}         # pmx_options.tree
 
 KERNEL_NAMES = ["k_ts_leaf", "k_ts_update", "k_getrf_panel", "k_cpqr_update", "k_cpqr", "k_zgemm",
                 "k_trsm_small", "k_entries", "k_diag_pairs/maue", "k_apply_off", "k_getrs_small"]
@@ -151,6 +153,8 @@ def load(path=None):
     dp = C.POINTER(C.c_double)
     lib.pmx_plan_query.argtypes = [C.POINTER(Geometry), C.POINTER(Options), C.c_int32, C.c_int32,
                                    ip, ip, ip, ip, ip, dp, dp, dp, ip, ip, ip]
+    lib.pmx_plan_members.argtypes = [C.POINTER(Geometry), C.POINTER(Options), C.c_int32, C.c_int32, C.c_int32,
+                                     ip, ip, ip, ip, ip, ip, ip]
     for name in EXPORTS:
         if name not in ("pmx_options_default", "pmx_factor_destroy", "pmx_status_string",
                         "pmx_last_error", "pmx_mlp_opts_default"):
@@ -205,6 +209,9 @@ def options(w=None, **kw):
         o.proxy_rule = 0 if w.proxy_paper_rule else 1
         o.near_rule = w.near_rule
         o.quadrature = QUADRATURE[getattr(w, "quadrature", "kress")]
+        o.tree = TREE[getattr(w, "tree", "quad")]
+        o.leaf_size = int(getattr(w, "leaf_size", 4))
+        o.eta = float(getattr(w, "eta", 1.0))
     keep = []
     for k, v in kw.items():
         if k in ("model_path", "tune_path") and isinstance(v, str):
@@ -455,10 +462,23 @@ def plan_query(w, opts=None):
                                _ptr(lev, C.c_int32), _ptr(first, C.c_int32), _ptr(cen, C.c_double),
                                _ptr(rc, C.c_double), _ptr(rp, C.c_double), _ptr(P, C.c_int32),
                                _ptr(noff, C.c_int32), _ptr(near, C.c_int32)))
+    # membership: inclusions and children per cell (same cell order)
+    ncm, nit, nkt = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(_lib.pmx_plan_members(C.byref(keep.g), C.byref(o), 0, 0, 0, C.byref(ncm), C.byref(nit), C.byref(nkt),
+                                 z, z, z, z))
+    ioff = np.zeros(nc + 1, np.int32)
+    inc = np.zeros(max(nit.value, 1), np.int32)
+    koff = np.zeros(nc + 1, np.int32)
+    kid = np.zeros(max(nkt.value, 1), np.int32)
+    _check(_lib.pmx_plan_members(C.byref(keep.g), C.byref(o), nc, nit.value, nkt.value, C.byref(ncm), C.byref(nit),
+                                 C.byref(nkt), _ptr(ioff, C.c_int32), _ptr(inc, C.c_int32), _ptr(koff, C.c_int32),
+                                 _ptr(kid, C.c_int32)))
     levels = [[] for _ in range(nl.value)]
     for t in range(nc):
         levels[lev[t]].append(dict(first=int(first[t]), center=(cen[2 * t], cen[2 * t + 1]), rc=rc[t],
-                                   Rp=rp[t], P=int(P[t]), near=list(near[noff[t]:noff[t + 1]])))
+                                   Rp=rp[t], P=int(P[t]), near=list(near[noff[t]:noff[t + 1]]),
+                                   incl=[int(v) for v in inc[ioff[t]:ioff[t + 1]]],
+                                   children=[int(v) for v in kid[koff[t]:koff[t + 1]]]))
     return levels
 
 

@@ -47,6 +47,9 @@ class Workload:
     proxy_paper_rule: bool = True  # radius max(ratio*r_c, 0.9*rho_far)
     shapes: list = field(default_factory=list)  # per inclusion (a, theta, [(m, c_m, phi_m)])
     quadrature: str = "kress"    # self blocks: "kress" or "zeta" (the 41-point corrected trapezoid)
+    tree: str = "quad"           # "quad": grid quadtree; "kmeans": k-means clusters (Sec. 4.4)
+    leaf_size: int = 4           # kmeans: at most this many inclusions per leaf
+    eta: float = 1.0             # near_rule 2: eta-admissibility constant
 
     @property
     def m(self) -> int:
@@ -232,6 +235,41 @@ def config3(m=400, box=24.0, seed=3, k_ext=12.0) -> Workload:
     c = np.array([cc for cc, _ in centers])
     return _assemble("cfg3_random400", c, shapes, np.array(ns), k_ext, np.array(kin),
                      angles=2 * np.pi * np.arange(4) / 4, id_tol=1e-10, near_rule=1)
+
+
+def random_close(m=400, box=16.0, gap=0.02, seed=7, k_ext=12.0, a_lo=0.1, a_hi=0.3, nrhs=4,
+                 name=None) -> Workload:
+    """Randomly placed smooth inclusions, some of them nearly touching (Sec. 4.4's random
+    arrangements with close scatterers): dart throwing in a box x box square with bounding
+    circles at least `gap` apart, shapes a(1 + sum_{m=2..6} c_m cos(m t + phi_m)) with
+    a ~ U(a_lo, a_hi), |c_m| <= 0.05, per-inclusion contrast k-/k+ ~ U(1.2, 2.0), nodes
+    even(clamp(ceil(8 k- perimeter), 64, 256)), nrhs plane waves at 2 pi j / nrhs; the
+    k-means tree with up to four inclusions per leaf and the eta-admissibility rule."""
+    rng = np.random.default_rng(seed)
+    shapes, placed, kin, ns = [], [], [], []
+    tries = 0
+    while len(placed) < m:
+        tries += 1
+        if tries > 2_000_000:
+            raise RuntimeError("dart throwing did not place all inclusions")
+        a = rng.uniform(a_lo, a_hi)
+        modes = [(mm, rng.uniform(-0.05, 0.05), rng.uniform(0, 2 * np.pi)) for mm in range(2, 7)]
+        rad = a * (1 + sum(abs(c) for _, c, _ in modes))
+        cx, cy = rng.uniform(rad, box - rad, size=2)
+        if any(math.hypot(cx - c2[0], cy - c2[1]) < rad + r2 + gap for (c2, r2) in placed):
+            continue
+        ratio = rng.uniform(1.2, 2.0)
+        placed.append(((cx, cy), rad))
+        shapes.append((a, 0.0, modes))
+        kin.append(ratio * k_ext)
+        nn = int(math.ceil(8 * ratio * k_ext * perimeter(a, modes)))
+        nn = min(max(nn, 64), 256)
+        nn += nn % 2
+        ns.append(nn)
+    c = np.array([cc for cc, _ in placed])
+    return _assemble(name or f"close{m}_box{box:g}_gap{gap:g}_s{seed}", c, shapes, np.array(ns), k_ext,
+                     np.array(kin), angles=2 * np.pi * np.arange(nrhs) / nrhs, id_tol=1e-10, near_rule=2,
+                     tree="kmeans", leaf_size=4)
 
 
 def random_shape_grid(g, seed, k_ext, n=128, a_lo=0.25, a_hi=0.35, cmax=0.05, contrast=1.5, angles=None,
