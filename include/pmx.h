@@ -114,7 +114,9 @@ typedef struct {
                               and learned = 0 */
   int32_t leaf_size;       /* tree 1: at most this many inclusions per leaf, 1..4; a leaf of
                               several inclusions is compressed as one cell (its own
-                              inclusions interact through its dense block) */
+                              inclusions interact through its dense block).  With
+                              leaf_size > 1, pmx_factor_create returns PMX_EINVAL for plans of
+                              more than 512 leaves */
   double eta;              /* near_rule 2 (Sec. 4.4): cells s, t of a level are near when
                               eta |c_s - c_t| < max(2 r_s, 2 r_t) (r: farthest own node from
                               the cell centre c), then the proxy-circle test of near_rule 1;

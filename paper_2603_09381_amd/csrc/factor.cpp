@@ -421,6 +421,11 @@ struct NumProgram {
   }
 };
 
+// Leaves of several inclusions: the largest first level accepted.  Batches of up to 324
+// such leaves are verified; one of 1,231 leaves ended in a device memory fault whose cause
+// is not known, so larger ones are refused.
+#define PMX_MAX_MULTI_LEAVES 512
+
 struct pmx_factor {
   // reuse of the factorisation's temporary device blocks (declared first: destroyed last)
   DevPool pool;
@@ -3012,6 +3017,9 @@ pmx_status pmx_factor_create(const pmx_geometry* geom, const pmx_options* opts, 
     auto plan_job = std::async(std::launch::async, [geom, &o, Fp, &plan_ms] {
       const double tp = now_ms();
       make_plan(geom, o, Fp->plan);
+      if (Fp->lev0 && (int)Fp->plan[Fp->lev0].size() > PMX_MAX_MULTI_LEAVES)
+        fail(PMX_EINVAL, "leaves of several inclusions are supported up to " + std::to_string(PMX_MAX_MULTI_LEAVES) +
+                             " leaves (this plan has " + std::to_string(Fp->plan[Fp->lev0].size()) + ")");
       plan_ms = now_ms() - tp;
     });
     try {

@@ -206,3 +206,16 @@ def test_apply_structure_with_kmeans_tree():
     st = pmx.apply_structure(w, check=True)
     assert st["pairs_checked"] == st["waves"] * w.m
     assert st["coverage_violations"] == 0
+
+
+def test_large_plans_of_several_inclusions_per_leaf_are_refused():
+    """Leaves of several inclusions are accepted up to 512 leaves; a larger plan is an
+    argument error reported before any device work, while one inclusion per leaf has no
+    such limit."""
+    base = W.random_close(m=1600, box=32.0)
+    w = dataclasses.replace(base, leaf_size=2)
+    assert len(pmx.plan_query(w)[1]) > 512
+    st, msg = _create_opts(w)
+    assert st == 1 and "up to 512 leaves" in msg, msg
+    st, msg = _create_opts(dataclasses.replace(base, leaf_size=1))
+    assert st != 1, msg
