@@ -1783,28 +1783,36 @@ struct LeafMap {
   RowSrc *d_to_dens = nullptr, *d_to_leaf = nullptr, *d_incl_to_dens = nullptr;
 };
 
-// rows, cols: the active codes of the leaf cells (node codes only), offsets offS [ncell + 1]
+// rows, cols: the active codes of the leaf cells (node codes only), offsets offS [ncell + 1];
+// same: the leaf cells are the plan's level-0 cells (one inclusion each, [q; u]), so that
+// the inclusion layout is the leaf layout
 void build_leaf_map(pmx_factor* F, int nrhs, const std::vector<int>& rows, const std::vector<int>& cols,
-                    const std::vector<int64_t>& offS, int ncell, LeafMap& M, Arena& A, hipStream_t s) {
+                    const std::vector<int64_t>& offS, int ncell, bool same, LeafMap& M, Arena& A, hipStream_t s) {
   const std::vector<int64_t>& no = F->node_off;
-  M.n2 = 2 * F->n_nodes;
+  const int N = F->n_nodes;
+  M.n2 = 2 * N;
   M.ncell = ncell;
-  std::vector<RowSrc> to_dens(M.n2, RowSrc{0, 0}), to_leaf(M.n2, RowSrc{0, 0}), incl_to_dens(M.n2, RowSrc{0, 0});
+  M.same = same;
+  std::vector<RowSrc> to_dens(M.n2), to_leaf(M.n2);
   M.leaf_off.assign(ncell, 0);
   M.cell_rows.assign(ncell, 0);
   M.max_cell = 0;
-  // density index of a node code (2 node + type)
+  // density index of each node code (2 node + type): base[node] + type * n_j
+  std::vector<int64_t> base(N);
+  std::vector<int> nj(N);
+  for (int j = 0; j + 1 < (int)no.size(); ++j)
+    for (int64_t i = no[j]; i < no[j + 1]; ++i) {
+      base[i] = 2 * no[j] + (i - no[j]);
+      nj[i] = (int)(no[j + 1] - no[j]);
+    }
   auto dens = [&](int code) {
-    const int64_t node = code >> 1;
-    const int ty = code & 1;
-    const int j = (int)(std::upper_bound(no.begin(), no.end(), node) - no.begin()) - 1;
-    return 2 * no[j] + ty * (no[j + 1] - no[j]) + (node - no[j]);
+    if (code < 0 || (code >> 1) >= N) fail(PMX_EINVAL, "a leaf row that is not a boundary node");
+    return base[code >> 1] + (int64_t)(code & 1) * nj[code >> 1];
   };
   for (int t = 0; t < ncell; ++t) {
     const int64_t off = offS[t];
     const int sz = (int)(offS[t + 1] - off);
     for (int r = 0; r < sz; ++r) {
-      if (rows[off + r] < 0 || cols[off + r] < 0) fail(PMX_EINVAL, "a leaf row that is not a boundary node");
       to_leaf[off + r] = RowSrc{dens(rows[off + r]), M.n2};
       to_dens[dens(cols[off + r])] = RowSrc{off * nrhs + r, sz};
     }
@@ -1812,6 +1820,13 @@ void build_leaf_map(pmx_factor* F, int nrhs, const std::vector<int>& rows, const
     M.cell_rows[t] = sz;
     M.max_cell = std::max(M.max_cell, sz);
   }
+  M.d_to_dens = A.upload(to_dens, s);
+  M.d_to_leaf = A.upload(to_leaf, s);
+  if (same) {
+    M.d_incl_to_dens = M.d_to_dens;
+    return;
+  }
+  std::vector<RowSrc> incl_to_dens(M.n2);
   int64_t o = 0;
   for (const CellPlan& c : F->plan[0]) {
     const int j = c.incl[0];
@@ -1819,12 +1834,7 @@ void build_leaf_map(pmx_factor* F, int nrhs, const std::vector<int>& rows, const
     for (int r = 0; r < n2j; ++r) incl_to_dens[2 * no[j] + r] = RowSrc{o * nrhs + r, n2j};
     o += n2j;
   }
-  M.same = true;
-  for (int64_t i = 0; i < M.n2 && M.same; ++i)
-    M.same = incl_to_dens[i].off == to_dens[i].off && incl_to_dens[i].ld == to_dens[i].ld;
-  M.d_to_dens = A.upload(to_dens, s);
-  M.d_to_leaf = A.upload(to_leaf, s);
-  M.d_incl_to_dens = M.same ? M.d_to_dens : A.upload(incl_to_dens, s);
+  M.d_incl_to_dens = A.upload(incl_to_dens, s);
 }
 
 // descriptors: leaf vectors -> one density-layout buffer, and back per cell
@@ -2498,11 +2508,12 @@ void ensure_state(pmx_factor* F, int nrhs) {
   F->info.t_phase_ms[9] += tl - tp;
   {
     const Tier<R>& T = tier<R>(F);
+    const bool same = F->lev0 == 0;
     if (T.lev.empty()) {
       const std::vector<int64_t> offS{0, (int64_t)T.root_rows.size()};
-      build_leaf_map(F, nrhs, T.root_rows, T.root_cols, offS, 1, S.map, A, s);
+      build_leaf_map(F, nrhs, T.root_rows, T.root_cols, offS, 1, same, S.map, A, s);
     } else {
-      build_leaf_map(F, nrhs, T.lev[0].rows, T.lev[0].cols, T.lev[0].offS, T.lev[0].ncell, S.map, A, s);
+      build_leaf_map(F, nrhs, T.lev[0].rows, T.lev[0].cols, T.lev[0].offS, T.lev[0].ncell, same, S.map, A, s);
     }
   }
   F->info.t_phase_ms[10] += now_ms() - tl;
