@@ -91,6 +91,20 @@ void asm_diag(DevGeom g, ExtParams e, const DiagDesc* d, int batch, int max_n, c
 template <class R>
 void asm_entries(DevGeom g, DevProxy p, ExtParams e, const EntryMatT<R>* d, int batch, int max_a, int max_b,
                  hipStream_t s);
+// Node-node rows of the four ID matrices of a cell of one inclusion (own nodes own0 ..
+// own0 + n_own - 1, all of them active, value / q rows before derivative / u rows) against a
+// near cell of one inclusion (nodes near0 .. near0 + n_near - 1): out[kd] points at the near
+// cell's first row in ID matrix kd (0 q columns, 1 u columns, 2 value rows, 3 derivative
+// rows; column major, leading dimension ld); rows [0, n_near) take the near nodes' first
+// type, [n_near, 2 n_near) the second.
+template <class R>
+struct LeafPairDescT {
+  cx<R>* out[4];
+  int64_t ld;
+  int own0, n_own, near0, n_near;
+};
+template <class R>
+void asm_leaf_pairs(DevGeom g, ExtParams e, const LeafPairDescT<R>* d, int n, hipStream_t s);
 template <class R>
 void asm_parent(DevGeom g, ExtParams e, const ParentDescT<R>* d, int batch, int max_s, hipStream_t s);
 // leaf right-hand sides: rows [0,n) = -u^I, [n,2n) = -q^I per cell, column per angle

@@ -56,14 +56,9 @@ __device__ inline Pt fetch_pt(const DevGeom& g, const DevProxy& p, int code) {
 static __constant__ FarTable pmx_far_table = make_far_table();
 static __constant__ SeriesTable pmx_series_table = make_series_table();
 
-__device__ inline zd omit_entry(const Pt& t, const Pt& s, const ExtParams& e) {
-  const double d1 = t.x - s.x, d2 = t.y - s.y;
-  const double r = sqrt(d1 * d1 + d2 * d2);
-  const double ir = 1.0 / r;
-  // coefficient tables read through scalar loads at each use (kept out of vector registers)
-  pmx_ctab tab = (pmx_ctab)pmx_far_table.v, ser = (pmx_ctab)pmx_series_table.v;
-  asm volatile("" : "+s"(tab), "+s"(ser));
-  const bes4 b = bessel01_t(e.k * r, tab, ser);
+// The entry from its geometry (d = x_t - x_s, 1/|d|) and the Bessel values at k+ |d|.
+__device__ inline zd omit_entry_from(const Pt& t, const Pt& s, double d1, double d2, double ir, const bes4& b,
+                                     const ExtParams& e) {
   if (t.type == 0) {
     if (s.type == 0) {  // -e+ (i/4) H0 w
       const double f = 0.25 * e.eps * s.w;
@@ -84,6 +79,20 @@ __device__ inline zd omit_entry(const Pt& t, const Pt& s, const ExtParams& e) {
   const double Y = e.k * b.y0 * a + b.y1 * bc;
   const double f = 0.25 * e.k * s.w / e.eps;
   return zmk(-f * Y, f * X);
+}
+
+__device__ inline bes4 omit_bessel(double kr) {
+  // coefficient tables read through scalar loads at each use (kept out of vector registers)
+  pmx_ctab tab = (pmx_ctab)pmx_far_table.v, ser = (pmx_ctab)pmx_series_table.v;
+  asm volatile("" : "+s"(tab), "+s"(ser));
+  return bessel01_t(kr, tab, ser);
+}
+
+__device__ inline zd omit_entry(const Pt& t, const Pt& s, const ExtParams& e) {
+  const double d1 = t.x - s.x, d2 = t.y - s.y;
+  const double r = sqrt(d1 * d1 + d2 * d2);
+  const double ir = 1.0 / r;
+  return omit_entry_from(t, s, d1, d2, ir, omit_bessel(e.k * r), e);
 }
 
 // ---------------------------------------------------------------------------------
@@ -329,6 +338,64 @@ void asm_entries(DevGeom g, DevProxy p, ExtParams e, const EntryMatT<R>* d, int 
   dim3 grid((max_a + ENT_ROWS - 1) / ENT_ROWS, (max_b + ENT_COLS - 1) / ENT_COLS, batch);
   KScope ks(PK_ENTRIES, s);
   PMX_LAUNCH(k_entries<R>, grid, dim3(256), 0, s, g, p, e, d);
+}
+
+// The node-node part of the four ID matrices of a one-inclusion cell against one near
+// one-inclusion cell: for the pair (near node i, own node j) the Bessel values at k+ |x_i -
+// x_j| serve all eight entries: rows (i, value) and (i, derivative) of the q- and u-column
+// IDs (target i, source j), and rows (i, q) and (i, u) of the value- and derivative-row IDs
+// (target j, source i).  Each entry equals what omit_entry gives for it.
+template <class R>
+__global__ __launch_bounds__(256) void k_leaf_pairs(DevGeom g, ExtParams e, const LeafPairDescT<R>* ds) {
+  const LeafPairDescT<R> d = ds[blockIdx.x];
+  const int64_t np = (int64_t)d.n_near * d.n_own;
+  for (int64_t q = threadIdx.x; q < np; q += blockDim.x) {
+    const int li = (int)(q % d.n_near), lj = (int)(q / d.n_near);
+    const int ni = d.near0 + li, nj = d.own0 + lj;
+    Pt pi, pj;
+    pi.x = g.x[ni];
+    pi.y = g.y[ni];
+    pi.nx = g.nx[ni];
+    pi.ny = g.ny[ni];
+    pi.w = g.w[ni];
+    pj.x = g.x[nj];
+    pj.y = g.y[nj];
+    pj.nx = g.nx[nj];
+    pj.ny = g.ny[nj];
+    pj.w = g.w[nj];
+    const double d1 = pi.x - pj.x, d2 = pi.y - pj.y;
+    const double r = sqrt(d1 * d1 + d2 * d2);
+    const double ir = 1.0 / r;
+    const bes4 b = omit_bessel(e.k * r);
+    const double d1r = pj.x - pi.x, d2r = pj.y - pi.y;   // reversed pair, same |d| and Bessel values
+    const int64_t o0 = li + (int64_t)lj * d.ld, o1 = o0 + d.n_near;
+#pragma unroll
+    for (int kd = 0; kd < 4; ++kd) {
+      zd v0, v1;
+      if (kd < 2) {   // column IDs: target i (value, derivative row), source j (q or u column)
+        pj.type = kd;
+        pi.type = 0;
+        v0 = omit_entry_from(pi, pj, d1, d2, ir, b, e);
+        pi.type = 1;
+        v1 = omit_entry_from(pi, pj, d1, d2, ir, b, e);
+      } else {        // row IDs: target j (value or derivative row), source i (q, u column)
+        pj.type = kd - 2;
+        pi.type = 0;
+        v0 = omit_entry_from(pj, pi, d1r, d2r, ir, b, e);
+        pi.type = 1;
+        v1 = omit_entry_from(pj, pi, d1r, d2r, ir, b, e);
+      }
+      d.out[kd][o0] = cmk<R>(v0.re, v0.im);
+      d.out[kd][o1] = cmk<R>(v1.re, v1.im);
+    }
+  }
+}
+
+template <class R>
+void asm_leaf_pairs(DevGeom g, ExtParams e, const LeafPairDescT<R>* d, int n, hipStream_t s) {
+  if (n <= 0) return;
+  KScope ks(PK_ENTRIES, s);
+  PMX_LAUNCH(k_leaf_pairs<R>, dim3(n), dim3(256), 0, s, g, e, d);
 }
 
 template <class R>
@@ -725,6 +792,7 @@ void asm_probe_bessel(const double* z, int64_t n, double* out, hipStream_t s) {
 // explicit instantiations: storage in complex FP64 and complex FP32
 #define PMX_ASM_INST(R)                                                                                    \
   template void asm_entries<R>(DevGeom, DevProxy, ExtParams, const EntryMatT<R>*, int, int, int, hipStream_t); \
+  template void asm_leaf_pairs<R>(DevGeom, ExtParams, const LeafPairDescT<R>*, int, hipStream_t);             \
   template void asm_parent<R>(DevGeom, ExtParams, const ParentDescT<R>*, int, int, hipStream_t);          \
   template void asm_identity<R>(const Mat2T<R>*, int, int, hipStream_t);                                  \
   template void asm_zero<R>(cx<R>*, int64_t, hipStream_t);                                                \

@@ -749,7 +749,7 @@ struct IdOut {
 // tol |R_11|, for both IDs of both pairs; other cells take the full path.
 template <class R>
 void id_stage(pmx_factor* F, const LevelData<R>& L, const std::vector<CellPlan>& cells, const ProxyTable& PT,
-              const LearnedPlan* lp, IdOut<R>& io, Arena& tmp, hipStream_t s) {
+              const LearnedPlan* lp, IdOut<R>& io, Arena& tmp, hipStream_t s, bool pairs) {
   const int nc = L.ncell;
   const double tol = F->opts.id_tol;
   // near code lists, built on the device from the level's code arrays (the host only
@@ -839,18 +839,40 @@ void id_stage(pmx_factor* F, const LevelData<R>& L, const std::vector<CellPlan>&
       }
     }
     const int* d_ord = learned ? tmp.upload(ordcodes, s) : nullptr;
+    // cells of one inclusion with all nodes active (the inclusion level): the node-node rows
+    // come from the pair kernel, one Bessel evaluation for the eight entries of a node pair,
+    // and the general kernel fills the proxy rows
+    const bool fused = pairs && !learned;
+    std::vector<LeafPairDescT<R>> lpd;
+    int maxa = 0;
     for (int i = 0; i < nb; ++i) {
       const int q = 4 * sel[i / 4] + (i % 4), t = q / 4, kd = q % 4, ty = kd & 1;
       const int m = io.idm[q], c = io.idc[q];
       const int kc = learned ? std::min(std::min(m, c), lp->cand[q]) : std::min(m, c);
       EntryMatT<R>& e = em[i];
-      e.a = ((kd < 2) ? d_nr : d_ncol) + nro[t];
-      e.na = m;
+      const int skip = fused ? m - 2 * cells[t].P : 0;   // node rows left to the pair kernel
+      e.a = ((kd < 2) ? d_nr : d_ncol) + nro[t] + skip;
+      e.na = m - skip;
       e.b = learned ? d_ord + ordoff[i] : ((kd < 2) ? d_cols : d_rows) + L.offS[t] + (ty ? L.s0[t] : 0);
       e.nb = c;
-      e.out = Mb + offM[q];
+      e.out = Mb + offM[q] + skip;
       e.ld = m;
       e.a_is_target = (kd < 2) ? 1 : 0;
+      maxa = std::max(maxa, e.na);
+      if (fused && kd == 0) {
+        int64_t o = 0;
+        for (int sg : cells[t].near) {
+          LeafPairDescT<R> d;
+          for (int k = 0; k < 4; ++k) d.out[k] = Mb + offM[q + k] + o;
+          d.ld = m;
+          d.own0 = (int)F->node_off[cells[t].incl[0]];
+          d.n_own = L.s0[t];
+          d.near0 = (int)F->node_off[cells[sg].incl[0]];
+          d.n_near = L.s0[sg];
+          lpd.push_back(d);
+          o += L.s0[sg] + L.s1[sg];
+        }
+      }
       QrDescT<R>& Q = qd[i];
       Q.a = Mb + offM[q];
       Q.ld = m;
@@ -882,7 +904,8 @@ void id_stage(pmx_factor* F, const LevelData<R>& L, const std::vector<CellPlan>&
     EntryMatT<R>* d_em = tmp.upload(em, s);
     QrDescT<R>* d_qd = tmp.upload(qd, s);
     CpqrDescT<R>* d_cd = tmp.upload(cd, s);
-    asm_entries(F->geom(), PT.dev, F->ext(), d_em, nb, maxm, maxc, s);
+    asm_entries(F->geom(), PT.dev, F->ext(), d_em, nb, maxa, maxc, s);
+    if (!lpd.empty()) asm_leaf_pairs(F->geom(), F->ext(), tmp.upload(lpd, s), (int)lpd.size(), s);
     la_geqrf_r(d_qd, nb, maxm, maxc, s);
     if (learned) la_qr_tail_norms(d_qd, tmp.upload(tails, s), nb, maxc, s);
     HIPCHK(la_cpqr(d_cd, nb, maxc, tol, nullptr, 1, d_work, s));
@@ -962,7 +985,8 @@ void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>&
   // the leaves when a model is loaded, the full CPQR for every cell they do not settle)
   IdOut<R> io;
   const double ti = now_ms();
-  id_stage<R>(F, L, cells, PT, lp, io, tmp, s);
+  // the inclusion level: cells of one inclusion, all of its nodes active
+  id_stage<R>(F, L, cells, PT, lp, io, tmp, s, leaf && F->lev0 == 0);
   if (leaf) F->info.t_phase_ms[7] += now_ms() - ti;   // id_stage ends with its ranks downloaded
   F->info.id_learned += io.learned;
   F->info.id_fallback += io.fallback;
@@ -3450,7 +3474,7 @@ pmx_status pmx_id_dataset(const pmx_geometry* geom, const pmx_options* opts, con
     Arena tmp;
     ProxyTable PT = make_proxies(tmp, F.plan[0], s);
     IdOut<double> io;
-    id_stage<double>(&F, L0, F.plan[0], PT, nullptr, io, tmp, s);
+    id_stage<double>(&F, L0, F.plan[0], PT, nullptr, io, tmp, s, false);
     // labels: skeleton membership of every node for the four IDs, and their ranks k / n
     const int nc = L0.ncell;
     std::vector<float> X, Y((size_t)PMX_NOUT * L0.tot_s / 2, 0.0f);
