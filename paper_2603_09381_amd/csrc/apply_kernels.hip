@@ -956,18 +956,18 @@ __global__ __launch_bounds__(64) void k_apply_near(ApplyArgs A, const double* __
   if (active) apply_store<NR>(A, A.part + (int64_t)(slot0 + y) * A.nrhs * A.ld, r0, nr, a, vr, vi, dr, di);
 }
 
-// Near pairs through stored coefficients.  Every (wave, near inclusion) pair has a block of
-// the four coefficients of apply_pair (value row: -e+ H0, k (n_s.d/r) H1; derivative row:
-// k (n_t.d/r) H1, (k/e+)(k a H0 + b H1)) for each source node and target lane, made once per
-// solve state: entry (b, c, lane) of block q at near_blk[near_blk_off[q] + (4 b + c) 64 +
-// lane].  The apply then streams them (coalesced) against the weighted densities.
+// Near pairs through stored Bessel values.  Every (wave, near inclusion) pair has a block of
+// the pair's J0 + i Y0 and J1 + i Y1 at k+ |x_t - x_s| for each source node and target lane,
+// made once per solve state: entry (b, c, lane) of block q at near_blk[near_blk_off[q] +
+// (2 b + c) 64 + lane].  The apply streams them (coalesced) and forms the four coefficients
+// of apply_pair from the pair's geometry, so that it reads 32 B a pair instead of 64 B.
 __global__ __launch_bounds__(64) void k_apply_near_build(ApplyArgs A) {
   const int wv = blockIdx.x;
   const int w0 = A.wave_node[2 * wv], wn = A.wave_node[2 * wv + 1];
   const int lane = threadIdx.x;
   const int a = w0 + (lane < wn ? lane : wn - 1);
-  const double ax = A.x[a], ay = A.y[a], anx = A.nx[a], any = A.ny[a];
-  const double k = A.k, eps = A.eps, ke = k / eps;
+  const double ax = A.x[a], ay = A.y[a];
+  const double k = A.k;
   for (int q = A.near_off[wv]; q < A.near_off[wv + 1]; ++q) {
     const int j = A.near_idx[q];
     const int bb0 = (int)A.node_off[j], b1 = (int)A.node_off[j + 1];
@@ -979,16 +979,9 @@ __global__ __launch_bounds__(64) void k_apply_near_build(ApplyArgs A) {
       const double dd = d1 * d1 + d2 * d2;
       const double ir = rsqrt_nr(dd);
       const bes4 h = bessel01_t(k * (dd * ir), tab, ser);
-      const double snx = A.nx[b], sny = A.ny[b];
-      const double nsd = (snx * d1 + sny * d2) * ir;
-      const double ntd = (anx * d1 + any * d2) * ir;
-      const double aa = ntd * nsd;
-      const double bc = (anx * snx + any * sny - 2.0 * aa) * ir;
-      zd* e = blk + (int64_t)(b - bb0) * 4 * 64 + lane;
-      e[0] = zmk(-eps * h.j0, -eps * h.y0);
-      e[64] = zmk(k * nsd * h.j1, k * nsd * h.y1);
-      e[128] = zmk(k * ntd * h.j1, k * ntd * h.y1);
-      e[192] = zmk(ke * (k * aa * h.j0 + bc * h.j1), ke * (k * aa * h.y0 + bc * h.y1));
+      zd* e = blk + (int64_t)(b - bb0) * 2 * 64 + lane;
+      e[0] = zmk(h.j0, h.y0);
+      e[64] = zmk(h.j1, h.y1);
     }
   }
 }
@@ -1009,6 +1002,8 @@ __global__ __launch_bounds__(64) void k_apply_near_blk(ApplyArgs A, const double
   double vr[NR], vi[NR], dr[NR], di[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) vr[r] = vi[r] = dr[r] = di[r] = 0.0;
+  const double ax = A.x[a], ay = A.y[a], anx = A.nx[a], any = A.ny[a];
+  const double k = A.k, eps = A.eps, ke = k / eps;
   const int qs = A.near_off[wv], len = A.near_off[wv + 1] - qs;
   const int ns = A.nsplit_near, y = blockIdx.y;
   const int q0 = qs + (int)((int64_t)len * y / ns), q1 = qs + (int)((int64_t)len * (y + 1) / ns);
@@ -1017,17 +1012,12 @@ __global__ __launch_bounds__(64) void k_apply_near_blk(ApplyArgs A, const double
     const int bb0 = (int)A.node_off[j], b1 = (int)A.node_off[j + 1];
     const zd* blk = A.near_blk + A.near_blk_off[q] + lane;
     for (int b = bb0; b < b1; ++b) {
-      const zd* e = blk + (int64_t)(b - bb0) * 4 * 64;
-      const zd c1 = e[0], c2 = e[64], c3 = e[128], c4 = e[192];
+      const zd* e = blk + (int64_t)(b - bb0) * 2 * 64;
+      const zd h0 = e[0], h1 = e[64];
       const double* p = pk + (int64_t)b * S;
-#pragma unroll
-      for (int rr = 0; rr < NR; ++rr) {
-        const double qr = p[5 + 4 * rr], qi = p[6 + 4 * rr], ur = p[7 + 4 * rr], ui = p[8 + 4 * rr];
-        vr[rr] = fma(c1.re, qr, fma(-c1.im, qi, fma(c2.re, ur, fma(-c2.im, ui, vr[rr]))));
-        vi[rr] = fma(c1.re, qi, fma(c1.im, qr, fma(c2.re, ui, fma(c2.im, ur, vi[rr]))));
-        dr[rr] = fma(c3.re, qr, fma(-c3.im, qi, fma(c4.re, ur, fma(-c4.im, ui, dr[rr]))));
-        di[rr] = fma(c3.re, qi, fma(c3.im, qr, fma(c4.re, ui, fma(c4.im, ur, di[rr]))));
-      }
+      const double d1 = ax - p[0], d2 = ay - p[1];
+      const double ir = rsqrt_nr(d1 * d1 + d2 * d2);
+      apply_pair<NR>(h0.re, h1.re, h0.im, h1.im, ir, d1, d2, anx, any, p, k, eps, ke, 1.0, vr, vi, dr, di);
     }
   }
   if (active) apply_store<NR>(A, A.part + (int64_t)(slot0 + y) * A.nrhs * A.ld, r0, nr, a, vr, vi, dr, di);

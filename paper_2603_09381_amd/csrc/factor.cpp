@@ -2387,7 +2387,7 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
   aa.n_l2l_lev = (int)G.l2l_lev.size() - 1;
   for (int l = 0; l <= aa.n_l2l_lev; ++l) aa.l2l_lev[l] = G.l2l_lev[l];
   asm_apply_tables(aa, (int)G.m2l_src.size(), (int)G.l2l_child.size(), s);
-  // near pairs: the four coefficients of every (target, source node) pair stored once, when
+  // near pairs: the Bessel values of every (target, source node) pair stored once, when
   // they fit the budget and at least four right-hand sides share them
   aa.near_blk = nullptr;
   aa.near_blk_off = nullptr;
@@ -2398,7 +2398,7 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
     for (size_t q = 0; q < G.idx.size(); ++q) {
       boff[q] = tot;
       const int j = G.idx[q];
-      tot += 4 * 64 * (F->node_off[j + 1] - F->node_off[j]);
+      tot += 2 * 64 * (F->node_off[j + 1] - F->node_off[j]);
     }
     if (nrhs >= 4 && tot > 0 && 16 * tot <= PMX_APPLY_NEAR_BYTES) {
       aa.near_blk = A.alloc<zd>(tot);
@@ -2602,12 +2602,13 @@ void upload_angles(pmx_factor* F, const double* angles) {
 void count_apply_work(pmx_factor* F, int nrhs) {
   const DenseApply& D = F->ss->apply;
   const double N2 = 2.0 * F->n_nodes;
-  // with stored near coefficients, their evaluation (130 flops a pair) leaves the apply and
-  // their reading (four complex numbers a pair) enters it
+  // with stored near Bessel values, their evaluation (90 of the pair's 130 flops; the
+  // geometry and the four coefficients, 40 flops, stay) leaves the apply and their reading
+  // (two complex numbers a pair) enters it
   F->info.kernel_flops[PK_APPLY] +=
-      D.flops_fixed - 130.0 * D.near_pairs_stored + D.flops_rhs * nrhs + 8.0 * D.self_sq * nrhs;
+      D.flops_fixed - 90.0 * D.near_pairs_stored + D.flops_rhs * nrhs + 8.0 * D.self_sq * nrhs;
   F->info.kernel_bytes[PK_APPLY] +=
-      8.0 * 5 * F->n_nodes + 16.0 * D.self_sq + 16.0 * N2 * nrhs * 3 + 64.0 * D.near_pairs_stored;
+      8.0 * 5 * F->n_nodes + 16.0 * D.self_sq + 16.0 * N2 * nrhs * 3 + 32.0 * D.near_pairs_stored;
 }
 
 // FP64 factor: right-hand side into the leaf vectors, one solve pass, solution to xout.
