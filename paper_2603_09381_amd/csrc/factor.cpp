@@ -374,6 +374,8 @@ struct SolveProgram {
   cx<R>* leaf = nullptr;     // leaf vectors: input and output of a pass
   MatT<R>* d_bm_root = nullptr;
   MatT<R>* d_w_root = nullptr;
+  zd *Wroot64 = nullptr, *Yroot64 = nullptr;   // top right-hand sides and solution in FP64
+  GemmArgsT<double>* d_root_gemm = nullptr;    // Yroot64 = Ainv_root Wroot64
   Arena arena;
 };
 
@@ -386,6 +388,10 @@ struct Tier {
   int* ipiv_root = nullptr;
   int* perm_root = nullptr;
   LuDescT<R>* d_lu_root = nullptr;
+  // refined forms: the FP64 inverse of the top system (the block as assembled in the factor's
+  // type, inverted through an FP64 LU), so that each of the many solves of a refinement takes
+  // one product instead of two sequential triangular sweeps
+  zd* Ainv_root = nullptr;
   std::vector<int> root_rows, root_cols;
   SolveProgram<R> prog;
 };
@@ -1506,20 +1512,43 @@ void factor_all(pmx_factor* F, hipStream_t s) {
       T.perm_root = cur.perm;
       T.root_rows = cur.rows;
       T.root_cols = cur.cols;
-      std::vector<LuDescT<R>> lu{LuDescT<R>{T.Droot, T.root_s, T.root_s, T.ipiv_root, T.perm_root}};
-      T.d_lu_root = F->arena.upload(lu, s);
       Arena tmp(&F->pool);
       int* d_info = num_arena(F, tmp).alloc<int>(1);
-      {
+      if (F->opts.precision != 0) {
+        // refined forms: FP64 LU of the block, then its inverse (the LU's solves with the
+        // identity); the block in the factor's type is not factored
+        const int rs = T.root_s;
+        zd* D64 = num_arena(F, tmp).alloc<zd>((int64_t)rs * rs);
+        int* ip = num_arena(F, tmp).alloc<int>(rs);
+        int* pm = num_arena(F, tmp).alloc<int>(rs);
+        T.Ainv_root = F->arena.alloc<zd>((int64_t)rs * rs);
+        std::vector<LuDescT<double>> lu{LuDescT<double>{D64, rs, rs, ip, pm}};
+        std::vector<Mat2T<double>> id{Mat2T<double>{T.Ainv_root, rs, rs}};
+        std::vector<MatT<double>> am{MatT<double>{T.Ainv_root, rs, rs, rs}};
+        const LuDescT<double>* dl = num_arena(F, tmp).upload(lu, s);
+        const Mat2T<double>* d_id = num_arena(F, tmp).upload(id, s);
+        const MatT<double>* d_am = num_arena(F, tmp).upload(am, s);
+        const cx<R>* D = T.Droot;
+        num_step(F, s, [=](hipStream_t st) {
+          asm_convert(D, D64, (int64_t)rs * rs, st);
+          asm_zero_i32(d_info, 1, st);
+          la_getrf(dl, 1, rs, d_info, st);
+          asm_identity(d_id, 1, rs, st);
+          la_getrs(dl, d_am, 1, rs, rs, st);
+        });
+        la_getrf_work(rs, 8, &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
+      } else {
+        std::vector<LuDescT<R>> lu{LuDescT<R>{T.Droot, T.root_s, T.root_s, T.ipiv_root, T.perm_root}};
+        T.d_lu_root = F->arena.upload(lu, s);
         const LuDescT<R>* dl = T.d_lu_root;
         const int rs = T.root_s;
         num_step(F, s, [=](hipStream_t st) {
           asm_zero_i32(d_info, 1, st);
           la_getrf(dl, 1, rs, d_info, st);
         });
+        la_getrf_work(T.root_s, (int)sizeof(R), &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
       }
       if (F->num.on) F->num.infos.push_back({d_info, 1});
-      la_getrf_work(T.root_s, (int)sizeof(R), &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
       std::vector<int> info;
       download(info, d_info, 1, s);
       if (info[0]) fail(PMX_ESINGULAR, "zero pivot in the LU of the top compressed system");
@@ -1732,6 +1761,14 @@ void build_program(pmx_factor* F, int nrhs, hipStream_t s) {
   P.d_bm_root = A.upload(rb, s);
   std::vector<MatT<R>> rw{MatT<R>{A.alloc<cx<R>>((int64_t)T.root_s * nrhs), T.root_s, T.root_s, nrhs}};
   P.d_w_root = A.upload(rw, s);
+  P.d_root_gemm = nullptr;
+  if (T.Ainv_root) {
+    const int rs = T.root_s;
+    P.Wroot64 = A.alloc<zd>((int64_t)rs * nrhs);
+    P.Yroot64 = A.alloc<zd>((int64_t)rs * nrhs);
+    std::vector<GemmArgsT<double>> rg{GemmArgsT<double>{rs, nrhs, rs, T.Ainv_root, rs, P.Wroot64, rs, P.Yroot64, rs}};
+    P.d_root_gemm = A.upload(rg, s);
+  }
   P.leaf = nl ? P.lv[0].F : P.Froot;
   P.nrhs = nrhs;
 }
@@ -1780,7 +1817,14 @@ void launch_program(pmx_factor* F, hipStream_t s) {
     (void)top;
     asm_gather(S.G, S.d_par, S.n_par, S.max_par, nrhs, s);
   }
-  level_getrs(T.d_lu_root, P.d_bm_root, P.d_w_root, 1, T.root_s, nrhs, s);
+  if (P.d_root_gemm) {
+    const int64_t n = (int64_t)T.root_s * nrhs;
+    asm_convert(P.Froot, P.Wroot64, n, s);
+    la_zgemm_list(OP_N, OP_N, P.d_root_gemm, 1, T.root_s, nrhs, cmk<double>(1, 0), cmk<double>(0, 0), s);
+    asm_convert(P.Yroot64, P.Froot, n, s);
+  } else {
+    level_getrs(T.d_lu_root, P.d_bm_root, P.d_w_root, 1, T.root_s, nrhs, s);
+  }
   for (int l = nl - 1; l >= 0; --l) {
     const LevelData<R>& L = T.lev[l];
     SolveLevel<R>& S = P.lv[l];
