@@ -388,9 +388,8 @@ struct Tier {
   int* ipiv_root = nullptr;
   int* perm_root = nullptr;
   LuDescT<R>* d_lu_root = nullptr;
-  // refined forms: the FP64 inverse of the top system (the block as assembled in the factor's
-  // type, inverted through an FP64 LU), so that each of the many solves of a refinement takes
-  // one product instead of two sequential triangular sweeps
+  // refined forms: the FP64 inverse of the top system's LU factors, so that each of the many
+  // solves of a refinement takes one product instead of two sequential triangular sweeps
   zd* Ainv_root = nullptr;
   std::vector<int> root_rows, root_cols;
   SolveProgram<R> prog;
@@ -1514,30 +1513,7 @@ void factor_all(pmx_factor* F, hipStream_t s) {
       T.root_cols = cur.cols;
       Arena tmp(&F->pool);
       int* d_info = num_arena(F, tmp).alloc<int>(1);
-      if (F->opts.precision != 0) {
-        // refined forms: FP64 LU of the block, then its inverse (the LU's solves with the
-        // identity); the block in the factor's type is not factored
-        const int rs = T.root_s;
-        zd* D64 = num_arena(F, tmp).alloc<zd>((int64_t)rs * rs);
-        int* ip = num_arena(F, tmp).alloc<int>(rs);
-        int* pm = num_arena(F, tmp).alloc<int>(rs);
-        T.Ainv_root = F->arena.alloc<zd>((int64_t)rs * rs);
-        std::vector<LuDescT<double>> lu{LuDescT<double>{D64, rs, rs, ip, pm}};
-        std::vector<Mat2T<double>> id{Mat2T<double>{T.Ainv_root, rs, rs}};
-        std::vector<MatT<double>> am{MatT<double>{T.Ainv_root, rs, rs, rs}};
-        const LuDescT<double>* dl = num_arena(F, tmp).upload(lu, s);
-        const Mat2T<double>* d_id = num_arena(F, tmp).upload(id, s);
-        const MatT<double>* d_am = num_arena(F, tmp).upload(am, s);
-        const cx<R>* D = T.Droot;
-        num_step(F, s, [=](hipStream_t st) {
-          asm_convert(D, D64, (int64_t)rs * rs, st);
-          asm_zero_i32(d_info, 1, st);
-          la_getrf(dl, 1, rs, d_info, st);
-          asm_identity(d_id, 1, rs, st);
-          la_getrs(dl, d_am, 1, rs, rs, st);
-        });
-        la_getrf_work(rs, 8, &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
-      } else {
+      {
         std::vector<LuDescT<R>> lu{LuDescT<R>{T.Droot, T.root_s, T.root_s, T.ipiv_root, T.perm_root}};
         T.d_lu_root = F->arena.upload(lu, s);
         const LuDescT<R>* dl = T.d_lu_root;
@@ -1547,6 +1523,25 @@ void factor_all(pmx_factor* F, hipStream_t s) {
           la_getrf(dl, 1, rs, d_info, st);
         });
         la_getrf_work(T.root_s, (int)sizeof(R), &F->info.kernel_bytes[PK_GETRF_PANEL], &F->info.kernel_flops[PK_GETRF_PANEL]);
+      }
+      if (F->opts.precision != 0) {
+        // refined forms: the inverse of the LU's factors, formed in FP64 (the LU's solves with
+        // the identity as right-hand sides)
+        const int rs = T.root_s;
+        zd* LU64 = num_arena(F, tmp).alloc<zd>((int64_t)rs * rs);
+        T.Ainv_root = F->arena.alloc<zd>((int64_t)rs * rs);
+        std::vector<LuDescT<double>> lu{LuDescT<double>{LU64, rs, rs, T.ipiv_root, T.perm_root}};
+        std::vector<Mat2T<double>> id{Mat2T<double>{T.Ainv_root, rs, rs}};
+        std::vector<MatT<double>> am{MatT<double>{T.Ainv_root, rs, rs, rs}};
+        const LuDescT<double>* dl = num_arena(F, tmp).upload(lu, s);
+        const Mat2T<double>* d_id = num_arena(F, tmp).upload(id, s);
+        const MatT<double>* d_am = num_arena(F, tmp).upload(am, s);
+        const cx<R>* D = T.Droot;
+        num_step(F, s, [=](hipStream_t st) {
+          asm_convert(D, LU64, (int64_t)rs * rs, st);
+          asm_identity(d_id, 1, rs, st);
+          la_getrs(dl, d_am, 1, rs, rs, st);
+        });
       }
       if (F->num.on) F->num.infos.push_back({d_info, 1});
       std::vector<int> info;
