@@ -119,7 +119,10 @@ void la_geqrf_r(const QrDescT<R>* d_qr, int batch, int max_m, int max_c, hipStre
 // Runs steps until |R_jj| <= tol |R_11| (phase 1, tol > 0) or until the step count
 // reaches kmin[b] (continuation, tol <= 0; kmin may be NULL).  A zero column stops both.
 // Matrices with max_c >= PMX_CPQR_MULTI_MIN columns use the multi-workgroup variant, which
-// needs d_work (one device int) and synchronises the stream every 16 steps; a launch table
+// needs d_work (one device int); every 16 steps it copies the done count to a pinned host
+// buffer of the calling thread and waits for the count of the 16 steps before, so the
+// stream never runs dry while the host checks (the call returns after its last copy has
+// landed); a launch table
 // may choose its persistent form instead (the whole loop in one cooperative launch, no
 // host synchronisation).  Returns the first error of its progress polls (hipSuccess when
 // there is none; launch errors stay with the stream as for every launcher).

@@ -2797,22 +2797,47 @@ hipError_t la_cpqr(const CpqrDescT<R>* d_cp, int batch, int max_c, double tol, c
     if (e == hipSuccess) return hipSuccess;
     (void)hipGetLastError();   // not launchable as one resident grid: the step-by-step loop below
   }
-  for (int it = 0; it <= max_c; ++it) {
+  // Progress polls, one chunk behind: after every 16 columns the done count is copied to
+  // pinned host memory behind an event, and the host waits for the previous chunk's copy
+  // only, so that the stream always holds the current chunk while the host checks (a
+  // matrix that is done makes the later steps return at once).
+  static thread_local int* h_nd = nullptr;
+  if (!h_nd) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) return hipErrorOutOfMemory;
+    h_nd = (int*)p;
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t err = hipSuccess;
+  for (int k = 0; k < 2 && err == hipSuccess; ++k) err = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+  int pending = -1, chunk = 0;
+  for (int it = 0; it <= max_c && err == hipSuccess; ++it) {
     PMX_LAUNCH(k_cpqr_pivot<R>, dim3(batch), dim3(256), 0, s, d_cp, tol, d_kmin, d_work);
     {
       KScope ks(PK_CPQR_UPDATE, s);
       PMX_LAUNCH(k_cpqr_update<R>, dim3(ucols, batch), dim3(256), shm, s, d_cp);
     }
     if ((it & 15) == 15) {
-      int nd = 0;
-      hipError_t e = hipMemcpyAsync(&nd, d_work, sizeof(int), hipMemcpyDeviceToHost, s);
-      pmx_count_sync();
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
-      if (e != hipSuccess) return e;
-      if (nd >= batch) break;
+      const int slot = chunk & 1;
+      err = hipMemcpyAsync(&h_nd[slot], d_work, sizeof(int), hipMemcpyDeviceToHost, s);
+      if (err == hipSuccess) err = hipEventRecord(ev[slot], s);
+      if (err == hipSuccess && pending >= 0) {
+        pmx_count_sync();
+        err = hipEventSynchronize(ev[pending]);
+        if (err == hipSuccess && h_nd[pending] >= batch) break;
+      }
+      pending = slot;
+      ++chunk;
     }
   }
-  return hipSuccess;
+  // no copy into the host buffer may still be in flight when the call returns
+  if (chunk > 0) {
+    const hipError_t e = hipEventSynchronize(ev[(chunk - 1) & 1]);
+    if (err == hipSuccess) err = e;
+  }
+  for (int k = 0; k < 2; ++k)
+    if (ev[k]) (void)hipEventDestroy(ev[k]);
+  return err;
 }
 
 // T = R11^-1 R12 in place
