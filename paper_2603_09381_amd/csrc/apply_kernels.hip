@@ -21,7 +21,8 @@
 //   Mq_n = sum_y R_n q~,  Mu_n = (k/2) sum_y (-nu R_{n+1} + conj(nu) R_{n-1}) u~.
 // The truncation order of a (wave, inclusion) pair is the larger of the order the sources'
 // J_n decay needs and ceil(PMX_APPLY_TRUNC / ln(rho_min / r_j)) (rho_min: the centre's distance
-// to the wave's bounding circle), so that dropped terms stay below about 1e-17 of the kept ones.
+// to the wave's bounding circle), so that dropped terms stay below about e^-PMX_APPLY_TRUNC of the
+// kept ones.
 #include "assemble.h"
 #include "bessel.h"
 #include "hankel_fast.h"
@@ -319,7 +320,7 @@ __global__ __launch_bounds__(256) void k_apply_p2m(ApplyArgs A, const double* __
 // R_nu(d), nu = -M2M_NU .. M2M_NU, follows.  Per child the workgroup stages the child's A_n
 // and B_n in LDS, and each thread accumulates its (order, right-hand side) outputs in
 // registers: orders up to the cluster's own order + 2 (its sources' J_n decay; beyond,
-// the coefficients are below 1e-17 of the leading ones and are written as zeros), child
+// the coefficients are below e^-PMX_APPLY_TRUNC of the leading ones and are written as zeros), child
 // orders up to the child's order + 2.  The records are then written as p2m writes them,
 // orders up to PMX_APPLY_PMAXC + 1.
 constexpr int M2M_MO = PMX_APPLY_PMAXC + 2;                // outputs for orders -M2M_MO .. M2M_MO
@@ -1058,7 +1059,7 @@ int64_t apply_m2l_coef_size(int n_src, int nr_max) { return (int64_t)n_src * 2 *
 
 int apply_source_order(double kr) {
   for (int p = 1; p < 1000; ++p)
-    if (p > 0.5 * M_E * kr + 2 && std::pow(0.5 * M_E * kr / p, p) <= 1e-17) return p;
+    if (p > 0.5 * M_E * kr + 2 && std::pow(0.5 * M_E * kr / p, p) <= std::exp(-PMX_APPLY_TRUNC)) return p;
   return 1000;
 }
 

@@ -196,9 +196,12 @@ void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s);
 #define PMX_APPLY_RATIO 3.0
 #define PMX_APPLY_PMAX 48
 #define PMX_APPLY_PMAXC 96   // largest order of a cluster expansion
-// truncation of a far pair: orders until (r_j / rho_min)^p <= e^-PMX_APPLY_TRUNC, about 1e-17
-// (on the star grids the sources' own order, from k r_j, is the larger one for most pairs)
-#define PMX_APPLY_TRUNC 39.2
+// truncation of a far pair: orders until (r_j / rho_min)^p <= e^-PMX_APPLY_TRUNC, about
+// 1e-13, and of a source's own expansion: until its J_p decay reaches the same bound (on the
+// star grids the sources' own order, from k r_j, is the larger one for most pairs).  The
+// apply then stays within about 1e-13 of the assembled operator, three orders below the
+// refinement's tolerances, which end at 1e-10.
+#define PMX_APPLY_TRUNC 30.0
 // coefficient records per source: orders m = 0 .. PMX_APPLY_PMAXC + 1, per right-hand side
 // six complex numbers A_m, A_-m, B_m+1, B_-m+1, B_m-1, B_-m-1 (A: value rows, B: normal
 // derivative rows; the -m entries are zero for m = 0); an inclusion fills orders up to
@@ -278,11 +281,11 @@ struct ApplyArgs {
 void asm_apply_tables(const ApplyArgs& a, int n_m2l, int n_l2l, hipStream_t s);
 // the stored near coefficients (once per solve state), when a.near_blk is set
 void asm_apply_near_build(const ApplyArgs& a, hipStream_t s);
-// budget of the stored near coefficients; beyond it (or for fewer than 4 right-hand sides)
+// budget of the stored near Bessel values; beyond it (or for fewer than 4 right-hand sides)
 // the near pairs are evaluated in every apply
 #define PMX_APPLY_NEAR_BYTES ((int64_t)48 << 30)
 // orders needed for the sources of an inclusion of radius r: the smallest p with
-// (e k r / 2p)^p <= 1e-17 and p > e k r / 2 + 2
+// (e k r / 2p)^p <= e^-PMX_APPLY_TRUNC and p > e k r / 2 + 2
 int apply_source_order(double kr);
 // source splits giving about wg_target workgroups per launch
 int apply_splits(int n_nodes, int wg_target);
