@@ -193,7 +193,7 @@ void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s);
 // reached that way is near when its centre is closer than PMX_APPLY_RATIO radii or its
 // expansion would need more than PMX_APPLY_PMAX orders, else far.  Partial sums go to
 // part [nsplit + nsplit_near][nrhs][ld].
-#define PMX_APPLY_RATIO 3.0
+#define PMX_APPLY_RATIO 2.5
 #define PMX_APPLY_PMAX 48
 #define PMX_APPLY_PMAXC 96   // largest order of a cluster expansion
 // truncation of a far pair: orders until (r_j / rho_min)^p <= e^-PMX_APPLY_TRUNC, about
