@@ -38,7 +38,7 @@ typedef enum {
   PMX_EGEOM = 2,      /* geometry not supported (shared grid cell, missing grid) */
   PMX_ENOMEM = 3,     /* device allocation failed */
   PMX_EHIP = 4,       /* a HIP runtime call failed */
-  PMX_ESINGULAR = 5,  /* zero pivot in an LU factorisation */
+  PMX_ESINGULAR = 5,  /* zero or non-finite pivot in an LU factorisation */
   PMX_ENOTCONV = 6    /* iterative refinement did not reach its tolerance */
 } pmx_status;
 

@@ -1240,10 +1240,10 @@ void compress_level(pmx_factor* F, LevelData<R>& L, const std::vector<CellPlan>&
   std::vector<int> info;
   download(info, d_info, nc, s);
   for (int t = 0; t < nc; ++t)
-    if (info[t]) fail(PMX_ESINGULAR, "zero pivot in the LU of a cell block");
+    if (info[t]) fail(PMX_ESINGULAR, "zero or non-finite pivot in the LU of a cell block");
   download(info, d_info2, nc, s);
   for (int t = 0; t < nc; ++t)
-    if (info[t]) fail(PMX_ESINGULAR, "zero pivot in the LU of R D^-1 L");
+    if (info[t]) fail(PMX_ESINGULAR, "zero or non-finite pivot in the LU of R D^-1 L");
   if (F->num.on) {
     F->num.infos.push_back({d_info, nc});
     F->num.infos.push_back({d_info2, nc});
@@ -1546,7 +1546,7 @@ void factor_all(pmx_factor* F, hipStream_t s) {
       if (F->num.on) F->num.infos.push_back({d_info, 1});
       std::vector<int> info;
       download(info, d_info, 1, s);
-      if (info[0]) fail(PMX_ESINGULAR, "zero pivot in the LU of the top compressed system");
+      if (info[0]) fail(PMX_ESINGULAR, "zero or non-finite pivot in the LU of the top compressed system");
       F->info.t_phase_ms[3] += now_ms() - tr;
       break;
     }

@@ -112,8 +112,10 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // argmax of (val, idx): larger val wins, ties go to the smaller index (evaluated without
-// branches)
+// branches).  A NaN candidate counts as +infinity, so that a search over any real or NaN
+// values ends with a valid index (the pivot checks then report such a pivot as unusable).
 __device__ inline void argmax_pair(double& v, int& i, double v2, int i2) {
+  v2 = (v2 == v2) ? v2 : __builtin_huge_val();
   const bool take = (v2 > v) | ((v2 == v) & (i2 >= 0) & ((i < 0) | (i2 < i)));
   v = take ? v2 : v;
   i = take ? i2 : i;
@@ -553,7 +555,7 @@ __global__ __launch_bounds__(256) void k_getrf_panel(const LuDescT<R>* lus, int 
     const int p = block_argmax<256>(best, bi, redv, redi, &bestv);
     if (tid == 0) {
       gbl(L.ipiv)[c] = p;
-      if (bestv == 0.0 && info && info[blockIdx.x] == 0) info[blockIdx.x] = c + 1;
+      if ((bestv == 0.0 || bestv == __builtin_huge_val()) && info && info[blockIdx.x] == 0) info[blockIdx.x] = c + 1;
     }
     if (p != c) {
       for (int cc = j0 + tid; cc < j0 + jb; cc += 256) {
@@ -619,7 +621,7 @@ __global__ __launch_bounds__(NT) void k_getrf_panel_reg(const LuDescT<R>* lus, i
     const int p = block_argmax<NT>(best, bi, redv, redi, &bestv);
     if (tid == 0) {
       gbl(L.ipiv)[col] = p;
-      if (bestv == 0.0 && info && info[blockIdx.x] == 0) info[blockIdx.x] = col + 1;
+      if ((bestv == 0.0 || bestv == __builtin_huge_val()) && info && info[blockIdx.x] == 0) info[blockIdx.x] = col + 1;
     }
     // exchange rows col and p through LDS
 #pragma unroll
@@ -734,7 +736,7 @@ __global__ __launch_bounds__(NT) void k_getrf_panel_u(const LuDescT<R>* lus, int
     for (int w = 1; w < NW; ++w) argmax_pair(bv, p, sv[w], si[w]);
     if (tid == 0) {
       gbl(L.ipiv)[col] = p;
-      if (bv == 0.0 && info && info[blockIdx.x] == 0) info[blockIdx.x] = col + 1;
+      if ((bv == 0.0 || bv == __builtin_huge_val()) && info && info[blockIdx.x] == 0) info[blockIdx.x] = col + 1;
     }
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -819,7 +821,7 @@ __global__ __launch_bounds__(NT) void k_getrf_panel_t(const LuDescT<R>* lus, int
     for (int w = 1; w < NW; ++w) argmax_pair(bv, p, sv[w], si[w]);
     if (tid == 0) {
       gbl(L.ipiv)[col] = p;
-      if (bv == 0.0 && info && info[blockIdx.x] == 0) info[blockIdx.x] = col + 1;
+      if ((bv == 0.0 || bv == __builtin_huge_val()) && info && info[blockIdx.x] == 0) info[blockIdx.x] = col + 1;
     }
     if (tid < NB) {
       C b = cmk<R>(0, 0);
@@ -2519,7 +2521,7 @@ __global__ __launch_bounds__(CP_NT) void k_cpqr(const CpqrDescT<R>* cps, double 
     if (tid == 0) {
       if (j == 0 && cpiv >= c) r11 = xn;
       int stop = 0;
-      if (xn == 0.0) stop = 1;
+      if (!(xn > 0.0)) stop = 1;   // zero or NaN
       else if (tol > 0.0 && xn <= tol * r11) stop = 1;
       sh_stop = stop;
       if (!stop) {
@@ -2654,7 +2656,7 @@ __device__ void cpqr_pivot_step(const CpqrDescT<R>& Cd, int b, double tol, const
     double r11 = (j == 0) ? first : *Cd.r11;
     if (j == 0) *Cd.r11 = first;
     int stop = 0;
-    if (xn == 0.0) stop = 1;
+    if (!(xn > 0.0)) stop = 1;   // zero or NaN
     else if (tol > 0.0 && xn <= tol * r11) stop = 1;
     sh_stop = stop;
     if (stop) {

@@ -102,6 +102,17 @@ def test_lu_detects_singular(pmx):
     assert info[0] == 0 and info[1] > 0
 
 
+@pytest.mark.parametrize("n", [40, 700])
+def test_lu_reports_non_finite_pivot(pmx, n):
+    """A column of NaNs (the register panel at 40 rows, the tall panel at 700): the pivot
+    search still yields a row of the matrix, and info names the column."""
+    A = crandn(2, n, n) + 2 * np.sqrt(n) * np.eye(n)
+    A[1, :, 5] = np.nan
+    _, piv, _, info = pmx.probe_lu_solve(A, crandn(2, n, 1))
+    assert info[0] == 0 and info[1] == 6
+    assert piv.min() >= 0 and piv.max() < n
+
+
 def _lowrank(m, c, r, decay=None):
     U = crandn(m, r)
     V = crandn(r, c)
