@@ -2454,7 +2454,7 @@ void build_dense_apply(pmx_factor* F, int nrhs, const zd* dself, const std::vect
 }
 
 void launch_dense_apply(const DenseApply& D, hipStream_t s) {
-  la_zgemm_list(OP_N, OP_N, D.d_ga, D.n_ga, D.max_s, D.nrhs, zmk(1, 0), zmk(0, 0), s);
+  la_zgemm_apply_list(D.d_ga, D.n_ga, D.max_s, D.nrhs, s);
   asm_apply_off(D.aa, D.nsplit, D.nr_max, s);
   if (D.f)
     asm_apply_finish(D.f, D.ydiag, D.part, D.nslots, D.total, 1.0, -1.0, D.out, s);

@@ -78,6 +78,10 @@ enum { OP_N = 0, OP_T = 1, OP_C = 2 };
 template <class R>
 void la_zgemm_list(int opa, int opb, const GemmArgsT<R>* d_list, int batch, int max_m, int max_n,
                    cx<R> alpha, cx<R> beta, hipStream_t s);
+// C = A B (FP64) for a device list, as la_zgemm_list, under a kernel name of its own
+// (k_zgemm...<FApplyList>) so that profiles count the operator apply's self-block products
+// apart from the solver's FP64 products.
+void la_zgemm_apply_list(const GemmArgsT<double>* d_list, int batch, int max_m, int max_n, hipStream_t s);
 // algorithmic bytes and flops of the LU panels of one n x n factorisation; real_bytes is
 // sizeof(R)
 void la_getrf_work(int n, int real_bytes, double* bytes, double* flops);

@@ -432,6 +432,16 @@ void la_zgemm_list(int opa, int opb, const GemmArgsT<R>* d_list, int batch, int 
 #undef PMX_G
 }
 
+template <class R>
+struct FApplyList : FList<R> {};
+
+void la_zgemm_apply_list(const GemmArgsT<double>* d_list, int batch, int max_m, int max_n, hipStream_t s) {
+  FApplyList<double> f{{d_list}};
+  const zd one = zmk(1.0, 0.0), zero = zmk(0.0, 0.0);
+  if (launch_zgemm_skinny<double>(f, batch, max_m, max_n, one, zero, s)) return;
+  launch_zgemm<double, OP_N, OP_N>(f, batch, max_m, max_n, one, zero, s);
+}
+
 // ---------------------------------------------------------------------------------
 // small triangular solve on a <=32 x <=32 diagonal block, one thread per right-hand side
 template <class R>
