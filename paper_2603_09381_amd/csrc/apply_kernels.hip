@@ -788,6 +788,16 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
     double Hcr = H0r, Hci = H0i, Hpr = -H1r, Hpi = -H1i;   // H_{-1} = -H_1
     double Emr = 1.0, Emi = 0.0;
     const double* rec = cf + (int64_t)j * PMX_APPLY_NRECA * NR * 12;
+    // the next source's record rows, one double per 128-byte line, are read into L2 while
+    // this source is summed, so that their scalar loads find them there
+    double pf = 0.0;
+    if (q + 1 < q1) {
+      const int j1 = A.far_idx[q + 1];
+      const int rows = min((int)A.incl_geo[4 * j1 + 3] + 2, PMX_APPLY_NRECA);
+      const double* r1 = cf + (int64_t)j1 * PMX_APPLY_NRECA * NR * 12;
+      const int nd = rows * NR * 12;
+      for (int c = lane * 16; c < nd; c += 64 * 16) pf += r1[c];
+    }
     for (int m = 0; m <= p + 1; ++m) {
       const double sg = (m & 1) ? -1.0 : 1.0;
       const double Opr = Hcr * Emr - Hci * Emi, Opi = Hcr * Emi + Hci * Emr;               // O_m
@@ -820,6 +830,7 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
       Emi = Emr * ei + Emi * er;
       Emr = t;
     }
+    vr[0] = fma(fmin(fabs(pf), 1.0), 0.0, vr[0]);   // keeps the prefetch; adds zero
   }
   // the local expansion of the wave's inclusion (part 0 only): I_m(x - c_T) = J_m e^{i m th}
   // with J_m by Miller's backward recurrence (a first pass for the norm J_0 + 2 sum J_2k),
