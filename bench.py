@@ -247,7 +247,8 @@ def roofline(info_list, k, top, names, real_bytes, tag, thash):
 SLOT_KERNELS = {"k_apply_off": (("k_apply_pack", "k_apply_p2m", "k_apply_m2m", "k_apply_m2l_coef", "k_apply_m2l",
                                  "k_apply_m2l_sum", "k_apply_l2l", "k_apply_far", "k_apply_near",
                                  "k_apply_near_blk", "k_zgemm<double, 0, 0, FApplyList",
-                                 "k_zgemm_skinny<double, 4, 8, FApplyList", "k_zgemm_skinny<double, 8, 8, FApplyList",
+                                 "k_zgemm_n16<double, FApplyList", "k_zgemm_skinny<double, 4, 8, FApplyList",
+                                 "k_zgemm_skinny<double, 8, 8, FApplyList",
                                  "k_apply_finish"), "k_apply_finish"),
                 "k_ts_update": (("k_ts_update_f64", "k_ts_update_f32"), None)}
 

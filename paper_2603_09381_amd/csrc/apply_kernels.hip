@@ -736,7 +736,7 @@ __global__ __launch_bounds__(64) void k_apply_l2l(ApplyArgs A, int q0) {
 // and e^{i(m+1)th} = e^{i m th} e^{i th}; O_{-m} = (-1)^m H_m e^{-i m th}.  The sums
 // S1 = sum O_m B_{m+1}, S2 = sum O_m B_{m-1} are kept over all sources and turned into
 // derivative rows once at the end.
-template <int NR>
+template <int NR, int NH>
 __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __restrict__ cf, int r0) {
   const int wv = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * 256 + threadIdx.x) >> 6));
   if (wv >= A.n_waves) return;            // a wave past the last target (no barrier follows)
@@ -744,13 +744,15 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
   const int w0 = A.wave_node[2 * wv], wn = A.wave_node[2 * wv + 1];
   const bool active = lane < wn;
   const int a = w0 + (active ? lane : wn - 1);   // idle lanes follow the wave's last node and write nothing
-  const int nr = min(NR, A.nrhs - r0);
+  const int h0 = (int)blockIdx.z * NH;   // this slice: right-hand sides h0 .. h0 + NH - 1 of the group
+  const int nr = min(NH, A.nrhs - r0 - h0);
+  if (nr <= 0) return;
   const double ax = A.x[a], ay = A.y[a], anx = A.nx[a], any = A.ny[a];
   const double k = A.k, ik = 1.0 / k;
   const double wcx = A.wave_geo[4 * wv], wcy = A.wave_geo[4 * wv + 1], wr = A.wave_geo[4 * wv + 2];
-  double vr[NR], vi[NR], s1r[NR], s1i[NR], s2r[NR], s2i[NR];
+  double vr[NH], vi[NH], s1r[NH], s1i[NH], s2r[NH], s2i[NH];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) vr[r] = vi[r] = s1r[r] = s1i[r] = s2r[r] = s2i[r] = 0.0;
+  for (int r = 0; r < NH; ++r) vr[r] = vi[r] = s1r[r] = s1i[r] = s2r[r] = s2i[r] = 0.0;
   const int fq0 = A.far_off[wv], flen = A.far_off[wv + 1] - fq0;
   const int ns = gridDim.y, ys = blockIdx.y;
   const int q0 = fq0 + (int)((int64_t)flen * ys / ns), q1 = fq0 + (int)((int64_t)flen * (ys + 1) / ns);
@@ -788,15 +790,16 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
     double Hcr = H0r, Hci = H0i, Hpr = -H1r, Hpi = -H1i;   // H_{-1} = -H_1
     double Emr = 1.0, Emi = 0.0;
     const double* rec = cf + (int64_t)j * PMX_APPLY_NRECA * NR * 12;
-    // the next source's record rows, one double per 128-byte line, are read into L2 while
-    // this source is summed, so that their scalar loads find them there
+    // this slice's part of the next source's record rows (12 NH doubles a row), one double
+    // per 128-byte line, is read into L2 while this source is summed, so that the scalar
+    // loads of the next source find it there
     double pf = 0.0;
     if (q + 1 < q1) {
       const int j1 = A.far_idx[q + 1];
       const int rows = min((int)A.incl_geo[4 * j1 + 3] + 2, PMX_APPLY_NRECA);
-      const double* r1 = cf + (int64_t)j1 * PMX_APPLY_NRECA * NR * 12;
-      const int nd = rows * NR * 12;
-      for (int c = lane * 16; c < nd; c += 64 * 16) pf += r1[c];
+      const double* r1 = cf + (int64_t)j1 * PMX_APPLY_NRECA * NR * 12 + h0 * 12;
+      constexpr int LPR = (12 * NH + 15) / 16;   // lines of a row's slice
+      for (int c = lane; c < rows * LPR; c += 64) pf += r1[(c / LPR) * NR * 12 + (c % LPR) * 16];
     }
     for (int m = 0; m <= p + 1; ++m) {
       const double sg = (m & 1) ? -1.0 : 1.0;
@@ -804,9 +807,9 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
       const double Omr = sg * (Hcr * Emr + Hci * Emi), Omi = sg * (Hci * Emr - Hcr * Emi);  // O_-m
       const double* o = rec + (int64_t)m * NR * 12;
 #pragma unroll
-      for (int rr = 0; rr < NR; ++rr) {
+      for (int rr = 0; rr < NH; ++rr) {
         // A_m, A_-m, B_m+1, B_-m+1, B_m-1, B_-m-1 (wave-uniform addresses: scalar loads)
-        const double* c = o + rr * 12;
+        const double* c = o + (h0 + rr) * 12;
         // four fused operations into each accumulator
         vr[rr] = fma(-Omi, c[3], fma(Omr, c[2], fma(-Opi, c[1], fma(Opr, c[0], vr[rr]))));
         vi[rr] = fma(Omi, c[2], fma(Omr, c[3], fma(Opi, c[0], fma(Opr, c[1], vi[rr]))));
@@ -878,12 +881,12 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
         const double sg = (m & 1) ? -1.0 : 1.0;
         const double Ipr = Jm * Er, Ipi = Jm * Ei;                 // I_m
         const double Imr = sg * Jm * Er, Imi = -sg * Jm * Ei;      // I_-m
-        const zd* la = L + (int64_t)(m + PMX_FMM_PL + 1) * NR;                   // L^A_m
-        const zd* lna = L + (int64_t)(-m + PMX_FMM_PL + 1) * NR;                 // L^A_-m
-        const zd* lb = L + (int64_t)(PMX_FMM_NL + m + PMX_FMM_PL + 1) * NR;      // L^B_m
-        const zd* lnb = L + (int64_t)(PMX_FMM_NL - m + PMX_FMM_PL + 1) * NR;     // L^B_-m
+        const zd* la = L + (int64_t)(m + PMX_FMM_PL + 1) * NR + h0;                // L^A_m
+        const zd* lna = L + (int64_t)(-m + PMX_FMM_PL + 1) * NR + h0;              // L^A_-m
+        const zd* lb = L + (int64_t)(PMX_FMM_NL + m + PMX_FMM_PL + 1) * NR + h0;   // L^B_m
+        const zd* lnb = L + (int64_t)(PMX_FMM_NL - m + PMX_FMM_PL + 1) * NR + h0;  // L^B_-m
 #pragma unroll
-        for (int rr = 0; rr < NR; ++rr) {
+        for (int rr = 0; rr < NH; ++rr) {
           zd c = la[rr];
           vr[rr] = fma(Ipr, c.re, fma(-Ipi, c.im, vr[rr]));
           vi[rr] = fma(Ipr, c.im, fma(Ipi, c.re, vi[rr]));
@@ -919,13 +922,13 @@ __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __
   if (!active) return;
   // der = (k/2)(nu S1 - conj(nu) S2)
   const double hk = 0.5 * k;
-  double dr[NR], di[NR];
+  double dr[NH], di[NH];
 #pragma unroll
-  for (int rr = 0; rr < NR; ++rr) {
+  for (int rr = 0; rr < NH; ++rr) {
     dr[rr] = hk * (anx * s1r[rr] - any * s1i[rr] - (anx * s2r[rr] + any * s2i[rr]));
     di[rr] = hk * (anx * s1i[rr] + any * s1r[rr] - (anx * s2i[rr] - any * s2r[rr]));
   }
-  apply_store<NR>(A, A.part + (int64_t)blockIdx.y * A.nrhs * A.ld, r0, nr, a, vr, vi, dr, di);
+  apply_store<NH>(A, A.part + (int64_t)blockIdx.y * A.nrhs * A.ld, r0 + h0, nr, a, vr, vi, dr, di);
 }
 
 // Near part: one wave per workgroup; part blockIdx.y of the wave's near list, every
@@ -1095,8 +1098,10 @@ static void apply_group(const ApplyArgs& A, double* pk, int r0, int nsplit, hipS
       if (A.l2l_lev[l + 1] > A.l2l_lev[l])
         PMX_LAUNCH(k_apply_l2l<NR>, dim3(A.l2l_lev[l + 1] - A.l2l_lev[l]), dim3(64), 0, s, A, A.l2l_lev[l]);
   }
-  PMX_LAUNCH(k_apply_far<NR>, dim3((A.n_waves + 3) / 4, nsplit), dim3(256), 0, s, A, (const double*)A.coef,
-                     r0);
+  // groups of 8 right-hand sides run as two workgroup slices of 4 (half the accumulators)
+  constexpr int NH = NR > 4 ? NR / 2 : NR;
+  PMX_LAUNCH((k_apply_far<NR, NH>), dim3((A.n_waves + 3) / 4, nsplit, NR / NH), dim3(256), 0, s, A,
+                     (const double*)A.coef, r0);
 }
 
 // near pairs of a group of right-hand sides (the Bessel functions of a pair are evaluated

@@ -327,11 +327,95 @@ __global__ __launch_bounds__(256, 2) void k_zgemm(F f, cx<R> alpha, cx<R> beta) 
       }
 }
 
+// C = alpha A B + beta C (both untransposed) for n <= 16: 64 x 16 tiles, wave w the 16 x 16
+// MFMA block of rows 16 w.  Same k slices, prefetch and complex product forms as k_zgemm,
+// so every entry is the same sum in the same order; k_zgemm's 64-column tiles would spend
+// three quarters of their MFMA work on absent columns.
+template <class R, class F>
+__global__ __launch_bounds__(256) void k_zgemm_n16(F f, cx<R> alpha, cx<R> beta) {
+  typedef cx<R> C;
+  typedef typename AccT<R>::type V4;
+  GemmArgsT<R> g;
+  if (!f(blockIdx.z, g)) return;
+  const auto gA = gbl(g.A);
+  const auto gB = gbl(g.B);
+  const auto gC = gbl(g.C);
+  const int tm = blockIdx.x * 64;
+  if (tm >= g.m) return;
+  __shared__ C As[ZG_KS][64 + 1];
+  __shared__ C Bs[ZG_KS][16 + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave * 16;
+  constexpr bool ZG_GAUSS = sizeof(R) == 8;
+  V4 p1 = V4{0, 0, 0, 0}, p2 = V4{0, 0, 0, 0}, p3 = V4{0, 0, 0, 0};
+  // slice loads: 64 x 16 of A (four entries per thread), 16 x 16 of B (one)
+  constexpr int NP = 64 * ZG_KS / 256;
+  C ra[NP], rb = cmk<R>(0, 0);
+#pragma unroll
+  for (int pass = 0; pass < NP; ++pass) ra[pass] = cmk<R>(0, 0);
+  const int bk = tid & (ZG_KS - 1), bj = tid / ZG_KS;
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int pass = 0; pass < NP; ++pass) {
+      const int i = tid & 63, kk = (tid >> 6) + 4 * pass;
+      const int gi = tm + i, gk = k0 + kk;
+      const C v = gA[min(gi, g.m - 1) + (int64_t)min(gk, g.k - 1) * g.lda];
+      ra[pass] = (gi < g.m && gk < g.k) ? v : cmk<R>(0, 0);
+    }
+    const int gk = k0 + bk;
+    const C v = gB[min(gk, g.k - 1) + (int64_t)min(bj, g.n - 1) * g.ldb];
+    rb = (bj < g.n && gk < g.k) ? v : cmk<R>(0, 0);
+  };
+  if (g.k > 0) load(0);   // k = 0: no loads, C = beta C
+  for (int k0 = 0; k0 < g.k; k0 += ZG_KS) {
+#pragma unroll
+    for (int pass = 0; pass < NP; ++pass) As[(tid >> 6) + 4 * pass][tid & 63] = ra[pass];
+    Bs[bk][bj] = rb;
+    __syncthreads();
+    if (k0 + ZG_KS < g.k) load(k0 + ZG_KS);
+#pragma unroll
+    for (int ks = 0; ks < ZG_KS; ks += 4) {
+      const C a = As[ks + (lane >> 4)][wm + (lane & 15)];
+      const C b = Bs[ks + (lane >> 4)][lane & 15];
+      if constexpr (ZG_GAUSS) {
+        p1 = mfma16(a.re, b.re, p1);
+        p2 = mfma16(a.im, b.im, p2);
+        p3 = mfma16(a.re + a.im, b.re + b.im, p3);
+      } else {
+        p1 = mfma16(a.re, b.re, p1);
+        p1 = mfma16(-a.im, b.im, p1);
+        p2 = mfma16(a.re, b.im, p2);
+        p2 = mfma16(a.im, b.re, p2);
+      }
+    }
+    __syncthreads();
+  }
+  const bool use_beta = (beta.re != R(0) || beta.im != R(0));
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = tm + wm + mfma_row<R>(lane, r);
+    const int col = lane & 15;
+    if (row < g.m && col < g.n) {
+      const R x1 = p1[r], x2 = p2[r], x3 = p3[r];
+      C v = zmul(alpha, ZG_GAUSS ? cmk<R>(x1 - x2, x3 - x1 - x2) : cmk<R>(x1, x2));
+      auto cp = gC + row + (int64_t)col * g.ldc;
+      if (use_beta) v = zfma(beta, *cp, v);
+      *cp = v;
+    }
+  }
+}
+
 template <class R, int OPA, int OPB, class F>
 static void launch_zgemm(F f, int batch, int max_m, int max_n, cx<R> alpha, cx<R> beta, hipStream_t s) {
   if (batch <= 0 || max_m <= 0 || max_n <= 0) return;
-  dim3 grid((max_m + 63) / 64, (max_n + 63) / 64, batch);
   KScope ks(PK_ZGEMM, s);
+  if constexpr (OPA == OP_N && OPB == OP_N) {
+    if (max_n <= 16) {   // same sums in the same order on 64 x 16 tiles
+      PMX_LAUNCH((k_zgemm_n16<R, F>), dim3((max_m + 63) / 64, 1, batch), dim3(256), 0, s, f, alpha, beta);
+      return;
+    }
+  }
+  dim3 grid((max_m + 63) / 64, (max_n + 63) / 64, batch);
   PMX_LAUNCH((k_zgemm<R, OPA, OPB, F>), grid, dim3(256), 0, s, f, alpha, beta);
 }
 

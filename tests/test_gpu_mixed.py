@@ -96,7 +96,7 @@ def test_id_fp32(pmx, m, c):
 
 
 @pytest.mark.parametrize("g,n,k,nrhs", [(2, 64, 10.0, 3), (3, 48, 10.0, 3), (4, 48, 45.0, 3), (2, 64, 1.0, 1),
-                                        (3, 48, 30.0, 5), (4, 64, 60.0, 16)])
+                                        (3, 48, 30.0, 5), (4, 64, 60.0, 16), (3, 48, 10.0, 12)])
 def test_dense_apply_against_oracle(pmx, g, n, k, nrhs):
     """k = 45 on a 4x4 grid puts k r between about 20 and 190: every branch of the apply's
     Hankel evaluation (near pairs: series, Chebyshev, 20-term expansion; far pairs: 20-,
