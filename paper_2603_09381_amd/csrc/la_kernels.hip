@@ -2081,6 +2081,22 @@ __global__ __launch_bounds__(NT) void k_ts_leaf(const QrDescT<R>* qrs, int j0, i
   }
 }
 
+// The chip's eight XCDs each have their own L2, and consecutive workgroups of a dispatch go
+// to them in turn (workgroup b to XCD b mod 8).  The column tiles of one block of a QR
+// trailing update all read that block's V, so the update kernels map their linear workgroup
+// index through this bijection, which hands each XCD runs of TS_XCD_RUN consecutive indices
+// (run c of XCD x: indices (8 c + x) TS_XCD_RUN + i); indices past the last whole group of
+// runs map to themselves.
+#ifndef TS_XCD_RUN
+#define TS_XCD_RUN 64
+#endif
+__device__ inline int ts_xcd_run(int b, int n) {
+  constexpr int G = 8 * TS_XCD_RUN;
+  if (b >= (n / G) * G) return b;
+  const int x = b % 8, j = b / 8;
+  return (j / TS_XCD_RUN) * G + x * TS_XCD_RUN + j % TS_XCD_RUN;
+}
+
 // trailing update of one block of one tree level in FP64: A_b -= V (T^H (V^H A_b)) on 32
 // columns per workgroup.  Wave w owns columns 16 (w & 1) .. +15 and half w >> 1 of the
 // block's rows; each lane keeps its entries of A_b in registers for the whole update, in
@@ -2099,17 +2115,20 @@ __global__ __launch_bounds__(128 * CB, 2) void k_ts_update_f64(const QrDescT<dou
   typedef cx<R> C;
   constexpr int NT = 128 * CB, TSU64_COLS = 16 * CB;
   constexpr int NRB = PMX_TS_BR / 32;   // 16-row blocks per half
-  const QrDescT<R> Q = qrs[blockIdx.z];
+  const int gx = (int)gridDim.x, gy = (int)gridDim.y;
+  const int lb = ts_xcd_run((int)(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z)), gx * gy * (int)gridDim.z);
+  const int bx = lb % gx, by = (lb / gx) % gy, bz = lb / (gx * gy);
+  const QrDescT<R> Q = qrs[bz];
   const int kmax = Q.kc;
   const int jb = min(PMX_QR_NB, kmax - j0);
   const int nc = Q.c - j0 - jb;
   if (jb <= 0 || nc <= 0) return;
-  const int c0 = blockIdx.x * TSU64_COLS;
+  const int c0 = bx * TSU64_COLS;
   if (c0 >= nc) return;
   TsGeom g;
   ts_geom(Q.m, j0, jb, g);
   if (L >= g.nlev) return;
-  const int b = blockIdx.y;
+  const int b = by;
   if (b >= ts_sel(L, g.nb0, g.nb1, g.nb2, g.nb3)) return;
   const int nrb = min(PMX_TS_BR, ts_sel(L, g.mr0, g.mr1, g.mr2, g.mr3) - b * PMX_TS_BR);
   const int64_t wo = ts_sel64(L, g.wo0, g.wo1, g.wo2, g.wo3) + (int64_t)b * PMX_TS_BR * PMX_QR_NB;
@@ -2241,17 +2260,20 @@ __global__ __launch_bounds__(256) void k_ts_update_f32(const QrDescT<float>* qrs
   typedef cx<R> C;
   typedef typename AccT<R>::type V4;
   constexpr int NS = PMX_TS_BR / TSU_ROWS;
-  const QrDescT<R> Q = qrs[blockIdx.z];
+  const int gx = (int)gridDim.x, gy = (int)gridDim.y;
+  const int lb = ts_xcd_run((int)(blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z)), gx * gy * (int)gridDim.z);
+  const int bx = lb % gx, by = (lb / gx) % gy, bz = lb / (gx * gy);
+  const QrDescT<R> Q = qrs[bz];
   const int kmax = Q.kc;
   const int jb = min(PMX_QR_NB, kmax - j0);
   const int nc = Q.c - j0 - jb;
   if (jb <= 0 || nc <= 0) return;
-  const int c0 = blockIdx.x * 64;
+  const int c0 = bx * 64;
   if (c0 >= nc) return;
   TsGeom g;
   ts_geom(Q.m, j0, jb, g);
   if (L >= g.nlev) return;
-  const int b = blockIdx.y;
+  const int b = by;
   if (b >= ts_sel(L, g.nb0, g.nb1, g.nb2, g.nb3)) return;
   const int nrb = min(PMX_TS_BR, ts_sel(L, g.mr0, g.mr1, g.mr2, g.mr3) - b * PMX_TS_BR);
   const int64_t wo = ts_sel64(L, g.wo0, g.wo1, g.wo2, g.wo3) + (int64_t)b * PMX_TS_BR * PMX_QR_NB;
