@@ -61,6 +61,25 @@ def test_zgemm_few_columns(pmx, m, n, k):
     assert np.abs(got - ref).max() < 1e-13 * scale * max(1, k)
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("m,n,k", [(100, 12, 45), (64, 16, 64), (129, 9, 33), (1, 16, 5), (70, 16, 0),
+                                   (200, 16, 300)])
+def test_zgemm_sixteen_columns(pmx, m, n, k, fp32):
+    """Untransposed products of 9 to 16 columns take the 64 x 16 MFMA tiles (rows beyond a
+    multiple of 64, k not a multiple of the 16-wide slices, k = 0), in FP64 and FP32 (inputs
+    rounded to complex64 on both sides)."""
+    batch = 3
+    A = crandn(batch, m, k)
+    B = crandn(batch, k, n)
+    if fp32:
+        A = A.astype(np.complex64).astype(np.complex128)
+        B = B.astype(np.complex64).astype(np.complex128)
+    ref = A @ B
+    got = pmx.probe_zgemm(A, B, 0, 0, fp32=fp32)
+    scale = max(1.0, np.abs(ref).max())
+    assert np.abs(got - ref).max() < (2e-6 if fp32 else 1e-13) * scale * max(1, k)
+
+
 @pytest.mark.parametrize("variant", [-1, 0, 1, 2])
 @pytest.mark.parametrize("n,nrhs", [(1, 1), (31, 3), (64, 1), (100, 40), (257, 7), (33, 5), (100, 80),
                                     (300, 65), (1100, 4), (700, 9)])
