@@ -735,7 +735,9 @@ __global__ __launch_bounds__(64) void k_apply_l2l(ApplyArgs A, int q0) {
 // by the upward recurrence H_{m+1} = (2m/z) H_m - H_{m-1} (stable for the Hankel function)
 // and e^{i(m+1)th} = e^{i m th} e^{i th}; O_{-m} = (-1)^m H_m e^{-i m th}.  The sums
 // S1 = sum O_m B_{m+1}, S2 = sum O_m B_{m-1} are kept over all sources and turned into
-// derivative rows once at the end.
+// derivative rows once at the end.  Slice blockIdx.z takes right-hand sides NH z .. NH z +
+// NH - 1 of the group of NR (the records keep the group's layout): fewer accumulators, so
+// more waves per SIMD, for one Hankel evaluation and recurrence per slice.
 template <int NR, int NH>
 __global__ __launch_bounds__(256) void k_apply_far(ApplyArgs A, const double* __restrict__ cf, int r0) {
   const int wv = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * 256 + threadIdx.x) >> 6));
