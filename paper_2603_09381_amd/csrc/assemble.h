@@ -219,7 +219,7 @@ void asm_axpy(zd* y, const zd* x, zd a, int64_t n, hipStream_t s);
 #endif
 #define PMX_FMM_PL 94     // at most 94: the m2l kernel's three passes hold orders -96 .. 95
 #define PMX_FMM_NMAX 80   // largest source order of a translated pair (<= PMX_APPLY_PMAXC)
-#define PMX_FMM_CHUNK 32  // translated pairs per work item of the m2l kernel
+#define PMX_FMM_CHUNK 16  // translated pairs per work item of the m2l kernel
 #define PMX_FMM_NL (2 * PMX_FMM_PL + 3)
 struct ApplyArgs {
   const double *x, *y, *nx, *ny, *w;
